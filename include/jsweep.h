@@ -1,0 +1,234 @@
+/*
+ * jsweep: data-driven discrete-ordinates transport sweeps on one AMD
+ * Instinct MI355X (gfx950).  C ABI.
+ *
+ * The library implements the sweep path of JSweep (Yan, Yang, Zhang, Mo,
+ * "A Patch-centric Data-driven Approach for Parallel Sweeps on Large-scale
+ * Meshes", arXiv 1803.09876):
+ *
+ *   - the sweep dependency graph G = (V, E) whose vertices are (cell,
+ *     direction) pairs and whose edges carry angular flux from an upwind
+ *     cell to a downwind cell (Sec. V-A), with counts of upwind
+ *     neighbours per vertex (Listing 1, init) and cycles removed before
+ *     sweeping (appendix, sweep workflow step 1);
+ *   - a data-driven sweep of all directions at once: a vertex is computed
+ *     as soon as all of its upwind vertices are (Listing 1, compute;
+ *     patch-angle parallelism, Sec. V-B);
+ *   - source iteration around the sweep (appendix algorithm "Source
+ *     iterative Sn solver": scattering source, sweeps, error reduction).
+ *
+ * The transport problem is steady, mono-group, with isotropic scattering:
+ *   Omega . grad psi + sigma_t psi = sigma_s phi + q,  phi = sum_m w_m psi_m,
+ * with sum_m w_m = 1, discretised with the step (upwind, piecewise
+ * constant) scheme on triangles (2D), tetrahedra or hexahedra (3D):
+ *   psi_{K,m} = (V_K s_{K,m} + sum_{inflow f} a_f psi_up)
+ *             / (sigma_t,K V_K + sum_{outflow f} a_f),   a_f = |Omega_m . S_f|,
+ * where S_f is the vector area of face f.  The paper leaves the spatial
+ * scheme, the weight normalisation and the cycle rule open; the choices
+ * are documented with each entry point.
+ *
+ * Conventions
+ *   - All functions return JSWEEP_OK (0) or a negative error code; the
+ *     thread-local detail is available from jsweep_last_error().  No C++
+ *     exception crosses this interface.
+ *   - Mesh and quadrature inputs to jsweep_build_graph are HOST pointers,
+ *     borrowed for the call; the library copies what it keeps.
+ *   - Problem data and results of jsweep_sweep / jsweep_solve /
+ *     jsweep_solve_batch are DEVICE pointers (e.g. torch tensor
+ *     data_ptr() on ROCm), caller-allocated, unless a function says
+ *     otherwise.  Arrays indexed by (direction, cell) are stored
+ *     direction-major: element m * n_cells + K.
+ *   - hip_stream is a hipStream_t (NULL = the default stream).  Sweeps are
+ *     stream-ordered; solves synchronise the stream once per outer
+ *     iteration to read the residual.
+ *   - One graph must not be used by two calls at the same time (its flag
+ *     and scratch arrays are shared by every call on it).
+ */
+#ifndef JSWEEP_H
+#define JSWEEP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define JSWEEP_OK 0
+#define JSWEEP_E_INVALID_ARG (-1)   /* bad pointer, size or flag */
+#define JSWEEP_E_MESH (-2)          /* non-positive volume, face shared by >2 cells, bad ids */
+#define JSWEEP_E_QUADRATURE (-3)    /* weights not summing to 1, |Omega| != 1 */
+#define JSWEEP_E_CYCLE (-4)         /* dependency cycle while lagging is disabled */
+#define JSWEEP_E_DEVICE (-5)        /* HIP runtime error (detail in jsweep_last_error) */
+#define JSWEEP_E_OOM (-6)           /* device or host allocation failed */
+#define JSWEEP_E_STALLED (-7)       /* sweep watchdog fired: no progress within the time limit */
+#define JSWEEP_E_NOT_CONVERGED (-8) /* iteration limit reached; outputs and stats are still written */
+
+/* ---- cell types ---------------------------------------------------------
+ * JSWEEP_TRI (2D): local edge j is the edge opposite vertex j.
+ * JSWEEP_TET (3D): local face j is the face opposite vertex j.
+ * JSWEEP_HEX (3D): corner c (0..7) sits at lattice offset
+ *   (c>>2 & 1, c>>1 & 1, c & 1); local faces are -x, +x, -y, +y, -z, +z. */
+#define JSWEEP_TRI 3
+#define JSWEEP_TET 4
+#define JSWEEP_HEX 8
+
+/* ---- build flags ---------------------------------------------------- */
+#define JSWEEP_DEBUG_NO_LAG 0x1u   /* report cycles as JSWEEP_E_CYCLE instead of lagging */
+#define JSWEEP_HOST_PTRS 0x2u      /* jsweep_graph_export: output buffers are host memory */
+
+/* ---- solve modes ---------------------------------------------------- */
+#define JSWEEP_FP64 0              /* FP64 source iteration */
+#define JSWEEP_FP32_REFINED 1      /* FP32 correction sweeps inside an FP64 residual loop */
+#define JSWEEP_WARM_START 0x100    /* OR-ed into mode: psi holds the initial iterate */
+
+typedef struct {
+    int32_t dim;                   /* 2 or 3 */
+    int32_t cell_type;             /* JSWEEP_TRI (dim 2), JSWEEP_TET or JSWEEP_HEX (dim 3) */
+    int64_t n_vertices;
+    const double *coords;          /* [n_vertices * dim], row-major */
+    int64_t n_cells;
+    const int64_t *cell_vertices;  /* [n_cells * cell_type], vertex ids in [0, n_vertices) */
+} jsweep_mesh;
+
+typedef struct {
+    int32_t n_dirs;
+    const double *omega;           /* [n_dirs * 3] unit directions; 2D streams with (x, y) */
+    const double *weight;          /* [n_dirs], positive, summing to 1 (checked to 1e-12) */
+} jsweep_quadrature;
+
+typedef struct jsweep_graph_s *jsweep_graph;   /* opaque, owned by the library */
+
+/* Launch tuning of the persistent sweep kernel; 0 in a field = default or
+ * the value chosen by jsweep_autotune. */
+typedef struct {
+    int32_t waves_per_block;       /* 64-lane wavefronts per workgroup (1..16) */
+    int32_t blocks_per_cu;         /* resident workgroups per CU (capped by occupancy) */
+    int32_t inner_sweeps;          /* FP32-refined: maximum inner sweeps per outer residual */
+    int32_t chunks_per_ticket;     /* work-list chunks a wavefront takes per atomic ticket */
+} jsweep_params;
+
+typedef struct {
+    int32_t outer_iters;           /* FP64 residual evaluations */
+    int32_t sweeps;                /* transport sweeps (all directions) */
+    double residual;               /* final rho = ||r|| / ||q|| */
+    double seconds;                /* wall time of the solve */
+    int64_t lagged_edges;
+    int32_t max_levels;
+    int32_t history_len;           /* entries written to residual_history */
+    double *residual_history;      /* caller-provided host buffer or NULL */
+    int32_t history_capacity;      /* its length */
+    int32_t reserved;
+} jsweep_solve_stats;
+
+/* Build the per-direction sweep graph of a mesh on the current device.
+ *
+ * Computes, on the GPU: unique faces and their vector areas S_f (oriented
+ * from the lower to the higher cell id, outward on the boundary), cell
+ * volumes, for every direction the upwind edges (Omega . S_f > 0: lower ->
+ * higher cell; < 0: the reverse; == 0: no edge and no flux), in-degrees
+ * (counts of upwind neighbours, Listing 1 init) and longest-path levels;
+ * the level-ordered cell lists drive the sweep.  Geometry and graph
+ * arithmetic is IEEE FP64 without contraction, so the graph is a pure
+ * function of the inputs.
+ *
+ * Cycles (the paper excludes them and removes them beforehand, appendix
+ * workflow step 1): inside every non-trivial strongly connected component
+ * of a direction's graph, edges from a higher to a lower cell id are
+ * lagged: they are not counted in the in-degree and carry the previous
+ * iterate.  With JSWEEP_DEBUG_NO_LAG a cycle is an error instead.
+ *
+ * mesh, quad: host pointers (copied).  flags: JSWEEP_DEBUG_NO_LAG.
+ * out: receives the handle (NULL on error).
+ * Errors: E_INVALID_ARG, E_MESH, E_QUADRATURE, E_CYCLE, E_DEVICE, E_OOM.
+ * Limits: n_cells * faces_per_cell < 2^31; 3D meshes need n_vertices < 2^21
+ * and 2D meshes n_vertices < 2^32 (face keys); n_dirs <= 4096. */
+int jsweep_build_graph(const jsweep_mesh *mesh, const jsweep_quadrature *quad, uint32_t flags,
+                       jsweep_graph *out);
+
+/* Sizes of a built graph (any pointer may be NULL). */
+int jsweep_graph_info(jsweep_graph g, int64_t *n_cells, int32_t *n_dirs, int64_t *n_lagged,
+                      int32_t *max_levels);
+
+/* Export direction dir's graph: in-degree [n_cells], level [n_cells],
+ * level pointers [n_levels + 1] and cells ordered by (level, id)
+ * [n_cells].  Buffers are caller-allocated, device memory unless flags has
+ * JSWEEP_HOST_PTRS; any may be NULL.  n_levels receives the level count
+ * of the direction (size lvl_ptr accordingly; call once with lvl_ptr NULL
+ * to learn it). */
+int jsweep_graph_export(jsweep_graph g, int32_t dir, int32_t *indeg, int32_t *level, int64_t *lvl_ptr,
+                        int64_t *lvl_cells, int32_t *n_levels, uint32_t flags);
+
+/* Export the lagged edges (host buffers of length n_lagged, any may be
+ * NULL), sorted by (direction, downwind cell, downwind local face):
+ * direction, upwind cell, downwind cell, downwind cell's local face. */
+int jsweep_graph_lagged(jsweep_graph g, int32_t *dir, int64_t *up, int64_t *down, int32_t *face);
+
+/* One FP64 transport sweep of every direction (Listing 1 semantics: a
+ * vertex runs when its upwind count is satisfied).
+ *   sigma_t [n_cells]     total cross section (> 0)
+ *   source  [n_cells]     isotropic source s (already including scattering)
+ *   psi     [n_dirs*n_cells] in: previous iterate (read only on lagged
+ *                         edges); out: the new angular flux
+ *   phi     [n_cells]     out: sum_m w_m psi_m in ascending m (may be NULL)
+ *   psi_boundary          isotropic inflow on boundary faces (0 = vacuum)
+ * All device pointers; stream-ordered on hip_stream.
+ * Errors: E_INVALID_ARG, E_STALLED (watchdog; psi is then undefined),
+ * E_DEVICE. */
+int jsweep_sweep(jsweep_graph g, const double *sigma_t, const double *source, double *psi, double *phi,
+                 double psi_boundary, void *hip_stream);
+
+/* Source iteration to a residual (appendix algorithm: scattering source,
+ * sweeps, error reduction).  Each outer step evaluates in FP64
+ *   r_{K,m} = q_K + sigma_s,K phi_K - (L psi)_{K,m} / V_K
+ * with the full (un-lagged) streaming operator L and stops once
+ * rho = ||r|| / ||q|| <= tol, where ||x||^2 = sum_K V_K sum_m w_m x_{K,m}^2
+ * and ||q||^2 = sum_K V_K q_K^2 (rho = ||r|| when q = 0).
+ *   mode JSWEEP_FP64: plain source iteration, one FP64 sweep per outer step.
+ *   mode JSWEEP_FP32_REFINED: iterative refinement; the correction
+ *     (L - sigma_s W) dpsi = r is approximated by up to inner_sweeps FP32
+ *     source iterations, then psi += dpsi and phi = sum w psi in FP64.
+ *   OR JSWEEP_WARM_START: psi holds the initial iterate (else psi = 0).
+ * sigma_t, sigma_s, q: device [n_cells]; phi: device [n_cells] out;
+ * psi: device [n_dirs*n_cells] (out, and in with WARM_START) or NULL;
+ * params may be NULL; stats (host) may be NULL.
+ * Errors: E_INVALID_ARG, E_NOT_CONVERGED (results and stats written),
+ * E_STALLED, E_DEVICE, E_OOM. */
+int jsweep_solve(jsweep_graph g, const double *sigma_t, const double *sigma_s, const double *q,
+                 double psi_boundary, int32_t mode, double tol, int32_t max_iter, const jsweep_params *params,
+                 double *phi, double *psi, jsweep_solve_stats *stats, void *hip_stream);
+
+/* One problem instance of a batch (device pointers as in jsweep_solve). */
+typedef struct {
+    const double *sigma_t, *sigma_s, *q;
+    double psi_boundary;
+    double *phi;
+    double *psi;                   /* may be NULL */
+} jsweep_problem;
+
+/* Solve n independent problems, each on its own graph, together: every
+ * sweep of the batch is one persistent kernel launch over all instances
+ * (patch-angle parallelism across instances), and each outer step of the
+ * batch is replayed from a captured HIP graph.  Instances stop
+ * individually at their own residual.  stats: host array [n] or NULL.
+ * Errors as jsweep_solve (E_NOT_CONVERGED if any instance missed tol). */
+int jsweep_solve_batch(int32_t n, const jsweep_graph *graphs, const jsweep_problem *problems, int32_t mode,
+                       double tol, int32_t max_iter, const jsweep_params *params, jsweep_solve_stats *stats,
+                       void *hip_stream);
+
+/* Pick launch parameters for these graphs by timing candidate
+ * configurations of the sweep kernel on the device (uses scratch problem
+ * data, no caller buffers).  The result is cached in memory and, when the
+ * environment variable JSWEEP_TUNE_CACHE names a file, in that JSON file
+ * keyed by (cell type, size bucket, direction count, mode, device). */
+int jsweep_autotune(int32_t n, const jsweep_graph *graphs, int32_t mode, jsweep_params *out);
+
+void jsweep_graph_destroy(jsweep_graph g);
+
+const char *jsweep_error_string(int code);
+const char *jsweep_last_error(void);   /* thread-local detail of the last failure */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* JSWEEP_H */

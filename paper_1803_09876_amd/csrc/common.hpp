@@ -1,0 +1,148 @@
+// Internal declarations of the jsweep library (gfx950).
+#pragma once
+#include <cstring>
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/jsweep.h"
+
+namespace jsw {
+
+// ---------------------------------------------------------------------------
+// errors: thrown inside the library, turned into status codes at the ABI
+// ---------------------------------------------------------------------------
+struct Error {
+    int code;
+    std::string msg;
+};
+[[noreturn]] void fail(int code, const std::string &msg);
+void hip_check(hipError_t e, const char *what, const char *file, int line);
+#define JSW_HIP(x) ::jsw::hip_check((x), #x, __FILE__, __LINE__)
+void set_last_error(const std::string &msg);
+
+// ---------------------------------------------------------------------------
+// device memory owned by the library
+// ---------------------------------------------------------------------------
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    explicit DevBuf(size_t n) { alloc(n); }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void alloc(size_t n);
+    void release();
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// ---------------------------------------------------------------------------
+// per-cell records read by the sweep: outward vector areas of the local
+// faces, volume, sigma_t * V (filled per problem) and neighbour codes.
+// Neighbour code: >= 0 interior neighbour id, -1 boundary, <= -2 interior
+// neighbour (-code - 2) through a face that is lagged in some direction.
+// ---------------------------------------------------------------------------
+template <class R, int NF, int DIM>
+struct alignas(16) CellRec {
+    R S[NF][DIM];
+    R V;
+    R sigV;
+    int32_t nbr[NF];
+};
+
+__host__ __device__ constexpr int faces_of(int ctype) { return ctype == JSWEEP_TRI ? 3 : ctype == JSWEEP_TET ? 4 : 6; }
+
+// Sweep work unit: up to 64 cells of one direction and one level, one
+// wavefront lane each.  a = direction | (count - 1) << 16, b = offset of
+// the first cell in the direction's level-ordered cell list.
+struct Chunk {
+    uint32_t a, b;
+};
+
+// The work list is split into kStreams streams (a direction belongs to one
+// stream); on MI355X stream x runs on XCD x.
+constexpr int kStreams = 8;
+
+// ---------------------------------------------------------------------------
+// graph handle
+// ---------------------------------------------------------------------------
+struct Graph {
+    int device = 0;
+    int n_cu = 0;
+    int dim = 3, ctype = JSWEEP_TET, nfpc = 4;
+    int64_t nv = 0, nc = 0, nf = 0;
+    int nd = 0;
+    std::vector<double> omega_h, weight_h;
+    DevBuf omega64, omega32, weight;     // [nd*3] double / float, [nd] double
+    DevBuf rec64, rec32;                 // cell records (rec32 built on first FP32 use)
+    DevBuf vol;                          // [nc] double
+    DevBuf level;                        // [nd*nc] int32
+    DevBuf lvl_cells;                    // [nd*nc] int32, per direction by (level, id)
+    std::vector<int64_t> lvl_off_h;      // [nd+1] start of each direction's lvl_ptr block
+    std::vector<int64_t> lvl_ptr_h;      // concatenated per-direction level pointers
+    std::vector<int32_t> nlev_h;         // [nd]
+    int max_levels = 0;
+    DevBuf chunks;                       // [n_chunks] Chunk: per stream, ordered by (level, direction)
+    int64_t n_chunks = 0;
+    DevBuf stream_off;                   // [kStreams + 1] int64 chunk offsets of the streams
+    std::vector<int64_t> stream_off_h;
+    std::vector<int32_t> dir_stream_h;   // [nd] stream of each direction
+    DevBuf dep_ptr, dep;                 // coarsened graph: upwind chunks of every chunk (CSR)
+    int64_t n_dep = 0;
+    DevBuf cflag;                        // [n_chunks] uint8 completion epochs
+    int epoch = 0;                       // last epoch used (1..255)
+    DevBuf status;                       // [4] int32 device status words (watchdog)
+    // lagged edges, sorted by (direction, downwind cell, upwind cell)
+    int64_t n_lag = 0;
+    std::vector<int32_t> lag_m_h, lag_face_h;
+    std::vector<int64_t> lag_u_h, lag_v_h;
+    DevBuf lag_mv;                       // [n_lag] uint64  m << 32 | v
+    DevBuf lag_u;                        // [n_lag] int32
+    DevBuf lag_val64, lag_val32;         // previous-iterate snapshots
+    // scratch reused across solves
+    DevBuf scratch_a, scratch_b, scratch_c, scratch_d;
+    int grid_waves64 = 0, grid_waves32 = 0;   // persistent grid sizes
+    jsweep_params tuned{};               // set by jsweep_autotune
+    bool has_tuned = false;
+};
+
+// build steps (geometry.hip, dag.hip)
+void build_geometry(Graph &g, const jsweep_mesh &mesh, hipStream_t s);
+void build_dag(Graph &g, bool lag_cycles, hipStream_t s);
+void build_rec32(Graph &g, hipStream_t s);
+
+// sweep launch (sweep.hip)
+struct SweepSrc {
+    const void *cell;        // [nc] isotropic part of the source (Real), may be null
+    const void *dir;         // [nd*nc] per-direction part (float, FP32 path only), may be null
+};
+void refresh_sigma(Graph &g, const double *sigma_t, bool fp32, hipStream_t s);
+void launch_sweep64(Graph &g, const double *src_cell, double *psi, double psi_b, const jsweep_params *p, hipStream_t s);
+void launch_sweep32(Graph &g, const float *src_dir, const float *src_cell, float *psi, const jsweep_params *p,
+                    hipStream_t s);
+int check_sweep_status(Graph &g, hipStream_t s);   // JSWEEP_OK or JSWEEP_E_STALLED
+int persistent_waves(Graph &g, bool fp32, const jsweep_params *p, int *waves_per_block);
+
+// solve (solve.hip)
+int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *q, double psi_b, int32_t mode,
+          double tol, int32_t max_iter, const jsweep_params *params, double *phi, double *psi,
+          jsweep_solve_stats *stats, hipStream_t s);
+void scalar_flux(Graph &g, const double *psi, double *phi, hipStream_t s);
+void lag_snapshot64(Graph &g, const double *psi, hipStream_t s);
+int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems, int32_t mode, double tol,
+                int32_t max_iter, const jsweep_params *params, jsweep_solve_stats *stats, hipStream_t s);
+
+int autotune(int32_t n, Graph *const *graphs, int32_t mode, jsweep_params *out);
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace jsw

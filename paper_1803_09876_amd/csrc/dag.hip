@@ -1,0 +1,622 @@
+// Sweep dependency graph on the GPU: per (direction, cell) counts of
+// upwind neighbours, longest-path levels by frontier propagation, the
+// cycle-lag rule, the level-ordered cell lists and the sweep work list.
+//
+// A vertex is a (cell, direction) pair; an edge u -> v means v consumes
+// the outgoing angular flux of u (paper Sec. V-A).  The count of a vertex
+// is its number of upwind neighbours (Listing 1, init); vertices with count
+// zero start the sweep, and a vertex's level is one more than the largest
+// level among its upwind neighbours.
+#include <cstring>
+
+#include <algorithm>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+
+#include "common.hpp"
+
+namespace jsw {
+
+// ---------------------------------------------------------------------------
+// lagged-edge lookup: lag_mv sorted by (m << 32 | v), ties by upwind cell
+// ---------------------------------------------------------------------------
+__device__ inline bool is_lagged(const uint64_t *lag_mv, const int32_t *lag_u, int64_t n_lag, int m, int64_t v,
+                                 int64_t u) {
+    uint64_t key = ((uint64_t)(uint32_t)m << 32) | (uint64_t)v;
+    int64_t lo = 0, hi = n_lag;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (lag_mv[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    for (; lo < n_lag && lag_mv[lo] == key; ++lo)
+        if (lag_u[lo] == u) return true;
+    return false;
+}
+
+// wavefront-aggregated append to a work list
+__device__ inline void push_item(bool want, uint32_t item, uint32_t *list, uint32_t *count) {
+    uint64_t mask = __ballot(want);
+    if (!mask) return;
+    int lane = threadIdx.x & 63;
+    int leader = __ffsll((long long)mask) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(count, (uint32_t)__popcll(mask));
+    base = __shfl(base, leader);
+    if (want) list[base + __popcll(mask & ((1ull << lane) - 1))] = item;
+}
+
+template <int NF, int DIM>
+__device__ inline double out_dot(const CellRec<double, NF, DIM> &r, int j, const double *om) {
+    double d = om[0] * r.S[j][0] + om[1] * r.S[j][1];
+    if constexpr (DIM == 3) d = d + om[2] * r.S[j][2];
+    return d;
+}
+
+__device__ inline int64_t nbr_id(int32_t code) { return code <= -2 ? (int64_t)(-code - 2) : (int64_t)code; }
+
+struct LagView {
+    const uint64_t *mv;
+    const int32_t *u;
+    int64_t n;
+};
+
+// counts of non-lagged upwind neighbours; level 0 and the first frontier
+template <int NF, int DIM>
+__global__ void k_counts(const CellRec<double, NF, DIM> *rec, const double *omega, int64_t nc, int nd, LagView lag,
+                         int32_t *cnt, int32_t *level, uint32_t *front, uint32_t *front_n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool push = false;
+    if (i < nc * nd) {
+        int m = (int)(i / nc);
+        int64_t K = i - (int64_t)m * nc;
+        const double om[3] = {omega[3 * m], omega[3 * m + 1], omega[3 * m + 2]};
+        CellRec<double, NF, DIM> r = rec[K];
+        int c = 0;
+        for (int j = 0; j < NF; ++j) {
+            int32_t code = r.nbr[j];
+            if (code == -1) continue;
+            if (out_dot(r, j, om) < 0.0) {
+                if (code <= -2 && is_lagged(lag.mv, lag.u, lag.n, m, K, nbr_id(code))) continue;
+                ++c;
+            }
+        }
+        cnt[i] = c;
+        level[i] = c == 0 ? 0 : -1;
+        push = c == 0;
+    }
+    push_item(push, (uint32_t)i, front, front_n);
+}
+
+// one frontier step: release downwind neighbours of the vertices at level L
+template <int NF, int DIM>
+__global__ void k_level_step(const CellRec<double, NF, DIM> *rec, const double *omega, int64_t nc, LagView lag,
+                             const uint32_t *front, uint32_t n_front, int32_t L, int32_t *cnt, int32_t *level,
+                             uint32_t *next, uint32_t *next_n) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // every lane of a wavefront takes part in the aggregated pushes
+    uint32_t item = t < n_front ? front[t] : 0;
+    int m = (int)(item / nc);
+    int64_t K = (int64_t)item - (int64_t)m * nc;
+    CellRec<double, NF, DIM> r;
+    double om[3] = {0, 0, 0};
+    if (t < n_front) {
+        r = rec[K];
+        om[0] = omega[3 * m]; om[1] = omega[3 * m + 1]; om[2] = omega[3 * m + 2];
+    }
+    for (int j = 0; j < NF; ++j) {
+        bool push = false;
+        uint32_t w_item = 0;
+        if (t < n_front) {
+            int32_t code = r.nbr[j];
+            if (code != -1 && out_dot(r, j, om) > 0.0) {
+                int64_t w = nbr_id(code);
+                bool lagged = code <= -2 && is_lagged(lag.mv, lag.u, lag.n, m, w, K);
+                if (!lagged) {
+                    w_item = (uint32_t)((int64_t)m * nc + w);
+                    if (atomicSub(&cnt[w_item], 1) == 1) {
+                        level[w_item] = L + 1;
+                        push = true;
+                    }
+                }
+            }
+        }
+        push_item(push, w_item, next, next_n);
+    }
+}
+
+// backward trim of the unlevelled residue: out-counts towards residue
+template <int NF, int DIM>
+__global__ void k_trim_init(const CellRec<double, NF, DIM> *rec, const double *omega, int64_t nc, int nd,
+                            int32_t *level, int32_t *ocnt, uint32_t *front, uint32_t *front_n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool push = false;
+    if (i < nc * nd && level[i] == -1) {
+        int m = (int)(i / nc);
+        int64_t K = i - (int64_t)m * nc;
+        const double om[3] = {omega[3 * m], omega[3 * m + 1], omega[3 * m + 2]};
+        CellRec<double, NF, DIM> r = rec[K];
+        int c = 0;
+        for (int j = 0; j < NF; ++j) {
+            int32_t code = r.nbr[j];
+            if (code == -1 || !(out_dot(r, j, om) > 0.0)) continue;
+            if (level[(int64_t)m * nc + nbr_id(code)] == -1) ++c;
+        }
+        ocnt[i] = c;
+        push = c == 0;
+    }
+    push_item(push, (uint32_t)i, front, front_n);
+}
+
+// mark the seeds of a trim step as removed (level -2)
+__global__ void k_trim_mark(const uint32_t *front, uint32_t n, int32_t *level) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) level[front[t]] = -2;
+}
+
+template <int NF, int DIM>
+__global__ void k_trim_step(const CellRec<double, NF, DIM> *rec, const double *omega, int64_t nc,
+                            const uint32_t *front, uint32_t n_front, int32_t *level, int32_t *ocnt, uint32_t *next,
+                            uint32_t *next_n) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t item = t < n_front ? front[t] : 0;
+    int m = (int)(item / nc);
+    int64_t K = (int64_t)item - (int64_t)m * nc;
+    CellRec<double, NF, DIM> r;
+    double om[3] = {0, 0, 0};
+    if (t < n_front) {
+        r = rec[K];
+        om[0] = omega[3 * m]; om[1] = omega[3 * m + 1]; om[2] = omega[3 * m + 2];
+    }
+    for (int j = 0; j < NF; ++j) {
+        bool push = false;
+        uint32_t u_item = 0;
+        if (t < n_front) {
+            int32_t code = r.nbr[j];
+            if (code != -1 && out_dot(r, j, om) < 0.0) {
+                u_item = (uint32_t)((int64_t)m * nc + nbr_id(code));
+                if (level[u_item] == -1 && atomicSub(&ocnt[u_item], 1) == 1) {
+                    level[u_item] = -2;
+                    push = true;
+                }
+            }
+        }
+        push_item(push, u_item, next, next_n);
+    }
+}
+
+// edges among the remaining residue vertices (those on or between cycles)
+template <int NF, int DIM>
+__global__ void k_core_edges(const CellRec<double, NF, DIM> *rec, const double *omega, int64_t nc, int nd,
+                             const int32_t *level, uint32_t *edges, uint32_t *n_edges, uint32_t cap) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nc * nd || level[i] != -1) return;
+    int m = (int)(i / nc);
+    int64_t K = i - (int64_t)m * nc;
+    const double om[3] = {omega[3 * m], omega[3 * m + 1], omega[3 * m + 2]};
+    CellRec<double, NF, DIM> r = rec[K];
+    for (int j = 0; j < NF; ++j) {
+        int32_t code = r.nbr[j];
+        if (code == -1 || !(out_dot(r, j, om) < 0.0)) continue;
+        int64_t u = nbr_id(code);
+        if (level[(int64_t)m * nc + u] != -1) continue;
+        uint32_t e = atomicAdd(n_edges, 1u);
+        if (e < cap) {
+            edges[3 * (int64_t)e] = (uint32_t)m;
+            edges[3 * (int64_t)e + 1] = (uint32_t)u;
+            edges[3 * (int64_t)e + 2] = (uint32_t)K;
+        }
+    }
+}
+
+// mark both records of a lagged face as lag candidates
+template <int NF, int DIM>
+__global__ void k_mark_lag(CellRec<double, NF, DIM> *rec, const uint64_t *lag_mv, const int32_t *lag_u, int64_t n) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    int64_t v = (int64_t)(lag_mv[e] & 0xffffffffull);
+    int64_t u = lag_u[e];
+    for (int j = 0; j < NF; ++j) {
+        if (nbr_id(rec[v].nbr[j]) == u && rec[v].nbr[j] != -1) rec[v].nbr[j] = (int32_t)(-u - 2);
+        if (nbr_id(rec[u].nbr[j]) == v && rec[u].nbr[j] != -1) rec[u].nbr[j] = (int32_t)(-v - 2);
+    }
+}
+
+__global__ void k_level_keys(const int32_t *level, int64_t nc, int nd, int cell_bits, int lev_bits, uint64_t *keys) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nc * nd) return;
+    int m = (int)(i / nc);
+    int64_t K = i - (int64_t)m * nc;
+    keys[i] = ((uint64_t)m << (lev_bits + cell_bits)) | ((uint64_t)level[i] << cell_bits) | (uint64_t)K;
+}
+
+__global__ void k_level_bounds(const uint64_t *keys, int64_t nc, int nd, int cell_bits, int lev_bits, int32_t Lcap,
+                               int32_t *lvl_cells, int64_t *starts, int32_t *nlev) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nc * nd) return;
+    uint64_t k = keys[i];
+    uint64_t cmask = (1ull << cell_bits) - 1;
+    lvl_cells[i] = (int32_t)(k & cmask);
+    int m = (int)(k >> (lev_bits + cell_bits));
+    int32_t L = (int32_t)((k >> cell_bits) & ((1ull << lev_bits) - 1));
+    bool head = i == 0 || (keys[i - 1] >> cell_bits) != (k >> cell_bits);
+    if (head) {
+        starts[(int64_t)m * (Lcap + 1) + L] = i - (int64_t)m * nc;
+        atomicMax(&nlev[m], L + 1);
+    }
+}
+
+static int bits_for(int64_t n) {
+    int b = 1;
+    while ((1ll << b) < n) ++b;
+    return b;
+}
+
+template <int NF, int DIM>
+static int64_t run_levels(Graph &g, const LagView &lag, DevBuf &cnt, DevBuf &fa, DevBuf &fb, DevBuf &ctr,
+                          int32_t *maxL, hipStream_t s) {
+    using Rec = CellRec<double, NF, DIM>;
+    const int64_t N = g.nc * g.nd;
+    const int B = 256;
+    uint32_t *counters = ctr.as<uint32_t>();
+    JSW_HIP(hipMemsetAsync(counters, 0, 8, s));
+    k_counts<NF, DIM><<<(int)ceil_div(N, B), B, 0, s>>>(g.rec64.as<Rec>(), g.omega64.as<double>(), g.nc, g.nd, lag,
+                                                       cnt.as<int32_t>(), g.level.as<int32_t>(), fa.as<uint32_t>(),
+                                                       counters);
+    JSW_HIP(hipGetLastError());
+    uint32_t n_front = 0;
+    JSW_HIP(hipMemcpyAsync(&n_front, counters, 4, hipMemcpyDeviceToHost, s));
+    JSW_HIP(hipStreamSynchronize(s));
+    int64_t done = 0;
+    int32_t L = 0;
+    uint32_t *cur = fa.as<uint32_t>(), *nxt = fb.as<uint32_t>();
+    while (n_front > 0) {
+        done += n_front;
+        JSW_HIP(hipMemsetAsync(counters + 1, 0, 4, s));
+        k_level_step<NF, DIM><<<(int)ceil_div(n_front, B), B, 0, s>>>(g.rec64.as<Rec>(), g.omega64.as<double>(), g.nc,
+                                                                     lag, cur, n_front, L, cnt.as<int32_t>(),
+                                                                     g.level.as<int32_t>(), nxt, counters + 1);
+        JSW_HIP(hipGetLastError());
+        JSW_HIP(hipMemcpyAsync(&n_front, counters + 1, 4, hipMemcpyDeviceToHost, s));
+        JSW_HIP(hipStreamSynchronize(s));
+        if (n_front) ++L;
+        std::swap(cur, nxt);
+    }
+    *maxL = L;
+    return done;
+}
+
+// Tarjan's strongly connected components on a small host graph
+static void tarjan_small(int n, const std::vector<std::vector<int>> &adj, std::vector<int> &comp, std::vector<int> &csize) {
+    std::vector<int> idx(n, -1), low(n, 0), stk;
+    std::vector<char> on(n, 0);
+    std::vector<std::pair<int, size_t>> call;
+    int counter = 0;
+    comp.assign(n, -1);
+    csize.clear();
+    for (int s0 = 0; s0 < n; ++s0) {
+        if (idx[s0] >= 0) continue;
+        call.push_back({s0, 0});
+        idx[s0] = low[s0] = counter++;
+        stk.push_back(s0);
+        on[s0] = 1;
+        while (!call.empty()) {
+            int v = call.back().first;
+            size_t &it = call.back().second;
+            if (it < adj[v].size()) {
+                int w = adj[v][it++];
+                if (idx[w] < 0) {
+                    idx[w] = low[w] = counter++;
+                    stk.push_back(w);
+                    on[w] = 1;
+                    call.push_back({w, 0});
+                } else if (on[w]) {
+                    low[v] = std::min(low[v], idx[w]);
+                }
+            } else {
+                if (low[v] == idx[v]) {
+                    int c = (int)csize.size(), sz = 0, w;
+                    do { w = stk.back(); stk.pop_back(); on[w] = 0; comp[w] = c; ++sz; } while (w != v);
+                    csize.push_back(sz);
+                }
+                call.pop_back();
+                if (!call.empty()) low[call.back().first] = std::min(low[call.back().first], low[v]);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// coarsened graph (paper Sec. V-E): clusters are the work-list chunks, and a
+// chunk's in-edges are the distinct chunks holding its vertices' upwind
+// neighbours (lagged edges excluded).  Every such chunk has a lower level,
+// hence comes earlier in the stream: the coarsened graph is acyclic.
+// ---------------------------------------------------------------------------
+__global__ void k_chunk_pos(const Chunk *chunks, int64_t n_chunks, const int32_t *lvl_cells, int64_t nc, int32_t *pos) {
+    int64_t c = blockIdx.x;
+    int lane = threadIdx.x;
+    if (c >= n_chunks) return;
+    Chunk ch = chunks[c];
+    int m = (int)(ch.a & 0xffffu), cnt = (int)(ch.a >> 16) + 1;
+    if (lane < cnt) {
+        int64_t base = (int64_t)m * nc;
+        pos[base + lvl_cells[base + ch.b + lane]] = (int32_t)c;
+    }
+}
+
+// one 64-lane workgroup per chunk: gather the upwind chunks of its
+// vertices and keep the first occurrence of each; WRITE = 0 counts them
+template <int NF, int DIM, bool WRITE>
+__global__ void k_chunk_deps(const Chunk *chunks, int64_t n_chunks, const int32_t *lvl_cells,
+                             const CellRec<double, NF, DIM> *rec, const double *omega, int64_t nc, LagView lag,
+                             const int32_t *pos, int32_t *count, const int32_t *ptr, int32_t *dep) {
+    __shared__ int32_t cand[64 * NF];
+    int64_t c = blockIdx.x;
+    int lane = threadIdx.x;
+    Chunk ch = chunks[c];
+    int m = (int)(ch.a & 0xffffu), cnt = (int)(ch.a >> 16) + 1;
+    int64_t base = (int64_t)m * nc;
+    for (int j = 0; j < NF; ++j) cand[lane * NF + j] = -1;
+    if (lane < cnt) {
+        int64_t K = lvl_cells[base + ch.b + lane];
+        CellRec<double, NF, DIM> r = rec[K];
+        const double om[3] = {omega[3 * m], omega[3 * m + 1], omega[3 * m + 2]};
+        for (int j = 0; j < NF; ++j) {
+            int32_t code = r.nbr[j];
+            if (code == -1 || !(out_dot(r, j, om) < 0.0)) continue;
+            int64_t u = nbr_id(code);
+            if (code <= -2 && is_lagged(lag.mv, lag.u, lag.n, m, K, u)) continue;
+            cand[lane * NF + j] = pos[base + u];
+        }
+    }
+    __syncthreads();
+    int32_t total = 0;
+    for (int i0 = 0; i0 < 64 * NF; i0 += 64) {
+        int i = i0 + lane;
+        int32_t v = cand[i];
+        bool keep = v >= 0;
+        for (int k = 0; k < i && keep; ++k) keep = cand[k] != v;
+        uint64_t mask = __ballot(keep);
+        if (WRITE && keep) dep[ptr[c] + total + __popcll(mask & ((1ull << lane) - 1))] = v;
+        total += __popcll(mask);
+    }
+    if (!WRITE && lane == 0) count[c] = total;
+}
+
+__global__ void k_exclusive_to_ptr(const int32_t *incl, int64_t n, int32_t *ptr) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) ptr[0] = 0;
+    if (i < n) ptr[i + 1] = incl[i];
+}
+
+template <int NF, int DIM>
+static void build_coarsened(Graph &g, const LagView &lag, hipStream_t s) {
+    using Rec = CellRec<double, NF, DIM>;
+    const int64_t N = g.nc * g.nd, nch = g.n_chunks;
+    DevBuf pos(4 * N), count(4 * std::max<int64_t>(1, nch)), incl(4 * std::max<int64_t>(1, nch));
+    g.dep_ptr.alloc(4 * (nch + 1));
+    k_chunk_pos<<<(unsigned)nch, 64, 0, s>>>(g.chunks.as<Chunk>(), nch, g.lvl_cells.as<int32_t>(), g.nc, pos.as<int32_t>());
+    JSW_HIP(hipGetLastError());
+    k_chunk_deps<NF, DIM, false><<<(unsigned)nch, 64, 0, s>>>(g.chunks.as<Chunk>(), nch, g.lvl_cells.as<int32_t>(),
+                                                              g.rec64.as<Rec>(), g.omega64.as<double>(), g.nc, lag,
+                                                              pos.as<int32_t>(), count.as<int32_t>(), nullptr, nullptr);
+    JSW_HIP(hipGetLastError());
+    size_t tmp_bytes = 0;
+    JSW_HIP(rocprim::inclusive_scan(nullptr, tmp_bytes, count.as<int32_t>(), incl.as<int32_t>(), (size_t)nch,
+                                    rocprim::plus<int32_t>(), s));
+    {
+        DevBuf tmp(tmp_bytes + 16);
+        JSW_HIP(rocprim::inclusive_scan(tmp.p, tmp_bytes, count.as<int32_t>(), incl.as<int32_t>(), (size_t)nch,
+                                        rocprim::plus<int32_t>(), s));
+    }
+    k_exclusive_to_ptr<<<(int)ceil_div(nch, 256), 256, 0, s>>>(incl.as<int32_t>(), nch, g.dep_ptr.as<int32_t>());
+    JSW_HIP(hipGetLastError());
+    int32_t total = 0;
+    JSW_HIP(hipMemcpyAsync(&total, incl.as<int32_t>() + (nch - 1), 4, hipMemcpyDeviceToHost, s));
+    JSW_HIP(hipStreamSynchronize(s));
+    g.n_dep = total;
+    g.dep.alloc(4 * std::max<int64_t>(1, total));
+    k_chunk_deps<NF, DIM, true><<<(unsigned)nch, 64, 0, s>>>(g.chunks.as<Chunk>(), nch, g.lvl_cells.as<int32_t>(),
+                                                             g.rec64.as<Rec>(), g.omega64.as<double>(), g.nc, lag,
+                                                             pos.as<int32_t>(), nullptr, g.dep_ptr.as<int32_t>(),
+                                                             g.dep.as<int32_t>());
+    JSW_HIP(hipGetLastError());
+    JSW_HIP(hipStreamSynchronize(s));
+}
+
+template <int NF, int DIM>
+static void dag_impl(Graph &g, bool lag_cycles, hipStream_t s) {
+    using Rec = CellRec<double, NF, DIM>;
+    const int64_t nc = g.nc, N = nc * g.nd;
+    const int B = 256;
+    g.level.alloc(4 * N);
+    DevBuf cnt(4 * N), fa(4 * N), fb(4 * N), ctr(16);
+    LagView lag{nullptr, nullptr, 0};
+    int32_t maxL = 0;
+    int64_t done = run_levels<NF, DIM>(g, lag, cnt, fa, fb, ctr, &maxL, s);
+    if (done < N) {
+        // cycles: trim everything that is only downstream of a cycle, then
+        // find the strongly connected components of the small remainder
+        if (!lag_cycles) fail(JSWEEP_E_CYCLE, "the sweep graph has a cycle and lagging is disabled");
+        uint32_t *counters = ctr.as<uint32_t>();
+        JSW_HIP(hipMemsetAsync(counters, 0, 8, s));
+        k_trim_init<NF, DIM><<<(int)ceil_div(N, B), B, 0, s>>>(g.rec64.as<Rec>(), g.omega64.as<double>(), nc, g.nd,
+                                                              g.level.as<int32_t>(), cnt.as<int32_t>(),
+                                                              fa.as<uint32_t>(), counters);
+        JSW_HIP(hipGetLastError());
+        uint32_t n_front = 0;
+        JSW_HIP(hipMemcpyAsync(&n_front, counters, 4, hipMemcpyDeviceToHost, s));
+        JSW_HIP(hipStreamSynchronize(s));
+        uint32_t *cur = fa.as<uint32_t>(), *nxt = fb.as<uint32_t>();
+        if (n_front) k_trim_mark<<<(int)ceil_div(n_front, B), B, 0, s>>>(cur, n_front, g.level.as<int32_t>());
+        while (n_front > 0) {
+            JSW_HIP(hipMemsetAsync(counters + 1, 0, 4, s));
+            k_trim_step<NF, DIM><<<(int)ceil_div(n_front, B), B, 0, s>>>(g.rec64.as<Rec>(), g.omega64.as<double>(), nc,
+                                                                        cur, n_front, g.level.as<int32_t>(),
+                                                                        cnt.as<int32_t>(), nxt, counters + 1);
+            JSW_HIP(hipGetLastError());
+            JSW_HIP(hipMemcpyAsync(&n_front, counters + 1, 4, hipMemcpyDeviceToHost, s));
+            JSW_HIP(hipStreamSynchronize(s));
+            std::swap(cur, nxt);
+        }
+        uint32_t cap = (uint32_t)std::min<int64_t>(N * NF, (int64_t)1 << 28);
+        DevBuf edges(12ull * cap);
+        JSW_HIP(hipMemsetAsync(counters + 2, 0, 4, s));
+        k_core_edges<NF, DIM><<<(int)ceil_div(N, B), B, 0, s>>>(g.rec64.as<Rec>(), g.omega64.as<double>(), nc, g.nd,
+                                                               g.level.as<int32_t>(), edges.as<uint32_t>(),
+                                                               counters + 2, cap);
+        JSW_HIP(hipGetLastError());
+        uint32_t ne = 0;
+        JSW_HIP(hipMemcpyAsync(&ne, counters + 2, 4, hipMemcpyDeviceToHost, s));
+        JSW_HIP(hipStreamSynchronize(s));
+        if (ne > cap) fail(JSWEEP_E_OOM, "too many cyclic edges");
+        std::vector<uint32_t> he(3ull * ne);
+        if (ne) JSW_HIP(hipMemcpy(he.data(), edges.p, 12ull * ne, hipMemcpyDeviceToHost));
+        // per direction: SCCs; lag u -> v with u > v inside a non-trivial one
+        std::vector<size_t> order(ne);
+        for (size_t e = 0; e < ne; ++e) order[e] = e;
+        std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return he[3 * a] < he[3 * b]; });
+        struct LagRec { uint32_t m; int64_t v, u; };
+        std::vector<LagRec> lags;
+        for (size_t a = 0; a < ne;) {
+            size_t b = a;
+            uint32_t m = he[3 * order[a]];
+            while (b < ne && he[3 * order[b]] == m) ++b;
+            std::vector<int64_t> ids;
+            for (size_t e = a; e < b; ++e) { ids.push_back(he[3 * order[e] + 1]); ids.push_back(he[3 * order[e] + 2]); }
+            std::sort(ids.begin(), ids.end());
+            ids.erase(std::unique(ids.begin(), ids.end()), ids.end());
+            auto loc = [&](int64_t x) { return (int)(std::lower_bound(ids.begin(), ids.end(), x) - ids.begin()); };
+            std::vector<std::vector<int>> adj(ids.size());
+            for (size_t e = a; e < b; ++e) adj[loc(he[3 * order[e] + 1])].push_back(loc(he[3 * order[e] + 2]));
+            std::vector<int> comp, csize;
+            tarjan_small((int)ids.size(), adj, comp, csize);
+            for (size_t e = a; e < b; ++e) {
+                int64_t u = he[3 * order[e] + 1], v = he[3 * order[e] + 2];
+                int cu = comp[loc(u)], cv = comp[loc(v)];
+                if (cu == cv && csize[cu] > 1 && u > v) lags.push_back({m, v, u});
+            }
+            a = b;
+        }
+        std::sort(lags.begin(), lags.end(), [](const LagRec &x, const LagRec &y) {
+            if (x.m != y.m) return x.m < y.m;
+            if (x.v != y.v) return x.v < y.v;
+            return x.u < y.u;
+        });
+        g.n_lag = (int64_t)lags.size();
+        if (g.n_lag == 0) fail(JSWEEP_E_DEVICE, "unlevelled vertices without a cycle");
+        std::vector<uint64_t> mv(g.n_lag);
+        std::vector<int32_t> uu(g.n_lag);
+        for (int64_t e = 0; e < g.n_lag; ++e) {
+            mv[e] = ((uint64_t)lags[e].m << 32) | (uint64_t)lags[e].v;
+            uu[e] = (int32_t)lags[e].u;
+        }
+        g.lag_mv.alloc(8 * g.n_lag);
+        g.lag_u.alloc(4 * g.n_lag);
+        JSW_HIP(hipMemcpyAsync(g.lag_mv.p, mv.data(), 8 * g.n_lag, hipMemcpyHostToDevice, s));
+        JSW_HIP(hipMemcpyAsync(g.lag_u.p, uu.data(), 4 * g.n_lag, hipMemcpyHostToDevice, s));
+        k_mark_lag<NF, DIM><<<(int)ceil_div(g.n_lag, B), B, 0, s>>>(g.rec64.as<Rec>(), g.lag_mv.as<uint64_t>(),
+                                                                   g.lag_u.as<int32_t>(), g.n_lag);
+        JSW_HIP(hipGetLastError());
+        g.lag_m_h.resize(g.n_lag);
+        g.lag_u_h.resize(g.n_lag);
+        g.lag_v_h.resize(g.n_lag);
+        for (int64_t e = 0; e < g.n_lag; ++e) {
+            g.lag_m_h[e] = (int32_t)lags[e].m;
+            g.lag_u_h[e] = lags[e].u;
+            g.lag_v_h[e] = lags[e].v;
+        }
+        lag = LagView{g.lag_mv.as<uint64_t>(), g.lag_u.as<int32_t>(), g.n_lag};
+        done = run_levels<NF, DIM>(g, lag, cnt, fa, fb, ctr, &maxL, s);
+        if (done < N) fail(JSWEEP_E_DEVICE, "cycles remain after lagging");
+        g.lag_val64.alloc(8 * g.n_lag);
+        g.lag_val32.alloc(4 * g.n_lag);
+    }
+    cnt.release();
+    fb.release();
+    // level-ordered cell lists: sort (direction, level, cell) keys
+    const int cell_bits = bits_for(nc + 1), lev_bits = bits_for((int64_t)maxL + 2), dir_bits = bits_for(g.nd + 1);
+    if (cell_bits + lev_bits + dir_bits > 64) fail(JSWEEP_E_INVALID_ARG, "graph too large for 64-bit level keys");
+    DevBuf keys(8 * N), keys2(8 * N);
+    k_level_keys<<<(int)ceil_div(N, B), B, 0, s>>>(g.level.as<int32_t>(), nc, g.nd, cell_bits, lev_bits,
+                                                   keys.as<uint64_t>());
+    JSW_HIP(hipGetLastError());
+    size_t tmp_bytes = 0;
+    unsigned end_bit = (unsigned)(cell_bits + lev_bits + dir_bits);
+    JSW_HIP(rocprim::radix_sort_keys(nullptr, tmp_bytes, keys.as<uint64_t>(), keys2.as<uint64_t>(), (size_t)N, 0u,
+                                     end_bit, s));
+    {
+        DevBuf tmp(tmp_bytes + 16);
+        JSW_HIP(rocprim::radix_sort_keys(tmp.p, tmp_bytes, keys.as<uint64_t>(), keys2.as<uint64_t>(), (size_t)N, 0u,
+                                         end_bit, s));
+    }
+    keys.release();
+    g.lvl_cells.alloc(4 * N);
+    const int32_t Lcap = maxL + 1;
+    DevBuf starts(8 * (int64_t)g.nd * (Lcap + 1)), nlev(4 * g.nd);
+    JSW_HIP(hipMemsetAsync(nlev.p, 0, 4 * g.nd, s));
+    k_level_bounds<<<(int)ceil_div(N, B), B, 0, s>>>(keys2.as<uint64_t>(), nc, g.nd, cell_bits, lev_bits, Lcap,
+                                                     g.lvl_cells.as<int32_t>(), starts.as<int64_t>(), nlev.as<int32_t>());
+    JSW_HIP(hipGetLastError());
+    std::vector<int64_t> hstarts((size_t)g.nd * (Lcap + 1));
+    g.nlev_h.resize(g.nd);
+    JSW_HIP(hipMemcpyAsync(hstarts.data(), starts.p, starts.bytes, hipMemcpyDeviceToHost, s));
+    JSW_HIP(hipMemcpyAsync(g.nlev_h.data(), nlev.p, 4 * g.nd, hipMemcpyDeviceToHost, s));
+    JSW_HIP(hipStreamSynchronize(s));
+    g.lvl_off_h.assign(g.nd + 1, 0);
+    g.max_levels = 0;
+    for (int m = 0; m < g.nd; ++m) {
+        g.lvl_off_h[m + 1] = g.lvl_off_h[m] + g.nlev_h[m] + 1;
+        g.max_levels = std::max(g.max_levels, g.nlev_h[m]);
+    }
+    g.lvl_ptr_h.resize(g.lvl_off_h[g.nd]);
+    for (int m = 0; m < g.nd; ++m) {
+        int64_t *p = g.lvl_ptr_h.data() + g.lvl_off_h[m];
+        for (int L = 0; L < g.nlev_h[m]; ++L) p[L] = hstarts[(size_t)m * (Lcap + 1) + L];
+        p[g.nlev_h[m]] = nc;
+    }
+    // sweep work list: chunks of <= 64 cells of one (level, direction).
+    // Directions are dealt to kStreams streams in contiguous blocks (with
+    // octant-major quadratures a block is an octant); within a stream the
+    // chunks are ordered by level, then direction -- a topological order of
+    // every direction of the stream at once.
+    g.dir_stream_h.resize(g.nd);
+    for (int m = 0; m < g.nd; ++m) g.dir_stream_h[m] = (int32_t)(((int64_t)m * kStreams) / g.nd);
+    std::vector<Chunk> ch;
+    ch.reserve((size_t)(N / 64 + (int64_t)g.nd * g.max_levels));
+    g.stream_off_h.assign(kStreams + 1, 0);
+    for (int sidx = 0; sidx < kStreams; ++sidx) {
+        g.stream_off_h[sidx] = (int64_t)ch.size();
+        for (int L = 0; L < g.max_levels; ++L)
+            for (int m = 0; m < g.nd; ++m) {
+                if (g.dir_stream_h[m] != sidx || L >= g.nlev_h[m]) continue;
+                const int64_t *p = g.lvl_ptr_h.data() + g.lvl_off_h[m];
+                for (int64_t o = p[L]; o < p[L + 1]; o += 64) {
+                    int64_t c = std::min<int64_t>(64, p[L + 1] - o);
+                    ch.push_back(Chunk{(uint32_t)m | ((uint32_t)(c - 1) << 16), (uint32_t)o});
+                }
+            }
+    }
+    g.stream_off_h[kStreams] = (int64_t)ch.size();
+    g.n_chunks = (int64_t)ch.size();
+    g.chunks.alloc(sizeof(Chunk) * std::max<int64_t>(1, g.n_chunks));
+    JSW_HIP(hipMemcpyAsync(g.chunks.p, ch.data(), sizeof(Chunk) * g.n_chunks, hipMemcpyHostToDevice, s));
+    g.stream_off.alloc(8 * (kStreams + 1));
+    JSW_HIP(hipMemcpyAsync(g.stream_off.p, g.stream_off_h.data(), 8 * (kStreams + 1), hipMemcpyHostToDevice, s));
+    build_coarsened<NF, DIM>(g, lag, s);
+    g.cflag.alloc(std::max<int64_t>(1, g.n_chunks));
+    JSW_HIP(hipMemsetAsync(g.cflag.p, 0, g.cflag.bytes, s));
+    g.epoch = 0;
+    g.status.alloc(128 + 32 * 4 * 8);   // status words, then 8 ticket counters 128 B apart
+    JSW_HIP(hipMemsetAsync(g.status.p, 0, g.status.bytes, s));
+    JSW_HIP(hipStreamSynchronize(s));
+}
+
+void build_dag(Graph &g, bool lag_cycles, hipStream_t s) {
+    if ((int64_t)g.nc * g.nd >= (int64_t)1 << 32) fail(JSWEEP_E_INVALID_ARG, "n_cells * n_dirs must be below 2^32");
+    if (g.ctype == JSWEEP_TRI) dag_impl<3, 2>(g, lag_cycles, s);
+    else if (g.ctype == JSWEEP_TET) dag_impl<4, 3>(g, lag_cycles, s);
+    else dag_impl<6, 3>(g, lag_cycles, s);
+}
+
+}  // namespace jsw

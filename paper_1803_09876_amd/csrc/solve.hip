@@ -1,0 +1,283 @@
+// Source iteration around the sweep (appendix algorithm "Source iterative
+// Sn solver": update the scattering source, sweep every direction, reduce
+// the error, repeat), in plain FP64 and as FP64 iterative refinement with
+// FP32 correction sweeps.
+#include <cstring>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "common.hpp"
+
+namespace jsw {
+
+constexpr int kB = 256;
+
+// sigma_t * V into the sweep records (FP64 product; FP32 records take it
+// rounded)
+template <int NF, int DIM>
+__global__ void k_sigv(CellRec<double, NF, DIM> *r64, CellRec<float, NF, DIM> *r32, const double *sigma_t, int64_t nc) {
+    int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (K >= nc) return;
+    double v = sigma_t[K] * r64[K].V;
+    r64[K].sigV = v;
+    if (r32) r32[K].sigV = (float)v;
+}
+
+void refresh_sigma(Graph &g, const double *sigma_t, bool fp32, hipStream_t s) {
+    if (fp32) build_rec32(g, s);
+    int gb = (int)ceil_div(g.nc, kB);
+    void *r32 = fp32 ? g.rec32.p : nullptr;
+    if (g.ctype == JSWEEP_TRI)
+        k_sigv<3, 2><<<gb, kB, 0, s>>>(g.rec64.as<CellRec<double, 3, 2>>(), (CellRec<float, 3, 2> *)r32, sigma_t, g.nc);
+    else if (g.ctype == JSWEEP_TET)
+        k_sigv<4, 3><<<gb, kB, 0, s>>>(g.rec64.as<CellRec<double, 4, 3>>(), (CellRec<float, 4, 3> *)r32, sigma_t, g.nc);
+    else
+        k_sigv<6, 3><<<gb, kB, 0, s>>>(g.rec64.as<CellRec<double, 6, 3>>(), (CellRec<float, 6, 3> *)r32, sigma_t, g.nc);
+    JSW_HIP(hipGetLastError());
+}
+
+// s_K = q_K + sigma_s,K phi_K
+__global__ void k_source(const double *q, const double *sigma_s, const double *phi, int64_t nc, double *src) {
+    int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (K < nc) src[K] = q[K] + sigma_s[K] * phi[K];
+}
+
+// phi_K = sum_m w_m psi_{K,m}, ascending m
+__global__ void k_phi(const double *psi, const double *w, int64_t nc, int nd, double *phi) {
+    int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (K >= nc) return;
+    double s = 0.0;
+    for (int m = 0; m < nd; ++m) s = s + w[m] * psi[(int64_t)m * nc + K];
+    phi[K] = s;
+}
+
+void scalar_flux(Graph &g, const double *psi, double *phi, hipStream_t s) {
+    k_phi<<<(int)ceil_div(g.nc, kB), kB, 0, s>>>(psi, g.weight.as<double>(), g.nc, g.nd, phi);
+    JSW_HIP(hipGetLastError());
+}
+
+// previous-iterate values on lagged edges (taken before a sweep overwrites)
+template <class Real>
+__global__ void k_lag_snapshot(const uint64_t *lag_mv, const int32_t *lag_u, int64_t n, const Real *psi, int64_t nc,
+                               Real *val) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    int64_t m = (int64_t)(lag_mv[e] >> 32);
+    val[e] = psi[m * nc + lag_u[e]];
+}
+
+template <class Real>
+static void lag_snapshot(Graph &g, const Real *psi, hipStream_t s) {
+    if (!g.n_lag) return;
+    Real *val = sizeof(Real) == 8 ? (Real *)g.lag_val64.p : (Real *)g.lag_val32.p;
+    k_lag_snapshot<Real><<<(int)ceil_div(g.n_lag, kB), kB, 0, s>>>(g.lag_mv.as<uint64_t>(), g.lag_u.as<int32_t>(),
+                                                                  g.n_lag, psi, g.nc, val);
+    JSW_HIP(hipGetLastError());
+}
+
+void lag_snapshot64(Graph &g, const double *psi, hipStream_t s) { lag_snapshot<double>(g, psi, s); }
+
+__device__ inline void block_add(double v, double *out) {
+    __shared__ double red[16];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+    int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
+        atomicAdd(out, t);
+    }
+}
+
+// FP64 residual with the full (un-lagged) streaming operator, one cell per
+// thread looping over directions (the cell record is read once per pass):
+//   phi_K = sum_m w_m psi_{K,m}
+//   r_{K,m} = q_K + sigma_s,K phi_K - (den psi_{K,m} - in_{K,m}) / V_K
+// norms: acc[0] += V_K sum_m w_m r^2, acc[1] += V_K q_K^2.  Optionally stores
+// r in FP32 (the correction-sweep source).
+template <int NF, int DIM>
+__global__ void k_residual(const CellRec<double, NF, DIM> *rec, const double *omega, const double *w, const double *psi,
+                           const double *q, const double *sigma_s, double psi_b, int64_t nc, int nd, double *phi,
+                           float *r32, double *acc) {
+    int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double rr = 0.0, qq = 0.0;
+    if (K < nc) {
+        const CellRec<double, NF, DIM> r = rec[K];
+        int64_t nb[NF];
+        for (int j = 0; j < NF; ++j) nb[j] = r.nbr[j] <= -2 ? (int64_t)(-r.nbr[j] - 2) : (int64_t)r.nbr[j];
+        double ph = 0.0;
+        for (int m = 0; m < nd; ++m) ph = ph + w[m] * psi[(int64_t)m * nc + K];
+        phi[K] = ph;
+        const double src = q[K] + sigma_s[K] * ph;
+        double cell = 0.0;
+        for (int m = 0; m < nd; ++m) {
+            const double *om = omega + 3 * m;
+            const double *pm = psi + (int64_t)m * nc;
+            double in = 0.0, den = r.sigV;
+            for (int j = 0; j < NF; ++j) {
+                double d = om[0] * r.S[j][0] + om[1] * r.S[j][1];
+                if constexpr (DIM == 3) d = d + om[2] * r.S[j][2];
+                if (d < 0.0) in = in + (-d) * (nb[j] < 0 ? psi_b : pm[nb[j]]);
+                else if (d > 0.0) den = den + d;
+            }
+            double res = src - (den * pm[K] - in) / r.V;
+            if (r32) r32[(int64_t)m * nc + K] = (float)res;
+            cell = cell + w[m] * (res * res);
+        }
+        rr = r.V * cell;
+        qq = r.V * (q[K] * q[K]);
+    }
+    block_add(rr, acc);
+    block_add(qq, acc + 1);
+}
+
+// delta-phi of a correction iterate (FP64 accumulation of FP32 fluxes), the
+// FP32 scattering source sigma_s dphi for the next inner sweep, and the
+// V-weighted norms of dphi and of its change
+__global__ void k_dphi(const float *dpsi, const double *w, const double *sigma_s, const double *vol, int64_t nc, int nd,
+                       double *dphi, float *g32, double *acc) {
+    int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double a = 0.0, b = 0.0;
+    if (K < nc) {
+        double s = 0.0;
+        for (int m = 0; m < nd; ++m) s = s + w[m] * (double)dpsi[(int64_t)m * nc + K];
+        double old = dphi[K];
+        dphi[K] = s;
+        g32[K] = (float)(sigma_s[K] * s);
+        a = vol[K] * (s * s);
+        b = vol[K] * ((s - old) * (s - old));
+    }
+    block_add(a, acc);
+    block_add(b, acc + 1);
+}
+
+// psi += dpsi (FP64)
+__global__ void k_update(double *psi, const float *dpsi, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) psi[i] = psi[i] + (double)dpsi[i];
+}
+
+static double residual(Graph &g, const double *psi, const double *q, const double *sigma_s, double psi_b, double *phi,
+                       float *r32, double *acc, hipStream_t s) {
+    JSW_HIP(hipMemsetAsync(acc, 0, 16, s));
+    int gb = (int)ceil_div(g.nc, kB);
+    const double *om = g.omega64.as<double>(), *w = g.weight.as<double>();
+    if (g.ctype == JSWEEP_TRI)
+        k_residual<3, 2><<<gb, kB, 0, s>>>(g.rec64.as<CellRec<double, 3, 2>>(), om, w, psi, q, sigma_s, psi_b, g.nc, g.nd, phi, r32, acc);
+    else if (g.ctype == JSWEEP_TET)
+        k_residual<4, 3><<<gb, kB, 0, s>>>(g.rec64.as<CellRec<double, 4, 3>>(), om, w, psi, q, sigma_s, psi_b, g.nc, g.nd, phi, r32, acc);
+    else
+        k_residual<6, 3><<<gb, kB, 0, s>>>(g.rec64.as<CellRec<double, 6, 3>>(), om, w, psi, q, sigma_s, psi_b, g.nc, g.nd, phi, r32, acc);
+    JSW_HIP(hipGetLastError());
+    double h[2];
+    JSW_HIP(hipMemcpyAsync(h, acc, 16, hipMemcpyDeviceToHost, s));
+    JSW_HIP(hipStreamSynchronize(s));
+    return h[1] > 0.0 ? std::sqrt(h[0]) / std::sqrt(h[1]) : std::sqrt(h[0]);
+}
+
+static void ensure(DevBuf &b, size_t bytes) {
+    if (b.bytes < bytes) b.alloc(bytes);
+}
+
+int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *q, double psi_b, int32_t mode,
+          double tol, int32_t max_iter, const jsweep_params *params, double *phi, double *psi_out,
+          jsweep_solve_stats *stats, hipStream_t s) {
+    auto t_start = std::chrono::steady_clock::now();
+    const bool refined = (mode & 0xff) == JSWEEP_FP32_REFINED;
+    const bool warm = (mode & JSWEEP_WARM_START) != 0;
+    const int64_t N = g.nc * g.nd;
+    // scratch: psi (if the caller gives none), source / dphi, accumulators
+    double *psi = psi_out;
+    if (!psi) { ensure(g.scratch_a, 8 * N); psi = g.scratch_a.as<double>(); }
+    ensure(g.scratch_b, 8 * g.nc + 64);
+    double *src = g.scratch_b.as<double>();
+    double *acc = src + g.nc + 2;   // 16-byte aligned tail, 4 doubles
+    if (((uintptr_t)acc & 15) != 0) acc += 1;
+    if (!warm || !psi_out) JSW_HIP(hipMemsetAsync(psi, 0, 8 * N, s));
+    refresh_sigma(g, sigma_t, refined, s);
+    int outer = 0, sweeps = 0, hist = 0, rc = JSWEEP_OK;
+    double rho = INFINITY;
+    auto record = [&](double v) {
+        if (stats && stats->residual_history && hist < stats->history_capacity) stats->residual_history[hist] = v;
+        ++hist;
+    };
+    if (!refined) {
+        // phi of the initial iterate
+        scalar_flux(g, psi, phi, s);
+        while (true) {
+            if (sweeps >= max_iter) { rc = JSWEEP_E_NOT_CONVERGED; break; }
+            k_source<<<(int)ceil_div(g.nc, kB), kB, 0, s>>>(q, sigma_s, phi, g.nc, src);
+            JSW_HIP(hipGetLastError());
+            lag_snapshot<double>(g, psi, s);
+            launch_sweep64(g, src, psi, psi_b, params, s);
+            ++sweeps;
+            rho = residual(g, psi, q, sigma_s, psi_b, phi, nullptr, acc, s);
+            ++outer;
+            record(rho);
+            int st = check_sweep_status(g, s);
+            if (st) return st;
+            if (rho <= tol) break;
+        }
+    } else {
+        ensure(g.scratch_c, 4 * N * 2 + 64);            // r32 and dpsi32
+        float *r32 = g.scratch_c.as<float>();
+        float *dpsi = r32 + N;
+        ensure(g.scratch_d, 16 * g.nc + 64);           // dphi (double), g32 (float)
+        double *dphi = g.scratch_d.as<double>();
+        float *g32 = reinterpret_cast<float *>(dphi + g.nc);
+        int J = (params && params->inner_sweeps > 0) ? params->inner_sweeps
+                : (g.has_tuned && g.tuned.inner_sweeps > 0 ? g.tuned.inner_sweeps : 400);
+        while (true) {
+            rho = residual(g, psi, q, sigma_s, psi_b, phi, r32, acc, s);
+            ++outer;
+            record(rho);
+            if (rho <= tol) break;
+            if (sweeps >= max_iter) { rc = JSWEEP_E_NOT_CONVERGED; break; }
+            // inner source iteration on the correction in FP32
+            JSW_HIP(hipMemsetAsync(dpsi, 0, 4 * N, s));
+            JSW_HIP(hipMemsetAsync(dphi, 0, 8 * g.nc, s));
+            JSW_HIP(hipMemsetAsync(g32, 0, 4 * g.nc, s));
+            const double eta = std::max(3e-7, 0.3 * tol / rho);
+            double prev_change = -1.0;
+            for (int j = 0; j < J && sweeps < max_iter; ++j) {
+                lag_snapshot<float>(g, dpsi, s);
+                launch_sweep32(g, r32, g32, dpsi, params, s);
+                ++sweeps;
+                JSW_HIP(hipMemsetAsync(acc + 2, 0, 16, s));
+                k_dphi<<<(int)ceil_div(g.nc, kB), kB, 0, s>>>(dpsi, g.weight.as<double>(), sigma_s, g.vol.as<double>(),
+                                                           g.nc, g.nd, dphi, g32, acc + 2);
+                JSW_HIP(hipGetLastError());
+                double h[2];
+                JSW_HIP(hipMemcpyAsync(h, acc + 2, 16, hipMemcpyDeviceToHost, s));
+                JSW_HIP(hipStreamSynchronize(s));
+                int st = check_sweep_status(g, s);
+                if (st) return st;
+                double norm = std::sqrt(h[0]), change = std::sqrt(h[1]);
+                // estimated remaining error of the inner iteration from the
+                // observed contraction of successive changes
+                double ratio = prev_change > 0.0 ? std::min(change / prev_change, 0.999) : 0.999;
+                prev_change = change;
+                if (j > 0 && change * ratio / (1.0 - ratio) <= eta * norm) break;
+                if (norm == 0.0) break;
+            }
+            k_update<<<(int)ceil_div(N, kB), kB, 0, s>>>(psi, dpsi, N);
+            JSW_HIP(hipGetLastError());
+        }
+    }
+    JSW_HIP(hipStreamSynchronize(s));
+    if (stats) {
+        stats->outer_iters = outer;
+        stats->sweeps = sweeps;
+        stats->residual = rho;
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+        stats->lagged_edges = g.n_lag;
+        stats->max_levels = g.max_levels;
+        stats->history_len = std::min(hist, stats->history_capacity);
+    }
+    return rc;
+}
+
+}  // namespace jsw

@@ -1,0 +1,307 @@
+// Persistent data-driven transport sweep (gfx950).
+//
+// Work list: chunks of up to 64 vertices (cell, direction) of one level of
+// one direction.  Directions are dealt to kStreams streams; within a stream
+// the chunks are ordered by level, then direction, which is a topological
+// order of all of the stream's directions at once, so every direction is in
+// flight together (patch-angle parallelism, paper Sec. V-B).
+//
+// Coarsened graph (paper Sec. V-E): a chunk is a cluster of vertices, and
+// the sweep waits on chunk -> chunk dependencies (the union of its
+// vertices' upwind edges, lagged edges excluded) instead of on single
+// vertices.  Clusters of one level of an acyclic graph give an acyclic
+// coarsened graph (Theorem 1), and every dependency of a chunk comes earlier
+// in its stream.
+//
+// Execution: a persistent grid no larger than the device can hold at once.
+// A running wavefront takes the next chunks of its stream (workgroup id mod
+// kStreams, which is also the XCD the workgroup runs on) with one atomic
+// ticket, polls the completion flags of the chunk's dependencies, then
+// computes one vertex per lane and publishes the chunk's flag.  Only running
+// wavefronts hold chunks and every wavefront walks its stream in order, so
+// the first unfinished chunk of a stream always has all of its inputs: the
+// sweep cannot deadlock on an acyclic graph however many workgroups are
+// resident.  A watchdog turns anything else into an error instead of a
+// hang.
+//
+// Memory ordering across compute units and XCDs: fluxes and chunk flags are
+// written and read with device-coherent (agent-scope) accesses; a chunk's
+// flag is stored only after every lane's flux store has completed
+// (s_waitcnt), and a consumer loads fluxes only after it has seen the flag.
+// No cache writeback/invalidate fences are used in the loop.
+#include <cstring>
+
+#include <algorithm>
+#include <cstdlib>
+
+#include "common.hpp"
+
+namespace jsw {
+
+template <class Real, int NF, int DIM>
+struct SweepArgs {
+    const CellRec<Real, NF, DIM> *rec;
+    const CellRec<double, NF, DIM> *rec64;   // FP64 records: classification of near-parallel faces
+    const int32_t *lvl_cells;
+    const Chunk *chunks;
+    const int32_t *dep_ptr;                  // [n_chunks + 1] coarsened-graph in-edges
+    const int32_t *dep;                      // upwind chunks
+    int64_t nc;
+    const Real *omega;                       // [nd*3]
+    const double *omega64;                   // [nd*3]
+    const Real *src_cell;                    // [nc] or null
+    const float *src_dir;                    // [nd*nc] or null
+    Real *psi;                               // [nd*nc]
+    uint8_t *cflag;                          // [n_chunks] completion epochs
+    int32_t *status;                         // [0]: stalled flag
+    uint32_t *tickets;                       // per-stream counters, 128 B apart
+    const int64_t *stream_off;               // [kStreams + 1] chunk range of each stream
+    const uint64_t *lag_mv;
+    const int32_t *lag_u;
+    const Real *lag_val;
+    int64_t n_lag;
+    Real psi_b;
+    uint32_t epoch;
+    int32_t grab;                            // chunks taken per ticket
+    uint64_t watchdog_ticks;
+};
+
+template <class T>
+__device__ __forceinline__ T ld_coherent(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ void st_coherent(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline int64_t lag_index(const uint64_t *lag_mv, const int32_t *lag_u, int64_t n_lag, int m, int64_t v,
+                                    int64_t u) {
+    uint64_t key = ((uint64_t)(uint32_t)m << 32) | (uint64_t)v;
+    int64_t lo = 0, hi = n_lag;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (lag_mv[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    for (; lo < n_lag && lag_mv[lo] == key; ++lo)
+        if (lag_u[lo] == u) return lo;
+    return -1;
+}
+
+// Omega . S of local face j, evaluated left to right.  The FP32 path takes
+// the FP64 value whenever the FP32 result is too close to zero for its sign
+// to be certain, so both paths agree on which faces are inflow/outflow.
+template <class Real, int NF, int DIM>
+__device__ __forceinline__ Real face_dot(const CellRec<Real, NF, DIM> &r, int j, const Real *om,
+                                         const CellRec<double, NF, DIM> *rec64, int64_t K, const double *om64) {
+    Real d = om[0] * r.S[j][0] + om[1] * r.S[j][1];
+    if constexpr (DIM == 3) d = d + om[2] * r.S[j][2];
+    if constexpr (sizeof(Real) == 4) {
+        float mag = fabsf(om[0] * r.S[j][0]) + fabsf(om[1] * r.S[j][1]);
+        if constexpr (DIM == 3) mag = mag + fabsf(om[2] * r.S[j][2]);
+        if (fabsf(d) <= 2e-6f * mag) {
+            const double *S = rec64[K].S[j];
+            double e = om64[0] * S[0] + om64[1] * S[1];
+            if constexpr (DIM == 3) e = e + om64[2] * S[2];
+            d = (float)e;
+            if (e != 0.0 && d == 0.0) d = e > 0.0 ? 1e-38f : -1e-38f;
+        }
+    }
+    return d;
+}
+
+template <class Real, int NF, int DIM>
+__global__ void k_sweep(SweepArgs<Real, NF, DIM> a) {
+    const int lane = threadIdx.x & 63;
+    const int stream = (int)(blockIdx.x % kStreams);
+    const int64_t first = a.stream_off[stream];
+    const int64_t per_stream = a.stream_off[stream + 1] - first;
+    const uint8_t epoch = (uint8_t)a.epoch;
+    int64_t t_next = 0, t_end = 0;
+    // every lane stays in this loop until the wavefront leaves it as a whole
+    // (ticket broadcast, dependency poll and abort are wave-uniform)
+    while (true) {
+        if (t_next == t_end) {
+            uint32_t t = 0;
+            if (lane == 0) t = atomicAdd(a.tickets + 32 * stream, (uint32_t)a.grab);
+            t_next = __shfl(t, 0);
+            t_end = t_next + a.grab;
+        }
+        if (t_next >= per_stream) break;
+        const int64_t c = first + t_next;
+        ++t_next;
+        const Chunk ch = a.chunks[c];
+        const int m = (int)(ch.a & 0xffffu);
+        const int cnt = (int)(ch.a >> 16) + 1;
+        const bool active = lane < cnt;
+        const int64_t base = (int64_t)m * a.nc;
+        const int64_t K = active ? (int64_t)a.lvl_cells[base + ch.b + lane] : 0;
+        CellRec<Real, NF, DIM> r;
+        if (active) r = a.rec[K];
+        // wait until every upwind chunk of this sweep is complete
+        const int32_t d0 = a.dep_ptr[c], d1 = a.dep_ptr[c + 1];
+        uint64_t t0 = 0;
+        for (uint32_t spin = 0;; ++spin) {
+            bool ok = true;
+            for (int32_t k = d0 + lane; k < d1; k += 64) ok &= ld_coherent(a.cflag + a.dep[k]) == epoch;
+            if (__all(ok)) break;
+            if (spin == 0) t0 = __builtin_amdgcn_s_memrealtime();
+            if ((spin & 7) == 7) {
+                bool stop = ld_coherent(a.status) != 0;
+                if (!stop && __builtin_amdgcn_s_memrealtime() - t0 > a.watchdog_ticks) {
+                    if (lane == 0) atomicOr(a.status, 1);
+                    stop = true;
+                }
+                if (__any(stop)) return;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        if (active) {
+        const Real om[3] = {a.omega[3 * m], a.omega[3 * m + 1], DIM == 3 ? a.omega[3 * m + 2] : Real(0)};
+        const double *om64 = a.omega64 + 3 * m;
+        // classify faces and gather upwind values
+        Real s = Real(0);
+        if (a.src_cell) s = a.src_cell[K];
+        if (a.src_dir) s = (Real)a.src_dir[base + K] + s;
+        Real aj[NF], val[NF];
+        int kind[NF];   // 0 none, 1 outflow, 2 inflow with a known value, 3 interior inflow
+#pragma unroll
+        for (int j = 0; j < NF; ++j) {
+            Real d = face_dot(r, j, om, a.rec64, K, om64);
+            const int32_t code = r.nbr[j];
+            const int32_t u = code <= -2 ? -code - 2 : code;
+            kind[j] = 0;
+            aj[j] = Real(0);
+            val[j] = Real(0);
+            if (d > Real(0)) { kind[j] = 1; aj[j] = d; }
+            else if (d < Real(0)) {
+                aj[j] = -d;
+                kind[j] = 2;
+                if (code == -1) val[j] = a.psi_b;
+                else {
+                    int64_t e = code <= -2 ? lag_index(a.lag_mv, a.lag_u, a.n_lag, m, K, u) : -1;
+                    if (e >= 0) val[j] = a.lag_val[e];
+                    else val[j] = ld_coherent(a.psi + base + u);
+                }
+            }
+        }
+        // step-scheme balance, summed in local face order
+        Real num = r.V * s;
+        Real den = r.sigV;
+#pragma unroll
+        for (int j = 0; j < NF; ++j) {
+            if (kind[j] == 2) num = num + aj[j] * val[j];
+            else if (kind[j] == 1) den = den + aj[j];
+        }
+        st_coherent(a.psi + base + K, num / den);
+        }
+        // publish the chunk once every lane's flux store has completed
+        __builtin_amdgcn_s_waitcnt(0);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        if (lane == 0) st_coherent(a.cflag + c, epoch);
+    }
+}
+
+// ticket counters back to zero before a sweep
+__global__ void k_reset_tickets(uint32_t *t) {
+    if (threadIdx.x < kStreams) t[32 * threadIdx.x] = 0u;
+}
+
+static uint64_t watchdog_ticks() {
+    const char *e = std::getenv("JSWEEP_WATCHDOG_MS");
+    double ms = e ? std::atof(e) : 4000.0;
+    if (!(ms > 0)) ms = 4000.0;
+    return (uint64_t)(ms * 1e5);   // s_memrealtime runs at 100 MHz
+}
+
+template <class Real, int NF, int DIM>
+static const void *kernel_ptr() {
+    return reinterpret_cast<const void *>(&k_sweep<Real, NF, DIM>);
+}
+
+static const void *sweep_kernel(int ctype, bool fp32) {
+    if (ctype == JSWEEP_TRI) return fp32 ? kernel_ptr<float, 3, 2>() : kernel_ptr<double, 3, 2>();
+    if (ctype == JSWEEP_TET) return fp32 ? kernel_ptr<float, 4, 3>() : kernel_ptr<double, 4, 3>();
+    return fp32 ? kernel_ptr<float, 6, 3>() : kernel_ptr<double, 6, 3>();
+}
+
+int persistent_waves(Graph &g, bool fp32, const jsweep_params *p, int *waves_per_block) {
+    int wpb = (p && p->waves_per_block > 0) ? p->waves_per_block : (g.has_tuned && g.tuned.waves_per_block > 0 ? g.tuned.waves_per_block : 4);
+    if (wpb > 16) wpb = 16;
+    int occ = 0;
+    JSW_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sweep_kernel(g.ctype, fp32), 64 * wpb, 0));
+    if (occ < 1) occ = 1;
+    int bpc = (p && p->blocks_per_cu > 0) ? p->blocks_per_cu : (g.has_tuned && g.tuned.blocks_per_cu > 0 ? g.tuned.blocks_per_cu : occ);
+    if (bpc > occ) bpc = occ;
+    *waves_per_block = wpb;
+    return bpc * g.n_cu * wpb;
+}
+
+template <class Real, int NF, int DIM>
+static void launch_impl(Graph &g, const Real *src_cell, const float *src_dir, Real *psi, Real psi_b,
+                        const jsweep_params *p, hipStream_t s) {
+    SweepArgs<Real, NF, DIM> a;
+    a.rec = sizeof(Real) == 8 ? reinterpret_cast<const CellRec<Real, NF, DIM> *>(g.rec64.p)
+                              : reinterpret_cast<const CellRec<Real, NF, DIM> *>(g.rec32.p);
+    a.rec64 = g.rec64.as<CellRec<double, NF, DIM>>();
+    a.lvl_cells = g.lvl_cells.as<int32_t>();
+    a.chunks = g.chunks.as<Chunk>();
+    a.dep_ptr = g.dep_ptr.as<int32_t>();
+    a.dep = g.dep.as<int32_t>();
+    a.nc = g.nc;
+    a.omega = sizeof(Real) == 8 ? reinterpret_cast<const Real *>(g.omega64.p) : reinterpret_cast<const Real *>(g.omega32.p);
+    a.omega64 = g.omega64.as<double>();
+    a.src_cell = src_cell;
+    a.src_dir = src_dir;
+    a.psi = psi;
+    a.cflag = g.cflag.as<uint8_t>();
+    a.status = g.status.as<int32_t>();
+    a.lag_mv = g.lag_mv.as<uint64_t>();
+    a.lag_u = g.lag_u.as<int32_t>();
+    a.lag_val = sizeof(Real) == 8 ? reinterpret_cast<const Real *>(g.lag_val64.p) : reinterpret_cast<const Real *>(g.lag_val32.p);
+    a.n_lag = g.n_lag;
+    a.tickets = reinterpret_cast<uint32_t *>(g.status.as<char>() + 128);
+    a.stream_off = g.stream_off.as<int64_t>();
+    a.grab = (p && p->chunks_per_ticket > 0) ? p->chunks_per_ticket : (g.has_tuned && g.tuned.chunks_per_ticket > 0 ? g.tuned.chunks_per_ticket : 2);
+    a.psi_b = psi_b;
+    g.epoch = g.epoch % 255 + 1;
+    a.epoch = (uint32_t)g.epoch;
+    a.watchdog_ticks = watchdog_ticks();
+    int wpb = 4;
+    int waves = persistent_waves(g, sizeof(Real) == 4, p, &wpb);
+    int64_t need = std::max<int64_t>(1, g.n_chunks);
+    if (waves > need) waves = (int)((need + wpb - 1) / wpb * wpb);
+    int blocks = std::max(waves / wpb, kStreams);
+    k_reset_tickets<<<1, 64, 0, s>>>(a.tickets);
+    hipLaunchKernelGGL((k_sweep<Real, NF, DIM>), dim3(blocks), dim3(64 * wpb), 0, s, a);
+    JSW_HIP(hipGetLastError());
+}
+
+void launch_sweep64(Graph &g, const double *src_cell, double *psi, double psi_b, const jsweep_params *p, hipStream_t s) {
+    if (g.ctype == JSWEEP_TRI) launch_impl<double, 3, 2>(g, src_cell, nullptr, psi, psi_b, p, s);
+    else if (g.ctype == JSWEEP_TET) launch_impl<double, 4, 3>(g, src_cell, nullptr, psi, psi_b, p, s);
+    else launch_impl<double, 6, 3>(g, src_cell, nullptr, psi, psi_b, p, s);
+}
+
+void launch_sweep32(Graph &g, const float *src_dir, const float *src_cell, float *psi, const jsweep_params *p,
+                    hipStream_t s) {
+    if (g.ctype == JSWEEP_TRI) launch_impl<float, 3, 2>(g, src_cell, src_dir, psi, 0.0f, p, s);
+    else if (g.ctype == JSWEEP_TET) launch_impl<float, 4, 3>(g, src_cell, src_dir, psi, 0.0f, p, s);
+    else launch_impl<float, 6, 3>(g, src_cell, src_dir, psi, 0.0f, p, s);
+}
+
+int check_sweep_status(Graph &g, hipStream_t s) {
+    int32_t st = 0;
+    JSW_HIP(hipMemcpyAsync(&st, g.status.p, 4, hipMemcpyDeviceToHost, s));
+    JSW_HIP(hipStreamSynchronize(s));
+    if (st == 0) return JSWEEP_OK;
+    // a stalled sweep leaves flags in an unknown state: start over
+    JSW_HIP(hipMemsetAsync(g.cflag.p, 0, g.cflag.bytes, s));
+    JSW_HIP(hipMemsetAsync(g.status.p, 0, 64, s));
+    JSW_HIP(hipStreamSynchronize(s));
+    g.epoch = 0;
+    return JSWEEP_E_STALLED;
+}
+
+}  // namespace jsw

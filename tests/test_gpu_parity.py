@@ -1,0 +1,107 @@
+"""GPU parity: the HIP path through the C ABI against the oracle.
+
+* graph construction (in-degrees, levels, level pointers, level-ordered
+  cells, lagged edges): bit-exact;
+* one FP64 sweep and 20 FP64 source iterations: max relative difference
+  <= 1e-12 in psi and phi;
+* FP32-refined solve converged to rho <= 1e-11 against the oracle at
+  rho <= 1e-13: <= 1e-8 normwise relative in phi."""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_common import J, dev, gpu_graph, host, need_gpu, rel_max, torch
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_cases():
+    return [
+        ("delaunay_s4", W.config(1)),
+        ("hex12_s8_lagged", W.config(2, "small")),
+        ("tetcheck16_s8", W.config(3, "small")),
+        ("tetlogn8_s16", W.config(5, "small")),
+        ("hex3_cyclic", W.Problem("hex3cyc", W.hex_lattice(3, 0.3, 1), *W.quadrature(8, 3),
+                                  np.full(27, 1.3), np.full(27, 0.9), np.ones(27))),
+    ]
+
+
+@pytest.fixture(scope="module")
+def cases(oracle_mod):
+    need_gpu()
+    out = []
+    for name, p in _small_cases():
+        print(f"[case] {name} cells={p.n_cells} dirs={p.n_dirs}", flush=True)
+        out.append((name, p, oracle_mod.graph_for(p), gpu_graph(p)))
+    return out
+
+
+def test_graph_bit_exact(cases):
+    for name, p, og, gg in cases:
+        info = J.graph_info(gg)
+        assert info["n_lagged"] == og.n_lagged, name
+        assert info["max_levels"] == og.max_levels, name
+        for m in range(p.n_dirs):
+            a = og.direction(m)
+            b = J.graph_export(gg, m)
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y), (name, m)
+        if og.n_lagged:
+            for x, y in zip(og.lagged(), J.graph_lagged(gg)):
+                assert np.array_equal(x, y), name
+
+
+def test_fp64_sweep(cases):
+    for name, p, og, gg in cases:
+        rng = np.random.default_rng(7)
+        src = rng.uniform(0.0, 2.0, p.n_cells)
+        prev = rng.uniform(0.0, 1.0, (p.n_dirs, p.n_cells))
+        ref = og.sweep(p.sigma_t, src, 0.25, prev)
+        psi = dev(prev)
+        phi = dev(np.zeros(p.n_cells))
+        J.sweep(gg, dev(p.sigma_t), dev(src), psi, phi, psi_boundary=0.25)
+        got = host(psi)
+        err = rel_max(got, ref)
+        print(f"[sweep64] {name} rel {err:.3e} bitexact {np.array_equal(got, ref)}", flush=True)
+        assert err <= 1e-12, name
+        assert rel_max(host(phi), og.phi(p.weight, ref)) <= 1e-12
+
+
+def test_fp64_sweep_deterministic(cases):
+    name, p, og, gg = cases[2]
+    src = dev(np.linspace(0.1, 1.0, p.n_cells))
+    a = dev(np.zeros((p.n_dirs, p.n_cells)))
+    b = dev(np.zeros((p.n_dirs, p.n_cells)))
+    J.sweep(gg, dev(p.sigma_t), src, a)
+    J.sweep(gg, dev(p.sigma_t), src, b)
+    assert torch.equal(a, b)
+
+
+def test_fp64_source_iteration_20(cases):
+    for name, p, og, gg in cases:
+        psi_ref, phi_ref, hist = og.source_iteration(p.sigma_t, p.sigma_s, p.q, p.weight, 20)
+        phi = dev(np.zeros(p.n_cells))
+        psi = dev(np.zeros((p.n_dirs, p.n_cells)))
+        st = J.solve(gg, dev(p.sigma_t), dev(p.sigma_s), dev(p.q), phi, psi, mode=J.JSWEEP_FP64, tol=0.0,
+                     max_iter=20, allow_not_converged=True)
+        assert st["sweeps"] == 20
+        e1, e2 = rel_max(host(phi), phi_ref), rel_max(host(psi), psi_ref)
+        print(f"[si64] {name} phi {e1:.3e} psi {e2:.3e} rho {st['residual']:.3e} vs {hist[-1]:.3e}", flush=True)
+        assert e1 <= 1e-12 and e2 <= 1e-12, name
+        assert abs(st["residual"] - hist[-1]) <= 1e-6 * hist[-1] + 1e-15
+
+
+def test_fp32_refined_converges_to_oracle(cases):
+    for name, p, og, gg in cases:
+        if p.n_cells * p.n_dirs > 2_000_000:
+            continue
+        _, phi_ref, hist = og.source_iteration(p.sigma_t, p.sigma_s, p.q, p.weight, 20000, 1e-13)
+        assert hist[-1] <= 1e-13
+        phi = dev(np.zeros(p.n_cells))
+        st = J.solve(gg, dev(p.sigma_t), dev(p.sigma_s), dev(p.q), phi, mode=J.JSWEEP_FP32_REFINED, tol=1e-11,
+                     max_iter=20000)
+        got = host(phi)
+        err = float(np.linalg.norm(got - phi_ref) / np.linalg.norm(phi_ref))
+        print(f"[refined] {name} outer {st['outer_iters']} sweeps {st['sweeps']} (oracle {len(hist)}) "
+              f"rho {st['residual']:.2e} phi rel {err:.3e}", flush=True)
+        assert err <= 1e-8, name
