@@ -223,6 +223,14 @@ int jsweep_solve_batch(int32_t n, const jsweep_graph *graphs, const jsweep_probl
  * keyed by (cell type, size bucket, direction count, mode, device). */
 int jsweep_autotune(int32_t n, const jsweep_graph *graphs, int32_t mode, jsweep_params *out);
 
+/* Kernel timing of the sweep launches on a graph: while enabled, the
+ * library records a HIP event pair around every launch of the sweep kernel
+ * (on the launch stream).  jsweep_profile_read synchronises on those
+ * events and returns the number of launches and their summed duration in
+ * milliseconds since the last reset (reset != 0 clears them afterwards). */
+int jsweep_profile(jsweep_graph g, int32_t enable);
+int jsweep_profile_read(jsweep_graph g, int32_t reset, int64_t *launches, double *total_ms);
+
 void jsweep_graph_destroy(jsweep_graph g);
 
 const char *jsweep_error_string(int code);

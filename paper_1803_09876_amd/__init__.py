@@ -35,8 +35,8 @@ JSWEEP_WARM_START = 0x100
 
 EXPORTED = [
     "jsweep_build_graph", "jsweep_graph_info", "jsweep_graph_export", "jsweep_graph_lagged", "jsweep_sweep",
-    "jsweep_solve", "jsweep_solve_batch", "jsweep_autotune", "jsweep_graph_destroy", "jsweep_error_string",
-    "jsweep_last_error",
+    "jsweep_solve", "jsweep_solve_batch", "jsweep_autotune", "jsweep_profile", "jsweep_profile_read",
+    "jsweep_graph_destroy", "jsweep_error_string", "jsweep_last_error",
 ]
 
 
@@ -96,6 +96,8 @@ def load_library(path: str | None = None):
     lib.jsweep_solve.argtypes = [P, P, P, P, dbl, i32, dbl, i32, P, P, P, P, P]
     lib.jsweep_solve_batch.argtypes = [i32, P, P, i32, dbl, i32, P, P, P]
     lib.jsweep_autotune.argtypes = [i32, P, i32, P]
+    lib.jsweep_profile.argtypes = [P, i32]
+    lib.jsweep_profile_read.argtypes = [P, i32, P, P]
     lib.jsweep_graph_destroy.argtypes = [P]
     lib.jsweep_graph_destroy.restype = None
     lib.jsweep_error_string.argtypes = [ctypes.c_int]
@@ -103,7 +105,8 @@ def load_library(path: str | None = None):
     lib.jsweep_last_error.argtypes = []
     lib.jsweep_last_error.restype = ctypes.c_char_p
     for name in ("jsweep_build_graph", "jsweep_graph_info", "jsweep_graph_export", "jsweep_graph_lagged",
-                 "jsweep_sweep", "jsweep_solve", "jsweep_solve_batch", "jsweep_autotune"):
+                 "jsweep_sweep", "jsweep_solve", "jsweep_solve_batch", "jsweep_autotune", "jsweep_profile",
+                 "jsweep_profile_read"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -284,6 +287,17 @@ def jsweep_autotune(graphs, mode: int = JSWEEP_FP32_REFINED) -> Params:
     out = Params()
     _check(lib.jsweep_autotune(n, hs, int(mode), ctypes.byref(out)))
     return out
+
+
+def jsweep_profile(g: Graph, enable: bool = True):
+    _check(load_library().jsweep_profile(g.handle, 1 if enable else 0))
+
+
+def jsweep_profile_read(g: Graph, reset: bool = True):
+    """(launches, total kernel milliseconds) of the sweep kernel."""
+    n, ms = ctypes.c_int64(), ctypes.c_double()
+    _check(load_library().jsweep_profile_read(g.handle, 1 if reset else 0, ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
 
 
 def jsweep_error_string(code: int) -> str:

@@ -321,6 +321,35 @@ int jsweep_autotune(int32_t n, const jsweep_graph *graphs, int32_t mode, jsweep_
     });
 }
 
+int jsweep_profile(jsweep_graph h, int32_t enable) {
+    return guarded([&]() -> int {
+        if (!h) fail(JSWEEP_E_INVALID_ARG, "graph is NULL");
+        G(h)->profile = enable != 0;
+        return JSWEEP_OK;
+    });
+}
+
+int jsweep_profile_read(jsweep_graph h, int32_t reset, int64_t *launches, double *total_ms) {
+    return guarded([&]() -> int {
+        if (!h) fail(JSWEEP_E_INVALID_ARG, "graph is NULL");
+        Graph &g = *G(h);
+        double ms = 0.0;
+        for (auto &e : g.prof_events) {
+            JSW_HIP(hipEventSynchronize(e.second));
+            float t = 0.0f;
+            JSW_HIP(hipEventElapsedTime(&t, e.first, e.second));
+            ms += t;
+        }
+        if (launches) *launches = (int64_t)g.prof_events.size();
+        if (total_ms) *total_ms = ms;
+        if (reset) {
+            for (auto &e : g.prof_events) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+            g.prof_events.clear();
+        }
+        return JSWEEP_OK;
+    });
+}
+
 void jsweep_graph_destroy(jsweep_graph h) {
     if (!h) return;
     try {

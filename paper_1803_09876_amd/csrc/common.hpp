@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <memory>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/jsweep.h"
@@ -113,6 +114,12 @@ struct Graph {
     int grid_waves64 = 0, grid_waves32 = 0;   // persistent grid sizes
     jsweep_params tuned{};               // set by jsweep_autotune
     bool has_tuned = false;
+    // kernel timing (jsweep_profile)
+    bool profile = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
+    ~Graph() {
+        for (auto &e : prof_events) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    }
 };
 
 // build steps (geometry.hip, dag.hip)

@@ -274,8 +274,18 @@ static void launch_impl(Graph &g, const Real *src_cell, const float *src_dir, Re
     if (waves > need) waves = (int)((need + wpb - 1) / wpb * wpb);
     int blocks = std::max(waves / wpb, kStreams);
     k_reset_tickets<<<1, 64, 0, s>>>(a.tickets);
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (g.profile) {
+        JSW_HIP(hipEventCreate(&ev0));
+        JSW_HIP(hipEventCreate(&ev1));
+        JSW_HIP(hipEventRecord(ev0, s));
+    }
     hipLaunchKernelGGL((k_sweep<Real, NF, DIM>), dim3(blocks), dim3(64 * wpb), 0, s, a);
     JSW_HIP(hipGetLastError());
+    if (g.profile) {
+        JSW_HIP(hipEventRecord(ev1, s));
+        g.prof_events.push_back({ev0, ev1});
+    }
 }
 
 void launch_sweep64(Graph &g, const double *src_cell, double *psi, double psi_b, const jsweep_params *p, hipStream_t s) {
