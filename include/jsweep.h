@@ -99,13 +99,25 @@ typedef struct {
 
 typedef struct jsweep_graph_s *jsweep_graph;   /* opaque, owned by the library */
 
-/* Launch tuning of the persistent sweep kernel; 0 in a field = default or
- * the value chosen by jsweep_autotune. */
+/* Sweep strategies.
+ * DATA_DRIVEN: a persistent kernel over all directions at once; vertices of
+ *   a level-ordered work list run as soon as their upwind vertices are done
+ *   (completion flags between compute units).
+ * DIRECTION: one workgroup per direction walks that direction's levels with
+ *   a workgroup barrier between levels; directions run side by side. */
+#define JSWEEP_STRATEGY_AUTO 0
+#define JSWEEP_STRATEGY_DATA_DRIVEN 1
+#define JSWEEP_STRATEGY_DIRECTION 2
+
+/* Launch tuning of the sweep kernels; 0 in a field = default or the value
+ * chosen by jsweep_autotune. */
 typedef struct {
     int32_t waves_per_block;       /* 64-lane wavefronts per workgroup (1..16) */
-    int32_t blocks_per_cu;         /* resident workgroups per CU (capped by occupancy) */
+    int32_t blocks_per_cu;         /* DATA_DRIVEN: resident workgroups per CU (capped by occupancy) */
     int32_t inner_sweeps;          /* FP32-refined: maximum inner sweeps per outer residual */
-    int32_t chunks_per_ticket;     /* work-list chunks a wavefront takes per atomic ticket */
+    int32_t chunks_per_ticket;     /* DATA_DRIVEN: work-list chunks a wavefront takes per atomic ticket */
+    int32_t strategy;              /* JSWEEP_STRATEGY_* */
+    int32_t reserved;
 } jsweep_params;
 
 typedef struct {
@@ -230,6 +242,19 @@ int jsweep_autotune(int32_t n, const jsweep_graph *graphs, int32_t mode, jsweep_
  * milliseconds since the last reset (reset != 0 clears them afterwards). */
 int jsweep_profile(jsweep_graph g, int32_t enable);
 int jsweep_profile_read(jsweep_graph g, int32_t reset, int64_t *launches, double *total_ms);
+
+/* Tracing of the data-driven sweep (the paper's runtime breakdown into
+ * scheduling, waiting and computing).  While enabled, every sweep records,
+ * per work-list chunk, three s_memrealtime stamps (100 MHz, low 32 bits):
+ * when a wavefront took the chunk, when all of its upwind chunks were
+ * complete, and when it published its own completion.
+ * jsweep_trace_read (host buffers, any may be NULL) returns the chunk count,
+ * the stamps of the last traced sweep [3 * n_chunks], per chunk (direction,
+ * vertex count, level) [3 * n_chunks], and the coarsened graph as CSR
+ * (deps_ptr [n_chunks + 1], deps [deps_ptr[n_chunks]]). */
+int jsweep_trace(jsweep_graph g, int32_t enable);
+int jsweep_trace_read(jsweep_graph g, int64_t *n_chunks, uint32_t *stamps, int32_t *chunk_info, int32_t *deps_ptr,
+                      int32_t *deps);
 
 void jsweep_graph_destroy(jsweep_graph g);
 

@@ -32,11 +32,12 @@ JSWEEP_HOST_PTRS = 0x2
 JSWEEP_FP64 = 0
 JSWEEP_FP32_REFINED = 1
 JSWEEP_WARM_START = 0x100
+JSWEEP_STRATEGY_AUTO, JSWEEP_STRATEGY_DATA_DRIVEN, JSWEEP_STRATEGY_DIRECTION = 0, 1, 2
 
 EXPORTED = [
     "jsweep_build_graph", "jsweep_graph_info", "jsweep_graph_export", "jsweep_graph_lagged", "jsweep_sweep",
     "jsweep_solve", "jsweep_solve_batch", "jsweep_autotune", "jsweep_profile", "jsweep_profile_read",
-    "jsweep_graph_destroy", "jsweep_error_string", "jsweep_last_error",
+    "jsweep_trace", "jsweep_trace_read", "jsweep_graph_destroy", "jsweep_error_string", "jsweep_last_error",
 ]
 
 
@@ -57,10 +58,11 @@ class _Quad(ctypes.Structure):
 
 class Params(ctypes.Structure):
     _fields_ = [("waves_per_block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("inner_sweeps", ctypes.c_int32), ("chunks_per_ticket", ctypes.c_int32)]
+                ("inner_sweeps", ctypes.c_int32), ("chunks_per_ticket", ctypes.c_int32),
+                ("strategy", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
-        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+        return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
 
 
 class SolveStats(ctypes.Structure):
@@ -98,6 +100,8 @@ def load_library(path: str | None = None):
     lib.jsweep_autotune.argtypes = [i32, P, i32, P]
     lib.jsweep_profile.argtypes = [P, i32]
     lib.jsweep_profile_read.argtypes = [P, i32, P, P]
+    lib.jsweep_trace.argtypes = [P, i32]
+    lib.jsweep_trace_read.argtypes = [P, P, P, P, P, P]
     lib.jsweep_graph_destroy.argtypes = [P]
     lib.jsweep_graph_destroy.restype = None
     lib.jsweep_error_string.argtypes = [ctypes.c_int]
@@ -106,7 +110,7 @@ def load_library(path: str | None = None):
     lib.jsweep_last_error.restype = ctypes.c_char_p
     for name in ("jsweep_build_graph", "jsweep_graph_info", "jsweep_graph_export", "jsweep_graph_lagged",
                  "jsweep_sweep", "jsweep_solve", "jsweep_solve_batch", "jsweep_autotune", "jsweep_profile",
-                 "jsweep_profile_read"):
+                 "jsweep_profile_read", "jsweep_trace", "jsweep_trace_read"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -298,6 +302,29 @@ def jsweep_profile_read(g: Graph, reset: bool = True):
     n, ms = ctypes.c_int64(), ctypes.c_double()
     _check(load_library().jsweep_profile_read(g.handle, 1 if reset else 0, ctypes.byref(n), ctypes.byref(ms)))
     return n.value, ms.value
+
+
+def jsweep_trace(g: Graph, enable: bool = True):
+    _check(load_library().jsweep_trace(g.handle, 1 if enable else 0))
+
+
+def jsweep_trace_read(g: Graph):
+    """Per-chunk stamps of the last traced sweep as a dict of numpy arrays:
+    take, ready, done (100 MHz ticks), dir, count, level, deps_ptr, deps."""
+    lib = load_library()
+    n = ctypes.c_int64()
+    _check(lib.jsweep_trace_read(g.handle, ctypes.byref(n), None, None, None, None))
+    n = n.value
+    stamps = np.zeros(3 * n, dtype=np.uint32)
+    info = np.zeros(3 * n, dtype=np.int32)
+    ptr = np.zeros(n + 1, dtype=np.int32)
+    _check(lib.jsweep_trace_read(g.handle, None, None, None, ptr.ctypes.data, None))
+    deps = np.zeros(max(1, int(ptr[-1])), dtype=np.int32)
+    _check(lib.jsweep_trace_read(g.handle, None, stamps.ctypes.data, info.ctypes.data, None, deps.ctypes.data))
+    st = stamps.reshape(n, 3).astype(np.int64)
+    inf = info.reshape(n, 3)
+    return {"take": st[:, 0], "ready": st[:, 1], "done": st[:, 2], "dir": inf[:, 0], "count": inf[:, 1],
+            "level": inf[:, 2], "deps_ptr": ptr, "deps": deps[:int(ptr[-1])]}
 
 
 def jsweep_error_string(code: int) -> str:

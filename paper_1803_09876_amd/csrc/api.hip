@@ -350,6 +350,48 @@ int jsweep_profile_read(jsweep_graph h, int32_t reset, int64_t *launches, double
     });
 }
 
+int jsweep_trace(jsweep_graph h, int32_t enable) {
+    return guarded([&]() -> int {
+        if (!h) fail(JSWEEP_E_INVALID_ARG, "graph is NULL");
+        Graph &g = *G(h);
+        g.trace = enable != 0;
+        if (g.trace && g.trace_buf.bytes < 12 * (size_t)std::max<int64_t>(1, g.n_chunks)) {
+            g.trace_buf.alloc(12 * (size_t)std::max<int64_t>(1, g.n_chunks));
+            JSW_HIP(hipMemset(g.trace_buf.p, 0, g.trace_buf.bytes));
+        }
+        return JSWEEP_OK;
+    });
+}
+
+int jsweep_trace_read(jsweep_graph h, int64_t *n_chunks, uint32_t *stamps, int32_t *chunk_info, int32_t *deps_ptr,
+                      int32_t *deps) {
+    return guarded([&]() -> int {
+        if (!h) fail(JSWEEP_E_INVALID_ARG, "graph is NULL");
+        Graph &g = *G(h);
+        if (n_chunks) *n_chunks = g.n_chunks;
+        JSW_HIP(hipDeviceSynchronize());
+        if (stamps) {
+            if (!g.trace_buf.p) fail(JSWEEP_E_INVALID_ARG, "tracing was never enabled");
+            JSW_HIP(hipMemcpy(stamps, g.trace_buf.p, 12 * (size_t)g.n_chunks, hipMemcpyDeviceToHost));
+        }
+        if (chunk_info) {
+            std::vector<Chunk> ch(g.n_chunks);
+            JSW_HIP(hipMemcpy(ch.data(), g.chunks.p, sizeof(Chunk) * g.n_chunks, hipMemcpyDeviceToHost));
+            for (int64_t c = 0; c < g.n_chunks; ++c) {
+                int m = (int)(ch[c].a & 0xffffu);
+                chunk_info[3 * c] = m;
+                chunk_info[3 * c + 1] = (int32_t)(ch[c].a >> 16) + 1;
+                // level of the chunk: position in the direction's level pointers
+                const int64_t *p = g.lvl_ptr_h.data() + g.lvl_off_h[m];
+                chunk_info[3 * c + 2] = (int32_t)(std::upper_bound(p, p + g.nlev_h[m] + 1, (int64_t)ch[c].b) - p - 1);
+            }
+        }
+        if (deps_ptr) JSW_HIP(hipMemcpy(deps_ptr, g.dep_ptr.p, 4 * (size_t)(g.n_chunks + 1), hipMemcpyDeviceToHost));
+        if (deps) JSW_HIP(hipMemcpy(deps, g.dep.p, 4 * (size_t)g.n_dep, hipMemcpyDeviceToHost));
+        return JSWEEP_OK;
+    });
+}
+
 void jsweep_graph_destroy(jsweep_graph h) {
     if (!h) return;
     try {

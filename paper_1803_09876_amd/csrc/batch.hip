@@ -1,17 +1,537 @@
-// Batched solves and the launch-parameter autotuner.
+// Batched source iteration over an ensemble of independent graphs, and the
+// launch-parameter autotuner.
+//
+// Every sweep of the batch is one launch of the batched direction-parallel
+// kernel (one workgroup per (instance, direction) task).  The FP64 residual,
+// scalar flux, correction flux and refinement update run as single
+// launches over the concatenated cells (or angular fluxes) of all
+// instances.  Instances converge independently: a device flag per instance
+// switches its work off.  In the FP32-refined mode the inner correction
+// sweeps are recorded once into a HIP graph (lag snapshot, sweep, scalar
+// correction flux -- kInnerBlock of them) and replayed.
 #include <cstring>
 
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <string>
+
 #include "common.hpp"
+#include "device.hpp"
 
 namespace jsw {
 
+constexpr int kB = 256;
+constexpr int kInnerBlock = 4;   // inner sweeps per graph replay
+
+struct BInst {
+    const void *rec64;
+    void *rec32;
+    const double *omega, *w, *vol;
+    const double *sigma_t, *sigma_s, *q;
+    double *phi, *psi, *src, *dphi;
+    float *r32, *dpsi, *g32;
+    const uint64_t *lag_mv;
+    const int32_t *lag_u;
+    double *lag64;
+    float *lag32;
+    int64_t n_lag, nc;
+    int32_t nd, ctype;
+    double psi_b;
+};
+
+// instance of a global index in a concatenation (off: n + 1 prefix sums)
+__device__ inline int find_inst(const int64_t *off, int n, int64_t g) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (off[mid] <= g) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_b_sigv(const BInst *I, const int64_t *coff, int n, int64_t total) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int i = find_inst(coff, n, g);
+    const BInst &b = I[i];
+    const int64_t K = g - coff[i];
+    if (b.ctype == JSWEEP_TRI) {
+        auto *r64 = (CellRec<double, 3, 2> *)b.rec64 + K;
+        double v = b.sigma_t[K] * r64->V;
+        r64->sigV = v;
+        if (b.rec32) ((CellRec<float, 3, 2> *)b.rec32 + K)->sigV = (float)v;
+    } else if (b.ctype == JSWEEP_TET) {
+        auto *r64 = (CellRec<double, 4, 3> *)b.rec64 + K;
+        double v = b.sigma_t[K] * r64->V;
+        r64->sigV = v;
+        if (b.rec32) ((CellRec<float, 4, 3> *)b.rec32 + K)->sigV = (float)v;
+    } else {
+        auto *r64 = (CellRec<double, 6, 3> *)b.rec64 + K;
+        double v = b.sigma_t[K] * r64->V;
+        r64->sigV = v;
+        if (b.rec32) ((CellRec<float, 6, 3> *)b.rec32 + K)->sigV = (float)v;
+    }
+}
+
+// zero the FP64 angular flux (what = 0), or the correction state (1)
+__global__ void k_b_zero(const BInst *I, const int64_t *off, int n, int64_t total, const int32_t *active, int what) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int i = find_inst(off, n, g);
+    if (active && !active[i]) return;
+    const BInst &b = I[i];
+    const int64_t x = g - off[i];
+    if (what == 0) b.psi[x] = 0.0;
+    else {
+        b.dpsi[x] = 0.0f;
+        if (x < b.nc) { b.dphi[x] = 0.0; b.g32[x] = 0.0f; }
+    }
+}
+
+__global__ void k_b_source(const BInst *I, const int64_t *coff, int n, int64_t total, const int32_t *active) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int i = find_inst(coff, n, g);
+    if (!active[i]) return;
+    const BInst &b = I[i];
+    const int64_t K = g - coff[i];
+    b.src[K] = b.q[K] + b.sigma_s[K] * b.phi[K];
+}
+
+__global__ void k_b_lag(const BInst *I, const int64_t *loff, int n, int64_t total, const int32_t *active, int fp32) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int i = find_inst(loff, n, g);
+    if (!active[i]) return;
+    const BInst &b = I[i];
+    const int64_t e = g - loff[i];
+    const int64_t m = (int64_t)(b.lag_mv[e] >> 32);
+    if (fp32) b.lag32[e] = b.dpsi[m * b.nc + b.lag_u[e]];
+    else b.lag64[e] = b.psi[m * b.nc + b.lag_u[e]];
+}
+
+// FP64 residual of every active instance; acc[4 i] += ||r||^2, acc[4 i + 1] += ||q||^2
+__global__ void k_b_residual(const BInst *I, const int64_t *coff, int n, int64_t total, const int32_t *active,
+                             int fp32, double *acc) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int i = find_inst(coff, n, g);
+    if (!active[i]) return;
+    const BInst &b = I[i];
+    const int64_t K = g - coff[i];
+    float *r32 = fp32 ? b.r32 : nullptr;
+    double rr, V;
+    if (b.ctype == JSWEEP_TRI) {
+        const CellRec<double, 3, 2> r = ((const CellRec<double, 3, 2> *)b.rec64)[K];
+        rr = residual_cell(r, K, b.omega, b.w, b.psi, b.q[K], b.sigma_s[K], b.psi_b, b.nc, b.nd, b.phi, r32);
+        V = r.V;
+    } else if (b.ctype == JSWEEP_TET) {
+        const CellRec<double, 4, 3> r = ((const CellRec<double, 4, 3> *)b.rec64)[K];
+        rr = residual_cell(r, K, b.omega, b.w, b.psi, b.q[K], b.sigma_s[K], b.psi_b, b.nc, b.nd, b.phi, r32);
+        V = r.V;
+    } else {
+        const CellRec<double, 6, 3> r = ((const CellRec<double, 6, 3> *)b.rec64)[K];
+        rr = residual_cell(r, K, b.omega, b.w, b.psi, b.q[K], b.sigma_s[K], b.psi_b, b.nc, b.nd, b.phi, r32);
+        V = r.V;
+    }
+    atomicAdd(acc + 4 * i, rr);
+    atomicAdd(acc + 4 * i + 1, V * (b.q[K] * b.q[K]));
+}
+
+// correction flux dphi (FP64 sum of FP32 fluxes), FP32 scattering source,
+// acc[4 i + 2] += ||dphi||^2, acc[4 i + 3] += ||dphi - dphi_prev||^2
+__global__ void k_b_dphi(const BInst *I, const int64_t *coff, int n, int64_t total, const int32_t *active, double *acc) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int i = find_inst(coff, n, g);
+    if (!active[i]) return;
+    const BInst &b = I[i];
+    const int64_t K = g - coff[i];
+    double s = 0.0;
+    for (int m = 0; m < b.nd; ++m) s = s + b.w[m] * (double)b.dpsi[(int64_t)m * b.nc + K];
+    const double old = b.dphi[K];
+    b.dphi[K] = s;
+    b.g32[K] = (float)(b.sigma_s[K] * s);
+    atomicAdd(acc + 4 * i + 2, b.vol[K] * (s * s));
+    atomicAdd(acc + 4 * i + 3, b.vol[K] * ((s - old) * (s - old)));
+}
+
+__global__ void k_b_update(const BInst *I, const int64_t *aoff, int n, int64_t total, const int32_t *active) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int i = find_inst(aoff, n, g);
+    if (!active[i]) return;
+    const BInst &b = I[i];
+    const int64_t x = g - aoff[i];
+    b.psi[x] = b.psi[x] + (double)b.dpsi[x];
+}
+
+__global__ void k_b_clear(double *acc, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) acc[i] = 0.0;
+}
+
+static void ensure(DevBuf &b, size_t bytes) {
+    if (b.bytes < bytes) b.alloc(bytes);
+}
+
+static unsigned grid_for(int64_t total) { return (unsigned)std::max<int64_t>(1, ceil_div(total, kB)); }
+
 int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems, int32_t mode, double tol,
-                int32_t max_iter, const jsweep_params *params, jsweep_solve_stats *stats, hipStream_t s) {
-    fail(JSWEEP_E_INVALID_ARG, "batched solve not available yet");
+                int32_t max_iter, const jsweep_params *params, jsweep_solve_stats *stats, hipStream_t user_s) {
+    auto t_start = std::chrono::steady_clock::now();
+    // the batch runs on a stream of its own (the legacy default stream
+    // cannot be captured into a graph), after the caller's stream's work
+    JSW_HIP(hipStreamSynchronize(user_s));
+    hipStream_t s = nullptr;
+    JSW_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    struct StreamGuard {
+        hipStream_t s;
+        ~StreamGuard() { (void)hipStreamSynchronize(s); (void)hipStreamDestroy(s); }
+    } stream_guard{s};
+    const bool refined = (mode & 0xff) == JSWEEP_FP32_REFINED;
+    std::vector<BInst> h(n);
+    std::vector<int64_t> coff(n + 1, 0), aoff(n + 1, 0), loff(n + 1, 0);
+    std::vector<const void *> src_cell(n);
+    std::vector<const float *> src_dir(n);
+    std::vector<void *> psi_sweep(n);
+    std::vector<double> psi_b(n);
+    for (int i = 0; i < n; ++i) {
+        Graph &g = *graphs[i];
+        const jsweep_problem &p = problems[i];
+        const int64_t N = g.nc * g.nd;
+        if (refined) build_rec32(g, s);
+        BInst &b = h[i];
+        b.rec64 = g.rec64.p;
+        b.rec32 = refined ? g.rec32.p : nullptr;
+        b.omega = g.omega64.as<double>();
+        b.w = g.weight.as<double>();
+        b.vol = g.vol.as<double>();
+        b.sigma_t = p.sigma_t;
+        b.sigma_s = p.sigma_s;
+        b.q = p.q;
+        b.phi = p.phi;
+        if (p.psi) b.psi = p.psi;
+        else { ensure(g.scratch_a, 8 * N); b.psi = g.scratch_a.as<double>(); }
+        ensure(g.scratch_b, 8 * g.nc + 64);
+        b.src = g.scratch_b.as<double>();
+        if (refined) {
+            ensure(g.scratch_c, 8 * N + 64);
+            b.r32 = g.scratch_c.as<float>();
+            b.dpsi = b.r32 + N;
+            ensure(g.scratch_d, 16 * g.nc + 64);
+            b.dphi = g.scratch_d.as<double>();
+            b.g32 = reinterpret_cast<float *>(b.dphi + g.nc);
+        } else {
+            b.r32 = b.dpsi = b.g32 = nullptr;
+            b.dphi = nullptr;
+        }
+        b.lag_mv = g.lag_mv.as<uint64_t>();
+        b.lag_u = g.lag_u.as<int32_t>();
+        b.lag64 = g.lag_val64.as<double>();
+        b.lag32 = g.lag_val32.as<float>();
+        b.n_lag = g.n_lag;
+        b.nc = g.nc;
+        b.nd = g.nd;
+        b.ctype = g.ctype;
+        b.psi_b = p.psi_boundary;
+        coff[i + 1] = coff[i] + g.nc;
+        aoff[i + 1] = aoff[i] + N;
+        loff[i + 1] = loff[i] + g.n_lag;
+        if (refined) { src_cell[i] = b.g32; src_dir[i] = b.r32; psi_sweep[i] = b.dpsi; psi_b[i] = 0.0; }
+        else { src_cell[i] = b.src; src_dir[i] = nullptr; psi_sweep[i] = b.psi; psi_b[i] = p.psi_boundary; }
+    }
+    DevBuf d_inst(sizeof(BInst) * n), d_coff(8 * (n + 1)), d_aoff(8 * (n + 1)), d_loff(8 * (n + 1));
+    DevBuf d_active(4 * n), d_all(4 * n), d_acc(8 * 4 * n);
+    JSW_HIP(hipMemcpyAsync(d_inst.p, h.data(), sizeof(BInst) * n, hipMemcpyHostToDevice, s));
+    JSW_HIP(hipMemcpyAsync(d_coff.p, coff.data(), 8 * (n + 1), hipMemcpyHostToDevice, s));
+    JSW_HIP(hipMemcpyAsync(d_aoff.p, aoff.data(), 8 * (n + 1), hipMemcpyHostToDevice, s));
+    JSW_HIP(hipMemcpyAsync(d_loff.p, loff.data(), 8 * (n + 1), hipMemcpyHostToDevice, s));
+    std::vector<int32_t> active(n, 1), inner_active(n, 1);
+    JSW_HIP(hipMemcpyAsync(d_all.p, active.data(), 4 * n, hipMemcpyHostToDevice, s));
+    const BInst *I = d_inst.as<BInst>();
+    const int64_t C = coff[n], A = aoff[n], LG = loff[n];
+    int threads = (params && params->waves_per_block > 0) ? 64 * params->waves_per_block : 256;
+    BatchSweep sweep;
+    sweep.setup(n, graphs, refined, src_cell.data(), src_dir.data(), psi_sweep.data(), psi_b.data(), threads, s);
+    k_b_sigv<<<grid_for(C), kB, 0, s>>>(I, d_coff.as<int64_t>(), n, C);
+    k_b_zero<<<grid_for(A), kB, 0, s>>>(I, d_aoff.as<int64_t>(), n, A, nullptr, 0);
+    JSW_HIP(hipGetLastError());
+
+    std::vector<int32_t> outer(n, 0), sweeps(n, 0), hist(n, 0);
+    std::vector<double> rho(n, INFINITY), acc(4 * n);
+    auto record = [&](int i, double v) {
+        if (stats && stats[i].residual_history && hist[i] < stats[i].history_capacity) stats[i].residual_history[hist[i]] = v;
+        ++hist[i];
+    };
+    auto residuals = [&]() {
+        k_b_clear<<<grid_for(4 * n), kB, 0, s>>>(d_acc.as<double>(), 4 * n);
+        k_b_residual<<<grid_for(C), kB, 0, s>>>(I, d_coff.as<int64_t>(), n, C, d_active.as<int32_t>(), refined ? 1 : 0,
+                                                d_acc.as<double>());
+        JSW_HIP(hipGetLastError());
+        JSW_HIP(hipMemcpyAsync(acc.data(), d_acc.p, 8 * 4 * n, hipMemcpyDeviceToHost, s));
+        JSW_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i < n; ++i) {
+            if (!active[i]) continue;
+            rho[i] = acc[4 * i + 1] > 0.0 ? std::sqrt(acc[4 * i]) / std::sqrt(acc[4 * i + 1]) : std::sqrt(acc[4 * i]);
+            ++outer[i];
+            record(i, rho[i]);
+        }
+    };
+    auto push_active = [&](const std::vector<int32_t> &v) {
+        JSW_HIP(hipMemcpyAsync(d_active.p, v.data(), 4 * n, hipMemcpyHostToDevice, s));
+    };
+    push_active(active);
+    int rc = JSWEEP_OK;
+    int total_sweeps = 0;
+    if (!refined) {
+        // phi of the zero iterate is zero; plain source iteration
+        JSW_HIP(hipMemsetAsync(d_acc.p, 0, 8 * 4 * n, s));
+        for (int i = 0; i < n; ++i) JSW_HIP(hipMemsetAsync(h[i].phi, 0, 8 * graphs[i]->nc, s));
+        while (true) {
+            bool any = false;
+            for (int i = 0; i < n; ++i) any = any || active[i];
+            if (!any) break;
+            if (total_sweeps >= max_iter) { rc = JSWEEP_E_NOT_CONVERGED; break; }
+            k_b_source<<<grid_for(C), kB, 0, s>>>(I, d_coff.as<int64_t>(), n, C, d_active.as<int32_t>());
+            if (LG) k_b_lag<<<grid_for(LG), kB, 0, s>>>(I, d_loff.as<int64_t>(), n, LG, d_active.as<int32_t>(), 0);
+            sweep.launch(d_active.as<int32_t>(), s);
+            ++total_sweeps;
+            for (int i = 0; i < n; ++i) sweeps[i] += active[i];
+            residuals();
+            for (int i = 0; i < n; ++i)
+                if (active[i] && rho[i] <= tol) active[i] = 0;
+            push_active(active);
+        }
+    } else {
+        const int J = (params && params->inner_sweeps > 0) ? params->inner_sweeps : 400;
+        DevBuf d_inner(4 * n);
+        // record kInnerBlock inner sweeps once; replay them per block
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        JSW_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < kInnerBlock; ++k) {
+            if (LG) k_b_lag<<<grid_for(LG), kB, 0, s>>>(I, d_loff.as<int64_t>(), n, LG, d_inner.as<int32_t>(), 1);
+            sweep.launch(d_inner.as<int32_t>(), s);
+            // the norms read back after a replay are those of its last pass
+            if (k == kInnerBlock - 1) k_b_clear<<<grid_for(4 * n), kB, 0, s>>>(d_acc.as<double>(), 4 * n);
+            k_b_dphi<<<grid_for(C), kB, 0, s>>>(I, d_coff.as<int64_t>(), n, C, d_inner.as<int32_t>(), d_acc.as<double>());
+        }
+        hipError_t ce = hipStreamEndCapture(s, &graph);
+        if (ce != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            JSW_HIP(ce);
+        }
+        JSW_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        struct GraphGuard {
+            hipGraph_t g; hipGraphExec_t e;
+            ~GraphGuard() { if (e) (void)hipGraphExecDestroy(e); if (g) (void)hipGraphDestroy(g); }
+        } guard{graph, exec};
+        std::vector<double> prev_change(n, -1.0);
+        while (true) {
+            residuals();
+            for (int i = 0; i < n; ++i)
+                if (active[i] && rho[i] <= tol) active[i] = 0;
+            push_active(active);
+            bool any = false;
+            for (int i = 0; i < n; ++i) any = any || active[i];
+            if (!any) break;
+            if (total_sweeps >= max_iter) { rc = JSWEEP_E_NOT_CONVERGED; break; }
+            // inner FP32 source iteration on the correction of every active instance
+            k_b_zero<<<grid_for(A), kB, 0, s>>>(I, d_aoff.as<int64_t>(), n, A, d_active.as<int32_t>(), 1);
+            JSW_HIP(hipGetLastError());
+            inner_active = active;
+            std::fill(prev_change.begin(), prev_change.end(), -1.0);
+            for (int j = 0; j < J && total_sweeps < max_iter; j += kInnerBlock) {
+                JSW_HIP(hipMemcpyAsync(d_inner.p, inner_active.data(), 4 * n, hipMemcpyHostToDevice, s));
+                JSW_HIP(hipGraphLaunch(exec, s));
+                total_sweeps += kInnerBlock;
+                JSW_HIP(hipMemcpyAsync(acc.data(), d_acc.p, 8 * 4 * n, hipMemcpyDeviceToHost, s));
+                JSW_HIP(hipStreamSynchronize(s));
+                bool more = false;
+                for (int i = 0; i < n; ++i) {
+                    if (!inner_active[i]) continue;
+                    sweeps[i] += kInnerBlock;
+                    // norms of the block's last pass; successive blocks are
+                    // kInnerBlock passes apart
+                    double norm = std::sqrt(acc[4 * i + 2]), change = std::sqrt(acc[4 * i + 3]);
+                    double ratio = prev_change[i] > 0.0 ? std::min(change / prev_change[i], 0.999) : 0.999;
+                    ratio = std::pow(ratio, 1.0 / kInnerBlock);
+                    prev_change[i] = change;
+                    const double eta = std::max(3e-7, 0.3 * tol / rho[i]);
+                    if (norm == 0.0 || (j > 0 && change * ratio / (1.0 - ratio) <= eta * norm)) inner_active[i] = 0;
+                    else more = true;
+                }
+                if (!more) break;
+            }
+            k_b_update<<<grid_for(A), kB, 0, s>>>(I, d_aoff.as<int64_t>(), n, A, d_active.as<int32_t>());
+            JSW_HIP(hipGetLastError());
+        }
+    }
+    JSW_HIP(hipStreamSynchronize(s));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    for (int i = 0; i < n; ++i) {
+        if (rho[i] > tol) rc = JSWEEP_E_NOT_CONVERGED;
+        if (stats) {
+            stats[i].outer_iters = outer[i];
+            stats[i].sweeps = sweeps[i];
+            stats[i].residual = rho[i];
+            stats[i].seconds = secs;
+            stats[i].lagged_edges = graphs[i]->n_lag;
+            stats[i].max_levels = graphs[i]->max_levels;
+            stats[i].history_len = std::min(hist[i], stats[i].history_capacity);
+        }
+    }
+    return rc;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner: time candidate launch configurations of the sweep on scratch
+// problem data and keep the fastest; results are cached in memory and, when
+// JSWEEP_TUNE_CACHE names a file, in that JSON file.
+// ---------------------------------------------------------------------------
+static std::string tune_key(Graph *const *graphs, int32_t n, int32_t mode, const char *arch) {
+    int64_t cells = 0;
+    int dirs = 0, ct = 0;
+    for (int i = 0; i < n; ++i) { cells += graphs[i]->nc; dirs = std::max(dirs, graphs[i]->nd); ct |= graphs[i]->ctype; }
+    int bucket = 0;
+    while ((1ll << bucket) < cells) ++bucket;
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "%s/ct%d/cells2^%d/dirs%d/n%d/mode%d", arch, ct, bucket, dirs, n, mode & 0xff);
+    return buf;
+}
+
+static std::map<std::string, jsweep_params> &tune_memory() {
+    static std::map<std::string, jsweep_params> m;
+    return m;
+}
+
+static bool cache_lookup(const std::string &key, jsweep_params *out) {
+    auto &mem = tune_memory();
+    auto it = mem.find(key);
+    if (it != mem.end()) { *out = it->second; return true; }
+    const char *path = std::getenv("JSWEEP_TUNE_CACHE");
+    if (!path) return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        char k[256];
+        jsweep_params p{};
+        if (std::sscanf(line, " \"%255[^\"]\": [%d, %d, %d, %d, %d]", k, &p.waves_per_block, &p.blocks_per_cu,
+                        &p.inner_sweeps, &p.chunks_per_ticket, &p.strategy) == 6 && key == k) {
+            *out = p;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    if (found) mem[key] = *out;
+    return found;
+}
+
+static void cache_store(const std::string &key, const jsweep_params &p) {
+    auto &mem = tune_memory();
+    mem[key] = p;
+    const char *path = std::getenv("JSWEEP_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "w");
+    if (!f) return;
+    std::fprintf(f, "{\n");
+    size_t i = 0;
+    for (auto &kv : mem) {
+        const jsweep_params &q = kv.second;
+        std::fprintf(f, "  \"%s\": [%d, %d, %d, %d, %d]%s\n", kv.first.c_str(), q.waves_per_block, q.blocks_per_cu,
+                     q.inner_sweeps, q.chunks_per_ticket, q.strategy, ++i < mem.size() ? "," : "");
+    }
+    std::fprintf(f, "}\n");
+    std::fclose(f);
 }
 
 int autotune(int32_t n, Graph *const *graphs, int32_t mode, jsweep_params *out) {
-    fail(JSWEEP_E_INVALID_ARG, "autotune not available yet");
+    hipDeviceProp_t prop;
+    JSW_HIP(hipGetDeviceProperties(&prop, graphs[0]->device));
+    const std::string key = tune_key(graphs, n, mode, prop.gcnArchName);
+    if (cache_lookup(key, out)) {
+        for (int i = 0; i < n; ++i) { graphs[i]->tuned = *out; graphs[i]->has_tuned = true; }
+        return JSWEEP_OK;
+    }
+    const bool fp32 = (mode & 0xff) == JSWEEP_FP32_REFINED;
+    hipStream_t s = nullptr;
+    // scratch problem: sigma_t = 1, source = 1, per graph
+    std::vector<DevBuf> st(n), src(n), psi(n);
+    std::vector<float *> src32(n);
+    for (int i = 0; i < n; ++i) {
+        Graph &g = *graphs[i];
+        const int64_t N = g.nc * g.nd;
+        st[i].alloc(8 * g.nc);
+        src[i].alloc(8 * g.nc);
+        psi[i].alloc((fp32 ? 4 : 8) * N);
+        std::vector<double> ones(g.nc, 1.0);
+        JSW_HIP(hipMemcpy(st[i].p, ones.data(), 8 * g.nc, hipMemcpyHostToDevice));
+        if (fp32) {
+            std::vector<float> f(g.nc, 1.0f);
+            JSW_HIP(hipMemcpy(src[i].p, f.data(), 4 * g.nc, hipMemcpyHostToDevice));
+        } else {
+            JSW_HIP(hipMemcpy(src[i].p, ones.data(), 8 * g.nc, hipMemcpyHostToDevice));
+        }
+        refresh_sigma(g, st[i].as<double>(), fp32, s);
+    }
+    std::vector<jsweep_params> cands;
+    if (n == 1) {
+        for (int bpc : {1, 2, 0})
+            for (int grab : {1, 2, 4}) cands.push_back(jsweep_params{4, bpc, 0, grab, JSWEEP_STRATEGY_DATA_DRIVEN, 0});
+        for (int w : {4, 8, 16}) cands.push_back(jsweep_params{w, 0, 0, 0, JSWEEP_STRATEGY_DIRECTION, 0});
+    } else {
+        for (int w : {1, 2, 4, 8, 16}) cands.push_back(jsweep_params{w, 0, 0, 0, JSWEEP_STRATEGY_DIRECTION, 0});
+    }
+    hipEvent_t e0, e1;
+    JSW_HIP(hipEventCreate(&e0));
+    JSW_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    jsweep_params best_p = cands[0];
+    std::vector<int32_t> ones(n, 1);
+    DevBuf d_active(4 * n);
+    JSW_HIP(hipMemcpy(d_active.p, ones.data(), 4 * n, hipMemcpyHostToDevice));
+    for (const jsweep_params &c : cands) {
+        float ms = 0.0f;
+        BatchSweep bs;
+        if (n > 1) {
+            std::vector<const void *> sc(n);
+            std::vector<const float *> sd(n, nullptr);
+            std::vector<void *> ps(n);
+            std::vector<double> pb(n, 0.0);
+            for (int i = 0; i < n; ++i) { sc[i] = src[i].p; ps[i] = psi[i].p; }
+            bs.setup(n, graphs, fp32, sc.data(), sd.data(), ps.data(), pb.data(), 64 * c.waves_per_block, s);
+        }
+        for (int rep = 0; rep < 3; ++rep) {
+            JSW_HIP(hipEventRecord(e0, s));
+            if (n == 1) {
+                if (fp32) launch_sweep32(*graphs[0], nullptr, src[0].as<float>(), psi[0].as<float>(), &c, s);
+                else launch_sweep64(*graphs[0], src[0].as<double>(), psi[0].as<double>(), 0.0, &c, s);
+            } else {
+                bs.launch(d_active.as<int32_t>(), s);
+            }
+            JSW_HIP(hipEventRecord(e1, s));
+            JSW_HIP(hipEventSynchronize(e1));
+            if (n == 1 && check_sweep_status(*graphs[0], s) != JSWEEP_OK) fail(JSWEEP_E_STALLED, "sweep stalled while tuning");
+            float t = 0.0f;
+            JSW_HIP(hipEventElapsedTime(&t, e0, e1));
+            if (rep > 0) ms += t;
+        }
+        if (ms < best) { best = ms; best_p = c; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *out = best_p;
+    cache_store(key, best_p);
+    for (int i = 0; i < n; ++i) { graphs[i]->tuned = best_p; graphs[i]->has_tuned = true; }
+    return JSWEEP_OK;
 }
 
 }  // namespace jsw

@@ -91,6 +91,7 @@ struct Graph {
     std::vector<int64_t> lvl_off_h;      // [nd+1] start of each direction's lvl_ptr block
     std::vector<int64_t> lvl_ptr_h;      // concatenated per-direction level pointers
     std::vector<int32_t> nlev_h;         // [nd]
+    DevBuf lvl_ptr_d, lvl_off_d;         // device copies of the level pointers
     int max_levels = 0;
     DevBuf chunks;                       // [n_chunks] Chunk: per stream, ordered by (level, direction)
     int64_t n_chunks = 0;
@@ -114,6 +115,9 @@ struct Graph {
     int grid_waves64 = 0, grid_waves32 = 0;   // persistent grid sizes
     jsweep_params tuned{};               // set by jsweep_autotune
     bool has_tuned = false;
+    // per-chunk time stamps of the last sweep (jsweep_trace)
+    bool trace = false;
+    DevBuf trace_buf;
     // kernel timing (jsweep_profile)
     bool profile = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
@@ -138,6 +142,19 @@ void launch_sweep32(Graph &g, const float *src_dir, const float *src_cell, float
                     hipStream_t s);
 int check_sweep_status(Graph &g, hipStream_t s);   // JSWEEP_OK or JSWEEP_E_STALLED
 int persistent_waves(Graph &g, bool fp32, const jsweep_params *p, int *waves_per_block);
+int sweep_strategy(const Graph &g, const jsweep_params *p);
+
+// batched sweep over an ensemble of graphs: one workgroup per
+// (instance, direction), one launch (sweep.hip)
+struct BatchSweep {
+    DevBuf inst, task_inst, task_dir;
+    int64_t n_tasks = 0;
+    int threads = 256;
+    bool fp32 = false;
+    void setup(int32_t n, Graph *const *graphs, bool fp32, const void *const *src_cell, const float *const *src_dir,
+               void *const *psi, const double *psi_b, int threads, hipStream_t s);
+    void launch(const int32_t *active, hipStream_t s);
+};
 
 // solve (solve.hip)
 int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *q, double psi_b, int32_t mode,

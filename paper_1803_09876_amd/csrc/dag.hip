@@ -575,6 +575,10 @@ static void dag_impl(Graph &g, bool lag_cycles, hipStream_t s) {
         for (int L = 0; L < g.nlev_h[m]; ++L) p[L] = hstarts[(size_t)m * (Lcap + 1) + L];
         p[g.nlev_h[m]] = nc;
     }
+    g.lvl_ptr_d.alloc(8 * g.lvl_ptr_h.size());
+    g.lvl_off_d.alloc(8 * g.lvl_off_h.size());
+    JSW_HIP(hipMemcpyAsync(g.lvl_ptr_d.p, g.lvl_ptr_h.data(), 8 * g.lvl_ptr_h.size(), hipMemcpyHostToDevice, s));
+    JSW_HIP(hipMemcpyAsync(g.lvl_off_d.p, g.lvl_off_h.data(), 8 * g.lvl_off_h.size(), hipMemcpyHostToDevice, s));
     // sweep work list: chunks of <= 64 cells of one (level, direction).
     // Directions are dealt to kStreams streams in contiguous blocks (with
     // octant-major quadratures a block is an octant); within a stream the

@@ -1,0 +1,55 @@
+// Device helpers shared by the solve kernels (single graph and batched).
+#pragma once
+#include "common.hpp"
+
+namespace jsw {
+
+// One cell of the FP64 residual with the full (un-lagged) streaming
+// operator, looping over directions:
+//   phi_K = sum_m w_m psi_{K,m}
+//   r_{K,m} = q_K + sigma_s,K phi_K - (den psi_{K,m} - in_{K,m}) / V_K
+// Returns V_K sum_m w_m r^2 (and writes phi_K; r in FP32 when r32 != null).
+template <int NF, int DIM>
+__device__ inline double residual_cell(const CellRec<double, NF, DIM> &r, int64_t K, const double *omega,
+                                       const double *w, const double *psi, double q, double sigma_s, double psi_b,
+                                       int64_t nc, int nd, double *phi, float *r32) {
+    int64_t nb[NF];
+    for (int j = 0; j < NF; ++j) nb[j] = r.nbr[j] <= -2 ? (int64_t)(-r.nbr[j] - 2) : (int64_t)r.nbr[j];
+    double ph = 0.0;
+    for (int m = 0; m < nd; ++m) ph = ph + w[m] * psi[(int64_t)m * nc + K];
+    phi[K] = ph;
+    const double src = q + sigma_s * ph;
+    double cell = 0.0;
+    for (int m = 0; m < nd; ++m) {
+        const double *om = omega + 3 * m;
+        const double *pm = psi + (int64_t)m * nc;
+        double in = 0.0, den = r.sigV;
+        for (int j = 0; j < NF; ++j) {
+            double d = om[0] * r.S[j][0] + om[1] * r.S[j][1];
+            if constexpr (DIM == 3) d = d + om[2] * r.S[j][2];
+            if (d < 0.0) in = in + (-d) * (nb[j] < 0 ? psi_b : pm[nb[j]]);
+            else if (d > 0.0) den = den + d;
+        }
+        const double res = src - (den * pm[K] - in) / r.V;
+        if (r32) r32[(int64_t)m * nc + K] = (float)res;
+        cell = cell + w[m] * (res * res);
+    }
+    return r.V * cell;
+}
+
+// wavefront + workgroup sum, one atomic per workgroup
+__device__ inline void block_add(double v, double *out) {
+    __shared__ double red[16];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
+        atomicAdd(out, t);
+    }
+}
+
+}  // namespace jsw

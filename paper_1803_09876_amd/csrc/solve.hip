@@ -9,6 +9,7 @@
 #include <cmath>
 
 #include "common.hpp"
+#include "device.hpp"
 
 namespace jsw {
 
@@ -79,19 +80,6 @@ static void lag_snapshot(Graph &g, const Real *psi, hipStream_t s) {
 
 void lag_snapshot64(Graph &g, const double *psi, hipStream_t s) { lag_snapshot<double>(g, psi, s); }
 
-__device__ inline void block_add(double v, double *out) {
-    __shared__ double red[16];
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
-    int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) red[w] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
-        atomicAdd(out, t);
-    }
-}
-
 // FP64 residual with the full (un-lagged) streaming operator, one cell per
 // thread looping over directions (the cell record is read once per pass):
 //   phi_K = sum_m w_m psi_{K,m}
@@ -106,28 +94,7 @@ __global__ void k_residual(const CellRec<double, NF, DIM> *rec, const double *om
     double rr = 0.0, qq = 0.0;
     if (K < nc) {
         const CellRec<double, NF, DIM> r = rec[K];
-        int64_t nb[NF];
-        for (int j = 0; j < NF; ++j) nb[j] = r.nbr[j] <= -2 ? (int64_t)(-r.nbr[j] - 2) : (int64_t)r.nbr[j];
-        double ph = 0.0;
-        for (int m = 0; m < nd; ++m) ph = ph + w[m] * psi[(int64_t)m * nc + K];
-        phi[K] = ph;
-        const double src = q[K] + sigma_s[K] * ph;
-        double cell = 0.0;
-        for (int m = 0; m < nd; ++m) {
-            const double *om = omega + 3 * m;
-            const double *pm = psi + (int64_t)m * nc;
-            double in = 0.0, den = r.sigV;
-            for (int j = 0; j < NF; ++j) {
-                double d = om[0] * r.S[j][0] + om[1] * r.S[j][1];
-                if constexpr (DIM == 3) d = d + om[2] * r.S[j][2];
-                if (d < 0.0) in = in + (-d) * (nb[j] < 0 ? psi_b : pm[nb[j]]);
-                else if (d > 0.0) den = den + d;
-            }
-            double res = src - (den * pm[K] - in) / r.V;
-            if (r32) r32[(int64_t)m * nc + K] = (float)res;
-            cell = cell + w[m] * (res * res);
-        }
-        rr = r.V * cell;
+        rr = residual_cell(r, K, omega, w, psi, q[K], sigma_s[K], psi_b, nc, nd, phi, r32);
         qq = r.V * (q[K] * q[K]);
     }
     block_add(rr, acc);

@@ -24,11 +24,16 @@
 // resident.  A watchdog turns anything else into an error instead of a
 // hang.
 //
-// Memory ordering across compute units and XCDs: fluxes and chunk flags are
-// written and read with device-coherent (agent-scope) accesses; a chunk's
-// flag is stored only after every lane's flux store has completed
-// (s_waitcnt), and a consumer loads fluxes only after it has seen the flag.
-// No cache writeback/invalidate fences are used in the loop.
+// Memory ordering across compute units and XCDs.  Fluxes and chunk flags
+// live in device-local memory, whose L2 copies the memory fabric keeps
+// coherent between XCDs (probes), so a store is visible device-wide once it
+// has reached L2; only the per-CU L1 can hold stale data.  A producer
+// stores its fluxes with ordinary (L1 write-through) stores, waits until
+// they have completed (s_waitcnt: acknowledged by L2) and then stores the
+// chunk flag.  Consumers read flags and fluxes with device-scope loads,
+// which bypass L1, and read fluxes only after seeing the flag.  This is an
+// agent-scope release/acquire without the L2 writeback/invalidate that
+// only non-local memory needs.
 #include <cstring>
 
 #include <algorithm>
@@ -63,7 +68,9 @@ struct SweepArgs {
     Real psi_b;
     uint32_t epoch;
     int32_t grab;                            // chunks taken per ticket
+    uint32_t nap;                            // s_sleep units between dependency polls
     uint64_t watchdog_ticks;
+    uint32_t *stamps;                        // tracing: [3 * n_chunks] or null
 };
 
 template <class T>
@@ -131,6 +138,7 @@ __global__ void k_sweep(SweepArgs<Real, NF, DIM> a) {
         if (t_next >= per_stream) break;
         const int64_t c = first + t_next;
         ++t_next;
+        const uint32_t t_take = (uint32_t)__builtin_amdgcn_s_memrealtime();
         const Chunk ch = a.chunks[c];
         const int m = (int)(ch.a & 0xffffu);
         const int cnt = (int)(ch.a >> 16) + 1;
@@ -138,7 +146,12 @@ __global__ void k_sweep(SweepArgs<Real, NF, DIM> a) {
         const int64_t base = (int64_t)m * a.nc;
         const int64_t K = active ? (int64_t)a.lvl_cells[base + ch.b + lane] : 0;
         CellRec<Real, NF, DIM> r;
-        if (active) r = a.rec[K];
+        Real s = Real(0);
+        if (active) {
+            r = a.rec[K];
+            if (a.src_cell) s = a.src_cell[K];
+            if (a.src_dir) s = (Real)a.src_dir[base + K] + s;
+        }
         // wait until every upwind chunk of this sweep is complete
         const int32_t d0 = a.dep_ptr[c], d1 = a.dep_ptr[c + 1];
         uint64_t t0 = 0;
@@ -155,52 +168,188 @@ __global__ void k_sweep(SweepArgs<Real, NF, DIM> a) {
                 }
                 if (__any(stop)) return;
             }
-            __builtin_amdgcn_s_sleep(2);
+            for (uint32_t z = 0; z < a.nap; ++z) __builtin_amdgcn_s_sleep(1);
         }
+        const uint32_t t_ready = (uint32_t)__builtin_amdgcn_s_memrealtime();
         if (active) {
-        const Real om[3] = {a.omega[3 * m], a.omega[3 * m + 1], DIM == 3 ? a.omega[3 * m + 2] : Real(0)};
-        const double *om64 = a.omega64 + 3 * m;
-        // classify faces and gather upwind values
-        Real s = Real(0);
-        if (a.src_cell) s = a.src_cell[K];
-        if (a.src_dir) s = (Real)a.src_dir[base + K] + s;
-        Real aj[NF], val[NF];
-        int kind[NF];   // 0 none, 1 outflow, 2 inflow with a known value, 3 interior inflow
+            const Real om[3] = {a.omega[3 * m], a.omega[3 * m + 1], DIM == 3 ? a.omega[3 * m + 2] : Real(0)};
+            const double *om64 = a.omega64 + 3 * m;
+            Real aj[NF], val[NF];
+            int kind[NF];   // 0 none, 1 outflow, 2 inflow
 #pragma unroll
-        for (int j = 0; j < NF; ++j) {
-            Real d = face_dot(r, j, om, a.rec64, K, om64);
-            const int32_t code = r.nbr[j];
-            const int32_t u = code <= -2 ? -code - 2 : code;
-            kind[j] = 0;
-            aj[j] = Real(0);
-            val[j] = Real(0);
-            if (d > Real(0)) { kind[j] = 1; aj[j] = d; }
-            else if (d < Real(0)) {
-                aj[j] = -d;
-                kind[j] = 2;
-                if (code == -1) val[j] = a.psi_b;
-                else {
-                    int64_t e = code <= -2 ? lag_index(a.lag_mv, a.lag_u, a.n_lag, m, K, u) : -1;
-                    if (e >= 0) val[j] = a.lag_val[e];
-                    else val[j] = ld_coherent(a.psi + base + u);
+            for (int j = 0; j < NF; ++j) {
+                const Real d = face_dot(r, j, om, a.rec64, K, om64);
+                const int32_t code = r.nbr[j];
+                const int32_t u = code <= -2 ? -code - 2 : code;
+                kind[j] = 0;
+                aj[j] = Real(0);
+                val[j] = Real(0);
+                if (d > Real(0)) { kind[j] = 1; aj[j] = d; }
+                else if (d < Real(0)) {
+                    aj[j] = -d;
+                    kind[j] = 2;
+                    if (code == -1) val[j] = a.psi_b;
+                    else {
+                        const int64_t e = code <= -2 ? lag_index(a.lag_mv, a.lag_u, a.n_lag, m, K, u) : -1;
+                        val[j] = e >= 0 ? a.lag_val[e] : ld_coherent(a.psi + base + u);
+                    }
                 }
             }
-        }
-        // step-scheme balance, summed in local face order
-        Real num = r.V * s;
-        Real den = r.sigV;
+            // step-scheme balance, summed in local face order
+            Real num = r.V * s;
+            Real den = r.sigV;
 #pragma unroll
-        for (int j = 0; j < NF; ++j) {
-            if (kind[j] == 2) num = num + aj[j] * val[j];
-            else if (kind[j] == 1) den = den + aj[j];
-        }
-        st_coherent(a.psi + base + K, num / den);
+            for (int j = 0; j < NF; ++j) {
+                if (kind[j] == 2) num = num + aj[j] * val[j];
+                else if (kind[j] == 1) den = den + aj[j];
+            }
+            a.psi[base + K] = num / den;
         }
         // publish the chunk once every lane's flux store has completed
         __builtin_amdgcn_s_waitcnt(0);
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        if (lane == 0) st_coherent(a.cflag + c, epoch);
+        if (lane == 0) a.cflag[c] = epoch;
+        if (a.stamps && lane == 0) {
+            a.stamps[3 * c] = t_take;
+            a.stamps[3 * c + 1] = t_ready;
+            a.stamps[3 * c + 2] = (uint32_t)__builtin_amdgcn_s_memrealtime();
+        }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Direction-parallel sweep: one workgroup per direction walks the
+// direction's levels in order, all lanes of the workgroup sharing each
+// level's vertices, with a workgroup barrier between levels.  Upwind fluxes
+// were written by the same workgroup (same compute unit) at an earlier
+// level, so they are read back through the compute unit's own L1/L2 and no
+// vertex ever waits on another compute unit.  The levels are a topological
+// order of the direction's graph, so the sweep needs no flags at all; many
+// directions (and batch instances) run side by side, one per compute unit.
+// ---------------------------------------------------------------------------
+template <class Real, int NF, int DIM>
+struct DirArgs {
+    const CellRec<Real, NF, DIM> *rec;
+    const CellRec<double, NF, DIM> *rec64;
+    const int32_t *lvl_cells;
+    const int64_t *lvl_ptr;                  // concatenated level pointers
+    const int64_t *lvl_off;                  // [nd + 1] block of each direction
+    int64_t nc;
+    const Real *omega;
+    const double *omega64;
+    const Real *src_cell;
+    const float *src_dir;
+    Real *psi;
+    const uint64_t *lag_mv;
+    const int32_t *lag_u;
+    const Real *lag_val;
+    int64_t n_lag;
+    Real psi_b;
+};
+
+// Sweep of direction m by one workgroup: the lanes share each level's
+// vertices; a barrier separates levels.
+template <class Real, int NF, int DIM>
+__device__ void sweep_direction(const DirArgs<Real, NF, DIM> &a, int m) {
+    const int64_t base = (int64_t)m * a.nc;
+    const int64_t *ptr = a.lvl_ptr + a.lvl_off[m];
+    const int nlev = (int)(a.lvl_off[m + 1] - a.lvl_off[m] - 1);
+    const Real om[3] = {a.omega[3 * m], a.omega[3 * m + 1], DIM == 3 ? a.omega[3 * m + 2] : Real(0)};
+    const double *om64 = a.omega64 + 3 * m;
+    for (int L = 0; L < nlev; ++L) {
+        const int64_t end = ptr[L + 1];
+        for (int64_t i = ptr[L] + threadIdx.x; i < end; i += blockDim.x) {
+            const int64_t K = a.lvl_cells[base + i];
+            const CellRec<Real, NF, DIM> r = a.rec[K];
+            Real s = Real(0);
+            if (a.src_cell) s = a.src_cell[K];
+            if (a.src_dir) s = (Real)a.src_dir[base + K] + s;
+            Real num = r.V * s;
+            Real den = r.sigV;
+#pragma unroll
+            for (int j = 0; j < NF; ++j) {
+                const Real d = face_dot(r, j, om, a.rec64, K, om64);
+                if (d > Real(0)) den = den + d;
+                else if (d < Real(0)) {
+                    const int32_t code = r.nbr[j];
+                    Real up;
+                    if (code == -1) up = a.psi_b;
+                    else {
+                        const int32_t u = code <= -2 ? -code - 2 : code;
+                        const int64_t e = code <= -2 ? lag_index(a.lag_mv, a.lag_u, a.n_lag, m, K, u) : -1;
+                        up = e >= 0 ? a.lag_val[e] : a.psi[base + u];
+                    }
+                    num = num + (-d) * up;
+                }
+            }
+            a.psi[base + K] = num / den;
+        }
+        __syncthreads();
+    }
+}
+
+template <class Real, int NF, int DIM>
+__global__ void __launch_bounds__(1024) k_sweep_dir(DirArgs<Real, NF, DIM> a) {
+    sweep_direction(a, (int)blockIdx.x);
+}
+
+// Batched sweep: one workgroup per (instance, direction) task of an
+// ensemble of independent graphs, all in one launch.  Instances may differ
+// in cell type; a task of a converged instance returns at once.
+template <class Real>
+struct BatchInst {
+    const void *rec;
+    const void *rec64;
+    const int32_t *lvl_cells;
+    const int64_t *lvl_ptr;
+    const int64_t *lvl_off;
+    int64_t nc;
+    const Real *omega;
+    const double *omega64;
+    const Real *src_cell;
+    const float *src_dir;
+    Real *psi;
+    const uint64_t *lag_mv;
+    const int32_t *lag_u;
+    const Real *lag_val;
+    int64_t n_lag;
+    Real psi_b;
+    int32_t ctype;
+    int32_t nd;
+};
+
+template <class Real, int NF, int DIM>
+__device__ void batch_task(const BatchInst<Real> &b, int m) {
+    DirArgs<Real, NF, DIM> a;
+    a.rec = static_cast<const CellRec<Real, NF, DIM> *>(b.rec);
+    a.rec64 = static_cast<const CellRec<double, NF, DIM> *>(b.rec64);
+    a.lvl_cells = b.lvl_cells;
+    a.lvl_ptr = b.lvl_ptr;
+    a.lvl_off = b.lvl_off;
+    a.nc = b.nc;
+    a.omega = b.omega;
+    a.omega64 = b.omega64;
+    a.src_cell = b.src_cell;
+    a.src_dir = b.src_dir;
+    a.psi = b.psi;
+    a.lag_mv = b.lag_mv;
+    a.lag_u = b.lag_u;
+    a.lag_val = b.lag_val;
+    a.n_lag = b.n_lag;
+    a.psi_b = b.psi_b;
+    sweep_direction(a, m);
+}
+
+template <class Real>
+__global__ void __launch_bounds__(1024) k_sweep_batch(const BatchInst<Real> *inst, const int32_t *task_inst,
+                                                     const int32_t *task_dir, const int32_t *active) {
+    const int i = task_inst[blockIdx.x];
+    if (!active[i]) return;
+    const BatchInst<Real> &b = inst[i];
+    const int m = task_dir[blockIdx.x];
+    if (b.ctype == JSWEEP_TRI) batch_task<Real, 3, 2>(b, m);
+    else if (b.ctype == JSWEEP_TET) batch_task<Real, 4, 3>(b, m);
+    else batch_task<Real, 6, 3>(b, m);
 }
 
 // ticket counters back to zero before a sweep
@@ -239,7 +388,7 @@ int persistent_waves(Graph &g, bool fp32, const jsweep_params *p, int *waves_per
 }
 
 template <class Real, int NF, int DIM>
-static void launch_impl(Graph &g, const Real *src_cell, const float *src_dir, Real *psi, Real psi_b,
+static void launch_persistent(Graph &g, const Real *src_cell, const float *src_dir, Real *psi, Real psi_b,
                         const jsweep_params *p, hipStream_t s) {
     SweepArgs<Real, NF, DIM> a;
     a.rec = sizeof(Real) == 8 ? reinterpret_cast<const CellRec<Real, NF, DIM> *>(g.rec64.p)
@@ -263,11 +412,16 @@ static void launch_impl(Graph &g, const Real *src_cell, const float *src_dir, Re
     a.n_lag = g.n_lag;
     a.tickets = reinterpret_cast<uint32_t *>(g.status.as<char>() + 128);
     a.stream_off = g.stream_off.as<int64_t>();
-    a.grab = (p && p->chunks_per_ticket > 0) ? p->chunks_per_ticket : (g.has_tuned && g.tuned.chunks_per_ticket > 0 ? g.tuned.chunks_per_ticket : 2);
+    a.grab = (p && p->chunks_per_ticket > 0) ? p->chunks_per_ticket : (g.has_tuned && g.tuned.chunks_per_ticket > 0 ? g.tuned.chunks_per_ticket : 4);
     a.psi_b = psi_b;
     g.epoch = g.epoch % 255 + 1;
     a.epoch = (uint32_t)g.epoch;
     a.watchdog_ticks = watchdog_ticks();
+    a.stamps = g.trace ? g.trace_buf.as<uint32_t>() : nullptr;
+    {
+        const char *e = std::getenv("JSWEEP_POLL_NAP");
+        a.nap = e ? (uint32_t)std::max(1, std::atoi(e)) : 2u;
+    }
     int wpb = 4;
     int waves = persistent_waves(g, sizeof(Real) == 4, p, &wpb);
     int64_t need = std::max<int64_t>(1, g.n_chunks);
@@ -286,6 +440,61 @@ static void launch_impl(Graph &g, const Real *src_cell, const float *src_dir, Re
         JSW_HIP(hipEventRecord(ev1, s));
         g.prof_events.push_back({ev0, ev1});
     }
+}
+
+template <class Real, int NF, int DIM>
+static void launch_dir(Graph &g, const Real *src_cell, const float *src_dir, Real *psi, Real psi_b,
+                       const jsweep_params *p, hipStream_t s) {
+    DirArgs<Real, NF, DIM> a;
+    a.rec = sizeof(Real) == 8 ? reinterpret_cast<const CellRec<Real, NF, DIM> *>(g.rec64.p)
+                              : reinterpret_cast<const CellRec<Real, NF, DIM> *>(g.rec32.p);
+    a.rec64 = g.rec64.as<CellRec<double, NF, DIM>>();
+    a.lvl_cells = g.lvl_cells.as<int32_t>();
+    a.lvl_ptr = g.lvl_ptr_d.as<int64_t>();
+    a.lvl_off = g.lvl_off_d.as<int64_t>();
+    a.nc = g.nc;
+    a.omega = sizeof(Real) == 8 ? reinterpret_cast<const Real *>(g.omega64.p) : reinterpret_cast<const Real *>(g.omega32.p);
+    a.omega64 = g.omega64.as<double>();
+    a.src_cell = src_cell;
+    a.src_dir = src_dir;
+    a.psi = psi;
+    a.lag_mv = g.lag_mv.as<uint64_t>();
+    a.lag_u = g.lag_u.as<int32_t>();
+    a.lag_val = sizeof(Real) == 8 ? reinterpret_cast<const Real *>(g.lag_val64.p) : reinterpret_cast<const Real *>(g.lag_val32.p);
+    a.n_lag = g.n_lag;
+    a.psi_b = psi_b;
+    int threads = (p && p->waves_per_block > 0) ? 64 * p->waves_per_block
+                  : (g.has_tuned && g.tuned.waves_per_block > 0 ? 64 * g.tuned.waves_per_block : 0);
+    if (threads <= 0) threads = g.nd <= g.n_cu ? 1024 : (g.nd <= 2 * g.n_cu ? 512 : 256);
+    threads = std::min(1024, std::max(64, threads));
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (g.profile) {
+        JSW_HIP(hipEventCreate(&ev0));
+        JSW_HIP(hipEventCreate(&ev1));
+        JSW_HIP(hipEventRecord(ev0, s));
+    }
+    hipLaunchKernelGGL((k_sweep_dir<Real, NF, DIM>), dim3(g.nd), dim3(threads), 0, s, a);
+    JSW_HIP(hipGetLastError());
+    if (g.profile) {
+        JSW_HIP(hipEventRecord(ev1, s));
+        g.prof_events.push_back({ev0, ev1});
+    }
+}
+
+// Sweep strategy: the direction-parallel kernel when there are enough
+// directions to occupy the compute units, the data-driven persistent
+// kernel otherwise (or as requested).
+int sweep_strategy(const Graph &g, const jsweep_params *p) {
+    int st = (p && p->strategy > 0) ? p->strategy : (g.has_tuned && g.tuned.strategy > 0 ? g.tuned.strategy : 0);
+    if (st == JSWEEP_STRATEGY_DATA_DRIVEN || st == JSWEEP_STRATEGY_DIRECTION) return st;
+    return 2 * g.nd >= g.n_cu ? JSWEEP_STRATEGY_DIRECTION : JSWEEP_STRATEGY_DATA_DRIVEN;
+}
+
+template <class Real, int NF, int DIM>
+static void launch_impl(Graph &g, const Real *src_cell, const float *src_dir, Real *psi, Real psi_b,
+                        const jsweep_params *p, hipStream_t s) {
+    if (sweep_strategy(g, p) == JSWEEP_STRATEGY_DIRECTION) launch_dir<Real, NF, DIM>(g, src_cell, src_dir, psi, psi_b, p, s);
+    else launch_persistent<Real, NF, DIM>(g, src_cell, src_dir, psi, psi_b, p, s);
 }
 
 void launch_sweep64(Graph &g, const double *src_cell, double *psi, double psi_b, const jsweep_params *p, hipStream_t s) {
@@ -312,6 +521,67 @@ int check_sweep_status(Graph &g, hipStream_t s) {
     JSW_HIP(hipStreamSynchronize(s));
     g.epoch = 0;
     return JSWEEP_E_STALLED;
+}
+
+// Host side of the batched sweep: the instance table and the task list are
+// built once per batch solve (BatchSweep) and the launch is a single kernel.
+template <class Real>
+static void fill_inst(Graph &g, BatchInst<Real> &b, const Real *src_cell, const float *src_dir, Real *psi, Real psi_b) {
+    b.rec = sizeof(Real) == 8 ? g.rec64.p : g.rec32.p;
+    b.rec64 = g.rec64.p;
+    b.lvl_cells = g.lvl_cells.as<int32_t>();
+    b.lvl_ptr = g.lvl_ptr_d.as<int64_t>();
+    b.lvl_off = g.lvl_off_d.as<int64_t>();
+    b.nc = g.nc;
+    b.omega = sizeof(Real) == 8 ? reinterpret_cast<const Real *>(g.omega64.p) : reinterpret_cast<const Real *>(g.omega32.p);
+    b.omega64 = g.omega64.as<double>();
+    b.src_cell = src_cell;
+    b.src_dir = src_dir;
+    b.psi = psi;
+    b.lag_mv = g.lag_mv.as<uint64_t>();
+    b.lag_u = g.lag_u.as<int32_t>();
+    b.lag_val = sizeof(Real) == 8 ? reinterpret_cast<const Real *>(g.lag_val64.p) : reinterpret_cast<const Real *>(g.lag_val32.p);
+    b.n_lag = g.n_lag;
+    b.psi_b = psi_b;
+    b.ctype = g.ctype;
+    b.nd = g.nd;
+}
+
+void BatchSweep::setup(int32_t n, Graph *const *graphs, bool fp32, const void *const *src_cell,
+                       const float *const *src_dir, void *const *psi, const double *psi_b, int threads_, hipStream_t s) {
+    this->fp32 = fp32;
+    std::vector<int32_t> ti, td;
+    for (int i = 0; i < n; ++i)
+        for (int m = 0; m < graphs[i]->nd; ++m) { ti.push_back(i); td.push_back(m); }
+    n_tasks = (int64_t)ti.size();
+    task_inst.alloc(4 * n_tasks);
+    task_dir.alloc(4 * n_tasks);
+    JSW_HIP(hipMemcpyAsync(task_inst.p, ti.data(), 4 * n_tasks, hipMemcpyHostToDevice, s));
+    JSW_HIP(hipMemcpyAsync(task_dir.p, td.data(), 4 * n_tasks, hipMemcpyHostToDevice, s));
+    if (fp32) {
+        std::vector<BatchInst<float>> h(n);
+        for (int i = 0; i < n; ++i)
+            fill_inst<float>(*graphs[i], h[i], (const float *)src_cell[i], src_dir[i], (float *)psi[i], (float)psi_b[i]);
+        inst.alloc(sizeof(BatchInst<float>) * n);
+        JSW_HIP(hipMemcpyAsync(inst.p, h.data(), sizeof(BatchInst<float>) * n, hipMemcpyHostToDevice, s));
+    } else {
+        std::vector<BatchInst<double>> h(n);
+        for (int i = 0; i < n; ++i)
+            fill_inst<double>(*graphs[i], h[i], (const double *)src_cell[i], src_dir[i], (double *)psi[i], psi_b[i]);
+        inst.alloc(sizeof(BatchInst<double>) * n);
+        JSW_HIP(hipMemcpyAsync(inst.p, h.data(), sizeof(BatchInst<double>) * n, hipMemcpyHostToDevice, s));
+    }
+    threads = threads_ > 0 ? std::min(1024, std::max(64, threads_)) : 256;
+}
+
+void BatchSweep::launch(const int32_t *active, hipStream_t s) {
+    if (fp32)
+        hipLaunchKernelGGL(k_sweep_batch<float>, dim3((unsigned)n_tasks), dim3(threads), 0, s,
+                           inst.as<BatchInst<float>>(), task_inst.as<int32_t>(), task_dir.as<int32_t>(), active);
+    else
+        hipLaunchKernelGGL(k_sweep_batch<double>, dim3((unsigned)n_tasks), dim3(threads), 0, s,
+                           inst.as<BatchInst<double>>(), task_inst.as<int32_t>(), task_dir.as<int32_t>(), active);
+    JSW_HIP(hipGetLastError());
 }
 
 }  // namespace jsw

@@ -1,0 +1,92 @@
+"""GPU: batched ensemble solves (one sweep launch for every instance),
+autotuning and solver options, against the oracle."""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_common import J, dev, gpu_graph, host, need_gpu, rel_max, torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ensemble(oracle_mod):
+    need_gpu()
+    probs = W.ensemble(seed=4, count=6, min_cells=300, max_cells=2500)
+    out = []
+    for p in probs:
+        print(f"[instance] {p.name} dim {p.mesh.dim} cells {p.n_cells} dirs {p.n_dirs} c {p.meta['c']:.3f}", flush=True)
+        out.append((p, oracle_mod.graph_for(p), gpu_graph(p)))
+    return out
+
+
+def _problems(ens):
+    return [{"sigma_t": dev(p.sigma_t), "sigma_s": dev(p.sigma_s), "q": dev(p.q),
+             "phi": dev(np.zeros(p.n_cells)), "psi": dev(np.zeros((p.n_dirs, p.n_cells)))} for p, _, _ in ens]
+
+
+def test_batch_fp64_matches_oracle_after_20_iterations(ensemble):
+    probs = _problems(ensemble)
+    stats = J.solve_batch([g for _, _, g in ensemble], probs, mode=J.JSWEEP_FP64, tol=0.0, max_iter=20,
+                          allow_not_converged=True)
+    for (p, og, _), pr, st in zip(ensemble, probs, stats):
+        psi_ref, phi_ref, hist = og.source_iteration(p.sigma_t, p.sigma_s, p.q, p.weight, 20)
+        e1, e2 = rel_max(host(pr["phi"]), phi_ref), rel_max(host(pr["psi"]), psi_ref)
+        print(f"[batch64] {p.name} phi {e1:.2e} psi {e2:.2e} sweeps {st['sweeps']} rho {st['residual']:.2e}", flush=True)
+        assert st["sweeps"] == 20
+        assert e1 <= 1e-12 and e2 <= 1e-12
+
+
+def test_batch_refined_converges_to_oracle(ensemble):
+    probs = _problems(ensemble)
+    stats = J.solve_batch([g for _, _, g in ensemble], probs, mode=J.JSWEEP_FP32_REFINED, tol=1e-11, max_iter=20000)
+    for (p, og, _), pr, st in zip(ensemble, probs, stats):
+        _, phi_ref, hist = og.source_iteration(p.sigma_t, p.sigma_s, p.q, p.weight, 20000, 1e-13)
+        got = host(pr["phi"])
+        err = float(np.linalg.norm(got - phi_ref) / np.linalg.norm(phi_ref))
+        print(f"[batch32] {p.name} outer {st['outer_iters']} sweeps {st['sweeps']} (oracle {len(hist)}) "
+              f"rho {st['residual']:.2e} phi rel {err:.2e}", flush=True)
+        assert st["residual"] <= 1e-11
+        assert err <= 1e-8
+
+
+def test_autotune_and_tuned_solve(ensemble):
+    p, og, g = ensemble[1]
+    prm = J.autotune([g], J.JSWEEP_FP64)
+    d = prm.as_dict()
+    assert d["strategy"] in (1, 2) and d["waves_per_block"] >= 1
+    phi = dev(np.zeros(p.n_cells))
+    J.solve(g, dev(p.sigma_t), dev(p.sigma_s), dev(p.q), phi, mode=J.JSWEEP_FP64, tol=0.0, max_iter=5,
+            allow_not_converged=True)
+    _, phi_ref, _ = og.source_iteration(p.sigma_t, p.sigma_s, p.q, p.weight, 5)
+    assert rel_max(host(phi), phi_ref) <= 1e-12
+    prm_b = J.autotune([g for _, _, g in ensemble], J.JSWEEP_FP32_REFINED)
+    assert prm_b.as_dict()["strategy"] == 2
+
+
+def test_warm_start_boundary_and_not_converged(ensemble):
+    p, og, g = ensemble[0]
+    st_, ss, q = dev(p.sigma_t), dev(p.sigma_s), dev(p.q)
+    # 10 + 10 iterations with a warm start equal 20 from zero
+    psi = dev(np.zeros((p.n_dirs, p.n_cells)))
+    phi = dev(np.zeros(p.n_cells))
+    r = J.solve(g, st_, ss, q, phi, psi, psi_boundary=0.4, mode=J.JSWEEP_FP64, tol=0.0, max_iter=10,
+                allow_not_converged=True)
+    assert not r["converged"]
+    J.solve(g, st_, ss, q, phi, psi, psi_boundary=0.4, mode=J.JSWEEP_FP64 | J.JSWEEP_WARM_START, tol=0.0,
+            max_iter=10, allow_not_converged=True)
+    psi_ref, phi_ref, _ = og.source_iteration(p.sigma_t, p.sigma_s, p.q, p.weight, 20, psi_b=0.4)
+    assert rel_max(host(phi), phi_ref) <= 1e-12 and rel_max(host(psi), psi_ref) <= 1e-12
+    with pytest.raises(J.JsweepError) as e:
+        J.solve(g, st_, ss, q, phi, mode=J.JSWEEP_FP64, tol=1e-30, max_iter=3)
+    assert e.value.code == J.JSWEEP_E_NOT_CONVERGED
+
+
+def test_residual_history(ensemble):
+    p, og, g = ensemble[2]
+    phi = dev(np.zeros(p.n_cells))
+    r = J.solve(g, dev(p.sigma_t), dev(p.sigma_s), dev(p.q), phi, mode=J.JSWEEP_FP64, tol=0.0, max_iter=8,
+                history=16, allow_not_converged=True)
+    _, _, hist = og.source_iteration(p.sigma_t, p.sigma_s, p.q, p.weight, 8)
+    assert len(r["history"]) == 8
+    assert np.allclose(r["history"], hist, rtol=1e-9, atol=1e-300)

@@ -77,21 +77,23 @@ def test_fp64_sweep_deterministic(cases):
     assert torch.equal(a, b)
 
 
-def test_fp64_source_iteration_20(cases):
+@pytest.mark.parametrize("strategy", [J.JSWEEP_STRATEGY_DATA_DRIVEN, J.JSWEEP_STRATEGY_DIRECTION])
+def test_fp64_source_iteration_20(cases, strategy):
     for name, p, og, gg in cases:
         psi_ref, phi_ref, hist = og.source_iteration(p.sigma_t, p.sigma_s, p.q, p.weight, 20)
         phi = dev(np.zeros(p.n_cells))
         psi = dev(np.zeros((p.n_dirs, p.n_cells)))
         st = J.solve(gg, dev(p.sigma_t), dev(p.sigma_s), dev(p.q), phi, psi, mode=J.JSWEEP_FP64, tol=0.0,
-                     max_iter=20, allow_not_converged=True)
+                     max_iter=20, params=J.Params(strategy=strategy), allow_not_converged=True)
         assert st["sweeps"] == 20
         e1, e2 = rel_max(host(phi), phi_ref), rel_max(host(psi), psi_ref)
-        print(f"[si64] {name} phi {e1:.3e} psi {e2:.3e} rho {st['residual']:.3e} vs {hist[-1]:.3e}", flush=True)
+        print(f"[si64 s{strategy}] {name} phi {e1:.3e} psi {e2:.3e} rho {st['residual']:.3e} vs {hist[-1]:.3e}", flush=True)
         assert e1 <= 1e-12 and e2 <= 1e-12, name
         assert abs(st["residual"] - hist[-1]) <= 1e-6 * hist[-1] + 1e-15
 
 
-def test_fp32_refined_converges_to_oracle(cases):
+@pytest.mark.parametrize("strategy", [J.JSWEEP_STRATEGY_DATA_DRIVEN, J.JSWEEP_STRATEGY_DIRECTION])
+def test_fp32_refined_converges_to_oracle(cases, strategy):
     for name, p, og, gg in cases:
         if p.n_cells * p.n_dirs > 2_000_000:
             continue
@@ -99,9 +101,9 @@ def test_fp32_refined_converges_to_oracle(cases):
         assert hist[-1] <= 1e-13
         phi = dev(np.zeros(p.n_cells))
         st = J.solve(gg, dev(p.sigma_t), dev(p.sigma_s), dev(p.q), phi, mode=J.JSWEEP_FP32_REFINED, tol=1e-11,
-                     max_iter=20000)
+                     max_iter=20000, params=J.Params(strategy=strategy))
         got = host(phi)
         err = float(np.linalg.norm(got - phi_ref) / np.linalg.norm(phi_ref))
-        print(f"[refined] {name} outer {st['outer_iters']} sweeps {st['sweeps']} (oracle {len(hist)}) "
+        print(f"[refined s{strategy}] {name} outer {st['outer_iters']} sweeps {st['sweeps']} (oracle {len(hist)}) "
               f"rho {st['residual']:.2e} phi rel {err:.3e}", flush=True)
         assert err <= 1e-8, name
