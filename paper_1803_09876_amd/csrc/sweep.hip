@@ -481,13 +481,14 @@ static void launch_dir(Graph &g, const Real *src_cell, const float *src_dir, Rea
     }
 }
 
-// Sweep strategy: the direction-parallel kernel when there are enough
-// directions to occupy the compute units, the data-driven persistent
-// kernel otherwise (or as requested).
+// Sweep strategy (unless requested or tuned): the data-driven persistent
+// kernel, which keeps many levels of every direction in flight; for small
+// graphs, where a sweep is a chain of short levels, the direction-parallel
+// kernel (no cross-CU hand-off per level).
 int sweep_strategy(const Graph &g, const jsweep_params *p) {
     int st = (p && p->strategy > 0) ? p->strategy : (g.has_tuned && g.tuned.strategy > 0 ? g.tuned.strategy : 0);
     if (st == JSWEEP_STRATEGY_DATA_DRIVEN || st == JSWEEP_STRATEGY_DIRECTION) return st;
-    return 2 * g.nd >= g.n_cu ? JSWEEP_STRATEGY_DIRECTION : JSWEEP_STRATEGY_DATA_DRIVEN;
+    return g.nc * g.nd <= (int64_t)2000000 ? JSWEEP_STRATEGY_DIRECTION : JSWEEP_STRATEGY_DATA_DRIVEN;
 }
 
 template <class Real, int NF, int DIM>
