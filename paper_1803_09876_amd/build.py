@@ -1,8 +1,9 @@
 """Builds the HIP library libjsweep.so for gfx950 (hipcc).
 
 All device code is compiled without floating-point contraction (the graph
-construction must be bit-reproducible) and with packed-FP32 instructions
-disabled."""
+construction must be bit-reproducible), with packed-FP32 instructions
+disabled, and without the compiler's wavefront-level atomic rewriting (it
+would wait for a prefetched work ticket right where it is requested)."""
 from __future__ import annotations
 
 import os
@@ -21,6 +22,7 @@ ARCH = os.environ.get("JSWEEP_ARCH", "gfx950")
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     "-Wno-unused-command-line-argument", "-Wno-unused-result",
 ]
 

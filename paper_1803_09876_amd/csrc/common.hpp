@@ -69,6 +69,13 @@ struct Chunk {
     uint32_t a, b;
 };
 
+// Chunk block, kBlock int32 words: [0, 64) the chunk's cells (-1 past the
+// end), [64] Chunk::a, [65] the number of upwind chunks (-1: more than
+// kBlockDeps, read the CSR lists instead), [66, 66 + kBlockDeps) the upwind
+// chunks.  Lane l of a wavefront reads words l and 64 + l (l < 32).
+constexpr int kBlock = 96;
+constexpr int kBlockDeps = kBlock - 66;
+
 // The work list is split into kStreams streams (a direction belongs to one
 // stream); on MI355X stream x runs on XCD x.
 constexpr int kStreams = 8;
@@ -94,6 +101,7 @@ struct Graph {
     DevBuf lvl_ptr_d, lvl_off_d;         // device copies of the level pointers
     int max_levels = 0;
     DevBuf chunks;                       // [n_chunks] Chunk: per stream, ordered by (level, direction)
+    DevBuf cblk;                         // [n_chunks * kBlock] int32 chunk blocks (see kBlock)
     int64_t n_chunks = 0;
     DevBuf stream_off;                   // [kStreams + 1] int64 chunk offsets of the streams
     std::vector<int64_t> stream_off_h;

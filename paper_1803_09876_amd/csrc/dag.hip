@@ -344,6 +344,26 @@ __global__ void k_chunk_pos(const Chunk *chunks, int64_t n_chunks, const int32_t
     }
 }
 
+// Chunk block: everything a wavefront needs to start a chunk, in one
+// contiguous record it reads in a single memory round trip: the cells
+// (-1 past the end), the descriptor, and the upwind chunks inline when they
+// fit (else the count is -1 and the CSR lists are used).
+__global__ void k_chunk_block(const Chunk *chunks, int64_t n_chunks, const int32_t *lvl_cells, int64_t nc,
+                              const int32_t *dep_ptr, const int32_t *dep, int32_t *blk) {
+    int64_t c = blockIdx.x;
+    int lane = threadIdx.x;
+    if (c >= n_chunks) return;
+    Chunk ch = chunks[c];
+    int m = (int)(ch.a & 0xffffu), cnt = (int)(ch.a >> 16) + 1;
+    int32_t *b = blk + c * kBlock;
+    b[lane] = lane < cnt ? lvl_cells[(int64_t)m * nc + ch.b + lane] : -1;
+    int32_t d0 = dep_ptr[c], nd = dep_ptr[c + 1] - d0;
+    bool inl = nd <= kBlockDeps;
+    if (lane == 0) b[64] = (int32_t)ch.a;
+    if (lane == 1) b[65] = inl ? nd : -1;
+    if (lane < kBlockDeps) b[66 + lane] = inl && lane < nd ? dep[d0 + lane] : -1;
+}
+
 // one 64-lane workgroup per chunk: gather the upwind chunks of its
 // vertices and keep the first occurrence of each; WRITE = 0 counts them
 template <int NF, int DIM, bool WRITE>
@@ -420,6 +440,10 @@ static void build_coarsened(Graph &g, const LagView &lag, hipStream_t s) {
                                                              g.rec64.as<Rec>(), g.omega64.as<double>(), g.nc, lag,
                                                              pos.as<int32_t>(), nullptr, g.dep_ptr.as<int32_t>(),
                                                              g.dep.as<int32_t>());
+    JSW_HIP(hipGetLastError());
+    g.cblk.alloc(4 * (size_t)kBlock * std::max<int64_t>(1, nch));
+    k_chunk_block<<<(unsigned)nch, 64, 0, s>>>(g.chunks.as<Chunk>(), nch, g.lvl_cells.as<int32_t>(), g.nc,
+                                               g.dep_ptr.as<int32_t>(), g.dep.as<int32_t>(), g.cblk.as<int32_t>());
     JSW_HIP(hipGetLastError());
     JSW_HIP(hipStreamSynchronize(s));
 }

@@ -47,8 +47,7 @@ template <class Real, int NF, int DIM>
 struct SweepArgs {
     const CellRec<Real, NF, DIM> *rec;
     const CellRec<double, NF, DIM> *rec64;   // FP64 records: classification of near-parallel faces
-    const int32_t *lvl_cells;
-    const Chunk *chunks;
+    const int32_t *cblk;                     // [n_chunks * kBlock] chunk blocks
     const int32_t *dep_ptr;                  // [n_chunks + 1] coarsened-graph in-edges
     const int32_t *dep;                      // upwind chunks
     int64_t nc;
@@ -125,26 +124,35 @@ __global__ void k_sweep(SweepArgs<Real, NF, DIM> a) {
     const int64_t first = a.stream_off[stream];
     const int64_t per_stream = a.stream_off[stream + 1] - first;
     const uint8_t epoch = (uint8_t)a.epoch;
+    // tickets: each is a range of a.grab consecutive chunks of the stream;
+    // the next one is requested together with the loads of the last chunk
+    // of the current range, so the two round trips overlap
+    uint32_t *ticket = a.tickets + 32 * stream;
+    uint32_t nxt = 0;
+    if (lane == 0) nxt = atomicAdd(ticket, (uint32_t)a.grab);
     int64_t t_next = 0, t_end = 0;
     // every lane stays in this loop until the wavefront leaves it as a whole
     // (ticket broadcast, dependency poll and abort are wave-uniform)
     while (true) {
         if (t_next == t_end) {
-            uint32_t t = 0;
-            if (lane == 0) t = atomicAdd(a.tickets + 32 * stream, (uint32_t)a.grab);
-            t_next = __shfl(t, 0);
+            t_next = (int64_t)__builtin_amdgcn_readfirstlane(nxt);
             t_end = t_next + a.grab;
         }
         if (t_next >= per_stream) break;
         const int64_t c = first + t_next;
         ++t_next;
+        if (t_next == t_end && lane == 0) nxt = atomicAdd(ticket, (uint32_t)a.grab);
         const uint32_t t_take = (uint32_t)__builtin_amdgcn_s_memrealtime();
-        const Chunk ch = a.chunks[c];
-        const int m = (int)(ch.a & 0xffffu);
-        const int cnt = (int)(ch.a >> 16) + 1;
+        const int32_t *blk = a.cblk + c * kBlock;
+        const int32_t item = blk[lane];
+        const int32_t w2 = lane < 32 ? blk[64 + lane] : -1;
+        const uint32_t hdr = (uint32_t)__builtin_amdgcn_readfirstlane(w2);
+        const int ndep = __builtin_amdgcn_readlane(w2, 1);
+        const int m = (int)(hdr & 0xffffu);
+        const int cnt = (int)(hdr >> 16) + 1;
         const bool active = lane < cnt;
         const int64_t base = (int64_t)m * a.nc;
-        const int64_t K = active ? (int64_t)a.lvl_cells[base + ch.b + lane] : 0;
+        const int64_t K = active ? (int64_t)item : 0;
         CellRec<Real, NF, DIM> r;
         Real s = Real(0);
         if (active) {
@@ -152,12 +160,18 @@ __global__ void k_sweep(SweepArgs<Real, NF, DIM> a) {
             if (a.src_cell) s = a.src_cell[K];
             if (a.src_dir) s = (Real)a.src_dir[base + K] + s;
         }
-        // wait until every upwind chunk of this sweep is complete
-        const int32_t d0 = a.dep_ptr[c], d1 = a.dep_ptr[c + 1];
+        // wait until every upwind chunk of this sweep is complete (inline
+        // list: lanes 2 .. 2 + ndep hold the upwind chunks)
+        int32_t d0 = 0, d1 = 0;
+        if (ndep < 0) { d0 = a.dep_ptr[c]; d1 = a.dep_ptr[c + 1]; }
         uint64_t t0 = 0;
         for (uint32_t spin = 0;; ++spin) {
             bool ok = true;
-            for (int32_t k = d0 + lane; k < d1; k += 64) ok &= ld_coherent(a.cflag + a.dep[k]) == epoch;
+            if (ndep >= 0) {
+                if (lane >= 2 && lane < 2 + ndep) ok = ld_coherent(a.cflag + w2) == epoch;
+            } else {
+                for (int32_t k = d0 + lane; k < d1; k += 64) ok &= ld_coherent(a.cflag + a.dep[k]) == epoch;
+            }
             if (__all(ok)) break;
             if (spin == 0) t0 = __builtin_amdgcn_s_memrealtime();
             if ((spin & 7) == 7) {
@@ -394,8 +408,7 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
     a.rec = sizeof(Real) == 8 ? reinterpret_cast<const CellRec<Real, NF, DIM> *>(g.rec64.p)
                               : reinterpret_cast<const CellRec<Real, NF, DIM> *>(g.rec32.p);
     a.rec64 = g.rec64.as<CellRec<double, NF, DIM>>();
-    a.lvl_cells = g.lvl_cells.as<int32_t>();
-    a.chunks = g.chunks.as<Chunk>();
+    a.cblk = g.cblk.as<int32_t>();
     a.dep_ptr = g.dep_ptr.as<int32_t>();
     a.dep = g.dep.as<int32_t>();
     a.nc = g.nc;
@@ -412,7 +425,7 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
     a.n_lag = g.n_lag;
     a.tickets = reinterpret_cast<uint32_t *>(g.status.as<char>() + 128);
     a.stream_off = g.stream_off.as<int64_t>();
-    a.grab = (p && p->chunks_per_ticket > 0) ? p->chunks_per_ticket : (g.has_tuned && g.tuned.chunks_per_ticket > 0 ? g.tuned.chunks_per_ticket : 4);
+    a.grab = (p && p->chunks_per_ticket > 0) ? p->chunks_per_ticket : (g.has_tuned && g.tuned.chunks_per_ticket > 0 ? g.tuned.chunks_per_ticket : 1);
     a.psi_b = psi_b;
     g.epoch = g.epoch % 255 + 1;
     a.epoch = (uint32_t)g.epoch;
