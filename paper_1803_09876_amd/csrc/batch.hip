@@ -36,6 +36,7 @@ struct BInst {
     float *r32, *dpsi, *g32;
     const uint64_t *lag_mv;
     const int32_t *lag_u;
+    const int32_t *posi;
     double *lag64;
     float *lag32;
     int64_t n_lag, nc;
@@ -128,15 +129,15 @@ __global__ void k_b_residual(const BInst *I, const int64_t *coff, int n, int64_t
     double rr, V;
     if (b.ctype == JSWEEP_TRI) {
         const CellRec<double, 3, 2> r = ((const CellRec<double, 3, 2> *)b.rec64)[K];
-        rr = residual_cell(r, K, b.omega, b.w, b.psi, b.q[K], b.sigma_s[K], b.psi_b, b.nc, b.nd, b.phi, r32);
+        rr = residual_cell(r, K, b.omega, b.w, b.psi, b.q[K], b.sigma_s[K], b.psi_b, b.nc, b.nd, b.phi, r32, b.posi);
         V = r.V;
     } else if (b.ctype == JSWEEP_TET) {
         const CellRec<double, 4, 3> r = ((const CellRec<double, 4, 3> *)b.rec64)[K];
-        rr = residual_cell(r, K, b.omega, b.w, b.psi, b.q[K], b.sigma_s[K], b.psi_b, b.nc, b.nd, b.phi, r32);
+        rr = residual_cell(r, K, b.omega, b.w, b.psi, b.q[K], b.sigma_s[K], b.psi_b, b.nc, b.nd, b.phi, r32, b.posi);
         V = r.V;
     } else {
         const CellRec<double, 6, 3> r = ((const CellRec<double, 6, 3> *)b.rec64)[K];
-        rr = residual_cell(r, K, b.omega, b.w, b.psi, b.q[K], b.sigma_s[K], b.psi_b, b.nc, b.nd, b.phi, r32);
+        rr = residual_cell(r, K, b.omega, b.w, b.psi, b.q[K], b.sigma_s[K], b.psi_b, b.nc, b.nd, b.phi, r32, b.posi);
         V = r.V;
     }
     atomicAdd(acc + 4 * i, rr);
@@ -233,6 +234,7 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
         }
         b.lag_mv = g.lag_mv.as<uint64_t>();
         b.lag_u = g.lag_u.as<int32_t>();
+        b.posi = g.posi.as<int32_t>();
         b.lag64 = g.lag_val64.as<double>();
         b.lag32 = g.lag_val32.as<float>();
         b.n_lag = g.n_lag;

@@ -71,10 +71,36 @@ struct Chunk {
 
 // Chunk block, kBlock int32 words: [0, 64) the chunk's cells (-1 past the
 // end), [64] Chunk::a, [65] the number of upwind chunks (-1: more than
-// kBlockDeps, read the CSR lists instead), [66, 66 + kBlockDeps) the upwind
-// chunks.  Lane l of a wavefront reads words l and 64 + l (l < 32).
+// kBlockDeps, read the CSR lists instead), [66] Chunk::b (the first
+// position), [67, 67 + kBlockDeps) the upwind chunks.  Lane l of a
+// wavefront reads words l and 64 + l (l < 32).
 constexpr int kBlock = 96;
-constexpr int kBlockDeps = kBlock - 66;
+constexpr int kBlockDeps = kBlock - 67;
+
+// Sweep program: per chunk lane (index c * 64 + lane, stride S = 64 *
+// n_chunks) the vertex's inflow faces in local face order, ns slots each:
+// code >= 0 position of the upwind vertex in the direction's level order,
+// -1 boundary (psi_b), <= -2 lagged edge -(e + 2),
+// kNoFace empty; coefficient a_f = |Omega . S_f| (FP64 and FP32 copies);
+// and den = sigma_t V + sum of outflow a_f in local face order (refreshed
+// when sigma_t changes).
+constexpr int32_t kNoFace = INT32_MIN;
+
+// Index of the lagged edge u -> v of direction m in the (m, v, u)-sorted
+// lists, or -1 when that edge is not lagged.
+__device__ inline int64_t lag_index(const uint64_t *lag_mv, const int32_t *lag_u, int64_t n_lag, int m, int64_t v,
+                                    int64_t u) {
+    uint64_t key = ((uint64_t)(uint32_t)m << 32) | (uint64_t)v;
+    int64_t lo = 0, hi = n_lag;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (lag_mv[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    for (; lo < n_lag && lag_mv[lo] == key; ++lo)
+        if (lag_u[lo] == u) return lo;
+    return -1;
+}
 
 // The work list is split into kStreams streams (a direction belongs to one
 // stream); on MI355X stream x runs on XCD x.
@@ -109,6 +135,14 @@ struct Graph {
     DevBuf dep_ptr, dep;                 // coarsened graph: upwind chunks of every chunk (CSR)
     int64_t n_dep = 0;
     DevBuf cflag;                        // [n_chunks] uint8 completion epochs
+    int ns = 0;                          // sweep program: inflow slots per vertex
+    DevBuf pcode, pa64, pa32;            // [ns * S] int32 / double / float (pa32 on first FP32 use)
+    DevBuf pden64, pden32;               // [S] double / float
+    DevBuf sig_last;                     // [nc] sigma_t the denominators were built for
+    bool den64_ok = false, den32_ok = false;
+    DevBuf vsrc;                         // [nc] V s (FP64) or {V, s} (FP32) of the running sweep
+    DevBuf psi_pos;                      // [nd*nc] fluxes of the running sweep in level order
+    DevBuf posi;                         // [nd*nc] int32 level position of every vertex
     int epoch = 0;                       // last epoch used (1..255)
     DevBuf status;                       // [4] int32 device status words (watchdog)
     // lagged edges, sorted by (direction, downwind cell, upwind cell)

@@ -22,16 +22,7 @@ namespace jsw {
 // ---------------------------------------------------------------------------
 __device__ inline bool is_lagged(const uint64_t *lag_mv, const int32_t *lag_u, int64_t n_lag, int m, int64_t v,
                                  int64_t u) {
-    uint64_t key = ((uint64_t)(uint32_t)m << 32) | (uint64_t)v;
-    int64_t lo = 0, hi = n_lag;
-    while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (lag_mv[mid] < key) lo = mid + 1;
-        else hi = mid;
-    }
-    for (; lo < n_lag && lag_mv[lo] == key; ++lo)
-        if (lag_u[lo] == u) return true;
-    return false;
+    return lag_index(lag_mv, lag_u, n_lag, m, v, u) >= 0;
 }
 
 // wavefront-aggregated append to a work list
@@ -361,7 +352,92 @@ __global__ void k_chunk_block(const Chunk *chunks, int64_t n_chunks, const int32
     bool inl = nd <= kBlockDeps;
     if (lane == 0) b[64] = (int32_t)ch.a;
     if (lane == 1) b[65] = inl ? nd : -1;
-    if (lane < kBlockDeps) b[66 + lane] = inl && lane < nd ? dep[d0 + lane] : -1;
+    if (lane == 2) b[66] = (int32_t)ch.b;
+    if (lane < kBlockDeps) b[67 + lane] = inl && lane < nd ? dep[d0 + lane] : -1;
+}
+
+// ---------------------------------------------------------------------------
+// Sweep program (layout in common.hpp): the inflow faces of every chunk
+// lane, classified exactly as in the graph (FP64 Omega . S, left to right),
+// so the sweep reads coalesced per-lane streams instead of cell records.
+// COUNT = true: the largest number of inflow faces of any vertex.
+// ---------------------------------------------------------------------------
+template <int NF, int DIM, bool COUNT>
+__global__ void k_program(const int32_t *blk, int64_t n_chunks, const CellRec<double, NF, DIM> *rec,
+                          const double *omega, LagView lag, const int32_t *posi, int64_t nc, int ns, int32_t *max_in,
+                          int32_t *code, double *a) {
+    const int64_t c = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (c >= n_chunks) return;
+    const int64_t S = 64 * n_chunks, idx = c * 64 + lane;
+    const int32_t K = blk[c * kBlock + lane];
+    const int m = (int)((uint32_t)blk[c * kBlock + 64] & 0xffffu);
+    int n = 0;
+    if (K >= 0) {
+        const CellRec<double, NF, DIM> r = rec[K];
+        const double om[3] = {omega[3 * m], omega[3 * m + 1], omega[3 * m + 2]};
+        for (int j = 0; j < NF; ++j) {
+            const double d = out_dot(r, j, om);
+            if (!(d < 0.0)) continue;
+            if (!COUNT) {
+                const int32_t nb = r.nbr[j];
+                int32_t cd = -1;
+                if (nb != -1) {
+                    const int64_t u = nbr_id(nb);
+                    const int64_t e = nb <= -2 ? lag_index(lag.mv, lag.u, lag.n, m, K, u) : -1;
+                    cd = e >= 0 ? (int32_t)(-(e + 2)) : posi[(int64_t)m * nc + u];
+                }
+                code[n * S + idx] = cd;
+                a[n * S + idx] = -d;
+            }
+            ++n;
+        }
+    }
+    if (COUNT) {
+        if (n > 0) atomicMax(max_in, n);
+    } else {
+        for (int j = n; j < ns; ++j) {
+            code[j * S + idx] = kNoFace;
+            a[j * S + idx] = 0.0;
+        }
+    }
+}
+
+__global__ void k_positions(const int32_t *lvl_cells, int64_t nc, int64_t n, int32_t *posi) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t m = i / nc;
+    posi[m * nc + lvl_cells[i]] = (int32_t)(i - m * nc);
+}
+
+template <int NF, int DIM>
+static void build_program(Graph &g, const LagView &lag, hipStream_t s) {
+    using Rec = CellRec<double, NF, DIM>;
+    const int64_t nch = g.n_chunks, S = 64 * nch;
+    DevBuf mx(4);
+    JSW_HIP(hipMemsetAsync(mx.p, 0, 4, s));
+    k_program<NF, DIM, true><<<(unsigned)nch, 64, 0, s>>>(g.cblk.as<int32_t>(), nch, g.rec64.as<Rec>(),
+                                                          g.omega64.as<double>(), lag, nullptr, g.nc, 0,
+                                                          mx.as<int32_t>(), nullptr, nullptr);
+    JSW_HIP(hipGetLastError());
+    int32_t ns = 0;
+    JSW_HIP(hipMemcpyAsync(&ns, mx.p, 4, hipMemcpyDeviceToHost, s));
+    JSW_HIP(hipStreamSynchronize(s));
+    g.ns = std::max(1, (int)ns);
+    g.pcode.alloc(4 * (size_t)g.ns * S);
+    g.pa64.alloc(8 * (size_t)g.ns * S);
+    // position of every vertex in its direction's level order
+    const int64_t N = g.nc * g.nd;
+    g.posi.alloc(4 * N);
+    DevBuf &posi = g.posi;
+    k_positions<<<(unsigned)ceil_div(N, 256), 256, 0, s>>>(g.lvl_cells.as<int32_t>(), g.nc, N, posi.as<int32_t>());
+    JSW_HIP(hipGetLastError());
+    k_program<NF, DIM, false><<<(unsigned)nch, 64, 0, s>>>(g.cblk.as<int32_t>(), nch, g.rec64.as<Rec>(),
+                                                           g.omega64.as<double>(), lag, posi.as<int32_t>(), g.nc,
+                                                           g.ns, nullptr, g.pcode.as<int32_t>(), g.pa64.as<double>());
+    JSW_HIP(hipGetLastError());
+    g.pden64.alloc(8 * (size_t)S);
+    g.den64_ok = g.den32_ok = false;
 }
 
 // one 64-lane workgroup per chunk: gather the upwind chunks of its
@@ -632,6 +708,7 @@ static void dag_impl(Graph &g, bool lag_cycles, hipStream_t s) {
     g.stream_off.alloc(8 * (kStreams + 1));
     JSW_HIP(hipMemcpyAsync(g.stream_off.p, g.stream_off_h.data(), 8 * (kStreams + 1), hipMemcpyHostToDevice, s));
     build_coarsened<NF, DIM>(g, lag, s);
+    build_program<NF, DIM>(g, lag, s);
     g.cflag.alloc(std::max<int64_t>(1, g.n_chunks));
     JSW_HIP(hipMemsetAsync(g.cflag.p, 0, g.cflag.bytes, s));
     g.epoch = 0;

@@ -8,11 +8,12 @@ namespace jsw {
 // operator, looping over directions:
 //   phi_K = sum_m w_m psi_{K,m}
 //   r_{K,m} = q_K + sigma_s,K phi_K - (den psi_{K,m} - in_{K,m}) / V_K
-// Returns V_K sum_m w_m r^2 (and writes phi_K; r in FP32 when r32 != null).
+// Returns V_K sum_m w_m r^2 (and writes phi_K; r in FP32 when r32 != null,
+// at the vertex's level position posi[m nc + K] within direction m).
 template <int NF, int DIM>
 __device__ inline double residual_cell(const CellRec<double, NF, DIM> &r, int64_t K, const double *omega,
                                        const double *w, const double *psi, double q, double sigma_s, double psi_b,
-                                       int64_t nc, int nd, double *phi, float *r32) {
+                                       int64_t nc, int nd, double *phi, float *r32, const int32_t *posi) {
     int64_t nb[NF];
     for (int j = 0; j < NF; ++j) nb[j] = r.nbr[j] <= -2 ? (int64_t)(-r.nbr[j] - 2) : (int64_t)r.nbr[j];
     double ph = 0.0;
@@ -31,7 +32,7 @@ __device__ inline double residual_cell(const CellRec<double, NF, DIM> &r, int64_
             else if (d > 0.0) den = den + d;
         }
         const double res = src - (den * pm[K] - in) / r.V;
-        if (r32) r32[(int64_t)m * nc + K] = (float)res;
+        if (r32) r32[(int64_t)m * nc + posi[(int64_t)m * nc + K]] = (float)res;
         cell = cell + w[m] * (res * res);
     }
     return r.V * cell;

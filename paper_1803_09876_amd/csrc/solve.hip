@@ -26,6 +26,68 @@ __global__ void k_sigv(CellRec<double, NF, DIM> *r64, CellRec<float, NF, DIM> *r
     if (r32) r32[K].sigV = (float)v;
 }
 
+// flags a change of sigma_t since the last call (and keeps the new values)
+__global__ void k_sig_changed(const double *sig, double *last, int64_t nc, int32_t *flag) {
+    int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (K >= nc) return;
+    const double v = sig[K];
+    if (__double_as_longlong(v) != __double_as_longlong(last[K])) {
+        last[K] = v;
+        *flag = 1;
+    }
+}
+
+// Sweep-program denominators, one per chunk lane: sigma_t V plus the
+// outflow a_f in local face order (FP64; the FP32 copy sums the rounded
+// terms in FP32).
+template <int NF, int DIM, bool F32>
+__global__ void k_den(const int32_t *blk, int64_t n_chunks, const CellRec<double, NF, DIM> *rec, const double *omega,
+                      double *den64, float *den32) {
+    const int64_t c = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (c >= n_chunks) return;
+    const int64_t idx = c * 64 + lane;
+    const int32_t K = blk[c * kBlock + lane];
+    if (K < 0) {
+        if (F32) den32[idx] = 1.0f;
+        else den64[idx] = 1.0;
+        return;
+    }
+    const int m = (int)((uint32_t)blk[c * kBlock + 64] & 0xffffu);
+    const CellRec<double, NF, DIM> r = rec[K];
+    const double om[3] = {omega[3 * m], omega[3 * m + 1], omega[3 * m + 2]};
+    double den = r.sigV;
+    float den_f = (float)r.sigV;
+    for (int j = 0; j < NF; ++j) {
+        double d = om[0] * r.S[j][0] + om[1] * r.S[j][1];
+        if constexpr (DIM == 3) d = d + om[2] * r.S[j][2];
+        if (d > 0.0) {
+            den = den + d;
+            den_f = den_f + (float)d;
+        }
+    }
+    if (F32) den32[idx] = den_f;
+    else den64[idx] = den;
+}
+
+__global__ void k_narrow(const double *a, int64_t n, float *b) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
+template <int NF, int DIM>
+static void refresh_den(Graph &g, bool f32, hipStream_t s) {
+    const int64_t nch = g.n_chunks;
+    const unsigned gb = (unsigned)ceil_div(nch, 4);
+    if (f32)
+        k_den<NF, DIM, true><<<gb, 256, 0, s>>>(g.cblk.as<int32_t>(), nch, g.rec64.as<CellRec<double, NF, DIM>>(),
+                                                g.omega64.as<double>(), nullptr, g.pden32.as<float>());
+    else
+        k_den<NF, DIM, false><<<gb, 256, 0, s>>>(g.cblk.as<int32_t>(), nch, g.rec64.as<CellRec<double, NF, DIM>>(),
+                                                 g.omega64.as<double>(), g.pden64.as<double>(), nullptr);
+    JSW_HIP(hipGetLastError());
+}
+
 void refresh_sigma(Graph &g, const double *sigma_t, bool fp32, hipStream_t s) {
     if (fp32) build_rec32(g, s);
     int gb = (int)ceil_div(g.nc, kB);
@@ -37,6 +99,41 @@ void refresh_sigma(Graph &g, const double *sigma_t, bool fp32, hipStream_t s) {
     else
         k_sigv<6, 3><<<gb, kB, 0, s>>>(g.rec64.as<CellRec<double, 6, 3>>(), (CellRec<float, 6, 3> *)r32, sigma_t, g.nc);
     JSW_HIP(hipGetLastError());
+    // sweep-program denominators: rebuilt only when sigma_t has changed
+    if (!g.n_chunks) return;
+    if (!g.sig_last.p) {
+        g.sig_last.alloc(8 * g.nc + 64);
+        g.den64_ok = g.den32_ok = false;
+    }
+    int32_t *flag = reinterpret_cast<int32_t *>(g.sig_last.as<char>() + 8 * g.nc);
+    JSW_HIP(hipMemsetAsync(flag, 0, 4, s));
+    k_sig_changed<<<gb, kB, 0, s>>>(sigma_t, g.sig_last.as<double>(), g.nc, flag);
+    JSW_HIP(hipGetLastError());
+    int32_t changed = 0;
+    JSW_HIP(hipMemcpyAsync(&changed, flag, 4, hipMemcpyDeviceToHost, s));
+    JSW_HIP(hipStreamSynchronize(s));
+    if (changed) g.den64_ok = g.den32_ok = false;
+    auto run = [&](bool f32) {
+        if (g.ctype == JSWEEP_TRI) refresh_den<3, 2>(g, f32, s);
+        else if (g.ctype == JSWEEP_TET) refresh_den<4, 3>(g, f32, s);
+        else refresh_den<6, 3>(g, f32, s);
+    };
+    if (!g.den64_ok) {
+        run(false);
+        g.den64_ok = true;
+    }
+    if (fp32 && !g.den32_ok) {
+        const int64_t S = 64 * g.n_chunks;
+        if (!g.pa32.p) {
+            g.pa32.alloc(4 * (size_t)g.ns * S);
+            k_narrow<<<(unsigned)ceil_div((int64_t)g.ns * S, kB), kB, 0, s>>>(g.pa64.as<double>(), (int64_t)g.ns * S,
+                                                                            g.pa32.as<float>());
+            JSW_HIP(hipGetLastError());
+        }
+        if (!g.pden32.p) g.pden32.alloc(4 * (size_t)S);
+        run(true);
+        g.den32_ok = true;
+    }
 }
 
 // s_K = q_K + sigma_s,K phi_K
@@ -85,16 +182,16 @@ void lag_snapshot64(Graph &g, const double *psi, hipStream_t s) { lag_snapshot<d
 //   phi_K = sum_m w_m psi_{K,m}
 //   r_{K,m} = q_K + sigma_s,K phi_K - (den psi_{K,m} - in_{K,m}) / V_K
 // norms: acc[0] += V_K sum_m w_m r^2, acc[1] += V_K q_K^2.  Optionally stores
-// r in FP32 (the correction-sweep source).
+// r in FP32 (the correction-sweep source, in level-position order).
 template <int NF, int DIM>
 __global__ void k_residual(const CellRec<double, NF, DIM> *rec, const double *omega, const double *w, const double *psi,
                            const double *q, const double *sigma_s, double psi_b, int64_t nc, int nd, double *phi,
-                           float *r32, double *acc) {
+                           float *r32, const int32_t *posi, double *acc) {
     int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double rr = 0.0, qq = 0.0;
     if (K < nc) {
         const CellRec<double, NF, DIM> r = rec[K];
-        rr = residual_cell(r, K, omega, w, psi, q[K], sigma_s[K], psi_b, nc, nd, phi, r32);
+        rr = residual_cell(r, K, omega, w, psi, q[K], sigma_s[K], psi_b, nc, nd, phi, r32, posi);
         qq = r.V * (q[K] * q[K]);
     }
     block_add(rr, acc);
@@ -133,11 +230,11 @@ static double residual(Graph &g, const double *psi, const double *q, const doubl
     int gb = (int)ceil_div(g.nc, kB);
     const double *om = g.omega64.as<double>(), *w = g.weight.as<double>();
     if (g.ctype == JSWEEP_TRI)
-        k_residual<3, 2><<<gb, kB, 0, s>>>(g.rec64.as<CellRec<double, 3, 2>>(), om, w, psi, q, sigma_s, psi_b, g.nc, g.nd, phi, r32, acc);
+        k_residual<3, 2><<<gb, kB, 0, s>>>(g.rec64.as<CellRec<double, 3, 2>>(), om, w, psi, q, sigma_s, psi_b, g.nc, g.nd, phi, r32, g.posi.as<int32_t>(), acc);
     else if (g.ctype == JSWEEP_TET)
-        k_residual<4, 3><<<gb, kB, 0, s>>>(g.rec64.as<CellRec<double, 4, 3>>(), om, w, psi, q, sigma_s, psi_b, g.nc, g.nd, phi, r32, acc);
+        k_residual<4, 3><<<gb, kB, 0, s>>>(g.rec64.as<CellRec<double, 4, 3>>(), om, w, psi, q, sigma_s, psi_b, g.nc, g.nd, phi, r32, g.posi.as<int32_t>(), acc);
     else
-        k_residual<6, 3><<<gb, kB, 0, s>>>(g.rec64.as<CellRec<double, 6, 3>>(), om, w, psi, q, sigma_s, psi_b, g.nc, g.nd, phi, r32, acc);
+        k_residual<6, 3><<<gb, kB, 0, s>>>(g.rec64.as<CellRec<double, 6, 3>>(), om, w, psi, q, sigma_s, psi_b, g.nc, g.nd, phi, r32, g.posi.as<int32_t>(), acc);
     JSW_HIP(hipGetLastError());
     double h[2];
     JSW_HIP(hipMemcpyAsync(h, acc, 16, hipMemcpyDeviceToHost, s));

@@ -13,6 +13,11 @@
 // coarsened graph (Theorem 1), and every dependency of a chunk comes earlier
 // in its stream.
 //
+// Data: a chunk's lanes read the sweep program (common.hpp) at c * 64 +
+// lane -- inflow-face codes and coefficients, denominator -- as coalesced
+// streams, so the only scattered accesses are the cell's V s (or V and s in
+// FP32) and the upwind fluxes; cell records are not read at all.
+//
 // Execution: a persistent grid no larger than the device can hold at once.
 // A running wavefront takes the next chunks of its stream (workgroup id mod
 // kStreams, which is also the XCD the workgroup runs on) with one atomic
@@ -43,27 +48,25 @@
 
 namespace jsw {
 
-template <class Real, int NF, int DIM>
+template <class Real>
 struct SweepArgs {
-    const CellRec<Real, NF, DIM> *rec;
-    const CellRec<double, NF, DIM> *rec64;   // FP64 records: classification of near-parallel faces
     const int32_t *cblk;                     // [n_chunks * kBlock] chunk blocks
     const int32_t *dep_ptr;                  // [n_chunks + 1] coarsened-graph in-edges
     const int32_t *dep;                      // upwind chunks
     int64_t nc;
-    const Real *omega;                       // [nd*3]
-    const double *omega64;                   // [nd*3]
-    const Real *src_cell;                    // [nc] or null
-    const float *src_dir;                    // [nd*nc] or null
-    Real *psi;                               // [nd*nc]
+    int64_t stride;                          // 64 * n_chunks: program slot stride
+    const int32_t *pcode;                    // [ns * stride]
+    const Real *pa;                          // [ns * stride]
+    const Real *pden;                        // [stride]
+    const void *vs;                          // [nc] V s (double) or {V, s} (float2)
+    const float *src_dir;                    // [nd*nc] or null (FP32 path)
+    Real *psi;                               // [nd*nc] by cell
+    Real *psi_pos;                           // [nd*nc] by level position (upwind reads)
     uint8_t *cflag;                          // [n_chunks] completion epochs
     int32_t *status;                         // [0]: stalled flag
     uint32_t *tickets;                       // per-stream counters, 128 B apart
     const int64_t *stream_off;               // [kStreams + 1] chunk range of each stream
-    const uint64_t *lag_mv;
-    const int32_t *lag_u;
     const Real *lag_val;
-    int64_t n_lag;
     Real psi_b;
     uint32_t epoch;
     int32_t grab;                            // chunks taken per ticket
@@ -79,20 +82,6 @@ __device__ __forceinline__ T ld_coherent(const T *p) {
 template <class T>
 __device__ __forceinline__ void st_coherent(T *p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ inline int64_t lag_index(const uint64_t *lag_mv, const int32_t *lag_u, int64_t n_lag, int m, int64_t v,
-                                    int64_t u) {
-    uint64_t key = ((uint64_t)(uint32_t)m << 32) | (uint64_t)v;
-    int64_t lo = 0, hi = n_lag;
-    while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (lag_mv[mid] < key) lo = mid + 1;
-        else hi = mid;
-    }
-    for (; lo < n_lag && lag_mv[lo] == key; ++lo)
-        if (lag_u[lo] == u) return lo;
-    return -1;
 }
 
 // Omega . S of local face j, evaluated left to right.  The FP32 path takes
@@ -117,8 +106,9 @@ __device__ __forceinline__ Real face_dot(const CellRec<Real, NF, DIM> &r, int j,
     return d;
 }
 
-template <class Real, int NF, int DIM>
-__global__ void k_sweep(SweepArgs<Real, NF, DIM> a) {
+// NS: inflow slots per vertex (the program's ns, up to the faces per cell)
+template <class Real, int NS>
+__global__ void k_sweep(SweepArgs<Real> a) {
     const int lane = threadIdx.x & 63;
     const int stream = (int)(blockIdx.x % kStreams);
     const int64_t first = a.stream_off[stream];
@@ -143,32 +133,48 @@ __global__ void k_sweep(SweepArgs<Real, NF, DIM> a) {
         ++t_next;
         if (t_next == t_end && lane == 0) nxt = atomicAdd(ticket, (uint32_t)a.grab);
         const uint32_t t_take = (uint32_t)__builtin_amdgcn_s_memrealtime();
+        // one round trip: block (cells, descriptor, upwind chunks) and the
+        // lane's program entries
         const int32_t *blk = a.cblk + c * kBlock;
         const int32_t item = blk[lane];
         const int32_t w2 = lane < 32 ? blk[64 + lane] : -1;
+        const int64_t idx = c * 64 + lane;
+        const Real den = a.pden[idx];
+        int32_t code[NS];
+        Real af[NS];
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            code[j] = a.pcode[j * a.stride + idx];
+            af[j] = a.pa[j * a.stride + idx];
+        }
         const uint32_t hdr = (uint32_t)__builtin_amdgcn_readfirstlane(w2);
         const int ndep = __builtin_amdgcn_readlane(w2, 1);
+        const int64_t pos0 = (int64_t)(uint32_t)__builtin_amdgcn_readlane(w2, 2);
         const int m = (int)(hdr & 0xffffu);
-        const int cnt = (int)(hdr >> 16) + 1;
-        const bool active = lane < cnt;
+        const bool active = item >= 0;
         const int64_t base = (int64_t)m * a.nc;
         const int64_t K = active ? (int64_t)item : 0;
-        CellRec<Real, NF, DIM> r;
-        Real s = Real(0);
+        // V s of the cell
+        Real num = Real(0);
         if (active) {
-            r = a.rec[K];
-            if (a.src_cell) s = a.src_cell[K];
-            if (a.src_dir) s = (Real)a.src_dir[base + K] + s;
+            if constexpr (sizeof(Real) == 8) {
+                num = reinterpret_cast<const double *>(a.vs)[K];
+            } else {
+                const float2 vs = reinterpret_cast<const float2 *>(a.vs)[K];
+                float sv = vs.y;
+                if (a.src_dir) sv = a.src_dir[base + pos0 + lane] + sv;
+                num = vs.x * sv;
+            }
         }
         // wait until every upwind chunk of this sweep is complete (inline
-        // list: lanes 2 .. 2 + ndep hold the upwind chunks)
+        // list: lanes 3 .. 3 + ndep hold the upwind chunks)
         int32_t d0 = 0, d1 = 0;
         if (ndep < 0) { d0 = a.dep_ptr[c]; d1 = a.dep_ptr[c + 1]; }
         uint64_t t0 = 0;
         for (uint32_t spin = 0;; ++spin) {
             bool ok = true;
             if (ndep >= 0) {
-                if (lane >= 2 && lane < 2 + ndep) ok = ld_coherent(a.cflag + w2) == epoch;
+                if (lane >= 3 && lane < 3 + ndep) ok = ld_coherent(a.cflag + w2) == epoch;
             } else {
                 for (int32_t k = d0 + lane; k < d1; k += 64) ok &= ld_coherent(a.cflag + a.dep[k]) == epoch;
             }
@@ -186,38 +192,26 @@ __global__ void k_sweep(SweepArgs<Real, NF, DIM> a) {
         }
         const uint32_t t_ready = (uint32_t)__builtin_amdgcn_s_memrealtime();
         if (active) {
-            const Real om[3] = {a.omega[3 * m], a.omega[3 * m + 1], DIM == 3 ? a.omega[3 * m + 2] : Real(0)};
-            const double *om64 = a.omega64 + 3 * m;
-            Real aj[NF], val[NF];
-            int kind[NF];   // 0 none, 1 outflow, 2 inflow
+            // upwind fluxes: interior and lagged ones are loaded together
+            // (one device-scope load per slot, the address selected without
+            // branching; other slots read the cell's own entry and discard it)
+            Real val[NS];
 #pragma unroll
-            for (int j = 0; j < NF; ++j) {
-                const Real d = face_dot(r, j, om, a.rec64, K, om64);
-                const int32_t code = r.nbr[j];
-                const int32_t u = code <= -2 ? -code - 2 : code;
-                kind[j] = 0;
-                aj[j] = Real(0);
-                val[j] = Real(0);
-                if (d > Real(0)) { kind[j] = 1; aj[j] = d; }
-                else if (d < Real(0)) {
-                    aj[j] = -d;
-                    kind[j] = 2;
-                    if (code == -1) val[j] = a.psi_b;
-                    else {
-                        const int64_t e = code <= -2 ? lag_index(a.lag_mv, a.lag_u, a.n_lag, m, K, u) : -1;
-                        val[j] = e >= 0 ? a.lag_val[e] : ld_coherent(a.psi + base + u);
-                    }
-                }
+            for (int j = 0; j < NS; ++j) {
+                const int32_t cd = code[j];
+                const bool lagged = cd <= -2 && cd != kNoFace;
+                const Real *src = cd >= 0 ? a.psi_pos + base + cd
+                                  : lagged ? a.lag_val + (-(int64_t)cd - 2) : a.psi_pos + base + pos0 + lane;
+                const Real v = ld_coherent(src);
+                val[j] = (cd >= 0 || lagged) ? v : (cd == -1 ? a.psi_b : Real(0));
             }
-            // step-scheme balance, summed in local face order
-            Real num = r.V * s;
-            Real den = r.sigV;
+            // step-scheme balance, inflow faces in local face order
 #pragma unroll
-            for (int j = 0; j < NF; ++j) {
-                if (kind[j] == 2) num = num + aj[j] * val[j];
-                else if (kind[j] == 1) den = den + aj[j];
-            }
-            a.psi[base + K] = num / den;
+            for (int j = 0; j < NS; ++j)
+                if (code[j] != kNoFace) num = num + af[j] * val[j];
+            const Real v = num / den;
+            a.psi_pos[base + pos0 + lane] = v;
+            a.psi[base + K] = v;
         }
         // publish the chunk once every lane's flux store has completed
         __builtin_amdgcn_s_waitcnt(0);
@@ -229,6 +223,17 @@ __global__ void k_sweep(SweepArgs<Real, NF, DIM> a) {
             a.stamps[3 * c + 2] = (uint32_t)__builtin_amdgcn_s_memrealtime();
         }
     }
+}
+
+// V s per cell for the FP64 sweep (the same product the balance takes),
+// {V, s} for the FP32 sweep
+__global__ void k_vs64(const double *vol, const double *src, int64_t nc, double *vs) {
+    int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (K < nc) vs[K] = src ? vol[K] * src[K] : vol[K] * 0.0;
+}
+__global__ void k_vs32(const double *vol, const float *src, int64_t nc, float2 *vs) {
+    int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (K < nc) vs[K] = make_float2((float)vol[K], src ? src[K] : 0.0f);
 }
 
 // ---------------------------------------------------------------------------
@@ -277,7 +282,7 @@ __device__ void sweep_direction(const DirArgs<Real, NF, DIM> &a, int m) {
             const CellRec<Real, NF, DIM> r = a.rec[K];
             Real s = Real(0);
             if (a.src_cell) s = a.src_cell[K];
-            if (a.src_dir) s = (Real)a.src_dir[base + K] + s;
+            if (a.src_dir) s = (Real)a.src_dir[base + i] + s;
             Real num = r.V * s;
             Real den = r.sigV;
 #pragma unroll
@@ -378,54 +383,83 @@ static uint64_t watchdog_ticks() {
     return (uint64_t)(ms * 1e5);   // s_memrealtime runs at 100 MHz
 }
 
-template <class Real, int NF, int DIM>
+template <class Real, int NS>
 static const void *kernel_ptr() {
-    return reinterpret_cast<const void *>(&k_sweep<Real, NF, DIM>);
+    return reinterpret_cast<const void *>(&k_sweep<Real, NS>);
 }
 
-static const void *sweep_kernel(int ctype, bool fp32) {
-    if (ctype == JSWEEP_TRI) return fp32 ? kernel_ptr<float, 3, 2>() : kernel_ptr<double, 3, 2>();
-    if (ctype == JSWEEP_TET) return fp32 ? kernel_ptr<float, 4, 3>() : kernel_ptr<double, 4, 3>();
-    return fp32 ? kernel_ptr<float, 6, 3>() : kernel_ptr<double, 6, 3>();
+template <class Real>
+static const void *sweep_kernel_t(int ns) {
+    switch (ns) {
+    case 1: return kernel_ptr<Real, 1>();
+    case 2: return kernel_ptr<Real, 2>();
+    case 3: return kernel_ptr<Real, 3>();
+    case 4: return kernel_ptr<Real, 4>();
+    case 5: return kernel_ptr<Real, 5>();
+    default: return kernel_ptr<Real, 6>();
+    }
+}
+
+static const void *sweep_kernel(int ns, bool fp32) {
+    if (ns < 1 || ns > 6) fail(JSWEEP_E_DEVICE, "sweep program with an unsupported number of inflow slots");
+    return fp32 ? sweep_kernel_t<float>(ns) : sweep_kernel_t<double>(ns);
 }
 
 int persistent_waves(Graph &g, bool fp32, const jsweep_params *p, int *waves_per_block) {
     int wpb = (p && p->waves_per_block > 0) ? p->waves_per_block : (g.has_tuned && g.tuned.waves_per_block > 0 ? g.tuned.waves_per_block : 4);
     if (wpb > 16) wpb = 16;
     int occ = 0;
-    JSW_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sweep_kernel(g.ctype, fp32), 64 * wpb, 0));
+    JSW_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sweep_kernel(g.ns, fp32), 64 * wpb, 0));
     if (occ < 1) occ = 1;
-    int bpc = (p && p->blocks_per_cu > 0) ? p->blocks_per_cu : (g.has_tuned && g.tuned.blocks_per_cu > 0 ? g.tuned.blocks_per_cu : occ);
+    // default: two workgroups per CU for graphs of a few hundred thousand
+    // chunks (fewer wavefronts contend for the critical path), all that fit
+    // for larger ones
+    int bpc = (p && p->blocks_per_cu > 0) ? p->blocks_per_cu
+              : (g.has_tuned && g.tuned.blocks_per_cu > 0 ? g.tuned.blocks_per_cu
+                                                          : (g.n_chunks < (int64_t)1000000 ? 2 : occ));
     if (bpc > occ) bpc = occ;
     *waves_per_block = wpb;
     return bpc * g.n_cu * wpb;
 }
 
-template <class Real, int NF, int DIM>
+template <class Real>
 static void launch_persistent(Graph &g, const Real *src_cell, const float *src_dir, Real *psi, Real psi_b,
-                        const jsweep_params *p, hipStream_t s) {
-    SweepArgs<Real, NF, DIM> a;
-    a.rec = sizeof(Real) == 8 ? reinterpret_cast<const CellRec<Real, NF, DIM> *>(g.rec64.p)
-                              : reinterpret_cast<const CellRec<Real, NF, DIM> *>(g.rec32.p);
-    a.rec64 = g.rec64.as<CellRec<double, NF, DIM>>();
+                              const jsweep_params *p, hipStream_t s) {
+    const bool f32 = sizeof(Real) == 4;
+    if (!(f32 ? g.den32_ok : g.den64_ok)) fail(JSWEEP_E_DEVICE, "sweep program denominators not built");
+    SweepArgs<Real> a;
     a.cblk = g.cblk.as<int32_t>();
     a.dep_ptr = g.dep_ptr.as<int32_t>();
     a.dep = g.dep.as<int32_t>();
     a.nc = g.nc;
-    a.omega = sizeof(Real) == 8 ? reinterpret_cast<const Real *>(g.omega64.p) : reinterpret_cast<const Real *>(g.omega32.p);
-    a.omega64 = g.omega64.as<double>();
-    a.src_cell = src_cell;
+    a.stride = 64 * g.n_chunks;
+    a.pcode = g.pcode.as<int32_t>();
+    a.pa = reinterpret_cast<const Real *>(f32 ? g.pa32.p : g.pa64.p);
+    a.pden = reinterpret_cast<const Real *>(f32 ? g.pden32.p : g.pden64.p);
+    if (g.vsrc.bytes < (size_t)(8 * g.nc)) g.vsrc.alloc(8 * g.nc);
+    const int gb = (int)ceil_div(g.nc, 256);
+    if (f32)
+        k_vs32<<<gb, 256, 0, s>>>(g.vol.as<double>(), reinterpret_cast<const float *>(src_cell), g.nc,
+                                 g.vsrc.as<float2>());
+    else
+        k_vs64<<<gb, 256, 0, s>>>(g.vol.as<double>(), reinterpret_cast<const double *>(src_cell), g.nc,
+                                 g.vsrc.as<double>());
+    JSW_HIP(hipGetLastError());
+    a.vs = g.vsrc.p;
     a.src_dir = src_dir;
     a.psi = psi;
+    if (g.psi_pos.bytes < (size_t)(8 * g.nc * g.nd)) g.psi_pos.alloc(8 * g.nc * g.nd);
+    a.psi_pos = g.psi_pos.as<Real>();
     a.cflag = g.cflag.as<uint8_t>();
     a.status = g.status.as<int32_t>();
-    a.lag_mv = g.lag_mv.as<uint64_t>();
-    a.lag_u = g.lag_u.as<int32_t>();
-    a.lag_val = sizeof(Real) == 8 ? reinterpret_cast<const Real *>(g.lag_val64.p) : reinterpret_cast<const Real *>(g.lag_val32.p);
-    a.n_lag = g.n_lag;
+    a.lag_val = reinterpret_cast<const Real *>(f32 ? g.lag_val32.p : g.lag_val64.p);
     a.tickets = reinterpret_cast<uint32_t *>(g.status.as<char>() + 128);
     a.stream_off = g.stream_off.as<int64_t>();
-    a.grab = (p && p->chunks_per_ticket > 0) ? p->chunks_per_ticket : (g.has_tuned && g.tuned.chunks_per_ticket > 0 ? g.tuned.chunks_per_ticket : 1);
+    // defaults (measured): one chunk per ticket for graphs of a few hundred
+    // thousand chunks, where the critical path dominates; two for larger ones
+    a.grab = (p && p->chunks_per_ticket > 0) ? p->chunks_per_ticket
+             : (g.has_tuned && g.tuned.chunks_per_ticket > 0 ? g.tuned.chunks_per_ticket
+                                                              : (g.n_chunks < (int64_t)1000000 ? 1 : 2));
     a.psi_b = psi_b;
     g.epoch = g.epoch % 255 + 1;
     a.epoch = (uint32_t)g.epoch;
@@ -436,7 +470,7 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
         a.nap = e ? (uint32_t)std::max(1, std::atoi(e)) : 2u;
     }
     int wpb = 4;
-    int waves = persistent_waves(g, sizeof(Real) == 4, p, &wpb);
+    int waves = persistent_waves(g, f32, p, &wpb);
     int64_t need = std::max<int64_t>(1, g.n_chunks);
     if (waves > need) waves = (int)((need + wpb - 1) / wpb * wpb);
     int blocks = std::max(waves / wpb, kStreams);
@@ -447,8 +481,8 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
         JSW_HIP(hipEventCreate(&ev1));
         JSW_HIP(hipEventRecord(ev0, s));
     }
-    hipLaunchKernelGGL((k_sweep<Real, NF, DIM>), dim3(blocks), dim3(64 * wpb), 0, s, a);
-    JSW_HIP(hipGetLastError());
+    void *args[] = {&a};
+    JSW_HIP(hipLaunchKernel(sweep_kernel(g.ns, f32), dim3(blocks), dim3(64 * wpb), args, 0, s));
     if (g.profile) {
         JSW_HIP(hipEventRecord(ev1, s));
         g.prof_events.push_back({ev0, ev1});
@@ -508,7 +542,7 @@ template <class Real, int NF, int DIM>
 static void launch_impl(Graph &g, const Real *src_cell, const float *src_dir, Real *psi, Real psi_b,
                         const jsweep_params *p, hipStream_t s) {
     if (sweep_strategy(g, p) == JSWEEP_STRATEGY_DIRECTION) launch_dir<Real, NF, DIM>(g, src_cell, src_dir, psi, psi_b, p, s);
-    else launch_persistent<Real, NF, DIM>(g, src_cell, src_dir, psi, psi_b, p, s);
+    else launch_persistent<Real>(g, src_cell, src_dir, psi, psi_b, p, s);
 }
 
 void launch_sweep64(Graph &g, const double *src_cell, double *psi, double psi_b, const jsweep_params *p, hipStream_t s) {
