@@ -21,10 +21,16 @@ Also reported:
   cpu_baseline  the oracle (serial FP64 CPU code) timed on a bounded sample
                 of the same workload on this host;
   time_to_tol   wall time of jsweep_solve to rho <= 1e-8, plain FP64 and
-                FP32-refined, with the error of each result against the FP64
-                GPU fixed point (and the sample sweep's error vs the oracle).
+                FP32-refined, on this workload and on the S16 tetrahedral one
+                (60^3 lattice, 6 tets per cube, 288 directions), with the
+                error of each result against the FP64 GPU fixed point (and the
+                sample sweep's error vs the oracle).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-s16]
+                       [--copy-probe] [--steps-only]
+  --copy-probe  first copies 512 MiB device to device (the calibration
+                dispatch for HBM byte counters taken on this run)
+  --steps-only  only the timed steps and the roofline (for profiler runs)
 """
 from __future__ import annotations
 
@@ -50,7 +56,7 @@ def _source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def _traffic(kernel_key: str, launches_bytes_alg: float):
+def _traffic(kernel_key: str):
     """HBM bytes per launch from the committed counter summary, or None if
     it was measured on a different sweep kernel source."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -62,6 +68,28 @@ def _traffic(kernel_key: str, launches_bytes_alg: float):
     if not rec or rec.get("source_hash") != _source_hash():
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def time_to_tol(J, torch, g, p, tol=1e-8):
+    """jsweep_solve to rho <= tol, plain FP64 then FP32-refined, from zero."""
+    st, ss, q = (torch.tensor(a, device="cuda") for a in (p.sigma_t, p.sigma_s, p.q))
+    out, ref = {}, None
+    for name, mode in (("fp64", J.JSWEEP_FP64), ("fp32_refined", J.JSWEEP_FP32_REFINED)):
+        phi = torch.zeros(p.n_cells, dtype=torch.float64, device="cuda")
+        # untimed warm-up of the mode's kernels (one outer iteration)
+        J.solve(g, st, ss, q, torch.zeros_like(phi), mode=mode, tol=0.0, max_iter=1, allow_not_converged=True)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        s = J.solve(g, st, ss, q, phi, mode=mode, tol=tol, max_iter=20000)
+        torch.cuda.synchronize()
+        out[name] = {"seconds": time.perf_counter() - a, "sweeps": s["sweeps"], "outer": s["outer_iters"],
+                     "residual": s["residual"]}
+        if ref is None:
+            ref = phi
+        else:
+            out[name]["phi_rel_err_vs_fp64"] = float(torch.linalg.norm(phi - ref) / torch.linalg.norm(ref))
+    out["speedup_fp32_refined"] = out["fp64"]["seconds"] / out["fp32_refined"]["seconds"]
+    return out
 
 
 def algorithmic_bytes(J, g, n_cells, n_dirs, word):
@@ -97,12 +125,50 @@ def cpu_baseline(problem, psi_gpu_sample):
     }, err
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def extras(args, J, W, torch, g, p, st, ss, q, phi):
+    """FP32 sweep kernel time, the oracle comparison, time-to-1e-8 and the CPU baseline."""
+    nc, nd = p.n_cells, p.n_dirs
+    # FP32 sweep kernel time on the same graph (correction sweeps)
+    J.jsweep_profile(g, True)
+    J.solve(g, st, ss, q, torch.zeros_like(phi), mode=J.JSWEEP_FP32_REFINED, tol=0.0, max_iter=1 + args.warmup,
+            allow_not_converged=True)
+    J.jsweep_profile_read(g, reset=True)
+    J.solve(g, st, ss, q, torch.zeros_like(phi), mode=J.JSWEEP_FP32_REFINED, tol=0.0, max_iter=10,
+            allow_not_converged=True)
+    n32, ms32 = J.jsweep_profile_read(g, reset=True)
+    J.jsweep_profile(g, False)
+    avg32_s = ms32 / max(1, n32) * 1e-3
+    log(f"FP32 sweep kernel {avg32_s * 1e3:.3f} ms")
+    # one sweep on fixed inputs for the comparison with the oracle
+    psi_s = torch.zeros(nd * nc, dtype=torch.float64, device="cuda")
+    J.sweep(g, st, q, psi_s)
+    psi_sample = psi_s.view(nd, nc).cpu().numpy()
+    # time to rho <= 1e-8: plain FP64 vs FP32-refined
+    ttt = {p.name: time_to_tol(J, torch, g, p)}
+    log(f"time to 1e-8 on {p.name}: {json.dumps(ttt[p.name])}")
+    if not args.no_s16:
+        p5 = W.config(5)
+        g5 = J.build_graph(p5.mesh, p5.omega, p5.weight)
+        ttt[p5.name] = time_to_tol(J, torch, g5, p5)
+        g5.close()
+        log(f"time to 1e-8 on {p5.name}: {json.dumps(ttt[p5.name])}")
+    cpu, err = (None, None) if args.no_cpu else cpu_baseline(p, psi_sample)
+    return avg32_s, ttt, cpu, err
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-s16", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--steps-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the sweep path of this "
@@ -117,6 +183,12 @@ def main():
         print("no GPU available", file=sys.stderr)
         sys.exit(1)
     J.load_library()
+    if args.copy_probe:
+        x = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     p = W.config(2)
     nc, nd = p.n_cells, p.n_dirs
     t = time.time()
@@ -127,6 +199,7 @@ def main():
     st, ss, q = (torch.tensor(a, device="cuda") for a in (p.sigma_t, p.sigma_s, p.q))
     phi = torch.zeros(nc, dtype=torch.float64, device="cuda")
     psi = torch.zeros(nd * nc, dtype=torch.float64, device="cuda")
+    log(f"{p.name}: graph built in {t_build:.2f} s")
 
     # warmup, then the timed steps (K source iterations, no early stop)
     J.solve(g, st, ss, q, phi, psi, mode=J.JSWEEP_FP64, tol=0.0, max_iter=max(1, args.warmup),
@@ -146,32 +219,12 @@ def main():
     bytes_alg, edges = algorithmic_bytes(J, g, nc, nd, 8)
     avg_kernel_s = kernel_ms / max(1, launches) * 1e-3
     achieved = bytes_alg / avg_kernel_s / 1e9
-    kernel_key = "k_sweep<double,6,3> hex64_s8"
-    traffic = _traffic(kernel_key, bytes_alg)
+    kernel_key = "k_sweep<double> hex64_s8"
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, sweep kernel {avg_kernel_s * 1e3:.3f} ms")
 
-    # one sweep on fixed inputs for the comparison with the oracle
-    psi_s = torch.zeros(nd * nc, dtype=torch.float64, device="cuda")
-    J.sweep(g, st, q, psi_s)
-    psi_sample = psi_s.view(nd, nc).cpu().numpy()
-
-    # time to rho <= 1e-8: plain FP64 vs FP32-refined
-    ttt = {}
-    phi64 = torch.zeros_like(phi)
-    for name, mode in (("fp64", J.JSWEEP_FP64), ("fp32_refined", J.JSWEEP_FP32_REFINED)):
-        out = torch.zeros_like(phi)
-        torch.cuda.synchronize()
-        a = time.perf_counter()
-        s = J.solve(g, st, ss, q, out, mode=mode, tol=1e-8, max_iter=5000)
-        torch.cuda.synchronize()
-        ttt[name] = {"seconds": time.perf_counter() - a, "sweeps": s["sweeps"], "outer": s["outer_iters"],
-                     "residual": s["residual"]}
-        if name == "fp64":
-            phi64 = out
-        else:
-            ttt[name]["phi_rel_err_vs_fp64"] = float(torch.linalg.norm(out - phi64) / torch.linalg.norm(phi64))
-    ttt["speedup_fp32_refined"] = ttt["fp64"]["seconds"] / ttt["fp32_refined"]["seconds"]
-
-    cpu, err = (None, None) if args.no_cpu else cpu_baseline(p, psi_sample)
+    avg32_s, ttt, cpu, err = None, None, None, None
+    if not args.steps_only:
+        avg32_s, ttt, cpu, err = extras(args, J, W, torch, g, p, st, ss, q, phi)
 
     line = {
         "metric": "cell-angle updates/s per sweep; time-to-1e-8 residual, FP32-refined vs FP64",
@@ -191,11 +244,13 @@ def main():
                    "cells": nc, "dirs": nd, "lagged_edges": info["n_lagged"], "max_levels": info["max_levels"],
                    "graph_build_s": t_build},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": _traffic(kernel_key),
                      "kernel": kernel_key, "algorithmic_bytes_per_launch": bytes_alg,
                      "interior_edges": edges, "avg_kernel_ms": avg_kernel_s * 1e3, "launches": launches},
         "cpu_baseline": cpu,
-        "sweep_updates_per_s_kernel": nc * nd / avg_kernel_s,
+        "sweep_kernel_ms": {"fp64": avg_kernel_s * 1e3, "fp32": avg32_s * 1e3 if avg32_s else None},
+        "sweep_updates_per_s_kernel": {"fp64": nc * nd / avg_kernel_s,
+                                       "fp32": nc * nd / avg32_s if avg32_s else None},
         "time_to_tol": ttt,
         "sweep_rel_err_vs_oracle": err,
     }

@@ -104,10 +104,16 @@ typedef struct jsweep_graph_s *jsweep_graph;   /* opaque, owned by the library *
  *   a level-ordered work list run as soon as their upwind vertices are done
  *   (completion flags between compute units).
  * DIRECTION: one workgroup per direction walks that direction's levels with
- *   a workgroup barrier between levels; directions run side by side. */
+ *   a workgroup barrier between levels; directions run side by side.
+ * DIRECTION_LDS: as DIRECTION, with the recent fluxes of the direction in an
+ *   LDS window and the per-vertex data streamed one level ahead; for graphs
+ *   whose consecutive levels hold at most 16384 (FP64) / 32768 (FP32)
+ *   vertices together and at most 2048 levels
+ *   (otherwise DIRECTION is used). */
 #define JSWEEP_STRATEGY_AUTO 0
 #define JSWEEP_STRATEGY_DATA_DRIVEN 1
 #define JSWEEP_STRATEGY_DIRECTION 2
+#define JSWEEP_STRATEGY_DIRECTION_LDS 3
 
 /* Launch tuning of the sweep kernels; 0 in a field = default or the value
  * chosen by jsweep_autotune. */

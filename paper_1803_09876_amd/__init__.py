@@ -33,6 +33,7 @@ JSWEEP_FP64 = 0
 JSWEEP_FP32_REFINED = 1
 JSWEEP_WARM_START = 0x100
 JSWEEP_STRATEGY_AUTO, JSWEEP_STRATEGY_DATA_DRIVEN, JSWEEP_STRATEGY_DIRECTION = 0, 1, 2
+JSWEEP_STRATEGY_DIRECTION_LDS = 3
 
 EXPORTED = [
     "jsweep_build_graph", "jsweep_graph_info", "jsweep_graph_export", "jsweep_graph_lagged", "jsweep_sweep",

@@ -1,9 +1,11 @@
 """Builds the HIP library libjsweep.so for gfx950 (hipcc).
 
 All device code is compiled without floating-point contraction (the graph
-construction must be bit-reproducible), with packed-FP32 instructions
-disabled, and without the compiler's wavefront-level atomic rewriting (it
-would wait for a prefetched work ticket right where it is requested)."""
+construction must be bit-reproducible) and with packed-FP32 instructions
+disabled.  The sweep kernels are built without the compiler's
+wavefront-level atomic rewriting (it would wait for a prefetched work
+ticket right where it is requested); the other files keep it, since it
+aggregates their same-address atomics."""
 from __future__ import annotations
 
 import os
@@ -22,14 +24,14 @@ ARCH = os.environ.get("JSWEEP_ARCH", "gfx950")
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     "-Wno-unused-command-line-argument", "-Wno-unused-result",
 ]
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    extra = ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"] if src == "sweep.hip" else []
+    cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)

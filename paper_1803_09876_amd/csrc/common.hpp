@@ -125,6 +125,9 @@ struct Graph {
     std::vector<int64_t> lvl_ptr_h;      // concatenated per-direction level pointers
     std::vector<int32_t> nlev_h;         // [nd]
     DevBuf lvl_ptr_d, lvl_off_d;         // device copies of the level pointers
+    std::vector<int32_t> lvl_chunk_h;    // first chunk of each (direction, level), indexed like lvl_ptr_h
+    DevBuf lvl_chunk_d;
+    int64_t max_w = 0, max_w2 = 0;       // widest level; widest pair of consecutive levels
     int max_levels = 0;
     DevBuf chunks;                       // [n_chunks] Chunk: per stream, ordered by (level, direction)
     DevBuf cblk;                         // [n_chunks * kBlock] int32 chunk blocks (see kBlock)
@@ -142,6 +145,7 @@ struct Graph {
     bool den64_ok = false, den32_ok = false;
     DevBuf vsrc;                         // [nc] V s (FP64) or {V, s} (FP32) of the running sweep
     DevBuf psi_pos;                      // [nd*nc] fluxes of the running sweep in level order
+    DevBuf vsp;                          // [64 n_chunks] V s (or {V, s}) in program order
     DevBuf posi;                         // [nd*nc] int32 level position of every vertex
     int epoch = 0;                       // last epoch used (1..255)
     DevBuf status;                       // [4] int32 device status words (watchdog)

@@ -689,12 +689,17 @@ static void dag_impl(Graph &g, bool lag_cycles, hipStream_t s) {
     std::vector<Chunk> ch;
     ch.reserve((size_t)(N / 64 + (int64_t)g.nd * g.max_levels));
     g.stream_off_h.assign(kStreams + 1, 0);
+    g.lvl_chunk_h.assign(g.lvl_ptr_h.size(), 0);
+    g.max_w = g.max_w2 = 0;
     for (int sidx = 0; sidx < kStreams; ++sidx) {
         g.stream_off_h[sidx] = (int64_t)ch.size();
         for (int L = 0; L < g.max_levels; ++L)
             for (int m = 0; m < g.nd; ++m) {
                 if (g.dir_stream_h[m] != sidx || L >= g.nlev_h[m]) continue;
                 const int64_t *p = g.lvl_ptr_h.data() + g.lvl_off_h[m];
+                g.lvl_chunk_h[g.lvl_off_h[m] + L] = (int32_t)ch.size();
+                g.max_w = std::max(g.max_w, p[L + 1] - p[L]);
+                g.max_w2 = std::max(g.max_w2, p[L + 1] - (L > 0 ? p[L - 1] : p[L]));
                 for (int64_t o = p[L]; o < p[L + 1]; o += 64) {
                     int64_t c = std::min<int64_t>(64, p[L + 1] - o);
                     ch.push_back(Chunk{(uint32_t)m | ((uint32_t)(c - 1) << 16), (uint32_t)o});
@@ -703,6 +708,9 @@ static void dag_impl(Graph &g, bool lag_cycles, hipStream_t s) {
     }
     g.stream_off_h[kStreams] = (int64_t)ch.size();
     g.n_chunks = (int64_t)ch.size();
+    if (g.n_chunks >= ((int64_t)1 << 31)) fail(JSWEEP_E_INVALID_ARG, "too many sweep chunks");
+    g.lvl_chunk_d.alloc(4 * g.lvl_chunk_h.size());
+    JSW_HIP(hipMemcpyAsync(g.lvl_chunk_d.p, g.lvl_chunk_h.data(), 4 * g.lvl_chunk_h.size(), hipMemcpyHostToDevice, s));
     g.chunks.alloc(sizeof(Chunk) * std::max<int64_t>(1, g.n_chunks));
     JSW_HIP(hipMemcpyAsync(g.chunks.p, ch.data(), sizeof(Chunk) * g.n_chunks, hipMemcpyHostToDevice, s));
     g.stream_off.alloc(8 * (kStreams + 1));

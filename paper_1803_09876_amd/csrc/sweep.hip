@@ -528,20 +528,293 @@ static void launch_dir(Graph &g, const Real *src_cell, const float *src_dir, Rea
     }
 }
 
-// Sweep strategy (unless requested or tuned): the data-driven persistent
-// kernel, which keeps many levels of every direction in flight; for small
-// graphs, where a sweep is a chain of short levels, the direction-parallel
-// kernel (no cross-CU hand-off per level).
+// ---------------------------------------------------------------------------
+// Direction-parallel sweep with an LDS window (graphs whose levels are
+// narrow): one 1024-lane workgroup per direction walks the levels in order,
+// reading the sweep program as coalesced streams one level ahead of the
+// compute.  The fluxes of the most recent kRing level positions live in an
+// LDS ring indexed by position; an upwind value further back (rare) is read
+// from the level-ordered copy in memory, which holds every level completed
+// two levels earlier (a level's stores are issued at the start of the next
+// level and complete at that level's barrier).  Every level therefore costs
+// a barrier and LDS traffic instead of cross-CU hand-offs.
+// Requirements (checked by the launcher): two consecutive levels fit in the
+// ring and the level table fits in LDS.
+// ---------------------------------------------------------------------------
+constexpr int kRingThreads = 1024;
+constexpr int kRingMaxLev = 2048;
+template <class Real>
+constexpr int ring_size() { return sizeof(Real) == 8 ? 16384 : 32768; }
+
+template <class Real>
+struct RingArgs {
+    const int64_t *lvl_ptr;                  // concatenated level pointers (positions)
+    const int64_t *lvl_off;                  // [nd + 1]
+    const int32_t *lvl_chunk;                // first chunk of each (direction, level)
+    const int32_t *lvl_cells;                // [nd*nc]
+    int64_t nc;
+    int64_t stride;                          // program slot stride
+    const int32_t *pcode;
+    const Real *pa;
+    const Real *pden;
+    const void *vsp;                         // [stride] V s (double) or {V, s} (float2)
+    const float *src_dir;                    // [nd*nc] by position, or null
+    Real *psi;                               // [nd*nc] by cell
+    Real *psi_pos;                           // [nd*nc] by position
+    const Real *lag_val;
+    Real psi_b;
+};
+
+template <class Real, int NS>
+struct RingItem {
+    Real den, vs, sv;
+    int32_t K;
+    int32_t code[NS];
+    Real af[NS];
+};
+
+// one pass: vertices [s0 + off, s0 + off + n) of a level whose first chunk
+// is c0; lane t takes vertices t, t + kRingThreads, ...
+template <class Real, int NS, int ITEMS>
+__device__ __forceinline__ void ring_load(const RingArgs<Real> &a, int64_t base, int64_t s0, int off, int n,
+                                          int64_t c0, RingItem<Real, NS> (&it)[ITEMS]) {
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const int i = off + (int)threadIdx.x + k * kRingThreads;
+        if (i < off + n) {
+            const int64_t idx = (c0 + (i >> 6)) * 64 + (i & 63);
+            it[k].den = a.pden[idx];
+            it[k].K = a.lvl_cells[base + s0 + i];
+#pragma unroll
+            for (int j = 0; j < NS; ++j) {
+                it[k].code[j] = a.pcode[j * a.stride + idx];
+                it[k].af[j] = a.pa[j * a.stride + idx];
+            }
+            if constexpr (sizeof(Real) == 8) {
+                it[k].vs = reinterpret_cast<const double *>(a.vsp)[idx];
+                it[k].sv = Real(0);
+            } else {
+                const float2 v = reinterpret_cast<const float2 *>(a.vsp)[idx];
+                it[k].vs = v.x;
+                it[k].sv = a.src_dir ? a.src_dir[base + s0 + i] + v.y : v.y;
+            }
+        }
+    }
+}
+
+// A level is processed in passes of at most kRingThreads * ITEMS vertices
+// (its vertices are independent); the next pass's data is loaded while the
+// current one computes.  After every pass: all loads and stores complete,
+// then a barrier.  A pass's fluxes are stored at the start of the next
+// pass, so values of levels two or more back are always readable from
+// memory; the ring holds the previous level and the current one.
+template <class Real, int NS, int ITEMS>
+__global__ void __launch_bounds__(kRingThreads) k_sweep_ring(RingArgs<Real> a) {
+    constexpr int R = ring_size<Real>();
+    constexpr int P = kRingThreads * ITEMS;
+    __shared__ Real ring[R];
+    __shared__ int32_t lp[kRingMaxLev + 1], lc[kRingMaxLev + 1];
+    const int m = blockIdx.x;
+    const int64_t base = (int64_t)m * a.nc;
+    const int64_t off0 = a.lvl_off[m];
+    const int nlev = (int)(a.lvl_off[m + 1] - off0 - 1);
+    for (int i = threadIdx.x; i <= nlev; i += kRingThreads) {
+        lp[i] = (int32_t)a.lvl_ptr[off0 + i];
+        lc[i] = i < nlev ? a.lvl_chunk[off0 + i] : 0;
+    }
+    __syncthreads();
+    if (nlev <= 0) return;
+    RingItem<Real, NS> cur[ITEMS], nxt[ITEMS];
+    Real prev_v[ITEMS];
+    int32_t prev_K[ITEMS];
+    int64_t prev_s = -1;      // first position of the stored-but-not-yet-written pass
+    int prev_n = 0;
+    // pass cursor: level L, vertices [off, off + n)
+    int L = 0, off = 0;
+    int n = min(P, lp[1] - lp[0]);
+    ring_load<Real, NS, ITEMS>(a, base, lp[0], 0, n, lc[0], cur);
+    while (true) {
+        const int64_t s0 = lp[L];
+        const int w = lp[L + 1] - lp[L];
+        // the previous pass's fluxes to memory
+        if (prev_s >= 0) {
+#pragma unroll
+            for (int k = 0; k < ITEMS; ++k) {
+                const int i = (int)threadIdx.x + k * kRingThreads;
+                if (i < prev_n) {
+                    a.psi_pos[base + prev_s + i] = prev_v[k];
+                    a.psi[base + prev_K[k]] = prev_v[k];
+                }
+            }
+        }
+        // the next pass
+        int nL = L, noff = off + n;
+        if (noff >= w) { nL = L + 1; noff = 0; }
+        int nn = 0;
+        if (nL < nlev) {
+            nn = min(P, lp[nL + 1] - lp[nL] - noff);
+            ring_load<Real, NS, ITEMS>(a, base, lp[nL], noff, nn, lc[nL], nxt);
+        }
+        // this pass: positions [e - R, s0) of the direction are in the ring
+        const int64_t lo = s0 + w - R;
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            const int i = off + (int)threadIdx.x + k * kRingThreads;
+            if (i < off + n) {
+                const RingItem<Real, NS> &it = cur[k];
+                Real num;
+                if constexpr (sizeof(Real) == 8) num = it.vs;
+                else num = it.vs * it.sv;
+#pragma unroll
+                for (int j = 0; j < NS; ++j) {
+                    const int32_t cd = it.code[j];
+                    if (cd == kNoFace) continue;
+                    Real v;
+                    if (cd >= 0) v = cd >= lo ? ring[cd & (R - 1)] : ld_coherent(a.psi_pos + base + cd);
+                    else if (cd == -1) v = a.psi_b;
+                    else v = a.lag_val[-(int64_t)cd - 2];
+                    num = num + it.af[j] * v;
+                }
+                const Real v = num / it.den;
+                ring[(s0 + i) & (R - 1)] = v;
+                prev_v[k] = v;
+                prev_K[k] = it.K;
+            }
+        }
+        prev_s = s0 + off;
+        prev_n = n;
+        // every load and store of this pass complete (the previous pass's
+        // fluxes are now readable from memory), then the ring
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (nL >= nlev) break;
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) cur[k] = nxt[k];
+        L = nL;
+        off = noff;
+        n = nn;
+    }
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const int i = (int)threadIdx.x + k * kRingThreads;
+        if (i < prev_n) {
+            a.psi_pos[base + prev_s + i] = prev_v[k];
+            a.psi[base + prev_K[k]] = prev_v[k];
+        }
+    }
+}
+
+// V s (or {V, s}) of every program slot's cell, for the ring kernel
+__global__ void k_vsp64(const int32_t *cblk, int64_t stride, const double *vol, const double *src, double *vsp) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= stride) return;
+    const int32_t K = cblk[(idx >> 6) * kBlock + (idx & 63)];
+    vsp[idx] = K < 0 ? 0.0 : (src ? vol[K] * src[K] : vol[K] * 0.0);
+}
+__global__ void k_vsp32(const int32_t *cblk, int64_t stride, const double *vol, const float *src, float2 *vsp) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= stride) return;
+    const int32_t K = cblk[(idx >> 6) * kBlock + (idx & 63)];
+    vsp[idx] = K < 0 ? make_float2(0.0f, 0.0f) : make_float2((float)vol[K], src ? src[K] : 0.0f);
+}
+
+// vertices per lane and pass for the ring kernel (0: not applicable to
+// this graph): two consecutive levels must fit in the ring and the level
+// table in LDS; two per lane unless the inflow slots need the registers
+static int ring_items(const Graph &g, bool f32) {
+    const int64_t R = f32 ? ring_size<float>() : ring_size<double>();
+    if (g.max_w2 > R || g.max_levels > kRingMaxLev || g.ns < 1 || g.ns > 6) return 0;
+    return (!f32 && g.ns >= 6) ? 1 : 2;
+}
+
+template <class Real, int NS>
+static const void *ring_kernel_ns(int items) {
+    if (items == 1) return reinterpret_cast<const void *>(&k_sweep_ring<Real, NS, 1>);
+    return reinterpret_cast<const void *>(&k_sweep_ring<Real, NS, 2>);
+}
+
+template <class Real>
+static const void *ring_kernel(int ns, int items) {
+    switch (ns) {
+    case 1: return ring_kernel_ns<Real, 1>(items);
+    case 2: return ring_kernel_ns<Real, 2>(items);
+    case 3: return ring_kernel_ns<Real, 3>(items);
+    case 4: return ring_kernel_ns<Real, 4>(items);
+    case 5: return ring_kernel_ns<Real, 5>(items);
+    default: return ring_kernel_ns<Real, 6>(items);
+    }
+}
+
+template <class Real>
+static void launch_ring(Graph &g, const Real *src_cell, const float *src_dir, Real *psi, Real psi_b, hipStream_t s) {
+    const bool f32 = sizeof(Real) == 4;
+    const int items = ring_items(g, f32);
+    if (!items) fail(JSWEEP_E_DEVICE, "ring sweep not applicable to this graph");
+    if (!(f32 ? g.den32_ok : g.den64_ok)) fail(JSWEEP_E_DEVICE, "sweep program denominators not built");
+    const int64_t S = 64 * g.n_chunks;
+    if (g.vsp.bytes < (size_t)(8 * S)) g.vsp.alloc(8 * S);
+    const unsigned gb = (unsigned)ceil_div(S, 256);
+    if (f32)
+        k_vsp32<<<gb, 256, 0, s>>>(g.cblk.as<int32_t>(), S, g.vol.as<double>(), reinterpret_cast<const float *>(src_cell),
+                                  g.vsp.as<float2>());
+    else
+        k_vsp64<<<gb, 256, 0, s>>>(g.cblk.as<int32_t>(), S, g.vol.as<double>(), reinterpret_cast<const double *>(src_cell),
+                                  g.vsp.as<double>());
+    JSW_HIP(hipGetLastError());
+    RingArgs<Real> a;
+    a.lvl_ptr = g.lvl_ptr_d.as<int64_t>();
+    a.lvl_off = g.lvl_off_d.as<int64_t>();
+    a.lvl_chunk = g.lvl_chunk_d.as<int32_t>();
+    a.lvl_cells = g.lvl_cells.as<int32_t>();
+    a.nc = g.nc;
+    a.stride = S;
+    a.pcode = g.pcode.as<int32_t>();
+    a.pa = reinterpret_cast<const Real *>(f32 ? g.pa32.p : g.pa64.p);
+    a.pden = reinterpret_cast<const Real *>(f32 ? g.pden32.p : g.pden64.p);
+    a.vsp = g.vsp.p;
+    a.src_dir = src_dir;
+    a.psi = psi;
+    if (g.psi_pos.bytes < (size_t)(8 * g.nc * g.nd)) g.psi_pos.alloc(8 * g.nc * g.nd);
+    a.psi_pos = g.psi_pos.as<Real>();
+    a.lag_val = reinterpret_cast<const Real *>(f32 ? g.lag_val32.p : g.lag_val64.p);
+    a.psi_b = psi_b;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (g.profile) {
+        JSW_HIP(hipEventCreate(&ev0));
+        JSW_HIP(hipEventCreate(&ev1));
+        JSW_HIP(hipEventRecord(ev0, s));
+    }
+    void *args[] = {&a};
+    JSW_HIP(hipLaunchKernel(ring_kernel<Real>(g.ns, items), dim3(g.nd), dim3(kRingThreads), args, 0, s));
+    if (g.profile) {
+        JSW_HIP(hipEventRecord(ev1, s));
+        g.prof_events.push_back({ev0, ev1});
+    }
+}
+
+// Sweep strategy (unless requested or tuned), from measurements:
+// - the LDS-window direction kernel when it applies and either every CU
+//   gets a direction (nd >= CUs) or the graph is small;
+// - the direction-parallel kernel for other small graphs (a sweep is a chain
+//   of short levels, and no level is handed between CUs);
+// - otherwise the data-driven persistent kernel, which keeps many levels of
+//   every direction in flight.
 int sweep_strategy(const Graph &g, const jsweep_params *p) {
     int st = (p && p->strategy > 0) ? p->strategy : (g.has_tuned && g.tuned.strategy > 0 ? g.tuned.strategy : 0);
     if (st == JSWEEP_STRATEGY_DATA_DRIVEN || st == JSWEEP_STRATEGY_DIRECTION) return st;
-    return g.nc * g.nd <= (int64_t)2000000 ? JSWEEP_STRATEGY_DIRECTION : JSWEEP_STRATEGY_DATA_DRIVEN;
+    if (st == JSWEEP_STRATEGY_DIRECTION_LDS) return ring_items(g, false) ? st : JSWEEP_STRATEGY_DIRECTION;
+    const bool small = g.nc * g.nd <= (int64_t)2000000;
+    if (ring_items(g, false) && (g.nd >= g.n_cu || small)) return JSWEEP_STRATEGY_DIRECTION_LDS;
+    return small ? JSWEEP_STRATEGY_DIRECTION : JSWEEP_STRATEGY_DATA_DRIVEN;
 }
 
 template <class Real, int NF, int DIM>
 static void launch_impl(Graph &g, const Real *src_cell, const float *src_dir, Real *psi, Real psi_b,
                         const jsweep_params *p, hipStream_t s) {
-    if (sweep_strategy(g, p) == JSWEEP_STRATEGY_DIRECTION) launch_dir<Real, NF, DIM>(g, src_cell, src_dir, psi, psi_b, p, s);
+    const int st = sweep_strategy(g, p);
+    if (st == JSWEEP_STRATEGY_DIRECTION_LDS && ring_items(g, sizeof(Real) == 4)) launch_ring<Real>(g, src_cell, src_dir, psi, psi_b, s);
+    else if (st == JSWEEP_STRATEGY_DIRECTION || st == JSWEEP_STRATEGY_DIRECTION_LDS)
+        launch_dir<Real, NF, DIM>(g, src_cell, src_dir, psi, psi_b, p, s);
     else launch_persistent<Real>(g, src_cell, src_dir, psi, psi_b, p, s);
 }
 

@@ -36,11 +36,14 @@ def test_hex64_s8_full(oracle_mod):
     print(f"[hex64] sweep rel {rel_max(got, ref):.2e} bitexact {np.array_equal(got, ref)}", flush=True)
     assert rel_max(got, ref) <= 1e-12
     psi_ref, phi_ref, _ = og.source_iteration(p.sigma_t, p.sigma_s, p.q, p.weight, 3)
-    phi = dev(np.zeros(p.n_cells))
-    J.solve(gg, dev(p.sigma_t), dev(p.sigma_s), dev(p.q), phi, psi, mode=J.JSWEEP_FP64, tol=0.0, max_iter=3,
-            allow_not_converged=True)
-    assert rel_max(phi.cpu().numpy(), phi_ref) <= 1e-12
-    assert rel_max(psi.cpu().numpy(), psi_ref) <= 1e-12
+    for strategy in (J.JSWEEP_STRATEGY_AUTO, J.JSWEEP_STRATEGY_DATA_DRIVEN, J.JSWEEP_STRATEGY_DIRECTION_LDS):
+        phi = dev(np.zeros(p.n_cells))
+        psi = dev(np.zeros((p.n_dirs, p.n_cells)))
+        J.solve(gg, dev(p.sigma_t), dev(p.sigma_s), dev(p.q), phi, psi, mode=J.JSWEEP_FP64, tol=0.0, max_iter=3,
+                params=J.Params(strategy=strategy), allow_not_converged=True)
+        e1, e2 = rel_max(phi.cpu().numpy(), phi_ref), rel_max(psi.cpu().numpy(), psi_ref)
+        print(f"[hex64] 3 SI strategy {strategy}: phi {e1:.2e} psi {e2:.2e}", flush=True)
+        assert e1 <= 1e-12 and e2 <= 1e-12
 
 
 @pytest.mark.parametrize("k,sample", [(3, [0, 17, 45, 79]), (5, [0, 100, 200, 287])])

@@ -77,7 +77,8 @@ def test_fp64_sweep_deterministic(cases):
     assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("strategy", [J.JSWEEP_STRATEGY_DATA_DRIVEN, J.JSWEEP_STRATEGY_DIRECTION])
+@pytest.mark.parametrize("strategy", [J.JSWEEP_STRATEGY_DATA_DRIVEN, J.JSWEEP_STRATEGY_DIRECTION,
+                                      J.JSWEEP_STRATEGY_DIRECTION_LDS])
 def test_fp64_source_iteration_20(cases, strategy):
     for name, p, og, gg in cases:
         psi_ref, phi_ref, hist = og.source_iteration(p.sigma_t, p.sigma_s, p.q, p.weight, 20)
@@ -92,7 +93,8 @@ def test_fp64_source_iteration_20(cases, strategy):
         assert abs(st["residual"] - hist[-1]) <= 1e-6 * hist[-1] + 1e-15
 
 
-@pytest.mark.parametrize("strategy", [J.JSWEEP_STRATEGY_DATA_DRIVEN, J.JSWEEP_STRATEGY_DIRECTION])
+@pytest.mark.parametrize("strategy", [J.JSWEEP_STRATEGY_DATA_DRIVEN, J.JSWEEP_STRATEGY_DIRECTION,
+                                      J.JSWEEP_STRATEGY_DIRECTION_LDS])
 def test_fp32_refined_converges_to_oracle(cases, strategy):
     for name, p, og, gg in cases:
         if p.n_cells * p.n_dirs > 2_000_000:
