@@ -143,9 +143,9 @@ struct Graph {
     DevBuf pden64, pden32;               // [S] double / float
     DevBuf sig_last;                     // [nc] sigma_t the denominators were built for
     bool den64_ok = false, den32_ok = false;
-    DevBuf vsrc;                         // [nc] V s (FP64) or {V, s} (FP32) of the running sweep
     DevBuf psi_pos;                      // [nd*nc] fluxes of the running sweep in level order
-    DevBuf vsp;                          // [64 n_chunks] V s (or {V, s}) in program order
+    DevBuf vsp;                          // [64 n_chunks] V s (or {V, s}) of the running sweep, program order
+    DevBuf vsc;                          // [nc] V s (or {V, s}) of the running sweep, per cell
     DevBuf posi;                         // [nd*nc] int32 level position of every vertex
     int epoch = 0;                       // last epoch used (1..255)
     DevBuf status;                       // [4] int32 device status words (watchdog)
@@ -156,6 +156,7 @@ struct Graph {
     DevBuf lag_mv;                       // [n_lag] uint64  m << 32 | v
     DevBuf lag_u;                        // [n_lag] int32
     DevBuf lag_val64, lag_val32;         // previous-iterate snapshots
+    DevBuf lag_a;                        // [n_lag] double |Omega . S| of the lagged face
     // scratch reused across solves
     DevBuf scratch_a, scratch_b, scratch_c, scratch_d;
     int grid_waves64 = 0, grid_waves32 = 0;   // persistent grid sizes

@@ -403,6 +403,14 @@ __global__ void k_program(const int32_t *blk, int64_t n_chunks, const CellRec<do
     }
 }
 
+// coefficient of every lagged edge, from the program slot that names it
+__global__ void k_lag_coef(const int32_t *code, const double *a, int64_t n, double *lag_a) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t cd = code[i];
+    if (cd <= -2 && cd != kNoFace) lag_a[-(int64_t)cd - 2] = a[i];
+}
+
 __global__ void k_positions(const int32_t *lvl_cells, int64_t nc, int64_t n, int32_t *posi) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -438,6 +446,12 @@ static void build_program(Graph &g, const LagView &lag, hipStream_t s) {
     JSW_HIP(hipGetLastError());
     g.pden64.alloc(8 * (size_t)S);
     g.den64_ok = g.den32_ok = false;
+    if (g.n_lag) {
+        g.lag_a.alloc(8 * g.n_lag);
+        k_lag_coef<<<(unsigned)ceil_div((int64_t)g.ns * S, 256), 256, 0, s>>>(g.pcode.as<int32_t>(), g.pa64.as<double>(),
+                                                                           (int64_t)g.ns * S, g.lag_a.as<double>());
+        JSW_HIP(hipGetLastError());
+    }
 }
 
 // one 64-lane workgroup per chunk: gather the upwind chunks of its

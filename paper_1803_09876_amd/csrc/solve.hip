@@ -198,6 +198,52 @@ __global__ void k_residual(const CellRec<double, NF, DIM> *rec, const double *om
     block_add(qq, acc + 1);
 }
 
+// Residual of a plain FP64 source iteration without re-applying the
+// operator.  The sweep solved, per vertex, den psi' - sum_in a psi'_up =
+// V (q + sigma_s phi) with lagged faces on the previous iterate, so the
+// un-lagged residual of psi' is exactly
+//   r = sigma_s (phi' - phi) + sum over lagged in-faces a (psi'_u - psi_u) / V.
+// k_phi_delta: phi' (ascending m), the isotropic part d = sigma_s (phi' -
+// phi) and its norm W V d^2 (W = sum of the weights), and V q^2.
+__global__ void k_phi_delta(const double *psi, const double *w, double wsum, const double *q, const double *sigma_s,
+                            const double *vol, int64_t nc, int nd, double *phi, double *dcell, double *acc) {
+    int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double a = 0.0, b = 0.0;
+    if (K < nc) {
+        double s = 0.0;
+        for (int m = 0; m < nd; ++m) s = s + w[m] * psi[(int64_t)m * nc + K];
+        const double d = sigma_s[K] * (s - phi[K]);
+        phi[K] = s;
+        dcell[K] = d;
+        a = wsum * (vol[K] * (d * d));
+        b = vol[K] * (q[K] * q[K]);
+    }
+    block_add(a, acc);
+    block_add(b, acc + 1);
+}
+
+// lagged corrections, one thread per (direction, downwind cell) group of
+// the (m, v, u)-sorted lagged edges: w_m V ((d + l)^2 - d^2); thread 0 also
+// copies the sweep status word next to the norms
+__global__ void k_lag_residual(const uint64_t *lag_mv, const int32_t *lag_u, const double *lag_a,
+                               const double *lag_old, int64_t n_lag, const double *psi, const double *w,
+                               const double *vol, const double *dcell, int64_t nc, const int32_t *status,
+                               double *acc) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e == 0) acc[2] = (double)status[0];
+    double c = 0.0;
+    if (e < n_lag && (e == 0 || lag_mv[e - 1] != lag_mv[e])) {
+        const uint64_t key = lag_mv[e];
+        const int64_t m = (int64_t)(key >> 32), v = (int64_t)(key & 0xffffffffu);
+        double l = 0.0;
+        for (int64_t f = e; f < n_lag && lag_mv[f] == key; ++f)
+            l = l + lag_a[f] * (psi[m * nc + lag_u[f]] - lag_old[f]) / vol[v];
+        const double d = dcell[v];
+        c = w[m] * (vol[v] * ((d + l) * (d + l) - d * d));
+    }
+    block_add(c, acc);
+}
+
 // delta-phi of a correction iterate (FP64 accumulation of FP32 fluxes), the
 // FP32 scattering source sigma_s dphi for the next inner sweep, and the
 // V-weighted norms of dphi and of its change
@@ -271,6 +317,11 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
     if (!refined) {
         // phi of the initial iterate
         scalar_flux(g, psi, phi, s);
+        ensure(g.scratch_d, 8 * g.nc + 64);
+        double *dcell = g.scratch_d.as<double>();
+        double wsum = 0.0;
+        for (double x : g.weight_h) wsum += x;
+        const int64_t nl = std::max<int64_t>(1, g.n_lag);
         while (true) {
             if (sweeps >= max_iter) { rc = JSWEEP_E_NOT_CONVERGED; break; }
             k_source<<<(int)ceil_div(g.nc, kB), kB, 0, s>>>(q, sigma_s, phi, g.nc, src);
@@ -278,11 +329,23 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
             lag_snapshot<double>(g, psi, s);
             launch_sweep64(g, src, psi, psi_b, params, s);
             ++sweeps;
-            rho = residual(g, psi, q, sigma_s, psi_b, phi, nullptr, acc, s);
+            // residual of the new iterate from the identity above (one
+            // pass over psi for phi, then the lagged edges)
+            JSW_HIP(hipMemsetAsync(acc, 0, 24, s));
+            k_phi_delta<<<(int)ceil_div(g.nc, kB), kB, 0, s>>>(psi, g.weight.as<double>(), wsum, q, sigma_s,
+                                                               g.vol.as<double>(), g.nc, g.nd, phi, dcell, acc);
+            JSW_HIP(hipGetLastError());
+            k_lag_residual<<<(int)ceil_div(nl, kB), kB, 0, s>>>(
+                g.lag_mv.as<uint64_t>(), g.lag_u.as<int32_t>(), g.lag_a.as<double>(), g.lag_val64.as<double>(),
+                g.n_lag, psi, g.weight.as<double>(), g.vol.as<double>(), dcell, g.nc, g.status.as<int32_t>(), acc);
+            JSW_HIP(hipGetLastError());
+            double h[3];
+            JSW_HIP(hipMemcpyAsync(h, acc, 24, hipMemcpyDeviceToHost, s));
+            JSW_HIP(hipStreamSynchronize(s));
+            if (h[2] != 0.0) return check_sweep_status(g, s);
+            rho = h[1] > 0.0 ? std::sqrt(std::max(h[0], 0.0)) / std::sqrt(h[1]) : std::sqrt(std::max(h[0], 0.0));
             ++outer;
             record(rho);
-            int st = check_sweep_status(g, s);
-            if (st) return st;
             if (rho <= tol) break;
         }
     } else {

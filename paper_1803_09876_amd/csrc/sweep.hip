@@ -15,8 +15,9 @@
 //
 // Data: a chunk's lanes read the sweep program (common.hpp) at c * 64 +
 // lane -- inflow-face codes and coefficients, denominator -- as coalesced
-// streams, so the only scattered accesses are the cell's V s (or V and s in
-// FP32) and the upwind fluxes; cell records are not read at all.
+// streams; the scattered accesses are the cell's V s (or V and s in FP32),
+// the upwind fluxes and the cell-order flux store.  Cell records are not
+// read at all.
 //
 // Execution: a persistent grid no larger than the device can hold at once.
 // A running wavefront takes the next chunks of its stream (workgroup id mod
@@ -58,7 +59,7 @@ struct SweepArgs {
     const int32_t *pcode;                    // [ns * stride]
     const Real *pa;                          // [ns * stride]
     const Real *pden;                        // [stride]
-    const void *vs;                          // [nc] V s (double) or {V, s} (float2)
+    const void *vs;                          // [nc] V s (double) or {V, s} (float2) per cell
     const float *src_dir;                    // [nd*nc] or null (FP32 path)
     Real *psi;                               // [nd*nc] by cell
     Real *psi_pos;                           // [nd*nc] by level position (upwind reads)
@@ -140,6 +141,7 @@ __global__ void k_sweep(SweepArgs<Real> a) {
         const int32_t w2 = lane < 32 ? blk[64 + lane] : -1;
         const int64_t idx = c * 64 + lane;
         const Real den = a.pden[idx];
+
         int32_t code[NS];
         Real af[NS];
 #pragma unroll
@@ -154,7 +156,7 @@ __global__ void k_sweep(SweepArgs<Real> a) {
         const bool active = item >= 0;
         const int64_t base = (int64_t)m * a.nc;
         const int64_t K = active ? (int64_t)item : 0;
-        // V s of the cell
+        // V s of the cell (one gather from a per-cell array)
         Real num = Real(0);
         if (active) {
             if constexpr (sizeof(Real) == 8) {
@@ -223,17 +225,6 @@ __global__ void k_sweep(SweepArgs<Real> a) {
             a.stamps[3 * c + 2] = (uint32_t)__builtin_amdgcn_s_memrealtime();
         }
     }
-}
-
-// V s per cell for the FP64 sweep (the same product the balance takes),
-// {V, s} for the FP32 sweep
-__global__ void k_vs64(const double *vol, const double *src, int64_t nc, double *vs) {
-    int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (K < nc) vs[K] = src ? vol[K] * src[K] : vol[K] * 0.0;
-}
-__global__ void k_vs32(const double *vol, const float *src, int64_t nc, float2 *vs) {
-    int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (K < nc) vs[K] = make_float2((float)vol[K], src ? src[K] : 0.0f);
 }
 
 // ---------------------------------------------------------------------------
@@ -422,6 +413,46 @@ int persistent_waves(Graph &g, bool fp32, const jsweep_params *p, int *waves_per
     return bpc * g.n_cu * wpb;
 }
 
+// V s (FP64: the same product the balance takes) or {V, s} (FP32) of every
+// program slot's cell: the sweeps read it as a coalesced stream
+__global__ void k_vsp64(const int32_t *cblk, int64_t stride, const double *vol, const double *src, double *vsp) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= stride) return;
+    const int32_t K = cblk[(idx >> 6) * kBlock + (idx & 63)];
+    vsp[idx] = K < 0 ? 0.0 : (src ? vol[K] * src[K] : vol[K] * 0.0);
+}
+__global__ void k_vsp32(const int32_t *cblk, int64_t stride, const double *vol, const float *src, float2 *vsp) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= stride) return;
+    const int32_t K = cblk[(idx >> 6) * kBlock + (idx & 63)];
+    vsp[idx] = K < 0 ? make_float2(0.0f, 0.0f) : make_float2((float)vol[K], src ? src[K] : 0.0f);
+}
+
+// V s per cell for the FP64 sweep (the same product the balance takes),
+// {V, s} for the FP32 sweep
+__global__ void k_vs64(const double *vol, const double *src, int64_t nc, double *vs) {
+    int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (K < nc) vs[K] = src ? vol[K] * src[K] : vol[K] * 0.0;
+}
+__global__ void k_vs32(const double *vol, const float *src, int64_t nc, float2 *vs) {
+    int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (K < nc) vs[K] = make_float2((float)vol[K], src ? src[K] : 0.0f);
+}
+
+template <class Real>
+static void program_vs(Graph &g, const Real *src_cell, hipStream_t s) {
+    const int64_t S = 64 * g.n_chunks;
+    if (g.vsp.bytes < (size_t)(8 * S)) g.vsp.alloc(8 * S);
+    const unsigned gb = (unsigned)ceil_div(S, 256);
+    if (sizeof(Real) == 4)
+        k_vsp32<<<gb, 256, 0, s>>>(g.cblk.as<int32_t>(), S, g.vol.as<double>(), reinterpret_cast<const float *>(src_cell),
+                                  g.vsp.as<float2>());
+    else
+        k_vsp64<<<gb, 256, 0, s>>>(g.cblk.as<int32_t>(), S, g.vol.as<double>(), reinterpret_cast<const double *>(src_cell),
+                                  g.vsp.as<double>());
+    JSW_HIP(hipGetLastError());
+}
+
 template <class Real>
 static void launch_persistent(Graph &g, const Real *src_cell, const float *src_dir, Real *psi, Real psi_b,
                               const jsweep_params *p, hipStream_t s) {
@@ -436,16 +467,16 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
     a.pcode = g.pcode.as<int32_t>();
     a.pa = reinterpret_cast<const Real *>(f32 ? g.pa32.p : g.pa64.p);
     a.pden = reinterpret_cast<const Real *>(f32 ? g.pden32.p : g.pden64.p);
-    if (g.vsrc.bytes < (size_t)(8 * g.nc)) g.vsrc.alloc(8 * g.nc);
+    if (g.vsc.bytes < (size_t)(8 * g.nc)) g.vsc.alloc(8 * g.nc);
     const int gb = (int)ceil_div(g.nc, 256);
     if (f32)
         k_vs32<<<gb, 256, 0, s>>>(g.vol.as<double>(), reinterpret_cast<const float *>(src_cell), g.nc,
-                                 g.vsrc.as<float2>());
+                                 g.vsc.as<float2>());
     else
         k_vs64<<<gb, 256, 0, s>>>(g.vol.as<double>(), reinterpret_cast<const double *>(src_cell), g.nc,
-                                 g.vsrc.as<double>());
+                                 g.vsc.as<double>());
     JSW_HIP(hipGetLastError());
-    a.vs = g.vsrc.p;
+    a.vs = g.vsc.p;
     a.src_dir = src_dir;
     a.psi = psi;
     if (g.psi_pos.bytes < (size_t)(8 * g.nc * g.nd)) g.psi_pos.alloc(8 * g.nc * g.nd);
@@ -704,20 +735,6 @@ __global__ void __launch_bounds__(kRingThreads) k_sweep_ring(RingArgs<Real> a) {
     }
 }
 
-// V s (or {V, s}) of every program slot's cell, for the ring kernel
-__global__ void k_vsp64(const int32_t *cblk, int64_t stride, const double *vol, const double *src, double *vsp) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= stride) return;
-    const int32_t K = cblk[(idx >> 6) * kBlock + (idx & 63)];
-    vsp[idx] = K < 0 ? 0.0 : (src ? vol[K] * src[K] : vol[K] * 0.0);
-}
-__global__ void k_vsp32(const int32_t *cblk, int64_t stride, const double *vol, const float *src, float2 *vsp) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= stride) return;
-    const int32_t K = cblk[(idx >> 6) * kBlock + (idx & 63)];
-    vsp[idx] = K < 0 ? make_float2(0.0f, 0.0f) : make_float2((float)vol[K], src ? src[K] : 0.0f);
-}
-
 // vertices per lane and pass for the ring kernel (0: not applicable to
 // this graph): two consecutive levels must fit in the ring and the level
 // table in LDS; two per lane unless the inflow slots need the registers
@@ -752,15 +769,7 @@ static void launch_ring(Graph &g, const Real *src_cell, const float *src_dir, Re
     if (!items) fail(JSWEEP_E_DEVICE, "ring sweep not applicable to this graph");
     if (!(f32 ? g.den32_ok : g.den64_ok)) fail(JSWEEP_E_DEVICE, "sweep program denominators not built");
     const int64_t S = 64 * g.n_chunks;
-    if (g.vsp.bytes < (size_t)(8 * S)) g.vsp.alloc(8 * S);
-    const unsigned gb = (unsigned)ceil_div(S, 256);
-    if (f32)
-        k_vsp32<<<gb, 256, 0, s>>>(g.cblk.as<int32_t>(), S, g.vol.as<double>(), reinterpret_cast<const float *>(src_cell),
-                                  g.vsp.as<float2>());
-    else
-        k_vsp64<<<gb, 256, 0, s>>>(g.cblk.as<int32_t>(), S, g.vol.as<double>(), reinterpret_cast<const double *>(src_cell),
-                                  g.vsp.as<double>());
-    JSW_HIP(hipGetLastError());
+    program_vs<Real>(g, src_cell, s);
     RingArgs<Real> a;
     a.lvl_ptr = g.lvl_ptr_d.as<int64_t>();
     a.lvl_off = g.lvl_off_d.as<int64_t>();
@@ -793,8 +802,9 @@ static void launch_ring(Graph &g, const Real *src_cell, const float *src_dir, Re
 }
 
 // Sweep strategy (unless requested or tuned), from measurements:
-// - the LDS-window direction kernel when it applies and either every CU
-//   gets a direction (nd >= CUs) or the graph is small;
+// - the LDS-window direction kernel for small graphs when it applies (its
+//   per-sweep expansion of V s into program order costs a gather per
+//   vertex, which only small graphs amortise);
 // - the direction-parallel kernel for other small graphs (a sweep is a chain
 //   of short levels, and no level is handed between CUs);
 // - otherwise the data-driven persistent kernel, which keeps many levels of
@@ -804,7 +814,7 @@ int sweep_strategy(const Graph &g, const jsweep_params *p) {
     if (st == JSWEEP_STRATEGY_DATA_DRIVEN || st == JSWEEP_STRATEGY_DIRECTION) return st;
     if (st == JSWEEP_STRATEGY_DIRECTION_LDS) return ring_items(g, false) ? st : JSWEEP_STRATEGY_DIRECTION;
     const bool small = g.nc * g.nd <= (int64_t)2000000;
-    if (ring_items(g, false) && (g.nd >= g.n_cu || small)) return JSWEEP_STRATEGY_DIRECTION_LDS;
+    if (ring_items(g, false) && small) return JSWEEP_STRATEGY_DIRECTION_LDS;
     return small ? JSWEEP_STRATEGY_DIRECTION : JSWEEP_STRATEGY_DATA_DRIVEN;
 }
 
