@@ -24,10 +24,15 @@ Also reported:
                 FP32-refined, on this workload and on the S16 tetrahedral one
                 (60^3 lattice, 6 tets per cube, 288 directions), with the
                 error of each result against the FP64 GPU fixed point (and the
-                sample sweep's error vs the oracle).
+                sample sweep's error vs the oracle);
+  ensemble      256 independent meshes (500-50,000 cells, half triangles,
+                half tets, S4-S8) solved together by jsweep_solve_batch (one
+                sweep launch for every instance and direction): FP64 step
+                throughput and time-to-1e-8, FP64 vs FP32-refined, with the
+                autotuned launch parameters.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-s16]
-                       [--copy-probe] [--steps-only]
+                       [--no-ensemble] [--copy-probe] [--steps-only]
   --copy-probe  first copies 512 MiB device to device (the calibration
                 dispatch for HBM byte counters taken on this run)
   --steps-only  only the timed steps and the roofline (for profiler runs)
@@ -125,6 +130,49 @@ def cpu_baseline(problem, psi_gpu_sample):
     }, err
 
 
+def ensemble_bench(J, W, torch, steps=5):
+    ps = W.ensemble(seed=4, count=256, min_cells=500, max_cells=50000)
+    gs = [J.build_graph(p.mesh, p.omega, p.weight) for p in ps]
+    upd = sum(p.n_cells * p.n_dirs for p in ps)
+    tuned = J.autotune(gs, mode=J.JSWEEP_FP32_REFINED)
+
+    def problems():
+        return [{"sigma_t": torch.tensor(p.sigma_t, device="cuda"), "sigma_s": torch.tensor(p.sigma_s, device="cuda"),
+                 "q": torch.tensor(p.q, device="cuda"), "phi": torch.zeros(p.n_cells, dtype=torch.float64, device="cuda")}
+                for p in ps]
+
+    out = {"instances": len(ps), "cells": sum(p.n_cells for p in ps), "cell_angle_updates_per_sweep": upd,
+           "autotuned": tuned.as_dict()}
+    pr = problems()
+    J.solve_batch(gs, pr, mode=J.JSWEEP_FP64, tol=0.0, max_iter=2, params=tuned, allow_not_converged=True)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    J.solve_batch(gs, pr, mode=J.JSWEEP_FP64, tol=0.0, max_iter=steps, params=tuned, allow_not_converged=True)
+    torch.cuda.synchronize()
+    step = (time.perf_counter() - a) / steps
+    out["fp64_step_ms"] = step * 1e3
+    out["fp64_updates_per_s"] = upd / step
+    ttt, ref = {}, None
+    for name, mode in (("fp64", J.JSWEEP_FP64), ("fp32_refined", J.JSWEEP_FP32_REFINED)):
+        pr = problems()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        st = J.solve_batch(gs, pr, mode=mode, tol=1e-8, max_iter=20000, params=tuned)
+        torch.cuda.synchronize()
+        ttt[name] = {"seconds": time.perf_counter() - a, "max_sweeps": max(x["sweeps"] for x in st),
+                     "max_residual": max(x["residual"] for x in st)}
+        phis = torch.cat([x["phi"] for x in pr])
+        if ref is None:
+            ref = phis
+        else:
+            ttt[name]["phi_rel_err_vs_fp64"] = float(torch.linalg.norm(phis - ref) / torch.linalg.norm(ref))
+    ttt["speedup_fp32_refined"] = ttt["fp64"]["seconds"] / ttt["fp32_refined"]["seconds"]
+    out["time_to_tol"] = ttt
+    for g in gs:
+        g.close()
+    return out
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -156,8 +204,12 @@ def extras(args, J, W, torch, g, p, st, ss, q, phi):
         ttt[p5.name] = time_to_tol(J, torch, g5, p5)
         g5.close()
         log(f"time to 1e-8 on {p5.name}: {json.dumps(ttt[p5.name])}")
+    ens = None
+    if not args.no_ensemble:
+        ens = ensemble_bench(J, W, torch)
+        log(f"ensemble: {json.dumps(ens)}")
     cpu, err = (None, None) if args.no_cpu else cpu_baseline(p, psi_sample)
-    return avg32_s, ttt, cpu, err
+    return avg32_s, ttt, ens, cpu, err
 
 
 def main():
@@ -167,6 +219,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-s16", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--steps-only", action="store_true")
     args = ap.parse_args()
@@ -222,9 +275,9 @@ def main():
     kernel_key = "k_sweep<double> hex64_s8"
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, sweep kernel {avg_kernel_s * 1e3:.3f} ms")
 
-    avg32_s, ttt, cpu, err = None, None, None, None
+    avg32_s, ttt, ens, cpu, err = None, None, None, None, None
     if not args.steps_only:
-        avg32_s, ttt, cpu, err = extras(args, J, W, torch, g, p, st, ss, q, phi)
+        avg32_s, ttt, ens, cpu, err = extras(args, J, W, torch, g, p, st, ss, q, phi)
 
     line = {
         "metric": "cell-angle updates/s per sweep; time-to-1e-8 residual, FP32-refined vs FP64",
@@ -252,6 +305,7 @@ def main():
         "sweep_updates_per_s_kernel": {"fp64": nc * nd / avg_kernel_s,
                                        "fp32": nc * nd / avg32_s if avg32_s else None},
         "time_to_tol": ttt,
+        "ensemble": ens,
         "sweep_rel_err_vs_oracle": err,
     }
     print(json.dumps(line))

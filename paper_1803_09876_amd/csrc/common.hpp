@@ -144,7 +144,7 @@ struct Graph {
     DevBuf sig_last;                     // [nc] sigma_t the denominators were built for
     bool den64_ok = false, den32_ok = false;
     DevBuf psi_pos;                      // [nd*nc] fluxes of the running sweep in level order
-    DevBuf vsp;                          // [64 n_chunks] V s (or {V, s}) of the running sweep, program order
+    DevBuf pvol64, pvol32;               // [64 n_chunks] cell volume in program order (ring sweep)
     DevBuf vsc;                          // [nc] V s (or {V, s}) of the running sweep, per cell
     DevBuf posi;                         // [nd*nc] int32 level position of every vertex
     int epoch = 0;                       // last epoch used (1..255)

@@ -248,8 +248,9 @@ __global__ void k_lag_residual(const uint64_t *lag_mv, const int32_t *lag_u, con
 // FP32 scattering source sigma_s dphi for the next inner sweep, and the
 // V-weighted norms of dphi and of its change
 __global__ void k_dphi(const float *dpsi, const double *w, const double *sigma_s, const double *vol, int64_t nc, int nd,
-                       double *dphi, float *g32, double *acc) {
+                       double *dphi, float *g32, const int32_t *status, double *acc) {
     int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (K == 0) acc[2] = (double)status[0];
     double a = 0.0, b = 0.0;
     if (K < nc) {
         double s = 0.0;
@@ -367,7 +368,10 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
             JSW_HIP(hipMemsetAsync(dpsi, 0, 4 * N, s));
             JSW_HIP(hipMemsetAsync(dphi, 0, 8 * g.nc, s));
             JSW_HIP(hipMemsetAsync(g32, 0, 4 * g.nc, s));
-            const double eta = std::max(3e-7, 0.3 * tol / rho);
+            // inner target: what the next outer residual needs (the outer
+            // loop re-checks the true residual, so landing short costs one
+            // more outer iteration), but no finer than FP32 sweeps resolve
+            const double eta = std::max(3e-7, tol / rho);
             double prev_change = -1.0;
             for (int j = 0; j < J && sweeps < max_iter; ++j) {
                 lag_snapshot<float>(g, dpsi, s);
@@ -375,13 +379,12 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
                 ++sweeps;
                 JSW_HIP(hipMemsetAsync(acc + 2, 0, 16, s));
                 k_dphi<<<(int)ceil_div(g.nc, kB), kB, 0, s>>>(dpsi, g.weight.as<double>(), sigma_s, g.vol.as<double>(),
-                                                           g.nc, g.nd, dphi, g32, acc + 2);
+                                                           g.nc, g.nd, dphi, g32, g.status.as<int32_t>(), acc + 2);
                 JSW_HIP(hipGetLastError());
-                double h[2];
-                JSW_HIP(hipMemcpyAsync(h, acc + 2, 16, hipMemcpyDeviceToHost, s));
+                double h[3];   // norms of dphi and of its change, sweep status
+                JSW_HIP(hipMemcpyAsync(h, acc + 2, 24, hipMemcpyDeviceToHost, s));
                 JSW_HIP(hipStreamSynchronize(s));
-                int st = check_sweep_status(g, s);
-                if (st) return st;
+                if (h[2] != 0.0) return check_sweep_status(g, s);
                 double norm = std::sqrt(h[0]), change = std::sqrt(h[1]);
                 // estimated remaining error of the inner iteration from the
                 // observed contraction of successive changes

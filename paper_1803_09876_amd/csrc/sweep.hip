@@ -413,19 +413,14 @@ int persistent_waves(Graph &g, bool fp32, const jsweep_params *p, int *waves_per
     return bpc * g.n_cu * wpb;
 }
 
-// V s (FP64: the same product the balance takes) or {V, s} (FP32) of every
-// program slot's cell: the sweeps read it as a coalesced stream
-__global__ void k_vsp64(const int32_t *cblk, int64_t stride, const double *vol, const double *src, double *vsp) {
+// cell volume of every program slot (0 past a chunk's end), FP64 or rounded
+// to FP32 as in the FP32 sweep
+template <class Real>
+__global__ void k_pvol(const int32_t *cblk, int64_t stride, const double *vol, Real *pvol) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= stride) return;
     const int32_t K = cblk[(idx >> 6) * kBlock + (idx & 63)];
-    vsp[idx] = K < 0 ? 0.0 : (src ? vol[K] * src[K] : vol[K] * 0.0);
-}
-__global__ void k_vsp32(const int32_t *cblk, int64_t stride, const double *vol, const float *src, float2 *vsp) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= stride) return;
-    const int32_t K = cblk[(idx >> 6) * kBlock + (idx & 63)];
-    vsp[idx] = K < 0 ? make_float2(0.0f, 0.0f) : make_float2((float)vol[K], src ? src[K] : 0.0f);
+    pvol[idx] = K < 0 ? Real(0) : (Real)vol[K];
 }
 
 // V s per cell for the FP64 sweep (the same product the balance takes),
@@ -437,20 +432,6 @@ __global__ void k_vs64(const double *vol, const double *src, int64_t nc, double 
 __global__ void k_vs32(const double *vol, const float *src, int64_t nc, float2 *vs) {
     int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (K < nc) vs[K] = make_float2((float)vol[K], src ? src[K] : 0.0f);
-}
-
-template <class Real>
-static void program_vs(Graph &g, const Real *src_cell, hipStream_t s) {
-    const int64_t S = 64 * g.n_chunks;
-    if (g.vsp.bytes < (size_t)(8 * S)) g.vsp.alloc(8 * S);
-    const unsigned gb = (unsigned)ceil_div(S, 256);
-    if (sizeof(Real) == 4)
-        k_vsp32<<<gb, 256, 0, s>>>(g.cblk.as<int32_t>(), S, g.vol.as<double>(), reinterpret_cast<const float *>(src_cell),
-                                  g.vsp.as<float2>());
-    else
-        k_vsp64<<<gb, 256, 0, s>>>(g.cblk.as<int32_t>(), S, g.vol.as<double>(), reinterpret_cast<const double *>(src_cell),
-                                  g.vsp.as<double>());
-    JSW_HIP(hipGetLastError());
 }
 
 template <class Real>
@@ -588,7 +569,8 @@ struct RingArgs {
     const int32_t *pcode;
     const Real *pa;
     const Real *pden;
-    const void *vsp;                         // [stride] V s (double) or {V, s} (float2)
+    const Real *pvol;                        // [stride] cell volume, program order
+    const Real *src_cell;                    // [nc] isotropic source, or null
     const float *src_dir;                    // [nd*nc] by position, or null
     Real *psi;                               // [nd*nc] by cell
     Real *psi_pos;                           // [nd*nc] by position
@@ -598,7 +580,7 @@ struct RingArgs {
 
 template <class Real, int NS>
 struct RingItem {
-    Real den, vs, sv;
+    Real den, V, sd;                         // sd: per-direction source part (FP32 path)
     int32_t K;
     int32_t code[NS];
     Real af[NS];
@@ -621,13 +603,10 @@ __device__ __forceinline__ void ring_load(const RingArgs<Real> &a, int64_t base,
                 it[k].code[j] = a.pcode[j * a.stride + idx];
                 it[k].af[j] = a.pa[j * a.stride + idx];
             }
-            if constexpr (sizeof(Real) == 8) {
-                it[k].vs = reinterpret_cast<const double *>(a.vsp)[idx];
-                it[k].sv = Real(0);
-            } else {
-                const float2 v = reinterpret_cast<const float2 *>(a.vsp)[idx];
-                it[k].vs = v.x;
-                it[k].sv = a.src_dir ? a.src_dir[base + s0 + i] + v.y : v.y;
+            it[k].V = a.pvol[idx];
+            it[k].sd = Real(0);
+            if constexpr (sizeof(Real) == 4) {
+                if (a.src_dir) it[k].sd = a.src_dir[base + s0 + i];
             }
         }
     }
@@ -667,6 +646,14 @@ __global__ void __launch_bounds__(kRingThreads) k_sweep_ring(RingArgs<Real> a) {
     while (true) {
         const int64_t s0 = lp[L];
         const int w = lp[L + 1] - lp[L];
+        // this pass's isotropic source: a gather from a per-cell array,
+        // issued first so that it returns ahead of the next pass's loads
+        Real sc[ITEMS];
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            const int i = off + (int)threadIdx.x + k * kRingThreads;
+            sc[k] = (a.src_cell && i < off + n) ? a.src_cell[cur[k].K] : Real(0);
+        }
         // the previous pass's fluxes to memory
         if (prev_s >= 0) {
 #pragma unroll
@@ -693,9 +680,10 @@ __global__ void __launch_bounds__(kRingThreads) k_sweep_ring(RingArgs<Real> a) {
             const int i = off + (int)threadIdx.x + k * kRingThreads;
             if (i < off + n) {
                 const RingItem<Real, NS> &it = cur[k];
+                // V s, evaluated as in the other sweep kernels
                 Real num;
-                if constexpr (sizeof(Real) == 8) num = it.vs;
-                else num = it.vs * it.sv;
+                if constexpr (sizeof(Real) == 8) num = it.V * sc[k];
+                else num = it.V * (a.src_dir ? it.sd + sc[k] : sc[k]);
 #pragma unroll
                 for (int j = 0; j < NS; ++j) {
                     const int32_t cd = it.code[j];
@@ -769,7 +757,12 @@ static void launch_ring(Graph &g, const Real *src_cell, const float *src_dir, Re
     if (!items) fail(JSWEEP_E_DEVICE, "ring sweep not applicable to this graph");
     if (!(f32 ? g.den32_ok : g.den64_ok)) fail(JSWEEP_E_DEVICE, "sweep program denominators not built");
     const int64_t S = 64 * g.n_chunks;
-    program_vs<Real>(g, src_cell, s);
+    DevBuf &pv = f32 ? g.pvol32 : g.pvol64;
+    if (!pv.p) {
+        pv.alloc((f32 ? 4 : 8) * (size_t)S);
+        k_pvol<Real><<<(unsigned)ceil_div(S, 256), 256, 0, s>>>(g.cblk.as<int32_t>(), S, g.vol.as<double>(), pv.as<Real>());
+        JSW_HIP(hipGetLastError());
+    }
     RingArgs<Real> a;
     a.lvl_ptr = g.lvl_ptr_d.as<int64_t>();
     a.lvl_off = g.lvl_off_d.as<int64_t>();
@@ -780,7 +773,8 @@ static void launch_ring(Graph &g, const Real *src_cell, const float *src_dir, Re
     a.pcode = g.pcode.as<int32_t>();
     a.pa = reinterpret_cast<const Real *>(f32 ? g.pa32.p : g.pa64.p);
     a.pden = reinterpret_cast<const Real *>(f32 ? g.pden32.p : g.pden64.p);
-    a.vsp = g.vsp.p;
+    a.pvol = pv.as<Real>();
+    a.src_cell = src_cell;
     a.src_dir = src_dir;
     a.psi = psi;
     if (g.psi_pos.bytes < (size_t)(8 * g.nc * g.nd)) g.psi_pos.alloc(8 * g.nc * g.nd);

@@ -54,10 +54,12 @@ def test_autotune_and_tuned_solve(ensemble):
     p, og, g = ensemble[1]
     prm = J.autotune([g], J.JSWEEP_FP64)
     d = prm.as_dict()
-    assert d["strategy"] in (1, 2) and d["waves_per_block"] >= 1
+    assert d["strategy"] in (J.JSWEEP_STRATEGY_DATA_DRIVEN, J.JSWEEP_STRATEGY_DIRECTION,
+                             J.JSWEEP_STRATEGY_DIRECTION_LDS)
+    assert d["strategy"] == J.JSWEEP_STRATEGY_DIRECTION_LDS or d["waves_per_block"] >= 1
     phi = dev(np.zeros(p.n_cells))
     J.solve(g, dev(p.sigma_t), dev(p.sigma_s), dev(p.q), phi, mode=J.JSWEEP_FP64, tol=0.0, max_iter=5,
-            allow_not_converged=True)
+            params=prm, allow_not_converged=True)
     _, phi_ref, _ = og.source_iteration(p.sigma_t, p.sigma_s, p.q, p.weight, 5)
     assert rel_max(host(phi), phi_ref) <= 1e-12
     prm_b = J.autotune([g for _, _, g in ensemble], J.JSWEEP_FP32_REFINED)
