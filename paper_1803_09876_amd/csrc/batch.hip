@@ -365,7 +365,7 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
                     double ratio = prev_change[i] > 0.0 ? std::min(change / prev_change[i], 0.999) : 0.999;
                     ratio = std::pow(ratio, 1.0 / kInnerBlock);
                     prev_change[i] = change;
-                    const double eta = std::max(3e-7, 0.3 * tol / rho[i]);
+                    const double eta = std::max(3e-7, tol / rho[i]);   // as in the single-graph solve
                     if (norm == 0.0 || (j > 0 && change * ratio / (1.0 - ratio) <= eta * norm)) inner_active[i] = 0;
                     else more = true;
                 }
