@@ -26,6 +26,8 @@ namespace jsw {
 
 constexpr int kB = 256;
 constexpr int kInnerBlock = 4;   // inner sweeps per graph replay
+// outer residual reduction an FP32 correction solve reliably achieves
+constexpr double kFp32Floor = 4e-6;
 
 struct BInst {
     const void *rec64;
@@ -145,7 +147,8 @@ __global__ void k_b_residual(const BInst *I, const int64_t *coff, int n, int64_t
 }
 
 // correction flux dphi (FP64 sum of FP32 fluxes), FP32 scattering source,
-// acc[4 i + 2] += ||dphi||^2, acc[4 i + 3] += ||dphi - dphi_prev||^2
+// acc[4 i + 2] += ||dphi||^2, acc[4 i + 3] += ||sigma_s (dphi - dphi_prev)||^2
+// (the correction equation's residual, as in the single-graph solve)
 __global__ void k_b_dphi(const BInst *I, const int64_t *coff, int n, int64_t total, const int32_t *active, double *acc) {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= total) return;
@@ -159,7 +162,8 @@ __global__ void k_b_dphi(const BInst *I, const int64_t *coff, int n, int64_t tot
     b.dphi[K] = s;
     b.g32[K] = (float)(b.sigma_s[K] * s);
     atomicAdd(acc + 4 * i + 2, b.vol[K] * (s * s));
-    atomicAdd(acc + 4 * i + 3, b.vol[K] * ((s - old) * (s - old)));
+    const double d = b.sigma_s[K] * (s - old);
+    atomicAdd(acc + 4 * i + 3, b.vol[K] * (d * d));
 }
 
 __global__ void k_b_update(const BInst *I, const int64_t *aoff, int n, int64_t total, const int32_t *active) {
@@ -266,7 +270,9 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
     JSW_HIP(hipGetLastError());
 
     std::vector<int32_t> outer(n, 0), sweeps(n, 0), hist(n, 0);
-    std::vector<double> rho(n, INFINITY), acc(4 * n);
+    std::vector<double> rho(n, INFINITY), acc(4 * n), qnorm(n, 1.0), wsum(n, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (double x : graphs[i]->weight_h) wsum[i] += x;
     auto record = [&](int i, double v) {
         if (stats && stats[i].residual_history && hist[i] < stats[i].history_capacity) stats[i].residual_history[hist[i]] = v;
         ++hist[i];
@@ -280,6 +286,7 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
         JSW_HIP(hipStreamSynchronize(s));
         for (int i = 0; i < n; ++i) {
             if (!active[i]) continue;
+            qnorm[i] = acc[4 * i + 1] > 0.0 ? std::sqrt(acc[4 * i + 1]) : 1.0;
             rho[i] = acc[4 * i + 1] > 0.0 ? std::sqrt(acc[4 * i]) / std::sqrt(acc[4 * i + 1]) : std::sqrt(acc[4 * i]);
             ++outer[i];
             record(i, rho[i]);
@@ -334,7 +341,7 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
             hipGraph_t g; hipGraphExec_t e;
             ~GraphGuard() { if (e) (void)hipGraphExecDestroy(e); if (g) (void)hipGraphDestroy(g); }
         } guard{graph, exec};
-        std::vector<double> prev_change(n, -1.0);
+        std::vector<double> prev_pred(n, INFINITY), target(n, 0.0);
         while (true) {
             residuals();
             for (int i = 0; i < n; ++i)
@@ -348,7 +355,13 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
             k_b_zero<<<grid_for(A), kB, 0, s>>>(I, d_aoff.as<int64_t>(), n, A, d_active.as<int32_t>(), 1);
             JSW_HIP(hipGetLastError());
             inner_active = active;
-            std::fill(prev_change.begin(), prev_change.end(), -1.0);
+            // inner stop as in the single-graph solve: the predicted outer
+            // residual below half the tolerance, below the FP32 floor of the
+            // current residual, or no longer improving close to that floor
+            for (int i = 0; i < n; ++i) {
+                prev_pred[i] = INFINITY;
+                target[i] = std::max(0.5 * tol, kFp32Floor * rho[i]);
+            }
             for (int j = 0; j < J && total_sweeps < max_iter; j += kInnerBlock) {
                 JSW_HIP(hipMemcpyAsync(d_inner.p, inner_active.data(), 4 * n, hipMemcpyHostToDevice, s));
                 JSW_HIP(hipGraphLaunch(exec, s));
@@ -359,15 +372,13 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
                 for (int i = 0; i < n; ++i) {
                     if (!inner_active[i]) continue;
                     sweeps[i] += kInnerBlock;
-                    // norms of the block's last pass; successive blocks are
-                    // kInnerBlock passes apart
-                    double norm = std::sqrt(acc[4 * i + 2]), change = std::sqrt(acc[4 * i + 3]);
-                    double ratio = prev_change[i] > 0.0 ? std::min(change / prev_change[i], 0.999) : 0.999;
-                    ratio = std::pow(ratio, 1.0 / kInnerBlock);
-                    prev_change[i] = change;
-                    const double eta = std::max(3e-7, tol / rho[i]);   // as in the single-graph solve
-                    if (norm == 0.0 || (j > 0 && change * ratio / (1.0 - ratio) <= eta * norm)) inner_active[i] = 0;
+                    // norms of the block's last pass
+                    const double norm = acc[4 * i + 2];
+                    const double pred = std::sqrt(wsum[i] * acc[4 * i + 3]) / qnorm[i];
+                    const bool stalled = j > 0 && pred > 0.9 * prev_pred[i] && pred < 100.0 * kFp32Floor * rho[i];
+                    if (norm == 0.0 || pred <= target[i] || stalled) inner_active[i] = 0;
                     else more = true;
+                    prev_pred[i] = pred;
                 }
                 if (!more) break;
             }

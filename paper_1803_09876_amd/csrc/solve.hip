@@ -14,6 +14,9 @@
 namespace jsw {
 
 constexpr int kB = 256;
+// outer residual reduction an FP32 correction solve reliably achieves
+// (measured: 3e-6 to 1e-5 of the residual it corrects)
+constexpr double kFp32Floor = 4e-6;
 
 // sigma_t * V into the sweep records (FP64 product; FP32 records take it
 // rounded)
@@ -245,8 +248,11 @@ __global__ void k_lag_residual(const uint64_t *lag_mv, const int32_t *lag_u, con
 }
 
 // delta-phi of a correction iterate (FP64 accumulation of FP32 fluxes), the
-// FP32 scattering source sigma_s dphi for the next inner sweep, and the
-// V-weighted norms of dphi and of its change
+// FP32 scattering source sigma_s dphi for the next inner sweep, the
+// V-weighted norm of dphi and that of sigma_s (dphi - dphi_prev): by the
+// sweep identity the latter is the isotropic part of the correction
+// equation's residual, i.e. of the outer residual once the correction is
+// applied
 __global__ void k_dphi(const float *dpsi, const double *w, const double *sigma_s, const double *vol, int64_t nc, int nd,
                        double *dphi, float *g32, const int32_t *status, double *acc) {
     int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -259,7 +265,8 @@ __global__ void k_dphi(const float *dpsi, const double *w, const double *sigma_s
         dphi[K] = s;
         g32[K] = (float)(sigma_s[K] * s);
         a = vol[K] * (s * s);
-        b = vol[K] * ((s - old) * (s - old));
+        const double d = sigma_s[K] * (s - old);
+        b = vol[K] * (d * d);
     }
     block_add(a, acc);
     block_add(b, acc + 1);
@@ -272,7 +279,7 @@ __global__ void k_update(double *psi, const float *dpsi, int64_t n) {
 }
 
 static double residual(Graph &g, const double *psi, const double *q, const double *sigma_s, double psi_b, double *phi,
-                       float *r32, double *acc, hipStream_t s) {
+                       float *r32, double *acc, hipStream_t s, double *qq = nullptr) {
     JSW_HIP(hipMemsetAsync(acc, 0, 16, s));
     int gb = (int)ceil_div(g.nc, kB);
     const double *om = g.omega64.as<double>(), *w = g.weight.as<double>();
@@ -286,6 +293,7 @@ static double residual(Graph &g, const double *psi, const double *q, const doubl
     double h[2];
     JSW_HIP(hipMemcpyAsync(h, acc, 16, hipMemcpyDeviceToHost, s));
     JSW_HIP(hipStreamSynchronize(s));
+    if (qq) *qq = h[1];
     return h[1] > 0.0 ? std::sqrt(h[0]) / std::sqrt(h[1]) : std::sqrt(h[0]);
 }
 
@@ -358,8 +366,12 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
         float *g32 = reinterpret_cast<float *>(dphi + g.nc);
         int J = (params && params->inner_sweeps > 0) ? params->inner_sweeps
                 : (g.has_tuned && g.tuned.inner_sweeps > 0 ? g.tuned.inner_sweeps : 400);
+        double wsum = 0.0;
+        for (double x : g.weight_h) wsum += x;
         while (true) {
-            rho = residual(g, psi, q, sigma_s, psi_b, phi, r32, acc, s);
+            double qq = 0.0;
+            rho = residual(g, psi, q, sigma_s, psi_b, phi, r32, acc, s, &qq);
+            const double qn = qq > 0.0 ? std::sqrt(qq) : 1.0;
             ++outer;
             record(rho);
             if (rho <= tol) break;
@@ -368,11 +380,15 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
             JSW_HIP(hipMemsetAsync(dpsi, 0, 4 * N, s));
             JSW_HIP(hipMemsetAsync(dphi, 0, 8 * g.nc, s));
             JSW_HIP(hipMemsetAsync(g32, 0, 4 * g.nc, s));
-            // inner target: what the next outer residual needs (the outer
-            // loop re-checks the true residual, so landing short costs one
-            // more outer iteration), but no finer than FP32 sweeps resolve
-            const double eta = std::max(3e-7, tol / rho);
-            double prev_change = -1.0;
+            // Inner stop: the outer residual the correction leaves behind is
+            // predicted after every inner sweep from the correction
+            // equation's residual (isotropic part; lagged faces left out)
+            // and the inner loop stops once it is below half the tolerance,
+            // or below what FP32 corrections resolve (a few 1e-6 of the
+            // current residual), or stops improving close to that floor.
+            // The outer loop then measures the true residual.
+            const double target = std::max(0.5 * tol, kFp32Floor * rho);
+            double prev_pred = INFINITY;
             for (int j = 0; j < J && sweeps < max_iter; ++j) {
                 lag_snapshot<float>(g, dpsi, s);
                 launch_sweep32(g, r32, g32, dpsi, params, s);
@@ -381,17 +397,16 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
                 k_dphi<<<(int)ceil_div(g.nc, kB), kB, 0, s>>>(dpsi, g.weight.as<double>(), sigma_s, g.vol.as<double>(),
                                                            g.nc, g.nd, dphi, g32, g.status.as<int32_t>(), acc + 2);
                 JSW_HIP(hipGetLastError());
-                double h[3];   // norms of dphi and of its change, sweep status
+                double h[3];   // norm of dphi, correction residual, sweep status
                 JSW_HIP(hipMemcpyAsync(h, acc + 2, 24, hipMemcpyDeviceToHost, s));
                 JSW_HIP(hipStreamSynchronize(s));
                 if (h[2] != 0.0) return check_sweep_status(g, s);
-                double norm = std::sqrt(h[0]), change = std::sqrt(h[1]);
-                // estimated remaining error of the inner iteration from the
-                // observed contraction of successive changes
-                double ratio = prev_change > 0.0 ? std::min(change / prev_change, 0.999) : 0.999;
-                prev_change = change;
-                if (j > 0 && change * ratio / (1.0 - ratio) <= eta * norm) break;
-                if (norm == 0.0) break;
+                const double pred = std::sqrt(wsum * h[1]) / qn;
+                if (h[0] == 0.0 || pred <= target) break;
+                // stalled near the FP32 floor (slow contraction far above it
+                // is ordinary source iteration and continues)
+                if (j > 0 && pred > 0.9 * prev_pred && pred < 100.0 * kFp32Floor * rho) break;
+                prev_pred = pred;
             }
             k_update<<<(int)ceil_div(N, kB), kB, 0, s>>>(psi, dpsi, N);
             JSW_HIP(hipGetLastError());
