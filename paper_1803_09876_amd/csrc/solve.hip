@@ -247,6 +247,14 @@ __global__ void k_lag_residual(const uint64_t *lag_mv, const int32_t *lag_u, con
     block_add(c, acc);
 }
 
+// ||q||^2 = sum_K V_K q_K^2
+__global__ void k_qnorm(const double *q, const double *vol, int64_t nc, double *acc) {
+    int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double a = 0.0;
+    if (K < nc) a = vol[K] * (q[K] * q[K]);
+    block_add(a, acc);
+}
+
 // delta-phi of a correction iterate (FP64 accumulation of FP32 fluxes), the
 // FP32 scattering source sigma_s dphi for the next inner sweep, the
 // V-weighted norm of dphi and that of sigma_s (dphi - dphi_prev): by the
@@ -254,7 +262,7 @@ __global__ void k_lag_residual(const uint64_t *lag_mv, const int32_t *lag_u, con
 // equation's residual, i.e. of the outer residual once the correction is
 // applied
 __global__ void k_dphi(const float *dpsi, const double *w, const double *sigma_s, const double *vol, int64_t nc, int nd,
-                       double *dphi, float *g32, const int32_t *status, double *acc) {
+                       const double *q, double *dphi, float *g32, const int32_t *status, double *acc) {
     int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (K == 0) acc[2] = (double)status[0];
     double a = 0.0, b = 0.0;
@@ -263,7 +271,7 @@ __global__ void k_dphi(const float *dpsi, const double *w, const double *sigma_s
         for (int m = 0; m < nd; ++m) s = s + w[m] * (double)dpsi[(int64_t)m * nc + K];
         double old = dphi[K];
         dphi[K] = s;
-        g32[K] = (float)(sigma_s[K] * s);
+        g32[K] = q ? (float)(q[K] + sigma_s[K] * s) : (float)(sigma_s[K] * s);
         a = vol[K] * (s * s);
         const double d = sigma_s[K] * (s - old);
         b = vol[K] * (d * d);
@@ -315,7 +323,8 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
     double *src = g.scratch_b.as<double>();
     double *acc = src + g.nc + 2;   // 16-byte aligned tail, 4 doubles
     if (((uintptr_t)acc & 15) != 0) acc += 1;
-    if (!warm || !psi_out) JSW_HIP(hipMemsetAsync(psi, 0, 8 * N, s));
+    const bool zero_start = !warm || !psi_out;
+    if (zero_start) JSW_HIP(hipMemsetAsync(psi, 0, 8 * N, s));
     refresh_sigma(g, sigma_t, refined, s);
     int outer = 0, sweeps = 0, hist = 0, rc = JSWEEP_OK;
     double rho = INFINITY;
@@ -369,8 +378,22 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
         double wsum = 0.0;
         for (double x : g.weight_h) wsum += x;
         while (true) {
+            // From a zero iterate with no boundary inflow the residual is
+            // q itself (rho = 1), and the first correction solve is source
+            // iteration on the problem itself: isotropic source q + sigma_s
+            // dphi, no per-direction part, no operator application needed.
+            const bool from_zero = outer == 0 && zero_start && psi_b == 0.0;
             double qq = 0.0;
-            rho = residual(g, psi, q, sigma_s, psi_b, phi, r32, acc, s, &qq);
+            if (from_zero) {
+                JSW_HIP(hipMemsetAsync(acc, 0, 8, s));
+                k_qnorm<<<(int)ceil_div(g.nc, kB), kB, 0, s>>>(q, g.vol.as<double>(), g.nc, acc);
+                JSW_HIP(hipGetLastError());
+                JSW_HIP(hipMemcpyAsync(&qq, acc, 8, hipMemcpyDeviceToHost, s));
+                JSW_HIP(hipStreamSynchronize(s));
+                rho = qq > 0.0 ? 1.0 : 0.0;
+            } else {
+                rho = residual(g, psi, q, sigma_s, psi_b, phi, r32, acc, s, &qq);
+            }
             const double qn = qq > 0.0 ? std::sqrt(qq) : 1.0;
             ++outer;
             record(rho);
@@ -379,7 +402,12 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
             // inner source iteration on the correction in FP32
             JSW_HIP(hipMemsetAsync(dpsi, 0, 4 * N, s));
             JSW_HIP(hipMemsetAsync(dphi, 0, 8 * g.nc, s));
-            JSW_HIP(hipMemsetAsync(g32, 0, 4 * g.nc, s));
+            if (from_zero) {
+                k_narrow<<<(int)ceil_div(g.nc, kB), kB, 0, s>>>(q, g.nc, g32);
+                JSW_HIP(hipGetLastError());
+            } else {
+                JSW_HIP(hipMemsetAsync(g32, 0, 4 * g.nc, s));
+            }
             // Inner stop: the outer residual the correction leaves behind is
             // predicted after every inner sweep from the correction
             // equation's residual (isotropic part; lagged faces left out)
@@ -391,11 +419,12 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
             double prev_pred = INFINITY;
             for (int j = 0; j < J && sweeps < max_iter; ++j) {
                 lag_snapshot<float>(g, dpsi, s);
-                launch_sweep32(g, r32, g32, dpsi, params, s);
+                launch_sweep32(g, from_zero ? nullptr : r32, g32, dpsi, params, s);
                 ++sweeps;
                 JSW_HIP(hipMemsetAsync(acc + 2, 0, 16, s));
                 k_dphi<<<(int)ceil_div(g.nc, kB), kB, 0, s>>>(dpsi, g.weight.as<double>(), sigma_s, g.vol.as<double>(),
-                                                           g.nc, g.nd, dphi, g32, g.status.as<int32_t>(), acc + 2);
+                                                           g.nc, g.nd, from_zero ? q : nullptr, dphi, g32,
+                                                           g.status.as<int32_t>(), acc + 2);
                 JSW_HIP(hipGetLastError());
                 double h[3];   // norm of dphi, correction residual, sweep status
                 JSW_HIP(hipMemcpyAsync(h, acc + 2, 24, hipMemcpyDeviceToHost, s));
