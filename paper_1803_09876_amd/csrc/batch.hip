@@ -39,6 +39,7 @@ struct BInst {
     const uint64_t *lag_mv;
     const int32_t *lag_u;
     const int32_t *posi;
+    double *sig_last;                    // sigma_t of the last denominator build
     double *lag64;
     float *lag32;
     int64_t n_lag, nc;
@@ -57,31 +58,38 @@ __device__ inline int find_inst(const int64_t *off, int n, int64_t g) {
     return lo;
 }
 
-__global__ void k_b_sigv(const BInst *I, const int64_t *coff, int n, int64_t total) {
+// sigma_t V into every instance's records (FP32 copies too); flags the
+// instances whose sigma_t differs from the one their denominators were
+// built for, keeping the new values
+__global__ void k_b_sigma(const BInst *I, const int64_t *coff, int n, int64_t total, int32_t *changed) {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= total) return;
     const int i = find_inst(coff, n, g);
     const BInst &b = I[i];
     const int64_t K = g - coff[i];
+    const double st = b.sigma_t[K];
+    if (__double_as_longlong(st) != __double_as_longlong(b.sig_last[K])) {
+        b.sig_last[K] = st;
+        changed[i] = 1;
+    }
     if (b.ctype == JSWEEP_TRI) {
         auto *r64 = (CellRec<double, 3, 2> *)b.rec64 + K;
-        double v = b.sigma_t[K] * r64->V;
+        double v = st * r64->V;
         r64->sigV = v;
         if (b.rec32) ((CellRec<float, 3, 2> *)b.rec32 + K)->sigV = (float)v;
     } else if (b.ctype == JSWEEP_TET) {
         auto *r64 = (CellRec<double, 4, 3> *)b.rec64 + K;
-        double v = b.sigma_t[K] * r64->V;
+        double v = st * r64->V;
         r64->sigV = v;
         if (b.rec32) ((CellRec<float, 4, 3> *)b.rec32 + K)->sigV = (float)v;
     } else {
         auto *r64 = (CellRec<double, 6, 3> *)b.rec64 + K;
-        double v = b.sigma_t[K] * r64->V;
+        double v = st * r64->V;
         r64->sigV = v;
         if (b.rec32) ((CellRec<float, 6, 3> *)b.rec32 + K)->sigV = (float)v;
     }
 }
 
-// zero the FP64 angular flux (what = 0), or the correction state (1)
 __global__ void k_b_zero(const BInst *I, const int64_t *off, int n, int64_t total, const int32_t *active, int what) {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= total) return;
@@ -239,6 +247,11 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
         b.lag_mv = g.lag_mv.as<uint64_t>();
         b.lag_u = g.lag_u.as<int32_t>();
         b.posi = g.posi.as<int32_t>();
+        if (!g.sig_last.p) {
+            g.sig_last.alloc(8 * g.nc + 64);
+            g.den64_ok = g.den32_ok = false;
+        }
+        b.sig_last = g.sig_last.as<double>();
         b.lag64 = g.lag_val64.as<double>();
         b.lag32 = g.lag_val32.as<float>();
         b.n_lag = g.n_lag;
@@ -263,9 +276,25 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
     const BInst *I = d_inst.as<BInst>();
     const int64_t C = coff[n], A = aoff[n], LG = loff[n];
     int threads = (params && params->waves_per_block > 0) ? 64 * params->waves_per_block : 256;
+    // sigma_t V in the records of every instance and the sweep-program
+    // denominators, rebuilt only where sigma_t changed (one kernel and one
+    // read-back for the whole batch)
+    {
+        DevBuf d_changed(4 * n);
+        JSW_HIP(hipMemsetAsync(d_changed.p, 0, 4 * n, s));
+        k_b_sigma<<<grid_for(C), kB, 0, s>>>(I, d_coff.as<int64_t>(), n, C, d_changed.as<int32_t>());
+        JSW_HIP(hipGetLastError());
+        std::vector<int32_t> changed(n);
+        JSW_HIP(hipMemcpyAsync(changed.data(), d_changed.p, 4 * n, hipMemcpyDeviceToHost, s));
+        JSW_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i < n; ++i) {
+            if (changed[i]) graphs[i]->den64_ok = graphs[i]->den32_ok = false;
+            ensure_den(*graphs[i], refined, s);
+        }
+    }
     BatchSweep sweep;
-    sweep.setup(n, graphs, refined, src_cell.data(), src_dir.data(), psi_sweep.data(), psi_b.data(), threads, s);
-    k_b_sigv<<<grid_for(C), kB, 0, s>>>(I, d_coff.as<int64_t>(), n, C);
+    sweep.setup(n, graphs, refined, src_cell.data(), src_dir.data(), psi_sweep.data(), psi_b.data(), threads,
+                params ? params->strategy : 0, s);
     k_b_zero<<<grid_for(A), kB, 0, s>>>(I, d_aoff.as<int64_t>(), n, A, nullptr, 0);
     JSW_HIP(hipGetLastError());
 
@@ -506,6 +535,7 @@ int autotune(int32_t n, Graph *const *graphs, int32_t mode, jsweep_params *out) 
             cands.push_back(ring_probe);
     } else {
         for (int w : {1, 2, 4, 8, 16}) cands.push_back(jsweep_params{w, 0, 0, 0, JSWEEP_STRATEGY_DIRECTION, 0});
+        cands.push_back(ring_probe);
     }
     hipEvent_t e0, e1;
     JSW_HIP(hipEventCreate(&e0));
@@ -524,7 +554,7 @@ int autotune(int32_t n, Graph *const *graphs, int32_t mode, jsweep_params *out) 
             std::vector<void *> ps(n);
             std::vector<double> pb(n, 0.0);
             for (int i = 0; i < n; ++i) { sc[i] = src[i].p; ps[i] = psi[i].p; }
-            bs.setup(n, graphs, fp32, sc.data(), sd.data(), ps.data(), pb.data(), 64 * c.waves_per_block, s);
+            bs.setup(n, graphs, fp32, sc.data(), sd.data(), ps.data(), pb.data(), 64 * c.waves_per_block, c.strategy, s);
         }
         for (int rep = 0; rep < 3; ++rep) {
             JSW_HIP(hipEventRecord(e0, s));

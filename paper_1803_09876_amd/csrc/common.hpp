@@ -184,6 +184,8 @@ struct SweepSrc {
     const void *dir;         // [nd*nc] per-direction part (float, FP32 path only), may be null
 };
 void refresh_sigma(Graph &g, const double *sigma_t, bool fp32, hipStream_t s);
+// sweep-program denominators from the records' sigma_t V, where not valid
+void ensure_den(Graph &g, bool fp32, hipStream_t s);
 void launch_sweep64(Graph &g, const double *src_cell, double *psi, double psi_b, const jsweep_params *p, hipStream_t s);
 void launch_sweep32(Graph &g, const float *src_dir, const float *src_cell, float *psi, const jsweep_params *p,
                     hipStream_t s);
@@ -198,8 +200,11 @@ struct BatchSweep {
     int64_t n_tasks = 0;
     int threads = 256;
     bool fp32 = false;
+    bool ring = false;                   // LDS-window kernel (every instance fits its limits)
+    // strategy: JSWEEP_STRATEGY_DIRECTION forces the plain direction kernel;
+    // otherwise the LDS-window kernel is used where every instance fits it
     void setup(int32_t n, Graph *const *graphs, bool fp32, const void *const *src_cell, const float *const *src_dir,
-               void *const *psi, const double *psi_b, int threads, hipStream_t s);
+               void *const *psi, const double *psi_b, int threads, int strategy, hipStream_t s);
     void launch(const int32_t *active, hipStream_t s);
 };
 

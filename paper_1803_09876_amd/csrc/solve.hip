@@ -116,6 +116,11 @@ void refresh_sigma(Graph &g, const double *sigma_t, bool fp32, hipStream_t s) {
     JSW_HIP(hipMemcpyAsync(&changed, flag, 4, hipMemcpyDeviceToHost, s));
     JSW_HIP(hipStreamSynchronize(s));
     if (changed) g.den64_ok = g.den32_ok = false;
+    ensure_den(g, fp32, s);
+}
+
+void ensure_den(Graph &g, bool fp32, hipStream_t s) {
+    if (!g.n_chunks) return;
     auto run = [&](bool f32) {
         if (g.ctype == JSWEEP_TRI) refresh_den<3, 2>(g, f32, s);
         else if (g.ctype == JSWEEP_TET) refresh_den<4, 3>(g, f32, s);

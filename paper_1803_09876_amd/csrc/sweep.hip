@@ -566,6 +566,7 @@ struct RingArgs {
     const int32_t *lvl_cells;                // [nd*nc]
     int64_t nc;
     int64_t stride;                          // program slot stride
+    int32_t ns;                              // program slots (the batched kernel reads up to its NS)
     const int32_t *pcode;
     const Real *pa;
     const Real *pden;
@@ -587,21 +588,27 @@ struct RingItem {
 };
 
 // one pass: vertices [s0 + off, s0 + off + n) of a level whose first chunk
-// is c0; lane t takes vertices t, t + kRingThreads, ...
-template <class Real, int NS, int ITEMS>
+// is c0; lane t takes vertices t, t + T, ...  With DYN, slots at or past
+// a.ns are empty.
+template <class Real, int NS, int ITEMS, int T, bool DYN>
 __device__ __forceinline__ void ring_load(const RingArgs<Real> &a, int64_t base, int64_t s0, int off, int n,
                                           int64_t c0, RingItem<Real, NS> (&it)[ITEMS]) {
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
-        const int i = off + (int)threadIdx.x + k * kRingThreads;
+        const int i = off + (int)threadIdx.x + k * T;
         if (i < off + n) {
             const int64_t idx = (c0 + (i >> 6)) * 64 + (i & 63);
             it[k].den = a.pden[idx];
             it[k].K = a.lvl_cells[base + s0 + i];
 #pragma unroll
             for (int j = 0; j < NS; ++j) {
-                it[k].code[j] = a.pcode[j * a.stride + idx];
-                it[k].af[j] = a.pa[j * a.stride + idx];
+                if (!DYN || j < a.ns) {
+                    it[k].code[j] = a.pcode[j * a.stride + idx];
+                    it[k].af[j] = a.pa[j * a.stride + idx];
+                } else {
+                    it[k].code[j] = kNoFace;
+                    it[k].af[j] = Real(0);
+                }
             }
             it[k].V = a.pvol[idx];
             it[k].sd = Real(0);
@@ -612,23 +619,19 @@ __device__ __forceinline__ void ring_load(const RingArgs<Real> &a, int64_t base,
     }
 }
 
-// A level is processed in passes of at most kRingThreads * ITEMS vertices
-// (its vertices are independent); the next pass's data is loaded while the
+// A level is processed in passes of at most T * ITEMS vertices (its
+// vertices are independent); the next pass's data is loaded while the
 // current one computes.  After every pass: all loads and stores complete,
 // then a barrier.  A pass's fluxes are stored at the start of the next
 // pass, so values of levels two or more back are always readable from
-// memory; the ring holds the previous level and the current one.
-template <class Real, int NS, int ITEMS>
-__global__ void __launch_bounds__(kRingThreads) k_sweep_ring(RingArgs<Real> a) {
-    constexpr int R = ring_size<Real>();
-    constexpr int P = kRingThreads * ITEMS;
-    __shared__ Real ring[R];
-    __shared__ int32_t lp[kRingMaxLev + 1], lc[kRingMaxLev + 1];
-    const int m = blockIdx.x;
+// memory; the ring (R entries) holds the previous level and the current one.
+template <class Real, int NS, int ITEMS, int T, int R, int MAXLEV, bool DYN>
+__device__ __forceinline__ void ring_direction(const RingArgs<Real> &a, int m, Real *ring, int32_t *lp, int32_t *lc) {
+    constexpr int P = T * ITEMS;
     const int64_t base = (int64_t)m * a.nc;
     const int64_t off0 = a.lvl_off[m];
     const int nlev = (int)(a.lvl_off[m + 1] - off0 - 1);
-    for (int i = threadIdx.x; i <= nlev; i += kRingThreads) {
+    for (int i = threadIdx.x; i <= nlev; i += T) {
         lp[i] = (int32_t)a.lvl_ptr[off0 + i];
         lc[i] = i < nlev ? a.lvl_chunk[off0 + i] : 0;
     }
@@ -642,7 +645,7 @@ __global__ void __launch_bounds__(kRingThreads) k_sweep_ring(RingArgs<Real> a) {
     // pass cursor: level L, vertices [off, off + n)
     int L = 0, off = 0;
     int n = min(P, lp[1] - lp[0]);
-    ring_load<Real, NS, ITEMS>(a, base, lp[0], 0, n, lc[0], cur);
+    ring_load<Real, NS, ITEMS, T, DYN>(a, base, lp[0], 0, n, lc[0], cur);
     while (true) {
         const int64_t s0 = lp[L];
         const int w = lp[L + 1] - lp[L];
@@ -651,14 +654,14 @@ __global__ void __launch_bounds__(kRingThreads) k_sweep_ring(RingArgs<Real> a) {
         Real sc[ITEMS];
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
-            const int i = off + (int)threadIdx.x + k * kRingThreads;
+            const int i = off + (int)threadIdx.x + k * T;
             sc[k] = (a.src_cell && i < off + n) ? a.src_cell[cur[k].K] : Real(0);
         }
         // the previous pass's fluxes to memory
         if (prev_s >= 0) {
 #pragma unroll
             for (int k = 0; k < ITEMS; ++k) {
-                const int i = (int)threadIdx.x + k * kRingThreads;
+                const int i = (int)threadIdx.x + k * T;
                 if (i < prev_n) {
                     a.psi_pos[base + prev_s + i] = prev_v[k];
                     a.psi[base + prev_K[k]] = prev_v[k];
@@ -671,13 +674,13 @@ __global__ void __launch_bounds__(kRingThreads) k_sweep_ring(RingArgs<Real> a) {
         int nn = 0;
         if (nL < nlev) {
             nn = min(P, lp[nL + 1] - lp[nL] - noff);
-            ring_load<Real, NS, ITEMS>(a, base, lp[nL], noff, nn, lc[nL], nxt);
+            ring_load<Real, NS, ITEMS, T, DYN>(a, base, lp[nL], noff, nn, lc[nL], nxt);
         }
         // this pass: positions [e - R, s0) of the direction are in the ring
         const int64_t lo = s0 + w - R;
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
-            const int i = off + (int)threadIdx.x + k * kRingThreads;
+            const int i = off + (int)threadIdx.x + k * T;
             if (i < off + n) {
                 const RingItem<Real, NS> &it = cur[k];
                 // V s, evaluated as in the other sweep kernels
@@ -715,12 +718,40 @@ __global__ void __launch_bounds__(kRingThreads) k_sweep_ring(RingArgs<Real> a) {
     }
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
-        const int i = (int)threadIdx.x + k * kRingThreads;
+        const int i = (int)threadIdx.x + k * T;
         if (i < prev_n) {
             a.psi_pos[base + prev_s + i] = prev_v[k];
             a.psi[base + prev_K[k]] = prev_v[k];
         }
     }
+}
+
+template <class Real, int NS, int ITEMS>
+__global__ void __launch_bounds__(kRingThreads) k_sweep_ring(RingArgs<Real> a) {
+    constexpr int R = ring_size<Real>();
+    __shared__ Real ring[R];
+    __shared__ int32_t lp[kRingMaxLev + 1], lc[kRingMaxLev + 1];
+    ring_direction<Real, NS, ITEMS, kRingThreads, R, kRingMaxLev, false>(a, blockIdx.x, ring, lp, lc);
+}
+
+// Batched form: one 256-lane workgroup per (instance, direction), a 32 KB
+// ring and a 1024-level table, so several tasks share a compute unit.
+constexpr int kBRingThreads = 256;
+constexpr int kBRingMaxLev = 1024;
+constexpr int kBRingNS = 6;
+template <class Real>
+constexpr int bring_size() { return sizeof(Real) == 8 ? 4096 : 8192; }
+
+template <class Real>
+__global__ void __launch_bounds__(kBRingThreads) k_sweep_batch_ring(const RingArgs<Real> *inst, const int32_t *task_inst,
+                                                                   const int32_t *task_dir, const int32_t *active) {
+    constexpr int R = bring_size<Real>();
+    __shared__ Real ring[R];
+    __shared__ int32_t lp[kBRingMaxLev + 1], lc[kBRingMaxLev + 1];
+    const int i = task_inst[blockIdx.x];
+    if (!active[i]) return;
+    ring_direction<Real, kBRingNS, 2, kBRingThreads, R, kBRingMaxLev, true>(inst[i], task_dir[blockIdx.x], ring, lp,
+                                                                           lc);
 }
 
 // vertices per lane and pass for the ring kernel (0: not applicable to
@@ -750,11 +781,12 @@ static const void *ring_kernel(int ns, int items) {
     }
 }
 
+// arguments of the ring sweep for one graph (builds the program-order
+// volumes and the level-ordered flux copy on first use)
 template <class Real>
-static void launch_ring(Graph &g, const Real *src_cell, const float *src_dir, Real *psi, Real psi_b, hipStream_t s) {
+static RingArgs<Real> ring_args(Graph &g, const Real *src_cell, const float *src_dir, Real *psi, Real psi_b,
+                                hipStream_t s) {
     const bool f32 = sizeof(Real) == 4;
-    const int items = ring_items(g, f32);
-    if (!items) fail(JSWEEP_E_DEVICE, "ring sweep not applicable to this graph");
     if (!(f32 ? g.den32_ok : g.den64_ok)) fail(JSWEEP_E_DEVICE, "sweep program denominators not built");
     const int64_t S = 64 * g.n_chunks;
     DevBuf &pv = f32 ? g.pvol32 : g.pvol64;
@@ -770,6 +802,7 @@ static void launch_ring(Graph &g, const Real *src_cell, const float *src_dir, Re
     a.lvl_cells = g.lvl_cells.as<int32_t>();
     a.nc = g.nc;
     a.stride = S;
+    a.ns = g.ns;
     a.pcode = g.pcode.as<int32_t>();
     a.pa = reinterpret_cast<const Real *>(f32 ? g.pa32.p : g.pa64.p);
     a.pden = reinterpret_cast<const Real *>(f32 ? g.pden32.p : g.pden64.p);
@@ -781,6 +814,15 @@ static void launch_ring(Graph &g, const Real *src_cell, const float *src_dir, Re
     a.psi_pos = g.psi_pos.as<Real>();
     a.lag_val = reinterpret_cast<const Real *>(f32 ? g.lag_val32.p : g.lag_val64.p);
     a.psi_b = psi_b;
+    return a;
+}
+
+template <class Real>
+static void launch_ring(Graph &g, const Real *src_cell, const float *src_dir, Real *psi, Real psi_b, hipStream_t s) {
+    const bool f32 = sizeof(Real) == 4;
+    const int items = ring_items(g, f32);
+    if (!items) fail(JSWEEP_E_DEVICE, "ring sweep not applicable to this graph");
+    RingArgs<Real> a = ring_args<Real>(g, src_cell, src_dir, psi, psi_b, s);
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (g.profile) {
         JSW_HIP(hipEventCreate(&ev0));
@@ -873,7 +915,8 @@ static void fill_inst(Graph &g, BatchInst<Real> &b, const Real *src_cell, const 
 }
 
 void BatchSweep::setup(int32_t n, Graph *const *graphs, bool fp32, const void *const *src_cell,
-                       const float *const *src_dir, void *const *psi, const double *psi_b, int threads_, hipStream_t s) {
+                       const float *const *src_dir, void *const *psi, const double *psi_b, int threads_, int strategy,
+                       hipStream_t s) {
     this->fp32 = fp32;
     std::vector<int32_t> ti, td;
     for (int i = 0; i < n; ++i)
@@ -883,29 +926,63 @@ void BatchSweep::setup(int32_t n, Graph *const *graphs, bool fp32, const void *c
     task_dir.alloc(4 * n_tasks);
     JSW_HIP(hipMemcpyAsync(task_inst.p, ti.data(), 4 * n_tasks, hipMemcpyHostToDevice, s));
     JSW_HIP(hipMemcpyAsync(task_dir.p, td.data(), 4 * n_tasks, hipMemcpyHostToDevice, s));
+    // the LDS-window kernel when every instance fits it
+    ring = strategy != JSWEEP_STRATEGY_DIRECTION;
+    const int64_t R = fp32 ? bring_size<float>() : bring_size<double>();
+    for (int i = 0; i < n && ring; ++i) {
+        const Graph &g = *graphs[i];
+        ring = g.n_chunks > 0 && g.max_w2 <= R && g.max_levels <= kBRingMaxLev && g.ns >= 1 && g.ns <= kBRingNS;
+    }
+    if (ring) {
+        if (fp32) {
+            std::vector<RingArgs<float>> h(n);
+            for (int i = 0; i < n; ++i)
+                h[i] = ring_args<float>(*graphs[i], (const float *)src_cell[i], src_dir[i], (float *)psi[i], (float)psi_b[i], s);
+            inst.alloc(sizeof(RingArgs<float>) * n);
+            JSW_HIP(hipMemcpyAsync(inst.p, h.data(), sizeof(RingArgs<float>) * n, hipMemcpyHostToDevice, s));
+        } else {
+            std::vector<RingArgs<double>> h(n);
+            for (int i = 0; i < n; ++i)
+                h[i] = ring_args<double>(*graphs[i], (const double *)src_cell[i], src_dir[i], (double *)psi[i], psi_b[i], s);
+            inst.alloc(sizeof(RingArgs<double>) * n);
+            JSW_HIP(hipMemcpyAsync(inst.p, h.data(), sizeof(RingArgs<double>) * n, hipMemcpyHostToDevice, s));
+        }
+        JSW_HIP(hipStreamSynchronize(s));   // host tables above go out of scope
+        threads = kBRingThreads;
+        return;
+    }
     if (fp32) {
         std::vector<BatchInst<float>> h(n);
         for (int i = 0; i < n; ++i)
             fill_inst<float>(*graphs[i], h[i], (const float *)src_cell[i], src_dir[i], (float *)psi[i], (float)psi_b[i]);
         inst.alloc(sizeof(BatchInst<float>) * n);
         JSW_HIP(hipMemcpyAsync(inst.p, h.data(), sizeof(BatchInst<float>) * n, hipMemcpyHostToDevice, s));
+        JSW_HIP(hipStreamSynchronize(s));
     } else {
         std::vector<BatchInst<double>> h(n);
         for (int i = 0; i < n; ++i)
             fill_inst<double>(*graphs[i], h[i], (const double *)src_cell[i], src_dir[i], (double *)psi[i], psi_b[i]);
         inst.alloc(sizeof(BatchInst<double>) * n);
         JSW_HIP(hipMemcpyAsync(inst.p, h.data(), sizeof(BatchInst<double>) * n, hipMemcpyHostToDevice, s));
+        JSW_HIP(hipStreamSynchronize(s));
     }
     threads = threads_ > 0 ? std::min(1024, std::max(64, threads_)) : 256;
 }
-
 void BatchSweep::launch(const int32_t *active, hipStream_t s) {
-    if (fp32)
+    if (ring) {
+        if (fp32)
+            hipLaunchKernelGGL(k_sweep_batch_ring<float>, dim3((unsigned)n_tasks), dim3(kBRingThreads), 0, s,
+                               inst.as<RingArgs<float>>(), task_inst.as<int32_t>(), task_dir.as<int32_t>(), active);
+        else
+            hipLaunchKernelGGL(k_sweep_batch_ring<double>, dim3((unsigned)n_tasks), dim3(kBRingThreads), 0, s,
+                               inst.as<RingArgs<double>>(), task_inst.as<int32_t>(), task_dir.as<int32_t>(), active);
+    } else if (fp32) {
         hipLaunchKernelGGL(k_sweep_batch<float>, dim3((unsigned)n_tasks), dim3(threads), 0, s,
                            inst.as<BatchInst<float>>(), task_inst.as<int32_t>(), task_dir.as<int32_t>(), active);
-    else
+    } else {
         hipLaunchKernelGGL(k_sweep_batch<double>, dim3((unsigned)n_tasks), dim3(threads), 0, s,
                            inst.as<BatchInst<double>>(), task_inst.as<int32_t>(), task_dir.as<int32_t>(), active);
+    }
     JSW_HIP(hipGetLastError());
 }
 
