@@ -201,7 +201,11 @@ int jsweep_sweep(jsweep_graph g, const double *sigma_t, const double *source, do
  *   r_{K,m} = q_K + sigma_s,K phi_K - (L psi)_{K,m} / V_K
  * with the full (un-lagged) streaming operator L and stops once
  * rho = ||r|| / ||q|| <= tol, where ||x||^2 = sum_K V_K sum_m w_m x_{K,m}^2
- * and ||q||^2 = sum_K V_K q_K^2 (rho = ||r|| when q = 0).
+ * and ||q||^2 = sum_K V_K q_K^2 (rho = ||r|| when q = 0); tol = 0 runs
+ * exactly max_iter sweeps.  After a plain FP64 sweep r is evaluated through
+ * the identity the sweep satisfies (sigma_s times the change of phi plus
+ * the lagged-face differences), which equals the operator form up to
+ * rounding.
  *   mode JSWEEP_FP64: plain source iteration, one FP64 sweep per outer step.
  *   mode JSWEEP_FP32_REFINED: iterative refinement; the correction
  *     (L - sigma_s W) dpsi = r is approximated by up to inner_sweeps FP32

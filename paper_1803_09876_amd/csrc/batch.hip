@@ -25,7 +25,7 @@
 namespace jsw {
 
 constexpr int kB = 256;
-constexpr int kInnerBlock = 4;   // inner sweeps per graph replay
+constexpr int kInnerBlock = 2;   // inner sweeps per graph replay (the granularity of the inner stop)
 // outer residual reduction an FP32 correction solve reliably achieves
 constexpr double kFp32Floor = 4e-6;
 
@@ -40,6 +40,8 @@ struct BInst {
     const int32_t *lag_u;
     const int32_t *posi;
     double *sig_last;                    // sigma_t of the last denominator build
+    const double *lag_a;                 // |Omega . S| of the lagged faces
+    double wsum;                         // sum of the weights
     double *lag64;
     float *lag32;
     int64_t n_lag, nc;
@@ -99,9 +101,22 @@ __global__ void k_b_zero(const BInst *I, const int64_t *off, int n, int64_t tota
     const int64_t x = g - off[i];
     if (what == 0) b.psi[x] = 0.0;
     else {
+        // 1: a correction solve; 2: the first solve from a zero iterate,
+        // whose source is q itself (no per-direction part)
         b.dpsi[x] = 0.0f;
-        if (x < b.nc) { b.dphi[x] = 0.0; b.g32[x] = 0.0f; }
+        if (what == 2) b.r32[x] = 0.0f;
+        if (x < b.nc) { b.dphi[x] = 0.0; b.g32[x] = what == 2 ? (float)b.q[x] : 0.0f; }
     }
+}
+
+// ||q||^2 of every instance into acc[4 i + 1]
+__global__ void k_b_qnorm(const BInst *I, const int64_t *coff, int n, int64_t total, double *acc) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int i = find_inst(coff, n, g);
+    const BInst &b = I[i];
+    const int64_t K = g - coff[i];
+    atomicAdd(acc + 4 * i + 1, b.vol[K] * (b.q[K] * b.q[K]));
 }
 
 __global__ void k_b_source(const BInst *I, const int64_t *coff, int n, int64_t total, const int32_t *active) {
@@ -154,10 +169,51 @@ __global__ void k_b_residual(const BInst *I, const int64_t *coff, int n, int64_t
     atomicAdd(acc + 4 * i + 1, V * (b.q[K] * b.q[K]));
 }
 
+// Residual of a plain FP64 source iteration from the sweep identity (as in
+// the single-graph solve): phi' (ascending m), d = sigma_s (phi' - phi),
+// acc[4 i] += W V d^2, acc[4 i + 1] += V q^2; then the lagged-edge terms.
+__global__ void k_b_phi_delta(const BInst *I, const int64_t *coff, int n, int64_t total, const int32_t *active,
+                              double *acc) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int i = find_inst(coff, n, g);
+    if (!active[i]) return;
+    const BInst &b = I[i];
+    const int64_t K = g - coff[i];
+    double s = 0.0;
+    for (int m = 0; m < b.nd; ++m) s = s + b.w[m] * b.psi[(int64_t)m * b.nc + K];
+    const double d = b.sigma_s[K] * (s - b.phi[K]);
+    b.phi[K] = s;
+    b.dphi[K] = d;
+    atomicAdd(acc + 4 * i, b.wsum * (b.vol[K] * (d * d)));
+    atomicAdd(acc + 4 * i + 1, b.vol[K] * (b.q[K] * b.q[K]));
+}
+
+// one thread per (direction, downwind cell) group of an instance's lagged
+// edges: w_m V ((d + l)^2 - d^2) with l = sum a (psi'_u - psi_u) / V
+__global__ void k_b_lag_residual(const BInst *I, const int64_t *loff, int n, int64_t total, const int32_t *active,
+                                 double *acc) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int i = find_inst(loff, n, g);
+    if (!active[i]) return;
+    const BInst &b = I[i];
+    const int64_t e = g - loff[i];
+    if (e > 0 && b.lag_mv[e - 1] == b.lag_mv[e]) return;
+    const uint64_t key = b.lag_mv[e];
+    const int64_t m = (int64_t)(key >> 32), v = (int64_t)(key & 0xffffffffu);
+    double l = 0.0;
+    for (int64_t f = e; f < b.n_lag && b.lag_mv[f] == key; ++f)
+        l = l + b.lag_a[f] * (b.psi[m * b.nc + b.lag_u[f]] - b.lag64[f]) / b.vol[v];
+    const double d = b.dphi[v];
+    atomicAdd(acc + 4 * i, b.w[m] * (b.vol[v] * ((d + l) * (d + l) - d * d)));
+}
+
 // correction flux dphi (FP64 sum of FP32 fluxes), FP32 scattering source,
 // acc[4 i + 2] += ||dphi||^2, acc[4 i + 3] += ||sigma_s (dphi - dphi_prev)||^2
 // (the correction equation's residual, as in the single-graph solve)
-__global__ void k_b_dphi(const BInst *I, const int64_t *coff, int n, int64_t total, const int32_t *active, double *acc) {
+__global__ void k_b_dphi(const BInst *I, const int64_t *coff, int n, int64_t total, const int32_t *active,
+                         const int32_t *with_q, double *acc) {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= total) return;
     const int i = find_inst(coff, n, g);
@@ -168,7 +224,7 @@ __global__ void k_b_dphi(const BInst *I, const int64_t *coff, int n, int64_t tot
     for (int m = 0; m < b.nd; ++m) s = s + b.w[m] * (double)b.dpsi[(int64_t)m * b.nc + K];
     const double old = b.dphi[K];
     b.dphi[K] = s;
-    b.g32[K] = (float)(b.sigma_s[K] * s);
+    b.g32[K] = with_q[i] ? (float)(b.q[K] + b.sigma_s[K] * s) : (float)(b.sigma_s[K] * s);
     atomicAdd(acc + 4 * i + 2, b.vol[K] * (s * s));
     const double d = b.sigma_s[K] * (s - old);
     atomicAdd(acc + 4 * i + 3, b.vol[K] * (d * d));
@@ -242,7 +298,8 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
             b.g32 = reinterpret_cast<float *>(b.dphi + g.nc);
         } else {
             b.r32 = b.dpsi = b.g32 = nullptr;
-            b.dphi = nullptr;
+            ensure(g.scratch_d, 8 * g.nc + 64);
+            b.dphi = g.scratch_d.as<double>();   // sigma_s (phi' - phi) of the last iteration
         }
         b.lag_mv = g.lag_mv.as<uint64_t>();
         b.lag_u = g.lag_u.as<int32_t>();
@@ -252,6 +309,9 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
             g.den64_ok = g.den32_ok = false;
         }
         b.sig_last = g.sig_last.as<double>();
+        b.lag_a = g.lag_a.as<double>();
+        b.wsum = 0.0;
+        for (double x : g.weight_h) b.wsum += x;
         b.lag64 = g.lag_val64.as<double>();
         b.lag32 = g.lag_val32.as<float>();
         b.n_lag = g.n_lag;
@@ -341,14 +401,30 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
             sweep.launch(d_active.as<int32_t>(), s);
             ++total_sweeps;
             for (int i = 0; i < n; ++i) sweeps[i] += active[i];
-            residuals();
-            for (int i = 0; i < n; ++i)
-                if (active[i] && rho[i] <= tol) active[i] = 0;
+            // residual from the sweep identity (one pass over psi)
+            k_b_clear<<<grid_for(4 * n), kB, 0, s>>>(d_acc.as<double>(), 4 * n);
+            k_b_phi_delta<<<grid_for(C), kB, 0, s>>>(I, d_coff.as<int64_t>(), n, C, d_active.as<int32_t>(),
+                                                     d_acc.as<double>());
+            if (LG)
+                k_b_lag_residual<<<grid_for(LG), kB, 0, s>>>(I, d_loff.as<int64_t>(), n, LG, d_active.as<int32_t>(),
+                                                             d_acc.as<double>());
+            JSW_HIP(hipGetLastError());
+            JSW_HIP(hipMemcpyAsync(acc.data(), d_acc.p, 8 * 4 * n, hipMemcpyDeviceToHost, s));
+            JSW_HIP(hipStreamSynchronize(s));
+            for (int i = 0; i < n; ++i) {
+                if (!active[i]) continue;
+                const double rr = std::max(acc[4 * i], 0.0);
+                rho[i] = acc[4 * i + 1] > 0.0 ? std::sqrt(rr) / std::sqrt(acc[4 * i + 1]) : std::sqrt(rr);
+                ++outer[i];
+                record(i, rho[i]);
+                if (tol > 0.0 && rho[i] <= tol) active[i] = 0;
+            }
             push_active(active);
         }
     } else {
         const int J = (params && params->inner_sweeps > 0) ? params->inner_sweeps : 400;
-        DevBuf d_inner(4 * n);
+        DevBuf d_inner(4 * n), d_withq(4 * n);
+        std::vector<int32_t> withq(n, 0);
         // record kInnerBlock inner sweeps once; replay them per block
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
@@ -358,7 +434,8 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
             sweep.launch(d_inner.as<int32_t>(), s);
             // the norms read back after a replay are those of its last pass
             if (k == kInnerBlock - 1) k_b_clear<<<grid_for(4 * n), kB, 0, s>>>(d_acc.as<double>(), 4 * n);
-            k_b_dphi<<<grid_for(C), kB, 0, s>>>(I, d_coff.as<int64_t>(), n, C, d_inner.as<int32_t>(), d_acc.as<double>());
+            k_b_dphi<<<grid_for(C), kB, 0, s>>>(I, d_coff.as<int64_t>(), n, C, d_inner.as<int32_t>(),
+                                                d_withq.as<int32_t>(), d_acc.as<double>());
         }
         hipError_t ce = hipStreamEndCapture(s, &graph);
         if (ce != hipSuccess) {
@@ -371,18 +448,41 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
             ~GraphGuard() { if (e) (void)hipGraphExecDestroy(e); if (g) (void)hipGraphDestroy(g); }
         } guard{graph, exec};
         std::vector<double> prev_pred(n, INFINITY), target(n, 0.0);
+        // From the zero iterate with no boundary inflow the residual is q
+        // itself (rho = 1): the first solve is source iteration on the
+        // problem, with no operator application (as in the single-graph
+        // solve).
+        bool from_zero = true;
+        for (int i = 0; i < n; ++i) from_zero = from_zero && problems[i].psi_boundary == 0.0;
         while (true) {
-            residuals();
+            if (from_zero) {
+                k_b_clear<<<grid_for(4 * n), kB, 0, s>>>(d_acc.as<double>(), 4 * n);
+                k_b_qnorm<<<grid_for(C), kB, 0, s>>>(I, d_coff.as<int64_t>(), n, C, d_acc.as<double>());
+                JSW_HIP(hipGetLastError());
+                JSW_HIP(hipMemcpyAsync(acc.data(), d_acc.p, 8 * 4 * n, hipMemcpyDeviceToHost, s));
+                JSW_HIP(hipStreamSynchronize(s));
+                for (int i = 0; i < n; ++i) {
+                    qnorm[i] = acc[4 * i + 1] > 0.0 ? std::sqrt(acc[4 * i + 1]) : 1.0;
+                    rho[i] = acc[4 * i + 1] > 0.0 ? 1.0 : 0.0;
+                    ++outer[i];
+                    record(i, rho[i]);
+                }
+            } else {
+                residuals();
+            }
             for (int i = 0; i < n; ++i)
-                if (active[i] && rho[i] <= tol) active[i] = 0;
+                if (tol > 0.0 && active[i] && rho[i] <= tol) active[i] = 0;
             push_active(active);
             bool any = false;
             for (int i = 0; i < n; ++i) any = any || active[i];
             if (!any) break;
             if (total_sweeps >= max_iter) { rc = JSWEEP_E_NOT_CONVERGED; break; }
             // inner FP32 source iteration on the correction of every active instance
-            k_b_zero<<<grid_for(A), kB, 0, s>>>(I, d_aoff.as<int64_t>(), n, A, d_active.as<int32_t>(), 1);
+            k_b_zero<<<grid_for(A), kB, 0, s>>>(I, d_aoff.as<int64_t>(), n, A, d_active.as<int32_t>(), from_zero ? 2 : 1);
             JSW_HIP(hipGetLastError());
+            std::fill(withq.begin(), withq.end(), from_zero ? 1 : 0);
+            JSW_HIP(hipMemcpyAsync(d_withq.p, withq.data(), 4 * n, hipMemcpyHostToDevice, s));
+            from_zero = false;
             inner_active = active;
             // inner stop as in the single-graph solve: the predicted outer
             // residual below half the tolerance, below the FP32 floor of the

@@ -369,7 +369,7 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
             rho = h[1] > 0.0 ? std::sqrt(std::max(h[0], 0.0)) / std::sqrt(h[1]) : std::sqrt(std::max(h[0], 0.0));
             ++outer;
             record(rho);
-            if (rho <= tol) break;
+            if (tol > 0.0 && rho <= tol) break;
         }
     } else {
         ensure(g.scratch_c, 4 * N * 2 + 64);            // r32 and dpsi32
@@ -402,7 +402,7 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
             const double qn = qq > 0.0 ? std::sqrt(qq) : 1.0;
             ++outer;
             record(rho);
-            if (rho <= tol) break;
+            if (tol > 0.0 && rho <= tol) break;
             if (sweeps >= max_iter) { rc = JSWEEP_E_NOT_CONVERGED; break; }
             // inner source iteration on the correction in FP32
             JSW_HIP(hipMemsetAsync(dpsi, 0, 4 * N, s));
