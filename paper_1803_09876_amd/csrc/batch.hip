@@ -49,15 +49,36 @@ struct BInst {
     double psi_b;
 };
 
-// instance of a global index in a concatenation (off: n + 1 prefix sums)
+// instance of a global index in a concatenation (off: n + 1 prefix sums).
+// The indices of a wavefront's lanes ascend with the lane, so the search is
+// done once, wave-uniformly, for the first active lane's index, and every
+// lane then steps over the (few) instance boundaries between the two.
 __device__ inline int find_inst(const int64_t *off, int n, int64_t g) {
+    const uint64_t gu = (uint64_t)g;
+    const int64_t g0 = (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(gu >> 32)) << 32) |
+                                 (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)gu));
     int lo = 0, hi = n;
     while (hi - lo > 1) {
         int mid = (lo + hi) >> 1;
-        if (off[mid] <= g) lo = mid;
+        if (off[mid] <= g0) lo = mid;
         else hi = mid;
     }
+    while (lo + 1 < n && off[lo + 1] <= g) ++lo;
     return lo;
+}
+
+// acc[4 i + slot] += v for every lane of a wavefront (i < 0: nothing).  The
+// lanes that share the first lane's instance are summed in registers and
+// added with one atomic; lanes past an instance boundary add their own.
+// Every lane of the wavefront must call it.
+__device__ inline void acc_add(double *acc, int i, int slot, double v) {
+    const int i0 = __builtin_amdgcn_readfirstlane(i);
+    const bool mine = i == i0;
+    double x = mine ? v : 0.0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x = x + __shfl_xor(x, off, 64);
+    if ((threadIdx.x & 63) == 0 && i0 >= 0) atomicAdd(acc + 4 * i0 + slot, x);
+    if (!mine && i >= 0) atomicAdd(acc + 4 * i + slot, v);
 }
 
 // sigma_t V into every instance's records (FP32 copies too); flags the
@@ -112,11 +133,15 @@ __global__ void k_b_zero(const BInst *I, const int64_t *off, int n, int64_t tota
 // ||q||^2 of every instance into acc[4 i + 1]
 __global__ void k_b_qnorm(const BInst *I, const int64_t *coff, int n, int64_t total, double *acc) {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= total) return;
-    const int i = find_inst(coff, n, g);
-    const BInst &b = I[i];
-    const int64_t K = g - coff[i];
-    atomicAdd(acc + 4 * i + 1, b.vol[K] * (b.q[K] * b.q[K]));
+    int i = -1;
+    double v = 0.0;
+    if (g < total) {
+        i = find_inst(coff, n, g);
+        const BInst &b = I[i];
+        const int64_t K = g - coff[i];
+        v = b.vol[K] * (b.q[K] * b.q[K]);
+    }
+    acc_add(acc, i, 1, v);
 }
 
 __global__ void k_b_source(const BInst *I, const int64_t *coff, int n, int64_t total, const int32_t *active) {
@@ -145,28 +170,31 @@ __global__ void k_b_lag(const BInst *I, const int64_t *loff, int n, int64_t tota
 __global__ void k_b_residual(const BInst *I, const int64_t *coff, int n, int64_t total, const int32_t *active,
                              int fp32, double *acc) {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= total) return;
-    const int i = find_inst(coff, n, g);
-    if (!active[i]) return;
-    const BInst &b = I[i];
-    const int64_t K = g - coff[i];
-    float *r32 = fp32 ? b.r32 : nullptr;
-    double rr, V;
-    if (b.ctype == JSWEEP_TRI) {
-        const CellRec<double, 3, 2> r = ((const CellRec<double, 3, 2> *)b.rec64)[K];
-        rr = residual_cell(r, K, b.omega, b.w, b.psi, b.q[K], b.sigma_s[K], b.psi_b, b.nc, b.nd, b.phi, r32, b.posi);
-        V = r.V;
-    } else if (b.ctype == JSWEEP_TET) {
-        const CellRec<double, 4, 3> r = ((const CellRec<double, 4, 3> *)b.rec64)[K];
-        rr = residual_cell(r, K, b.omega, b.w, b.psi, b.q[K], b.sigma_s[K], b.psi_b, b.nc, b.nd, b.phi, r32, b.posi);
-        V = r.V;
-    } else {
-        const CellRec<double, 6, 3> r = ((const CellRec<double, 6, 3> *)b.rec64)[K];
-        rr = residual_cell(r, K, b.omega, b.w, b.psi, b.q[K], b.sigma_s[K], b.psi_b, b.nc, b.nd, b.phi, r32, b.posi);
-        V = r.V;
+    int i = g < total ? find_inst(coff, n, g) : -1;
+    if (i >= 0 && !active[i]) i = -1;
+    double rr = 0.0, qq = 0.0;
+    if (i >= 0) {
+        const BInst &b = I[i];
+        const int64_t K = g - coff[i];
+        float *r32 = fp32 ? b.r32 : nullptr;
+        double V;
+        if (b.ctype == JSWEEP_TRI) {
+            const CellRec<double, 3, 2> r = ((const CellRec<double, 3, 2> *)b.rec64)[K];
+            rr = residual_cell(r, K, b.omega, b.w, b.psi, b.q[K], b.sigma_s[K], b.psi_b, b.nc, b.nd, b.phi, r32, b.posi);
+            V = r.V;
+        } else if (b.ctype == JSWEEP_TET) {
+            const CellRec<double, 4, 3> r = ((const CellRec<double, 4, 3> *)b.rec64)[K];
+            rr = residual_cell(r, K, b.omega, b.w, b.psi, b.q[K], b.sigma_s[K], b.psi_b, b.nc, b.nd, b.phi, r32, b.posi);
+            V = r.V;
+        } else {
+            const CellRec<double, 6, 3> r = ((const CellRec<double, 6, 3> *)b.rec64)[K];
+            rr = residual_cell(r, K, b.omega, b.w, b.psi, b.q[K], b.sigma_s[K], b.psi_b, b.nc, b.nd, b.phi, r32, b.posi);
+            V = r.V;
+        }
+        qq = V * (b.q[K] * b.q[K]);
     }
-    atomicAdd(acc + 4 * i, rr);
-    atomicAdd(acc + 4 * i + 1, V * (b.q[K] * b.q[K]));
+    acc_add(acc, i, 0, rr);
+    acc_add(acc, i, 1, qq);
 }
 
 // Residual of a plain FP64 source iteration from the sweep identity (as in
@@ -175,18 +203,22 @@ __global__ void k_b_residual(const BInst *I, const int64_t *coff, int n, int64_t
 __global__ void k_b_phi_delta(const BInst *I, const int64_t *coff, int n, int64_t total, const int32_t *active,
                               double *acc) {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= total) return;
-    const int i = find_inst(coff, n, g);
-    if (!active[i]) return;
-    const BInst &b = I[i];
-    const int64_t K = g - coff[i];
-    double s = 0.0;
-    for (int m = 0; m < b.nd; ++m) s = s + b.w[m] * b.psi[(int64_t)m * b.nc + K];
-    const double d = b.sigma_s[K] * (s - b.phi[K]);
-    b.phi[K] = s;
-    b.dphi[K] = d;
-    atomicAdd(acc + 4 * i, b.wsum * (b.vol[K] * (d * d)));
-    atomicAdd(acc + 4 * i + 1, b.vol[K] * (b.q[K] * b.q[K]));
+    int i = g < total ? find_inst(coff, n, g) : -1;
+    if (i >= 0 && !active[i]) i = -1;
+    double rr = 0.0, qq = 0.0;
+    if (i >= 0) {
+        const BInst &b = I[i];
+        const int64_t K = g - coff[i];
+        double s = 0.0;
+        for (int m = 0; m < b.nd; ++m) s = s + b.w[m] * b.psi[(int64_t)m * b.nc + K];
+        const double d = b.sigma_s[K] * (s - b.phi[K]);
+        b.phi[K] = s;
+        b.dphi[K] = d;
+        rr = b.wsum * (b.vol[K] * (d * d));
+        qq = b.vol[K] * (b.q[K] * b.q[K]);
+    }
+    acc_add(acc, i, 0, rr);
+    acc_add(acc, i, 1, qq);
 }
 
 // one thread per (direction, downwind cell) group of an instance's lagged
@@ -194,19 +226,23 @@ __global__ void k_b_phi_delta(const BInst *I, const int64_t *coff, int n, int64_
 __global__ void k_b_lag_residual(const BInst *I, const int64_t *loff, int n, int64_t total, const int32_t *active,
                                  double *acc) {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= total) return;
-    const int i = find_inst(loff, n, g);
-    if (!active[i]) return;
-    const BInst &b = I[i];
-    const int64_t e = g - loff[i];
-    if (e > 0 && b.lag_mv[e - 1] == b.lag_mv[e]) return;
-    const uint64_t key = b.lag_mv[e];
-    const int64_t m = (int64_t)(key >> 32), v = (int64_t)(key & 0xffffffffu);
-    double l = 0.0;
-    for (int64_t f = e; f < b.n_lag && b.lag_mv[f] == key; ++f)
-        l = l + b.lag_a[f] * (b.psi[m * b.nc + b.lag_u[f]] - b.lag64[f]) / b.vol[v];
-    const double d = b.dphi[v];
-    atomicAdd(acc + 4 * i, b.w[m] * (b.vol[v] * ((d + l) * (d + l) - d * d)));
+    int i = g < total ? find_inst(loff, n, g) : -1;
+    if (i >= 0 && !active[i]) i = -1;
+    double rr = 0.0;
+    if (i >= 0) {
+        const BInst &b = I[i];
+        const int64_t e = g - loff[i];
+        if (e == 0 || b.lag_mv[e - 1] != b.lag_mv[e]) {
+            const uint64_t key = b.lag_mv[e];
+            const int64_t m = (int64_t)(key >> 32), v = (int64_t)(key & 0xffffffffu);
+            double l = 0.0;
+            for (int64_t f = e; f < b.n_lag && b.lag_mv[f] == key; ++f)
+                l = l + b.lag_a[f] * (b.psi[m * b.nc + b.lag_u[f]] - b.lag64[f]) / b.vol[v];
+            const double d = b.dphi[v];
+            rr = b.w[m] * (b.vol[v] * ((d + l) * (d + l) - d * d));
+        }
+    }
+    acc_add(acc, i, 0, rr);
 }
 
 // correction flux dphi (FP64 sum of FP32 fluxes), FP32 scattering source,
@@ -215,19 +251,23 @@ __global__ void k_b_lag_residual(const BInst *I, const int64_t *loff, int n, int
 __global__ void k_b_dphi(const BInst *I, const int64_t *coff, int n, int64_t total, const int32_t *active,
                          const int32_t *with_q, double *acc) {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= total) return;
-    const int i = find_inst(coff, n, g);
-    if (!active[i]) return;
-    const BInst &b = I[i];
-    const int64_t K = g - coff[i];
-    double s = 0.0;
-    for (int m = 0; m < b.nd; ++m) s = s + b.w[m] * (double)b.dpsi[(int64_t)m * b.nc + K];
-    const double old = b.dphi[K];
-    b.dphi[K] = s;
-    b.g32[K] = with_q[i] ? (float)(b.q[K] + b.sigma_s[K] * s) : (float)(b.sigma_s[K] * s);
-    atomicAdd(acc + 4 * i + 2, b.vol[K] * (s * s));
-    const double d = b.sigma_s[K] * (s - old);
-    atomicAdd(acc + 4 * i + 3, b.vol[K] * (d * d));
+    int i = g < total ? find_inst(coff, n, g) : -1;
+    if (i >= 0 && !active[i]) i = -1;
+    double ss = 0.0, dd = 0.0;
+    if (i >= 0) {
+        const BInst &b = I[i];
+        const int64_t K = g - coff[i];
+        double s = 0.0;
+        for (int m = 0; m < b.nd; ++m) s = s + b.w[m] * (double)b.dpsi[(int64_t)m * b.nc + K];
+        const double old = b.dphi[K];
+        b.dphi[K] = s;
+        b.g32[K] = with_q[i] ? (float)(b.q[K] + b.sigma_s[K] * s) : (float)(b.sigma_s[K] * s);
+        ss = b.vol[K] * (s * s);
+        const double d = b.sigma_s[K] * (s - old);
+        dd = b.vol[K] * (d * d);
+    }
+    acc_add(acc, i, 2, ss);
+    acc_add(acc, i, 3, dd);
 }
 
 __global__ void k_b_update(const BInst *I, const int64_t *aoff, int n, int64_t total, const int32_t *active) {

@@ -193,6 +193,7 @@ __global__ void k_sweep(SweepArgs<Real> a) {
             for (uint32_t z = 0; z < a.nap; ++z) __builtin_amdgcn_s_sleep(1);
         }
         const uint32_t t_ready = (uint32_t)__builtin_amdgcn_s_memrealtime();
+        Real out = Real(0);
         if (active) {
             // upwind fluxes: interior and lagged ones are loaded together
             // (one device-scope load per slot, the address selected without
@@ -211,14 +212,16 @@ __global__ void k_sweep(SweepArgs<Real> a) {
 #pragma unroll
             for (int j = 0; j < NS; ++j)
                 if (code[j] != kNoFace) num = num + af[j] * val[j];
-            const Real v = num / den;
-            a.psi_pos[base + pos0 + lane] = v;
-            a.psi[base + K] = v;
+            out = num / den;
+            a.psi_pos[base + pos0 + lane] = out;
         }
-        // publish the chunk once every lane's flux store has completed
+        // publish the chunk once every lane's level-order store has
+        // completed; the cell-order copy is read only after the kernel, so
+        // it is written after the flag, off the dependency chain
         __builtin_amdgcn_s_waitcnt(0);
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         if (lane == 0) a.cflag[c] = epoch;
+        if (active) a.psi[base + K] = out;
         if (a.stamps && lane == 0) {
             a.stamps[3 * c] = t_take;
             a.stamps[3 * c + 1] = t_ready;
@@ -354,7 +357,7 @@ template <class Real>
 __global__ void __launch_bounds__(1024) k_sweep_batch(const BatchInst<Real> *inst, const int32_t *task_inst,
                                                      const int32_t *task_dir, const int32_t *active) {
     const int i = task_inst[blockIdx.x];
-    if (!active[i]) return;
+    if (i < 0 || !active[i]) return;
     const BatchInst<Real> &b = inst[i];
     const int m = task_dir[blockIdx.x];
     if (b.ctype == JSWEEP_TRI) batch_task<Real, 3, 2>(b, m);
@@ -749,7 +752,7 @@ __global__ void __launch_bounds__(kBRingThreads) k_sweep_batch_ring(const RingAr
     __shared__ Real ring[R];
     __shared__ int32_t lp[kBRingMaxLev + 1], lc[kBRingMaxLev + 1];
     const int i = task_inst[blockIdx.x];
-    if (!active[i]) return;
+    if (i < 0 || !active[i]) return;
     ring_direction<Real, kBRingNS, 2, kBRingThreads, R, kBRingMaxLev, true>(inst[i], task_dir[blockIdx.x], ring, lp,
                                                                            lc);
 }
@@ -914,18 +917,65 @@ static void fill_inst(Graph &g, BatchInst<Real> &b, const Real *src_cell, const 
     b.nd = g.nd;
 }
 
+// Launch order of the (instance, direction) tasks; index b runs on XCD
+// b % kStreams.  All directions of an instance go to one XCD, so they share
+// its L2 (the instance's cell records, volumes and sources are read by every
+// direction); instances are dealt to the XCDs by estimated cost, costliest
+// first, onto the least loaded XCD; within an XCD the costliest tasks start
+// first.  Cost of a task: its rounds of T vertices over the direction's
+// levels.  Slots left over where the XCDs' task counts differ hold -1.
+static void batch_order(int32_t n, Graph *const *graphs, int T, DevBuf &task_inst, DevBuf &task_dir,
+                        int64_t &n_tasks, hipStream_t s) {
+    struct Task {
+        int64_t cost;
+        int32_t inst, dir;
+    };
+    std::vector<std::vector<Task>> per(n);
+    std::vector<std::pair<int64_t, int32_t>> inst_cost(n);
+    for (int i = 0; i < n; ++i) {
+        const Graph &g = *graphs[i];
+        int64_t tot = 0;
+        for (int m = 0; m < g.nd; ++m) {
+            const int64_t *ptr = g.lvl_ptr_h.data() + g.lvl_off_h[m];
+            const int nlev = (int)(g.lvl_off_h[m + 1] - g.lvl_off_h[m] - 1);
+            int64_t c = 1;
+            for (int L = 0; L < nlev; ++L) c += ceil_div(ptr[L + 1] - ptr[L], T);
+            per[i].push_back(Task{c, i, m});
+            tot += c;
+        }
+        inst_cost[i] = {tot, i};
+    }
+    std::vector<std::vector<Task>> q(kStreams);
+    std::stable_sort(inst_cost.begin(), inst_cost.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+    std::vector<int64_t> load(kStreams, 0);
+    for (const auto &ic : inst_cost) {
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[x] += ic.first;
+        q[x].insert(q[x].end(), per[ic.second].begin(), per[ic.second].end());
+    }
+    size_t len = 0;
+    for (auto &v : q) {
+        std::stable_sort(v.begin(), v.end(), [](const Task &a, const Task &b) { return a.cost > b.cost; });
+        len = std::max(len, v.size());
+    }
+    n_tasks = (int64_t)len * kStreams;
+    std::vector<int32_t> ti(n_tasks, -1), td(n_tasks, 0);
+    for (int x = 0; x < kStreams; ++x)
+        for (size_t k = 0; k < q[x].size(); ++k) {
+            ti[k * kStreams + x] = q[x][k].inst;
+            td[k * kStreams + x] = q[x][k].dir;
+        }
+    task_inst.alloc(4 * std::max<int64_t>(1, n_tasks));
+    task_dir.alloc(4 * std::max<int64_t>(1, n_tasks));
+    JSW_HIP(hipMemcpyAsync(task_inst.p, ti.data(), 4 * n_tasks, hipMemcpyHostToDevice, s));
+    JSW_HIP(hipMemcpyAsync(task_dir.p, td.data(), 4 * n_tasks, hipMemcpyHostToDevice, s));
+    JSW_HIP(hipStreamSynchronize(s));   // the host tables go out of scope
+}
+
 void BatchSweep::setup(int32_t n, Graph *const *graphs, bool fp32, const void *const *src_cell,
                        const float *const *src_dir, void *const *psi, const double *psi_b, int threads_, int strategy,
                        hipStream_t s) {
     this->fp32 = fp32;
-    std::vector<int32_t> ti, td;
-    for (int i = 0; i < n; ++i)
-        for (int m = 0; m < graphs[i]->nd; ++m) { ti.push_back(i); td.push_back(m); }
-    n_tasks = (int64_t)ti.size();
-    task_inst.alloc(4 * n_tasks);
-    task_dir.alloc(4 * n_tasks);
-    JSW_HIP(hipMemcpyAsync(task_inst.p, ti.data(), 4 * n_tasks, hipMemcpyHostToDevice, s));
-    JSW_HIP(hipMemcpyAsync(task_dir.p, td.data(), 4 * n_tasks, hipMemcpyHostToDevice, s));
     // the LDS-window kernel when every instance fits it
     ring = strategy != JSWEEP_STRATEGY_DIRECTION;
     const int64_t R = fp32 ? bring_size<float>() : bring_size<double>();
@@ -933,6 +983,8 @@ void BatchSweep::setup(int32_t n, Graph *const *graphs, bool fp32, const void *c
         const Graph &g = *graphs[i];
         ring = g.n_chunks > 0 && g.max_w2 <= R && g.max_levels <= kBRingMaxLev && g.ns >= 1 && g.ns <= kBRingNS;
     }
+    const int T = ring ? kBRingThreads * 2 : (threads_ > 0 ? std::min(1024, std::max(64, threads_)) : 256);
+    batch_order(n, graphs, T, task_inst, task_dir, n_tasks, s);
     if (ring) {
         if (fp32) {
             std::vector<RingArgs<float>> h(n);
