@@ -109,11 +109,25 @@ typedef struct jsweep_graph_s *jsweep_graph;   /* opaque, owned by the library *
  *   LDS window and the per-vertex data streamed one level ahead; for graphs
  *   whose consecutive levels hold at most 16384 (FP64) / 32768 (FP32)
  *   vertices together and at most 2048 levels
- *   (otherwise DIRECTION is used). */
+ *   (otherwise DIRECTION is used).
+ * PATCH: the paper's patch-program form (Sec. V-A, V-B): cells are cut into
+ *   spatial patches (Morton order of the cell centres); one wavefront runs a
+ *   patch of one direction as a task, its vertices level by level out of
+ *   LDS, after the upstream tasks have completed; tasks are scheduled data
+ *   driven as in DATA_DRIVEN.  The paper's patch programs are re-entrant: a
+ *   patch whose cells and another patch's wait on each other is computed
+ *   in several visits.  The visits are fixed when the program is built, by
+ *   running each direction's graph patch by patch on the host (the patch
+ *   with the lowest-level ready cell next, as far as it goes); each visit
+ *   is a task, and the task graph is acyclic.  The program is built on the
+ *   first PATCH sweep; FP64 sweeps only (FP32 sweeps use DATA_DRIVEN);
+ *   graphs above 2^26 (cell, direction) pairs or whose tasks exceed the
+ *   kernel's LDS limits fall back to DATA_DRIVEN. */
 #define JSWEEP_STRATEGY_AUTO 0
 #define JSWEEP_STRATEGY_DATA_DRIVEN 1
 #define JSWEEP_STRATEGY_DIRECTION 2
 #define JSWEEP_STRATEGY_DIRECTION_LDS 3
+#define JSWEEP_STRATEGY_PATCH 4
 
 /* Launch tuning of the sweep kernels; 0 in a field = default or the value
  * chosen by jsweep_autotune. */
@@ -245,6 +259,18 @@ int jsweep_solve_batch(int32_t n, const jsweep_graph *graphs, const jsweep_probl
  * keyed by (cell type, size bucket, direction count, mode, device). */
 int jsweep_autotune(int32_t n, const jsweep_graph *graphs, int32_t mode, jsweep_params *out);
 
+/* Launch parameters of a graph's sweeps: the ones jsweep_sweep uses and
+ * jsweep_solve uses when its params argument is NULL (the same slot
+ * jsweep_autotune fills).  p == NULL returns the graph to the defaults. */
+int jsweep_set_params(jsweep_graph g, const jsweep_params *p);
+
+/* The PATCH strategy's program of a graph, built now if it was not yet
+ * (hip_stream as for the other calls).  out[6] (host): 1 if the strategy
+ * applies to this graph (else 0, and PATCH sweeps run DATA_DRIVEN), tasks,
+ * rounds, halo entries, task dependencies, visits beyond one per (patch,
+ * direction). */
+int jsweep_patch_info(jsweep_graph g, void *hip_stream, int64_t *out);
+
 /* Kernel timing of the sweep launches on a graph: while enabled, the
  * library records a HIP event pair around every launch of the sweep kernel
  * (on the launch stream).  jsweep_profile_read synchronises on those
@@ -261,7 +287,10 @@ int jsweep_profile_read(jsweep_graph g, int32_t reset, int64_t *launches, double
  * jsweep_trace_read (host buffers, any may be NULL) returns the chunk count,
  * the stamps of the last traced sweep [3 * n_chunks], per chunk (direction,
  * vertex count, level) [3 * n_chunks], and the coarsened graph as CSR
- * (deps_ptr [n_chunks + 1], deps [deps_ptr[n_chunks]]). */
+ * (deps_ptr [n_chunks + 1], deps [deps_ptr[n_chunks]]).  When the last
+ * traced sweep ran the PATCH kernel, the units are its tasks instead: the
+ * stamps are those of the task, and the per-unit triple is (direction,
+ * vertex count, rounds); the CSR lists the upstream tasks. */
 int jsweep_trace(jsweep_graph g, int32_t enable);
 int jsweep_trace_read(jsweep_graph g, int64_t *n_chunks, uint32_t *stamps, int32_t *chunk_info, int32_t *deps_ptr,
                       int32_t *deps);

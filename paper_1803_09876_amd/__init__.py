@@ -34,11 +34,13 @@ JSWEEP_FP32_REFINED = 1
 JSWEEP_WARM_START = 0x100
 JSWEEP_STRATEGY_AUTO, JSWEEP_STRATEGY_DATA_DRIVEN, JSWEEP_STRATEGY_DIRECTION = 0, 1, 2
 JSWEEP_STRATEGY_DIRECTION_LDS = 3
+JSWEEP_STRATEGY_PATCH = 4
 
 EXPORTED = [
     "jsweep_build_graph", "jsweep_graph_info", "jsweep_graph_export", "jsweep_graph_lagged", "jsweep_sweep",
     "jsweep_solve", "jsweep_solve_batch", "jsweep_autotune", "jsweep_profile", "jsweep_profile_read",
     "jsweep_trace", "jsweep_trace_read", "jsweep_graph_destroy", "jsweep_error_string", "jsweep_last_error",
+    "jsweep_set_params", "jsweep_patch_info",
 ]
 
 
@@ -99,6 +101,8 @@ def load_library(path: str | None = None):
     lib.jsweep_solve.argtypes = [P, P, P, P, dbl, i32, dbl, i32, P, P, P, P, P]
     lib.jsweep_solve_batch.argtypes = [i32, P, P, i32, dbl, i32, P, P, P]
     lib.jsweep_autotune.argtypes = [i32, P, i32, P]
+    lib.jsweep_set_params.argtypes = [P, P]
+    lib.jsweep_patch_info.argtypes = [P, P, P]
     lib.jsweep_profile.argtypes = [P, i32]
     lib.jsweep_profile_read.argtypes = [P, i32, P, P]
     lib.jsweep_trace.argtypes = [P, i32]
@@ -111,7 +115,8 @@ def load_library(path: str | None = None):
     lib.jsweep_last_error.restype = ctypes.c_char_p
     for name in ("jsweep_build_graph", "jsweep_graph_info", "jsweep_graph_export", "jsweep_graph_lagged",
                  "jsweep_sweep", "jsweep_solve", "jsweep_solve_batch", "jsweep_autotune", "jsweep_profile",
-                 "jsweep_profile_read", "jsweep_trace", "jsweep_trace_read"):
+                 "jsweep_profile_read", "jsweep_trace", "jsweep_trace_read", "jsweep_set_params",
+                 "jsweep_patch_info"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -294,6 +299,20 @@ def jsweep_autotune(graphs, mode: int = JSWEEP_FP32_REFINED) -> Params:
     return out
 
 
+def jsweep_set_params(g: Graph, params: Params | None):
+    """Pin the launch parameters of the graph's sweeps (None: defaults)."""
+    _check(load_library().jsweep_set_params(g.handle, ctypes.byref(params) if params is not None else None))
+
+
+def jsweep_patch_info(g: Graph, stream=None):
+    """The PATCH strategy's program (built on demand): dict of available,
+    tasks, rounds, halo, deps, revisits."""
+    out = np.zeros(6, dtype=np.int64)
+    _check(load_library().jsweep_patch_info(g.handle, _stream(stream), out.ctypes.data))
+    return {"available": bool(out[0]), "tasks": int(out[1]), "rounds": int(out[2]), "halo": int(out[3]),
+            "deps": int(out[4]), "revisits": int(out[5])}
+
+
 def jsweep_profile(g: Graph, enable: bool = True):
     _check(load_library().jsweep_profile(g.handle, 1 if enable else 0))
 
@@ -338,6 +357,8 @@ def jsweep_last_error() -> str:
 
 # short aliases
 graph_info = jsweep_graph_info
+set_params = jsweep_set_params
+patch_info = jsweep_patch_info
 graph_export = jsweep_graph_export
 graph_lagged = jsweep_graph_lagged
 sweep = jsweep_sweep

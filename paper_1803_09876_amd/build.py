@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libjsweep.so")
-SOURCES = ["api.hip", "geometry.hip", "dag.hip", "sweep.hip", "solve.hip", "batch.hip"]
+SOURCES = ["api.hip", "geometry.hip", "dag.hip", "sweep.hip", "patch.hip", "solve.hip", "batch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("JSWEEP_ARCH", "gfx950")
 
@@ -30,7 +30,7 @@ FLAGS = [
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-    extra = ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"] if src == "sweep.hip" else []
+    extra = ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"] if src in ("sweep.hip", "patch.hip") else []
     cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

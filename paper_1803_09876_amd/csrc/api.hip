@@ -321,6 +321,39 @@ int jsweep_autotune(int32_t n, const jsweep_graph *graphs, int32_t mode, jsweep_
     });
 }
 
+int jsweep_set_params(jsweep_graph h, const jsweep_params *p) {
+    return guarded([&]() -> int {
+        if (!h) fail(JSWEEP_E_INVALID_ARG, "graph is NULL");
+        Graph &g = *G(h);
+        if (p) {
+            if (p->strategy < 0 || p->strategy > JSWEEP_STRATEGY_PATCH || p->waves_per_block < 0 ||
+                p->blocks_per_cu < 0 || p->inner_sweeps < 0 || p->chunks_per_ticket < 0)
+                fail(JSWEEP_E_INVALID_ARG, "bad launch parameters");
+            g.tuned = *p;
+            g.has_tuned = true;
+        } else {
+            g.tuned = jsweep_params{};
+            g.has_tuned = false;
+        }
+        return JSWEEP_OK;
+    });
+}
+
+int jsweep_patch_info(jsweep_graph h, void *hip_stream, int64_t *out) {
+    return guarded([&]() -> int {
+        if (!h || !out) fail(JSWEEP_E_INVALID_ARG, "NULL argument");
+        Graph &g = *G(h);
+        const bool ok = patch_ready(g, reinterpret_cast<hipStream_t>(hip_stream));
+        out[0] = ok ? 1 : 0;
+        out[1] = g.pp.n_tasks;
+        out[2] = g.pp.n_rounds;
+        out[3] = g.pp.n_halo;
+        out[4] = g.pp.n_dep;
+        out[5] = g.pp.revisits;
+        return JSWEEP_OK;
+    });
+}
+
 int jsweep_profile(jsweep_graph h, int32_t enable) {
     return guarded([&]() -> int {
         if (!h) fail(JSWEEP_E_INVALID_ARG, "graph is NULL");
@@ -368,8 +401,31 @@ int jsweep_trace_read(jsweep_graph h, int64_t *n_chunks, uint32_t *stamps, int32
     return guarded([&]() -> int {
         if (!h) fail(JSWEEP_E_INVALID_ARG, "graph is NULL");
         Graph &g = *G(h);
-        if (n_chunks) *n_chunks = g.n_chunks;
         JSW_HIP(hipDeviceSynchronize());
+        if (g.trace_units == 1) {
+            // the last traced sweep ran the patch kernel: units are its tasks
+            const int64_t nt = g.pp.n_tasks;
+            if (n_chunks) *n_chunks = nt;
+            if (stamps) JSW_HIP(hipMemcpy(stamps, g.trace_buf.p, 12 * (size_t)nt, hipMemcpyDeviceToHost));
+            std::vector<int32_t> desc;
+            if (chunk_info || deps_ptr) {
+                desc.resize(kPatchDesc * (size_t)nt);
+                JSW_HIP(hipMemcpy(desc.data(), g.pp.desc.p, 4 * desc.size(), hipMemcpyDeviceToHost));
+            }
+            if (chunk_info)
+                for (int64_t t = 0; t < nt; ++t) {
+                    chunk_info[3 * t] = desc[kPatchDesc * t + 1];
+                    chunk_info[3 * t + 1] = desc[kPatchDesc * t + 2];
+                    chunk_info[3 * t + 2] = desc[kPatchDesc * t + 3];
+                }
+            if (deps_ptr) {
+                deps_ptr[0] = 0;
+                for (int64_t t = 0; t < nt; ++t) deps_ptr[t + 1] = deps_ptr[t] + desc[kPatchDesc * t + 7];
+            }
+            if (deps && g.pp.n_dep) JSW_HIP(hipMemcpy(deps, g.pp.dep.p, 4 * (size_t)g.pp.n_dep, hipMemcpyDeviceToHost));
+            return JSWEEP_OK;
+        }
+        if (n_chunks) *n_chunks = g.n_chunks;
         if (stamps) {
             if (!g.trace_buf.p) fail(JSWEEP_E_INVALID_ARG, "tracing was never enabled");
             JSW_HIP(hipMemcpy(stamps, g.trace_buf.p, 12 * (size_t)g.n_chunks, hipMemcpyDeviceToHost));

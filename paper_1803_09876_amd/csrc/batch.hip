@@ -388,7 +388,7 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
         JSW_HIP(hipMemcpyAsync(changed.data(), d_changed.p, 4 * n, hipMemcpyDeviceToHost, s));
         JSW_HIP(hipStreamSynchronize(s));
         for (int i = 0; i < n; ++i) {
-            if (changed[i]) graphs[i]->den64_ok = graphs[i]->den32_ok = false;
+            if (changed[i]) graphs[i]->den64_ok = graphs[i]->den32_ok = graphs[i]->pp.den64_ok = false;
             ensure_den(*graphs[i], refined, s);
         }
     }

@@ -106,6 +106,43 @@ __device__ inline int64_t lag_index(const uint64_t *lag_mv, const int32_t *lag_u
 // stream); on MI355X stream x runs on XCD x.
 constexpr int kStreams = 8;
 
+// Patch-task sweep program (built on the first sweep that uses it).  The
+// cells are cut into patches of consecutive Morton rank; a task is one visit
+// of a patch in one direction (a patch may need several visits when its
+// cells and another patch's wait on each other).  Per direction, positions
+// run task by task (tasks in ticket order), by level within a task; a task's
+// levels are split into rounds of at most 64 vertices.  Codes (kPatch*
+// limits below): >= 0 LDS slot of the upwind flux (the task's own vertices
+// first, then its halo), -1 boundary, kNoFace empty.  A halo entry >= 0 is
+// an upwind position of another task of the direction, < 0 the lagged edge
+// -(h + 1).
+constexpr int kPatchSlots = 1024;        // task vertices + halo entries
+constexpr int kPatchCells = 512;         // vertices of a task
+constexpr int kPatchHalo = 512;          // halo entries of a task
+constexpr int kPatchRounds = 128;        // rounds of a task
+constexpr int kPatchDesc = 16;           // descriptor words per task
+struct PatchProg {
+    bool built = false, ok = false;      // ok: every task fits the limits above
+    int P = 0;                           // cells per patch
+    int ns = 0;                          // inflow slots per vertex
+    int64_t n_tasks = 0, n_rounds = 0, n_halo = 0, n_dep = 0;
+    int64_t revisits = 0;                // visits beyond one per (patch, direction)
+    std::vector<int64_t> stream_off_h;
+    DevBuf stream_off;                   // [kStreams + 1] int64 task offsets of the streams
+    DevBuf desc;                         // [n_tasks * kPatchDesc] int32: q0, m, n, rounds, round0, halo, halo0, deps, dep0
+    DevBuf round;                        // [n_rounds] int32 offset in the task | (count - 1) << 16
+    DevBuf halo;                         // [n_halo] int32
+    DevBuf dep;                          // [n_dep] int32 upstream tasks
+    DevBuf cell;                         // [nd*nc] int32 vertex at each position
+    DevBuf code;                         // [ns * nd*nc] int32
+    DevBuf a64;                          // [ns * nd*nc] double
+    DevBuf den64;                        // [nd*nc] double
+    bool den64_ok = false;
+    DevBuf psi;                          // [nd*nc] double fluxes by position (halo source)
+    DevBuf flag;                         // [n_tasks] uint8 completion epochs
+    int epoch = 0;
+};
+
 // ---------------------------------------------------------------------------
 // graph handle
 // ---------------------------------------------------------------------------
@@ -147,6 +184,7 @@ struct Graph {
     DevBuf pvol64, pvol32;               // [64 n_chunks] cell volume in program order (ring sweep)
     DevBuf vsc;                          // [nc] V s (or {V, s}) of the running sweep, per cell
     DevBuf posi;                         // [nd*nc] int32 level position of every vertex
+    DevBuf mrank;                        // [nc] int32 rank of every cell in the Morton order of the vertex averages
     int epoch = 0;                       // last epoch used (1..255)
     DevBuf status;                       // [4] int32 device status words (watchdog)
     // lagged edges, sorted by (direction, downwind cell, upwind cell)
@@ -164,7 +202,9 @@ struct Graph {
     bool has_tuned = false;
     // per-chunk time stamps of the last sweep (jsweep_trace)
     bool trace = false;
+    int trace_units = 0;                 // units of the last traced sweep: 0 work-list chunks, 1 patch tasks
     DevBuf trace_buf;
+    PatchProg pp;                        // patch-task sweep program
     // kernel timing (jsweep_profile)
     bool profile = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
@@ -192,6 +232,13 @@ void launch_sweep32(Graph &g, const float *src_dir, const float *src_cell, float
 int check_sweep_status(Graph &g, hipStream_t s);   // JSWEEP_OK or JSWEEP_E_STALLED
 int persistent_waves(Graph &g, bool fp32, const jsweep_params *p, int *waves_per_block);
 int sweep_strategy(const Graph &g, const jsweep_params *p);
+
+// patch-task sweep (patch.hip): program built on first use; false when the
+// graph does not fit the patch limits (the caller then uses another kernel)
+bool patch_ready(Graph &g, hipStream_t s);
+void patch_den(Graph &g, hipStream_t s);
+void launch_patch64(Graph &g, const double *src_cell, double *psi, double psi_b, const jsweep_params *p,
+                    hipStream_t s);
 
 // batched sweep over an ensemble of graphs: one workgroup per
 // (instance, direction), one launch (sweep.hip)

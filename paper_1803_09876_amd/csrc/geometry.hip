@@ -5,6 +5,7 @@
 // library is compiled without floating-point contraction), so the face
 // areas, and therefore the upwind signs Omega . S that define the sweep
 // graph, are a pure function of the input coordinates.
+#include <algorithm>
 #include <cstring>
 
 #include <rocprim/device/device_radix_sort.hpp>
@@ -277,6 +278,47 @@ __global__ void k_cell_records(const double *coords, const int64_t *cells, const
     vol[K] = V;
 }
 
+// Morton code of every cell's vertex average on a 2^21 grid per axis over
+// the mesh's bounding box (lo, 1 / extent), with the cell id as the value:
+// sorted, it gives the space-filling-curve order the sweep patches are cut
+// from.
+__device__ inline uint64_t spread3(uint64_t x) {
+    x &= 0x1fffffull;
+    x = (x | x << 32) & 0x1f00000000ffffull;
+    x = (x | x << 16) & 0x1f0000ff0000ffull;
+    x = (x | x << 8) & 0x100f00f00f00f00full;
+    x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+    x = (x | x << 2) & 0x1249249249249249ull;
+    return x;
+}
+
+template <int CT>
+__global__ void k_cell_morton(const double *coords, const int64_t *cells, int64_t nc, double lx, double ly,
+                              double lz, double sx, double sy, double sz, uint64_t *keys, int32_t *vals) {
+    constexpr int DIM = CT == JSWEEP_TRI ? 2 : 3;
+    int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (K >= nc) return;
+    double c[3] = {0.0, 0.0, 0.0};
+    for (int v = 0; v < CT; ++v) {
+        const int64_t p = cells[K * CT + v];
+        for (int d = 0; d < DIM; ++d) c[d] += coords[p * DIM + d];
+    }
+    const double lo[3] = {lx, ly, lz}, sc[3] = {sx, sy, sz};
+    uint64_t q[3] = {0, 0, 0};
+    for (int d = 0; d < DIM; ++d) {
+        double t = (c[d] / CT - lo[d]) * sc[d];
+        t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+        q[d] = (uint64_t)(t * 2097151.0);
+    }
+    keys[K] = spread3(q[0]) << 2 | spread3(q[1]) << 1 | spread3(q[2]);
+    vals[K] = (int32_t)K;
+}
+
+__global__ void k_rank_of(const int32_t *order, int64_t nc, int32_t *rank) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nc) rank[order[i]] = (int32_t)i;
+}
+
 template <int CT>
 static void geometry_impl(Graph &g, const jsweep_mesh &mesh, hipStream_t s) {
     constexpr int NF = faces_of(CT);
@@ -340,6 +382,31 @@ static void geometry_impl(Graph &g, const jsweep_mesh &mesh, hipStream_t s) {
     JSW_HIP(hipStreamSynchronize(s));
     if (herr & kErrVolume) fail(JSWEEP_E_MESH, "a cell has a non-positive volume");
     if (herr) fail(JSWEEP_E_MESH, "invalid mesh");
+    // Morton rank of every cell (patches of the patch sweep)
+    double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
+    for (int d = 0; d < DIM; ++d) { lo[d] = mesh.coords[d]; hi[d] = mesh.coords[d]; }
+    for (int64_t i = 0; i < nv; ++i)
+        for (int d = 0; d < DIM; ++d) {
+            lo[d] = std::min(lo[d], mesh.coords[i * DIM + d]);
+            hi[d] = std::max(hi[d], mesh.coords[i * DIM + d]);
+        }
+    double sc[3] = {0.0, 0.0, 0.0};
+    for (int d = 0; d < DIM; ++d) sc[d] = hi[d] > lo[d] ? 1.0 / (hi[d] - lo[d]) : 0.0;
+    DevBuf mk(8 * nc), mk2(8 * nc), mv(4 * nc), mv2(4 * nc);
+    k_cell_morton<CT><<<(int)ceil_div(nc, B), B, 0, s>>>(d_coords.as<double>(), d_cells.as<int64_t>(), nc, lo[0],
+                                                         lo[1], lo[2], sc[0], sc[1], sc[2], mk.as<uint64_t>(),
+                                                         mv.as<int32_t>());
+    JSW_HIP(hipGetLastError());
+    size_t mt_bytes = 0;
+    JSW_HIP(rocprim::radix_sort_pairs(nullptr, mt_bytes, mk.as<uint64_t>(), mk2.as<uint64_t>(), mv.as<int32_t>(),
+                                      mv2.as<int32_t>(), (size_t)nc, 0u, 63u, s));
+    DevBuf mt(mt_bytes + 16);
+    JSW_HIP(rocprim::radix_sort_pairs(mt.p, mt_bytes, mk.as<uint64_t>(), mk2.as<uint64_t>(), mv.as<int32_t>(),
+                                      mv2.as<int32_t>(), (size_t)nc, 0u, 63u, s));
+    g.mrank.alloc(4 * nc);
+    k_rank_of<<<(int)ceil_div(nc, B), B, 0, s>>>(mv2.as<int32_t>(), nc, g.mrank.as<int32_t>());
+    JSW_HIP(hipGetLastError());
+    JSW_HIP(hipStreamSynchronize(s));
 }
 
 void build_geometry(Graph &g, const jsweep_mesh &mesh, hipStream_t s) {

@@ -115,7 +115,7 @@ void refresh_sigma(Graph &g, const double *sigma_t, bool fp32, hipStream_t s) {
     int32_t changed = 0;
     JSW_HIP(hipMemcpyAsync(&changed, flag, 4, hipMemcpyDeviceToHost, s));
     JSW_HIP(hipStreamSynchronize(s));
-    if (changed) g.den64_ok = g.den32_ok = false;
+    if (changed) g.den64_ok = g.den32_ok = g.pp.den64_ok = false;
     ensure_den(g, fp32, s);
 }
 

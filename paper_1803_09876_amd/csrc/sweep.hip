@@ -480,6 +480,7 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
     a.epoch = (uint32_t)g.epoch;
     a.watchdog_ticks = watchdog_ticks();
     a.stamps = g.trace ? g.trace_buf.as<uint32_t>() : nullptr;
+    if (g.trace) g.trace_units = 0;
     {
         const char *e = std::getenv("JSWEEP_POLL_NAP");
         a.nap = e ? (uint32_t)std::max(1, std::atoi(e)) : 2u;
@@ -850,7 +851,7 @@ static void launch_ring(Graph &g, const Real *src_cell, const float *src_dir, Re
 //   every direction in flight.
 int sweep_strategy(const Graph &g, const jsweep_params *p) {
     int st = (p && p->strategy > 0) ? p->strategy : (g.has_tuned && g.tuned.strategy > 0 ? g.tuned.strategy : 0);
-    if (st == JSWEEP_STRATEGY_DATA_DRIVEN || st == JSWEEP_STRATEGY_DIRECTION) return st;
+    if (st == JSWEEP_STRATEGY_DATA_DRIVEN || st == JSWEEP_STRATEGY_DIRECTION || st == JSWEEP_STRATEGY_PATCH) return st;
     if (st == JSWEEP_STRATEGY_DIRECTION_LDS) return ring_items(g, false) ? st : JSWEEP_STRATEGY_DIRECTION;
     const bool small = g.nc * g.nd <= (int64_t)2000000;
     if (ring_items(g, false) && small) return JSWEEP_STRATEGY_DIRECTION_LDS;
@@ -861,6 +862,12 @@ template <class Real, int NF, int DIM>
 static void launch_impl(Graph &g, const Real *src_cell, const float *src_dir, Real *psi, Real psi_b,
                         const jsweep_params *p, hipStream_t s) {
     const int st = sweep_strategy(g, p);
+    if constexpr (sizeof(Real) == 8) {
+        if (st == JSWEEP_STRATEGY_PATCH && patch_ready(g, s)) {
+            launch_patch64(g, src_cell, psi, psi_b, p, s);
+            return;
+        }
+    }
     if (st == JSWEEP_STRATEGY_DIRECTION_LDS && ring_items(g, sizeof(Real) == 4)) launch_ring<Real>(g, src_cell, src_dir, psi, psi_b, s);
     else if (st == JSWEEP_STRATEGY_DIRECTION || st == JSWEEP_STRATEGY_DIRECTION_LDS)
         launch_dir<Real, NF, DIM>(g, src_cell, src_dir, psi, psi_b, p, s);
@@ -887,9 +894,11 @@ int check_sweep_status(Graph &g, hipStream_t s) {
     if (st == 0) return JSWEEP_OK;
     // a stalled sweep leaves flags in an unknown state: start over
     JSW_HIP(hipMemsetAsync(g.cflag.p, 0, g.cflag.bytes, s));
+    if (g.pp.flag.p) JSW_HIP(hipMemsetAsync(g.pp.flag.p, 0, g.pp.flag.bytes, s));
     JSW_HIP(hipMemsetAsync(g.status.p, 0, 64, s));
     JSW_HIP(hipStreamSynchronize(s));
     g.epoch = 0;
+    g.pp.epoch = 0;
     return JSWEEP_E_STALLED;
 }
 

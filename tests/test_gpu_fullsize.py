@@ -35,8 +35,12 @@ def test_hex64_s8_full(oracle_mod):
     got = psi.cpu().numpy()
     print(f"[hex64] sweep rel {rel_max(got, ref):.2e} bitexact {np.array_equal(got, ref)}", flush=True)
     assert rel_max(got, ref) <= 1e-12
+    info = J.patch_info(gg)
+    print(f"[hex64] patch program {info}", flush=True)
+    assert info["available"]
     psi_ref, phi_ref, _ = og.source_iteration(p.sigma_t, p.sigma_s, p.q, p.weight, 3)
-    for strategy in (J.JSWEEP_STRATEGY_AUTO, J.JSWEEP_STRATEGY_DATA_DRIVEN, J.JSWEEP_STRATEGY_DIRECTION_LDS):
+    for strategy in (J.JSWEEP_STRATEGY_AUTO, J.JSWEEP_STRATEGY_DATA_DRIVEN, J.JSWEEP_STRATEGY_DIRECTION_LDS,
+                     J.JSWEEP_STRATEGY_PATCH):
         phi = dev(np.zeros(p.n_cells))
         psi = dev(np.zeros((p.n_dirs, p.n_cells)))
         J.solve(gg, dev(p.sigma_t), dev(p.sigma_s), dev(p.q), phi, psi, mode=J.JSWEEP_FP64, tol=0.0, max_iter=3,

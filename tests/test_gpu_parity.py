@@ -77,8 +77,34 @@ def test_fp64_sweep_deterministic(cases):
     assert torch.equal(a, b)
 
 
+def test_patch_program_and_sweep(cases):
+    """PATCH strategy: its program applies to every case (bands where a
+    direction's patch graph has a cycle), and one FP64 sweep with boundary
+    inflow and a lagged previous iterate matches the oracle."""
+    for name, p, og, gg in cases:
+        info = J.patch_info(gg)
+        print(f"[patch] {name} {info}", flush=True)
+        assert info["available"], name
+        assert info["tasks"] >= p.n_dirs and info["rounds"] >= info["tasks"]
+        J.set_params(gg, J.Params(strategy=J.JSWEEP_STRATEGY_PATCH))
+        try:
+            rng = np.random.default_rng(7)
+            src = rng.uniform(0.0, 2.0, p.n_cells)
+            prev = rng.uniform(0.0, 1.0, (p.n_dirs, p.n_cells))
+            ref = og.sweep(p.sigma_t, src, 0.25, prev)
+            for rep in range(2):
+                psi = dev(prev)
+                J.sweep(gg, dev(p.sigma_t), dev(src), psi, psi_boundary=0.25)
+                got = host(psi)
+                err = rel_max(got, ref)
+                print(f"[patch sweep64] {name} rep {rep} rel {err:.3e} bitexact {np.array_equal(got, ref)}", flush=True)
+                assert err <= 1e-12, name
+        finally:
+            J.set_params(gg, None)
+
+
 @pytest.mark.parametrize("strategy", [J.JSWEEP_STRATEGY_DATA_DRIVEN, J.JSWEEP_STRATEGY_DIRECTION,
-                                      J.JSWEEP_STRATEGY_DIRECTION_LDS])
+                                      J.JSWEEP_STRATEGY_DIRECTION_LDS, J.JSWEEP_STRATEGY_PATCH])
 def test_fp64_source_iteration_20(cases, strategy):
     for name, p, og, gg in cases:
         psi_ref, phi_ref, hist = og.source_iteration(p.sigma_t, p.sigma_s, p.q, p.weight, 20)
