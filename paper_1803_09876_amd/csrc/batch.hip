@@ -673,6 +673,8 @@ int autotune(int32_t n, Graph *const *graphs, int32_t mode, jsweep_params *out) 
         if (sweep_strategy(*graphs[0], nullptr) == JSWEEP_STRATEGY_DIRECTION_LDS ||
             sweep_strategy(*graphs[0], &ring_probe) == JSWEEP_STRATEGY_DIRECTION_LDS)
             cands.push_back(ring_probe);
+        // the patch-task kernel (FP64 sweeps only), where its program applies
+        if (!fp32 && patch_ready(*graphs[0], s)) cands.push_back(jsweep_params{1, 0, 0, 0, JSWEEP_STRATEGY_PATCH, 0});
     } else {
         for (int w : {1, 2, 4, 8, 16}) cands.push_back(jsweep_params{w, 0, 0, 0, JSWEEP_STRATEGY_DIRECTION, 0});
         cands.push_back(ring_probe);

@@ -116,10 +116,10 @@ constexpr int kStreams = 8;
 // first, then its halo), -1 boundary, kNoFace empty.  A halo entry >= 0 is
 // an upwind position of another task of the direction, < 0 the lagged edge
 // -(h + 1).
-constexpr int kPatchSlots = 1024;        // task vertices + halo entries
-constexpr int kPatchCells = 512;         // vertices of a task
-constexpr int kPatchHalo = 512;          // halo entries of a task
-constexpr int kPatchRounds = 128;        // rounds of a task
+constexpr int kPatchSlots = 512;         // task vertices + halo entries
+constexpr int kPatchCells = 256;         // vertices of a task
+constexpr int kPatchHalo = 256;          // halo entries of a task
+constexpr int kPatchRounds = 64;         // rounds of a task
 constexpr int kPatchDesc = 16;           // descriptor words per task
 struct PatchProg {
     bool built = false, ok = false;      // ok: every task fits the limits above

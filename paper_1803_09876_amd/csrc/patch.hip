@@ -8,7 +8,8 @@
 // turn waits on it is computed in several goes), and the visits are fixed
 // here ahead of the sweep by running the direction's graph sequentially on
 // the host: the patch holding the lowest-level ready cell runs next, as far
-// as it can go (every cell of it that becomes ready is taken along).  Cells
+// as it can go (every cell of it that becomes ready is taken along, in level
+// order, until the kernel's rounds or halo budget is reached).  Cells
 // of one visit form a task; visits in that order are a topological order of
 // the task graph, so it is acyclic.  A task's vertices run on one wavefront,
 // level by level (rounds of at most 64 vertices), with the fluxes of the task
@@ -23,6 +24,8 @@
 #include <algorithm>
 #include <atomic>
 #include <climits>
+#include <functional>
+#include <queue>
 #include <cstdlib>
 #include <thread>
 #include <vector>
@@ -38,7 +41,6 @@ namespace jsw {
 namespace {
 
 constexpr int kB = 256;
-constexpr int kHaloPerLane = kPatchHalo / 64;
 
 unsigned blocks_for(int64_t n) { return (unsigned)std::max<int64_t>(1, ceil_div(n, kB)); }
 
@@ -366,7 +368,9 @@ std::vector<T> to_host(const DevBuf &b, int64_t n, hipStream_t s) {
     return h;
 }
 
-int patch_cells(int ctype) { return ctype == JSWEEP_HEX ? 512 : ctype == JSWEEP_TET ? 384 : 256; }
+// cells per patch: Morton runs of whole lattice blocks where the mesh is a
+// lattice (4 x 8 x 8 hexahedra, 32 cubes of 6 tetrahedra)
+int patch_cells(int ctype) { return ctype == JSWEEP_HEX ? 256 : ctype == JSWEEP_TET ? 192 : 128; }
 
 // Visits of one direction's patches (see the top of the file): up[v * ns +
 // k] are v's upwind cells (-1 past the last), lev the levels, patch the
@@ -394,7 +398,7 @@ void visits(int64_t nc, int ns, const int32_t *up, const int32_t *lev, const int
             }
     }
     // ready cells per patch (linked lists) and their lowest level
-    std::vector<int32_t> head(npatch, -1), nxt(nc, -1), cnt(npatch, 0), minlev(npatch, INT32_MAX), stack;
+    std::vector<int32_t> head(npatch, -1), nxt(nc, -1), cnt(npatch, 0), minlev(npatch, INT32_MAX);
     auto push = [&](int32_t w) {
         const int32_t p = patch[w];
         nxt[w] = head[p];
@@ -404,7 +408,12 @@ void visits(int64_t nc, int ns, const int32_t *up, const int32_t *lev, const int
     };
     for (int64_t v = 0; v < nc; ++v)
         if (indeg[v] == 0) push((int32_t)v);
-    stack.reserve(1024);
+    // a visit takes its ready cells in level order and stops before it
+    // would exceed the kernel's rounds or halo budget (halo counted as
+    // upwind references from outside the visit; lagged edges, which are not
+    // in up, get the last quarter of the budget)
+    std::priority_queue<std::pair<int32_t, int32_t>, std::vector<std::pair<int32_t, int32_t>>, std::greater<>> pq;
+    std::fill(visit, visit + nc, UINT32_MAX);
     int64_t done = 0;
     uint32_t nv = 0;
     while (done < nc) {
@@ -412,23 +421,39 @@ void visits(int64_t nc, int ns, const int32_t *up, const int32_t *lev, const int
         for (int32_t p = 0; p < npatch; ++p)
             if (cnt[p] && (best < 0 || minlev[p] < minlev[best])) best = p;
         const uint32_t t = nv++;
-        stack.clear();
-        for (int32_t v = head[best]; v >= 0; v = nxt[v]) stack.push_back(v);
+        for (int32_t v = head[best]; v >= 0; v = nxt[v]) pq.push({lev[v], v});
         head[best] = -1;
         cnt[best] = 0;
         minlev[best] = INT32_MAX;
-        while (!stack.empty()) {
-            const int32_t v = stack.back();
-            stack.pop_back();
+        int rounds = 0, cur_lev = -1, cur_cnt = 0, ext = 0;
+        while (!pq.empty()) {
+            const int32_t l = pq.top().first, v = pq.top().second;
+            const int add = (l != cur_lev || cur_cnt % 64 == 0) ? 1 : 0;
+            int ev = 0;
+            for (int k = 0; k < ns; ++k) {
+                const int32_t u = up[v * ns + k];
+                if (u < 0) break;
+                ev += visit[u] != t;
+            }
+            if (rounds + add > kPatchRounds || ext + ev > kPatchHalo * 3 / 4) break;
+            pq.pop();
             visit[v] = t;
             ++done;
+            rounds += add;
+            if (l != cur_lev) { cur_lev = l; cur_cnt = 0; }
+            ++cur_cnt;
+            ext += ev;
             for (int32_t k = dptr[v]; k < dptr[v + 1]; ++k) {
                 const int32_t w = dn[k];
                 if (--indeg[w] == 0) {
-                    if (patch[w] == best) stack.push_back(w);
+                    if (patch[w] == best) pq.push({lev[w], w});
                     else push(w);
                 }
             }
+        }
+        while (!pq.empty()) {
+            push(pq.top().second);
+            pq.pop();
         }
     }
     // depth: visits were made in a topological order of the task graph
@@ -700,62 +725,23 @@ struct PatchArgs {
     uint32_t *stamps;   // per task: taken, upstream complete, published (s_memrealtime), or null
 };
 
-template <int NS>
-struct PRound {
-    int32_t code[NS];
-    double af[NS];
-    double den;
-};
-
 template <class T>
 __device__ __forceinline__ T ld_agent(const T *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// program of round r, branch free: rounds past the last and lanes past a
-// round's count load an entry of the task that exists (and is not used), so
-// the loads carry no control flow and the compiler's wait counting stays
-// exact across the rounds
-template <int NS>
-__device__ __forceinline__ void pp_fetch(const PatchArgs &a, int64_t qa, const int32_t *srnd, int r, int nr,
-                                         PRound<NS> &p) {
-    const int32_t rd = srnd[min(r, nr - 1)];
-    const int off = rd & 0xffff, cnt = (rd >> 16) + 1;
-    const int64_t q = qa + off + min((int)threadIdx.x, cnt - 1);
-#pragma unroll
-    for (int j = 0; j < NS; ++j) {
-        p.code[j] = a.code[(int64_t)j * a.N + q];
-        p.af[j] = a.pa[(int64_t)j * a.N + q];
-    }
-    p.den = a.pden[q];
-}
+// LDS code of an inflow slot: an LDS slot, the boundary or no face
+constexpr uint16_t kLdsBoundary = 0xffff, kLdsNoFace = 0xfffe;
 
-// One load per 128-byte line of the task's program (its positions are
-// contiguous in every program array), so that the rounds' loads find it in
-// L2; returns a value the caller keeps live.
+// NS: inflow slots per vertex
 template <int NS>
-__device__ __forceinline__ uint32_t pp_touch(const PatchArgs &a, int64_t qa, int n) {
-    const int lane = threadIdx.x;
-    uint32_t acc = 0;
-    const int nl4 = (n + 31) / 32;     // lines of an int32 array
-    const int nl8 = (n + 15) / 16;     // lines of a double array
-    const int64_t q0 = qa & ~(int64_t)31;
-    for (int j = 0; j < NS; ++j) {
-        for (int k = lane; k < nl4; k += 64) acc += (uint32_t)a.code[(int64_t)j * a.N + q0 + 32 * k];
-        for (int k = lane; k < nl8; k += 64)
-            acc += (uint32_t)reinterpret_cast<const uint32_t *>(a.pa + (int64_t)j * a.N + (qa & ~(int64_t)15) + 16 * k)[0];
-    }
-    for (int k = lane; k < nl8; k += 64)
-        acc += reinterpret_cast<const uint32_t *>(a.pden + (qa & ~(int64_t)15) + 16 * k)[0];
-    return acc;
-}
-
-// NS: inflow slots per vertex; D: rounds whose program is in flight ahead
-template <int NS, int D>
 __global__ void __launch_bounds__(64) k_sweep_patch(PatchArgs a) {
-    constexpr int kCL = kPatchCells / 64, kRL = kPatchRounds / 64;
+    constexpr int kCL = kPatchCells / 64, kHL = kPatchHalo / 64;
     __shared__ double sv[kPatchSlots];         // fluxes: the task's vertices, then its halo
     __shared__ double svs[kPatchCells];        // V s of the task's vertices
+    __shared__ double sden[kPatchCells];
+    __shared__ double sa[NS][kPatchCells];
+    __shared__ uint16_t scode[NS][kPatchCells];
     __shared__ int32_t scell[kPatchCells];
     __shared__ int32_t srnd[kPatchRounds];
     const int lane = threadIdx.x;
@@ -764,7 +750,6 @@ __global__ void __launch_bounds__(64) k_sweep_patch(PatchArgs a) {
     const int64_t per_stream = a.stream_off[stream + 1] - first;
     const uint8_t epoch = (uint8_t)a.epoch;
     uint32_t *ticket = a.tickets + 32 * stream;
-    uint32_t keep = 0;
     while (true) {
         uint32_t tk = 0;
         if (lane == 0) tk = atomicAdd(ticket, 1u);
@@ -779,34 +764,48 @@ __global__ void __launch_bounds__(64) k_sweep_patch(PatchArgs a) {
         const int h0 = __builtin_amdgcn_readlane(w, 6), ndep = __builtin_amdgcn_readlane(w, 7);
         const int d0 = __builtin_amdgcn_readlane(w, 8);
         const int64_t base = (int64_t)m * a.nc, qa = base + q0;
-        // the task's vertices, rounds and halo list: all loads issued
-        // together, then written to LDS
-        int32_t cl[kCL], rl[kRL], hsrc[kHaloPerLane];
+        // the whole task program into LDS while the upstream tasks finish:
+        // all loads issued together (positions of a task are contiguous)
+        {
+            int32_t cl[kCL], cd[NS][kCL];
+            double af[NS][kCL], dn[kCL];
 #pragma unroll
-        for (int k = 0; k < kCL; ++k) cl[k] = lane + 64 * k < n ? a.cell[qa + lane + 64 * k] : 0;
+            for (int k = 0; k < kCL; ++k) {
+                const bool in = lane + 64 * k < n;
+                const int64_t q = qa + (in ? lane + 64 * k : 0);
+                cl[k] = a.cell[q];
 #pragma unroll
-        for (int k = 0; k < kRL; ++k) rl[k] = lane + 64 * k < nr ? a.round[r0 + lane + 64 * k] : 0;
-#pragma unroll
-        for (int k = 0; k < kHaloPerLane; ++k) hsrc[k] = lane + 64 * k < nh ? a.halo[h0 + lane + 64 * k] : 0;
-        // V s of the vertices, and the task's program pulled into L2
-        double vl[kCL];
-#pragma unroll
-        for (int k = 0; k < kCL; ++k) vl[k] = lane + 64 * k < n ? a.vs[cl[k]] : 0.0;
-        keep += pp_touch<NS>(a, qa, n);
-#pragma unroll
-        for (int k = 0; k < kCL; ++k)
-            if (lane + 64 * k < n) {
-                scell[lane + 64 * k] = cl[k];
-                svs[lane + 64 * k] = vl[k];
+                for (int j = 0; j < NS; ++j) {
+                    cd[j][k] = a.code[(int64_t)j * a.N + q];
+                    af[j][k] = a.pa[(int64_t)j * a.N + q];
+                }
+                dn[k] = a.pden[q];
             }
+            const int32_t rl = lane < nr ? a.round[r0 + lane] : 0;
+            double vl[kCL];
 #pragma unroll
-        for (int k = 0; k < kRL; ++k)
-            if (lane + 64 * k < nr) srnd[lane + 64 * k] = rl[k];
+            for (int k = 0; k < kCL; ++k) vl[k] = a.vs[cl[k]];
+#pragma unroll
+            for (int k = 0; k < kCL; ++k) {
+                const int i = lane + 64 * k;
+                if (i < n) {
+                    scell[i] = cl[k];
+                    svs[i] = vl[k];
+                    sden[i] = dn[k];
+#pragma unroll
+                    for (int j = 0; j < NS; ++j) {
+                        const int32_t c = cd[j][k];
+                        scode[j][i] = c >= 0 ? (uint16_t)c : c == -1 ? kLdsBoundary : kLdsNoFace;
+                        sa[j][i] = af[j][k];
+                    }
+                }
+            }
+            if (lane < nr) srnd[lane] = rl;
+        }
+        int32_t hsrc[kHL];
+#pragma unroll
+        for (int k = 0; k < kHL; ++k) hsrc[k] = lane + 64 * k < nh ? a.halo[h0 + lane + 64 * k] : 0;
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        // program of the first rounds, fetched while the upstream tasks finish
-        PRound<NS> pr[D];
-#pragma unroll
-        for (int d = 0; d < D; ++d) pp_fetch<NS>(a, qa, srnd, d, nr, pr[d]);
         // wait until every upstream task of this sweep is complete
         uint64_t t0 = 0;
         for (uint32_t spin = 0;; ++spin) {
@@ -827,47 +826,57 @@ __global__ void __launch_bounds__(64) k_sweep_patch(PatchArgs a) {
         const uint32_t t_ready = (uint32_t)__builtin_amdgcn_s_memrealtime();
         // halo fluxes into LDS (all loads first)
         {
-            double hv[kHaloPerLane];
+            double hv[kHL];
 #pragma unroll
-            for (int k = 0; k < kHaloPerLane; ++k) {
+            for (int k = 0; k < kHL; ++k) {
                 const int32_t src = hsrc[k];
                 hv[k] = lane + 64 * k >= nh ? 0.0
                         : src >= 0      ? ld_agent(a.ppsi + base + src)
                                         : a.lag_val[-(int64_t)src - 1];
             }
 #pragma unroll
-            for (int k = 0; k < kHaloPerLane; ++k)
+            for (int k = 0; k < kHL; ++k)
                 if (lane + 64 * k < nh) sv[n + lane + 64 * k] = hv[k];
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        // rounds: round r computes from pr[r % D], which is then refilled
-        // with the program of round r + D (in place: no register copies, so
-        // no wait on the loads in flight)
-        for (int rb = 0; rb < nr; rb += D) {
+        // rounds, out of LDS only; the next round's program is read while
+        // the current one computes (it does not depend on the fluxes)
+        {
+            struct Rd {
+                uint16_t c[NS];
+                double af[NS], den, num0;
+                int i, cnt;
+            };
+            auto read_round = [&](int r, Rd &x) {
+                const int32_t rd = srnd[r];
+                x.cnt = (rd >> 16) + 1;
+                x.i = (rd & 0xffff) + min(lane, x.cnt - 1);
 #pragma unroll
-            for (int d = 0; d < D; ++d) {
-                const int r = rb + d;
-                if (r < nr) {
-                    const int32_t rd = srnd[r];
-                    const int off = rd & 0xffff, cnt = (rd >> 16) + 1;
-                    const int i = off + min(lane, cnt - 1);
-                    // every upwind read issued before the first use
-                    double vv[NS];
-#pragma unroll
-                    for (int j = 0; j < NS; ++j) vv[j] = sv[max(pr[d].code[j], 0)];
-                    double num = svs[i];
-#pragma unroll
-                    for (int j = 0; j < NS; ++j) {
-                        const int32_t cd = pr[d].code[j];
-                        const double v = cd >= 0 ? vv[j] : a.psi_b;
-                        const double acc = num + pr[d].af[j] * v;
-                        num = cd != kNoFace ? acc : num;
-                    }
-                    const double res = num / pr[d].den;
-                    if (lane < cnt) sv[i] = res;
-                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                for (int j = 0; j < NS; ++j) {
+                    x.c[j] = scode[j][x.i];
+                    x.af[j] = sa[j][x.i];
                 }
-                pp_fetch<NS>(a, qa, srnd, r + D, nr, pr[d]);
+                x.den = sden[x.i];
+                x.num0 = svs[x.i];
+            };
+            Rd cur, nxt;
+            read_round(0, cur);
+            for (int r = 0; r < nr; ++r) {
+                double vv[NS];
+#pragma unroll
+                for (int j = 0; j < NS; ++j) vv[j] = sv[cur.c[j] < kLdsNoFace ? cur.c[j] : 0];
+                read_round(min(r + 1, nr - 1), nxt);
+                double num = cur.num0;
+#pragma unroll
+                for (int j = 0; j < NS; ++j) {
+                    const double v = cur.c[j] == kLdsBoundary ? a.psi_b : vv[j];
+                    const double acc = num + cur.af[j] * v;
+                    num = cur.c[j] != kLdsNoFace ? acc : num;
+                }
+                const double res = num / cur.den;
+                if (lane < cur.cnt) sv[cur.i] = res;
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                cur = nxt;
             }
         }
         // publish: fluxes by position, then the flag, then the cell-order copy
@@ -882,14 +891,11 @@ __global__ void __launch_bounds__(64) k_sweep_patch(PatchArgs a) {
             a.stamps[3 * t + 2] = (uint32_t)__builtin_amdgcn_s_memrealtime();
         }
     }
-    // the prefetch loads' sum is never 0xffffffff together with epoch 0
-    if (keep == 0xffffffffu && a.epoch == 0u) a.status[2] = 1;
 }
 
-// rounds in flight ahead: fewer for more inflow slots (register budget)
 template <int NS>
 const void *patch_kernel_ns() {
-    return reinterpret_cast<const void *>(&k_sweep_patch<NS, NS <= 3 ? 4 : 2>);
+    return reinterpret_cast<const void *>(&k_sweep_patch<NS>);
 }
 
 const void *patch_kernel(int ns) {

@@ -67,7 +67,7 @@ def test_autotune_and_tuned_solve(ensemble):
     prm = J.autotune([g], J.JSWEEP_FP64)
     d = prm.as_dict()
     assert d["strategy"] in (J.JSWEEP_STRATEGY_DATA_DRIVEN, J.JSWEEP_STRATEGY_DIRECTION,
-                             J.JSWEEP_STRATEGY_DIRECTION_LDS)
+                             J.JSWEEP_STRATEGY_DIRECTION_LDS, J.JSWEEP_STRATEGY_PATCH)
     assert d["strategy"] == J.JSWEEP_STRATEGY_DIRECTION_LDS or d["waves_per_block"] >= 1
     phi = dev(np.zeros(p.n_cells))
     J.solve(g, dev(p.sigma_t), dev(p.sigma_s), dev(p.q), phi, mode=J.JSWEEP_FP64, tol=0.0, max_iter=5,
