@@ -222,6 +222,8 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--steps-only", action="store_true")
+    ap.add_argument("--ensemble-only", action="store_true",
+                    help="only the 256-instance batched solve (for profiling the batch kernels)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the sweep path of this "
@@ -242,6 +244,10 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         del x, y
+    if args.ensemble_only:
+        ens = ensemble_bench(J, W, torch, steps=max(1, args.steps))
+        print(json.dumps({"ensemble": ens}))
+        return
     p = W.config(2)
     nc, nd = p.n_cells, p.n_dirs
     t = time.time()
