@@ -103,6 +103,33 @@ def test_patch_program_and_sweep(cases):
             J.set_params(gg, None)
 
 
+@pytest.mark.parametrize("strategy", [J.JSWEEP_STRATEGY_DATA_DRIVEN, J.JSWEEP_STRATEGY_PATCH])
+def test_sweep_trace_respects_dependencies(cases, strategy):
+    """Trace of one sweep (work-list chunks, or PATCH tasks): every unit
+    became ready only after each of its upstream units had become ready and
+    published, stamps are ordered taken <= ready <= done, and the units
+    cover every (cell, direction) once."""
+    for name, p, og, gg in cases[:3]:
+        J.set_params(gg, J.Params(strategy=strategy))
+        try:
+            J.jsweep_trace(gg, True)
+            psi = dev(np.zeros((p.n_dirs, p.n_cells)))
+            J.sweep(gg, dev(p.sigma_t), dev(p.q), psi)
+            tr = J.jsweep_trace_read(gg)
+        finally:
+            J.jsweep_trace(gg, False)
+            J.set_params(gg, None)
+        x0 = int(tr["take"].min())
+        take, ready, done = ((tr[k] - x0) % (1 << 32) for k in ("take", "ready", "done"))
+        n = len(take)
+        ptr, deps = tr["deps_ptr"], tr["deps"]
+        down = np.repeat(np.arange(n), np.diff(ptr))
+        print(f"[trace s{strategy}] {name} units {n} deps {len(deps)} span {(done.max()) / 100:.1f} us", flush=True)
+        assert (take <= ready).all() and (ready <= done).all(), name
+        assert int(tr["count"].sum()) == p.n_cells * p.n_dirs, name
+        assert len(deps) == 0 or (ready[deps] < ready[down]).all(), name
+
+
 @pytest.mark.parametrize("strategy", [J.JSWEEP_STRATEGY_DATA_DRIVEN, J.JSWEEP_STRATEGY_DIRECTION,
                                       J.JSWEEP_STRATEGY_DIRECTION_LDS, J.JSWEEP_STRATEGY_PATCH])
 def test_fp64_source_iteration_20(cases, strategy):
@@ -120,7 +147,7 @@ def test_fp64_source_iteration_20(cases, strategy):
 
 
 @pytest.mark.parametrize("strategy", [J.JSWEEP_STRATEGY_DATA_DRIVEN, J.JSWEEP_STRATEGY_DIRECTION,
-                                      J.JSWEEP_STRATEGY_DIRECTION_LDS])
+                                      J.JSWEEP_STRATEGY_DIRECTION_LDS, J.JSWEEP_STRATEGY_PATCH])
 def test_fp32_refined_converges_to_oracle(cases, strategy):
     for name, p, og, gg in cases:
         if p.n_cells * p.n_dirs > 2_000_000:
