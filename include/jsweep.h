@@ -113,13 +113,14 @@ typedef struct jsweep_graph_s *jsweep_graph;   /* opaque, owned by the library *
  * PATCH: the paper's patch-program form (Sec. V-A, V-B): cells are cut into
  *   spatial patches (Morton order of the cell centres); one wavefront runs a
  *   patch of one direction as a task, its vertices level by level out of
- *   LDS, after the upstream tasks have completed; tasks are scheduled data
- *   driven as in DATA_DRIVEN.  The paper's patch programs are re-entrant: a
- *   patch whose cells and another patch's wait on each other is computed
- *   in several visits.  The visits are fixed when the program is built, by
- *   running each direction's graph patch by patch on the host (the patch
- *   with the lowest-level ready cell next, as far as it goes); each visit
- *   is a task, and the task graph is acyclic.  The program is built on the
+ *   LDS.  The paper's patch programs are re-entrant: a patch whose cells and
+ *   another patch's wait on each other is computed in several visits.  The
+ *   visits are fixed when the program is built, by running each direction's
+ *   graph patch by patch on the host (the patch with the lowest-level ready
+ *   cell next, as far as the kernel's per-task budget allows); each visit is
+ *   a task, and the task graph is acyclic.  A task enters its stream's
+ *   ready queue when the last of its upstream tasks completes, and
+ *   wavefronts take tasks from the queues.  The program is built on the
  *   first PATCH sweep; FP64 sweeps only (FP32 sweeps use DATA_DRIVEN);
  *   graphs above 2^26 (cell, direction) pairs or whose tasks exceed the
  *   kernel's LDS limits fall back to DATA_DRIVEN. */

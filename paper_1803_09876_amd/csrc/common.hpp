@@ -129,7 +129,8 @@ struct PatchProg {
     int64_t revisits = 0;                // visits beyond one per (patch, direction)
     std::vector<int64_t> stream_off_h;
     DevBuf stream_off;                   // [kStreams + 1] int64 task offsets of the streams
-    DevBuf desc;                         // [n_tasks * kPatchDesc] int32: q0, m, n, rounds, round0, halo, halo0, deps, dep0
+    DevBuf desc;                         // [n_tasks * kPatchDesc] int32: q0, m, n, rounds, round0, halo, halo0,
+                                         //   deps, dep0, downstream tasks, down0
     DevBuf round;                        // [n_rounds] int32 offset in the task | (count - 1) << 16
     DevBuf halo;                         // [n_halo] int32
     DevBuf dep;                          // [n_dep] int32 upstream tasks
@@ -139,7 +140,11 @@ struct PatchProg {
     DevBuf den64;                        // [nd*nc] double
     bool den64_ok = false;
     DevBuf psi;                          // [nd*nc] double fluxes by position (halo source)
-    DevBuf flag;                         // [n_tasks] uint8 completion epochs
+    DevBuf down;                         // [n_dep] int32 downstream tasks (ranges in the descriptors)
+    DevBuf cnt;                          // [n_tasks] int32 upstream tasks not yet complete
+    DevBuf slot;                         // [n_tasks] uint32 ready queues, stream by stream
+    DevBuf qctl;                         // [32 * kStreams] uint32 queue heads and tails
+    DevBuf nsrc;                         // [kStreams] int32 tasks without upstream tasks
     int epoch = 0;
 };
 

@@ -316,9 +316,6 @@ __global__ void k_pp_vs(const double *vol, const double *src, int64_t nc, double
     if (K < nc) vs[K] = src ? vol[K] * src[K] : vol[K] * 0.0;
 }
 
-__global__ void k_pp_reset_tickets(uint32_t *t) {
-    if (threadIdx.x < kStreams) t[32 * threadIdx.x] = 0u;
-}
 
 // sort keys (optionally with values) in place through a scratch copy
 template <class K, class V>
@@ -685,10 +682,47 @@ void build_patch(Graph &g, hipStream_t s) {
         if (d[2] > kPatchCells || d[5] > kPatchHalo || d[2] + d[5] > kPatchSlots || d[3] > kPatchRounds || d[2] < 1)
             return;
     }
+    // downstream tasks of every task (the upstream lists reversed), and the
+    // tasks without upstream tasks, which are the first of their stream
+    {
+        std::vector<int32_t> dep_h = to_host<int32_t>(pp.dep, pp.n_dep, s);
+        std::vector<int32_t> dptr(nt + 1, 0), dn(std::max<int64_t>(1, pp.n_dep));
+        for (int64_t t = 0; t < nt; ++t) {
+            const int32_t *d = desc.data() + t * kPatchDesc;
+            for (int32_t k = 0; k < d[7]; ++k) ++dptr[dep_h[d[8] + k] + 1];
+        }
+        for (int64_t t = 0; t < nt; ++t) dptr[t + 1] += dptr[t];
+        std::vector<int32_t> fill(dptr.begin(), dptr.end() - 1);
+        for (int64_t t = 0; t < nt; ++t) {
+            const int32_t *d = desc.data() + t * kPatchDesc;
+            for (int32_t k = 0; k < d[7]; ++k) dn[fill[dep_h[d[8] + k]]++] = (int32_t)t;
+        }
+        std::vector<int32_t> nsrc(kStreams, 0);
+        for (int k = 0; k < kStreams; ++k) {
+            int64_t t = pp.stream_off_h[k];
+            while (t < pp.stream_off_h[k + 1] && desc[t * kPatchDesc + 7] == 0) ++t;
+            nsrc[k] = (int32_t)(t - pp.stream_off_h[k]);
+            for (; t < pp.stream_off_h[k + 1]; ++t)
+                if (desc[t * kPatchDesc + 7] == 0) return;   // sources must lead their stream
+        }
+        for (int64_t t = 0; t < nt; ++t) {
+            desc[t * kPatchDesc + 9] = dptr[t + 1] - dptr[t];
+            desc[t * kPatchDesc + 10] = dptr[t];
+        }
+        JSW_HIP(hipMemcpyAsync(pp.desc.p, desc.data(), 4 * desc.size(), hipMemcpyHostToDevice, s));
+        pp.down.alloc(4 * dn.size());
+        JSW_HIP(hipMemcpyAsync(pp.down.p, dn.data(), 4 * dn.size(), hipMemcpyHostToDevice, s));
+        pp.nsrc.alloc(4 * kStreams);
+        JSW_HIP(hipMemcpyAsync(pp.nsrc.p, nsrc.data(), 4 * kStreams, hipMemcpyHostToDevice, s));
+        JSW_HIP(hipStreamSynchronize(s));
+    }
+    if (nt >= (1ll << 24)) return;   // queue entries carry 24-bit task ids
     pp.stream_off.alloc(8 * (kStreams + 1));
     JSW_HIP(hipMemcpyAsync(pp.stream_off.p, pp.stream_off_h.data(), 8 * (kStreams + 1), hipMemcpyHostToDevice, s));
-    pp.flag.alloc(std::max<int64_t>(nt, 1));
-    JSW_HIP(hipMemsetAsync(pp.flag.p, 0, pp.flag.bytes, s));
+    pp.cnt.alloc(4 * std::max<int64_t>(nt, 1));
+    pp.slot.alloc(4 * std::max<int64_t>(nt, 1));
+    JSW_HIP(hipMemsetAsync(pp.slot.p, 0, pp.slot.bytes, s));
+    pp.qctl.alloc(4 * 32 * kStreams);
     pp.psi.alloc(8 * N);
     pp.den64.alloc(8 * N);
     pp.den64_ok = false;
@@ -715,9 +749,11 @@ struct PatchArgs {
     const double *vs;
     double *psi, *ppsi;
     const double *lag_val;
-    uint8_t *flag;
+    int32_t *cnt;          // upstream tasks not yet complete, per task
+    uint32_t *slot;        // ready queue of every stream: epoch << 24 | task
+    uint32_t *qctl;        // per stream (128 B apart): head, tail at +16
+    const int32_t *down;   // downstream tasks (CSR through the descriptors)
     int32_t *status;
-    uint32_t *tickets;
     const int64_t *stream_off;
     uint32_t epoch, nap;
     uint64_t watchdog_ticks;
@@ -733,7 +769,10 @@ __device__ __forceinline__ T ld_agent(const T *p) {
 // LDS code of an inflow slot: an LDS slot, the boundary or no face
 constexpr uint16_t kLdsBoundary = 0xffff, kLdsNoFace = 0xfffe;
 
-// NS: inflow slots per vertex
+// NS: inflow slots per vertex.  Tasks come out of the stream's ready queue
+// (the paper's ready queues, Listing 1, at task granularity): a wavefront
+// only ever takes a task whose upstream tasks are complete, and the last
+// upstream task to finish appends it.
 template <int NS>
 __global__ void __launch_bounds__(64) k_sweep_patch(PatchArgs a) {
     constexpr int kCL = kPatchCells / 64, kHL = kPatchHalo / 64;
@@ -748,26 +787,44 @@ __global__ void __launch_bounds__(64) k_sweep_patch(PatchArgs a) {
     const int stream = (int)(blockIdx.x % kStreams);
     const int64_t first = a.stream_off[stream];
     const int64_t per_stream = a.stream_off[stream + 1] - first;
-    const uint8_t epoch = (uint8_t)a.epoch;
-    uint32_t *ticket = a.tickets + 32 * stream;
+    const uint32_t epoch = a.epoch & 0xffu;
+    uint32_t *qctl = a.qctl + 32 * stream;
     while (true) {
-        uint32_t tk = 0;
-        if (lane == 0) tk = atomicAdd(ticket, 1u);
-        const int64_t ti = (int64_t)__builtin_amdgcn_readfirstlane(tk);
-        if (ti >= per_stream) break;
-        const int64_t t = first + ti;
+        uint32_t hv = 0;
+        if (lane == 0) hv = atomicAdd(qctl, 1u);
+        const int64_t h = (int64_t)__builtin_amdgcn_readfirstlane(hv);
+        if (h >= per_stream) break;
         const uint32_t t_take = (uint32_t)__builtin_amdgcn_s_memrealtime();
+        // the h-th task to become ready in this stream
+        uint32_t sl = 0;
+        uint64_t t0 = 0;
+        for (uint32_t spin = 0;; ++spin) {
+            sl = __builtin_amdgcn_readfirstlane(ld_agent(a.slot + first + h));
+            if ((sl >> 24) == epoch) break;
+            if (spin == 0) t0 = __builtin_amdgcn_s_memrealtime();
+            if ((spin & 7) == 7) {
+                bool stop = ld_agent(a.status) != 0;
+                if (!stop && __builtin_amdgcn_s_memrealtime() - t0 > a.watchdog_ticks) {
+                    if (lane == 0) atomicOr(a.status, 1);
+                    stop = true;
+                }
+                if (__any(stop)) return;
+            }
+            for (uint32_t z = 0; z < a.nap; ++z) __builtin_amdgcn_s_sleep(1);
+        }
+        const int64_t t = sl & 0xffffffu;
+        const uint32_t t_ready = (uint32_t)__builtin_amdgcn_s_memrealtime();
         const int32_t w = lane < kPatchDesc ? a.desc[t * kPatchDesc + lane] : 0;
         const int q0 = __builtin_amdgcn_readlane(w, 0), m = __builtin_amdgcn_readlane(w, 1);
         const int n = __builtin_amdgcn_readlane(w, 2), nr = __builtin_amdgcn_readlane(w, 3);
         const int r0 = __builtin_amdgcn_readlane(w, 4), nh = __builtin_amdgcn_readlane(w, 5);
-        const int h0 = __builtin_amdgcn_readlane(w, 6), ndep = __builtin_amdgcn_readlane(w, 7);
-        const int d0 = __builtin_amdgcn_readlane(w, 8);
+        const int h0 = __builtin_amdgcn_readlane(w, 6), ndn = __builtin_amdgcn_readlane(w, 9);
+        const int dn0 = __builtin_amdgcn_readlane(w, 10);
         const int64_t base = (int64_t)m * a.nc, qa = base + q0;
-        // the whole task program into LDS while the upstream tasks finish:
-        // all loads issued together (positions of a task are contiguous)
+        // the whole task into LDS: program, vertices, rounds and halo, all
+        // loads issued together (a task's positions are contiguous)
         {
-            int32_t cl[kCL], cd[NS][kCL];
+            int32_t cl[kCL], cd[NS][kCL], hs[kHL];
             double af[NS][kCL], dn[kCL];
 #pragma unroll
             for (int k = 0; k < kCL; ++k) {
@@ -782,9 +839,16 @@ __global__ void __launch_bounds__(64) k_sweep_patch(PatchArgs a) {
                 dn[k] = a.pden[q];
             }
             const int32_t rl = lane < nr ? a.round[r0 + lane] : 0;
-            double vl[kCL];
+#pragma unroll
+            for (int k = 0; k < kHL; ++k) hs[k] = lane + 64 * k < nh ? a.halo[h0 + lane + 64 * k] : 0;
+            double vl[kCL], hv2[kHL];
 #pragma unroll
             for (int k = 0; k < kCL; ++k) vl[k] = a.vs[cl[k]];
+#pragma unroll
+            for (int k = 0; k < kHL; ++k)
+                hv2[k] = lane + 64 * k >= nh ? 0.0
+                         : hs[k] >= 0     ? ld_agent(a.ppsi + base + hs[k])
+                                          : a.lag_val[-(int64_t)hs[k] - 1];
 #pragma unroll
             for (int k = 0; k < kCL; ++k) {
                 const int i = lane + 64 * k;
@@ -801,42 +865,9 @@ __global__ void __launch_bounds__(64) k_sweep_patch(PatchArgs a) {
                 }
             }
             if (lane < nr) srnd[lane] = rl;
-        }
-        int32_t hsrc[kHL];
-#pragma unroll
-        for (int k = 0; k < kHL; ++k) hsrc[k] = lane + 64 * k < nh ? a.halo[h0 + lane + 64 * k] : 0;
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        // wait until every upstream task of this sweep is complete
-        uint64_t t0 = 0;
-        for (uint32_t spin = 0;; ++spin) {
-            bool ok = true;
-            for (int k = lane; k < ndep; k += 64) ok &= ld_agent(a.flag + a.dep[d0 + k]) == epoch;
-            if (__all(ok)) break;
-            if (spin == 0) t0 = __builtin_amdgcn_s_memrealtime();
-            if ((spin & 7) == 7) {
-                bool stop = ld_agent(a.status) != 0;
-                if (!stop && __builtin_amdgcn_s_memrealtime() - t0 > a.watchdog_ticks) {
-                    if (lane == 0) atomicOr(a.status, 1);
-                    stop = true;
-                }
-                if (__any(stop)) return;
-            }
-            for (uint32_t z = 0; z < a.nap; ++z) __builtin_amdgcn_s_sleep(1);
-        }
-        const uint32_t t_ready = (uint32_t)__builtin_amdgcn_s_memrealtime();
-        // halo fluxes into LDS (all loads first)
-        {
-            double hv[kHL];
-#pragma unroll
-            for (int k = 0; k < kHL; ++k) {
-                const int32_t src = hsrc[k];
-                hv[k] = lane + 64 * k >= nh ? 0.0
-                        : src >= 0      ? ld_agent(a.ppsi + base + src)
-                                        : a.lag_val[-(int64_t)src - 1];
-            }
 #pragma unroll
             for (int k = 0; k < kHL; ++k)
-                if (lane + 64 * k < nh) sv[n + lane + 64 * k] = hv[k];
+                if (lane + 64 * k < nh) sv[n + lane + 64 * k] = hv2[k];
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         // rounds, out of LDS only; the next round's program is read while
@@ -879,11 +910,18 @@ __global__ void __launch_bounds__(64) k_sweep_patch(PatchArgs a) {
                 cur = nxt;
             }
         }
-        // publish: fluxes by position, then the flag, then the cell-order copy
+        // publish the fluxes by position; once they are complete, count
+        // this task off every downstream task and queue those it completes
         for (int i = lane; i < n; i += 64) a.ppsi[qa + i] = sv[i];
         __builtin_amdgcn_s_waitcnt(0);
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        if (lane == 0) a.flag[t] = epoch;
+        for (int k = lane; k < ndn; k += 64) {
+            const int32_t d = a.down[dn0 + k];
+            if (atomicSub(a.cnt + d, 1) == 1) {
+                const uint32_t pos = atomicAdd(qctl + 16, 1u);
+                a.slot[first + pos] = epoch << 24 | (uint32_t)d;
+            }
+        }
         for (int i = lane; i < n; i += 64) a.psi[base + scell[i]] = sv[i];
         if (a.stamps && lane == 0) {
             a.stamps[3 * t] = t_take;
@@ -891,6 +929,22 @@ __global__ void __launch_bounds__(64) k_sweep_patch(PatchArgs a) {
             a.stamps[3 * t + 2] = (uint32_t)__builtin_amdgcn_s_memrealtime();
         }
     }
+}
+
+// per sweep: dependency counts, the queues' heads and tails, and the
+// sources (the first tasks of every stream) queued
+__global__ void k_pp_reset(const int32_t *desc, int64_t n_tasks, const int64_t *stream_off, const int32_t *nsrc,
+                           uint32_t epoch, int32_t *cnt, uint32_t *slot, uint32_t *qctl) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < kStreams) {
+        qctl[32 * t] = 0u;
+        qctl[32 * t + 16] = (uint32_t)nsrc[t];
+    }
+    if (t >= n_tasks) return;
+    cnt[t] = desc[t * kPatchDesc + 7];
+    int s = 0;
+    while (s + 1 < kStreams && stream_off[s + 1] <= t) ++s;
+    if (t - stream_off[s] < nsrc[s]) slot[t] = (epoch & 0xffu) << 24 | (uint32_t)t;
 }
 
 template <int NS>
@@ -962,9 +1016,11 @@ void launch_patch64(Graph &g, const double *src_cell, double *psi, double psi_b,
     a.psi = psi;
     a.ppsi = pp.psi.as<double>();
     a.lag_val = g.lag_val64.as<double>();
-    a.flag = pp.flag.as<uint8_t>();
+    a.cnt = pp.cnt.as<int32_t>();
+    a.slot = pp.slot.as<uint32_t>();
+    a.qctl = pp.qctl.as<uint32_t>();
+    a.down = pp.down.as<int32_t>();
     a.status = g.status.as<int32_t>();
-    a.tickets = reinterpret_cast<uint32_t *>(g.status.as<char>() + 128);
     a.stream_off = pp.stream_off.as<int64_t>();
     pp.epoch = pp.epoch % 255 + 1;
     a.epoch = (uint32_t)pp.epoch;
@@ -984,7 +1040,10 @@ void launch_patch64(Graph &g, const double *src_cell, double *psi, double psi_b,
     int64_t blocks = (int64_t)occ * g.n_cu;
     blocks = std::min<int64_t>(blocks, std::max<int64_t>(pp.n_tasks, kStreams));
     blocks = std::max<int64_t>(blocks, kStreams);
-    k_pp_reset_tickets<<<1, 64, 0, s>>>(a.tickets);
+    k_pp_reset<<<blocks_for(std::max<int64_t>(pp.n_tasks, kStreams)), kB, 0, s>>>(
+        pp.desc.as<int32_t>(), pp.n_tasks, pp.stream_off.as<int64_t>(), pp.nsrc.as<int32_t>(), a.epoch,
+        pp.cnt.as<int32_t>(), pp.slot.as<uint32_t>(), pp.qctl.as<uint32_t>());
+    JSW_HIP(hipGetLastError());
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (g.profile) {
         JSW_HIP(hipEventCreate(&ev0));

@@ -894,7 +894,7 @@ int check_sweep_status(Graph &g, hipStream_t s) {
     if (st == 0) return JSWEEP_OK;
     // a stalled sweep leaves flags in an unknown state: start over
     JSW_HIP(hipMemsetAsync(g.cflag.p, 0, g.cflag.bytes, s));
-    if (g.pp.flag.p) JSW_HIP(hipMemsetAsync(g.pp.flag.p, 0, g.pp.flag.bytes, s));
+    if (g.pp.slot.p) JSW_HIP(hipMemsetAsync(g.pp.slot.p, 0, g.pp.slot.bytes, s));
     JSW_HIP(hipMemsetAsync(g.status.p, 0, 64, s));
     JSW_HIP(hipStreamSynchronize(s));
     g.epoch = 0;
