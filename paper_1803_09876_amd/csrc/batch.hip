@@ -209,8 +209,7 @@ __global__ void k_b_phi_delta(const BInst *I, const int64_t *coff, int n, int64_
     if (i >= 0) {
         const BInst &b = I[i];
         const int64_t K = g - coff[i];
-        double s = 0.0;
-        for (int m = 0; m < b.nd; ++m) s = s + b.w[m] * b.psi[(int64_t)m * b.nc + K];
+        const double s = dir_sum(b.w, b.psi, b.nc, b.nd, K);
         const double d = b.sigma_s[K] * (s - b.phi[K]);
         b.phi[K] = s;
         b.dphi[K] = d;
@@ -257,8 +256,7 @@ __global__ void k_b_dphi(const BInst *I, const int64_t *coff, int n, int64_t tot
     if (i >= 0) {
         const BInst &b = I[i];
         const int64_t K = g - coff[i];
-        double s = 0.0;
-        for (int m = 0; m < b.nd; ++m) s = s + b.w[m] * (double)b.dpsi[(int64_t)m * b.nc + K];
+        const double s = dir_sum(b.w, b.dpsi, b.nc, b.nd, K);
         const double old = b.dphi[K];
         b.dphi[K] = s;
         b.g32[K] = with_q[i] ? (float)(b.q[K] + b.sigma_s[K] * s) : (float)(b.sigma_s[K] * s);

@@ -4,6 +4,23 @@
 
 namespace jsw {
 
+// sum_m w_m x_{m, K} in ascending m (the order of the scalar flux), with the
+// loads of eight directions issued together
+template <class T>
+__device__ inline double dir_sum(const double *w, const T *x, int64_t nc, int nd, int64_t K) {
+    double s = 0.0;
+    int m = 0;
+    for (; m + 8 <= nd; m += 8) {
+        T v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = x[(int64_t)(m + k) * nc + K];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s = s + w[m + k] * (double)v[k];
+    }
+    for (; m < nd; ++m) s = s + w[m] * (double)x[(int64_t)m * nc + K];
+    return s;
+}
+
 // One cell of the FP64 residual with the full (un-lagged) streaming
 // operator, looping over directions:
 //   phi_K = sum_m w_m psi_{K,m}
@@ -16,8 +33,7 @@ __device__ inline double residual_cell(const CellRec<double, NF, DIM> &r, int64_
                                        int64_t nc, int nd, double *phi, float *r32, const int32_t *posi) {
     int64_t nb[NF];
     for (int j = 0; j < NF; ++j) nb[j] = r.nbr[j] <= -2 ? (int64_t)(-r.nbr[j] - 2) : (int64_t)r.nbr[j];
-    double ph = 0.0;
-    for (int m = 0; m < nd; ++m) ph = ph + w[m] * psi[(int64_t)m * nc + K];
+    const double ph = dir_sum(w, psi, nc, nd, K);
     phi[K] = ph;
     const double src = q + sigma_s * ph;
     double cell = 0.0;

@@ -145,17 +145,20 @@ void ensure_den(Graph &g, bool fp32, hipStream_t s) {
 }
 
 // s_K = q_K + sigma_s,K phi_K
-__global__ void k_source(const double *q, const double *sigma_s, const double *phi, int64_t nc, double *src) {
+// s = q + sigma_s phi; thread 0 also zeroes the iteration's norm
+// accumulators (three doubles at acc, or nothing when acc is null)
+__global__ void k_source(const double *q, const double *sigma_s, const double *phi, int64_t nc, double *src,
+                         double *acc) {
     int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (K < nc) src[K] = q[K] + sigma_s[K] * phi[K];
+    if (acc && K < 3) acc[K] = 0.0;
 }
 
 // phi_K = sum_m w_m psi_{K,m}, ascending m
 __global__ void k_phi(const double *psi, const double *w, int64_t nc, int nd, double *phi) {
     int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (K >= nc) return;
-    double s = 0.0;
-    for (int m = 0; m < nd; ++m) s = s + w[m] * psi[(int64_t)m * nc + K];
+    const double s = dir_sum(w, psi, nc, nd, K);
     phi[K] = s;
 }
 
@@ -218,8 +221,7 @@ __global__ void k_phi_delta(const double *psi, const double *w, double wsum, con
     int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double a = 0.0, b = 0.0;
     if (K < nc) {
-        double s = 0.0;
-        for (int m = 0; m < nd; ++m) s = s + w[m] * psi[(int64_t)m * nc + K];
+        const double s = dir_sum(w, psi, nc, nd, K);
         const double d = sigma_s[K] * (s - phi[K]);
         phi[K] = s;
         dcell[K] = d;
@@ -272,8 +274,7 @@ __global__ void k_dphi(const float *dpsi, const double *w, const double *sigma_s
     if (K == 0) acc[2] = (double)status[0];
     double a = 0.0, b = 0.0;
     if (K < nc) {
-        double s = 0.0;
-        for (int m = 0; m < nd; ++m) s = s + w[m] * (double)dpsi[(int64_t)m * nc + K];
+        const double s = dir_sum(w, dpsi, nc, nd, K);
         double old = dphi[K];
         dphi[K] = s;
         g32[K] = q ? (float)(q[K] + sigma_s[K] * s) : (float)(sigma_s[K] * s);
@@ -345,23 +346,33 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
         double wsum = 0.0;
         for (double x : g.weight_h) wsum += x;
         const int64_t nl = std::max<int64_t>(1, g.n_lag);
+        // a fixed number of iterations (tol = 0) keeps every iteration's
+        // norms on the device and reads them once at the end; otherwise they
+        // are read after every sweep for the stopping test
+        const bool fixed = !(tol > 0.0);
+        DevBuf norms;
+        if (fixed) {
+            norms.alloc(8 * 4 * (size_t)max_iter);
+            JSW_HIP(hipMemsetAsync(norms.p, 0, norms.bytes, s));
+        }
         while (true) {
             if (sweeps >= max_iter) { rc = JSWEEP_E_NOT_CONVERGED; break; }
-            k_source<<<(int)ceil_div(g.nc, kB), kB, 0, s>>>(q, sigma_s, phi, g.nc, src);
+            double *it_acc = fixed ? norms.as<double>() + 4 * sweeps : acc;
+            k_source<<<(int)ceil_div(g.nc, kB), kB, 0, s>>>(q, sigma_s, phi, g.nc, src, fixed ? nullptr : acc);
             JSW_HIP(hipGetLastError());
             lag_snapshot<double>(g, psi, s);
             launch_sweep64(g, src, psi, psi_b, params, s);
             ++sweeps;
             // residual of the new iterate from the identity above (one
             // pass over psi for phi, then the lagged edges)
-            JSW_HIP(hipMemsetAsync(acc, 0, 24, s));
             k_phi_delta<<<(int)ceil_div(g.nc, kB), kB, 0, s>>>(psi, g.weight.as<double>(), wsum, q, sigma_s,
-                                                               g.vol.as<double>(), g.nc, g.nd, phi, dcell, acc);
+                                                               g.vol.as<double>(), g.nc, g.nd, phi, dcell, it_acc);
             JSW_HIP(hipGetLastError());
             k_lag_residual<<<(int)ceil_div(nl, kB), kB, 0, s>>>(
                 g.lag_mv.as<uint64_t>(), g.lag_u.as<int32_t>(), g.lag_a.as<double>(), g.lag_val64.as<double>(),
-                g.n_lag, psi, g.weight.as<double>(), g.vol.as<double>(), dcell, g.nc, g.status.as<int32_t>(), acc);
+                g.n_lag, psi, g.weight.as<double>(), g.vol.as<double>(), dcell, g.nc, g.status.as<int32_t>(), it_acc);
             JSW_HIP(hipGetLastError());
+            if (fixed) continue;
             double h[3];
             JSW_HIP(hipMemcpyAsync(h, acc, 24, hipMemcpyDeviceToHost, s));
             JSW_HIP(hipStreamSynchronize(s));
@@ -369,7 +380,19 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
             rho = h[1] > 0.0 ? std::sqrt(std::max(h[0], 0.0)) / std::sqrt(h[1]) : std::sqrt(std::max(h[0], 0.0));
             ++outer;
             record(rho);
-            if (tol > 0.0 && rho <= tol) break;
+            if (rho <= tol) break;
+        }
+        if (fixed && sweeps > 0) {
+            std::vector<double> h(4 * (size_t)sweeps);
+            JSW_HIP(hipMemcpyAsync(h.data(), norms.p, 8 * h.size(), hipMemcpyDeviceToHost, s));
+            JSW_HIP(hipStreamSynchronize(s));
+            for (int k = 0; k < sweeps; ++k) {
+                const double *x = h.data() + 4 * k;
+                if (x[2] != 0.0) return check_sweep_status(g, s);
+                rho = x[1] > 0.0 ? std::sqrt(std::max(x[0], 0.0)) / std::sqrt(x[1]) : std::sqrt(std::max(x[0], 0.0));
+                ++outer;
+                record(rho);
+            }
         }
     } else {
         ensure(g.scratch_c, 4 * N * 2 + 64);            // r32 and dpsi32
