@@ -5,17 +5,24 @@
 namespace jsw {
 
 // sum_m w_m x_{m, K} in ascending m (the order of the scalar flux), with the
-// loads of eight directions issued together
+// loads of sixteen directions issued together
 template <class T>
 __device__ inline double dir_sum(const double *w, const T *x, int64_t nc, int nd, int64_t K) {
     double s = 0.0;
     int m = 0;
-    for (; m + 8 <= nd; m += 8) {
-        T v[8];
+    for (; m + 16 <= nd; m += 16) {
+        T v[16];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = x[(int64_t)(m + k) * nc + K];
+        for (int k = 0; k < 16; ++k) v[k] = x[(int64_t)(m + k) * nc + K];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) s = s + w[m + k] * (double)v[k];
+        for (int k = 0; k < 16; ++k) s = s + w[m + k] * (double)v[k];
+    }
+    for (; m + 4 <= nd; m += 4) {
+        T v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = x[(int64_t)(m + k) * nc + K];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s = s + w[m + k] * (double)v[k];
     }
     for (; m < nd; ++m) s = s + w[m] * (double)x[(int64_t)m * nc + K];
     return s;
@@ -36,20 +43,39 @@ __device__ inline double residual_cell(const CellRec<double, NF, DIM> &r, int64_
     const double ph = dir_sum(w, psi, nc, nd, K);
     phi[K] = ph;
     const double src = q + sigma_s * ph;
-    double cell = 0.0;
-    for (int m = 0; m < nd; ++m) {
+    // residual of direction m from the loaded fluxes (own and neighbours)
+    auto res_of = [&](int m, double own, const double (&up)[NF]) {
         const double *om = omega + 3 * m;
-        const double *pm = psi + (int64_t)m * nc;
         double in = 0.0, den = r.sigV;
         for (int j = 0; j < NF; ++j) {
             double d = om[0] * r.S[j][0] + om[1] * r.S[j][1];
             if constexpr (DIM == 3) d = d + om[2] * r.S[j][2];
-            if (d < 0.0) in = in + (-d) * (nb[j] < 0 ? psi_b : pm[nb[j]]);
+            if (d < 0.0) in = in + (-d) * (nb[j] < 0 ? psi_b : up[j]);
             else if (d > 0.0) den = den + d;
         }
-        const double res = src - (den * pm[K] - in) / r.V;
-        if (r32) r32[(int64_t)m * nc + posi[(int64_t)m * nc + K]] = (float)res;
-        cell = cell + w[m] * (res * res);
+        return src - (den * own - in) / r.V;
+    };
+    // four directions' fluxes are loaded before any is used
+    constexpr int B = 4;
+    double cell = 0.0;
+    int m = 0;
+    for (; m < nd; m += B) {
+        double own[B], up[B][NF];
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int mm = m + k < nd ? m + k : m;
+            const double *pm = psi + (int64_t)mm * nc;
+            own[k] = pm[K];
+#pragma unroll
+            for (int j = 0; j < NF; ++j) up[k][j] = nb[j] < 0 ? 0.0 : pm[nb[j]];
+        }
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            if (m + k >= nd) break;
+            const double res = res_of(m + k, own[k], up[k]);
+            if (r32) r32[(int64_t)(m + k) * nc + posi[(int64_t)(m + k) * nc + K]] = (float)res;
+            cell = cell + w[m + k] * (res * res);
+        }
     }
     return r.V * cell;
 }
