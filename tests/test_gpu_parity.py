@@ -103,6 +103,22 @@ def test_patch_program_and_sweep(cases):
             J.set_params(gg, None)
 
 
+def test_set_params_validation_and_reset(cases):
+    """jsweep_set_params: bad parameters are refused, pinned parameters
+    apply to jsweep_sweep, None returns to the defaults (same fluxes)."""
+    name, p, og, gg = cases[0]
+    with pytest.raises(J.JsweepError):
+        J.set_params(gg, J.Params(strategy=9))
+    with pytest.raises(J.JsweepError):
+        J.set_params(gg, J.Params(waves_per_block=-1))
+    ref = og.sweep(p.sigma_t, p.q)
+    for prm in (J.Params(strategy=J.JSWEEP_STRATEGY_DIRECTION), None):
+        J.set_params(gg, prm)
+        psi = dev(np.zeros((p.n_dirs, p.n_cells)))
+        J.sweep(gg, dev(p.sigma_t), dev(p.q), psi)
+        assert rel_max(host(psi), ref) <= 1e-12, prm
+
+
 @pytest.mark.parametrize("strategy", [J.JSWEEP_STRATEGY_DATA_DRIVEN, J.JSWEEP_STRATEGY_PATCH])
 def test_sweep_trace_respects_dependencies(cases, strategy):
     """Trace of one sweep (work-list chunks, or PATCH tasks): every unit
