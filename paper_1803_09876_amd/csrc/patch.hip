@@ -14,11 +14,15 @@
 // the task graph, so it is acyclic.  A task's vertices run on one wavefront,
 // level by level (rounds of at most 64 vertices), with the fluxes of the task
 // and of its halo (upwind vertices of other tasks, lagged values) held in
-// LDS; a task starts when all its upstream tasks have completed.
+// LDS.
 //
-// Tasks are numbered per stream (XCD) by their depth in the direction's task
-// graph, so the persistent kernel hands them out with one atomic ticket per
-// stream and never waits for a task that has not been taken.
+// Tasks run out of one ready queue per stream (XCD; a direction's tasks all
+// belong to one stream): every task has a count of its upstream tasks, reset
+// before each sweep; the tasks without any (the first of each stream, whose
+// tasks are numbered by depth in the task graph) start in the queue, and a
+// finishing task decrements the counts of its downstream tasks and appends
+// those it completes.  A wavefront only ever takes a task whose inputs are
+// final, so none waits while holding one.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
