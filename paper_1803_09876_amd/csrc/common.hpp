@@ -231,7 +231,11 @@ struct SweepSrc {
 void refresh_sigma(Graph &g, const double *sigma_t, bool fp32, hipStream_t s);
 // sweep-program denominators from the records' sigma_t V, where not valid
 void ensure_den(Graph &g, bool fp32, hipStream_t s);
-void launch_sweep64(Graph &g, const double *src_cell, double *psi, double psi_b, const jsweep_params *p, hipStream_t s);
+// prepared: g.vsc already holds V s of src_cell for this sweep and the
+// data-driven kernel's tickets are zero (the FP64 solve prepares the next
+// sweep in its residual kernels)
+void launch_sweep64(Graph &g, const double *src_cell, double *psi, double psi_b, const jsweep_params *p, hipStream_t s,
+                    bool prepared = false);
 void launch_sweep32(Graph &g, const float *src_dir, const float *src_cell, float *psi, const jsweep_params *p,
                     hipStream_t s);
 int check_sweep_status(Graph &g, hipStream_t s);   // JSWEEP_OK or JSWEEP_E_STALLED
@@ -243,7 +247,7 @@ int sweep_strategy(const Graph &g, const jsweep_params *p);
 bool patch_ready(Graph &g, hipStream_t s);
 void patch_den(Graph &g, hipStream_t s);
 void launch_patch64(Graph &g, const double *src_cell, double *psi, double psi_b, const jsweep_params *p,
-                    hipStream_t s);
+                    hipStream_t s, bool prepared = false);
 
 // batched sweep over an ensemble of graphs: one workgroup per
 // (instance, direction), one launch (sweep.hip)

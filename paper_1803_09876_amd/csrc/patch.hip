@@ -997,7 +997,7 @@ void patch_den(Graph &g, hipStream_t s) {
 }
 
 void launch_patch64(Graph &g, const double *src_cell, double *psi, double psi_b, const jsweep_params *p,
-                    hipStream_t s) {
+                    hipStream_t s, bool prepared) {
     (void)p;
     PatchProg &pp = g.pp;
     if (!pp.ok) fail(JSWEEP_E_DEVICE, "patch program not available for this graph");
@@ -1013,9 +1013,11 @@ void launch_patch64(Graph &g, const double *src_cell, double *psi, double psi_b,
     a.pden = pp.den64.as<double>();
     a.N = g.nc * g.nd;
     a.nc = g.nc;
-    if (g.vsc.bytes < (size_t)(8 * g.nc)) g.vsc.alloc(8 * g.nc);
-    k_pp_vs<<<blocks_for(g.nc), kB, 0, s>>>(g.vol.as<double>(), src_cell, g.nc, g.vsc.as<double>());
-    JSW_HIP(hipGetLastError());
+    if (!prepared) {
+        if (g.vsc.bytes < (size_t)(8 * g.nc)) g.vsc.alloc(8 * g.nc);
+        k_pp_vs<<<blocks_for(g.nc), kB, 0, s>>>(g.vol.as<double>(), src_cell, g.nc, g.vsc.as<double>());
+        JSW_HIP(hipGetLastError());
+    }
     a.vs = g.vsc.as<double>();
     a.psi = psi;
     a.ppsi = pp.psi.as<double>();

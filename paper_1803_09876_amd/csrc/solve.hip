@@ -145,13 +145,9 @@ void ensure_den(Graph &g, bool fp32, hipStream_t s) {
 }
 
 // s_K = q_K + sigma_s,K phi_K
-// s = q + sigma_s phi; thread 0 also zeroes the iteration's norm
-// accumulators (three doubles at acc, or nothing when acc is null)
-__global__ void k_source(const double *q, const double *sigma_s, const double *phi, int64_t nc, double *src,
-                         double *acc) {
+__global__ void k_source(const double *q, const double *sigma_s, const double *phi, int64_t nc, double *src) {
     int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (K < nc) src[K] = q[K] + sigma_s[K] * phi[K];
-    if (acc && K < 3) acc[K] = 0.0;
 }
 
 // phi_K = sum_m w_m psi_{K,m}, ascending m
@@ -216,8 +212,11 @@ __global__ void k_residual(const CellRec<double, NF, DIM> *rec, const double *om
 //   r = sigma_s (phi' - phi) + sum over lagged in-faces a (psi'_u - psi_u) / V.
 // k_phi_delta: phi' (ascending m), the isotropic part d = sigma_s (phi' -
 // phi) and its norm W V d^2 (W = sum of the weights), and V q^2.
+// It also prepares the next sweep: its source q + sigma_s phi' and the
+// product V s the sweep kernels read.
 __global__ void k_phi_delta(const double *psi, const double *w, double wsum, const double *q, const double *sigma_s,
-                            const double *vol, int64_t nc, int nd, double *phi, double *dcell, double *acc) {
+                            const double *vol, int64_t nc, int nd, double *phi, double *dcell, double *acc,
+                            double *src_next, double *vs_next) {
     int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double a = 0.0, b = 0.0;
     if (K < nc) {
@@ -225,6 +224,9 @@ __global__ void k_phi_delta(const double *psi, const double *w, double wsum, con
         const double d = sigma_s[K] * (s - phi[K]);
         phi[K] = s;
         dcell[K] = d;
+        const double sn = q[K] + sigma_s[K] * s;
+        src_next[K] = sn;
+        vs_next[K] = vol[K] * sn;
         a = wsum * (vol[K] * (d * d));
         b = vol[K] * (q[K] * q[K]);
     }
@@ -234,20 +236,27 @@ __global__ void k_phi_delta(const double *psi, const double *w, double wsum, con
 
 // lagged corrections, one thread per (direction, downwind cell) group of
 // the (m, v, u)-sorted lagged edges: w_m V ((d + l)^2 - d^2); thread 0 also
-// copies the sweep status word next to the norms
-__global__ void k_lag_residual(const uint64_t *lag_mv, const int32_t *lag_u, const double *lag_a,
-                               const double *lag_old, int64_t n_lag, const double *psi, const double *w,
-                               const double *vol, const double *dcell, int64_t nc, const int32_t *status,
-                               double *acc) {
+// copies the sweep status word next to the norms.  For the next sweep it
+// replaces the lagged values by the new iterate's, zeroes the next norm
+// accumulators (acc_next, unless null) and the data-driven kernel's tickets.
+__global__ void k_lag_residual(const uint64_t *lag_mv, const int32_t *lag_u, const double *lag_a, double *lag_val,
+                               int64_t n_lag, const double *psi, const double *w, const double *vol,
+                               const double *dcell, int64_t nc, const int32_t *status, double *acc,
+                               double *acc_next, uint32_t *tickets) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e == 0) acc[2] = (double)status[0];
+    if (acc_next && e < 3) acc_next[e] = 0.0;
+    if (e < kStreams) tickets[32 * e] = 0u;
     double c = 0.0;
     if (e < n_lag && (e == 0 || lag_mv[e - 1] != lag_mv[e])) {
         const uint64_t key = lag_mv[e];
         const int64_t m = (int64_t)(key >> 32), v = (int64_t)(key & 0xffffffffu);
         double l = 0.0;
-        for (int64_t f = e; f < n_lag && lag_mv[f] == key; ++f)
-            l = l + lag_a[f] * (psi[m * nc + lag_u[f]] - lag_old[f]) / vol[v];
+        for (int64_t f = e; f < n_lag && lag_mv[f] == key; ++f) {
+            const double now = psi[m * nc + lag_u[f]];
+            l = l + lag_a[f] * (now - lag_val[f]) / vol[v];
+            lag_val[f] = now;
+        }
         const double d = dcell[v];
         c = w[m] * (vol[v] * ((d + l) * (d + l) - d * d));
     }
@@ -346,35 +355,43 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
         double wsum = 0.0;
         for (double x : g.weight_h) wsum += x;
         const int64_t nl = std::max<int64_t>(1, g.n_lag);
+        if (g.vsc.bytes < (size_t)(8 * g.nc)) g.vsc.alloc(8 * g.nc);
+        uint32_t *tickets = reinterpret_cast<uint32_t *>(g.status.as<char>() + 128);
         // a fixed number of iterations (tol = 0) keeps every iteration's
-        // norms on the device and reads them once at the end; otherwise they
-        // are read after every sweep for the stopping test
-        const bool fixed = !(tol > 0.0);
-        DevBuf norms;
-        if (fixed) {
-            norms.alloc(8 * 4 * (size_t)max_iter);
-            JSW_HIP(hipMemsetAsync(norms.p, 0, norms.bytes, s));
-        }
+        // norms on the device and reads them once at the end; otherwise two
+        // accumulator sets alternate and are read after every sweep
+        const bool fixed = !(tol > 0.0) && max_iter <= 65536;
+        DevBuf norms(8 * 4 * (size_t)(fixed ? max_iter : 2));
+        JSW_HIP(hipMemsetAsync(norms.p, 0, norms.bytes, s));
+        // after the first sweep, the residual kernels prepare the next one
+        // (source, V s, lagged values, tickets)
+        bool prepared = false;
         while (true) {
             if (sweeps >= max_iter) { rc = JSWEEP_E_NOT_CONVERGED; break; }
-            double *it_acc = fixed ? norms.as<double>() + 4 * sweeps : acc;
-            k_source<<<(int)ceil_div(g.nc, kB), kB, 0, s>>>(q, sigma_s, phi, g.nc, src, fixed ? nullptr : acc);
-            JSW_HIP(hipGetLastError());
-            lag_snapshot<double>(g, psi, s);
-            launch_sweep64(g, src, psi, psi_b, params, s);
+            double *it_acc = norms.as<double>() + 4 * (fixed ? sweeps : (sweeps & 1));
+            double *next_acc = fixed ? nullptr : norms.as<double>() + 4 * ((sweeps + 1) & 1);
+            if (!prepared) {
+                k_source<<<(int)ceil_div(g.nc, kB), kB, 0, s>>>(q, sigma_s, phi, g.nc, src);
+                JSW_HIP(hipGetLastError());
+                lag_snapshot<double>(g, psi, s);
+            }
+            launch_sweep64(g, src, psi, psi_b, params, s, prepared);
             ++sweeps;
             // residual of the new iterate from the identity above (one
             // pass over psi for phi, then the lagged edges)
             k_phi_delta<<<(int)ceil_div(g.nc, kB), kB, 0, s>>>(psi, g.weight.as<double>(), wsum, q, sigma_s,
-                                                               g.vol.as<double>(), g.nc, g.nd, phi, dcell, it_acc);
+                                                               g.vol.as<double>(), g.nc, g.nd, phi, dcell, it_acc,
+                                                               src, g.vsc.as<double>());
             JSW_HIP(hipGetLastError());
             k_lag_residual<<<(int)ceil_div(nl, kB), kB, 0, s>>>(
                 g.lag_mv.as<uint64_t>(), g.lag_u.as<int32_t>(), g.lag_a.as<double>(), g.lag_val64.as<double>(),
-                g.n_lag, psi, g.weight.as<double>(), g.vol.as<double>(), dcell, g.nc, g.status.as<int32_t>(), it_acc);
+                g.n_lag, psi, g.weight.as<double>(), g.vol.as<double>(), dcell, g.nc, g.status.as<int32_t>(), it_acc,
+                next_acc, tickets);
             JSW_HIP(hipGetLastError());
+            prepared = true;
             if (fixed) continue;
             double h[3];
-            JSW_HIP(hipMemcpyAsync(h, acc, 24, hipMemcpyDeviceToHost, s));
+            JSW_HIP(hipMemcpyAsync(h, it_acc, 24, hipMemcpyDeviceToHost, s));
             JSW_HIP(hipStreamSynchronize(s));
             if (h[2] != 0.0) return check_sweep_status(g, s);
             rho = h[1] > 0.0 ? std::sqrt(std::max(h[0], 0.0)) / std::sqrt(h[1]) : std::sqrt(std::max(h[0], 0.0));

@@ -439,7 +439,7 @@ __global__ void k_vs32(const double *vol, const float *src, int64_t nc, float2 *
 
 template <class Real>
 static void launch_persistent(Graph &g, const Real *src_cell, const float *src_dir, Real *psi, Real psi_b,
-                              const jsweep_params *p, hipStream_t s) {
+                              const jsweep_params *p, hipStream_t s, bool prepared = false) {
     const bool f32 = sizeof(Real) == 4;
     if (!(f32 ? g.den32_ok : g.den64_ok)) fail(JSWEEP_E_DEVICE, "sweep program denominators not built");
     SweepArgs<Real> a;
@@ -451,15 +451,17 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
     a.pcode = g.pcode.as<int32_t>();
     a.pa = reinterpret_cast<const Real *>(f32 ? g.pa32.p : g.pa64.p);
     a.pden = reinterpret_cast<const Real *>(f32 ? g.pden32.p : g.pden64.p);
-    if (g.vsc.bytes < (size_t)(8 * g.nc)) g.vsc.alloc(8 * g.nc);
-    const int gb = (int)ceil_div(g.nc, 256);
-    if (f32)
-        k_vs32<<<gb, 256, 0, s>>>(g.vol.as<double>(), reinterpret_cast<const float *>(src_cell), g.nc,
-                                 g.vsc.as<float2>());
-    else
-        k_vs64<<<gb, 256, 0, s>>>(g.vol.as<double>(), reinterpret_cast<const double *>(src_cell), g.nc,
-                                 g.vsc.as<double>());
-    JSW_HIP(hipGetLastError());
+    if (!prepared) {
+        if (g.vsc.bytes < (size_t)(8 * g.nc)) g.vsc.alloc(8 * g.nc);
+        const int gb = (int)ceil_div(g.nc, 256);
+        if (f32)
+            k_vs32<<<gb, 256, 0, s>>>(g.vol.as<double>(), reinterpret_cast<const float *>(src_cell), g.nc,
+                                     g.vsc.as<float2>());
+        else
+            k_vs64<<<gb, 256, 0, s>>>(g.vol.as<double>(), reinterpret_cast<const double *>(src_cell), g.nc,
+                                     g.vsc.as<double>());
+        JSW_HIP(hipGetLastError());
+    }
     a.vs = g.vsc.p;
     a.src_dir = src_dir;
     a.psi = psi;
@@ -490,7 +492,7 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
     int64_t need = std::max<int64_t>(1, g.n_chunks);
     if (waves > need) waves = (int)((need + wpb - 1) / wpb * wpb);
     int blocks = std::max(waves / wpb, kStreams);
-    k_reset_tickets<<<1, 64, 0, s>>>(a.tickets);
+    if (!prepared) k_reset_tickets<<<1, 64, 0, s>>>(a.tickets);
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (g.profile) {
         JSW_HIP(hipEventCreate(&ev0));
@@ -860,24 +862,25 @@ int sweep_strategy(const Graph &g, const jsweep_params *p) {
 
 template <class Real, int NF, int DIM>
 static void launch_impl(Graph &g, const Real *src_cell, const float *src_dir, Real *psi, Real psi_b,
-                        const jsweep_params *p, hipStream_t s) {
+                        const jsweep_params *p, hipStream_t s, bool prepared = false) {
     const int st = sweep_strategy(g, p);
     if constexpr (sizeof(Real) == 8) {
         if (st == JSWEEP_STRATEGY_PATCH && patch_ready(g, s)) {
-            launch_patch64(g, src_cell, psi, psi_b, p, s);
+            launch_patch64(g, src_cell, psi, psi_b, p, s, prepared);
             return;
         }
     }
     if (st == JSWEEP_STRATEGY_DIRECTION_LDS && ring_items(g, sizeof(Real) == 4)) launch_ring<Real>(g, src_cell, src_dir, psi, psi_b, s);
     else if (st == JSWEEP_STRATEGY_DIRECTION || st == JSWEEP_STRATEGY_DIRECTION_LDS)
         launch_dir<Real, NF, DIM>(g, src_cell, src_dir, psi, psi_b, p, s);
-    else launch_persistent<Real>(g, src_cell, src_dir, psi, psi_b, p, s);
+    else launch_persistent<Real>(g, src_cell, src_dir, psi, psi_b, p, s, prepared);
 }
 
-void launch_sweep64(Graph &g, const double *src_cell, double *psi, double psi_b, const jsweep_params *p, hipStream_t s) {
-    if (g.ctype == JSWEEP_TRI) launch_impl<double, 3, 2>(g, src_cell, nullptr, psi, psi_b, p, s);
-    else if (g.ctype == JSWEEP_TET) launch_impl<double, 4, 3>(g, src_cell, nullptr, psi, psi_b, p, s);
-    else launch_impl<double, 6, 3>(g, src_cell, nullptr, psi, psi_b, p, s);
+void launch_sweep64(Graph &g, const double *src_cell, double *psi, double psi_b, const jsweep_params *p, hipStream_t s,
+                    bool prepared) {
+    if (g.ctype == JSWEEP_TRI) launch_impl<double, 3, 2>(g, src_cell, nullptr, psi, psi_b, p, s, prepared);
+    else if (g.ctype == JSWEEP_TET) launch_impl<double, 4, 3>(g, src_cell, nullptr, psi, psi_b, p, s, prepared);
+    else launch_impl<double, 6, 3>(g, src_cell, nullptr, psi, psi_b, p, s, prepared);
 }
 
 void launch_sweep32(Graph &g, const float *src_dir, const float *src_cell, float *psi, const jsweep_params *p,
