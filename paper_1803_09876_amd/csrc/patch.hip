@@ -398,14 +398,20 @@ void visits(int64_t nc, int ns, const int32_t *up, const int32_t *lev, const int
                 dn[fill[u]++] = (int32_t)v;
             }
     }
-    // ready cells per patch (linked lists) and their lowest level
+    // ready cells per patch (linked lists) and their lowest level; the
+    // patches with ready cells in a heap keyed by (lowest ready level,
+    // patch), entries made stale by a later change are skipped when popped
     std::vector<int32_t> head(npatch, -1), nxt(nc, -1), cnt(npatch, 0), minlev(npatch, INT32_MAX);
+    std::priority_queue<std::pair<int32_t, int32_t>, std::vector<std::pair<int32_t, int32_t>>, std::greater<>> ph;
     auto push = [&](int32_t w) {
         const int32_t p = patch[w];
         nxt[w] = head[p];
         head[p] = w;
         ++cnt[p];
-        minlev[p] = std::min(minlev[p], lev[w]);
+        if (lev[w] < minlev[p]) {
+            minlev[p] = lev[w];
+            ph.push({minlev[p], p});
+        }
     };
     for (int64_t v = 0; v < nc; ++v)
         if (indeg[v] == 0) push((int32_t)v);
@@ -418,9 +424,9 @@ void visits(int64_t nc, int ns, const int32_t *up, const int32_t *lev, const int
     int64_t done = 0;
     uint32_t nv = 0;
     while (done < nc) {
-        int32_t best = -1;
-        for (int32_t p = 0; p < npatch; ++p)
-            if (cnt[p] && (best < 0 || minlev[p] < minlev[best])) best = p;
+        while (cnt[ph.top().second] == 0 || minlev[ph.top().second] != ph.top().first) ph.pop();
+        const int32_t best = ph.top().second;
+        ph.pop();
         const uint32_t t = nv++;
         for (int32_t v = head[best]; v >= 0; v = nxt[v]) pq.push({lev[v], v});
         head[best] = -1;
