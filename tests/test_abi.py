@@ -74,3 +74,23 @@ def test_null_handles_rejected():
     assert lib.jsweep_profile(None, 1) == J.JSWEEP_E_INVALID_ARG
     lib.jsweep_graph_destroy(None)
     assert "graph is NULL" in J.jsweep_last_error() or J.jsweep_last_error()
+
+
+def test_set_params_and_patch_info_reject_null():
+    """The two parameter calls refuse a NULL graph (no device work)."""
+    lib = J.load_library()
+    assert lib.jsweep_set_params(None, None) == J.JSWEEP_E_INVALID_ARG
+    out = np.zeros(6, dtype=np.int64)
+    assert lib.jsweep_patch_info(None, None, out.ctypes.data) == J.JSWEEP_E_INVALID_ARG
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU: --gpus 2 exits with a message before any
+    device work."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
