@@ -41,8 +41,8 @@
  *   - hip_stream is a hipStream_t (NULL = the default stream).  Sweeps are
  *     stream-ordered; solves synchronise the stream once per outer
  *     iteration to read the residual.
- *   - One graph must not be used by two calls at the same time (its flag
- *     and scratch arrays are shared by every call on it).
+ *   - One graph must not be used by two calls at the same time (its work
+ *     lists, flux and scratch arrays are shared by every call on it).
  */
 #ifndef JSWEEP_H
 #define JSWEEP_H
@@ -102,7 +102,8 @@ typedef struct jsweep_graph_s *jsweep_graph;   /* opaque, owned by the library *
 /* Sweep strategies.
  * DATA_DRIVEN: a persistent kernel over all directions at once; vertices of
  *   a level-ordered work list run as soon as their upwind vertices are done
- *   (completion flags between compute units).
+ *   (the level-ordered flux array holds an empty marker until a flux is
+ *   written; waiting vertices poll it).
  * DIRECTION: one workgroup per direction walks that direction's levels with
  *   a workgroup barrier between levels; directions run side by side.
  * DIRECTION_LDS: as DIRECTION, with the recent fluxes of the direction in an
@@ -134,7 +135,7 @@ typedef struct jsweep_graph_s *jsweep_graph;   /* opaque, owned by the library *
  * chosen by jsweep_autotune. */
 typedef struct {
     int32_t waves_per_block;       /* 64-lane wavefronts per workgroup (1..16) */
-    int32_t blocks_per_cu;         /* DATA_DRIVEN: resident workgroups per CU (capped by occupancy) */
+    int32_t blocks_per_cu;         /* DATA_DRIVEN: resident workgroups per CU (at most 4, and occupancy) */
     int32_t inner_sweeps;          /* FP32-refined: maximum inner sweeps per outer residual */
     int32_t chunks_per_ticket;     /* DATA_DRIVEN: work-list chunks a wavefront takes per atomic ticket */
     int32_t strategy;              /* JSWEEP_STRATEGY_* */
@@ -283,8 +284,10 @@ int jsweep_profile_read(jsweep_graph g, int32_t reset, int64_t *launches, double
 /* Tracing of the data-driven sweep (the paper's runtime breakdown into
  * scheduling, waiting and computing).  While enabled, every sweep records,
  * per work-list chunk, three s_memrealtime stamps (100 MHz, low 32 bits):
- * when a wavefront took the chunk, when all of its upwind chunks were
- * complete, and when it published its own completion.
+ * when a wavefront took the chunk (issued the loads of its program), when
+ * every upwind flux of its vertices had arrived, and when it had issued the
+ * stores of its own fluxes.  Tracing runs a variant of the kernel that
+ * writes the stamps.
  * jsweep_trace_read (host buffers, any may be NULL) returns the chunk count,
  * the stamps of the last traced sweep [3 * n_chunks], per chunk (direction,
  * vertex count, level) [3 * n_chunks], and the coarsened graph as CSR

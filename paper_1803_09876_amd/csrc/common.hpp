@@ -179,18 +179,19 @@ struct Graph {
     std::vector<int32_t> dir_stream_h;   // [nd] stream of each direction
     DevBuf dep_ptr, dep;                 // coarsened graph: upwind chunks of every chunk (CSR)
     int64_t n_dep = 0;
-    DevBuf cflag;                        // [n_chunks] uint8 completion epochs
     int ns = 0;                          // sweep program: inflow slots per vertex
     DevBuf pcode, pa64, pa32;            // [ns * S] int32 / double / float (pa32 on first FP32 use)
     DevBuf pden64, pden32;               // [S] double / float
     DevBuf sig_last;                     // [nc] sigma_t the denominators were built for
     bool den64_ok = false, den32_ok = false;
-    DevBuf psi_pos;                      // [nd*nc] fluxes of the running sweep in level order
+    DevBuf psi_pos;                      // [nd*nc] fluxes of the running sweep in level order (LDS-window sweeps)
+    DevBuf dd_pos[2];                    // [nd*nc] alternating level-order flux arrays of the work-list sweep
+    int dd_state[2] = {0, 0};            // element size whose empty marker fills each array, 0 if unknown
+    int dd_cur = 0;                      // array of the next work-list sweep
     DevBuf pvol64, pvol32;               // [64 n_chunks] cell volume in program order (ring sweep)
     DevBuf vsc;                          // [nc] V s (or {V, s}) of the running sweep, per cell
     DevBuf posi;                         // [nd*nc] int32 level position of every vertex
     DevBuf mrank;                        // [nc] int32 rank of every cell in the Morton order of the vertex averages
-    int epoch = 0;                       // last epoch used (1..255)
     DevBuf status;                       // [4] int32 device status words (watchdog)
     // lagged edges, sorted by (direction, downwind cell, upwind cell)
     int64_t n_lag = 0;

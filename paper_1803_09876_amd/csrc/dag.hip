@@ -731,9 +731,7 @@ static void dag_impl(Graph &g, bool lag_cycles, hipStream_t s) {
     JSW_HIP(hipMemcpyAsync(g.stream_off.p, g.stream_off_h.data(), 8 * (kStreams + 1), hipMemcpyHostToDevice, s));
     build_coarsened<NF, DIM>(g, lag, s);
     build_program<NF, DIM>(g, lag, s);
-    g.cflag.alloc(std::max<int64_t>(1, g.n_chunks));
-    JSW_HIP(hipMemsetAsync(g.cflag.p, 0, g.cflag.bytes, s));
-    g.epoch = 0;
+    g.dd_state[0] = g.dd_state[1] = 0;
     g.status.alloc(128 + 32 * 4 * 8);   // status words, then 8 ticket counters 128 B apart
     JSW_HIP(hipMemsetAsync(g.status.p, 0, g.status.bytes, s));
     JSW_HIP(hipStreamSynchronize(s));

@@ -6,12 +6,14 @@
 // order of all of the stream's directions at once, so every direction is in
 // flight together (patch-angle parallelism, paper Sec. V-B).
 //
-// Coarsened graph (paper Sec. V-E): a chunk is a cluster of vertices, and
-// the sweep waits on chunk -> chunk dependencies (the union of its
-// vertices' upwind edges, lagged edges excluded) instead of on single
-// vertices.  Clusters of one level of an acyclic graph give an acyclic
-// coarsened graph (Theorem 1), and every dependency of a chunk comes earlier
-// in its stream.
+// Coarsened graph (paper Sec. V-E): a chunk is a cluster of vertices and the
+// work list is ordered by the clusters' graph (the union of their vertices'
+// upwind edges, lagged edges excluded).  Clusters of one level of an acyclic
+// graph give an acyclic coarsened graph (Theorem 1), and every upwind chunk
+// of a chunk comes earlier in its stream.  A chunk starts as soon as the
+// upwind fluxes of its own vertices are complete, which implies nothing
+// about the rest of the upwind chunks: the wait is per vertex, the order per
+// cluster.
 //
 // Data: a chunk's lanes read the sweep program (common.hpp) at c * 64 +
 // lane -- inflow-face codes and coefficients, denominator -- as coalesced
@@ -19,31 +21,44 @@
 // the upwind fluxes and the cell-order flux store.  Cell records are not
 // read at all.
 //
-// Execution: a persistent grid no larger than the device can hold at once.
-// A running wavefront takes the next chunks of its stream (workgroup id mod
-// kStreams, which is also the XCD the workgroup runs on) with one atomic
-// ticket, polls the completion flags of the chunk's dependencies, then
-// computes one vertex per lane and publishes the chunk's flag.  Only running
-// wavefronts hold chunks and every wavefront walks its stream in order, so
-// the first unfinished chunk of a stream always has all of its inputs: the
-// sweep cannot deadlock on an acyclic graph however many workgroups are
-// resident.  A watchdog turns anything else into an error instead of a
-// hang.
+// Execution: a persistent grid of a few workgroups per CU.  A running
+// wavefront takes chunks of its stream (workgroup id mod kStreams, which is
+// also the XCD the workgroup runs on) with atomic tickets, polls the upwind
+// fluxes of its vertices until all of them are there, then computes one
+// vertex per lane and stores the fluxes.  While it polls, the program of
+// its next chunk is already on the way, and the ticket after that too, so
+// a chunk costs the wavefront one memory round trip when its inputs are
+// ready.  Only running wavefronts hold chunks, every wavefront walks its
+// stream in order, and what it holds beyond the chunk it works on comes
+// later in the stream; so the first unfinished chunk of a stream is always
+// being worked on and has all of its inputs: the sweep cannot deadlock on
+// an acyclic graph however many workgroups are resident.  A watchdog turns
+// anything else into an error instead of a hang.
 //
-// Memory ordering across compute units and XCDs.  Fluxes and chunk flags
-// live in device-local memory, whose L2 copies the memory fabric keeps
-// coherent between XCDs (probes), so a store is visible device-wide once it
-// has reached L2; only the per-CU L1 can hold stale data.  A producer
-// stores its fluxes with ordinary (L1 write-through) stores, waits until
-// they have completed (s_waitcnt: acknowledged by L2) and then stores the
-// chunk flag.  Consumers read flags and fluxes with device-scope loads,
-// which bypass L1, and read fluxes only after seeing the flag.  This is an
-// agent-scope release/acquire without the L2 writeback/invalidate that
-// only non-local memory needs.
+// Completion.  The level-ordered flux array is its own completion flag:
+// before a sweep every entry holds an empty marker (a signalling-NaN bit
+// pattern that no arithmetic produces), and a flux is ready once its entry
+// holds anything else.  Two such arrays alternate between sweeps; while a
+// sweep fills one, it writes the marker into the same entries of the other,
+// so the next sweep starts from an empty array without a separate pass.  A
+// consumer therefore waits on the data it needs with the loads that fetch
+// it, and a producer publishes with the store of the value itself: one
+// memory round trip per dependency instead of a flag poll, a flux load and
+// a store acknowledgement.  Every entry is one naturally aligned 4- or
+// 8-byte store and load, so a reader sees either the marker or the whole
+// value.
+//
+// Memory ordering across compute units and XCDs.  Fluxes live in
+// device-local memory, whose L2 copies the memory fabric keeps coherent
+// between XCDs (probes), so a store is visible device-wide once it has
+// reached L2; only the per-CU L1 can hold stale data.  Producers store with
+// ordinary (L1 write-through) stores; consumers poll with device-scope
+// loads, which bypass L1.  No L2 writeback or invalidate is needed.
 #include <cstring>
 
 #include <algorithm>
 #include <cstdlib>
+#include <limits>
 
 #include "common.hpp"
 
@@ -62,16 +77,16 @@ struct SweepArgs {
     const void *vs;                          // [nc] V s (double) or {V, s} (float2) per cell
     const float *src_dir;                    // [nd*nc] or null (FP32 path)
     Real *psi;                               // [nd*nc] by cell
-    Real *psi_pos;                           // [nd*nc] by level position (upwind reads)
-    uint8_t *cflag;                          // [n_chunks] completion epochs
+    Real *psi_pos;                           // [nd*nc] by level position: this sweep's fluxes (upwind reads)
+    Real *pos_next;                          // [nd*nc] the other level-position array, emptied for the next sweep
     int32_t *status;                         // [0]: stalled flag
     uint32_t *tickets;                       // per-stream counters, 128 B apart
     const int64_t *stream_off;               // [kStreams + 1] chunk range of each stream
     const Real *lag_val;
     Real psi_b;
-    uint32_t epoch;
     int32_t grab;                            // chunks taken per ticket
-    uint32_t nap;                            // s_sleep units between dependency polls
+    uint32_t nap;                            // s_sleep units between input polls
+    uint32_t backoff;                        // the pause doubles every 8 polls, at most this many times
     uint64_t watchdog_ticks;
     uint32_t *stamps;                        // tracing: [3 * n_chunks] or null
 };
@@ -83,6 +98,24 @@ __device__ __forceinline__ T ld_coherent(const T *p) {
 template <class T>
 __device__ __forceinline__ void st_coherent(T *p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Empty marker of the level-position flux arrays: signalling NaNs, which
+// no arithmetic result equals (a NaN result is always quiet)
+constexpr uint64_t kEmpty64 = 0x7ff5a5a5a5a5a5a5ull;
+constexpr uint32_t kEmpty32 = 0x7fa5a5a5u;
+template <class Real>
+__device__ __forceinline__ Real empty_marker() {
+    if constexpr (sizeof(Real) == 8) return __builtin_bit_cast(double, kEmpty64);
+    else return __builtin_bit_cast(float, kEmpty32);
+}
+__device__ __forceinline__ bool is_empty(double v) { return __builtin_bit_cast(uint64_t, v) == kEmpty64; }
+__device__ __forceinline__ bool is_empty(float v) { return __builtin_bit_cast(uint32_t, v) == kEmpty32; }
+
+template <class Real>
+__global__ void k_fill_empty(Real *p, int64_t n) {
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) p[i] = empty_marker<Real>();
 }
 
 // Omega . S of local face j, evaluated left to right.  The FP32 path takes
@@ -107,78 +140,129 @@ __device__ __forceinline__ Real face_dot(const CellRec<Real, NF, DIM> &r, int j,
     return d;
 }
 
-// NS: inflow slots per vertex (the program's ns, up to the faces per cell)
+// A chunk's part of the sweep program as one lane holds it
 template <class Real, int NS>
+struct LaneProg {
+    int32_t item;                            // cell, or -1 past the chunk's end
+    int32_t w2;                              // descriptor word (lanes 0 .. 31)
+    Real den;
+    int32_t code[NS];
+    Real af[NS];
+};
+
+template <class Real, int NS>
+__device__ __forceinline__ void load_prog(const SweepArgs<Real> &a, int64_t c, int lane, LaneProg<Real, NS> &P) {
+    const int32_t *blk = a.cblk + c * kBlock;
+    P.item = blk[lane];
+    P.w2 = lane < 32 ? blk[64 + lane] : -1;
+    const int64_t idx = c * 64 + lane;
+    P.den = a.pden[idx];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        P.code[j] = a.pcode[j * a.stride + idx];
+        P.af[j] = a.pa[j * a.stride + idx];
+    }
+}
+
+// Keeps values in registers up to this point.  A store's data and address
+// registers may only be reused once the store has completed; values kept
+// live until the next chunk's poll has waited for everything (and with it
+// for these stores) leave the compiler no store to wait for earlier.
+template <class T>
+__device__ __forceinline__ void keep_live(const T &v) {
+    asm volatile("" ::"v"(v));
+}
+
+// NS: inflow slots per vertex (the program's ns, up to the faces per cell);
+// TRACE: record take / ready / done stamps per chunk
+template <class Real, int NS, bool TRACE>
 __global__ void k_sweep(SweepArgs<Real> a) {
     const int lane = threadIdx.x & 63;
     const int stream = (int)(blockIdx.x % kStreams);
     const int64_t first = a.stream_off[stream];
     const int64_t per_stream = a.stream_off[stream + 1] - first;
-    const uint8_t epoch = (uint8_t)a.epoch;
-    // tickets: each is a range of a.grab consecutive chunks of the stream;
-    // the next one is requested together with the loads of the last chunk
-    // of the current range, so the two round trips overlap
+    // tickets: each is a range of a.grab consecutive chunks of the stream.
+    // A wavefront holds its current chunk, the next one (whose program is
+    // loaded while the current one waits for its inputs) and one requested
+    // range beyond that, so neither the ticket nor the program load is a
+    // round trip of its own.
     uint32_t *ticket = a.tickets + 32 * stream;
     uint32_t nxt = 0;
     if (lane == 0) nxt = atomicAdd(ticket, (uint32_t)a.grab);
-    int64_t t_next = 0, t_end = 0;
+    int64_t t = (int64_t)__builtin_amdgcn_readfirstlane(nxt);
+    int64_t t_end = t + a.grab;
+    if (lane == 0) nxt = atomicAdd(ticket, (uint32_t)a.grab);
+    if (t >= per_stream) return;
+    LaneProg<Real, NS> P;
+    load_prog(a, first + t, lane, P);
+    uint32_t t_take = (uint32_t)__builtin_amdgcn_s_memrealtime();
+    int64_t pend = (int64_t)__builtin_amdgcn_readfirstlane(nxt);   // start of the requested range
+    __builtin_amdgcn_s_waitcnt(0);   // the loop starts with nothing in flight
+    // the previous chunk's stores: value and addresses (kept live, see keep_live)
+    Real out = Real(0);
+    Real *at_pos = nullptr, *at_cell = nullptr, *at_next = nullptr;
+    uint32_t t_done = 0, t_ready = 0;
     // every lane stays in this loop until the wavefront leaves it as a whole
-    // (ticket broadcast, dependency poll and abort are wave-uniform)
+    // (tickets, the input poll and abort are wave-uniform)
     while (true) {
-        if (t_next == t_end) {
-            t_next = (int64_t)__builtin_amdgcn_readfirstlane(nxt);
-            t_end = t_next + a.grab;
+        const int64_t c = first + t;
+        // next chunk: the rest of this range, else the requested range (and
+        // a new request, read back once this chunk's loads have returned)
+        int64_t tn = t + 1, tn_end = t_end;
+        const bool request = tn == t_end;
+        if (request) {
+            tn = pend;
+            tn_end = tn + a.grab;
+            if (lane == 0) nxt = atomicAdd(ticket, (uint32_t)a.grab);
         }
-        if (t_next >= per_stream) break;
-        const int64_t c = first + t_next;
-        ++t_next;
-        if (t_next == t_end && lane == 0) nxt = atomicAdd(ticket, (uint32_t)a.grab);
-        const uint32_t t_take = (uint32_t)__builtin_amdgcn_s_memrealtime();
-        // one round trip: block (cells, descriptor, upwind chunks) and the
-        // lane's program entries
-        const int32_t *blk = a.cblk + c * kBlock;
-        const int32_t item = blk[lane];
-        const int32_t w2 = lane < 32 ? blk[64 + lane] : -1;
-        const int64_t idx = c * 64 + lane;
-        const Real den = a.pden[idx];
-
-        int32_t code[NS];
-        Real af[NS];
-#pragma unroll
-        for (int j = 0; j < NS; ++j) {
-            code[j] = a.pcode[j * a.stride + idx];
-            af[j] = a.pa[j * a.stride + idx];
+        LaneProg<Real, NS> Pn;
+        uint32_t tn_take = 0;
+        if (tn < per_stream) {
+            load_prog(a, first + tn, lane, Pn);
+            tn_take = (uint32_t)__builtin_amdgcn_s_memrealtime();
         }
-        const uint32_t hdr = (uint32_t)__builtin_amdgcn_readfirstlane(w2);
-        const int ndep = __builtin_amdgcn_readlane(w2, 1);
-        const int64_t pos0 = (int64_t)(uint32_t)__builtin_amdgcn_readlane(w2, 2);
+        const uint32_t hdr = (uint32_t)__builtin_amdgcn_readfirstlane(P.w2);
+        const int64_t pos0 = (int64_t)(uint32_t)__builtin_amdgcn_readlane(P.w2, 2);
         const int m = (int)(hdr & 0xffffu);
-        const bool active = item >= 0;
+        const bool active = P.item >= 0;
         const int64_t base = (int64_t)m * a.nc;
-        const int64_t K = active ? (int64_t)item : 0;
-        // V s of the cell (one gather from a per-cell array)
+        const int64_t K = active ? (int64_t)P.item : 0;
+        const int64_t own = base + pos0 + lane;
+        // V s of the cell (one gather from a per-cell array; in FP32 V and
+        // s, combined with the per-direction source after the poll, so that
+        // nothing waits for these loads before it)
         Real num = Real(0);
+        float2 vs32 = make_float2(0.0f, 0.0f);
+        float sd32 = 0.0f;
         if (active) {
             if constexpr (sizeof(Real) == 8) {
                 num = reinterpret_cast<const double *>(a.vs)[K];
             } else {
-                const float2 vs = reinterpret_cast<const float2 *>(a.vs)[K];
-                float sv = vs.y;
-                if (a.src_dir) sv = a.src_dir[base + pos0 + lane] + sv;
-                num = vs.x * sv;
+                vs32 = reinterpret_cast<const float2 *>(a.vs)[K];
+                if (a.src_dir) sd32 = a.src_dir[own];
             }
         }
-        // wait until every upwind chunk of this sweep is complete (inline
-        // list: lanes 3 .. 3 + ndep hold the upwind chunks)
-        int32_t d0 = 0, d1 = 0;
-        if (ndep < 0) { d0 = a.dep_ptr[c]; d1 = a.dep_ptr[c + 1]; }
+        // upwind fluxes: interior and lagged ones are loaded together (one
+        // device-scope load per slot, the address selected without
+        // branching; other slots read the vertex's own entry and discard
+        // it).  The loads are repeated until no interior slot of any lane
+        // holds the empty marker; polls that keep failing back off.
+        const Real *from[NS];
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            const int32_t cd = P.code[j];
+            const bool lagged = cd <= -2 && cd != kNoFace;
+            from[j] = cd >= 0 ? a.psi_pos + base + cd : lagged ? a.lag_val + (-(int64_t)cd - 2) : a.psi_pos + own;
+        }
+        Real val[NS];
         uint64_t t0 = 0;
         for (uint32_t spin = 0;; ++spin) {
             bool ok = true;
-            if (ndep >= 0) {
-                if (lane >= 3 && lane < 3 + ndep) ok = ld_coherent(a.cflag + w2) == epoch;
-            } else {
-                for (int32_t k = d0 + lane; k < d1; k += 64) ok &= ld_coherent(a.cflag + a.dep[k]) == epoch;
+            if (active) {
+#pragma unroll
+                for (int j = 0; j < NS; ++j) val[j] = ld_coherent(from[j]);
+#pragma unroll
+                for (int j = 0; j < NS; ++j) ok = ok && !(P.code[j] >= 0 && is_empty(val[j]));
             }
             if (__all(ok)) break;
             if (spin == 0) t0 = __builtin_amdgcn_s_memrealtime();
@@ -188,45 +272,65 @@ __global__ void k_sweep(SweepArgs<Real> a) {
                     if (lane == 0) atomicOr(a.status, 1);
                     stop = true;
                 }
-                if (__any(stop)) return;
+                // the wavefront ends here (no barrier in this kernel); an
+                // end of program instead of a jump to the loop's exit keeps
+                // this path's loads in flight out of the loop's other paths
+                if (__any(stop)) __builtin_amdgcn_endpgm();
             }
-            for (uint32_t z = 0; z < a.nap; ++z) __builtin_amdgcn_s_sleep(1);
+            const uint32_t naps = a.nap << min(spin >> 3, a.backoff);
+            for (uint32_t z = 0; z < naps; ++z) __builtin_amdgcn_s_sleep(1);
         }
-        const uint32_t t_ready = (uint32_t)__builtin_amdgcn_s_memrealtime();
-        Real out = Real(0);
+        // every load issued so far has returned, and with them the previous
+        // chunk's stores (the poll waited for them, on every path): said
+        // explicitly, so that nothing after this chunk's stores waits for
+        // them (memory counters retire in order)
+        __builtin_amdgcn_s_waitcnt(0);
+        keep_live(out);
+        keep_live(at_pos);
+        keep_live(at_cell);
+        keep_live(at_next);
+        if constexpr (TRACE) {
+            keep_live(t_ready);
+            keep_live(t_done);
+        }
+        t_ready = (uint32_t)__builtin_amdgcn_s_memrealtime();
+        if (request) pend = (int64_t)__builtin_amdgcn_readfirstlane(nxt);
+        at_pos = a.psi_pos + own;
+        at_cell = a.psi + base + K;
+        at_next = a.pos_next + own;
         if (active) {
-            // upwind fluxes: interior and lagged ones are loaded together
-            // (one device-scope load per slot, the address selected without
-            // branching; other slots read the cell's own entry and discard it)
-            Real val[NS];
-#pragma unroll
-            for (int j = 0; j < NS; ++j) {
-                const int32_t cd = code[j];
-                const bool lagged = cd <= -2 && cd != kNoFace;
-                const Real *src = cd >= 0 ? a.psi_pos + base + cd
-                                  : lagged ? a.lag_val + (-(int64_t)cd - 2) : a.psi_pos + base + pos0 + lane;
-                const Real v = ld_coherent(src);
-                val[j] = (cd >= 0 || lagged) ? v : (cd == -1 ? a.psi_b : Real(0));
-            }
+            if constexpr (sizeof(Real) == 4) num = vs32.x * (a.src_dir ? sd32 + vs32.y : vs32.y);
             // step-scheme balance, inflow faces in local face order
 #pragma unroll
-            for (int j = 0; j < NS; ++j)
-                if (code[j] != kNoFace) num = num + af[j] * val[j];
-            out = num / den;
-            a.psi_pos[base + pos0 + lane] = out;
+            for (int j = 0; j < NS; ++j) {
+                const int32_t cd = P.code[j];
+                const bool lagged = cd <= -2 && cd != kNoFace;
+                const Real v = (cd >= 0 || lagged) ? val[j] : (cd == -1 ? a.psi_b : Real(0));
+                if (cd != kNoFace) num = num + P.af[j] * v;
+            }
+            out = num / P.den;
+            // a NaN carrying the marker's bits (never produced by arithmetic)
+            // would read as not yet computed
+            if (is_empty(out)) out = std::numeric_limits<Real>::quiet_NaN();
+            // the level-order store publishes the flux; the cell-order copy
+            // is read only after the kernel
+            *at_pos = out;
+            *at_cell = out;
+            *at_next = empty_marker<Real>();
         }
-        // publish the chunk once every lane's level-order store has
-        // completed; the cell-order copy is read only after the kernel, so
-        // it is written after the flag, off the dependency chain
-        __builtin_amdgcn_s_waitcnt(0);
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        if (lane == 0) a.cflag[c] = epoch;
-        if (active) a.psi[base + K] = out;
-        if (a.stamps && lane == 0) {
-            a.stamps[3 * c] = t_take;
-            a.stamps[3 * c + 1] = t_ready;
-            a.stamps[3 * c + 2] = (uint32_t)__builtin_amdgcn_s_memrealtime();
+        if constexpr (TRACE) {
+            t_done = (uint32_t)__builtin_amdgcn_s_memrealtime();
+            if (lane == 0) {
+                a.stamps[3 * c] = t_take;
+                a.stamps[3 * c + 1] = t_ready;
+                a.stamps[3 * c + 2] = t_done;
+            }
         }
+        if (tn >= per_stream) break;
+        t = tn;
+        t_end = tn_end;
+        P = Pn;
+        t_take = tn_take;
     }
 }
 
@@ -378,39 +482,47 @@ static uint64_t watchdog_ticks() {
 }
 
 template <class Real, int NS>
-static const void *kernel_ptr() {
-    return reinterpret_cast<const void *>(&k_sweep<Real, NS>);
+static const void *kernel_ptr(bool trace) {
+    return trace ? reinterpret_cast<const void *>(&k_sweep<Real, NS, true>)
+                 : reinterpret_cast<const void *>(&k_sweep<Real, NS, false>);
 }
 
 template <class Real>
-static const void *sweep_kernel_t(int ns) {
+static const void *sweep_kernel_t(int ns, bool trace) {
     switch (ns) {
-    case 1: return kernel_ptr<Real, 1>();
-    case 2: return kernel_ptr<Real, 2>();
-    case 3: return kernel_ptr<Real, 3>();
-    case 4: return kernel_ptr<Real, 4>();
-    case 5: return kernel_ptr<Real, 5>();
-    default: return kernel_ptr<Real, 6>();
+    case 1: return kernel_ptr<Real, 1>(trace);
+    case 2: return kernel_ptr<Real, 2>(trace);
+    case 3: return kernel_ptr<Real, 3>(trace);
+    case 4: return kernel_ptr<Real, 4>(trace);
+    case 5: return kernel_ptr<Real, 5>(trace);
+    default: return kernel_ptr<Real, 6>(trace);
     }
 }
 
-static const void *sweep_kernel(int ns, bool fp32) {
+static const void *sweep_kernel(int ns, bool fp32, bool trace = false) {
     if (ns < 1 || ns > 6) fail(JSWEEP_E_DEVICE, "sweep program with an unsupported number of inflow slots");
-    return fp32 ? sweep_kernel_t<float>(ns) : sweep_kernel_t<double>(ns);
+    return fp32 ? sweep_kernel_t<float>(ns, trace) : sweep_kernel_t<double>(ns, trace);
 }
 
+constexpr int kMaxSweepBlocksPerCU = 4;
+
 int persistent_waves(Graph &g, bool fp32, const jsweep_params *p, int *waves_per_block) {
-    int wpb = (p && p->waves_per_block > 0) ? p->waves_per_block : (g.has_tuned && g.tuned.waves_per_block > 0 ? g.tuned.waves_per_block : 4);
+    // defaults (measured on 0.3M- to 6.6M-chunk graphs): one workgroup per
+    // CU, of four wavefronts below a million chunks and six above
+    const bool big = g.n_chunks >= (int64_t)1000000;
+    int wpb = (p && p->waves_per_block > 0) ? p->waves_per_block
+              : (g.has_tuned && g.tuned.waves_per_block > 0 ? g.tuned.waves_per_block : (big ? 6 : 4));
     if (wpb > 16) wpb = 16;
     int occ = 0;
     JSW_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sweep_kernel(g.ns, fp32), 64 * wpb, 0));
     if (occ < 1) occ = 1;
-    // default: two workgroups per CU for graphs of a few hundred thousand
-    // chunks (fewer wavefronts contend for the critical path), all that fit
-    // for larger ones
+    // at most kMaxSweepBlocksPerCU workgroups per CU: every waiting
+    // wavefront polls its vertices' upwind fluxes, and with all resident
+    // wavefronts polling (measured on 5.3M-cell graphs) the polls crowd out
+    // the loads and stores of the chunks that could run
     int bpc = (p && p->blocks_per_cu > 0) ? p->blocks_per_cu
-              : (g.has_tuned && g.tuned.blocks_per_cu > 0 ? g.tuned.blocks_per_cu
-                                                          : (g.n_chunks < (int64_t)1000000 ? 2 : occ));
+              : (g.has_tuned && g.tuned.blocks_per_cu > 0 ? g.tuned.blocks_per_cu : 1);
+    if (bpc > kMaxSweepBlocksPerCU) bpc = kMaxSweepBlocksPerCU;
     if (bpc > occ) bpc = occ;
     *waves_per_block = wpb;
     return bpc * g.n_cu * wpb;
@@ -465,9 +577,27 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
     a.vs = g.vsc.p;
     a.src_dir = src_dir;
     a.psi = psi;
-    if (g.psi_pos.bytes < (size_t)(8 * g.nc * g.nd)) g.psi_pos.alloc(8 * g.nc * g.nd);
-    a.psi_pos = g.psi_pos.as<Real>();
-    a.cflag = g.cflag.as<uint8_t>();
+    // the two level-position arrays: this sweep's must hold the empty marker
+    // of its precision in every entry (the previous sweep of the same
+    // precision left it so; otherwise it is filled here), and the sweep
+    // empties the other one for the next sweep
+    const int want = (int)sizeof(Real);
+    for (int i = 0; i < 2; ++i)
+        if (g.dd_pos[i].bytes < (size_t)(8 * g.nc * g.nd)) {
+            g.dd_pos[i].alloc(8 * g.nc * g.nd);
+            g.dd_state[i] = 0;
+        }
+    const int cur = g.dd_cur;
+    if (g.dd_state[cur] != want && g.nc * g.nd > 0) {
+        const int64_t n = g.nc * g.nd;
+        k_fill_empty<Real><<<(int)std::min<int64_t>(ceil_div(n, 256), 8192), 256, 0, s>>>(g.dd_pos[cur].as<Real>(), n);
+        JSW_HIP(hipGetLastError());
+    }
+    a.psi_pos = g.dd_pos[cur].as<Real>();
+    a.pos_next = g.dd_pos[1 - cur].as<Real>();
+    g.dd_state[cur] = 0;
+    g.dd_state[1 - cur] = want;
+    g.dd_cur = 1 - cur;
     a.status = g.status.as<int32_t>();
     a.lag_val = reinterpret_cast<const Real *>(f32 ? g.lag_val32.p : g.lag_val64.p);
     a.tickets = reinterpret_cast<uint32_t *>(g.status.as<char>() + 128);
@@ -478,14 +608,14 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
              : (g.has_tuned && g.tuned.chunks_per_ticket > 0 ? g.tuned.chunks_per_ticket
                                                               : (g.n_chunks < (int64_t)1000000 ? 1 : 2));
     a.psi_b = psi_b;
-    g.epoch = g.epoch % 255 + 1;
-    a.epoch = (uint32_t)g.epoch;
     a.watchdog_ticks = watchdog_ticks();
     a.stamps = g.trace ? g.trace_buf.as<uint32_t>() : nullptr;
     if (g.trace) g.trace_units = 0;
     {
         const char *e = std::getenv("JSWEEP_POLL_NAP");
-        a.nap = e ? (uint32_t)std::max(1, std::atoi(e)) : 2u;
+        a.nap = e ? (uint32_t)std::max(1, std::atoi(e)) : 1u;
+        const char *b = std::getenv("JSWEEP_POLL_BACKOFF");
+        a.backoff = b ? (uint32_t)std::min(4, std::max(0, std::atoi(b))) : 3u;
     }
     int wpb = 4;
     int waves = persistent_waves(g, f32, p, &wpb);
@@ -500,7 +630,7 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
         JSW_HIP(hipEventRecord(ev0, s));
     }
     void *args[] = {&a};
-    JSW_HIP(hipLaunchKernel(sweep_kernel(g.ns, f32), dim3(blocks), dim3(64 * wpb), args, 0, s));
+    JSW_HIP(hipLaunchKernel(sweep_kernel(g.ns, f32, a.stamps != nullptr), dim3(blocks), dim3(64 * wpb), args, 0, s));
     if (g.profile) {
         JSW_HIP(hipEventRecord(ev1, s));
         g.prof_events.push_back({ev0, ev1});
@@ -895,12 +1025,12 @@ int check_sweep_status(Graph &g, hipStream_t s) {
     JSW_HIP(hipMemcpyAsync(&st, g.status.p, 4, hipMemcpyDeviceToHost, s));
     JSW_HIP(hipStreamSynchronize(s));
     if (st == 0) return JSWEEP_OK;
-    // a stalled sweep leaves flags in an unknown state: start over
-    JSW_HIP(hipMemsetAsync(g.cflag.p, 0, g.cflag.bytes, s));
+    // a stalled sweep leaves the level-position arrays and the task slots
+    // in an unknown state: start over
+    g.dd_state[0] = g.dd_state[1] = 0;
     if (g.pp.slot.p) JSW_HIP(hipMemsetAsync(g.pp.slot.p, 0, g.pp.slot.bytes, s));
     JSW_HIP(hipMemsetAsync(g.status.p, 0, 64, s));
     JSW_HIP(hipStreamSynchronize(s));
-    g.epoch = 0;
     g.pp.epoch = 0;
     return JSWEEP_E_STALLED;
 }
