@@ -48,12 +48,17 @@
 // 8-byte store and load, so a reader sees either the marker or the whole
 // value.
 //
-// Memory ordering across compute units and XCDs.  Fluxes live in
-// device-local memory, whose L2 copies the memory fabric keeps coherent
-// between XCDs (probes), so a store is visible device-wide once it has
-// reached L2; only the per-CU L1 can hold stale data.  Producers store with
-// ordinary (L1 write-through) stores; consumers poll with device-scope
-// loads, which bypass L1.  No L2 writeback or invalidate is needed.
+// Memory ordering across compute units.  Every hand-off stays inside one
+// XCD: a chunk's upwind chunks are in its own stream, and the workgroups of
+// a stream (ids congruent mod 8) are dispatched to the same XCD, whose L2 is
+// then the point of coherence.  Producers store with ordinary (L1
+// write-through) stores; consumers poll with device-scope loads, which
+// bypass L1 and read L2.  No L2 writeback or invalidate is needed.  Within a
+// kernel the L2s of different XCDs are not coherent for these accesses (a
+// plain store on one XCD was never seen by device-scope polls on another in
+// a two-wavefront test, while a same-XCD hand-off took 0.2 us), so the
+// stream-to-XCD pinning is what makes the hand-off work; between kernels
+// the runtime's cache maintenance makes every result visible.
 #include <cstring>
 
 #include <algorithm>
@@ -152,15 +157,17 @@ struct LaneProg {
 
 template <class Real, int NS>
 __device__ __forceinline__ void load_prog(const SweepArgs<Real> &a, int64_t c, int lane, LaneProg<Real, NS> &P) {
+    // read once per sweep: streamed past the caches (non-temporal), which
+    // leaves L2 to the fluxes being handed off and merged
     const int32_t *blk = a.cblk + c * kBlock;
-    P.item = blk[lane];
-    P.w2 = lane < 32 ? blk[64 + lane] : -1;
+    P.item = __builtin_nontemporal_load(blk + lane);
+    P.w2 = lane < 32 ? __builtin_nontemporal_load(blk + 64 + lane) : -1;
     const int64_t idx = c * 64 + lane;
-    P.den = a.pden[idx];
+    P.den = __builtin_nontemporal_load(a.pden + idx);
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
-        P.code[j] = a.pcode[j * a.stride + idx];
-        P.af[j] = a.pa[j * a.stride + idx];
+        P.code[j] = __builtin_nontemporal_load(a.pcode + j * a.stride + idx);
+        P.af[j] = __builtin_nontemporal_load(a.pa + j * a.stride + idx);
     }
 }
 
@@ -316,7 +323,7 @@ __global__ void k_sweep(SweepArgs<Real> a) {
             // is read only after the kernel
             *at_pos = out;
             *at_cell = out;
-            *at_next = empty_marker<Real>();
+            __builtin_nontemporal_store(empty_marker<Real>(), at_next);   // read in the next sweep
         }
         if constexpr (TRACE) {
             t_done = (uint32_t)__builtin_amdgcn_s_memrealtime();
@@ -507,11 +514,10 @@ static const void *sweep_kernel(int ns, bool fp32, bool trace = false) {
 constexpr int kMaxSweepBlocksPerCU = 4;
 
 int persistent_waves(Graph &g, bool fp32, const jsweep_params *p, int *waves_per_block) {
-    // defaults (measured on 0.3M- to 6.6M-chunk graphs): one workgroup per
-    // CU, of four wavefronts below a million chunks and six above
-    const bool big = g.n_chunks >= (int64_t)1000000;
+    // default (measured on 0.3M- to 6.6M-chunk graphs): one workgroup of
+    // five wavefronts per CU
     int wpb = (p && p->waves_per_block > 0) ? p->waves_per_block
-              : (g.has_tuned && g.tuned.waves_per_block > 0 ? g.tuned.waves_per_block : (big ? 6 : 4));
+              : (g.has_tuned && g.tuned.waves_per_block > 0 ? g.tuned.waves_per_block : 5);
     if (wpb > 16) wpb = 16;
     int occ = 0;
     JSW_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sweep_kernel(g.ns, fp32), 64 * wpb, 0));

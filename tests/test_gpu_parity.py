@@ -178,3 +178,79 @@ def test_fp32_refined_converges_to_oracle(cases, strategy):
         print(f"[refined s{strategy}] {name} outer {st['outer_iters']} sweeps {st['sweeps']} (oracle {len(hist)}) "
               f"rho {st['residual']:.2e} phi rel {err:.3e}", flush=True)
         assert err <= 1e-8, name
+
+
+def test_sweep_precision_switches_and_alternation(cases):
+    """The work-list sweep's level-ordered flux arrays hold an empty marker
+    of the running precision: FP64 sweeps alternating with FP32 correction
+    sweeps (an FP32-refined solve) on one graph keep every FP64 sweep equal
+    to the oracle's, twice in a row each time (both arrays)."""
+    dd = J.Params(strategy=J.JSWEEP_STRATEGY_DATA_DRIVEN)
+    for name, p, og, gg in cases[:4]:
+        J.set_params(gg, dd)
+        try:
+            rng = np.random.default_rng(11)
+            src = rng.uniform(0.0, 2.0, p.n_cells)
+            ref = og.sweep(p.sigma_t, src)
+            for rnd in range(2):
+                for rep in range(2):
+                    psi = dev(np.zeros((p.n_dirs, p.n_cells)))
+                    J.sweep(gg, dev(p.sigma_t), dev(src), psi)
+                    err = rel_max(host(psi), ref)
+                    print(f"[switch] {name} round {rnd} rep {rep} rel {err:.3e}", flush=True)
+                    assert err <= 1e-12, (name, rnd, rep)
+                phi = dev(np.zeros(p.n_cells))
+                J.solve(gg, dev(p.sigma_t), dev(p.sigma_s), dev(p.q), phi, mode=J.JSWEEP_FP32_REFINED, tol=0.0,
+                        max_iter=3, params=dd, allow_not_converged=True)
+        finally:
+            J.set_params(gg, None)
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (8, 4, 2), (16, 4, 4), (5, 9, 1)])
+def test_launch_shapes(cases, shape):
+    """Work-list sweep with other launch shapes (waves per workgroup,
+    workgroups per CU -- capped at 4 -- and chunks per ticket): same fluxes."""
+    wpb, bpc, grab = shape
+    prm = J.Params(waves_per_block=wpb, blocks_per_cu=bpc, chunks_per_ticket=grab,
+                   strategy=J.JSWEEP_STRATEGY_DATA_DRIVEN)
+    for name, p, og, gg in cases[1:4]:
+        ref = og.sweep(p.sigma_t, p.q)
+        J.set_params(gg, prm)
+        try:
+            psi = dev(np.zeros((p.n_dirs, p.n_cells)))
+            J.sweep(gg, dev(p.sigma_t), dev(p.q), psi)
+        finally:
+            J.set_params(gg, None)
+        err = rel_max(host(psi), ref)
+        print(f"[shape {shape}] {name} rel {err:.3e}", flush=True)
+        assert err <= 1e-12, (name, shape)
+
+
+def test_stalled_sweep_reports_and_recovers(oracle_mod, monkeypatch):
+    """A stall, forced from the host with a one-tick watchdog (every wave
+    that has polled eight times in vain gives up and ends), is reported as
+    JSWEEP_E_STALLED; the next sweep on the same graph starts from freshly
+    emptied flux arrays and matches the oracle."""
+    need_gpu()
+    p = W.config(2, "small")
+    og = oracle_mod.graph_for(p)
+    gg = gpu_graph(p)
+    try:
+        J.set_params(gg, J.Params(strategy=J.JSWEEP_STRATEGY_DATA_DRIVEN))
+        ref = og.sweep(p.sigma_t, p.q)
+        psi = dev(np.zeros((p.n_dirs, p.n_cells)))
+        J.sweep(gg, dev(p.sigma_t), dev(p.q), psi)
+        assert rel_max(host(psi), ref) <= 1e-12
+        monkeypatch.setenv("JSWEEP_WATCHDOG_MS", "0.00001")
+        with pytest.raises(J.JsweepError) as e:
+            J.sweep(gg, dev(p.sigma_t), dev(p.q), dev(np.zeros((p.n_dirs, p.n_cells))))
+        assert e.value.code == J.JSWEEP_E_STALLED
+        monkeypatch.delenv("JSWEEP_WATCHDOG_MS")
+        for rep in range(2):
+            psi = dev(np.zeros((p.n_dirs, p.n_cells)))
+            J.sweep(gg, dev(p.sigma_t), dev(p.q), psi)
+            err = rel_max(host(psi), ref)
+            print(f"[stall] recovered sweep {rep} rel {err:.3e}", flush=True)
+            assert err <= 1e-12
+    finally:
+        gg.close()
