@@ -71,9 +71,10 @@ struct Chunk {
 
 // Chunk block, kBlock int32 words: [0, 64) the chunk's cells (-1 past the
 // end), [64] Chunk::a, [65] the number of upwind chunks (-1: more than
-// kBlockDeps, read the CSR lists instead), [66] Chunk::b (the first
-// position), [67, 67 + kBlockDeps) the upwind chunks.  Lane l of a
-// wavefront reads words l and 64 + l (l < 32).
+// kBlockDeps, see the CSR lists), [66] Chunk::b (the first position),
+// [67, 67 + kBlockDeps) the upwind chunks.  Lane l of a wavefront reads
+// words l and 64 + l (l < 32); the work-list sweep uses words 0 - 66 (it
+// waits on the upwind fluxes themselves, not on the upwind chunks).
 constexpr int kBlock = 96;
 constexpr int kBlockDeps = kBlock - 67;
 

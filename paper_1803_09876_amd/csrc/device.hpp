@@ -28,6 +28,30 @@ __device__ inline double dir_sum(const double *w, const T *x, int64_t nc, int nd
     return s;
 }
 
+// dir_sum of the two cells K and K + 1 (K and nc even), each direction's
+// pair read as one 16-byte load; each sum in ascending m as in dir_sum
+__device__ inline void dir_sum2(const double *w, const double *x, int64_t nc, int nd, int64_t K, double &s0,
+                                double &s1) {
+    s0 = 0.0;
+    s1 = 0.0;
+    int m = 0;
+    for (; m + 16 <= nd; m += 16) {
+        double2 v[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = *reinterpret_cast<const double2 *>(x + (int64_t)(m + k) * nc + K);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            s0 = s0 + w[m + k] * v[k].x;
+            s1 = s1 + w[m + k] * v[k].y;
+        }
+    }
+    for (; m < nd; ++m) {
+        const double2 v = *reinterpret_cast<const double2 *>(x + (int64_t)m * nc + K);
+        s0 = s0 + w[m] * v.x;
+        s1 = s1 + w[m] * v.y;
+    }
+}
+
 // One cell of the FP64 residual with the full (un-lagged) streaming
 // operator, looping over directions:
 //   phi_K = sum_m w_m psi_{K,m}

@@ -234,6 +234,38 @@ __global__ void k_phi_delta(const double *psi, const double *w, double wsum, con
     block_add(b, acc + 1);
 }
 
+// k_phi_delta for two consecutive cells per thread (n_cells even), so that
+// every direction's fluxes are read in 16-byte pieces; the same
+// arithmetic per cell
+__global__ void k_phi_delta2(const double *psi, const double *w, double wsum, const double *q, const double *sigma_s,
+                             const double *vol, int64_t nc, int nd, double *phi, double *dcell, double *acc,
+                             double *src_next, double *vs_next) {
+    const int64_t K = 2 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    double a = 0.0, b = 0.0;
+    if (K < nc) {
+        double s[2];
+        dir_sum2(w, psi, nc, nd, K, s[0], s[1]);
+        const double2 ph = *reinterpret_cast<const double2 *>(phi + K);
+        const double2 ss = *reinterpret_cast<const double2 *>(sigma_s + K);
+        const double2 qq = *reinterpret_cast<const double2 *>(q + K);
+        const double2 vv = *reinterpret_cast<const double2 *>(vol + K);
+        const double old[2] = {ph.x, ph.y}, sig[2] = {ss.x, ss.y}, qk[2] = {qq.x, qq.y}, vk[2] = {vv.x, vv.y};
+        double d[2], sn[2];
+        for (int i = 0; i < 2; ++i) {
+            d[i] = sig[i] * (s[i] - old[i]);
+            sn[i] = qk[i] + sig[i] * s[i];
+            a = a + wsum * (vk[i] * (d[i] * d[i]));
+            b = b + vk[i] * (qk[i] * qk[i]);
+        }
+        *reinterpret_cast<double2 *>(phi + K) = make_double2(s[0], s[1]);
+        *reinterpret_cast<double2 *>(dcell + K) = make_double2(d[0], d[1]);
+        *reinterpret_cast<double2 *>(src_next + K) = make_double2(sn[0], sn[1]);
+        *reinterpret_cast<double2 *>(vs_next + K) = make_double2(vk[0] * sn[0], vk[1] * sn[1]);
+    }
+    block_add(a, acc);
+    block_add(b, acc + 1);
+}
+
 // lagged corrections, one thread per (direction, downwind cell) group of
 // the (m, v, u)-sorted lagged edges: w_m V ((d + l)^2 - d^2); thread 0 also
 // copies the sweep status word next to the norms.  For the next sweep it
@@ -366,6 +398,11 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
         // after the first sweep, the residual kernels prepare the next one
         // (source, V s, lagged values, tickets)
         bool prepared = false;
+        // the flux pass takes two cells per thread when every array it
+        // touches allows 16-byte accesses
+        auto al16 = [](const void *p) { return ((uintptr_t)p & 15) == 0; };
+        const bool pairs = g.nc % 2 == 0 && al16(psi) && al16(phi) && al16(q) && al16(sigma_s) && al16(src) &&
+                           al16(dcell) && al16(g.vol.p) && al16(g.vsc.p);
         while (true) {
             if (sweeps >= max_iter) { rc = JSWEEP_E_NOT_CONVERGED; break; }
             double *it_acc = norms.as<double>() + 4 * (fixed ? sweeps : (sweeps & 1));
@@ -379,9 +416,14 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
             ++sweeps;
             // residual of the new iterate from the identity above (one
             // pass over psi for phi, then the lagged edges)
-            k_phi_delta<<<(int)ceil_div(g.nc, kB), kB, 0, s>>>(psi, g.weight.as<double>(), wsum, q, sigma_s,
-                                                               g.vol.as<double>(), g.nc, g.nd, phi, dcell, it_acc,
-                                                               src, g.vsc.as<double>());
+            if (pairs)
+                k_phi_delta2<<<(int)ceil_div(g.nc / 2, kB), kB, 0, s>>>(psi, g.weight.as<double>(), wsum, q, sigma_s,
+                                                                    g.vol.as<double>(), g.nc, g.nd, phi, dcell,
+                                                                    it_acc, src, g.vsc.as<double>());
+            else
+                k_phi_delta<<<(int)ceil_div(g.nc, kB), kB, 0, s>>>(psi, g.weight.as<double>(), wsum, q, sigma_s,
+                                                                   g.vol.as<double>(), g.nc, g.nd, phi, dcell, it_acc,
+                                                                   src, g.vsc.as<double>());
             JSW_HIP(hipGetLastError());
             k_lag_residual<<<(int)ceil_div(nl, kB), kB, 0, s>>>(
                 g.lag_mv.as<uint64_t>(), g.lag_u.as<int32_t>(), g.lag_a.as<double>(), g.lag_val64.as<double>(),

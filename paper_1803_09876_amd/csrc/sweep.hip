@@ -72,8 +72,6 @@ namespace jsw {
 template <class Real>
 struct SweepArgs {
     const int32_t *cblk;                     // [n_chunks * kBlock] chunk blocks
-    const int32_t *dep_ptr;                  // [n_chunks + 1] coarsened-graph in-edges
-    const int32_t *dep;                      // upwind chunks
     int64_t nc;
     int64_t stride;                          // 64 * n_chunks: program slot stride
     const int32_t *pcode;                    // [ns * stride]
@@ -99,10 +97,6 @@ struct SweepArgs {
 template <class T>
 __device__ __forceinline__ T ld_coherent(const T *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <class T>
-__device__ __forceinline__ void st_coherent(T *p, T v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Empty marker of the level-position flux arrays: signalling NaNs, which
@@ -562,8 +556,6 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
     if (!(f32 ? g.den32_ok : g.den64_ok)) fail(JSWEEP_E_DEVICE, "sweep program denominators not built");
     SweepArgs<Real> a;
     a.cblk = g.cblk.as<int32_t>();
-    a.dep_ptr = g.dep_ptr.as<int32_t>();
-    a.dep = g.dep.as<int32_t>();
     a.nc = g.nc;
     a.stride = 64 * g.n_chunks;
     a.pcode = g.pcode.as<int32_t>();
