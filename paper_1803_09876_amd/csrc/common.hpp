@@ -77,6 +77,14 @@ struct Chunk {
 // waits on the upwind fluxes themselves, not on the upwind chunks).
 constexpr int kBlock = 96;
 constexpr int kBlockDeps = kBlock - 67;
+// Compact FP64 program of the work-list sweep (graphs with more than
+// kCompactSlots inflow slots): kCompactSlots slots per lane in the program
+// arrays, and the few further slots as at most kBlockExtra entries in the
+// chunk block: [65] the entry count, [67 + 4 e, 71 + 4 e) entry e = (lane |
+// slot << 8, code, low and high words of a_f).  These words replace the
+// inline upwind chunks, which the work-list sweep does not read.
+constexpr int kCompactSlots = 3;
+constexpr int kBlockExtra = 7;
 
 // Sweep program: per chunk lane (index c * 64 + lane, stride S = 64 *
 // n_chunks) the vertex's inflow faces in local face order, ns slots each:
@@ -182,6 +190,8 @@ struct Graph {
     int64_t n_dep = 0;
     int ns = 0;                          // sweep program: inflow slots per vertex
     DevBuf pcode, pa64, pa32;            // [ns * S] int32 / double / float (pa32 on first FP32 use)
+    DevBuf pcode3, pa3;                  // [kCompactSlots * S] compact FP64 program (see kCompactSlots)
+    int ns_x = 0;                        // slots past kCompactSlots in the blocks; 0: no compact program
     DevBuf pden64, pden32;               // [S] double / float
     DevBuf sig_last;                     // [nc] sigma_t the denominators were built for
     bool den64_ok = false, den32_ok = false;

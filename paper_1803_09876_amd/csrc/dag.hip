@@ -403,6 +403,66 @@ __global__ void k_program(const int32_t *blk, int64_t n_chunks, const CellRec<do
     }
 }
 
+// Compact FP64 program (common.hpp): one 64-lane workgroup per chunk copies
+// its lanes' first kCompactSlots slots and appends the rest, slot by slot
+// and lane by lane, as entries of the chunk block; *too_many is set when a
+// chunk has more than kBlockExtra of them.
+__global__ void k_compact(int32_t *blk, int64_t n_chunks, int ns, const int32_t *code, const double *a,
+                          int32_t *code3, double *a3, int32_t *too_many) {
+    const int64_t c = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (c >= n_chunks) return;
+    const int64_t S = 64 * n_chunks, idx = c * 64 + lane;
+    for (int j = 0; j < kCompactSlots; ++j) {
+        code3[j * S + idx] = code[j * S + idx];
+        a3[j * S + idx] = a[j * S + idx];
+    }
+    int32_t *b = blk + c * kBlock;
+    int n = 0;
+    for (int j = kCompactSlots; j < ns; ++j) {
+        const int32_t cd = code[j * S + idx];
+        const bool has = cd != kNoFace;
+        const uint64_t mask = __ballot(has);
+        const int e = n + __popcll(mask & ((1ull << lane) - 1ull));
+        if (has && e < kBlockExtra) {
+            const uint64_t bits = (uint64_t)__double_as_longlong(a[j * S + idx]);
+            b[67 + 4 * e] = lane | (j << 8);
+            b[68 + 4 * e] = cd;
+            b[69 + 4 * e] = (int32_t)(uint32_t)bits;
+            b[70 + 4 * e] = (int32_t)(uint32_t)(bits >> 32);
+        }
+        n += __popcll(mask);
+    }
+    if (lane == 0) {
+        b[65] = n;
+        if (n > kBlockExtra) atomicOr(too_many, 1);
+    }
+}
+
+static void build_compact(Graph &g, hipStream_t s) {
+    g.ns_x = 0;
+    g.pcode3.release();
+    g.pa3.release();
+    if (g.ns <= kCompactSlots || !g.n_chunks) return;
+    const int64_t nch = g.n_chunks, S = 64 * nch;
+    g.pcode3.alloc(4 * (size_t)kCompactSlots * S);
+    g.pa3.alloc(8 * (size_t)kCompactSlots * S);
+    DevBuf flag(4);
+    JSW_HIP(hipMemsetAsync(flag.p, 0, 4, s));
+    k_compact<<<(unsigned)nch, 64, 0, s>>>(g.cblk.as<int32_t>(), nch, g.ns, g.pcode.as<int32_t>(), g.pa64.as<double>(),
+                                           g.pcode3.as<int32_t>(), g.pa3.as<double>(), flag.as<int32_t>());
+    JSW_HIP(hipGetLastError());
+    int32_t too_many = 0;
+    JSW_HIP(hipMemcpyAsync(&too_many, flag.p, 4, hipMemcpyDeviceToHost, s));
+    JSW_HIP(hipStreamSynchronize(s));
+    if (too_many) {
+        g.pcode3.release();
+        g.pa3.release();
+        return;
+    }
+    g.ns_x = g.ns - kCompactSlots;
+}
+
 // coefficient of every lagged edge, from the program slot that names it
 __global__ void k_lag_coef(const int32_t *code, const double *a, int64_t n, double *lag_a) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -731,6 +791,7 @@ static void dag_impl(Graph &g, bool lag_cycles, hipStream_t s) {
     JSW_HIP(hipMemcpyAsync(g.stream_off.p, g.stream_off_h.data(), 8 * (kStreams + 1), hipMemcpyHostToDevice, s));
     build_coarsened<NF, DIM>(g, lag, s);
     build_program<NF, DIM>(g, lag, s);
+    build_compact(g, s);
     g.dd_state[0] = g.dd_state[1] = 0;
     g.status.alloc(128 + 32 * 4 * 8);   // status words, then 8 ticket counters 128 B apart
     JSW_HIP(hipMemsetAsync(g.status.p, 0, g.status.bytes, s));

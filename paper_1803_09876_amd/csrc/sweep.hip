@@ -50,8 +50,9 @@
 //
 // Memory ordering across compute units.  Every hand-off stays inside one
 // XCD: a chunk's upwind chunks are in its own stream, and the workgroups of
-// a stream (ids congruent mod 8) are dispatched to the same XCD, whose L2 is
-// then the point of coherence.  Producers store with ordinary (L1
+// a stream (ids congruent mod 8) are dispatched to the same XCD (workgroups
+// go round robin over the XCDs of the partition, and 1, 2, 4 or 8 XCDs all
+// divide 8), whose L2 is then the point of coherence.  Producers store with ordinary (L1
 // write-through) stores; consumers poll with device-scope loads, which
 // bypass L1 and read L2.  No L2 writeback or invalidate is needed.  Within a
 // kernel the L2s of different XCDs are not coherent for these accesses (a
@@ -174,10 +175,13 @@ __device__ __forceinline__ void keep_live(const T &v) {
     asm volatile("" ::"v"(v));
 }
 
-// NS: inflow slots per vertex (the program's ns, up to the faces per cell);
+// NS: inflow slots per vertex in the program arrays (the program's ns, up to
+// the faces per cell, or kCompactSlots for the compact program); NSX: slots
+// past NS that the compact program keeps in the chunk blocks (0: none);
 // TRACE: record take / ready / done stamps per chunk
-template <class Real, int NS, bool TRACE>
+template <class Real, int NS, int NSX, bool TRACE>
 __global__ void k_sweep(SweepArgs<Real> a) {
+    constexpr int NX = NSX > 0 ? NSX : 1;
     const int lane = threadIdx.x & 63;
     const int stream = (int)(blockIdx.x % kStreams);
     const int64_t first = a.stream_off[stream];
@@ -255,6 +259,43 @@ __global__ void k_sweep(SweepArgs<Real> a) {
             const bool lagged = cd <= -2 && cd != kNoFace;
             from[j] = cd >= 0 ? a.psi_pos + base + cd : lagged ? a.lag_val + (-(int64_t)cd - 2) : a.psi_pos + own;
         }
+        // the compact program's further slots: the chunk's few entries
+        // (descriptor lanes 3 ..) go to their lanes
+        int32_t code_x[NX];
+        Real af_x[NX], val_x[NX];
+        const Real *from_x[NX];
+        int nx = 0;
+#pragma unroll
+        for (int k = 0; k < NX; ++k) {
+            code_x[k] = kNoFace;
+            af_x[k] = Real(0);
+            val_x[k] = Real(0);
+            from_x[k] = a.psi_pos + own;
+        }
+        if constexpr (NSX > 0) {
+            nx = __builtin_amdgcn_readlane(P.w2, 1);
+            for (int e = 0; e < nx; ++e) {
+                const uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane(P.w2, 3 + 4 * e);
+                const int32_t cd = __builtin_amdgcn_readlane(P.w2, 4 + 4 * e);
+                const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane(P.w2, 5 + 4 * e);
+                const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane(P.w2, 6 + 4 * e);
+                if (lane == (int)(w0 & 63u)) {
+                    const int k = (int)(w0 >> 8) - NS;
+#pragma unroll
+                    for (int kk = 0; kk < NX; ++kk)
+                        if (k == kk) {
+                            code_x[kk] = cd;
+                            af_x[kk] = (Real)__builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+                        }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < NX; ++k) {
+                const int32_t cd = code_x[k];
+                const bool lagged = cd <= -2 && cd != kNoFace;
+                from_x[k] = cd >= 0 ? a.psi_pos + base + cd : lagged ? a.lag_val + (-(int64_t)cd - 2) : a.psi_pos + own;
+            }
+        }
         Real val[NS];
         uint64_t t0 = 0;
         for (uint32_t spin = 0;; ++spin) {
@@ -262,8 +303,16 @@ __global__ void k_sweep(SweepArgs<Real> a) {
             if (active) {
 #pragma unroll
                 for (int j = 0; j < NS; ++j) val[j] = ld_coherent(from[j]);
+                if constexpr (NSX > 0) {
+                    if (nx > 0) {
+#pragma unroll
+                        for (int k = 0; k < NX; ++k) val_x[k] = ld_coherent(from_x[k]);
+                    }
+                }
 #pragma unroll
                 for (int j = 0; j < NS; ++j) ok = ok && !(P.code[j] >= 0 && is_empty(val[j]));
+#pragma unroll
+                for (int k = 0; k < NX; ++k) ok = ok && !(code_x[k] >= 0 && is_empty(val_x[k]));
             }
             if (__all(ok)) break;
             if (spin == 0) t0 = __builtin_amdgcn_s_memrealtime();
@@ -308,6 +357,15 @@ __global__ void k_sweep(SweepArgs<Real> a) {
                 const bool lagged = cd <= -2 && cd != kNoFace;
                 const Real v = (cd >= 0 || lagged) ? val[j] : (cd == -1 ? a.psi_b : Real(0));
                 if (cd != kNoFace) num = num + P.af[j] * v;
+            }
+            if constexpr (NSX > 0) {
+#pragma unroll
+                for (int k = 0; k < NX; ++k) {
+                    const int32_t cd = code_x[k];
+                    const bool lagged = cd <= -2 && cd != kNoFace;
+                    const Real v = (cd >= 0 || lagged) ? val_x[k] : (cd == -1 ? a.psi_b : Real(0));
+                    if (cd != kNoFace) num = num + af_x[k] * v;
+                }
             }
             out = num / P.den;
             // a NaN carrying the marker's bits (never produced by arithmetic)
@@ -482,10 +540,10 @@ static uint64_t watchdog_ticks() {
     return (uint64_t)(ms * 1e5);   // s_memrealtime runs at 100 MHz
 }
 
-template <class Real, int NS>
+template <class Real, int NS, int NSX = 0>
 static const void *kernel_ptr(bool trace) {
-    return trace ? reinterpret_cast<const void *>(&k_sweep<Real, NS, true>)
-                 : reinterpret_cast<const void *>(&k_sweep<Real, NS, false>);
+    return trace ? reinterpret_cast<const void *>(&k_sweep<Real, NS, NSX, true>)
+                 : reinterpret_cast<const void *>(&k_sweep<Real, NS, NSX, false>);
 }
 
 template <class Real>
@@ -500,8 +558,21 @@ static const void *sweep_kernel_t(int ns, bool trace) {
     }
 }
 
-static const void *sweep_kernel(int ns, bool fp32, bool trace = false) {
+// the FP64 sweep of a graph with a compact program reads kCompactSlots
+// slots from the arrays and ns_x from the chunk blocks
+static bool use_compact(const Graph &g, bool fp32) { return !fp32 && g.ns_x > 0; }
+
+static const void *sweep_kernel(const Graph &g, bool fp32, bool trace = false) {
+    const int ns = g.ns;
     if (ns < 1 || ns > 6) fail(JSWEEP_E_DEVICE, "sweep program with an unsupported number of inflow slots");
+    if (use_compact(g, fp32)) {
+        static_assert(kCompactSlots == 3, "compact kernels are instantiated for 3 program slots");
+        switch (g.ns_x) {
+        case 1: return kernel_ptr<double, 3, 1>(trace);
+        case 2: return kernel_ptr<double, 3, 2>(trace);
+        default: return kernel_ptr<double, 3, 3>(trace);
+        }
+    }
     return fp32 ? sweep_kernel_t<float>(ns, trace) : sweep_kernel_t<double>(ns, trace);
 }
 
@@ -514,7 +585,7 @@ int persistent_waves(Graph &g, bool fp32, const jsweep_params *p, int *waves_per
               : (g.has_tuned && g.tuned.waves_per_block > 0 ? g.tuned.waves_per_block : 5);
     if (wpb > 16) wpb = 16;
     int occ = 0;
-    JSW_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sweep_kernel(g.ns, fp32), 64 * wpb, 0));
+    JSW_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sweep_kernel(g, fp32), 64 * wpb, 0));
     if (occ < 1) occ = 1;
     // at most kMaxSweepBlocksPerCU workgroups per CU: every waiting
     // wavefront polls its vertices' upwind fluxes, and with all resident
@@ -558,8 +629,9 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
     a.cblk = g.cblk.as<int32_t>();
     a.nc = g.nc;
     a.stride = 64 * g.n_chunks;
-    a.pcode = g.pcode.as<int32_t>();
-    a.pa = reinterpret_cast<const Real *>(f32 ? g.pa32.p : g.pa64.p);
+    const bool compact = use_compact(g, f32);
+    a.pcode = compact ? g.pcode3.as<int32_t>() : g.pcode.as<int32_t>();
+    a.pa = reinterpret_cast<const Real *>(compact ? g.pa3.p : f32 ? g.pa32.p : g.pa64.p);
     a.pden = reinterpret_cast<const Real *>(f32 ? g.pden32.p : g.pden64.p);
     if (!prepared) {
         if (g.vsc.bytes < (size_t)(8 * g.nc)) g.vsc.alloc(8 * g.nc);
@@ -628,7 +700,7 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
         JSW_HIP(hipEventRecord(ev0, s));
     }
     void *args[] = {&a};
-    JSW_HIP(hipLaunchKernel(sweep_kernel(g.ns, f32, a.stamps != nullptr), dim3(blocks), dim3(64 * wpb), args, 0, s));
+    JSW_HIP(hipLaunchKernel(sweep_kernel(g, f32, a.stamps != nullptr), dim3(blocks), dim3(64 * wpb), args, 0, s));
     if (g.profile) {
         JSW_HIP(hipEventRecord(ev1, s));
         g.prof_events.push_back({ev0, ev1});
