@@ -184,6 +184,16 @@ int jsweep_build_graph(const jsweep_mesh *mesh, const jsweep_quadrature *quad, u
 int jsweep_graph_info(jsweep_graph g, int64_t *n_cells, int32_t *n_dirs, int64_t *n_lagged,
                       int32_t *max_levels);
 
+/* The sweep program of a graph (any pointer may be NULL): *slots = its
+ * inflow slots per vertex (the largest number of inflow faces of any
+ * vertex, at most the faces per cell); *block_slots = how many of those
+ * slots the FP64 work-list sweep reads from the chunk blocks instead of the
+ * program arrays (0: it reads the full program).  Graphs with more than 3
+ * slots get a compact program of 3 slots per vertex when every work-list
+ * chunk has at most 7 further (vertex, slot) pairs; the sweep's results do
+ * not depend on which program it reads. */
+int jsweep_program_info(jsweep_graph g, int32_t *slots, int32_t *block_slots);
+
 /* Export direction dir's graph: in-degree [n_cells], level [n_cells],
  * level pointers [n_levels + 1] and cells ordered by (level, id)
  * [n_cells].  Buffers are caller-allocated, device memory unless flags has

@@ -40,7 +40,7 @@ EXPORTED = [
     "jsweep_build_graph", "jsweep_graph_info", "jsweep_graph_export", "jsweep_graph_lagged", "jsweep_sweep",
     "jsweep_solve", "jsweep_solve_batch", "jsweep_autotune", "jsweep_profile", "jsweep_profile_read",
     "jsweep_trace", "jsweep_trace_read", "jsweep_graph_destroy", "jsweep_error_string", "jsweep_last_error",
-    "jsweep_set_params", "jsweep_patch_info",
+    "jsweep_set_params", "jsweep_patch_info", "jsweep_program_info",
 ]
 
 
@@ -95,6 +95,7 @@ def load_library(path: str | None = None):
     P, i32, i64, dbl, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint32
     lib.jsweep_build_graph.argtypes = [ctypes.POINTER(_Mesh), ctypes.POINTER(_Quad), u32, ctypes.POINTER(P)]
     lib.jsweep_graph_info.argtypes = [P, P, P, P, P]
+    lib.jsweep_program_info.argtypes = [P, P, P]
     lib.jsweep_graph_export.argtypes = [P, i32, P, P, P, P, P, u32]
     lib.jsweep_graph_lagged.argtypes = [P, P, P, P, P]
     lib.jsweep_sweep.argtypes = [P, P, P, P, P, dbl, P]
@@ -116,7 +117,7 @@ def load_library(path: str | None = None):
     for name in ("jsweep_build_graph", "jsweep_graph_info", "jsweep_graph_export", "jsweep_graph_lagged",
                  "jsweep_sweep", "jsweep_solve", "jsweep_solve_batch", "jsweep_autotune", "jsweep_profile",
                  "jsweep_profile_read", "jsweep_trace", "jsweep_trace_read", "jsweep_set_params",
-                 "jsweep_patch_info"):
+                 "jsweep_patch_info", "jsweep_program_info"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -205,6 +206,15 @@ def jsweep_graph_info(g: Graph):
     nc, nd, nl, ml = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32()
     _check(lib.jsweep_graph_info(g.handle, ctypes.byref(nc), ctypes.byref(nd), ctypes.byref(nl), ctypes.byref(ml)))
     return {"n_cells": nc.value, "n_dirs": nd.value, "n_lagged": nl.value, "max_levels": ml.value}
+
+
+def jsweep_program_info(g: Graph):
+    """Sweep program shape: inflow slots per vertex, and how many of them the
+    FP64 work-list sweep reads from the chunk blocks (0: full program)."""
+    lib = load_library()
+    ns, nx = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib.jsweep_program_info(g.handle, ctypes.byref(ns), ctypes.byref(nx)))
+    return {"slots": ns.value, "block_slots": nx.value}
 
 
 def jsweep_graph_export(g: Graph, direction: int):
@@ -357,6 +367,7 @@ def jsweep_last_error() -> str:
 
 # short aliases
 graph_info = jsweep_graph_info
+program_info = jsweep_program_info
 set_params = jsweep_set_params
 patch_info = jsweep_patch_info
 graph_export = jsweep_graph_export

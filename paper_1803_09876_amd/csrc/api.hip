@@ -169,6 +169,16 @@ int jsweep_graph_info(jsweep_graph h, int64_t *n_cells, int32_t *n_dirs, int64_t
     });
 }
 
+int jsweep_program_info(jsweep_graph h, int32_t *slots, int32_t *block_slots) {
+    return guarded([&]() -> int {
+        if (!h) fail(JSWEEP_E_INVALID_ARG, "graph is NULL");
+        Graph &g = *G(h);
+        if (slots) *slots = g.ns;
+        if (block_slots) *block_slots = g.ns_x;
+        return JSWEEP_OK;
+    });
+}
+
 int jsweep_graph_export(jsweep_graph h, int32_t dir, int32_t *indeg, int32_t *level, int64_t *lvl_ptr,
                         int64_t *lvl_cells, int32_t *n_levels, uint32_t flags) {
     return guarded([&]() -> int {

@@ -1,8 +1,9 @@
 """GPU parity at the benchmark sizes, with the default launch configuration.
 
 * jittered 64^3 hexahedra, S8 (262,144 cells x 80 directions, 236 lagged
-  edges): graph arrays and lagged edges bit-exact for every direction, one
-  FP64 sweep and three FP64 source iterations against the oracle;
+  edges): graph arrays and lagged edges bit-exact for every direction, the
+  compact FP64 program in use, one FP64 sweep and three FP64 source
+  iterations against the oracle;
 * Kuhn tetrahedra of a 96^3 lattice, S8 (5.3M cells x 80 directions) and
   of a 60^3 lattice, S16 (1.3M cells x 288 directions): the oracle is built
   for four sampled directions only (directions are independent), and the
@@ -24,6 +25,9 @@ def test_hex64_s8_full(oracle_mod):
     gg = gpu_graph(p)
     info = J.graph_info(gg)
     assert info["n_lagged"] == og.n_lagged > 0 and info["max_levels"] == og.max_levels
+    prog = J.program_info(gg)
+    print(f"[hex64] program {prog}", flush=True)
+    assert prog["slots"] == 5 and prog["block_slots"] == 2   # the compact FP64 program
     for m in range(p.n_dirs):
         for x, y in zip(og.direction(m), J.graph_export(gg, m)):
             assert np.array_equal(x, y), m

@@ -254,3 +254,45 @@ def test_stalled_sweep_reports_and_recovers(oracle_mod, monkeypatch):
             assert err <= 1e-12
     finally:
         gg.close()
+
+
+def test_compact_and_full_programs(oracle_mod, cases):
+    """Meshes with more than 3 inflow slots: the jittered 12^3 hexahedra get
+    the compact FP64 program (3 slots in the arrays, the rest in the chunk
+    blocks); an 8^3 lattice jittered by 0.3 has chunks with too many further
+    slots and keeps the full program.  Both sweep and iterate like the
+    oracle."""
+    need_gpu()
+    name, p, og, gg = cases[1]
+    info = J.program_info(gg)
+    print(f"[program] {name} {info}", flush=True)
+    assert info["slots"] > 3 and info["block_slots"] == info["slots"] - 3
+    om, w = W.quadrature(8, 3)
+    n = 8
+    q = W.Problem("hex8_j30", W.hex_lattice(n, 0.3, 2), om, w, np.full(n ** 3, 1.1), np.full(n ** 3, 0.6),
+                  np.ones(n ** 3))
+    og2 = oracle_mod.graph_for(q)
+    gg2 = gpu_graph(q)
+    try:
+        info = J.program_info(gg2)
+        print(f"[program] {q.name} {info}", flush=True)
+        assert info["slots"] > 3 and info["block_slots"] == 0
+        for g_, o_, pr in ((gg, og, p), (gg2, og2, q)):
+            J.set_params(g_, J.Params(strategy=J.JSWEEP_STRATEGY_DATA_DRIVEN))
+            try:
+                ref = o_.sweep(pr.sigma_t, pr.q)
+                psi = dev(np.zeros((pr.n_dirs, pr.n_cells)))
+                J.sweep(g_, dev(pr.sigma_t), dev(pr.q), psi)
+                assert rel_max(host(psi), ref) <= 1e-12, pr.name
+                psi_ref, phi_ref, _ = o_.source_iteration(pr.sigma_t, pr.sigma_s, pr.q, pr.weight, 5)
+                phi = dev(np.zeros(pr.n_cells))
+                psi = dev(np.zeros((pr.n_dirs, pr.n_cells)))
+                J.solve(g_, dev(pr.sigma_t), dev(pr.sigma_s), dev(pr.q), phi, psi, mode=J.JSWEEP_FP64, tol=0.0,
+                        max_iter=5, params=J.Params(strategy=J.JSWEEP_STRATEGY_DATA_DRIVEN), allow_not_converged=True)
+                e1, e2 = rel_max(host(phi), phi_ref), rel_max(host(psi), psi_ref)
+                print(f"[program] {pr.name} SI5 phi {e1:.2e} psi {e2:.2e}", flush=True)
+                assert e1 <= 1e-12 and e2 <= 1e-12, pr.name
+            finally:
+                J.set_params(g_, None)
+    finally:
+        gg2.close()
