@@ -22,14 +22,16 @@ Also reported:
                 of the same workload on this host;
   time_to_tol   wall time of jsweep_solve to rho <= 1e-8, plain FP64 and
                 FP32-refined, on this workload and on the S16 tetrahedral one
-                (60^3 lattice, 6 tets per cube, 288 directions), with the
-                error of each result against the FP64 GPU fixed point (and the
-                sample sweep's error vs the oracle);
+                (60^3 lattice, 6 tets per cube, 288 directions), each the
+                fastest of three solves after an untimed warm-up of the mode,
+                with the error of each result against the FP64 GPU fixed point
+                (and the sample sweep's error vs the oracle);
   ensemble      256 independent meshes (500-50,000 cells, half triangles,
                 half tets, S4-S8) solved together by jsweep_solve_batch (one
                 sweep launch for every instance and direction): FP64 step
-                throughput and time-to-1e-8, FP64 vs FP32-refined, with the
-                autotuned launch parameters.
+                throughput and time-to-1e-8, FP64 vs FP32-refined (each the
+                fastest of three after a warm-up), with the autotuned launch
+                parameters.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-s16]
                        [--no-ensemble] [--copy-probe] [--steps-only]
@@ -75,20 +77,28 @@ def _traffic(kernel_key: str):
     return rec.get("hbm_bytes_per_launch")
 
 
+TTT_REPEATS = 3
+
+
 def time_to_tol(J, torch, g, p, tol=1e-8):
-    """jsweep_solve to rho <= tol, plain FP64 then FP32-refined, from zero."""
+    """jsweep_solve to rho <= tol, plain FP64 then FP32-refined, from zero;
+    each the fastest of TTT_REPEATS solves after an untimed warm-up."""
     st, ss, q = (torch.tensor(a, device="cuda") for a in (p.sigma_t, p.sigma_s, p.q))
     out, ref = {}, None
     for name, mode in (("fp64", J.JSWEEP_FP64), ("fp32_refined", J.JSWEEP_FP32_REFINED)):
-        phi = torch.zeros(p.n_cells, dtype=torch.float64, device="cuda")
         # untimed warm-up of the mode's kernels (one outer iteration)
-        J.solve(g, st, ss, q, torch.zeros_like(phi), mode=mode, tol=0.0, max_iter=1, allow_not_converged=True)
-        torch.cuda.synchronize()
-        a = time.perf_counter()
-        s = J.solve(g, st, ss, q, phi, mode=mode, tol=tol, max_iter=20000)
-        torch.cuda.synchronize()
-        out[name] = {"seconds": time.perf_counter() - a, "sweeps": s["sweeps"], "outer": s["outer_iters"],
-                     "residual": s["residual"]}
+        J.solve(g, st, ss, q, torch.zeros(p.n_cells, dtype=torch.float64, device="cuda"), mode=mode, tol=0.0,
+                max_iter=1, allow_not_converged=True)
+        best = None
+        for _ in range(TTT_REPEATS):
+            phi = torch.zeros(p.n_cells, dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            s = J.solve(g, st, ss, q, phi, mode=mode, tol=tol, max_iter=20000)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - a
+            best = sec if best is None else min(best, sec)
+        out[name] = {"seconds": best, "sweeps": s["sweeps"], "outer": s["outer_iters"], "residual": s["residual"]}
         if ref is None:
             ref = phi
         else:
@@ -154,12 +164,20 @@ def ensemble_bench(J, W, torch, steps=5):
     out["fp64_updates_per_s"] = upd / step
     ttt, ref = {}, None
     for name, mode in (("fp64", J.JSWEEP_FP64), ("fp32_refined", J.JSWEEP_FP32_REFINED)):
-        pr = problems()
-        torch.cuda.synchronize()
-        a = time.perf_counter()
-        st = J.solve_batch(gs, pr, mode=mode, tol=1e-8, max_iter=20000, params=tuned)
-        torch.cuda.synchronize()
-        ttt[name] = {"seconds": time.perf_counter() - a, "max_sweeps": max(x["sweeps"] for x in st),
+        # untimed warm-up of the mode (its first use builds the FP32 records
+        # and coefficients of every instance), then the fastest of
+        # TTT_REPEATS solves from zero
+        J.solve_batch(gs, problems(), mode=mode, tol=0.0, max_iter=2, params=tuned, allow_not_converged=True)
+        best = None
+        for _ in range(TTT_REPEATS):
+            pr = problems()
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            st = J.solve_batch(gs, pr, mode=mode, tol=1e-8, max_iter=20000, params=tuned)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - a
+            best = sec if best is None else min(best, sec)
+        ttt[name] = {"seconds": best, "max_sweeps": max(x["sweeps"] for x in st),
                      "max_residual": max(x["residual"] for x in st)}
         phis = torch.cat([x["phi"] for x in pr])
         if ref is None:
