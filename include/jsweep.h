@@ -125,6 +125,8 @@ typedef struct jsweep_graph_s *jsweep_graph;   /* opaque, owned by the library *
  *   first PATCH sweep; FP64 sweeps only (FP32 sweeps use DATA_DRIVEN);
  *   graphs above 2^26 (cell, direction) pairs or whose tasks exceed the
  *   kernel's LDS limits fall back to DATA_DRIVEN. */
+/* AUTO (and no strategy set) is DATA_DRIVEN for a single graph; the
+ * batched solve picks between its own direction kernels. */
 #define JSWEEP_STRATEGY_AUTO 0
 #define JSWEEP_STRATEGY_DATA_DRIVEN 1
 #define JSWEEP_STRATEGY_DIRECTION 2

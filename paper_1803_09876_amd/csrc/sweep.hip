@@ -1043,21 +1043,15 @@ static void launch_ring(Graph &g, const Real *src_cell, const float *src_dir, Re
     }
 }
 
-// Sweep strategy (unless requested or tuned), from measurements:
-// - the LDS-window direction kernel for small graphs when it applies (its
-//   per-sweep expansion of V s into program order costs a gather per
-//   vertex, which only small graphs amortise);
-// - the direction-parallel kernel for other small graphs (a sweep is a chain
-//   of short levels, and no level is handed between CUs);
-// - otherwise the data-driven persistent kernel, which keeps many levels of
-//   every direction in flight.
+// Sweep strategy: the requested or tuned one, else the data-driven
+// persistent kernel, which keeps many levels of every direction in flight
+// (the direction kernels, with a barrier per level, are slower on every
+// graph measured).
 int sweep_strategy(const Graph &g, const jsweep_params *p) {
     int st = (p && p->strategy > 0) ? p->strategy : (g.has_tuned && g.tuned.strategy > 0 ? g.tuned.strategy : 0);
     if (st == JSWEEP_STRATEGY_DATA_DRIVEN || st == JSWEEP_STRATEGY_DIRECTION || st == JSWEEP_STRATEGY_PATCH) return st;
     if (st == JSWEEP_STRATEGY_DIRECTION_LDS) return ring_items(g, false) ? st : JSWEEP_STRATEGY_DIRECTION;
-    const bool small = g.nc * g.nd <= (int64_t)2000000;
-    if (ring_items(g, false) && small) return JSWEEP_STRATEGY_DIRECTION_LDS;
-    return small ? JSWEEP_STRATEGY_DIRECTION : JSWEEP_STRATEGY_DATA_DRIVEN;
+    return JSWEEP_STRATEGY_DATA_DRIVEN;
 }
 
 template <class Real, int NF, int DIM>
