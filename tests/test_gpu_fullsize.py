@@ -60,6 +60,8 @@ def test_tet_full_sampled_directions(oracle_mod, k, sample):
     p = W.config(k)
     print(f"[case] {p.name} cells={p.n_cells} dirs={p.n_dirs} sample={sample}", flush=True)
     gg = gpu_graph(p)
+    prog = J.program_info(gg)
+    assert prog["slots"] <= 3 and prog["block_slots"] == 0   # a tet has at most 3 inflow faces
     og = oracle_mod.Graph(p.mesh, p.omega[sample])
     for i, m in enumerate(sample):
         for x, y in zip(og.direction(i), J.graph_export(gg, m)):
