@@ -296,3 +296,48 @@ def test_compact_and_full_programs(oracle_mod, cases):
                 J.set_params(g_, None)
     finally:
         gg2.close()
+
+
+def _tiny_problems():
+    """The smallest meshes of each kind: one hexahedron, the 6 Kuhn
+    tetrahedra of one cube, the triangles of a 2x2 point set; a pure
+    absorber (c = 0) and a strong scatterer with boundary inflow."""
+    om3, w3 = W.quadrature(8, 3)
+    om2, w2 = W.quadrature(4, 2)
+    out = []
+    for name, mesh, om, w in (("hex1", W.hex_lattice(1), om3, w3), ("kuhn1", W.kuhn_tets(1), om3, w3),
+                              ("tri2x2", W.delaunay_2d(2, 2, 0.0, 0), om2, w2)):
+        n = mesh.n_cells
+        out.append((name + "_absorber", W.Problem(name, mesh, om, w, np.full(n, 2.0), np.zeros(n), np.ones(n)), 0.0))
+        out.append((name + "_scatter", W.Problem(name, mesh, om, w, np.full(n, 1.0), np.full(n, 0.99), np.ones(n)),
+                    0.5))
+    return out
+
+
+@pytest.mark.parametrize("strategy", [J.JSWEEP_STRATEGY_DATA_DRIVEN, J.JSWEEP_STRATEGY_DIRECTION,
+                                      J.JSWEEP_STRATEGY_DIRECTION_LDS, J.JSWEEP_STRATEGY_PATCH])
+def test_tiny_meshes(oracle_mod, strategy):
+    """Degenerate sizes: every chunk holds one or a few vertices, every
+    vertex is a boundary vertex.  One FP64 sweep (with boundary inflow) and
+    10 FP64 source iterations match the oracle."""
+    need_gpu()
+    for name, p, psi_b in _tiny_problems():
+        og = oracle_mod.graph_for(p)
+        gg = gpu_graph(p)
+        try:
+            J.set_params(gg, J.Params(strategy=strategy))
+            ref = og.sweep(p.sigma_t, p.q, psi_b)
+            psi = dev(np.zeros((p.n_dirs, p.n_cells)))
+            J.sweep(gg, dev(p.sigma_t), dev(p.q), psi, psi_boundary=psi_b)
+            err = rel_max(host(psi), ref)
+            psi_ref, phi_ref, _ = og.source_iteration(p.sigma_t, p.sigma_s, p.q, p.weight, 10, psi_b=psi_b)
+            phi = dev(np.zeros(p.n_cells))
+            psi2 = dev(np.zeros((p.n_dirs, p.n_cells)))
+            J.solve(gg, dev(p.sigma_t), dev(p.sigma_s), dev(p.q), phi, psi2, psi_boundary=psi_b, mode=J.JSWEEP_FP64,
+                    tol=0.0, max_iter=10, params=J.Params(strategy=strategy), allow_not_converged=True)
+            e1, e2 = rel_max(host(phi), phi_ref), rel_max(host(psi2), psi_ref)
+            print(f"[tiny s{strategy}] {name} cells {p.n_cells} sweep {err:.2e} SI phi {e1:.2e} psi {e2:.2e}",
+                  flush=True)
+            assert err <= 1e-12 and e1 <= 1e-12 and e2 <= 1e-12, name
+        finally:
+            gg.close()
