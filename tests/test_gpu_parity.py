@@ -341,3 +341,40 @@ def test_tiny_meshes(oracle_mod, strategy):
             assert err <= 1e-12 and e1 <= 1e-12 and e2 <= 1e-12, name
         finally:
             gg.close()
+
+
+@pytest.mark.parametrize("strategy", [J.JSWEEP_STRATEGY_DATA_DRIVEN, J.JSWEEP_STRATEGY_DIRECTION])
+def test_directions_parallel_to_faces(oracle_mod, strategy):
+    """Omega . S == 0: on an undeformed 5^3 lattice, directions along the
+    axes and in the coordinate planes are parallel to whole families of
+    faces, which then carry no edge and no flux (neither inflow nor
+    outflow).  Sweep and 10 source iterations match the oracle."""
+    need_gpu()
+    om = np.array([[1.0, 0.0, 0.0], [0.0, -1.0, 0.0], [0.0, 0.0, 1.0], [0.6, 0.8, 0.0], [0.0, -0.6, -0.8],
+                   [-1.0, 0.0, 0.0], [0.48, 0.6, 0.64]])
+    om = om / np.linalg.norm(om, axis=1, keepdims=True)
+    w = np.full(len(om), 1.0 / len(om))
+    n = 5
+    mesh = W.hex_lattice(n)
+    p = W.Problem("hex5_parallel", mesh, om, w, np.full(n ** 3, 1.5), np.full(n ** 3, 0.7), np.ones(n ** 3))
+    og = oracle_mod.graph_for(p)
+    gg = gpu_graph(p)
+    try:
+        J.set_params(gg, J.Params(strategy=strategy))
+        for m in range(p.n_dirs):
+            for x, y in zip(og.direction(m), J.graph_export(gg, m)):
+                assert np.array_equal(x, y), m
+        ref = og.sweep(p.sigma_t, p.q, 0.3)
+        psi = dev(np.zeros((p.n_dirs, p.n_cells)))
+        J.sweep(gg, dev(p.sigma_t), dev(p.q), psi, psi_boundary=0.3)
+        err = rel_max(host(psi), ref)
+        psi_ref, phi_ref, _ = og.source_iteration(p.sigma_t, p.sigma_s, p.q, p.weight, 10, psi_b=0.3)
+        phi = dev(np.zeros(p.n_cells))
+        psi2 = dev(np.zeros((p.n_dirs, p.n_cells)))
+        J.solve(gg, dev(p.sigma_t), dev(p.sigma_s), dev(p.q), phi, psi2, psi_boundary=0.3, mode=J.JSWEEP_FP64, tol=0.0,
+                max_iter=10, params=J.Params(strategy=strategy), allow_not_converged=True)
+        e1, e2 = rel_max(host(phi), phi_ref), rel_max(host(psi2), psi_ref)
+        print(f"[parallel s{strategy}] sweep {err:.2e} SI phi {e1:.2e} psi {e2:.2e}", flush=True)
+        assert err <= 1e-12 and e1 <= 1e-12 and e2 <= 1e-12
+    finally:
+        gg.close()
