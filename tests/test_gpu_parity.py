@@ -378,3 +378,41 @@ def test_directions_parallel_to_faces(oracle_mod, strategy):
         assert err <= 1e-12 and e1 <= 1e-12 and e2 <= 1e-12
     finally:
         gg.close()
+
+
+@pytest.mark.parametrize("strategy", [J.JSWEEP_STRATEGY_DATA_DRIVEN, J.JSWEEP_STRATEGY_DIRECTION_LDS,
+                                      J.JSWEEP_STRATEGY_PATCH])
+def test_many_directions(oracle_mod, strategy):
+    """2,000 seeded random directions (beyond the PATCH program's 1,023,
+    which then falls back to the work list) on 48 jittered Kuhn tetrahedra:
+    sampled graph arrays bit-exact, sweep and 5 source iterations match the
+    oracle."""
+    need_gpu()
+    rng = np.random.default_rng(17)
+    om = rng.normal(size=(2000, 3))
+    om = om / np.linalg.norm(om, axis=1, keepdims=True)
+    w = np.full(len(om), 1.0 / len(om))
+    mesh = W.kuhn_tets(2, 0.15, 3)
+    n = mesh.n_cells
+    p = W.Problem("kuhn2_2000dirs", mesh, om, w, np.full(n, 1.2), np.full(n, 0.8), np.ones(n))
+    og = oracle_mod.graph_for(p)
+    gg = gpu_graph(p)
+    try:
+        for m in (0, 999, 1023, 1999):
+            for x, y in zip(og.direction(m), J.graph_export(gg, m)):
+                assert np.array_equal(x, y), m
+        J.set_params(gg, J.Params(strategy=strategy))
+        ref = og.sweep(p.sigma_t, p.q)
+        psi = dev(np.zeros((p.n_dirs, p.n_cells)))
+        J.sweep(gg, dev(p.sigma_t), dev(p.q), psi)
+        err = rel_max(host(psi), ref)
+        psi_ref, phi_ref, _ = og.source_iteration(p.sigma_t, p.sigma_s, p.q, p.weight, 5)
+        phi = dev(np.zeros(p.n_cells))
+        psi2 = dev(np.zeros((p.n_dirs, p.n_cells)))
+        J.solve(gg, dev(p.sigma_t), dev(p.sigma_s), dev(p.q), phi, psi2, mode=J.JSWEEP_FP64, tol=0.0, max_iter=5,
+                params=J.Params(strategy=strategy), allow_not_converged=True)
+        e1, e2 = rel_max(host(phi), phi_ref), rel_max(host(psi2), psi_ref)
+        print(f"[many dirs s{strategy}] sweep {err:.2e} SI phi {e1:.2e} psi {e2:.2e}", flush=True)
+        assert err <= 1e-12 and e1 <= 1e-12 and e2 <= 1e-12
+    finally:
+        gg.close()
