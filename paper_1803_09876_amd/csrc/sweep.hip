@@ -580,9 +580,10 @@ constexpr int kMaxSweepBlocksPerCU = 4;
 
 int persistent_waves(Graph &g, bool fp32, const jsweep_params *p, int *waves_per_block) {
     // default (measured on 0.3M- to 6.6M-chunk graphs): one workgroup of
-    // five wavefronts per CU
+    // five wavefronts per CU, six for FP32 sweeps above a million chunks
+    const int wpb_default = fp32 && g.n_chunks >= (int64_t)1000000 ? 6 : 5;
     int wpb = (p && p->waves_per_block > 0) ? p->waves_per_block
-              : (g.has_tuned && g.tuned.waves_per_block > 0 ? g.tuned.waves_per_block : 5);
+              : (g.has_tuned && g.tuned.waves_per_block > 0 ? g.tuned.waves_per_block : wpb_default);
     if (wpb > 16) wpb = 16;
     int occ = 0;
     JSW_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sweep_kernel(g, fp32), 64 * wpb, 0));
