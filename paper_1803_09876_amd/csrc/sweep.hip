@@ -244,7 +244,7 @@ __global__ void k_sweep(SweepArgs<Real> a) {
                 num = reinterpret_cast<const double *>(a.vs)[K];
             } else {
                 vs32 = reinterpret_cast<const float2 *>(a.vs)[K];
-                if (a.src_dir) sd32 = a.src_dir[own];
+                if (a.src_dir) sd32 = __builtin_nontemporal_load(a.src_dir + own);   // read once per sweep
             }
         }
         // upwind fluxes: interior and lagged ones are loaded together (one
