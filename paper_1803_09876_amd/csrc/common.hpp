@@ -243,13 +243,14 @@ struct SweepSrc {
 void refresh_sigma(Graph &g, const double *sigma_t, bool fp32, hipStream_t s);
 // sweep-program denominators from the records' sigma_t V, where not valid
 void ensure_den(Graph &g, bool fp32, hipStream_t s);
-// prepared: g.vsc already holds V s of src_cell for this sweep and the
-// data-driven kernel's tickets are zero (the FP64 solve prepares the next
-// sweep in its residual kernels)
+// prepared: g.vsc already holds V s of src_cell for this sweep (FP64) or
+// the (V, s) pairs (FP32) and the data-driven kernel's tickets are zero (the
+// FP64 solve prepares the next sweep in its residual kernels, the FP32
+// correction solve in k_dphi)
 void launch_sweep64(Graph &g, const double *src_cell, double *psi, double psi_b, const jsweep_params *p, hipStream_t s,
                     bool prepared = false);
 void launch_sweep32(Graph &g, const float *src_dir, const float *src_cell, float *psi, const jsweep_params *p,
-                    hipStream_t s);
+                    hipStream_t s, bool prepared = false);
 int check_sweep_status(Graph &g, hipStream_t s);   // JSWEEP_OK or JSWEEP_E_STALLED
 int persistent_waves(Graph &g, bool fp32, const jsweep_params *p, int *waves_per_block);
 int sweep_strategy(const Graph &g, const jsweep_params *p);

@@ -56,34 +56,25 @@ __device__ inline void dir_sum2(const double *w, const double *x, int64_t nc, in
 // operator, looping over directions:
 //   phi_K = sum_m w_m psi_{K,m}
 //   r_{K,m} = q_K + sigma_s,K phi_K - (den psi_{K,m} - in_{K,m}) / V_K
-// Returns V_K sum_m w_m r^2 (and writes phi_K; r in FP32 when r32 != null,
-// at the vertex's level position posi[m nc + K] within direction m).
+// Returns V_K sum_m w_m r^2 (and writes phi_K).  When r32 != null, r is
+// stored in FP32: at the vertex's level position posi[m nc + K] within
+// direction m, or at m nc + K (cell order) when posi is null.
 template <int NF, int DIM>
 __device__ inline double residual_cell(const CellRec<double, NF, DIM> &r, int64_t K, const double *omega,
                                        const double *w, const double *psi, double q, double sigma_s, double psi_b,
                                        int64_t nc, int nd, double *phi, float *r32, const int32_t *posi) {
-    int64_t nb[NF];
-    for (int j = 0; j < NF; ++j) nb[j] = r.nbr[j] <= -2 ? (int64_t)(-r.nbr[j] - 2) : (int64_t)r.nbr[j];
+    int32_t nb[NF];
+#pragma unroll
+    for (int j = 0; j < NF; ++j) nb[j] = r.nbr[j] <= -2 ? -r.nbr[j] - 2 : r.nbr[j];
     const double ph = dir_sum(w, psi, nc, nd, K);
     phi[K] = ph;
     const double src = q + sigma_s * ph;
-    // residual of direction m from the loaded fluxes (own and neighbours)
-    auto res_of = [&](int m, double own, const double (&up)[NF]) {
-        const double *om = omega + 3 * m;
-        double in = 0.0, den = r.sigV;
-        for (int j = 0; j < NF; ++j) {
-            double d = om[0] * r.S[j][0] + om[1] * r.S[j][1];
-            if constexpr (DIM == 3) d = d + om[2] * r.S[j][2];
-            if (d < 0.0) in = in + (-d) * (nb[j] < 0 ? psi_b : up[j]);
-            else if (d > 0.0) den = den + d;
-        }
-        return src - (den * own - in) / r.V;
-    };
-    // four directions' fluxes are loaded before any is used
-    constexpr int B = 4;
+    // B directions' fluxes (own and neighbours) are loaded before any is
+    // used: four, or three for hexahedra, whose records and neighbour
+    // fluxes would otherwise not fit in 128 registers
+    constexpr int B = NF >= 6 ? 3 : 4;
     double cell = 0.0;
-    int m = 0;
-    for (; m < nd; m += B) {
+    for (int m = 0; m < nd; m += B) {
         double own[B], up[B][NF];
 #pragma unroll
         for (int k = 0; k < B; ++k) {
@@ -95,10 +86,23 @@ __device__ inline double residual_cell(const CellRec<double, NF, DIM> &r, int64_
         }
 #pragma unroll
         for (int k = 0; k < B; ++k) {
-            if (m + k >= nd) break;
-            const double res = res_of(m + k, own[k], up[k]);
-            if (r32) r32[(int64_t)(m + k) * nc + posi[(int64_t)(m + k) * nc + K]] = (float)res;
-            cell = cell + w[m + k] * (res * res);
+            if (m + k < nd) {
+                const double *om = omega + 3 * (m + k);
+                double in = 0.0, den = r.sigV;
+#pragma unroll
+                for (int j = 0; j < NF; ++j) {
+                    double d = om[0] * r.S[j][0] + om[1] * r.S[j][1];
+                    if constexpr (DIM == 3) d = d + om[2] * r.S[j][2];
+                    if (d < 0.0) in = in + (-d) * (nb[j] < 0 ? psi_b : up[k][j]);
+                    else if (d > 0.0) den = den + d;
+                }
+                const double res = src - (den * own[k] - in) / r.V;
+                if (r32) {
+                    const int64_t o = (int64_t)(m + k) * nc;
+                    r32[o + (posi ? (int64_t)posi[o + K] : K)] = (float)res;
+                }
+                cell = cell + w[m + k] * (res * res);
+            }
         }
     }
     return r.V * cell;

@@ -308,20 +308,68 @@ __global__ void k_qnorm(const double *q, const double *vol, int64_t nc, double *
 // V-weighted norm of dphi and that of sigma_s (dphi - dphi_prev): by the
 // sweep identity the latter is the isotropic part of the correction
 // equation's residual, i.e. of the outer residual once the correction is
-// applied
+// applied.  It also prepares the next inner sweep: the (V, source) pairs
+// the sweep kernel reads, the lagged-edge values of this iterate, zeroed
+// accumulators (acc_next) and stream tickets.  CPT consecutive cells per
+// thread (1, or 4 when n_cells is a multiple of 4 and dpsi 16-byte
+// aligned: every direction's fluxes are then read in 16-byte pieces); each
+// cell's sum over directions in ascending m either way.
+template <int CPT>
 __global__ void k_dphi(const float *dpsi, const double *w, const double *sigma_s, const double *vol, int64_t nc, int nd,
-                       const double *q, double *dphi, float *g32, const int32_t *status, double *acc) {
-    int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (K == 0) acc[2] = (double)status[0];
+                       const double *q, double *dphi, float *g32, const int32_t *status, double *acc,
+                       double *acc_next, float2 *vs, uint32_t *tickets, const uint64_t *lag_mv,
+                       const int32_t *lag_u, int64_t n_lag, float *lag_val) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) acc[2] = (double)status[0];
+    if (t < 2) acc_next[t] = 0.0;
+    if (t < kStreams) tickets[32 * t] = 0u;
+    for (int64_t e = t; e < n_lag; e += (int64_t)gridDim.x * blockDim.x)
+        lag_val[e] = dpsi[(int64_t)(lag_mv[e] >> 32) * nc + lag_u[e]];
     double a = 0.0, b = 0.0;
-    if (K < nc) {
-        const double s = dir_sum(w, dpsi, nc, nd, K);
-        double old = dphi[K];
-        dphi[K] = s;
-        g32[K] = q ? (float)(q[K] + sigma_s[K] * s) : (float)(sigma_s[K] * s);
-        a = vol[K] * (s * s);
-        const double d = sigma_s[K] * (s - old);
-        b = vol[K] * (d * d);
+    const int64_t K0 = t * CPT;
+    if (K0 < nc) {
+        double sum[CPT];
+        if constexpr (CPT == 1) {
+            sum[0] = dir_sum(w, dpsi, nc, nd, K0);
+        } else {
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) sum[c] = 0.0;
+            int m = 0;
+            for (; m + 16 <= nd; m += 16) {
+                float4 v[16];
+#pragma unroll
+                for (int k = 0; k < 16; ++k) v[k] = *reinterpret_cast<const float4 *>(dpsi + (int64_t)(m + k) * nc + K0);
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    const double wk = w[m + k];
+                    sum[0] = sum[0] + wk * (double)v[k].x;
+                    sum[1] = sum[1] + wk * (double)v[k].y;
+                    sum[2] = sum[2] + wk * (double)v[k].z;
+                    sum[3] = sum[3] + wk * (double)v[k].w;
+                }
+            }
+            for (; m < nd; ++m) {
+                const float4 v = *reinterpret_cast<const float4 *>(dpsi + (int64_t)m * nc + K0);
+                const double wk = w[m];
+                sum[0] = sum[0] + wk * (double)v.x;
+                sum[1] = sum[1] + wk * (double)v.y;
+                sum[2] = sum[2] + wk * (double)v.z;
+                sum[3] = sum[3] + wk * (double)v.w;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const int64_t K = K0 + c;
+            const double s = sum[c];
+            const double old = dphi[K];
+            dphi[K] = s;
+            const float src = q ? (float)(q[K] + sigma_s[K] * s) : (float)(sigma_s[K] * s);
+            g32[K] = src;
+            vs[K] = make_float2((float)vol[K], src);
+            a = a + vol[K] * (s * s);
+            const double d = sigma_s[K] * (s - old);
+            b = b + vol[K] * (d * d);
+        }
     }
     block_add(a, acc);
     block_add(b, acc + 1);
@@ -333,18 +381,44 @@ __global__ void k_update(double *psi, const float *dpsi, int64_t n) {
     if (i < n) psi[i] = psi[i] + (double)dpsi[i];
 }
 
+// r in level-position order from its cell-order copy:
+//   r32[m nc + p] = rc[m nc + lvl_cells[m nc + p]].
+// Workgroup b works on block (b mod 8) * per_xcd + b / 8, so each XCD takes
+// one contiguous eighth of the entries and gathers every direction's
+// cell-order values through its own L2.
+__global__ void k_level_order(const float *rc, const int32_t *lvl_cells, int64_t nc, int64_t n, int64_t per_xcd,
+                              float *r32) {
+    const int64_t blk = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    const int64_t i = blk * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t m = i / nc;
+    r32[i] = rc[m * nc + lvl_cells[i]];
+}
+
+// FP64 residual rho = ||r||_V / ||q||_V.  With r32, r is also stored in FP32
+// in level-position order for the correction sweep: the residual kernel
+// writes it in cell order into rc (n_cells * n_dirs floats, coalesced) and
+// k_level_order permutes it, which costs far less than scattering 4-byte
+// stores from the residual kernel.
 static double residual(Graph &g, const double *psi, const double *q, const double *sigma_s, double psi_b, double *phi,
-                       float *r32, double *acc, hipStream_t s, double *qq = nullptr) {
+                       float *r32, float *rc, double *acc, hipStream_t s, double *qq = nullptr) {
     JSW_HIP(hipMemsetAsync(acc, 0, 16, s));
     int gb = (int)ceil_div(g.nc, kB);
     const double *om = g.omega64.as<double>(), *w = g.weight.as<double>();
+    float *out = r32 ? rc : nullptr;
     if (g.ctype == JSWEEP_TRI)
-        k_residual<3, 2><<<gb, kB, 0, s>>>(g.rec64.as<CellRec<double, 3, 2>>(), om, w, psi, q, sigma_s, psi_b, g.nc, g.nd, phi, r32, g.posi.as<int32_t>(), acc);
+        k_residual<3, 2><<<gb, kB, 0, s>>>(g.rec64.as<CellRec<double, 3, 2>>(), om, w, psi, q, sigma_s, psi_b, g.nc, g.nd, phi, out, nullptr, acc);
     else if (g.ctype == JSWEEP_TET)
-        k_residual<4, 3><<<gb, kB, 0, s>>>(g.rec64.as<CellRec<double, 4, 3>>(), om, w, psi, q, sigma_s, psi_b, g.nc, g.nd, phi, r32, g.posi.as<int32_t>(), acc);
+        k_residual<4, 3><<<gb, kB, 0, s>>>(g.rec64.as<CellRec<double, 4, 3>>(), om, w, psi, q, sigma_s, psi_b, g.nc, g.nd, phi, out, nullptr, acc);
     else
-        k_residual<6, 3><<<gb, kB, 0, s>>>(g.rec64.as<CellRec<double, 6, 3>>(), om, w, psi, q, sigma_s, psi_b, g.nc, g.nd, phi, r32, g.posi.as<int32_t>(), acc);
+        k_residual<6, 3><<<gb, kB, 0, s>>>(g.rec64.as<CellRec<double, 6, 3>>(), om, w, psi, q, sigma_s, psi_b, g.nc, g.nd, phi, out, nullptr, acc);
     JSW_HIP(hipGetLastError());
+    const int64_t N = g.nc * g.nd;
+    if (r32 && N > 0) {
+        const int64_t per_xcd = ceil_div(ceil_div(N, kB), 8);
+        k_level_order<<<(unsigned)(8 * per_xcd), kB, 0, s>>>(rc, g.lvl_cells.as<int32_t>(), g.nc, N, per_xcd, r32);
+        JSW_HIP(hipGetLastError());
+    }
     double h[2];
     JSW_HIP(hipMemcpyAsync(h, acc, 16, hipMemcpyDeviceToHost, s));
     JSW_HIP(hipStreamSynchronize(s));
@@ -366,9 +440,9 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
     // scratch: psi (if the caller gives none), source / dphi, accumulators
     double *psi = psi_out;
     if (!psi) { ensure(g.scratch_a, 8 * N); psi = g.scratch_a.as<double>(); }
-    ensure(g.scratch_b, 8 * g.nc + 64);
+    ensure(g.scratch_b, 8 * g.nc + 128);
     double *src = g.scratch_b.as<double>();
-    double *acc = src + g.nc + 2;   // 16-byte aligned tail, 4 doubles
+    double *acc = src + g.nc + 2;   // 16-byte aligned tail, 8 doubles
     if (((uintptr_t)acc & 15) != 0) acc += 1;
     const bool zero_start = !warm || !psi_out;
     if (zero_start) JSW_HIP(hipMemsetAsync(psi, 0, 8 * N, s));
@@ -479,7 +553,7 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
                 JSW_HIP(hipStreamSynchronize(s));
                 rho = qq > 0.0 ? 1.0 : 0.0;
             } else {
-                rho = residual(g, psi, q, sigma_s, psi_b, phi, r32, acc, s, &qq);
+                rho = residual(g, psi, q, sigma_s, psi_b, phi, r32, dpsi, acc, s, &qq);   // dpsi is free until the inner solve
             }
             const double qn = qq > 0.0 ? std::sqrt(qq) : 1.0;
             ++outer;
@@ -504,17 +578,27 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
             // The outer loop then measures the true residual.
             const double target = std::max(0.5 * tol, kFp32Floor * rho);
             double prev_pred = INFINITY;
+            // the first inner sweep is set up here; each later one by the
+            // k_dphi of the sweep before it (two accumulator sets alternate)
+            if (g.vsc.bytes < (size_t)(8 * g.nc)) g.vsc.alloc(8 * g.nc);
+            uint32_t *tickets = reinterpret_cast<uint32_t *>(g.status.as<char>() + 128);
+            const bool quads = g.nc % 4 == 0 && ((uintptr_t)dpsi & 15) == 0;
             for (int j = 0; j < J && sweeps < max_iter; ++j) {
-                lag_snapshot<float>(g, dpsi, s);
-                launch_sweep32(g, from_zero ? nullptr : r32, g32, dpsi, params, s);
+                double *a_cur = acc + 2 + 3 * (j & 1), *a_next = acc + 2 + 3 * ((j + 1) & 1);
+                if (j == 0) {
+                    lag_snapshot<float>(g, dpsi, s);
+                    JSW_HIP(hipMemsetAsync(a_cur, 0, 16, s));
+                }
+                launch_sweep32(g, from_zero ? nullptr : r32, g32, dpsi, params, s, j > 0);
                 ++sweeps;
-                JSW_HIP(hipMemsetAsync(acc + 2, 0, 16, s));
-                k_dphi<<<(int)ceil_div(g.nc, kB), kB, 0, s>>>(dpsi, g.weight.as<double>(), sigma_s, g.vol.as<double>(),
-                                                           g.nc, g.nd, from_zero ? q : nullptr, dphi, g32,
-                                                           g.status.as<int32_t>(), acc + 2);
+                auto dphi_kernel = quads ? k_dphi<4> : k_dphi<1>;
+                dphi_kernel<<<(int)ceil_div(g.nc, kB * (quads ? 4 : 1)), kB, 0, s>>>(
+                    dpsi, g.weight.as<double>(), sigma_s, g.vol.as<double>(), g.nc, g.nd, from_zero ? q : nullptr,
+                    dphi, g32, g.status.as<int32_t>(), a_cur, a_next, g.vsc.as<float2>(), tickets,
+                    g.lag_mv.as<uint64_t>(), g.lag_u.as<int32_t>(), g.n_lag, g.lag_val32.as<float>());
                 JSW_HIP(hipGetLastError());
                 double h[3];   // norm of dphi, correction residual, sweep status
-                JSW_HIP(hipMemcpyAsync(h, acc + 2, 24, hipMemcpyDeviceToHost, s));
+                JSW_HIP(hipMemcpyAsync(h, a_cur, 24, hipMemcpyDeviceToHost, s));
                 JSW_HIP(hipStreamSynchronize(s));
                 if (h[2] != 0.0) return check_sweep_status(g, s);
                 const double pred = std::sqrt(wsum * h[1]) / qn;

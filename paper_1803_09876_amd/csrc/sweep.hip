@@ -1079,10 +1079,10 @@ void launch_sweep64(Graph &g, const double *src_cell, double *psi, double psi_b,
 }
 
 void launch_sweep32(Graph &g, const float *src_dir, const float *src_cell, float *psi, const jsweep_params *p,
-                    hipStream_t s) {
-    if (g.ctype == JSWEEP_TRI) launch_impl<float, 3, 2>(g, src_cell, src_dir, psi, 0.0f, p, s);
-    else if (g.ctype == JSWEEP_TET) launch_impl<float, 4, 3>(g, src_cell, src_dir, psi, 0.0f, p, s);
-    else launch_impl<float, 6, 3>(g, src_cell, src_dir, psi, 0.0f, p, s);
+                    hipStream_t s, bool prepared) {
+    if (g.ctype == JSWEEP_TRI) launch_impl<float, 3, 2>(g, src_cell, src_dir, psi, 0.0f, p, s, prepared);
+    else if (g.ctype == JSWEEP_TET) launch_impl<float, 4, 3>(g, src_cell, src_dir, psi, 0.0f, p, s, prepared);
+    else launch_impl<float, 6, 3>(g, src_cell, src_dir, psi, 0.0f, p, s, prepared);
 }
 
 int check_sweep_status(Graph &g, hipStream_t s) {
