@@ -240,12 +240,15 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--steps-only", action="store_true")
+    ap.add_argument("--ttt-only", action="store_true",
+                    help="only the time-to-1e-8 solves (FP64 and FP32-refined) on hex64_s8 and, unless --no-s16, "
+                         "tetlogn60_s16; prints one JSON line")
     ap.add_argument("--ensemble-only", action="store_true",
                     help="only the 256-instance batched solve (for profiling the batch kernels)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the sweep path of this "
-              f"build is a single-device kernel).", file=sys.stderr)
+              f"library is a single-device kernel).", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -277,6 +280,15 @@ def main():
     phi = torch.zeros(nc, dtype=torch.float64, device="cuda")
     psi = torch.zeros(nd * nc, dtype=torch.float64, device="cuda")
     log(f"{p.name}: graph built in {t_build:.2f} s")
+    if args.ttt_only:
+        ttt = {p.name: time_to_tol(J, torch, g, p)}
+        if not args.no_s16:
+            p5 = W.config(5)
+            g5 = J.build_graph(p5.mesh, p5.omega, p5.weight)
+            ttt[p5.name] = time_to_tol(J, torch, g5, p5)
+            g5.close()
+        print(json.dumps({"time_to_tol": ttt}))
+        return
 
     # warmup, then the timed steps (K source iterations, no early stop)
     J.solve(g, st, ss, q, phi, psi, mode=J.JSWEEP_FP64, tol=0.0, max_iter=max(1, args.warmup),

@@ -1,8 +1,9 @@
 """Summaries of rocprofv3 output for the committed profiles.
 
-    python -m paper_1803_09876_amd.rocprof_summary kernels <csv dir> <out.md> <title> <command>
+    python -m paper_1803_09876_amd.rocprof_summary kernels <csv dir> <out.md> <title> <command> [rows]
         kernel statistics of a `rocprofv3 --kernel-trace --stats --output-format csv` run
-        (the run_kernel_stats.csv table) as a short markdown table.
+        (the run_kernel_stats.csv table) as a short markdown table (the first 12 kernels by
+        total time, or [rows]).
 
     python -m paper_1803_09876_amd.rocprof_summary traffic <fetch csv dir> <write csv dir> <kernel substring>
                                                          <key> <out.json> <out.md> <command>
@@ -33,7 +34,7 @@ def _one(pattern: str) -> str:
     return files[0]
 
 
-def kernels(csv_dir: str, out: str, title: str, command: str) -> None:
+def kernels(csv_dir: str, out: str, title: str, command: str, top: int = 12) -> None:
     path = _one(os.path.join(csv_dir, "**", "*kernel_stats.csv"))
     with open(path) as f:
         rows = list(csv.DictReader(f))
@@ -42,7 +43,7 @@ def kernels(csv_dir: str, out: str, title: str, command: str) -> None:
         f.write(f"# {title}\n\nCommand (on the MI355X, from /tmp with TMPDIR=/tmp):\n\n```\n{command}\n```\n\n")
         f.write("rocprofv3 kernel statistics (durations in microseconds):\n\n"
                 "| kernel | calls | total us | average us | min us | max us | % |\n|---|---|---|---|---|---|---|\n")
-        for r in rows[:12]:
+        for r in rows[:top]:
             name = r["Name"]
             name = name.split("(")[0] if "jsw::" in name else (name[:70] + "..." if len(name) > 70 else name)
             f.write(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e3:.1f} | "
@@ -104,7 +105,7 @@ def traffic(fetch_dir, write_dir, kernel, key, out_json, out_md, command) -> Non
 
 def main(argv):
     if len(argv) >= 5 and argv[0] == "kernels":
-        kernels(*argv[1:5])
+        kernels(*argv[1:5], *([int(argv[5])] if len(argv) > 5 else []))
     elif len(argv) >= 8 and argv[0] == "traffic":
         traffic(*argv[1:8])
     else:
