@@ -3,7 +3,8 @@
 * jittered 64^3 hexahedra, S8 (262,144 cells x 80 directions, 236 lagged
   edges): graph arrays and lagged edges bit-exact for every direction, the
   compact FP64 program in use, one FP64 sweep and three FP64 source
-  iterations against the oracle;
+  iterations against the oracle, and the FP32-refined solve to 1e-8 against
+  the FP64 one;
 * Kuhn tetrahedra of a 96^3 lattice, S8 (5.3M cells x 80 directions) and
   of a 60^3 lattice, S16 (1.3M cells x 288 directions): the oracle is built
   for four sampled directions only (directions are independent), and the
@@ -52,6 +53,23 @@ def test_hex64_s8_full(oracle_mod):
         e1, e2 = rel_max(phi.cpu().numpy(), phi_ref), rel_max(psi.cpu().numpy(), psi_ref)
         print(f"[hex64] 3 SI strategy {strategy}: phi {e1:.2e} psi {e2:.2e}", flush=True)
         assert e1 <= 1e-12 and e2 <= 1e-12
+    # FP32-refined solve to 1e-8 against the FP64 one (pinned to the oracle
+    # above): the same flux within the refined tolerance, and no more outer
+    # iterations or sweeps than a correct correction source needs (a
+    # misplaced per-direction residual would leave the corrections poor)
+    sol = {}
+    for mode in (J.JSWEEP_FP64, J.JSWEEP_FP32_REFINED):
+        phi = dev(np.zeros(p.n_cells))
+        st = J.solve(gg, dev(p.sigma_t), dev(p.sigma_s), dev(p.q), phi, mode=mode, tol=1e-8, max_iter=200)
+        sol[mode] = (phi.cpu().numpy(), st)
+        print(f"[hex64] to 1e-8 mode {mode}: sweeps {st['sweeps']} outer {st['outer_iters']} "
+              f"rho {st['residual']:.2e}", flush=True)
+        assert st["residual"] <= 1e-8
+    (phi64, st64), (phi32, st32) = sol[J.JSWEEP_FP64], sol[J.JSWEEP_FP32_REFINED]
+    err = float(np.linalg.norm(phi32 - phi64) / np.linalg.norm(phi64))
+    print(f"[hex64] refined vs FP64 phi rel {err:.2e}", flush=True)
+    assert err <= 1e-8
+    assert st32["outer_iters"] <= 4 and st32["sweeps"] <= st64["sweeps"] + 4
 
 
 @pytest.mark.parametrize("k,sample", [(3, [0, 17, 45, 79]), (5, [0, 100, 200, 287])])
