@@ -212,6 +212,8 @@ struct Graph {
     DevBuf lag_u;                        // [n_lag] int32
     DevBuf lag_val64, lag_val32;         // previous-iterate snapshots
     DevBuf lag_a;                        // [n_lag] double |Omega . S| of the lagged face
+    DevBuf lag_cptr;                     // [nc + 1] int32: each downwind cell's lagged-edge groups (n_lag > 0)
+    DevBuf lag_cgrp;                     // int32 first edge of every (direction, downwind cell) group, by cell
     // scratch reused across solves
     DevBuf scratch_a, scratch_b, scratch_c, scratch_d;
     int grid_waves64 = 0, grid_waves32 = 0;   // persistent grid sizes

@@ -700,6 +700,25 @@ static void dag_impl(Graph &g, bool lag_cycles, hipStream_t s) {
             g.lag_u_h[e] = lags[e].u;
             g.lag_v_h[e] = lags[e].v;
         }
+        // the (direction, downwind cell) groups of every downwind cell, in
+        // ascending direction (compressed rows by cell)
+        {
+            std::vector<int32_t> ptr(nc + 1, 0), grp;
+            for (int64_t e = 0; e < g.n_lag; ++e)
+                if (e == 0 || mv[e - 1] != mv[e]) ++ptr[lags[e].v + 1];
+            for (int64_t v = 0; v < nc; ++v) ptr[v + 1] += ptr[v];
+            grp.resize(ptr[nc]);
+            std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+            for (int64_t e = 0; e < g.n_lag; ++e)
+                if (e == 0 || mv[e - 1] != mv[e]) grp[fill[lags[e].v]++] = (int32_t)e;
+            // groups were visited in (m, v) order, so each cell's are in ascending m
+            g.lag_cptr.alloc(4 * (nc + 1));
+            g.lag_cgrp.alloc(4 * std::max<size_t>(1, grp.size()));
+            JSW_HIP(hipMemcpyAsync(g.lag_cptr.p, ptr.data(), 4 * (nc + 1), hipMemcpyHostToDevice, s));
+            if (!grp.empty())
+                JSW_HIP(hipMemcpyAsync(g.lag_cgrp.p, grp.data(), 4 * grp.size(), hipMemcpyHostToDevice, s));
+            JSW_HIP(hipStreamSynchronize(s));   // before the host vectors go
+        }
         lag = LagView{g.lag_mv.as<uint64_t>(), g.lag_u.as<int32_t>(), g.n_lag};
         done = run_levels<NF, DIM>(g, lag, cnt, fa, fb, ctr, &maxL, s);
         if (done < N) fail(JSWEEP_E_DEVICE, "cycles remain after lagging");

@@ -205,6 +205,47 @@ __global__ void k_residual(const CellRec<double, NF, DIM> *rec, const double *om
     block_add(qq, acc + 1);
 }
 
+// Lagged edges by downwind cell, for the residual kernels below.
+struct LagCells {
+    const int32_t *cptr;   // [nc + 1] groups of each cell
+    const int32_t *cgrp;   // first edge of each (direction, cell) group
+    const uint64_t *mv;    // [n] m << 32 | v, sorted
+    const int32_t *u;      // [n] upwind cell
+    const double *a;       // [n] |Omega . S| of the face
+    double *val;           // [n] previous-iterate value on the edge
+    int64_t n;
+};
+
+// Lagged in-edges of cell v: the un-lagged residual's extra term
+// w_m V ((d + l)^2 - d^2) per direction m, l = sum a (psi_now - psi_prev) / V;
+// the lagged values are replaced by the new iterate's for the next sweep
+__device__ inline double lag_terms(const LagCells &L, const double *psi, const double *w, int64_t nc, int64_t v,
+                                   double V, double d) {
+    double c = 0.0;
+    for (int32_t gi = L.cptr[v]; gi < L.cptr[v + 1]; ++gi) {
+        const int64_t e = L.cgrp[gi];
+        const uint64_t key = L.mv[e];
+        const int64_t m = (int64_t)(key >> 32);
+        double l = 0.0;
+        for (int64_t f = e; f < L.n && L.mv[f] == key; ++f) {
+            const double now = psi[m * nc + L.u[f]];
+            l = l + L.a[f] * (now - L.val[f]) / V;
+            L.val[f] = now;
+        }
+        c = c + w[m] * (V * ((d + l) * (d + l) - d * d));
+    }
+    return c;
+}
+
+// Set-up of the next sweep and status shared by the FP64 residual kernels:
+// the sweep status next to the norms, zeroed next norms, stream tickets
+__device__ inline void next_sweep_setup(int64_t t, const int32_t *status, double *acc, double *acc_next,
+                                        uint32_t *tickets) {
+    if (t == 0) acc[2] = (double)status[0];
+    if (acc_next && t < 3) acc_next[t] = 0.0;
+    if (t < kStreams) tickets[32 * t] = 0u;
+}
+
 // Residual of a plain FP64 source iteration without re-applying the
 // operator.  The sweep solved, per vertex, den psi' - sum_in a psi'_up =
 // V (q + sigma_s phi) with lagged faces on the previous iterate, so the
@@ -212,22 +253,25 @@ __global__ void k_residual(const CellRec<double, NF, DIM> *rec, const double *om
 //   r = sigma_s (phi' - phi) + sum over lagged in-faces a (psi'_u - psi_u) / V.
 // k_phi_delta: phi' (ascending m), the isotropic part d = sigma_s (phi' -
 // phi) and its norm W V d^2 (W = sum of the weights), and V q^2.
-// It also prepares the next sweep: its source q + sigma_s phi' and the
-// product V s the sweep kernels read.
+// The lagged in-faces of the cell add their terms (lag_terms), so that one
+// kernel gives the whole residual norm.  It also prepares the next sweep:
+// its source q + sigma_s phi', the product V s the sweep kernels read, the
+// lagged values, zeroed next norms (acc_next, unless null) and tickets.
 __global__ void k_phi_delta(const double *psi, const double *w, double wsum, const double *q, const double *sigma_s,
-                            const double *vol, int64_t nc, int nd, double *phi, double *dcell, double *acc,
-                            double *src_next, double *vs_next) {
-    int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                            const double *vol, int64_t nc, int nd, double *phi, double *acc, double *src_next,
+                            double *vs_next, LagCells L, const int32_t *status, double *acc_next, uint32_t *tickets) {
+    const int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    next_sweep_setup(K, status, acc, acc_next, tickets);
     double a = 0.0, b = 0.0;
     if (K < nc) {
         const double s = dir_sum(w, psi, nc, nd, K);
         const double d = sigma_s[K] * (s - phi[K]);
         phi[K] = s;
-        dcell[K] = d;
         const double sn = q[K] + sigma_s[K] * s;
         src_next[K] = sn;
         vs_next[K] = vol[K] * sn;
         a = wsum * (vol[K] * (d * d));
+        if (L.n > 0) a = a + lag_terms(L, psi, w, nc, K, vol[K], d);
         b = vol[K] * (q[K] * q[K]);
     }
     block_add(a, acc);
@@ -238,9 +282,12 @@ __global__ void k_phi_delta(const double *psi, const double *w, double wsum, con
 // every direction's fluxes are read in 16-byte pieces; the same
 // arithmetic per cell
 __global__ void k_phi_delta2(const double *psi, const double *w, double wsum, const double *q, const double *sigma_s,
-                             const double *vol, int64_t nc, int nd, double *phi, double *dcell, double *acc,
-                             double *src_next, double *vs_next) {
-    const int64_t K = 2 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+                             const double *vol, int64_t nc, int nd, double *phi, double *acc, double *src_next,
+                             double *vs_next, LagCells L, const int32_t *status, double *acc_next,
+                             uint32_t *tickets) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    next_sweep_setup(t, status, acc, acc_next, tickets);
+    const int64_t K = 2 * t;
     double a = 0.0, b = 0.0;
     if (K < nc) {
         double s[2];
@@ -255,44 +302,15 @@ __global__ void k_phi_delta2(const double *psi, const double *w, double wsum, co
             d[i] = sig[i] * (s[i] - old[i]);
             sn[i] = qk[i] + sig[i] * s[i];
             a = a + wsum * (vk[i] * (d[i] * d[i]));
+            if (L.n > 0) a = a + lag_terms(L, psi, w, nc, K + i, vk[i], d[i]);
             b = b + vk[i] * (qk[i] * qk[i]);
         }
         *reinterpret_cast<double2 *>(phi + K) = make_double2(s[0], s[1]);
-        *reinterpret_cast<double2 *>(dcell + K) = make_double2(d[0], d[1]);
         *reinterpret_cast<double2 *>(src_next + K) = make_double2(sn[0], sn[1]);
         *reinterpret_cast<double2 *>(vs_next + K) = make_double2(vk[0] * sn[0], vk[1] * sn[1]);
     }
     block_add(a, acc);
     block_add(b, acc + 1);
-}
-
-// lagged corrections, one thread per (direction, downwind cell) group of
-// the (m, v, u)-sorted lagged edges: w_m V ((d + l)^2 - d^2); thread 0 also
-// copies the sweep status word next to the norms.  For the next sweep it
-// replaces the lagged values by the new iterate's, zeroes the next norm
-// accumulators (acc_next, unless null) and the data-driven kernel's tickets.
-__global__ void k_lag_residual(const uint64_t *lag_mv, const int32_t *lag_u, const double *lag_a, double *lag_val,
-                               int64_t n_lag, const double *psi, const double *w, const double *vol,
-                               const double *dcell, int64_t nc, const int32_t *status, double *acc,
-                               double *acc_next, uint32_t *tickets) {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e == 0) acc[2] = (double)status[0];
-    if (acc_next && e < 3) acc_next[e] = 0.0;
-    if (e < kStreams) tickets[32 * e] = 0u;
-    double c = 0.0;
-    if (e < n_lag && (e == 0 || lag_mv[e - 1] != lag_mv[e])) {
-        const uint64_t key = lag_mv[e];
-        const int64_t m = (int64_t)(key >> 32), v = (int64_t)(key & 0xffffffffu);
-        double l = 0.0;
-        for (int64_t f = e; f < n_lag && lag_mv[f] == key; ++f) {
-            const double now = psi[m * nc + lag_u[f]];
-            l = l + lag_a[f] * (now - lag_val[f]) / vol[v];
-            lag_val[f] = now;
-        }
-        const double d = dcell[v];
-        c = w[m] * (vol[v] * ((d + l) * (d + l) - d * d));
-    }
-    block_add(c, acc);
 }
 
 // ||q||^2 = sum_K V_K q_K^2
@@ -456,11 +474,10 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
     if (!refined) {
         // phi of the initial iterate
         scalar_flux(g, psi, phi, s);
-        ensure(g.scratch_d, 8 * g.nc + 64);
-        double *dcell = g.scratch_d.as<double>();
         double wsum = 0.0;
         for (double x : g.weight_h) wsum += x;
-        const int64_t nl = std::max<int64_t>(1, g.n_lag);
+        const LagCells lagc{g.lag_cptr.as<int32_t>(), g.lag_cgrp.as<int32_t>(), g.lag_mv.as<uint64_t>(),
+                            g.lag_u.as<int32_t>(), g.lag_a.as<double>(), g.lag_val64.as<double>(), g.n_lag};
         if (g.vsc.bytes < (size_t)(8 * g.nc)) g.vsc.alloc(8 * g.nc);
         uint32_t *tickets = reinterpret_cast<uint32_t *>(g.status.as<char>() + 128);
         // a fixed number of iterations (tol = 0) keeps every iteration's
@@ -476,7 +493,7 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
         // touches allows 16-byte accesses
         auto al16 = [](const void *p) { return ((uintptr_t)p & 15) == 0; };
         const bool pairs = g.nc % 2 == 0 && al16(psi) && al16(phi) && al16(q) && al16(sigma_s) && al16(src) &&
-                           al16(dcell) && al16(g.vol.p) && al16(g.vsc.p);
+                           al16(g.vol.p) && al16(g.vsc.p);
         while (true) {
             if (sweeps >= max_iter) { rc = JSWEEP_E_NOT_CONVERGED; break; }
             double *it_acc = norms.as<double>() + 4 * (fixed ? sweeps : (sweeps & 1));
@@ -489,20 +506,16 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
             launch_sweep64(g, src, psi, psi_b, params, s, prepared);
             ++sweeps;
             // residual of the new iterate from the identity above (one
-            // pass over psi for phi, then the lagged edges)
+            // pass over psi for phi; the lagged edges by their downwind
+            // cells), and the set-up of the next sweep
             if (pairs)
-                k_phi_delta2<<<(int)ceil_div(g.nc / 2, kB), kB, 0, s>>>(psi, g.weight.as<double>(), wsum, q, sigma_s,
-                                                                    g.vol.as<double>(), g.nc, g.nd, phi, dcell,
-                                                                    it_acc, src, g.vsc.as<double>());
+                k_phi_delta2<<<(int)ceil_div(g.nc / 2, kB), kB, 0, s>>>(
+                    psi, g.weight.as<double>(), wsum, q, sigma_s, g.vol.as<double>(), g.nc, g.nd, phi, it_acc, src,
+                    g.vsc.as<double>(), lagc, g.status.as<int32_t>(), next_acc, tickets);
             else
-                k_phi_delta<<<(int)ceil_div(g.nc, kB), kB, 0, s>>>(psi, g.weight.as<double>(), wsum, q, sigma_s,
-                                                                   g.vol.as<double>(), g.nc, g.nd, phi, dcell, it_acc,
-                                                                   src, g.vsc.as<double>());
-            JSW_HIP(hipGetLastError());
-            k_lag_residual<<<(int)ceil_div(nl, kB), kB, 0, s>>>(
-                g.lag_mv.as<uint64_t>(), g.lag_u.as<int32_t>(), g.lag_a.as<double>(), g.lag_val64.as<double>(),
-                g.n_lag, psi, g.weight.as<double>(), g.vol.as<double>(), dcell, g.nc, g.status.as<int32_t>(), it_acc,
-                next_acc, tickets);
+                k_phi_delta<<<(int)ceil_div(g.nc, kB), kB, 0, s>>>(
+                    psi, g.weight.as<double>(), wsum, q, sigma_s, g.vol.as<double>(), g.nc, g.nd, phi, it_acc, src,
+                    g.vsc.as<double>(), lagc, g.status.as<int32_t>(), next_acc, tickets);
             JSW_HIP(hipGetLastError());
             prepared = true;
             if (fixed) continue;
