@@ -39,6 +39,7 @@ struct BInst {
     const uint64_t *lag_mv;
     const int32_t *lag_u;
     const int32_t *posi;
+    const int32_t *lvl;      // [nd*nc] level-ordered cells (position -> cell)
     double *sig_last;                    // sigma_t of the last denominator build
     const double *lag_a;                 // |Omega . S| of the lagged faces
     double wsum;                         // sum of the weights
@@ -176,25 +177,40 @@ __global__ void k_b_residual(const BInst *I, const int64_t *coff, int n, int64_t
     if (i >= 0) {
         const BInst &b = I[i];
         const int64_t K = g - coff[i];
-        float *r32 = fp32 ? b.r32 : nullptr;
+        // FP32 copy of r in cell order, in the correction buffer (free until
+        // the correction solve); k_b_level_order puts it in level order
+        float *r32 = fp32 ? b.dpsi : nullptr;
         double V;
         if (b.ctype == JSWEEP_TRI) {
             const CellRec<double, 3, 2> r = ((const CellRec<double, 3, 2> *)b.rec64)[K];
-            rr = residual_cell(r, K, b.omega, b.w, b.psi, b.q[K], b.sigma_s[K], b.psi_b, b.nc, b.nd, b.phi, r32, b.posi);
+            rr = residual_cell(r, K, b.omega, b.w, b.psi, b.q[K], b.sigma_s[K], b.psi_b, b.nc, b.nd, b.phi, r32, nullptr);
             V = r.V;
         } else if (b.ctype == JSWEEP_TET) {
             const CellRec<double, 4, 3> r = ((const CellRec<double, 4, 3> *)b.rec64)[K];
-            rr = residual_cell(r, K, b.omega, b.w, b.psi, b.q[K], b.sigma_s[K], b.psi_b, b.nc, b.nd, b.phi, r32, b.posi);
+            rr = residual_cell(r, K, b.omega, b.w, b.psi, b.q[K], b.sigma_s[K], b.psi_b, b.nc, b.nd, b.phi, r32, nullptr);
             V = r.V;
         } else {
             const CellRec<double, 6, 3> r = ((const CellRec<double, 6, 3> *)b.rec64)[K];
-            rr = residual_cell(r, K, b.omega, b.w, b.psi, b.q[K], b.sigma_s[K], b.psi_b, b.nc, b.nd, b.phi, r32, b.posi);
+            rr = residual_cell(r, K, b.omega, b.w, b.psi, b.q[K], b.sigma_s[K], b.psi_b, b.nc, b.nd, b.phi, r32, nullptr);
             V = r.V;
         }
         qq = V * (b.q[K] * b.q[K]);
     }
     acc_add(acc, i, 0, rr);
     acc_add(acc, i, 1, qq);
+}
+
+// r of every active instance in level-position order from its cell-order
+// copy: r32[m nc + p] = dpsi[m nc + lvl[m nc + p]]
+__global__ void k_b_level_order(const BInst *I, const int64_t *aoff, int n, int64_t total, const int32_t *active) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int i = find_inst(aoff, n, g);
+    if (!active[i]) return;
+    const BInst &b = I[i];
+    const int64_t x = g - aoff[i];
+    const int64_t m = x / b.nc;
+    b.r32[x] = b.dpsi[m * b.nc + b.lvl[x]];
 }
 
 // Residual of a plain FP64 source iteration from the sweep identity (as in
@@ -342,6 +358,7 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
         b.lag_mv = g.lag_mv.as<uint64_t>();
         b.lag_u = g.lag_u.as<int32_t>();
         b.posi = g.posi.as<int32_t>();
+        b.lvl = g.lvl_cells.as<int32_t>();
         if (!g.sig_last.p) {
             g.sig_last.alloc(8 * g.nc + 64);
             g.den64_ok = g.den32_ok = false;
@@ -409,6 +426,10 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
         k_b_residual<<<grid_for(C), kB, 0, s>>>(I, d_coff.as<int64_t>(), n, C, d_active.as<int32_t>(), refined ? 1 : 0,
                                                 d_acc.as<double>());
         JSW_HIP(hipGetLastError());
+        if (refined) {
+            k_b_level_order<<<grid_for(A), kB, 0, s>>>(I, d_aoff.as<int64_t>(), n, A, d_active.as<int32_t>());
+            JSW_HIP(hipGetLastError());
+        }
         JSW_HIP(hipMemcpyAsync(acc.data(), d_acc.p, 8 * 4 * n, hipMemcpyDeviceToHost, s));
         JSW_HIP(hipStreamSynchronize(s));
         for (int i = 0; i < n; ++i) {
