@@ -63,6 +63,8 @@
 #include <cstring>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <cstdlib>
 #include <limits>
 
@@ -585,8 +587,23 @@ int persistent_waves(Graph &g, bool fp32, const jsweep_params *p, int *waves_per
     int wpb = (p && p->waves_per_block > 0) ? p->waves_per_block
               : (g.has_tuned && g.tuned.waves_per_block > 0 ? g.tuned.waves_per_block : wpb_default);
     if (wpb > 16) wpb = 16;
+    // the occupancy query is answered once per (kernel, workgroup size):
+    // it is not free, and a tolerance-driven solve launches one sweep at a
+    // time, waiting for the last
+    static std::mutex occ_mu;
+    static std::map<std::pair<const void *, int>, int> occ_seen;
+    const void *kern = sweep_kernel(g, fp32);
     int occ = 0;
-    JSW_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, sweep_kernel(g, fp32), 64 * wpb, 0));
+    {
+        std::lock_guard<std::mutex> lock(occ_mu);
+        auto it = occ_seen.find({kern, wpb});
+        if (it != occ_seen.end()) {
+            occ = it->second;
+        } else {
+            JSW_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 64 * wpb, 0));
+            occ_seen[{kern, wpb}] = occ;
+        }
+    }
     if (occ < 1) occ = 1;
     // at most kMaxSweepBlocksPerCU workgroups per CU: every waiting
     // wavefront polls its vertices' upwind fluxes, and with all resident
