@@ -1,43 +1,51 @@
 """Benchmark of the data-driven transport sweep on one MI355X.
 
-Workload: the jittered 64^3 hexahedral mesh (262,144 cells, interior
-vertices moved by up to 0.15 h), level-symmetric S8 (80 directions),
-sigma_t = exp(N(0, 0.5^2)) per cell, scattering ratio 0.9, q = 1 in the
-central eighth, vacuum boundaries; FP64.
+Headline workload (the largest single-GPU configuration): Kuhn tetrahedra
+of a jittered 96^3 lattice (6 tets per cube, 5,308,416 cells, interior
+vertices moved by up to 0.15 h), level-symmetric S8 (80 directions), a
+checkerboard of 8^3 material blocks (sigma_t 1 / 10, scattering ratio
+0.5 / 0.99), q = 1, vacuum boundaries.
 
 A step is one FP64 source iteration through the C ABI: scattering source,
 data-driven sweep of all 80 directions over the per-direction dependency
 graph, scalar flux and FP64 residual.  The graph is built once before the
 timed region (preprocessing).  value = cell-angle updates per second over
-the timed steps.
+the timed steps, inputs resident in HBM.
 
 Also reported:
-  roofline      the sweep kernel's algorithmic bytes per launch (each
+  roofline      the FP64 sweep kernel's algorithmic bytes per launch (each
                 angular flux written once and read once per downwind
                 neighbour, 8 B each) over its average launch time, from HIP
                 events around every sweep launch in the timed region;
                 traffic from the committed rocprofv3 counter summary when it
                 was taken on the current kernel source, else null;
-  cpu_baseline  the oracle (serial FP64 CPU code) timed on a bounded sample
-                of the same workload on this host;
+  fp32_correction_sweep  the same for the FP32 correction sweep of the
+                refined solve (4 B per flux plus the 4 B per-(cell,
+                direction) correction source);
+  cpu_baseline  the oracle (plain FP64 CPU code) timed on this host: one
+                sweep of all 80 directions of the 64^3 hexahedral workload
+                serially and with its directions spread over threads, and
+                its source iteration to rho <= 1e-8 with threaded sweeps;
   time_to_tol   wall time of jsweep_solve to rho <= 1e-8, plain FP64 and
-                FP32-refined, on this workload and on the S16 tetrahedral one
-                (60^3 lattice, 6 tets per cube, 288 directions), each the
-                fastest of three solves after an untimed warm-up of the mode,
-                with the error of each result against the FP64 GPU fixed point
-                (and the sample sweep's error vs the oracle);
+                FP32-refined, on this workload, on the 64^3 hexahedral S8
+                one and on the S16 tetrahedral one (60^3 lattice, 288
+                directions), each the fastest of three solves after an
+                untimed warm-up of the mode, with the error of each result
+                against the oracle's converged scalar flux at the sampled
+                cells of tests/golden/fullsize_<name>.txt;
   ensemble      256 independent meshes (500-50,000 cells, half triangles,
-                half tets, S4-S8) solved together by jsweep_solve_batch (one
-                sweep launch for every instance and direction): FP64 step
-                throughput and time-to-1e-8, FP64 vs FP32-refined (each the
-                fastest of three after a warm-up), with the autotuned launch
-                parameters.
+                half tets, S4-S8) solved together by jsweep_solve_batch:
+                FP64 step throughput and time-to-1e-8, FP64 vs
+                FP32-refined (each the fastest of three after a warm-up),
+                with the autotuned launch parameters.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-s16]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-ttt]
                        [--no-ensemble] [--copy-probe] [--steps-only]
+                       [--workload tetcheck96_s8|hex64_s8|tetlogn60_s16] [--fp32-steps]
   --copy-probe  first copies 512 MiB device to device (the calibration
                 dispatch for HBM byte counters taken on this run)
   --steps-only  only the timed steps and the roofline (for profiler runs)
+  --fp32-steps  with --steps-only: time FP32 correction sweeps instead
 """
 from __future__ import annotations
 
@@ -46,6 +54,7 @@ import hashlib
 import json
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -54,6 +63,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+WORKLOADS = {"delaunay40x50_s4": 1, "hex64_s8": 2, "tetcheck96_s8": 3, "tetlogn60_s16": 5}
+DESCR = {
+    "tetcheck96_s8": "Kuhn tetrahedra of a jittered 96^3 lattice (5,308,416 cells), S8 (80 directions), "
+                     "8^3-block checkerboard (sigma_t 1/10, c 0.5/0.99), FP64 source iteration step",
+    "hex64_s8": "jittered 64^3 hexahedra (262,144 cells), S8 (80 directions), scattering ratio 0.9, "
+                "FP64 source iteration step",
+    "tetlogn60_s16": "Kuhn tetrahedra of a jittered 60^3 lattice (1,296,000 cells), S16 (288 directions), "
+                     "lognormal sigma_t, c 0.95, FP64 source iteration step",
+    "delaunay40x50_s4": "2D Delaunay of 2,000 jittered points (3,822 triangles), S4 (12 directions), "
+                        "FP64 source iteration step",
+}
 
 
 def _source_hash() -> str:
@@ -77,6 +97,28 @@ def _traffic(kernel_key: str):
     return rec.get("hbm_bytes_per_launch")
 
 
+def _golden(name):
+    """Sampled oracle values of a full-size workload (or None)."""
+    path = os.path.join(ROOT, "tests", "golden", f"fullsize_{name}.txt")
+    if not os.path.exists(path):
+        return None
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    from make_fullsize_golden import load
+    return load(name)
+
+
+def err_vs_oracle(phi, gold):
+    """max and normwise relative error of phi against the oracle's converged
+    scalar flux at the sampled cells."""
+    if gold is None or gold.get("phi_converged") is None:
+        return None
+    ref = gold["phi_converged"]
+    got = phi[gold["cells"]]
+    return {"max_rel": float(np.abs(got - ref).max() / np.abs(ref).max()),
+            "norm_rel": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+            "sampled_cells": int(len(ref)), "oracle_rho": gold.get("converged_rho")}
+
+
 TTT_REPEATS = 3
 
 
@@ -84,6 +126,7 @@ def time_to_tol(J, torch, g, p, tol=1e-8):
     """jsweep_solve to rho <= tol, plain FP64 then FP32-refined, from zero;
     each the fastest of TTT_REPEATS solves after an untimed warm-up."""
     st, ss, q = (torch.tensor(a, device="cuda") for a in (p.sigma_t, p.sigma_s, p.q))
+    gold = _golden(p.name)
     out, ref = {}, None
     for name, mode in (("fp64", J.JSWEEP_FP64), ("fp32_refined", J.JSWEEP_FP32_REFINED)):
         # untimed warm-up of the mode's kernels (one outer iteration)
@@ -99,6 +142,8 @@ def time_to_tol(J, torch, g, p, tol=1e-8):
             sec = time.perf_counter() - a
             best = sec if best is None else min(best, sec)
         out[name] = {"seconds": best, "sweeps": s["sweeps"], "outer": s["outer_iters"], "residual": s["residual"]}
+        phi_h = phi.cpu().numpy()
+        out[name]["phi_err_vs_oracle"] = err_vs_oracle(phi_h, gold)
         if ref is None:
             ref = phi
         else:
@@ -107,37 +152,90 @@ def time_to_tol(J, torch, g, p, tol=1e-8):
     return out
 
 
-def algorithmic_bytes(J, g, n_cells, n_dirs, word):
-    """(1 + n_in) * word summed over all vertices: one write per vertex and
-    one read per interior upwind edge (lagged edges included)."""
+def interior_edges(J, g, n_dirs):
+    """Interior upwind edges summed over directions (lagged ones included):
+    the in-degrees of every direction plus the lagged edges."""
     edges = 0
     for m in range(n_dirs):
-        indeg, _, _, _ = J.graph_export(g, m)
+        indeg, _, _, _ = J.graph_export(g, m, want=("indeg",))
         edges += int(indeg.sum())
-    edges += J.graph_info(g)["n_lagged"]
-    return (n_cells * n_dirs + edges) * word, edges
+    return edges + J.graph_info(g)["n_lagged"]
 
 
-def cpu_baseline(problem, psi_gpu_sample):
+def host_cpu():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return model, avail
+
+
+def cpu_baseline(W):
+    """The oracle timed on this host (hexahedral 64^3 S8 workload): one
+    serial sweep of all directions, the same sweep with directions spread
+    over threads, and its source iteration to rho <= 1e-8 with threaded
+    sweeps (the residual is the oracle's serial operator form)."""
     import oracle
+    p = W.config(2)
+    model, avail = host_cpu()
+    threads = max(1, min(16, avail))
     t = time.time()
-    og = oracle.graph_for(problem)
+    og = oracle.graph_for(p)
     t_build = time.time() - t
+    upd = p.n_cells * p.n_dirs
     t = time.time()
-    ref = og.sweep(problem.sigma_t, problem.q)
-    dt = time.time() - t
-    upd = problem.n_cells * problem.n_dirs
-    err = None
-    if psi_gpu_sample is not None:
-        err = float(np.abs(psi_gpu_sample - ref).max() / np.abs(ref).max())
+    og.sweep(p.sigma_t, p.q)
+    serial = time.time() - t
+
+    def threaded(src, prev, psi):
+        b = np.linspace(0, p.n_dirs, threads + 1).astype(int)
+        ths = [threading.Thread(target=og.sweep_dirs, args=(int(x), int(y), p.sigma_t, src),
+                                kwargs={"psi_prev": prev, "psi": psi}) for x, y in zip(b[:-1], b[1:]) if y > x]
+        for th in ths:
+            th.start()
+        for th in ths:
+            th.join()
+
+    psi = np.zeros((p.n_dirs, p.n_cells))
+    t = time.time()
+    threaded(p.q, None, psi)
+    par = time.time() - t
+    # source iteration to 1e-8 (threaded sweeps)
+    psi = np.zeros((p.n_dirs, p.n_cells))
+    prev = np.zeros_like(psi)
+    phi = np.zeros(p.n_cells)
+    t = time.time()
+    it, rho = 0, 1.0
+    while rho > 1e-8 and it < 200:
+        prev[...] = psi
+        threaded(p.q + p.sigma_s * phi, prev, psi)
+        phi = og.phi(p.weight, psi)
+        rho = og.residual(p.sigma_t, p.sigma_s, p.q, p.weight, psi, phi)
+        it += 1
+    solve_s = time.time() - t
     return {
-        "value": upd / dt,
+        "value": upd / par,
         "unit": "cell-angle updates/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": f"one FP64 sweep of all {problem.n_dirs} directions of {problem.name} "
-                  f"({upd} cell-angle updates) after a {t_build:.1f} s graph build, serial",
-    }, err
+        "sample": f"one FP64 sweep of all {p.n_dirs} directions of {p.name} ({upd} cell-angle updates), "
+                  f"directions spread over {threads} threads (graph build {t_build:.1f} s, untimed)",
+        "serial_value": upd / serial,
+        "serial_cores": 1,
+        "cpu_model": model,
+        "host_cpus_available": avail,
+        "solve_to_1e-8": {"seconds": solve_s, "sweeps": it, "residual": rho, "threads": threads,
+                          "workload": p.name},
+    }
 
 
 def ensemble_bench(J, W, torch, steps=5):
@@ -195,39 +293,26 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def extras(args, J, W, torch, g, p, st, ss, q, phi):
-    """FP32 sweep kernel time, the oracle comparison, time-to-1e-8 and the CPU baseline."""
-    nc, nd = p.n_cells, p.n_dirs
-    # FP32 sweep kernel time on the same graph (correction sweeps)
+def fp32_sweep_ms(J, torch, g, st, ss, q, nc, warmup, n=10):
+    """Average FP32 correction-sweep kernel time (HIP events) over the inner
+    sweeps of an FP32-refined solve."""
     J.jsweep_profile(g, True)
-    J.solve(g, st, ss, q, torch.zeros_like(phi), mode=J.JSWEEP_FP32_REFINED, tol=0.0, max_iter=1 + args.warmup,
-            allow_not_converged=True)
+    J.solve(g, st, ss, q, torch.zeros(nc, dtype=torch.float64, device="cuda"), mode=J.JSWEEP_FP32_REFINED,
+            tol=0.0, max_iter=1 + warmup, allow_not_converged=True)
     J.jsweep_profile_read(g, reset=True)
-    J.solve(g, st, ss, q, torch.zeros_like(phi), mode=J.JSWEEP_FP32_REFINED, tol=0.0, max_iter=10,
-            allow_not_converged=True)
+    J.solve(g, st, ss, q, torch.zeros(nc, dtype=torch.float64, device="cuda"), mode=J.JSWEEP_FP32_REFINED,
+            tol=0.0, max_iter=n, allow_not_converged=True)
     n32, ms32 = J.jsweep_profile_read(g, reset=True)
     J.jsweep_profile(g, False)
-    avg32_s = ms32 / max(1, n32) * 1e-3
-    log(f"FP32 sweep kernel {avg32_s * 1e3:.3f} ms")
-    # one sweep on fixed inputs for the comparison with the oracle
-    psi_s = torch.zeros(nd * nc, dtype=torch.float64, device="cuda")
-    J.sweep(g, st, q, psi_s)
-    psi_sample = psi_s.view(nd, nc).cpu().numpy()
-    # time to rho <= 1e-8: plain FP64 vs FP32-refined
-    ttt = {p.name: time_to_tol(J, torch, g, p)}
-    log(f"time to 1e-8 on {p.name}: {json.dumps(ttt[p.name])}")
-    if not args.no_s16:
-        p5 = W.config(5)
-        g5 = J.build_graph(p5.mesh, p5.omega, p5.weight)
-        ttt[p5.name] = time_to_tol(J, torch, g5, p5)
-        g5.close()
-        log(f"time to 1e-8 on {p5.name}: {json.dumps(ttt[p5.name])}")
-    ens = None
-    if not args.no_ensemble:
-        ens = ensemble_bench(J, W, torch)
-        log(f"ensemble: {json.dumps(ens)}")
-    cpu, err = (None, None) if args.no_cpu else cpu_baseline(p, psi_sample)
-    return avg32_s, ttt, ens, cpu, err
+    return ms32 / max(1, n32), n32
+
+
+def roofline(bytes_alg, avg_ms, kernel_key, launches, edges):
+    achieved = bytes_alg / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS, "traffic": _traffic(kernel_key), "kernel": kernel_key,
+            "algorithmic_bytes_per_launch": bytes_alg, "interior_edges": edges, "avg_kernel_ms": avg_ms,
+            "launches": launches}
 
 
 def main():
@@ -235,14 +320,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="tetcheck96_s8", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-s16", action="store_true")
+    ap.add_argument("--no-ttt", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--steps-only", action="store_true")
+    ap.add_argument("--fp32-steps", action="store_true")
     ap.add_argument("--ttt-only", action="store_true",
-                    help="only the time-to-1e-8 solves (FP64 and FP32-refined) on hex64_s8 and, unless --no-s16, "
-                         "tetlogn60_s16; prints one JSON line")
+                    help="only the time-to-1e-8 solves (FP64 and FP32-refined) of the workload; one JSON line")
     ap.add_argument("--ensemble-only", action="store_true",
                     help="only the 256-instance batched solve (for profiling the batch kernels)")
     args = ap.parse_args()
@@ -269,7 +355,7 @@ def main():
         ens = ensemble_bench(J, W, torch, steps=max(1, args.steps))
         print(json.dumps({"ensemble": ens}))
         return
-    p = W.config(2)
+    p = W.config(WORKLOADS[args.workload])
     nc, nd = p.n_cells, p.n_dirs
     t = time.time()
     g = J.build_graph(p.mesh, p.omega, p.weight)
@@ -281,13 +367,12 @@ def main():
     psi = torch.zeros(nd * nc, dtype=torch.float64, device="cuda")
     log(f"{p.name}: graph built in {t_build:.2f} s")
     if args.ttt_only:
-        ttt = {p.name: time_to_tol(J, torch, g, p)}
-        if not args.no_s16:
-            p5 = W.config(5)
-            g5 = J.build_graph(p5.mesh, p5.omega, p5.weight)
-            ttt[p5.name] = time_to_tol(J, torch, g5, p5)
-            g5.close()
-        print(json.dumps({"time_to_tol": ttt}))
+        print(json.dumps({"time_to_tol": {p.name: time_to_tol(J, torch, g, p)}}))
+        return
+    if args.steps_only and args.fp32_steps:
+        ms, n = fp32_sweep_ms(J, torch, g, st, ss, q, nc, args.warmup, args.steps)
+        log(f"FP32 correction sweep {ms:.3f} ms over {n} launches")
+        print(json.dumps({"workload": p.name, "fp32_sweep_ms": ms, "launches": n}))
         return
 
     # warmup, then the timed steps (K source iterations, no early stop)
@@ -304,16 +389,44 @@ def main():
     J.jsweep_profile(g, False)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = nc * nd * args.steps / (t1 - t0)
+    edges = interior_edges(J, g, nd)
+    avg64 = kernel_ms / max(1, launches)
+    roof = roofline((nc * nd + edges) * 8, avg64, f"k_sweep<double> {p.name}", launches, edges)
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, sweep kernel {avg64:.3f} ms, "
+        f"roofline frac {roof['frac']:.3f}")
 
-    bytes_alg, edges = algorithmic_bytes(J, g, nc, nd, 8)
-    avg_kernel_s = kernel_ms / max(1, launches) * 1e-3
-    achieved = bytes_alg / avg_kernel_s / 1e9
-    kernel_key = "k_sweep<double> hex64_s8"
-    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, sweep kernel {avg_kernel_s * 1e3:.3f} ms")
-
-    avg32_s, ttt, ens, cpu, err = None, None, None, None, None
+    line_extra = {}
     if not args.steps_only:
-        avg32_s, ttt, ens, cpu, err = extras(args, J, W, torch, g, p, st, ss, q, phi)
+        ms32, n32 = fp32_sweep_ms(J, torch, g, st, ss, q, nc, args.warmup)
+        roof32 = roofline((nc * nd + edges) * 4 + nc * nd * 4, ms32, f"k_sweep<float> {p.name}", n32, edges)
+        log(f"FP32 correction sweep {ms32:.3f} ms, roofline frac {roof32['frac']:.3f}")
+        line_extra["fp32_correction_sweep"] = {"updates_per_s": nc * nd / (ms32 * 1e-3), "roofline": roof32}
+        # one sweep on fixed inputs, compared with the oracle's sampled angular flux is in the GPU tests
+        ttt = None
+        if not args.no_ttt:
+            ttt = {p.name: time_to_tol(J, torch, g, p)}
+            log(f"time to 1e-8 on {p.name}: {json.dumps(ttt[p.name])}")
+        g.close()
+        if not args.no_ttt:
+            for k in (2, 5):
+                if WORKLOADS[args.workload] == k:
+                    continue
+                pk = W.config(k)
+                gk = J.build_graph(pk.mesh, pk.omega, pk.weight)
+                ttt[pk.name] = time_to_tol(J, torch, gk, pk)
+                gk.close()
+                log(f"time to 1e-8 on {pk.name}: {json.dumps(ttt[pk.name])}")
+        line_extra["time_to_tol"] = ttt
+        ens = None
+        if not args.no_ensemble:
+            ens = ensemble_bench(J, W, torch)
+            log(f"ensemble: {json.dumps(ens)}")
+        line_extra["ensemble"] = ens
+        cpu = None
+        if not args.no_cpu:
+            cpu = cpu_baseline(W)
+            log(f"cpu baseline: {json.dumps(cpu)}")
+        line_extra["cpu_baseline"] = cpu
 
     line = {
         "metric": "cell-angle updates/s per sweep; time-to-1e-8 residual, FP32-refined vs FP64",
@@ -328,22 +441,15 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "hex64_s8: jittered 64^3 hexahedra (262,144 cells), S8 (80 directions), "
-                               "scattering ratio 0.9, FP64 source iteration step",
+        "config": {"workload": f"{p.name}: {DESCR[p.name]}",
                    "cells": nc, "dirs": nd, "lagged_edges": info["n_lagged"], "max_levels": info["max_levels"],
                    "graph_build_s": t_build},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": _traffic(kernel_key),
-                     "kernel": kernel_key, "algorithmic_bytes_per_launch": bytes_alg,
-                     "interior_edges": edges, "avg_kernel_ms": avg_kernel_s * 1e3, "launches": launches},
-        "cpu_baseline": cpu,
-        "sweep_kernel_ms": {"fp64": avg_kernel_s * 1e3, "fp32": avg32_s * 1e3 if avg32_s else None},
-        "sweep_updates_per_s_kernel": {"fp64": nc * nd / avg_kernel_s,
-                                       "fp32": nc * nd / avg32_s if avg32_s else None},
-        "time_to_tol": ttt,
-        "ensemble": ens,
-        "sweep_rel_err_vs_oracle": err,
+        "roofline": roof,
+        "cpu_baseline": line_extra.pop("cpu_baseline", None),
+        "sweep_kernel_ms": {"fp64": avg64},
+        "sweep_updates_per_s_kernel": {"fp64": nc * nd / (avg64 * 1e-3)},
     }
+    line.update(line_extra)
     print(json.dumps(line))
 
 

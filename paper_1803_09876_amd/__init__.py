@@ -217,20 +217,22 @@ def jsweep_program_info(g: Graph):
     return {"slots": ns.value, "block_slots": nx.value}
 
 
-def jsweep_graph_export(g: Graph, direction: int):
+def jsweep_graph_export(g: Graph, direction: int, want=("indeg", "level", "lvl_ptr", "lvl_cells")):
     """Per-direction graph arrays as host numpy arrays:
-    (indeg int32, level int32, lvl_ptr int64, lvl_cells int64)."""
+    (indeg int32, level int32, lvl_ptr int64, lvl_cells int64); arrays not
+    named in ``want`` are not exported and come back as None."""
     lib = load_library()
     n = g.n_cells
     nlev = ctypes.c_int32()
     _check(lib.jsweep_graph_export(g.handle, int(direction), None, None, None, None, ctypes.byref(nlev),
                                    JSWEEP_HOST_PTRS))
-    indeg = np.zeros(n, dtype=np.int32)
-    level = np.zeros(n, dtype=np.int32)
-    lvl_ptr = np.zeros(nlev.value + 1, dtype=np.int64)
-    lvl_cells = np.zeros(n, dtype=np.int64)
-    _check(lib.jsweep_graph_export(g.handle, int(direction), indeg.ctypes.data, level.ctypes.data,
-                                   lvl_ptr.ctypes.data, lvl_cells.ctypes.data, None, JSWEEP_HOST_PTRS))
+    indeg = np.zeros(n, dtype=np.int32) if "indeg" in want else None
+    level = np.zeros(n, dtype=np.int32) if "level" in want else None
+    lvl_ptr = np.zeros(nlev.value + 1, dtype=np.int64) if "lvl_ptr" in want else None
+    lvl_cells = np.zeros(n, dtype=np.int64) if "lvl_cells" in want else None
+    addr = lambda a: None if a is None else a.ctypes.data  # noqa: E731
+    _check(lib.jsweep_graph_export(g.handle, int(direction), addr(indeg), addr(level), addr(lvl_ptr),
+                                   addr(lvl_cells), None, JSWEEP_HOST_PTRS))
     return indeg, level, lvl_ptr, lvl_cells
 
 
