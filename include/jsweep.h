@@ -63,6 +63,8 @@ extern "C" {
 #define JSWEEP_E_OOM (-6)           /* device or host allocation failed */
 #define JSWEEP_E_STALLED (-7)       /* sweep watchdog fired: no progress within the time limit */
 #define JSWEEP_E_NOT_CONVERGED (-8) /* iteration limit reached; outputs and stats are still written */
+#define JSWEEP_E_PLACEMENT (-9)     /* a work-list sweep workgroup ran on another XCD than its stream
+                                       (the hand-offs need each stream on one XCD); outputs undefined */
 
 /* ---- cell types ---------------------------------------------------------
  * JSWEEP_TRI (2D): local edge j is the edge opposite vertex j.

@@ -25,6 +25,7 @@ JSWEEP_E_DEVICE = -5
 JSWEEP_E_OOM = -6
 JSWEEP_E_STALLED = -7
 JSWEEP_E_NOT_CONVERGED = -8
+JSWEEP_E_PLACEMENT = -9
 
 JSWEEP_TRI, JSWEEP_TET, JSWEEP_HEX = 3, 4, 8
 JSWEEP_DEBUG_NO_LAG = 0x1

@@ -136,6 +136,14 @@ int jsweep_build_graph(const jsweep_mesh *mesh, const jsweep_quadrature *quad, u
         hipDeviceProp_t prop;
         JSW_HIP(hipGetDeviceProperties(&prop, g->device));
         g->n_cu = prop.multiProcessorCount;
+        {
+            int nx = 0;
+            if (hipDeviceGetAttribute(&nx, hipDeviceAttributeNumberOfXccs, g->device) != hipSuccess || nx < 1)
+                nx = kStreams;   // MI355X in its single-partition mode
+            (void)hipGetLastError();
+            if (kStreams % nx != 0) fail(JSWEEP_E_DEVICE, "XCD count does not divide the stream count");
+            g->n_xcc = nx;
+        }
         g->nd = quad->n_dirs;
         g->omega_h.assign(quad->omega, quad->omega + 3 * g->nd);
         if (M.dim == 2)
@@ -477,6 +485,7 @@ const char *jsweep_error_string(int code) {
     case JSWEEP_E_OOM: return "out of memory";
     case JSWEEP_E_STALLED: return "sweep stalled (watchdog)";
     case JSWEEP_E_NOT_CONVERGED: return "not converged";
+    case JSWEEP_E_PLACEMENT: return "sweep workgroup on another XCD than its stream";
     default: return "unknown error";
     }
 }

@@ -115,6 +115,32 @@ __device__ inline int64_t lag_index(const uint64_t *lag_mv, const int32_t *lag_u
 // stream); on MI355X stream x runs on XCD x.
 constexpr int kStreams = 8;
 
+// Device status word bits (Graph::status[0]): a sweep wavefront's watchdog
+// fired, or a workgroup found itself on another XCD than its stream's.
+constexpr int32_t kStatusStalled = 1;
+constexpr int32_t kStatusPlacement = 2;
+
+// XCD (accelerator complex die) the calling wavefront runs on: the XCC_ID
+// hardware register (hwreg 20, bits 3:0) of gfx94x / gfx950.
+__device__ __forceinline__ int xcc_id() {
+    return (int)(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 0xfu);
+}
+
+// The work-list sweeps hand fluxes from producer to consumer through the L2
+// of one XCD, so every workgroup of a stream (ids congruent mod kStreams)
+// must run on the same XCD.  The dispatcher deals workgroup ids round robin
+// over the n_xcc XCDs of the partition (n_xcc divides kStreams), so
+// workgroup b belongs on XCD b mod n_xcc; a workgroup elsewhere raises
+// kStatusPlacement (every waiting wavefront sees it and ends) instead of
+// leaving its stream's consumers to the watchdog.  Returns true when the
+// workgroup is where the hand-offs need it.
+__device__ __forceinline__ bool check_stream_placement(int n_xcc, int32_t *status) {
+    if (n_xcc <= 1) return true;
+    if (xcc_id() % n_xcc == (int)(blockIdx.x % (unsigned)n_xcc)) return true;
+    if (threadIdx.x == 0) atomicOr(status, kStatusPlacement);
+    return false;
+}
+
 // Patch-task sweep program (built on the first sweep that uses it).  The
 // cells are cut into patches of consecutive Morton rank; a task is one visit
 // of a patch in one direction (a patch may need several visits when its
@@ -163,6 +189,7 @@ struct PatchProg {
 struct Graph {
     int device = 0;
     int n_cu = 0;
+    int n_xcc = 8;                       // XCDs of the device's partition (workgroups dealt round robin)
     int dim = 3, ctype = JSWEEP_TET, nfpc = 4;
     int64_t nv = 0, nc = 0, nf = 0;
     int nd = 0;

@@ -769,6 +769,7 @@ struct PatchArgs {
     uint64_t watchdog_ticks;
     double psi_b;
     uint32_t *stamps;   // per task: taken, upstream complete, published (s_memrealtime), or null
+    int32_t n_xcc;      // XCDs the workgroups are dealt over
 };
 
 template <class T>
@@ -794,6 +795,7 @@ __global__ void __launch_bounds__(64) k_sweep_patch(PatchArgs a) {
     __shared__ int32_t scell[kPatchCells];
     __shared__ int32_t srnd[kPatchRounds];
     const int lane = threadIdx.x;
+    if (!check_stream_placement(a.n_xcc, a.status)) return;   // takes no task
     const int stream = (int)(blockIdx.x % kStreams);
     const int64_t first = a.stream_off[stream];
     const int64_t per_stream = a.stream_off[stream + 1] - first;
@@ -815,7 +817,7 @@ __global__ void __launch_bounds__(64) k_sweep_patch(PatchArgs a) {
             if ((spin & 7) == 7) {
                 bool stop = ld_agent(a.status) != 0;
                 if (!stop && __builtin_amdgcn_s_memrealtime() - t0 > a.watchdog_ticks) {
-                    if (lane == 0) atomicOr(a.status, 1);
+                    if (lane == 0) atomicOr(a.status, kStatusStalled);
                     stop = true;
                 }
                 if (__any(stop)) return;
@@ -1033,6 +1035,7 @@ void launch_patch64(Graph &g, const double *src_cell, double *psi, double psi_b,
     a.qctl = pp.qctl.as<uint32_t>();
     a.down = pp.down.as<int32_t>();
     a.status = g.status.as<int32_t>();
+    a.n_xcc = g.n_xcc;
     a.stream_off = pp.stream_off.as<int64_t>();
     pp.epoch = pp.epoch % 255 + 1;
     a.epoch = (uint32_t)pp.epoch;

@@ -95,6 +95,7 @@ struct SweepArgs {
     uint32_t backoff;                        // the pause doubles every 8 polls, at most this many times
     uint64_t watchdog_ticks;
     uint32_t *stamps;                        // tracing: [3 * n_chunks] or null
+    int32_t n_xcc;                           // XCDs the workgroups are dealt over
 };
 
 template <class T>
@@ -185,6 +186,9 @@ template <class Real, int NS, int NSX, bool TRACE>
 __global__ void k_sweep(SweepArgs<Real> a) {
     constexpr int NX = NSX > 0 ? NSX : 1;
     const int lane = threadIdx.x & 63;
+    // a workgroup off its stream's XCD takes no chunk (it holds nothing
+    // anyone waits for) and raises the placement flag
+    if (!check_stream_placement(a.n_xcc, a.status)) return;
     const int stream = (int)(blockIdx.x % kStreams);
     const int64_t first = a.stream_off[stream];
     const int64_t per_stream = a.stream_off[stream + 1] - first;
@@ -321,7 +325,7 @@ __global__ void k_sweep(SweepArgs<Real> a) {
             if ((spin & 7) == 7) {
                 bool stop = ld_coherent(a.status) != 0;
                 if (!stop && __builtin_amdgcn_s_memrealtime() - t0 > a.watchdog_ticks) {
-                    if (lane == 0) atomicOr(a.status, 1);
+                    if (lane == 0) atomicOr(a.status, kStatusStalled);
                     stop = true;
                 }
                 // the wavefront ends here (no barrier in this kernel); an
@@ -698,6 +702,7 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
     a.psi_b = psi_b;
     a.watchdog_ticks = watchdog_ticks();
     a.stamps = g.trace ? g.trace_buf.as<uint32_t>() : nullptr;
+    a.n_xcc = g.n_xcc;
     if (g.trace) g.trace_units = 0;
     {
         const char *e = std::getenv("JSWEEP_POLL_NAP");
@@ -1107,6 +1112,9 @@ int check_sweep_status(Graph &g, hipStream_t s) {
     JSW_HIP(hipMemcpyAsync(&st, g.status.p, 4, hipMemcpyDeviceToHost, s));
     JSW_HIP(hipStreamSynchronize(s));
     if (st == 0) return JSWEEP_OK;
+    const int rc = (st & kStatusPlacement) ? JSWEEP_E_PLACEMENT : JSWEEP_E_STALLED;
+    if (rc == JSWEEP_E_PLACEMENT)
+        set_last_error("a sweep workgroup ran on another XCD than the workgroups of its stream");
     // a stalled sweep leaves the level-position arrays and the task slots
     // in an unknown state: start over
     g.dd_state[0] = g.dd_state[1] = 0;
@@ -1114,7 +1122,7 @@ int check_sweep_status(Graph &g, hipStream_t s) {
     JSW_HIP(hipMemsetAsync(g.status.p, 0, 64, s));
     JSW_HIP(hipStreamSynchronize(s));
     g.pp.epoch = 0;
-    return JSWEEP_E_STALLED;
+    return rc;
 }
 
 // Host side of the batched sweep: the instance table and the task list are
