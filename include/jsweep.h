@@ -78,6 +78,33 @@ extern "C" {
 /* ---- build flags ---------------------------------------------------- */
 #define JSWEEP_DEBUG_NO_LAG 0x1u   /* report cycles as JSWEEP_E_CYCLE instead of lagging */
 #define JSWEEP_HOST_PTRS 0x2u      /* jsweep_graph_export: output buffers are host memory */
+/* bits 8-15 of the build flags: the work-list priority (below), e.g.
+ * JSWEEP_PRIORITY_FLAGS(JSWEEP_PRIORITY_SLBD | JSWEEP_PRIORITY_ANGLE_MAJOR) */
+#define JSWEEP_PRIORITY_FLAGS(p) (((uint32_t)(p) & 0xffu) << 8)
+
+/* ---- work-list priorities (paper Sec. V-D, "Optimization: Priority
+ * Strategy") ------------------------------------------------------------
+ * The data-driven sweep takes the chunks (clusters of <= 64 vertices of one
+ * level and direction, the coarsened graph of Sec. V-E) of each stream in a
+ * fixed order: the order in which a ready queue ordered by the priority
+ * would release them (Kahn's algorithm on the chunk graph, ties broken by
+ * level order).  Every order is topological, so every priority gives
+ * bit-identical fluxes; only the schedule changes.
+ *   BFS   breadth first: level, then direction (the default);
+ *   LDCP  longest distance on the critical path: the longest chunk path to
+ *         a sink of the graph first;
+ *   SLBD  shortest local boundary distance: the chunk with the shortest
+ *         such path (closest to the outflow boundary) first, a depth-first
+ *         variant;
+ *   ANGLE_MAJOR (OR-ed with one of the above): prior(a) * C + prior(p) with
+ *         a large C, i.e. the chunk's direction ranks first (ascending), the
+ *         strategy only among chunks of one direction.
+ * With a priority other than BFS the DIRECTION_LDS strategy is not used
+ * (its program lookup needs each level's chunks together). */
+#define JSWEEP_PRIORITY_BFS 1
+#define JSWEEP_PRIORITY_LDCP 2
+#define JSWEEP_PRIORITY_SLBD 3
+#define JSWEEP_PRIORITY_ANGLE_MAJOR 0x10
 
 /* ---- solve modes ---------------------------------------------------- */
 #define JSWEEP_FP64 0              /* FP64 source iteration */
@@ -143,7 +170,8 @@ typedef struct {
     int32_t inner_sweeps;          /* FP32-refined: maximum inner sweeps per outer residual */
     int32_t chunks_per_ticket;     /* DATA_DRIVEN: work-list chunks a wavefront takes per atomic ticket */
     int32_t strategy;              /* JSWEEP_STRATEGY_* */
-    int32_t reserved;
+    int32_t priority;              /* JSWEEP_PRIORITY_* (0: keep the graph's work-list order); a
+                                      different one rebuilds the graph's work list on first use */
 } jsweep_params;
 
 typedef struct {
@@ -176,7 +204,8 @@ typedef struct {
  * lagged: they are not counted in the in-degree and carry the previous
  * iterate.  With JSWEEP_DEBUG_NO_LAG a cycle is an error instead.
  *
- * mesh, quad: host pointers (copied).  flags: JSWEEP_DEBUG_NO_LAG.
+ * mesh, quad: host pointers (copied).  flags: JSWEEP_DEBUG_NO_LAG, and a
+ * work-list priority as JSWEEP_PRIORITY_FLAGS(p) (default BFS).
  * out: receives the handle (NULL on error).
  * Errors: E_INVALID_ARG, E_MESH, E_QUADRATURE, E_CYCLE, E_DEVICE, E_OOM.
  * Limits: n_cells * faces_per_cell < 2^31; 3D meshes need n_vertices < 2^21
@@ -277,7 +306,9 @@ int jsweep_autotune(int32_t n, const jsweep_graph *graphs, int32_t mode, jsweep_
 
 /* Launch parameters of a graph's sweeps: the ones jsweep_sweep uses and
  * jsweep_solve uses when its params argument is NULL (the same slot
- * jsweep_autotune fills).  p == NULL returns the graph to the defaults. */
+ * jsweep_autotune fills).  p == NULL returns the graph to the defaults
+ * (the work-list order stays as it is).  A nonzero p->priority reorders the
+ * work list now (paper Sec. V-D). */
 int jsweep_set_params(jsweep_graph g, const jsweep_params *p);
 
 /* The PATCH strategy's program of a graph, built now if it was not yet

@@ -36,6 +36,13 @@ JSWEEP_WARM_START = 0x100
 JSWEEP_STRATEGY_AUTO, JSWEEP_STRATEGY_DATA_DRIVEN, JSWEEP_STRATEGY_DIRECTION = 0, 1, 2
 JSWEEP_STRATEGY_DIRECTION_LDS = 3
 JSWEEP_STRATEGY_PATCH = 4
+JSWEEP_PRIORITY_BFS, JSWEEP_PRIORITY_LDCP, JSWEEP_PRIORITY_SLBD = 1, 2, 3
+JSWEEP_PRIORITY_ANGLE_MAJOR = 0x10
+
+
+def JSWEEP_PRIORITY_FLAGS(p: int) -> int:
+    """Build flags selecting a work-list priority (bits 8-15)."""
+    return (int(p) & 0xff) << 8
 
 EXPORTED = [
     "jsweep_build_graph", "jsweep_graph_info", "jsweep_graph_export", "jsweep_graph_lagged", "jsweep_sweep",
@@ -63,10 +70,10 @@ class _Quad(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("waves_per_block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("inner_sweeps", ctypes.c_int32), ("chunks_per_ticket", ctypes.c_int32),
-                ("strategy", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("strategy", ctypes.c_int32), ("priority", ctypes.c_int32)]
 
     def as_dict(self):
-        return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
 class SolveStats(ctypes.Structure):

@@ -118,7 +118,8 @@ int jsweep_build_graph(const jsweep_mesh *mesh, const jsweep_quadrature *quad, u
         if (!out) fail(JSWEEP_E_INVALID_ARG, "out is NULL");
         *out = nullptr;
         if (!mesh || !quad) fail(JSWEEP_E_INVALID_ARG, "mesh or quadrature is NULL");
-        if (flags & ~(JSWEEP_DEBUG_NO_LAG)) fail(JSWEEP_E_INVALID_ARG, "unknown build flag");
+        if (flags & ~(JSWEEP_DEBUG_NO_LAG | JSWEEP_PRIORITY_FLAGS(0xff))) fail(JSWEEP_E_INVALID_ARG, "unknown build flag");
+        const int priority = (int)((flags >> 8) & 0xffu);
         const jsweep_mesh &M = *mesh;
         bool ok_type = (M.dim == 2 && M.cell_type == JSWEEP_TRI) ||
                        (M.dim == 3 && (M.cell_type == JSWEEP_TET || M.cell_type == JSWEEP_HEX));
@@ -159,6 +160,7 @@ int jsweep_build_graph(const jsweep_mesh *mesh, const jsweep_quadrature *quad, u
         JSW_HIP(hipMemcpy(g->weight.p, g->weight_h.data(), 8 * g->nd, hipMemcpyHostToDevice));
         build_geometry(*g, M, s);
         build_dag(*g, !(flags & JSWEEP_DEBUG_NO_LAG), s);
+        if (priority) set_priority(*g, priority, s);
         JSW_HIP(hipDeviceSynchronize());
         *out = reinterpret_cast<jsweep_graph>(g.release());
         return JSWEEP_OK;
@@ -345,8 +347,9 @@ int jsweep_set_params(jsweep_graph h, const jsweep_params *p) {
         Graph &g = *G(h);
         if (p) {
             if (p->strategy < 0 || p->strategy > JSWEEP_STRATEGY_PATCH || p->waves_per_block < 0 ||
-                p->blocks_per_cu < 0 || p->inner_sweeps < 0 || p->chunks_per_ticket < 0)
+                p->blocks_per_cu < 0 || p->inner_sweeps < 0 || p->chunks_per_ticket < 0 || p->priority < 0)
                 fail(JSWEEP_E_INVALID_ARG, "bad launch parameters");
+            if (p->priority) set_priority(g, p->priority, nullptr);
             g.tuned = *p;
             g.has_tuned = true;
         } else {

@@ -190,6 +190,7 @@ struct Graph {
     int device = 0;
     int n_cu = 0;
     int n_xcc = 8;                       // XCDs of the device's partition (workgroups dealt round robin)
+    int priority = JSWEEP_PRIORITY_BFS;  // order of the work list (JSWEEP_PRIORITY_*)
     int dim = 3, ctype = JSWEEP_TET, nfpc = 4;
     int64_t nv = 0, nc = 0, nf = 0;
     int nd = 0;
@@ -262,6 +263,9 @@ struct Graph {
 // build steps (geometry.hip, dag.hip)
 void build_geometry(Graph &g, const jsweep_mesh &mesh, hipStream_t s);
 void build_dag(Graph &g, bool lag_cycles, hipStream_t s);
+// reorder the work list by a priority (JSWEEP_PRIORITY_*), rebuilding what
+// is kept in chunk order
+void set_priority(Graph &g, int priority, hipStream_t s);
 void build_rec32(Graph &g, hipStream_t s);
 
 // sweep launch (sweep.hip)

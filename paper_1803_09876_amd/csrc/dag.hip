@@ -10,6 +10,7 @@
 #include <cstring>
 
 #include <algorithm>
+#include <queue>
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
 
@@ -815,6 +816,173 @@ static void dag_impl(Graph &g, bool lag_cycles, hipStream_t s) {
     g.status.alloc(128 + 32 * 4 * 8);   // status words, then 8 ticket counters 128 B apart
     JSW_HIP(hipMemsetAsync(g.status.p, 0, g.status.bytes, s));
     JSW_HIP(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------------------
+// Priority strategies (paper Sec. V-D): the order of the chunks of every
+// stream, i.e. which ready cluster a wavefront takes next.  The paper ranks
+// a (patch, angle) pair by prior(a) * C + prior(p) with a large C (angle
+// first) and names three vertex / patch priorities: BFS, LDCP (longest
+// distance on the critical path) and SLBD (shortest local boundary
+// distance, a depth-first variant).  On the coarsened graph (chunks,
+// Sec. V-E; acyclic by Theorem 1) the order is produced the way a priority
+// ready queue releases work: Kahn's algorithm per stream, always taking the
+// ready chunk of smallest key, so every order is topological and the sweep
+// keeps its guarantee that a chunk's upwind chunks come earlier in its
+// stream.  Keys (ties broken by the level order):
+//   BFS   level, direction, position (the level order itself);
+//   LDCP  the longest chunk path from the chunk to a sink, longest first;
+//   SLBD  the same distance, shortest first (the chunk closest to the
+//         outflow boundary of its direction: depth first);
+//   ANGLE_MAJOR (OR-ed) the chunk's direction first, ascending.
+// Any topological order gives bit-identical fluxes (each flux is a pure
+// function of its upwind fluxes); only the schedule changes.
+// ---------------------------------------------------------------------------
+static std::vector<int64_t> priority_order(const std::vector<Chunk> &ch, const std::vector<int32_t> &dptr,
+                                           const std::vector<int32_t> &dep, const std::vector<int64_t> &stream_off,
+                                           int priority) {
+    const int64_t n = (int64_t)ch.size();
+    const int base = priority & 0xf;
+    const bool angle = (priority & JSWEEP_PRIORITY_ANGLE_MAJOR) != 0;
+    // longest path (in chunks) to a sink: chunks are in a topological order,
+    // so one reverse pass settles every chunk before its upwind chunks
+    std::vector<int32_t> bl(n, 0);
+    if (base != JSWEEP_PRIORITY_BFS)
+        for (int64_t c = n - 1; c >= 0; --c)
+            for (int32_t k = dptr[c]; k < dptr[c + 1]; ++k) bl[dep[k]] = std::max(bl[dep[k]], bl[c] + 1);
+    // downstream lists and counts of upwind chunks
+    std::vector<int32_t> cnt(n), uptr(n + 1, 0), down((size_t)dptr[n]);
+    for (int64_t c = 0; c < n; ++c) {
+        cnt[c] = dptr[c + 1] - dptr[c];
+        for (int32_t k = dptr[c]; k < dptr[c + 1]; ++k) ++uptr[dep[k] + 1];
+    }
+    for (int64_t c = 0; c < n; ++c) uptr[c + 1] += uptr[c];
+    {
+        std::vector<int32_t> fill(uptr.begin(), uptr.end() - 1);
+        for (int64_t c = 0; c < n; ++c)
+            for (int32_t k = dptr[c]; k < dptr[c + 1]; ++k) down[fill[dep[k]]++] = (int32_t)c;
+    }
+    struct Key {
+        int64_t a, b, c;
+        bool operator>(const Key &o) const { return a != o.a ? a > o.a : b != o.b ? b > o.b : c > o.c; }
+    };
+    auto key = [&](int64_t c) {
+        const int64_t m = angle ? (int64_t)(ch[c].a & 0xffffu) : 0;
+        const int64_t k = base == JSWEEP_PRIORITY_LDCP ? -(int64_t)bl[c] : base == JSWEEP_PRIORITY_SLBD ? bl[c] : 0;
+        return Key{m, k, c};
+    };
+    std::vector<int64_t> order;
+    order.reserve(n);
+    for (int sidx = 0; sidx < kStreams; ++sidx) {
+        std::priority_queue<Key, std::vector<Key>, std::greater<Key>> ready;
+        for (int64_t c = stream_off[sidx]; c < stream_off[sidx + 1]; ++c)
+            if (cnt[c] == 0) ready.push(key(c));
+        while (!ready.empty()) {
+            const int64_t c = ready.top().c;
+            ready.pop();
+            order.push_back(c);
+            for (int32_t k = uptr[c]; k < uptr[c + 1]; ++k)
+                if (--cnt[down[k]] == 0) ready.push(key(down[k]));
+        }
+        if ((int64_t)order.size() != stream_off[sidx + 1])
+            fail(JSWEEP_E_DEVICE, "coarsened graph of a stream is not acyclic");
+    }
+    return order;
+}
+
+template <int NF, int DIM>
+static void reorder_impl(Graph &g, int priority, hipStream_t s) {
+    const int64_t nch = g.n_chunks;
+    std::vector<Chunk> ch(nch);
+    std::vector<int32_t> dptr(nch + 1), dep((size_t)std::max<int64_t>(1, g.n_dep));
+    JSW_HIP(hipMemcpyAsync(ch.data(), g.chunks.p, sizeof(Chunk) * nch, hipMemcpyDeviceToHost, s));
+    JSW_HIP(hipMemcpyAsync(dptr.data(), g.dep_ptr.p, 4 * (nch + 1), hipMemcpyDeviceToHost, s));
+    if (g.n_dep) JSW_HIP(hipMemcpyAsync(dep.data(), g.dep.p, 4 * (size_t)g.n_dep, hipMemcpyDeviceToHost, s));
+    JSW_HIP(hipStreamSynchronize(s));
+    // the level order first (every other order is computed from it, so the
+    // result does not depend on the order the graph had before)
+    std::vector<int64_t> back(nch);
+    {
+        std::vector<int64_t> lv(nch);
+        for (int64_t c = 0; c < nch; ++c) lv[c] = c;
+        // level of a chunk (all of its vertices share it)
+        std::vector<int32_t> lev_of(nch);
+        for (int64_t c = 0; c < nch; ++c) {
+            const int m = (int)(ch[c].a & 0xffffu);
+            const int64_t *p = g.lvl_ptr_h.data() + g.lvl_off_h[m];
+            lev_of[c] = (int32_t)(std::upper_bound(p, p + g.nlev_h[m] + 1, (int64_t)ch[c].b) - p - 1);
+        }
+        std::stable_sort(lv.begin(), lv.end(), [&](int64_t x, int64_t y) {
+            const int sx = g.dir_stream_h[ch[x].a & 0xffffu], sy = g.dir_stream_h[ch[y].a & 0xffffu];
+            if (sx != sy) return sx < sy;
+            if (lev_of[x] != lev_of[y]) return lev_of[x] < lev_of[y];
+            const uint32_t mx = ch[x].a & 0xffffu, my = ch[y].a & 0xffffu;
+            if (mx != my) return mx < my;
+            return ch[x].b < ch[y].b;
+        });
+        back = lv;
+    }
+    bool identity = true;
+    for (int64_t c = 0; c < nch && identity; ++c) identity = back[c] == c;
+    if (!identity) {
+        // deps in level-order indices
+        std::vector<int64_t> inv(nch);
+        for (int64_t c = 0; c < nch; ++c) inv[back[c]] = c;
+        std::vector<Chunk> lch(nch);
+        std::vector<int32_t> lptr(nch + 1, 0), ldep(dep.size());
+        for (int64_t c = 0; c < nch; ++c) {
+            const int64_t o = back[c];
+            lch[c] = ch[o];
+            lptr[c + 1] = lptr[c] + (dptr[o + 1] - dptr[o]);
+            for (int32_t k = dptr[o], j = lptr[c]; k < dptr[o + 1]; ++k, ++j) ldep[j] = (int32_t)inv[dep[k]];
+        }
+        ch.swap(lch);
+        dptr.swap(lptr);
+        dep.swap(ldep);
+    }
+    const std::vector<int64_t> order = priority_order(ch, dptr, dep, g.stream_off_h, priority);
+    std::vector<Chunk> out(nch);
+    for (int64_t c = 0; c < nch; ++c) out[c] = ch[order[c]];
+    // first chunk (in the new order) of every (direction, level)
+    std::fill(g.lvl_chunk_h.begin(), g.lvl_chunk_h.end(), INT32_MAX);
+    for (int64_t c = 0; c < nch; ++c) {
+        const int m = (int)(out[c].a & 0xffffu);
+        const int64_t *p = g.lvl_ptr_h.data() + g.lvl_off_h[m];
+        const int L = (int)(std::upper_bound(p, p + g.nlev_h[m] + 1, (int64_t)out[c].b) - p - 1);
+        int32_t &f = g.lvl_chunk_h[g.lvl_off_h[m] + L];
+        f = std::min(f, (int32_t)c);
+    }
+    for (auto &f : g.lvl_chunk_h)
+        if (f == INT32_MAX) f = 0;
+    JSW_HIP(hipMemcpyAsync(g.lvl_chunk_d.p, g.lvl_chunk_h.data(), 4 * g.lvl_chunk_h.size(), hipMemcpyHostToDevice, s));
+    JSW_HIP(hipMemcpyAsync(g.chunks.p, out.data(), sizeof(Chunk) * nch, hipMemcpyHostToDevice, s));
+    JSW_HIP(hipStreamSynchronize(s));   // before the host vectors go
+    const LagView lag{g.n_lag ? g.lag_mv.as<uint64_t>() : nullptr, g.n_lag ? g.lag_u.as<int32_t>() : nullptr, g.n_lag};
+    build_coarsened<NF, DIM>(g, lag, s);
+    build_program<NF, DIM>(g, lag, s);
+    build_compact(g, s);
+    // everything kept in chunk order is rebuilt on its next use
+    g.pa32.release();
+    g.pden32.release();
+    g.pvol64.release();
+    g.pvol32.release();
+    g.den64_ok = g.den32_ok = false;
+    g.dd_state[0] = g.dd_state[1] = 0;
+    g.priority = priority;
+    JSW_HIP(hipStreamSynchronize(s));
+}
+
+void set_priority(Graph &g, int priority, hipStream_t s) {
+    const int base = priority & 0xf;
+    if ((priority & ~(0xf | JSWEEP_PRIORITY_ANGLE_MAJOR)) || base < JSWEEP_PRIORITY_BFS || base > JSWEEP_PRIORITY_SLBD)
+        fail(JSWEEP_E_INVALID_ARG, "unknown work-list priority");
+    if (priority == g.priority || !g.n_chunks) {
+        g.priority = priority;
+        return;
+    }
+    if (g.ctype == JSWEEP_TRI) reorder_impl<3, 2>(g, priority, s);
+    else if (g.ctype == JSWEEP_TET) reorder_impl<4, 3>(g, priority, s);
+    else reorder_impl<6, 3>(g, priority, s);
 }
 
 void build_dag(Graph &g, bool lag_cycles, hipStream_t s) {

@@ -452,6 +452,7 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
           double tol, int32_t max_iter, const jsweep_params *params, double *phi, double *psi_out,
           jsweep_solve_stats *stats, hipStream_t s) {
     auto t_start = std::chrono::steady_clock::now();
+    if (params && params->priority && params->priority != g.priority) set_priority(g, params->priority, s);
     const bool refined = (mode & 0xff) == JSWEEP_FP32_REFINED;
     const bool warm = (mode & JSWEEP_WARM_START) != 0;
     const int64_t N = g.nc * g.nd;
