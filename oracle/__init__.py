@@ -60,6 +60,10 @@ def _load():
     lib.orc_residual.restype = dbl
     lib.orc_si.argtypes = [P, P, P, P, dbl, P, i32, dbl, P, P, P]
     lib.orc_si.restype = i32
+    lib.orc_mg_residual.argtypes = [P, i32, P, P, P, dbl, P, P, P]
+    lib.orc_mg_residual.restype = dbl
+    lib.orc_mg_si.argtypes = [P, i32, P, P, P, dbl, P, i32, dbl, P, P, P]
+    lib.orc_mg_si.restype = i32
     _lib = lib
     return lib
 
@@ -172,6 +176,25 @@ class Graph:
         hist = np.zeros(max(1, max_iter))
         it = self._lib.orc_si(self._h, _p(st), _p(ss), _p(qq), float(psi_b), _p(w), int(max_iter), float(tol),
                               _p(psi), _p(phi), _p(hist))
+        return psi, phi, hist[:it]
+
+    # -- multigroup (arrays: sigma_t, q [G, nc]; sigma_s [G, G, nc] from g' (first index)
+    #    into g (second); psi [G, nd, nc]; phi [G, nc]) -------------------------------
+    def mg_residual(self, sigma_t, sigma_s, q, weight, psi, phi, psi_b: float = 0.0):
+        st, ss, qq, w = _f64(sigma_t), _f64(sigma_s), _f64(q), _f64(weight)
+        G = st.shape[0]
+        return self._lib.orc_mg_residual(self._h, G, _p(st), _p(ss), _p(qq), float(psi_b), _p(w), _p(_f64(psi)),
+                                         _p(_f64(phi)))
+
+    def mg_source_iteration(self, sigma_t, sigma_s, q, weight, max_iter: int, tol: float = 0.0,
+                            psi_b: float = 0.0):
+        st, ss, qq, w = _f64(sigma_t), _f64(sigma_s), _f64(q), _f64(weight)
+        G = st.shape[0]
+        psi = np.zeros((G, self.n_dirs, self.n_cells))
+        phi = np.zeros((G, self.n_cells))
+        hist = np.zeros(max(1, max_iter))
+        it = self._lib.orc_mg_si(self._h, G, _p(st), _p(ss), _p(qq), float(psi_b), _p(w), int(max_iter), float(tol),
+                                 _p(psi), _p(phi), _p(hist))
         return psi, phi, hist[:it]
 
 

@@ -690,3 +690,104 @@ int orc_si(const orc_graph *g, const double *sigma_t, const double *sigma_s, con
     free(s); free(prev);
     return it;
 }
+
+/* ------------------------------------------------------------------ */
+/* multigroup                                                           */
+/* ------------------------------------------------------------------ */
+
+/* Multigroup transport with isotropic scattering between energy groups
+ * (the appendix form of the transport equation: a flux per ordinate m and
+ * group g, collisions coupling every (m', g') into (m, g) through the
+ * direction weights and a group-to-group scattering cross section):
+ *   Omega_m . grad psi_{m,g} + sigma_t,g psi_{m,g}
+ *       = q_g + sum_{g'} sigma_s,g'->g phi_{g'},   phi_g = sum_m w_m psi_{m,g}.
+ * Layouts: sigma_t, q, phi [G][nc]; sigma_s [G][G][nc] with the cross
+ * section from group g' into group g at (g' * G + g) * nc + K; psi
+ * [G][nd][nc].  Every group uses the same sweep graph (the geometry and
+ * the directions do not depend on the energy). */
+
+/* Group source s_{K,g} = q_{K,g} + sum over g' (ascending) of
+ * sigma_s,g'->g,K phi_{K,g'}. */
+static void mg_source(const orc_graph *g, int G, const double *sigma_s, const double *q, const double *phi,
+                      int grp, double *s) {
+    int64_t n = g->nc;
+    for (int64_t K = 0; K < n; ++K) {
+        double v = q[(int64_t)grp * n + K];
+        for (int gp = 0; gp < G; ++gp)
+            v = v + sigma_s[((int64_t)gp * G + grp) * n + K] * phi[(int64_t)gp * n + K];
+        s[K] = v;
+    }
+}
+
+/* Residual of the multigroup equations with the full (un-lagged)
+ * streaming operator:
+ *   r_{K,m,g} = s_{K,g} - (den_g psi_{K,m,g} - in_{K,m,g}) / V_K
+ * with s the group source above (from the given phi), den_g and in as in
+ * the single-group residual with sigma_t,g.  Returns
+ * rho = sqrt(sum_g sum_K V_K sum_m w_m r^2) / sqrt(sum_g sum_K V_K q_g^2)
+ * (without the denominator when q = 0). */
+double orc_mg_residual(const orc_graph *g, int G, const double *sigma_t, const double *sigma_s, const double *q,
+                       double psi_b, const double *w, const double *psi, const double *phi) {
+    int64_t n = g->nc, N = n * g->nd;
+    double *s = malloc(sizeof(double) * (size_t)n);
+    double rr = 0.0, qq = 0.0;
+    for (int grp = 0; grp < G; ++grp) {
+        mg_source(g, G, sigma_s, q, phi, grp, s);
+        const double *st = sigma_t + (int64_t)grp * n;
+        const double *pg = psi + (int64_t)grp * N;
+        for (int64_t K = 0; K < n; ++K) {
+            double cell = 0.0;
+            for (int m = 0; m < g->nd; ++m) {
+                const double *om = g->omega + 3 * m;
+                const double *pm = pg + (int64_t)m * n;
+                double in = 0.0, den = st[K] * g->vol[K];
+                for (int j = 0; j < g->nfpc; ++j) {
+                    int64_t nb;
+                    double d = out_d(g, om, K, j, &nb);
+                    if (d < 0.0) in = in + (-d) * (nb < 0 ? psi_b : pm[nb]);
+                    else if (d > 0.0) den = den + d;
+                }
+                double res = s[K] - (den * pm[K] - in) / g->vol[K];
+                cell = cell + w[m] * (res * res);
+            }
+            double qk = q[(int64_t)grp * n + K];
+            rr = rr + g->vol[K] * cell;
+            qq = qq + g->vol[K] * (qk * qk);
+        }
+    }
+    free(s);
+    return qq > 0.0 ? sqrt(rr) / sqrt(qq) : sqrt(rr);
+}
+
+/* Multigroup source iteration from psi = phi = 0, Jacobi over groups
+ * (every group's source from the previous iterate of all groups, then the
+ * sweeps of every direction and group):
+ *   s_g = q_g + sum_g' sigma_s,g'->g phi_g';  sweep (m, g) for all m, g
+ *   (lagged in-edges take the previous iterate of the same group);
+ *   phi_g = sum_m w_m psi_{m,g};  rho = multigroup residual.
+ * Stops after max_iter iterations or once rho <= tol (tol <= 0: run all);
+ * hist (may be NULL) receives rho per iteration.  Returns iterations done. */
+int orc_mg_si(const orc_graph *g, int G, const double *sigma_t, const double *sigma_s, const double *q, double psi_b,
+              const double *w, int max_iter, double tol, double *psi, double *phi, double *hist) {
+    int64_t n = g->nc, N = n * g->nd;
+    double *s = malloc(sizeof(double) * (size_t)n * (size_t)G);
+    double *prev = g->nlag ? malloc(sizeof(double) * (size_t)N) : NULL;
+    memset(psi, 0, sizeof(double) * (size_t)N * (size_t)G);
+    memset(phi, 0, sizeof(double) * (size_t)n * (size_t)G);
+    int it = 0;
+    while (it < max_iter) {
+        for (int grp = 0; grp < G; ++grp) mg_source(g, G, sigma_s, q, phi, grp, s + (int64_t)grp * n);
+        for (int grp = 0; grp < G; ++grp) {
+            double *pg = psi + (int64_t)grp * N;
+            if (prev) memcpy(prev, pg, sizeof(double) * (size_t)N);
+            orc_sweep(g, sigma_t + (int64_t)grp * n, s + (int64_t)grp * n, 0, psi_b, prev, pg, 0);
+            orc_phi(g, w, pg, phi + (int64_t)grp * n);
+        }
+        double rho = orc_mg_residual(g, G, sigma_t, sigma_s, q, psi_b, w, psi, phi);
+        if (hist) hist[it] = rho;
+        ++it;
+        if (tol > 0.0 && rho <= tol) break;
+    }
+    free(s); free(prev);
+    return it;
+}

@@ -120,6 +120,27 @@ def dense_si_solution(S, fcell, cface, vol, sigma_t, sigma_s, q, omega, weight, 
     return np.linalg.solve(A, b).reshape(nd, n)
 
 
+def dense_mg_solution(S, fcell, cface, vol, sigma_t, sigma_s, q, omega, weight, dim, psi_b=0.0):
+    """Dense solve of the multigroup system: unknowns psi[g, m, K]; block
+    (g, m) holds the un-lagged streaming operator with sigma_t,g, and every
+    (g', m') couples into (g, m) through -sigma_s[g', g] V w_m'.  Returns
+    psi [G, nd, n]."""
+    G, n, nd = sigma_t.shape[0], len(vol), len(weight)
+    M = G * nd * n
+    A = np.zeros((M, M))
+    b = np.zeros(M)
+    blk = lambda g, m: slice((g * nd + m) * n, (g * nd + m + 1) * n)  # noqa: E731
+    for g in range(G):
+        for m in range(nd):
+            L, bnd, _ = dense_direction_operator(S, fcell, cface, vol, sigma_t[g], omega[m], dim)
+            A[blk(g, m), blk(g, m)] += L
+            b[blk(g, m)] = vol * q[g] + bnd * psi_b
+            for gp in range(G):
+                for mp in range(nd):
+                    A[blk(g, m), blk(gp, mp)] -= np.diag(sigma_s[gp, g] * vol * weight[mp])
+    return np.linalg.solve(A, b).reshape(G, nd, n)
+
+
 def closed_form_absorber(n, h, sigma_t, q, omega, digits=50):
     """Pure absorber on an undeformed n^3 hexahedral lattice with vacuum
     boundaries: the step recursion psi = g + a psi_x + b psi_y + c psi_z

@@ -429,6 +429,70 @@ def ensemble(seed: int = 4, count: int = 256, min_cells: int = 500, max_cells: i
     return out
 
 
+@dataclass
+class MultigroupProblem:
+    """Multigroup inputs on one mesh and quadrature: sigma_t, q [G, nc] and
+    the isotropic scattering cross sections sigma_s [G, G, nc] from group g'
+    (first index) into group g (second index)."""
+    name: str
+    mesh: Mesh
+    omega: np.ndarray
+    weight: np.ndarray
+    sigma_t: np.ndarray
+    sigma_s: np.ndarray
+    q: np.ndarray
+    psi_boundary: float = 0.0
+
+    @property
+    def n_cells(self) -> int:
+        return self.mesh.n_cells
+
+    @property
+    def n_dirs(self) -> int:
+        return int(self.omega.shape[0])
+
+    @property
+    def n_groups(self) -> int:
+        return int(self.sigma_t.shape[0])
+
+
+def multigroup(base: Problem, groups: int = 4, seed: int = 7) -> MultigroupProblem:
+    """Synthetic multigroup data on a single-group problem's mesh and
+    quadrature (the paper's unstructured runs use 4 energy groups).
+    Group g has sigma_t,g = f_g sigma_t with f = 0.5, 0.8, 1.2, 2.0, 3.0, ...
+    (x1.5 per further group) and source q_g = q / 2^g.  Its scattering
+    ratio is the base problem's c = sigma_s / sigma_t per cell; that total
+    is shared between destinations in proportions 0.75 (same group), 0.20
+    (next group, downscatter) and 0.05 (previous group, upscatter), each
+    proportion times a per-cell factor U[0.8, 1.2], renormalised over the
+    destinations that exist.  Draw order: one [G, 3, nc] array of factors."""
+    rng = np.random.default_rng(seed)
+    G, nc = int(groups), base.n_cells
+    f = [0.5, 0.8, 1.2, 2.0]
+    while len(f) < G:
+        f.append(f[-1] * 1.5)
+    c = np.where(base.sigma_t > 0, base.sigma_s / base.sigma_t, 0.0)
+    fac = rng.uniform(0.8, 1.2, size=(G, 3, nc))
+    st = np.stack([base.sigma_t * f[g] for g in range(G)])
+    ss = np.zeros((G, G, nc))
+    for g in range(G):
+        share = np.zeros((3, nc))
+        share[0] = 0.75 * fac[g, 0]
+        if g + 1 < G:
+            share[1] = 0.20 * fac[g, 1]
+        if g - 1 >= 0:
+            share[2] = 0.05 * fac[g, 2]
+        share /= share.sum(axis=0)
+        tot = c * st[g]
+        ss[g, g] = tot * share[0]
+        if g + 1 < G:
+            ss[g, g + 1] = tot * share[1]
+        if g - 1 >= 0:
+            ss[g, g - 1] = tot * share[2]
+    q = np.stack([base.q / (2.0 ** g) for g in range(G)])
+    return MultigroupProblem(f"{base.name}_g{G}", base.mesh, base.omega, base.weight, st, ss, q, base.psi_boundary)
+
+
 def config(k: int, scale: str = "full") -> Problem:
     """The five benchmark configurations (k = 1..5; 4 is ``ensemble``).
 
