@@ -279,6 +279,32 @@ int jsweep_solve(jsweep_graph g, const double *sigma_t, const double *sigma_s, c
                  double psi_boundary, int32_t mode, double tol, int32_t max_iter, const jsweep_params *params,
                  double *phi, double *psi, jsweep_solve_stats *stats, void *hip_stream);
 
+/* Multigroup source iteration (the appendix form of the transport
+ * equation, with a flux per ordinate and energy group and isotropic
+ * scattering from every group into every group; appendix algorithm "Source
+ * iterative Sn solver": 2.1 scattering source and coupling terms, 2.2 sweeps
+ * of every angle and energy, 2.3 error reduction):
+ *   Omega_m . grad psi_{m,g} + sigma_t,g psi_{m,g}
+ *       = q_g + sum_{g'} sigma_s,g'->g phi_{g'},   phi_g = sum_m w_m psi_{m,g}.
+ * Jacobi over groups: each iteration takes every group's source from the
+ * previous iterate of all groups (sum over g' ascending), then sweeps every
+ * (direction, group) in one launch of the data-driven kernel (the groups
+ * share the graph and its sweep program), then phi_g (ascending m) and
+ *   rho = sqrt(sum_g sum_K V_K sum_m w_m r_{K,m,g}^2) / sqrt(sum_g sum_K V_K q_{K,g}^2)
+ * with r the residual of the full (un-lagged) operator.  Stops once
+ * rho <= tol (tol = 0: exactly max_iter iterations).  FP64 throughout.
+ *   n_groups        1 .. 8
+ *   sigma_t, q      device [n_groups * n_cells], group-major
+ *   sigma_s         device [n_groups * n_groups * n_cells]: the cross
+ *                   section from group g' into group g of cell K at
+ *                   (g' * n_groups + g) * n_cells + K
+ *   phi             device [n_groups * n_cells] (out)
+ *   psi             device [n_groups * n_dirs * n_cells] (out) or NULL
+ * Starts from psi = 0.  Errors as jsweep_solve. */
+int jsweep_solve_groups(jsweep_graph g, int32_t n_groups, const double *sigma_t, const double *sigma_s, const double *q,
+                        double psi_boundary, double tol, int32_t max_iter, const jsweep_params *params, double *phi,
+                        double *psi, jsweep_solve_stats *stats, void *hip_stream);
+
 /* One problem instance of a batch (device pointers as in jsweep_solve). */
 typedef struct {
     const double *sigma_t, *sigma_s, *q;

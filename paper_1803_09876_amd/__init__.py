@@ -48,7 +48,7 @@ EXPORTED = [
     "jsweep_build_graph", "jsweep_graph_info", "jsweep_graph_export", "jsweep_graph_lagged", "jsweep_sweep",
     "jsweep_solve", "jsweep_solve_batch", "jsweep_autotune", "jsweep_profile", "jsweep_profile_read",
     "jsweep_trace", "jsweep_trace_read", "jsweep_graph_destroy", "jsweep_error_string", "jsweep_last_error",
-    "jsweep_set_params", "jsweep_patch_info", "jsweep_program_info",
+    "jsweep_set_params", "jsweep_patch_info", "jsweep_program_info", "jsweep_solve_groups",
 ]
 
 
@@ -109,6 +109,7 @@ def load_library(path: str | None = None):
     lib.jsweep_sweep.argtypes = [P, P, P, P, P, dbl, P]
     lib.jsweep_solve.argtypes = [P, P, P, P, dbl, i32, dbl, i32, P, P, P, P, P]
     lib.jsweep_solve_batch.argtypes = [i32, P, P, i32, dbl, i32, P, P, P]
+    lib.jsweep_solve_groups.argtypes = [P, i32, P, P, P, dbl, dbl, i32, P, P, P, P, P]
     lib.jsweep_autotune.argtypes = [i32, P, i32, P]
     lib.jsweep_set_params.argtypes = [P, P]
     lib.jsweep_patch_info.argtypes = [P, P, P]
@@ -123,7 +124,7 @@ def load_library(path: str | None = None):
     lib.jsweep_last_error.argtypes = []
     lib.jsweep_last_error.restype = ctypes.c_char_p
     for name in ("jsweep_build_graph", "jsweep_graph_info", "jsweep_graph_export", "jsweep_graph_lagged",
-                 "jsweep_sweep", "jsweep_solve", "jsweep_solve_batch", "jsweep_autotune", "jsweep_profile",
+                 "jsweep_sweep", "jsweep_solve", "jsweep_solve_groups", "jsweep_solve_batch", "jsweep_autotune", "jsweep_profile",
                  "jsweep_profile_read", "jsweep_trace", "jsweep_trace_read", "jsweep_set_params",
                  "jsweep_patch_info", "jsweep_program_info"):
         getattr(lib, name).restype = ctypes.c_int
@@ -287,6 +288,33 @@ def jsweep_solve(g: Graph, sigma_t, sigma_s, q, phi, psi=None, psi_boundary: flo
     return out
 
 
+def jsweep_solve_groups(g: Graph, sigma_t, sigma_s, q, phi, psi=None, psi_boundary: float = 0.0, tol: float = 1e-8,
+                        max_iter: int = 1000, params: Params | None = None, history: int = 0, stream=None,
+                        allow_not_converged: bool = False):
+    """Multigroup (Jacobi over groups) FP64 source iteration.  sigma_t, q,
+    phi: [G, n_cells]; sigma_s: [G, G, n_cells] (from g' into g); psi:
+    [G, n_dirs, n_cells] or None.  Returns a stats dict."""
+    lib = load_library()
+    n = g.n_cells
+    G = int(sigma_t.shape[0]) if sigma_t.dim() == 2 else sigma_t.numel() // n
+    st = SolveStats()
+    hist = np.zeros(max(history, 1))
+    if history:
+        st.residual_history = hist.ctypes.data
+        st.history_capacity = history
+    rc = lib.jsweep_solve_groups(g.handle, G, _f64(sigma_t, G * n), _f64(sigma_s, G * G * n), _f64(q, G * n),
+                                 float(psi_boundary), float(tol), int(max_iter),
+                                 ctypes.byref(params) if params is not None else None, _f64(phi, G * n),
+                                 _f64(psi, G * n * g.n_dirs) if psi is not None else None, ctypes.byref(st),
+                                 _stream(stream))
+    _check(rc, allow=(JSWEEP_E_NOT_CONVERGED,) if allow_not_converged else ())
+    out = {k: getattr(st, k) for k in ("outer_iters", "sweeps", "residual", "seconds")}
+    out["converged"] = rc == JSWEEP_OK
+    if history:
+        out["history"] = hist[:st.history_len].copy()
+    return out
+
+
 def jsweep_solve_batch(graphs, problems, mode: int = JSWEEP_FP32_REFINED, tol: float = 1e-8, max_iter: int = 1000,
                        params: Params | None = None, stream=None, allow_not_converged: bool = False):
     """problems: list of dicts with sigma_t, sigma_s, q, phi (tensors),
@@ -385,4 +413,5 @@ graph_lagged = jsweep_graph_lagged
 sweep = jsweep_sweep
 solve = jsweep_solve
 solve_batch = jsweep_solve_batch
+solve_groups = jsweep_solve_groups
 autotune = jsweep_autotune

@@ -304,6 +304,19 @@ int jsweep_solve(jsweep_graph h, const double *sigma_t, const double *sigma_s, c
     });
 }
 
+int jsweep_solve_groups(jsweep_graph h, int32_t n_groups, const double *sigma_t, const double *sigma_s, const double *q,
+                        double psi_boundary, double tol, int32_t max_iter, const jsweep_params *params, double *phi,
+                        double *psi, jsweep_solve_stats *stats, void *hip_stream) {
+    return guarded([&]() -> int {
+        if (!h || !sigma_t || !sigma_s || !q || !phi) fail(JSWEEP_E_INVALID_ARG, "NULL argument");
+        if (n_groups < 1 || n_groups > kMaxGroups) fail(JSWEEP_E_INVALID_ARG, "group count out of range (1..8)");
+        if (max_iter < 1 || !(tol >= 0.0) || !std::isfinite(psi_boundary)) fail(JSWEEP_E_INVALID_ARG, "bad tolerance or iteration limit");
+        if (stats && stats->residual_history && stats->history_capacity < 0) fail(JSWEEP_E_INVALID_ARG, "bad history capacity");
+        return solve_groups(*G(h), n_groups, sigma_t, sigma_s, q, psi_boundary, tol, max_iter, params, phi, psi, stats,
+                            reinterpret_cast<hipStream_t>(hip_stream));
+    });
+}
+
 int jsweep_solve_batch(int32_t n, const jsweep_graph *graphs, const jsweep_problem *problems, int32_t mode, double tol,
                        int32_t max_iter, const jsweep_params *params, jsweep_solve_stats *stats, void *hip_stream) {
     return guarded([&]() -> int {

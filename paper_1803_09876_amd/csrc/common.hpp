@@ -225,7 +225,7 @@ struct Graph {
     bool den64_ok = false, den32_ok = false;
     DevBuf psi_pos;                      // [nd*nc] fluxes of the running sweep in level order (LDS-window sweeps)
     DevBuf dd_pos[2];                    // [nd*nc] alternating level-order flux arrays of the work-list sweep
-    int dd_state[2] = {0, 0};            // element size whose empty marker fills each array, 0 if unknown
+    int dd_state[2] = {0, 0};            // element size | group blocks << 8 of the empty markers each array holds, 0 if unknown
     int dd_cur = 0;                      // array of the next work-list sweep
     DevBuf pvol64, pvol32;               // [64 n_chunks] cell volume in program order (ring sweep)
     DevBuf vsc;                          // [nc] V s (or {V, s}) of the running sweep, per cell
@@ -284,8 +284,22 @@ void launch_sweep64(Graph &g, const double *src_cell, double *psi, double psi_b,
                     bool prepared = false);
 void launch_sweep32(Graph &g, const float *src_dir, const float *src_cell, float *psi, const jsweep_params *p,
                     hipStream_t s, bool prepared = false);
-int check_sweep_status(Graph &g, hipStream_t s);   // JSWEEP_OK or JSWEEP_E_STALLED
-int persistent_waves(Graph &g, bool fp32, const jsweep_params *p, int *waves_per_block);
+// Multigroup FP64 sweep: groups (<= kMaxGroups) energy groups of one graph
+// in one launch of the data-driven kernel.  The caller has prepared
+// g.vsc as V s per (group, cell) [groups * nc] and zeroed the stream
+// tickets; den [groups][64 n_chunks] holds each group's denominators and
+// lag_val [groups][n_lag] each group's previous-iterate lagged values.
+// psi: [groups][nd][nc] cell-order fluxes (out).
+constexpr int kMaxGroups = 8;
+struct GroupSweep {
+    int groups;
+    const double *den;
+    const double *lag_val;
+    double psi_b;
+};
+void launch_sweep_groups(Graph &g, double *psi, const GroupSweep &mg, const jsweep_params *p, hipStream_t s);
+int check_sweep_status(Graph &g, hipStream_t s);   // JSWEEP_OK, JSWEEP_E_STALLED or JSWEEP_E_PLACEMENT
+int persistent_waves(Graph &g, bool fp32, const jsweep_params *p, int *waves_per_block, int groups = 0);
 int sweep_strategy(const Graph &g, const jsweep_params *p);
 
 // patch-task sweep (patch.hip): program built on first use; false when the
@@ -316,6 +330,9 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
           jsweep_solve_stats *stats, hipStream_t s);
 void scalar_flux(Graph &g, const double *psi, double *phi, hipStream_t s);
 void lag_snapshot64(Graph &g, const double *psi, hipStream_t s);
+int solve_groups(Graph &g, int G, const double *sigma_t, const double *sigma_s, const double *q, double psi_b,
+                 double tol, int32_t max_iter, const jsweep_params *params, double *phi, double *psi,
+                 jsweep_solve_stats *stats, hipStream_t s);
 int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems, int32_t mode, double tol,
                 int32_t max_iter, const jsweep_params *params, jsweep_solve_stats *stats, hipStream_t s);
 

@@ -96,6 +96,12 @@ struct SweepArgs {
     uint64_t watchdog_ticks;
     uint32_t *stamps;                        // tracing: [3 * n_chunks] or null
     int32_t n_xcc;                           // XCDs the workgroups are dealt over
+    // energy groups swept together (multigroup kernels, NG > 1): group g's
+    // arrays follow group 0's at these strides
+    int32_t n_groups;
+    int64_t gs_pos;                          // psi, psi_pos, pos_next: nd * nc
+    int64_t gs_den;                          // pden: stride (64 * n_chunks)
+    int64_t gs_lag;                          // lag_val: n_lag
 };
 
 template <class T>
@@ -144,24 +150,26 @@ __device__ __forceinline__ Real face_dot(const CellRec<Real, NF, DIM> &r, int j,
 }
 
 // A chunk's part of the sweep program as one lane holds it
-template <class Real, int NS>
+template <class Real, int NS, int NG = 1>
 struct LaneProg {
     int32_t item;                            // cell, or -1 past the chunk's end
     int32_t w2;                              // descriptor word (lanes 0 .. 31)
-    Real den;
+    Real den[NG];                            // one denominator per energy group
     int32_t code[NS];
     Real af[NS];
 };
 
-template <class Real, int NS>
-__device__ __forceinline__ void load_prog(const SweepArgs<Real> &a, int64_t c, int lane, LaneProg<Real, NS> &P) {
+template <class Real, int NS, int NG>
+__device__ __forceinline__ void load_prog(const SweepArgs<Real> &a, int64_t c, int lane, LaneProg<Real, NS, NG> &P) {
     // read once per sweep: streamed past the caches (non-temporal), which
     // leaves L2 to the fluxes being handed off and merged
     const int32_t *blk = a.cblk + c * kBlock;
     P.item = __builtin_nontemporal_load(blk + lane);
     P.w2 = lane < 32 ? __builtin_nontemporal_load(blk + 64 + lane) : -1;
     const int64_t idx = c * 64 + lane;
-    P.den = __builtin_nontemporal_load(a.pden + idx);
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+        P.den[g] = (g == 0 || g < a.n_groups) ? __builtin_nontemporal_load(a.pden + g * a.gs_den + idx) : Real(1);
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
         P.code[j] = __builtin_nontemporal_load(a.pcode + j * a.stride + idx);
@@ -181,10 +189,13 @@ __device__ __forceinline__ void keep_live(const T &v) {
 // NS: inflow slots per vertex in the program arrays (the program's ns, up to
 // the faces per cell, or kCompactSlots for the compact program); NSX: slots
 // past NS that the compact program keeps in the chunk blocks (0: none);
-// TRACE: record take / ready / done stamps per chunk
-template <class Real, int NS, int NSX, bool TRACE>
+// TRACE: record take / ready / done stamps per chunk; NG: energy groups
+// swept per chunk (multigroup: a.n_groups <= NG groups share the chunk's
+// program, each with its own denominator, source and fluxes).
+template <class Real, int NS, int NSX, bool TRACE, int NG = 1>
 __global__ void k_sweep(SweepArgs<Real> a) {
     constexpr int NX = NSX > 0 ? NSX : 1;
+    static_assert(NG == 1 || (NSX == 0 && sizeof(Real) == 8), "multigroup sweeps read the full FP64 program");
     const int lane = threadIdx.x & 63;
     // a workgroup off its stream's XCD takes no chunk (it holds nothing
     // anyone waits for) and raises the placement flag
@@ -192,6 +203,7 @@ __global__ void k_sweep(SweepArgs<Real> a) {
     const int stream = (int)(blockIdx.x % kStreams);
     const int64_t first = a.stream_off[stream];
     const int64_t per_stream = a.stream_off[stream + 1] - first;
+    const int ng = NG == 1 ? 1 : a.n_groups;
     // tickets: each is a range of a.grab consecutive chunks of the stream.
     // A wavefront holds its current chunk, the next one (whose program is
     // loaded while the current one waits for its inputs) and one requested
@@ -204,7 +216,7 @@ __global__ void k_sweep(SweepArgs<Real> a) {
     int64_t t_end = t + a.grab;
     if (lane == 0) nxt = atomicAdd(ticket, (uint32_t)a.grab);
     if (t >= per_stream) return;
-    LaneProg<Real, NS> P;
+    LaneProg<Real, NS, NG> P;
     load_prog(a, first + t, lane, P);
     uint32_t t_take = (uint32_t)__builtin_amdgcn_s_memrealtime();
     int64_t pend = (int64_t)__builtin_amdgcn_readfirstlane(nxt);   // start of the requested range
@@ -226,7 +238,7 @@ __global__ void k_sweep(SweepArgs<Real> a) {
             tn_end = tn + a.grab;
             if (lane == 0) nxt = atomicAdd(ticket, (uint32_t)a.grab);
         }
-        LaneProg<Real, NS> Pn;
+        LaneProg<Real, NS, NG> Pn;
         uint32_t tn_take = 0;
         if (tn < per_stream) {
             load_prog(a, first + tn, lane, Pn);
@@ -239,31 +251,37 @@ __global__ void k_sweep(SweepArgs<Real> a) {
         const int64_t base = (int64_t)m * a.nc;
         const int64_t K = active ? (int64_t)P.item : 0;
         const int64_t own = base + pos0 + lane;
-        // V s of the cell (one gather from a per-cell array; in FP32 V and
-        // s, combined with the per-direction source after the poll, so that
-        // nothing waits for these loads before it)
-        Real num = Real(0);
+        // V s of the cell (one gather from a per-cell array per group; in
+        // FP32 V and s, combined with the per-direction source after the
+        // poll, so that nothing waits for these loads before it)
+        Real num[NG];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) num[g] = Real(0);
         float2 vs32 = make_float2(0.0f, 0.0f);
         float sd32 = 0.0f;
         if (active) {
             if constexpr (sizeof(Real) == 8) {
-                num = reinterpret_cast<const double *>(a.vs)[K];
+#pragma unroll
+                for (int g = 0; g < NG; ++g)
+                    if (g < ng) num[g] = reinterpret_cast<const double *>(a.vs)[g * a.nc + K];
             } else {
                 vs32 = reinterpret_cast<const float2 *>(a.vs)[K];
                 if (a.src_dir) sd32 = __builtin_nontemporal_load(a.src_dir + own);   // read once per sweep
             }
         }
         // upwind fluxes: interior and lagged ones are loaded together (one
-        // device-scope load per slot, the address selected without
-        // branching; other slots read the vertex's own entry and discard
-        // it).  The loads are repeated until no interior slot of any lane
-        // holds the empty marker; polls that keep failing back off.
+        // device-scope load per slot and group, the address selected
+        // without branching; other slots read the vertex's own entry and
+        // discard it).  The loads are repeated until no interior slot of any
+        // lane holds the empty marker; polls that keep failing back off.
         const Real *from[NS];
+        int64_t gstep[NS];
 #pragma unroll
         for (int j = 0; j < NS; ++j) {
             const int32_t cd = P.code[j];
             const bool lagged = cd <= -2 && cd != kNoFace;
             from[j] = cd >= 0 ? a.psi_pos + base + cd : lagged ? a.lag_val + (-(int64_t)cd - 2) : a.psi_pos + own;
+            gstep[j] = lagged ? a.gs_lag : a.gs_pos;
         }
         // the compact program's further slots: the chunk's few entries
         // (descriptor lanes 3 ..) go to their lanes
@@ -302,13 +320,17 @@ __global__ void k_sweep(SweepArgs<Real> a) {
                 from_x[k] = cd >= 0 ? a.psi_pos + base + cd : lagged ? a.lag_val + (-(int64_t)cd - 2) : a.psi_pos + own;
             }
         }
-        Real val[NS];
+        Real val[NG][NS];
         uint64_t t0 = 0;
         for (uint32_t spin = 0;; ++spin) {
             bool ok = true;
             if (active) {
 #pragma unroll
-                for (int j = 0; j < NS; ++j) val[j] = ld_coherent(from[j]);
+                for (int g = 0; g < NG; ++g)
+                    if (g < ng) {
+#pragma unroll
+                        for (int j = 0; j < NS; ++j) val[g][j] = ld_coherent(from[j] + g * gstep[j]);
+                    }
                 if constexpr (NSX > 0) {
                     if (nx > 0) {
 #pragma unroll
@@ -316,7 +338,11 @@ __global__ void k_sweep(SweepArgs<Real> a) {
                     }
                 }
 #pragma unroll
-                for (int j = 0; j < NS; ++j) ok = ok && !(P.code[j] >= 0 && is_empty(val[j]));
+                for (int g = 0; g < NG; ++g)
+                    if (g < ng) {
+#pragma unroll
+                        for (int j = 0; j < NS; ++j) ok = ok && !(P.code[j] >= 0 && is_empty(val[g][j]));
+                    }
 #pragma unroll
                 for (int k = 0; k < NX; ++k) ok = ok && !(code_x[k] >= 0 && is_empty(val_x[k]));
             }
@@ -355,33 +381,39 @@ __global__ void k_sweep(SweepArgs<Real> a) {
         at_cell = a.psi + base + K;
         at_next = a.pos_next + own;
         if (active) {
-            if constexpr (sizeof(Real) == 4) num = vs32.x * (a.src_dir ? sd32 + vs32.y : vs32.y);
-            // step-scheme balance, inflow faces in local face order
 #pragma unroll
-            for (int j = 0; j < NS; ++j) {
-                const int32_t cd = P.code[j];
-                const bool lagged = cd <= -2 && cd != kNoFace;
-                const Real v = (cd >= 0 || lagged) ? val[j] : (cd == -1 ? a.psi_b : Real(0));
-                if (cd != kNoFace) num = num + P.af[j] * v;
-            }
-            if constexpr (NSX > 0) {
+            for (int g = 0; g < NG; ++g) {
+                if (g >= ng) continue;
+                Real ng_num = num[g];
+                if constexpr (sizeof(Real) == 4) ng_num = vs32.x * (a.src_dir ? sd32 + vs32.y : vs32.y);
+                // step-scheme balance, inflow faces in local face order
 #pragma unroll
-                for (int k = 0; k < NX; ++k) {
-                    const int32_t cd = code_x[k];
+                for (int j = 0; j < NS; ++j) {
+                    const int32_t cd = P.code[j];
                     const bool lagged = cd <= -2 && cd != kNoFace;
-                    const Real v = (cd >= 0 || lagged) ? val_x[k] : (cd == -1 ? a.psi_b : Real(0));
-                    if (cd != kNoFace) num = num + af_x[k] * v;
+                    const Real v = (cd >= 0 || lagged) ? val[g][j] : (cd == -1 ? a.psi_b : Real(0));
+                    if (cd != kNoFace) ng_num = ng_num + P.af[j] * v;
                 }
+                if constexpr (NSX > 0) {
+#pragma unroll
+                    for (int k = 0; k < NX; ++k) {
+                        const int32_t cd = code_x[k];
+                        const bool lagged = cd <= -2 && cd != kNoFace;
+                        const Real v = (cd >= 0 || lagged) ? val_x[k] : (cd == -1 ? a.psi_b : Real(0));
+                        if (cd != kNoFace) ng_num = ng_num + af_x[k] * v;
+                    }
+                }
+                Real o = ng_num / P.den[g];
+                // a NaN carrying the marker's bits (never produced by
+                // arithmetic) would read as not yet computed
+                if (is_empty(o)) o = std::numeric_limits<Real>::quiet_NaN();
+                // the level-order store publishes the flux; the cell-order
+                // copy is read only after the kernel
+                at_pos[g * a.gs_pos] = o;
+                at_cell[g * a.gs_pos] = o;
+                __builtin_nontemporal_store(empty_marker<Real>(), at_next + g * a.gs_pos);   // read in the next sweep
+                if (g == 0) out = o;
             }
-            out = num / P.den;
-            // a NaN carrying the marker's bits (never produced by arithmetic)
-            // would read as not yet computed
-            if (is_empty(out)) out = std::numeric_limits<Real>::quiet_NaN();
-            // the level-order store publishes the flux; the cell-order copy
-            // is read only after the kernel
-            *at_pos = out;
-            *at_cell = out;
-            __builtin_nontemporal_store(empty_marker<Real>(), at_next);   // read in the next sweep
         }
         if constexpr (TRACE) {
             t_done = (uint32_t)__builtin_amdgcn_s_memrealtime();
@@ -568,9 +600,33 @@ static const void *sweep_kernel_t(int ns, bool trace) {
 // slots from the arrays and ns_x from the chunk blocks
 static bool use_compact(const Graph &g, bool fp32) { return !fp32 && g.ns_x > 0; }
 
-static const void *sweep_kernel(const Graph &g, bool fp32, bool trace = false) {
+// multigroup FP64 kernels: NG groups per chunk, full program
+template <int NG>
+static const void *sweep_kernel_groups(int ns) {
+    switch (ns) {
+    case 1: return reinterpret_cast<const void *>(&k_sweep<double, 1, 0, false, NG>);
+    case 2: return reinterpret_cast<const void *>(&k_sweep<double, 2, 0, false, NG>);
+    case 3: return reinterpret_cast<const void *>(&k_sweep<double, 3, 0, false, NG>);
+    case 4: return reinterpret_cast<const void *>(&k_sweep<double, 4, 0, false, NG>);
+    case 5: return reinterpret_cast<const void *>(&k_sweep<double, 5, 0, false, NG>);
+    default: return reinterpret_cast<const void *>(&k_sweep<double, 6, 0, false, NG>);
+    }
+}
+
+// groups = 0: the single-group sweep (compact program where the graph has
+// one); groups >= 1: the multigroup sweep over that many groups, which
+// reads the full program
+static const void *sweep_kernel(const Graph &g, bool fp32, bool trace = false, int groups = 0) {
     const int ns = g.ns;
     if (ns < 1 || ns > 6) fail(JSWEEP_E_DEVICE, "sweep program with an unsupported number of inflow slots");
+    if (groups >= 1) {
+        if (fp32 || trace) fail(JSWEEP_E_INVALID_ARG, "multigroup sweeps are FP64 and untraced");
+        if (groups == 1) return sweep_kernel_t<double>(ns, false);
+        if (groups <= 2) return sweep_kernel_groups<2>(ns);
+        if (groups <= 4) return sweep_kernel_groups<4>(ns);
+        if (groups <= kMaxGroups) return sweep_kernel_groups<kMaxGroups>(ns);
+        fail(JSWEEP_E_INVALID_ARG, "too many energy groups");
+    }
     if (use_compact(g, fp32)) {
         static_assert(kCompactSlots == 3, "compact kernels are instantiated for 3 program slots");
         switch (g.ns_x) {
@@ -584,7 +640,7 @@ static const void *sweep_kernel(const Graph &g, bool fp32, bool trace = false) {
 
 constexpr int kMaxSweepBlocksPerCU = 4;
 
-int persistent_waves(Graph &g, bool fp32, const jsweep_params *p, int *waves_per_block) {
+int persistent_waves(Graph &g, bool fp32, const jsweep_params *p, int *waves_per_block, int groups) {
     // default (measured on 0.3M- to 6.6M-chunk graphs): one workgroup of
     // five wavefronts per CU, six for FP32 sweeps above a million chunks
     const int wpb_default = fp32 && g.n_chunks >= (int64_t)1000000 ? 6 : 5;
@@ -596,7 +652,7 @@ int persistent_waves(Graph &g, bool fp32, const jsweep_params *p, int *waves_per
     // time, waiting for the last
     static std::mutex occ_mu;
     static std::map<std::pair<const void *, int>, int> occ_seen;
-    const void *kern = sweep_kernel(g, fp32);
+    const void *kern = sweep_kernel(g, fp32, false, groups);
     int occ = 0;
     {
         std::lock_guard<std::mutex> lock(occ_mu);
@@ -644,14 +700,17 @@ __global__ void k_vs32(const double *vol, const float *src, int64_t nc, float2 *
 
 template <class Real>
 static void launch_persistent(Graph &g, const Real *src_cell, const float *src_dir, Real *psi, Real psi_b,
-                              const jsweep_params *p, hipStream_t s, bool prepared = false) {
+                              const jsweep_params *p, hipStream_t s, bool prepared = false,
+                              const GroupSweep *mg = nullptr) {
     const bool f32 = sizeof(Real) == 4;
-    if (!(f32 ? g.den32_ok : g.den64_ok)) fail(JSWEEP_E_DEVICE, "sweep program denominators not built");
+    const int G = mg ? mg->groups : 1;
+    if (mg && (f32 || !prepared)) fail(JSWEEP_E_DEVICE, "multigroup sweeps are FP64 with a prepared source");
+    if (!mg && !(f32 ? g.den32_ok : g.den64_ok)) fail(JSWEEP_E_DEVICE, "sweep program denominators not built");
     SweepArgs<Real> a;
     a.cblk = g.cblk.as<int32_t>();
     a.nc = g.nc;
     a.stride = 64 * g.n_chunks;
-    const bool compact = use_compact(g, f32);
+    const bool compact = use_compact(g, f32) && !mg;   // multigroup kernels read the full program
     a.pcode = compact ? g.pcode3.as<int32_t>() : g.pcode.as<int32_t>();
     a.pa = reinterpret_cast<const Real *>(compact ? g.pa3.p : f32 ? g.pa32.p : g.pa64.p);
     a.pden = reinterpret_cast<const Real *>(f32 ? g.pden32.p : g.pden64.p);
@@ -669,19 +728,29 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
     a.vs = g.vsc.p;
     a.src_dir = src_dir;
     a.psi = psi;
+    // groups: group g's fluxes, denominators and lagged values follow group
+    // 0's at these strides
+    a.n_groups = G;
+    a.gs_pos = g.nc * g.nd;
+    a.gs_den = a.stride;
+    a.gs_lag = g.n_lag;
+    if (mg) a.pden = reinterpret_cast<const Real *>(mg->den);
     // the two level-position arrays: this sweep's must hold the empty marker
-    // of its precision in every entry (the previous sweep of the same
-    // precision left it so; otherwise it is filled here), and the sweep
-    // empties the other one for the next sweep
-    const int want = (int)sizeof(Real);
+    // of its precision in every entry of its G group blocks (the previous
+    // sweep of the same precision left it so; otherwise it is filled here),
+    // and the sweep empties the other one for the next sweep.  State: element
+    // size | (group blocks holding the marker) << 8.
+    const int want = (int)sizeof(Real) | (G << 8);
+    const size_t need_bytes = (size_t)8 * g.nc * g.nd * G;
     for (int i = 0; i < 2; ++i)
-        if (g.dd_pos[i].bytes < (size_t)(8 * g.nc * g.nd)) {
-            g.dd_pos[i].alloc(8 * g.nc * g.nd);
+        if (g.dd_pos[i].bytes < need_bytes) {
+            g.dd_pos[i].alloc(need_bytes);
             g.dd_state[i] = 0;
         }
     const int cur = g.dd_cur;
-    if (g.dd_state[cur] != want && g.nc * g.nd > 0) {
-        const int64_t n = g.nc * g.nd;
+    const bool covered = (g.dd_state[cur] & 0xff) == (int)sizeof(Real) && (g.dd_state[cur] >> 8) >= G;
+    if (!covered && g.nc * g.nd > 0) {
+        const int64_t n = g.nc * g.nd * G;
         k_fill_empty<Real><<<(int)std::min<int64_t>(ceil_div(n, 256), 8192), 256, 0, s>>>(g.dd_pos[cur].as<Real>(), n);
         JSW_HIP(hipGetLastError());
     }
@@ -691,7 +760,7 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
     g.dd_state[1 - cur] = want;
     g.dd_cur = 1 - cur;
     a.status = g.status.as<int32_t>();
-    a.lag_val = reinterpret_cast<const Real *>(f32 ? g.lag_val32.p : g.lag_val64.p);
+    a.lag_val = reinterpret_cast<const Real *>(mg ? mg->lag_val : f32 ? g.lag_val32.p : g.lag_val64.p);
     a.tickets = reinterpret_cast<uint32_t *>(g.status.as<char>() + 128);
     a.stream_off = g.stream_off.as<int64_t>();
     // defaults (measured): one chunk per ticket for graphs of a few hundred
@@ -711,7 +780,7 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
         a.backoff = b ? (uint32_t)std::min(4, std::max(0, std::atoi(b))) : 3u;
     }
     int wpb = 4;
-    int waves = persistent_waves(g, f32, p, &wpb);
+    int waves = persistent_waves(g, f32, p, &wpb, mg ? G : 0);
     int64_t need = std::max<int64_t>(1, g.n_chunks);
     if (waves > need) waves = (int)((need + wpb - 1) / wpb * wpb);
     int blocks = std::max(waves / wpb, kStreams);
@@ -723,7 +792,9 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
         JSW_HIP(hipEventRecord(ev0, s));
     }
     void *args[] = {&a};
-    JSW_HIP(hipLaunchKernel(sweep_kernel(g, f32, a.stamps != nullptr), dim3(blocks), dim3(64 * wpb), args, 0, s));
+    if (mg) a.stamps = nullptr;
+    JSW_HIP(hipLaunchKernel(sweep_kernel(g, f32, a.stamps != nullptr, mg ? G : 0), dim3(blocks), dim3(64 * wpb), args,
+                            0, s));
     if (g.profile) {
         JSW_HIP(hipEventRecord(ev1, s));
         g.prof_events.push_back({ev0, ev1});
@@ -1101,6 +1172,10 @@ void launch_sweep64(Graph &g, const double *src_cell, double *psi, double psi_b,
     if (g.ctype == JSWEEP_TRI) launch_impl<double, 3, 2>(g, src_cell, nullptr, psi, psi_b, p, s, prepared);
     else if (g.ctype == JSWEEP_TET) launch_impl<double, 4, 3>(g, src_cell, nullptr, psi, psi_b, p, s, prepared);
     else launch_impl<double, 6, 3>(g, src_cell, nullptr, psi, psi_b, p, s, prepared);
+}
+
+void launch_sweep_groups(Graph &g, double *psi, const GroupSweep &mg, const jsweep_params *p, hipStream_t s) {
+    launch_persistent<double>(g, nullptr, nullptr, psi, mg.psi_b, p, s, true, &mg);
 }
 
 void launch_sweep32(Graph &g, const float *src_dir, const float *src_cell, float *psi, const jsweep_params *p,
