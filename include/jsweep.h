@@ -255,6 +255,23 @@ int jsweep_graph_lagged(jsweep_graph g, int32_t *dir, int64_t *up, int64_t *down
 int jsweep_sweep(jsweep_graph g, const double *sigma_t, const double *source, double *psi, double *phi,
                  double psi_boundary, void *hip_stream);
 
+/* jsweep_sweep for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, results and errors as jsweep_sweep, and it calls no
+ * hipMalloc, hipFree or other allocating routine: the per-cell V s of the
+ * sweep is staged in a fixed device array of the library (64 MiB, so at
+ * most 8,388,608 cells; larger graphs are rejected with
+ * JSWEEP_E_INVALID_ARG), which every GPU the library runs on holds until
+ * the process ends, and the graph's own arrays were allocated when it was
+ * built.  The data-driven strategy only (a graph pinned to another strategy
+ * with jsweep_set_params, or being traced, is rejected with
+ * JSWEEP_E_INVALID_ARG); no kernel timing is recorded.  Every call on one
+ * GPU shares that GPU's array: calls that overlap on one GPU (from two
+ * threads or on two streams) race.  The graph must live on the current
+ * device. */
+int jsweep_sweep_noalloc(jsweep_graph g, const double *sigma_t, const double *source, double *psi, double *phi,
+                         double psi_boundary, void *hip_stream);
+
 /* Source iteration to a residual (appendix algorithm: scattering source,
  * sweeps, error reduction).  Each outer step evaluates in FP64
  *   r_{K,m} = q_K + sigma_s,K phi_K - (L psi)_{K,m} / V_K

@@ -48,7 +48,7 @@ EXPORTED = [
     "jsweep_build_graph", "jsweep_graph_info", "jsweep_graph_export", "jsweep_graph_lagged", "jsweep_sweep",
     "jsweep_solve", "jsweep_solve_batch", "jsweep_autotune", "jsweep_profile", "jsweep_profile_read",
     "jsweep_trace", "jsweep_trace_read", "jsweep_graph_destroy", "jsweep_error_string", "jsweep_last_error",
-    "jsweep_set_params", "jsweep_patch_info", "jsweep_program_info", "jsweep_solve_groups",
+    "jsweep_set_params", "jsweep_patch_info", "jsweep_program_info", "jsweep_solve_groups", "jsweep_sweep_noalloc",
 ]
 
 
@@ -107,6 +107,7 @@ def load_library(path: str | None = None):
     lib.jsweep_graph_export.argtypes = [P, i32, P, P, P, P, P, u32]
     lib.jsweep_graph_lagged.argtypes = [P, P, P, P, P]
     lib.jsweep_sweep.argtypes = [P, P, P, P, P, dbl, P]
+    lib.jsweep_sweep_noalloc.argtypes = [P, P, P, P, P, dbl, P]
     lib.jsweep_solve.argtypes = [P, P, P, P, dbl, i32, dbl, i32, P, P, P, P, P]
     lib.jsweep_solve_batch.argtypes = [i32, P, P, i32, dbl, i32, P, P, P]
     lib.jsweep_solve_groups.argtypes = [P, i32, P, P, P, dbl, dbl, i32, P, P, P, P, P]
@@ -124,7 +125,7 @@ def load_library(path: str | None = None):
     lib.jsweep_last_error.argtypes = []
     lib.jsweep_last_error.restype = ctypes.c_char_p
     for name in ("jsweep_build_graph", "jsweep_graph_info", "jsweep_graph_export", "jsweep_graph_lagged",
-                 "jsweep_sweep", "jsweep_solve", "jsweep_solve_groups", "jsweep_solve_batch", "jsweep_autotune", "jsweep_profile",
+                 "jsweep_sweep", "jsweep_sweep_noalloc", "jsweep_solve", "jsweep_solve_groups", "jsweep_solve_batch", "jsweep_autotune", "jsweep_profile",
                  "jsweep_profile_read", "jsweep_trace", "jsweep_trace_read", "jsweep_set_params",
                  "jsweep_patch_info", "jsweep_program_info"):
         getattr(lib, name).restype = ctypes.c_int
@@ -263,6 +264,15 @@ def jsweep_sweep(g: Graph, sigma_t, source, psi, phi=None, psi_boundary: float =
     n = g.n_cells
     _check(lib.jsweep_sweep(g.handle, _f64(sigma_t, n), _f64(source, n), _f64(psi, n * g.n_dirs),
                             _f64(phi, n) if phi is not None else None, float(psi_boundary), _stream(stream)))
+
+
+def jsweep_sweep_noalloc(g: Graph, sigma_t, source, psi, phi=None, psi_boundary: float = 0.0, stream=None):
+    """jsweep_sweep without device allocation (V s staged in the library's
+    fixed device array; at most 8,388,608 cells)."""
+    lib = load_library()
+    n = g.n_cells
+    _check(lib.jsweep_sweep_noalloc(g.handle, _f64(sigma_t, n), _f64(source, n), _f64(psi, n * g.n_dirs),
+                                    _f64(phi, n) if phi is not None else None, float(psi_boundary), _stream(stream)))
 
 
 def jsweep_solve(g: Graph, sigma_t, sigma_s, q, phi, psi=None, psi_boundary: float = 0.0, mode: int = JSWEEP_FP64,
@@ -411,6 +421,7 @@ patch_info = jsweep_patch_info
 graph_export = jsweep_graph_export
 graph_lagged = jsweep_graph_lagged
 sweep = jsweep_sweep
+sweep_noalloc = jsweep_sweep_noalloc
 solve = jsweep_solve
 solve_batch = jsweep_solve_batch
 solve_groups = jsweep_solve_groups

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libjsweep.so")
-SOURCES = ["api.hip", "geometry.hip", "dag.hip", "sweep.hip", "patch.hip", "solve.hip", "groups.hip", "batch.hip"]
+SOURCES = ["api.hip", "geometry.hip", "dag.hip", "sweep.hip", "patch.hip", "solve.hip", "groups.hip", "batch.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("JSWEEP_ARCH", "gfx950")
 

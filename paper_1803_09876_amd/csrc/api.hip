@@ -288,6 +288,15 @@ int jsweep_sweep(jsweep_graph h, const double *sigma_t, const double *source, do
     });
 }
 
+int jsweep_sweep_noalloc(jsweep_graph h, const double *sigma_t, const double *source, double *psi, double *phi,
+                         double psi_boundary, void *hip_stream) {
+    return guarded([&]() -> int {
+        if (!h || !sigma_t || !source || !psi) fail(JSWEEP_E_INVALID_ARG, "NULL argument");
+        if (!std::isfinite(psi_boundary)) fail(JSWEEP_E_INVALID_ARG, "psi_boundary must be finite");
+        return sweep_noalloc(*G(h), sigma_t, source, psi, phi, psi_boundary, reinterpret_cast<hipStream_t>(hip_stream));
+    });
+}
+
 int jsweep_solve(jsweep_graph h, const double *sigma_t, const double *sigma_s, const double *q, double psi_boundary,
                  int32_t mode, double tol, int32_t max_iter, const jsweep_params *params, double *phi, double *psi,
                  jsweep_solve_stats *stats, void *hip_stream) {

@@ -298,6 +298,10 @@ struct GroupSweep {
     double psi_b;
 };
 void launch_sweep_groups(Graph &g, double *psi, const GroupSweep &mg, const jsweep_params *p, hipStream_t s);
+// FP64 data-driven sweep whose per-cell V s goes to vs_buf (8 n_cells bytes,
+// device) instead of a graph buffer: allocates nothing (the graph's flux
+// arrays are allocated when it is built)
+void launch_sweep64_staged(Graph &g, const double *src_cell, double *psi, double psi_b, void *vs_buf, hipStream_t s);
 int check_sweep_status(Graph &g, hipStream_t s);   // JSWEEP_OK, JSWEEP_E_STALLED or JSWEEP_E_PLACEMENT
 int persistent_waves(Graph &g, bool fp32, const jsweep_params *p, int *waves_per_block, int groups = 0);
 int sweep_strategy(const Graph &g, const jsweep_params *p);
@@ -330,6 +334,10 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
           jsweep_solve_stats *stats, hipStream_t s);
 void scalar_flux(Graph &g, const double *psi, double *phi, hipStream_t s);
 void lag_snapshot64(Graph &g, const double *psi, hipStream_t s);
+// jsweep_sweep without device allocation (noalloc.hip)
+int sweep_noalloc(Graph &g, const double *sigma_t, const double *source, double *psi, double *phi, double psi_b,
+                  hipStream_t s);
+int64_t noalloc_max_cells();
 int solve_groups(Graph &g, int G, const double *sigma_t, const double *sigma_s, const double *q, double psi_b,
                  double tol, int32_t max_iter, const jsweep_params *params, double *phi, double *psi,
                  jsweep_solve_stats *stats, hipStream_t s);

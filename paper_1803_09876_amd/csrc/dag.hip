@@ -812,6 +812,12 @@ static void dag_impl(Graph &g, bool lag_cycles, hipStream_t s) {
     build_coarsened<NF, DIM>(g, lag, s);
     build_program<NF, DIM>(g, lag, s);
     build_compact(g, s);
+    // the work-list sweep's two level-position flux arrays (FP64 size) and
+    // the sigma_t cache are allocated here, so that single-group sweeps
+    // allocate nothing
+    for (int i = 0; i < 2; ++i) g.dd_pos[i].alloc(8 * (size_t)std::max<int64_t>(1, N));
+    g.sig_last.alloc(8 * g.nc + 64);
+    g.den64_ok = g.den32_ok = false;
     g.dd_state[0] = g.dd_state[1] = 0;
     g.status.alloc(128 + 32 * 4 * 8);   // status words, then 8 ticket counters 128 B apart
     JSW_HIP(hipMemsetAsync(g.status.p, 0, g.status.bytes, s));

@@ -698,10 +698,13 @@ __global__ void k_vs32(const double *vol, const float *src, int64_t nc, float2 *
     if (K < nc) vs[K] = make_float2((float)vol[K], src ? src[K] : 0.0f);
 }
 
+// vs_buf: where the per-cell V s of this sweep is staged (null: the
+// graph's own buffer, allocated on first use); a caller-provided buffer
+// also keeps the launch free of HIP event creation (no profiling)
 template <class Real>
 static void launch_persistent(Graph &g, const Real *src_cell, const float *src_dir, Real *psi, Real psi_b,
                               const jsweep_params *p, hipStream_t s, bool prepared = false,
-                              const GroupSweep *mg = nullptr) {
+                              const GroupSweep *mg = nullptr, void *vs_buf = nullptr) {
     const bool f32 = sizeof(Real) == 4;
     const int G = mg ? mg->groups : 1;
     if (mg && (f32 || !prepared)) fail(JSWEEP_E_DEVICE, "multigroup sweeps are FP64 with a prepared source");
@@ -714,18 +717,22 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
     a.pcode = compact ? g.pcode3.as<int32_t>() : g.pcode.as<int32_t>();
     a.pa = reinterpret_cast<const Real *>(compact ? g.pa3.p : f32 ? g.pa32.p : g.pa64.p);
     a.pden = reinterpret_cast<const Real *>(f32 ? g.pden32.p : g.pden64.p);
+    void *vs = vs_buf;
+    if (!vs) {
+        if (!prepared && g.vsc.bytes < (size_t)(8 * g.nc)) g.vsc.alloc(8 * g.nc);
+        vs = g.vsc.p;
+    }
     if (!prepared) {
-        if (g.vsc.bytes < (size_t)(8 * g.nc)) g.vsc.alloc(8 * g.nc);
         const int gb = (int)ceil_div(g.nc, 256);
         if (f32)
             k_vs32<<<gb, 256, 0, s>>>(g.vol.as<double>(), reinterpret_cast<const float *>(src_cell), g.nc,
-                                     g.vsc.as<float2>());
+                                     static_cast<float2 *>(vs));
         else
             k_vs64<<<gb, 256, 0, s>>>(g.vol.as<double>(), reinterpret_cast<const double *>(src_cell), g.nc,
-                                     g.vsc.as<double>());
+                                     static_cast<double *>(vs));
         JSW_HIP(hipGetLastError());
     }
-    a.vs = g.vsc.p;
+    a.vs = vs;
     a.src_dir = src_dir;
     a.psi = psi;
     // groups: group g's fluxes, denominators and lagged values follow group
@@ -786,7 +793,8 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
     int blocks = std::max(waves / wpb, kStreams);
     if (!prepared) k_reset_tickets<<<1, 64, 0, s>>>(a.tickets);
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (g.profile) {
+    const bool prof = g.profile && !vs_buf;
+    if (prof) {
         JSW_HIP(hipEventCreate(&ev0));
         JSW_HIP(hipEventCreate(&ev1));
         JSW_HIP(hipEventRecord(ev0, s));
@@ -795,7 +803,7 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
     if (mg) a.stamps = nullptr;
     JSW_HIP(hipLaunchKernel(sweep_kernel(g, f32, a.stamps != nullptr, mg ? G : 0), dim3(blocks), dim3(64 * wpb), args,
                             0, s));
-    if (g.profile) {
+    if (prof) {
         JSW_HIP(hipEventRecord(ev1, s));
         g.prof_events.push_back({ev0, ev1});
     }
@@ -1172,6 +1180,13 @@ void launch_sweep64(Graph &g, const double *src_cell, double *psi, double psi_b,
     if (g.ctype == JSWEEP_TRI) launch_impl<double, 3, 2>(g, src_cell, nullptr, psi, psi_b, p, s, prepared);
     else if (g.ctype == JSWEEP_TET) launch_impl<double, 4, 3>(g, src_cell, nullptr, psi, psi_b, p, s, prepared);
     else launch_impl<double, 6, 3>(g, src_cell, nullptr, psi, psi_b, p, s, prepared);
+}
+
+void launch_sweep64_staged(Graph &g, const double *src_cell, double *psi, double psi_b, void *vs_buf, hipStream_t s) {
+    if (sweep_strategy(g, nullptr) != JSWEEP_STRATEGY_DATA_DRIVEN)
+        fail(JSWEEP_E_INVALID_ARG, "the staged sweep runs the data-driven strategy only");
+    if (g.trace) fail(JSWEEP_E_INVALID_ARG, "the staged sweep does not trace");
+    launch_persistent<double>(g, src_cell, nullptr, psi, psi_b, nullptr, s, false, nullptr, vs_buf);
 }
 
 void launch_sweep_groups(Graph &g, double *psi, const GroupSweep &mg, const jsweep_params *p, hipStream_t s) {

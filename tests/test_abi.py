@@ -29,7 +29,7 @@ def test_header_symbols_exported():
 
 
 def test_error_strings():
-    for code in range(0, -9, -1):
+    for code in range(0, -10, -1):
         assert J.jsweep_error_string(code)
     assert J.jsweep_error_string(-99) == "unknown error"
 
