@@ -41,12 +41,30 @@ N_CELL_SAMPLES = 2048
 N_PSI_SAMPLES = 1024
 TOL_CONVERGED = 1e-13
 
-# workload -> (config number, fixed iteration count, converge?)
+# workload -> (config number, fixed iteration count, converge?); "ens<i>"
+# is instance i of the 256-instance ensemble (seed 4, 500 - 50,000 cells):
+# its smallest and largest triangle and tetrahedron meshes
 PLAN = {
     "hex64_s8": (2, 20, True),
     "tetcheck96_s8": (3, 2, True),
     "tetlogn60_s16": (5, 2, True),
+    "ens49": (None, 20, True),
+    "ens86": (None, 20, True),
+    "ens95": (None, 20, True),
+    "ens216": (None, 20, True),
 }
+
+_ENSEMBLE = None
+
+
+def problem(name):
+    global _ENSEMBLE
+    k = PLAN[name][0]
+    if k is not None:
+        return W.config(k)
+    if _ENSEMBLE is None:
+        _ENSEMBLE = W.ensemble(seed=4, count=256, min_cells=500, max_cells=50000)
+    return _ENSEMBLE[int(name[3:])]
 
 
 def log(msg):
@@ -74,8 +92,8 @@ def samples(p, seed=12345):
 
 
 def run(name, threads):
-    k, n_fixed, converge = PLAN[name]
-    p = W.config(k)
+    _, n_fixed, converge = PLAN[name]
+    p = problem(name)
     t0 = time.time()
     g = oracle.graph_for(p)
     log(f"{name}: oracle graph built in {time.time() - t0:.0f} s ({g.n_lagged} lagged edges)")
