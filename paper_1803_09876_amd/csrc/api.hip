@@ -137,14 +137,6 @@ int jsweep_build_graph(const jsweep_mesh *mesh, const jsweep_quadrature *quad, u
         hipDeviceProp_t prop;
         JSW_HIP(hipGetDeviceProperties(&prop, g->device));
         g->n_cu = prop.multiProcessorCount;
-        {
-            int nx = 0;
-            if (hipDeviceGetAttribute(&nx, hipDeviceAttributeNumberOfXccs, g->device) != hipSuccess || nx < 1)
-                nx = kStreams;   // MI355X in its single-partition mode
-            (void)hipGetLastError();
-            if (kStreams % nx != 0) fail(JSWEEP_E_DEVICE, "XCD count does not divide the stream count");
-            g->n_xcc = nx;
-        }
         g->nd = quad->n_dirs;
         g->omega_h.assign(quad->omega, quad->omega + 3 * g->nd);
         if (M.dim == 2)

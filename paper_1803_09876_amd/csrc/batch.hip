@@ -729,7 +729,14 @@ int autotune(int32_t n, Graph *const *graphs, int32_t mode, jsweep_params *out) 
             }
             JSW_HIP(hipEventRecord(e1, s));
             JSW_HIP(hipEventSynchronize(e1));
-            if (n == 1 && check_sweep_status(*graphs[0], s) != JSWEEP_OK) fail(JSWEEP_E_STALLED, "sweep stalled while tuning");
+            if (n == 1) {
+                const int st = check_sweep_status(*graphs[0], s);
+                if (st != JSWEEP_OK)
+                    fail(st, "sweep failed while tuning (strategy " + std::to_string(c.strategy) + ", " +
+                                 std::to_string(c.waves_per_block) + " waves per workgroup, " +
+                                 std::to_string(c.blocks_per_cu) + " per CU, " + std::to_string(c.chunks_per_ticket) +
+                                 " chunks per ticket, repetition " + std::to_string(rep) + "): " + jsweep_last_error());
+            }
             float t = 0.0f;
             JSW_HIP(hipEventElapsedTime(&t, e0, e1));
             if (rep > 0) ms += t;

@@ -128,16 +128,25 @@ __device__ __forceinline__ int xcc_id() {
 
 // The work-list sweeps hand fluxes from producer to consumer through the L2
 // of one XCD, so every workgroup of a stream (ids congruent mod kStreams)
-// must run on the same XCD.  The dispatcher deals workgroup ids round robin
-// over the n_xcc XCDs of the partition (n_xcc divides kStreams), so
-// workgroup b belongs on XCD b mod n_xcc; a workgroup elsewhere raises
+// must run on the same XCD.  The dispatcher deals workgroups round robin
+// over the XCDs, which keeps ids congruent mod 8 together; which XCD a
+// stream lands on is not fixed (dispatches have been seen with workgroup b
+// on an XCD other than b mod 8), and nothing else needs it.  Each stream
+// has a slot next to its ticket, reset to kNoXcc before every sweep: the
+// first wavefront of the stream records its XCD there, every later one
+// compares.  A wavefront on another XCD takes no work and raises
 // kStatusPlacement (every waiting wavefront sees it and ends) instead of
 // leaving its stream's consumers to the watchdog.  Returns true when the
-// workgroup is where the hand-offs need it.
-__device__ __forceinline__ bool check_stream_placement(int n_xcc, int32_t *status) {
-    if (n_xcc <= 1) return true;
-    if (xcc_id() % n_xcc == (int)(blockIdx.x % (unsigned)n_xcc)) return true;
-    if (threadIdx.x == 0) atomicOr(status, kStatusPlacement);
+// wavefront is where the hand-offs need it.
+constexpr uint32_t kNoXcc = 0xffffffffu;
+constexpr int kXccSlot = 8;              // word of a stream's ticket block holding its XCD
+__device__ __forceinline__ bool check_stream_placement(uint32_t *slot, int32_t *status) {
+    const uint32_t x = (uint32_t)xcc_id();
+    uint32_t prev = kNoXcc;
+    if ((threadIdx.x & 63) == 0) prev = atomicCAS(slot, kNoXcc, x);
+    prev = __builtin_amdgcn_readfirstlane(prev);
+    if (prev == kNoXcc || prev == x) return true;
+    if ((threadIdx.x & 63) == 0) atomicOr(status, kStatusPlacement);
     return false;
 }
 
@@ -189,7 +198,6 @@ struct PatchProg {
 struct Graph {
     int device = 0;
     int n_cu = 0;
-    int n_xcc = 8;                       // XCDs of the device's partition (workgroups dealt round robin)
     int priority = JSWEEP_PRIORITY_BFS;  // order of the work list (JSWEEP_PRIORITY_*)
     int dim = 3, ctype = JSWEEP_TET, nfpc = 4;
     int64_t nv = 0, nc = 0, nf = 0;
@@ -284,6 +292,12 @@ void launch_sweep64(Graph &g, const double *src_cell, double *psi, double psi_b,
                     bool prepared = false);
 void launch_sweep32(Graph &g, const float *src_dir, const float *src_cell, float *psi, const jsweep_params *p,
                     hipStream_t s, bool prepared = false);
+// The data-driven sweep always leaves its fluxes in level-position order
+// (flux of cell K in direction m at m nc + posi[m nc + K]) in one of the
+// graph's two level-position arrays; psi == null to those launchers skips
+// the cell-order copy.  This returns the array the last data-driven sweep
+// filled (double or float by that sweep's precision).
+void *last_sweep_pos(Graph &g);
 // Multigroup FP64 sweep: groups (<= kMaxGroups) energy groups of one graph
 // in one launch of the data-driven kernel.  The caller has prepared
 // g.vsc as V s per (group, cell) [groups * nc] and zeroed the stream

@@ -52,6 +52,58 @@ __device__ inline void dir_sum2(const double *w, const double *x, int64_t nc, in
     }
 }
 
+// dir_sum over the level-ordered fluxes of a sweep: the flux of cell K in
+// direction m sits at m nc + posi[m nc + K].  Sixteen directions' positions
+// are loaded together, then their fluxes; the sum runs in ascending m.
+template <class T>
+__device__ inline double dir_sum_pos(const double *w, const T *pos, const int32_t *posi, int64_t nc, int nd, int64_t K) {
+    double s = 0.0;
+    int m = 0;
+    for (; m + 16 <= nd; m += 16) {
+        int32_t p[16];
+        T v[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) p[k] = posi[(int64_t)(m + k) * nc + K];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = pos[(int64_t)(m + k) * nc + p[k]];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) s = s + w[m + k] * (double)v[k];
+    }
+    for (; m < nd; ++m) s = s + w[m] * (double)pos[(int64_t)m * nc + posi[(int64_t)m * nc + K]];
+    return s;
+}
+
+// dir_sum_pos of the cells K and K + 1 (K and nc even): each direction's two
+// positions are one 8-byte load
+template <class T>
+__device__ inline void dir_sum_pos2(const double *w, const T *pos, const int32_t *posi, int64_t nc, int nd, int64_t K,
+                                    double &s0, double &s1) {
+    s0 = 0.0;
+    s1 = 0.0;
+    int m = 0;
+    for (; m + 16 <= nd; m += 16) {
+        int2 p[16];
+        T v0[16], v1[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) p[k] = *reinterpret_cast<const int2 *>(posi + (int64_t)(m + k) * nc + K);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            v0[k] = pos[(int64_t)(m + k) * nc + p[k].x];
+            v1[k] = pos[(int64_t)(m + k) * nc + p[k].y];
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            s0 = s0 + w[m + k] * (double)v0[k];
+            s1 = s1 + w[m + k] * (double)v1[k];
+        }
+    }
+    for (; m < nd; ++m) {
+        const int2 p = *reinterpret_cast<const int2 *>(posi + (int64_t)m * nc + K);
+        s0 = s0 + w[m] * (double)pos[(int64_t)m * nc + p.x];
+        s1 = s1 + w[m] * (double)pos[(int64_t)m * nc + p.y];
+    }
+}
+
 // One cell of the FP64 residual with the full (un-lagged) streaming
 // operator, looping over directions:
 //   phi_K = sum_m w_m psi_{K,m}

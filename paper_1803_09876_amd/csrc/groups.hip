@@ -66,7 +66,10 @@ __global__ void k_den_groups(const int32_t *blk, int64_t n_chunks, const CellRec
 __global__ void k_group_source(const double *q, const double *sigma_s, const double *phi, const double *vol,
                                int64_t nc, int G, double *vs, uint32_t *tickets) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < kStreams) tickets[32 * t] = 0u;
+    if (t < kStreams) {
+        tickets[32 * t] = 0u;
+        tickets[32 * t + kXccSlot] = kNoXcc;
+    }
     if (t >= nc * G) return;
     const int g = (int)(t / nc);
     const int64_t K = t - (int64_t)g * nc;

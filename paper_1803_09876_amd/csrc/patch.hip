@@ -769,7 +769,6 @@ struct PatchArgs {
     uint64_t watchdog_ticks;
     double psi_b;
     uint32_t *stamps;   // per task: taken, upstream complete, published (s_memrealtime), or null
-    int32_t n_xcc;      // XCDs the workgroups are dealt over
 };
 
 template <class T>
@@ -795,12 +794,12 @@ __global__ void __launch_bounds__(64) k_sweep_patch(PatchArgs a) {
     __shared__ int32_t scell[kPatchCells];
     __shared__ int32_t srnd[kPatchRounds];
     const int lane = threadIdx.x;
-    if (!check_stream_placement(a.n_xcc, a.status)) return;   // takes no task
     const int stream = (int)(blockIdx.x % kStreams);
     const int64_t first = a.stream_off[stream];
     const int64_t per_stream = a.stream_off[stream + 1] - first;
     const uint32_t epoch = a.epoch & 0xffu;
     uint32_t *qctl = a.qctl + 32 * stream;
+    if (!check_stream_placement(qctl + kXccSlot, a.status)) return;   // takes no task
     while (true) {
         uint32_t hv = 0;
         if (lane == 0) hv = atomicAdd(qctl, 1u);
@@ -950,6 +949,7 @@ __global__ void k_pp_reset(const int32_t *desc, int64_t n_tasks, const int64_t *
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < kStreams) {
         qctl[32 * t] = 0u;
+        qctl[32 * t + kXccSlot] = kNoXcc;
         qctl[32 * t + 16] = (uint32_t)nsrc[t];
     }
     if (t >= n_tasks) return;
@@ -1035,7 +1035,6 @@ void launch_patch64(Graph &g, const double *src_cell, double *psi, double psi_b,
     a.qctl = pp.qctl.as<uint32_t>();
     a.down = pp.down.as<int32_t>();
     a.status = g.status.as<int32_t>();
-    a.n_xcc = g.n_xcc;
     a.stream_off = pp.stream_off.as<int64_t>();
     pp.epoch = pp.epoch % 255 + 1;
     a.epoch = (uint32_t)pp.epoch;

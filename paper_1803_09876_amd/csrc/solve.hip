@@ -219,8 +219,9 @@ struct LagCells {
 // Lagged in-edges of cell v: the un-lagged residual's extra term
 // w_m V ((d + l)^2 - d^2) per direction m, l = sum a (psi_now - psi_prev) / V;
 // the lagged values are replaced by the new iterate's for the next sweep
-__device__ inline double lag_terms(const LagCells &L, const double *psi, const double *w, int64_t nc, int64_t v,
-                                   double V, double d) {
+// (psi in cell order, or in level-position order when posi is given)
+__device__ inline double lag_terms(const LagCells &L, const double *psi, const int32_t *posi, const double *w,
+                                   int64_t nc, int64_t v, double V, double d) {
     double c = 0.0;
     for (int32_t gi = L.cptr[v]; gi < L.cptr[v + 1]; ++gi) {
         const int64_t e = L.cgrp[gi];
@@ -228,7 +229,8 @@ __device__ inline double lag_terms(const LagCells &L, const double *psi, const d
         const int64_t m = (int64_t)(key >> 32);
         double l = 0.0;
         for (int64_t f = e; f < L.n && L.mv[f] == key; ++f) {
-            const double now = psi[m * nc + L.u[f]];
+            const int64_t u = L.u[f];
+            const double now = psi[m * nc + (posi ? (int64_t)posi[m * nc + u] : u)];
             l = l + L.a[f] * (now - L.val[f]) / V;
             L.val[f] = now;
         }
@@ -243,7 +245,10 @@ __device__ inline void next_sweep_setup(int64_t t, const int32_t *status, double
                                         uint32_t *tickets) {
     if (t == 0) acc[2] = (double)status[0];
     if (acc_next && t < 3) acc_next[t] = 0.0;
-    if (t < kStreams) tickets[32 * t] = 0u;
+    if (t < kStreams) {
+        tickets[32 * t] = 0u;
+        tickets[32 * t + kXccSlot] = kNoXcc;
+    }
 }
 
 // Residual of a plain FP64 source iteration without re-applying the
@@ -252,26 +257,29 @@ __device__ inline void next_sweep_setup(int64_t t, const int32_t *status, double
 // un-lagged residual of psi' is exactly
 //   r = sigma_s (phi' - phi) + sum over lagged in-faces a (psi'_u - psi_u) / V.
 // k_phi_delta: phi' (ascending m), the isotropic part d = sigma_s (phi' -
-// phi) and its norm W V d^2 (W = sum of the weights), and V q^2.
+// phi) and its norm W V d^2 (W = sum of the weights), and V q^2.  psi is
+// the sweep's output in cell order, or (posi given) the level-ordered
+// array the data-driven sweep filled, read through the level positions.
 // The lagged in-faces of the cell add their terms (lag_terms), so that one
 // kernel gives the whole residual norm.  It also prepares the next sweep:
 // its source q + sigma_s phi', the product V s the sweep kernels read, the
 // lagged values, zeroed next norms (acc_next, unless null) and tickets.
-__global__ void k_phi_delta(const double *psi, const double *w, double wsum, const double *q, const double *sigma_s,
-                            const double *vol, int64_t nc, int nd, double *phi, double *acc, double *src_next,
-                            double *vs_next, LagCells L, const int32_t *status, double *acc_next, uint32_t *tickets) {
+__global__ void k_phi_delta(const double *psi, const int32_t *posi, const double *w, double wsum, const double *q,
+                            const double *sigma_s, const double *vol, int64_t nc, int nd, double *phi, double *acc,
+                            double *src_next, double *vs_next, LagCells L, const int32_t *status, double *acc_next,
+                            uint32_t *tickets) {
     const int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     next_sweep_setup(K, status, acc, acc_next, tickets);
     double a = 0.0, b = 0.0;
     if (K < nc) {
-        const double s = dir_sum(w, psi, nc, nd, K);
+        const double s = posi ? dir_sum_pos(w, psi, posi, nc, nd, K) : dir_sum(w, psi, nc, nd, K);
         const double d = sigma_s[K] * (s - phi[K]);
         phi[K] = s;
         const double sn = q[K] + sigma_s[K] * s;
         src_next[K] = sn;
         vs_next[K] = vol[K] * sn;
         a = wsum * (vol[K] * (d * d));
-        if (L.n > 0) a = a + lag_terms(L, psi, w, nc, K, vol[K], d);
+        if (L.n > 0) a = a + lag_terms(L, psi, posi, w, nc, K, vol[K], d);
         b = vol[K] * (q[K] * q[K]);
     }
     block_add(a, acc);
@@ -281,9 +289,9 @@ __global__ void k_phi_delta(const double *psi, const double *w, double wsum, con
 // k_phi_delta for two consecutive cells per thread (n_cells even), so that
 // every direction's fluxes are read in 16-byte pieces; the same
 // arithmetic per cell
-__global__ void k_phi_delta2(const double *psi, const double *w, double wsum, const double *q, const double *sigma_s,
-                             const double *vol, int64_t nc, int nd, double *phi, double *acc, double *src_next,
-                             double *vs_next, LagCells L, const int32_t *status, double *acc_next,
+__global__ void k_phi_delta2(const double *psi, const int32_t *posi, const double *w, double wsum, const double *q,
+                             const double *sigma_s, const double *vol, int64_t nc, int nd, double *phi, double *acc,
+                             double *src_next, double *vs_next, LagCells L, const int32_t *status, double *acc_next,
                              uint32_t *tickets) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     next_sweep_setup(t, status, acc, acc_next, tickets);
@@ -291,7 +299,8 @@ __global__ void k_phi_delta2(const double *psi, const double *w, double wsum, co
     double a = 0.0, b = 0.0;
     if (K < nc) {
         double s[2];
-        dir_sum2(w, psi, nc, nd, K, s[0], s[1]);
+        if (posi) dir_sum_pos2(w, psi, posi, nc, nd, K, s[0], s[1]);
+        else dir_sum2(w, psi, nc, nd, K, s[0], s[1]);
         const double2 ph = *reinterpret_cast<const double2 *>(phi + K);
         const double2 ss = *reinterpret_cast<const double2 *>(sigma_s + K);
         const double2 qq = *reinterpret_cast<const double2 *>(q + K);
@@ -302,7 +311,7 @@ __global__ void k_phi_delta2(const double *psi, const double *w, double wsum, co
             d[i] = sig[i] * (s[i] - old[i]);
             sn[i] = qk[i] + sig[i] * s[i];
             a = a + wsum * (vk[i] * (d[i] * d[i]));
-            if (L.n > 0) a = a + lag_terms(L, psi, w, nc, K + i, vk[i], d[i]);
+            if (L.n > 0) a = a + lag_terms(L, psi, posi, w, nc, K + i, vk[i], d[i]);
             b = b + vk[i] * (qk[i] * qk[i]);
         }
         *reinterpret_cast<double2 *>(phi + K) = make_double2(s[0], s[1]);
@@ -332,22 +341,33 @@ __global__ void k_qnorm(const double *q, const double *vol, int64_t nc, double *
 // thread (1, or 4 when n_cells is a multiple of 4 and dpsi 16-byte
 // aligned: every direction's fluxes are then read in 16-byte pieces); each
 // cell's sum over directions in ascending m either way.
-template <int CPT>
-__global__ void k_dphi(const float *dpsi, const double *w, const double *sigma_s, const double *vol, int64_t nc, int nd,
-                       const double *q, double *dphi, float *g32, const int32_t *status, double *acc,
-                       double *acc_next, float2 *vs, uint32_t *tickets, const uint64_t *lag_mv,
-                       const int32_t *lag_u, int64_t n_lag, float *lag_val) {
+// With posi (POS), dpsi is the level-ordered array the data-driven sweep
+// filled and is read through the level positions (CPT 1 or 2).
+template <int CPT, bool POS = false>
+__global__ void k_dphi(const float *dpsi, const int32_t *posi, const double *w, const double *sigma_s,
+                       const double *vol, int64_t nc, int nd, const double *q, double *dphi, float *g32,
+                       const int32_t *status, double *acc, double *acc_next, float2 *vs, uint32_t *tickets,
+                       const uint64_t *lag_mv, const int32_t *lag_u, int64_t n_lag, float *lag_val) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t == 0) acc[2] = (double)status[0];
     if (t < 2) acc_next[t] = 0.0;
-    if (t < kStreams) tickets[32 * t] = 0u;
-    for (int64_t e = t; e < n_lag; e += (int64_t)gridDim.x * blockDim.x)
-        lag_val[e] = dpsi[(int64_t)(lag_mv[e] >> 32) * nc + lag_u[e]];
+    if (t < kStreams) {
+        tickets[32 * t] = 0u;
+        tickets[32 * t + kXccSlot] = kNoXcc;
+    }
+    for (int64_t e = t; e < n_lag; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t m = (int64_t)(lag_mv[e] >> 32), u = lag_u[e];
+        lag_val[e] = dpsi[m * nc + (POS ? (int64_t)posi[m * nc + u] : u)];
+    }
     double a = 0.0, b = 0.0;
     const int64_t K0 = t * CPT;
     if (K0 < nc) {
         double sum[CPT];
-        if constexpr (CPT == 1) {
+        if constexpr (POS) {
+            static_assert(CPT <= 2, "level-position gathers take one or two cells per thread");
+            if constexpr (CPT == 1) sum[0] = dir_sum_pos(w, dpsi, posi, nc, nd, K0);
+            else dir_sum_pos2(w, dpsi, posi, nc, nd, K0, sum[0], sum[1]);
+        } else if constexpr (CPT == 1) {
             sum[0] = dir_sum(w, dpsi, nc, nd, K0);
         } else {
 #pragma unroll
@@ -393,10 +413,18 @@ __global__ void k_dphi(const float *dpsi, const double *w, const double *sigma_s
     block_add(b, acc + 1);
 }
 
-// psi += dpsi (FP64)
-__global__ void k_update(double *psi, const float *dpsi, int64_t n) {
+// psi += dpsi (FP64); with posi, dpsi is in level-position order
+__global__ void k_update(double *psi, const float *dpsi, const int32_t *posi, int64_t nc, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) psi[i] = psi[i] + (double)dpsi[i];
+    if (i >= n) return;
+    const int64_t j = posi ? (i / nc) * nc + posi[i] : i;
+    psi[i] = psi[i] + (double)dpsi[j];
+}
+
+// cell-order copy of level-ordered fluxes: psi[m nc + K] = pos[m nc + posi[m nc + K]]
+__global__ void k_cell_order(const double *pos, const int32_t *posi, int64_t nc, int64_t n, double *psi) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) psi[i] = pos[(i / nc) * nc + posi[i]];
 }
 
 // r in level-position order from its cell-order copy:
@@ -456,15 +484,27 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
     const bool refined = (mode & 0xff) == JSWEEP_FP32_REFINED;
     const bool warm = (mode & JSWEEP_WARM_START) != 0;
     const int64_t N = g.nc * g.nd;
+    const bool zero_start = !warm || !psi_out;
+    // With the data-driven kernel the sweeps keep their fluxes in level
+    // order only (the graph's level-position arrays): the flux passes read
+    // them through the level positions, and the caller's psi (cell order)
+    // is written once at the end, so no sweep scatters a cell-order copy.
+    // The FP64 source iteration then needs no cell-order psi at all until
+    // that final copy; the FP32 refinement keeps psi (FP64, cell order) for
+    // its residual and adds each correction to it through the positions.
+    const bool lo = sweep_strategy(g, params) == JSWEEP_STRATEGY_DATA_DRIVEN;
+    const bool need_psi = !lo || refined || (warm && psi_out);
     // scratch: psi (if the caller gives none), source / dphi, accumulators
-    double *psi = psi_out;
-    if (!psi) { ensure(g.scratch_a, 8 * N); psi = g.scratch_a.as<double>(); }
+    double *psi = nullptr;
+    if (need_psi) {
+        psi = psi_out;
+        if (!psi) { ensure(g.scratch_a, 8 * N); psi = g.scratch_a.as<double>(); }
+    }
     ensure(g.scratch_b, 8 * g.nc + 128);
     double *src = g.scratch_b.as<double>();
     double *acc = src + g.nc + 2;   // 16-byte aligned tail, 8 doubles
     if (((uintptr_t)acc & 15) != 0) acc += 1;
-    const bool zero_start = !warm || !psi_out;
-    if (zero_start) JSW_HIP(hipMemsetAsync(psi, 0, 8 * N, s));
+    if (zero_start && need_psi) JSW_HIP(hipMemsetAsync(psi, 0, 8 * N, s));
     refresh_sigma(g, sigma_t, refined, s);
     int outer = 0, sweeps = 0, hist = 0, rc = JSWEEP_OK;
     double rho = INFINITY;
@@ -474,7 +514,8 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
     };
     if (!refined) {
         // phi of the initial iterate
-        scalar_flux(g, psi, phi, s);
+        if (zero_start && !need_psi) JSW_HIP(hipMemsetAsync(phi, 0, 8 * g.nc, s));
+        else scalar_flux(g, psi, phi, s);
         double wsum = 0.0;
         for (double x : g.weight_h) wsum += x;
         const LagCells lagc{g.lag_cptr.as<int32_t>(), g.lag_cgrp.as<int32_t>(), g.lag_mv.as<uint64_t>(),
@@ -493,8 +534,9 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
         // the flux pass takes two cells per thread when every array it
         // touches allows 16-byte accesses
         auto al16 = [](const void *p) { return ((uintptr_t)p & 15) == 0; };
-        const bool pairs = g.nc % 2 == 0 && al16(psi) && al16(phi) && al16(q) && al16(sigma_s) && al16(src) &&
+        const bool pairs = g.nc % 2 == 0 && (lo || al16(psi)) && al16(phi) && al16(q) && al16(sigma_s) && al16(src) &&
                            al16(g.vol.p) && al16(g.vsc.p);
+        const int32_t *posi = lo ? g.posi.as<int32_t>() : nullptr;
         while (true) {
             if (sweeps >= max_iter) { rc = JSWEEP_E_NOT_CONVERGED; break; }
             double *it_acc = norms.as<double>() + 4 * (fixed ? sweeps : (sweeps & 1));
@@ -502,21 +544,23 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
             if (!prepared) {
                 k_source<<<(int)ceil_div(g.nc, kB), kB, 0, s>>>(q, sigma_s, phi, g.nc, src);
                 JSW_HIP(hipGetLastError());
-                lag_snapshot<double>(g, psi, s);
+                if (psi) lag_snapshot<double>(g, psi, s);
+                else if (g.n_lag) JSW_HIP(hipMemsetAsync(g.lag_val64.p, 0, 8 * g.n_lag, s));
             }
-            launch_sweep64(g, src, psi, psi_b, params, s, prepared);
+            launch_sweep64(g, src, lo ? nullptr : psi, psi_b, params, s, prepared);
             ++sweeps;
             // residual of the new iterate from the identity above (one
-            // pass over psi for phi; the lagged edges by their downwind
-            // cells), and the set-up of the next sweep
+            // pass over the fluxes for phi; the lagged edges by their
+            // downwind cells), and the set-up of the next sweep
+            const double *flux = lo ? static_cast<const double *>(last_sweep_pos(g)) : psi;
             if (pairs)
                 k_phi_delta2<<<(int)ceil_div(g.nc / 2, kB), kB, 0, s>>>(
-                    psi, g.weight.as<double>(), wsum, q, sigma_s, g.vol.as<double>(), g.nc, g.nd, phi, it_acc, src,
-                    g.vsc.as<double>(), lagc, g.status.as<int32_t>(), next_acc, tickets);
+                    flux, posi, g.weight.as<double>(), wsum, q, sigma_s, g.vol.as<double>(), g.nc, g.nd, phi, it_acc,
+                    src, g.vsc.as<double>(), lagc, g.status.as<int32_t>(), next_acc, tickets);
             else
                 k_phi_delta<<<(int)ceil_div(g.nc, kB), kB, 0, s>>>(
-                    psi, g.weight.as<double>(), wsum, q, sigma_s, g.vol.as<double>(), g.nc, g.nd, phi, it_acc, src,
-                    g.vsc.as<double>(), lagc, g.status.as<int32_t>(), next_acc, tickets);
+                    flux, posi, g.weight.as<double>(), wsum, q, sigma_s, g.vol.as<double>(), g.nc, g.nd, phi, it_acc,
+                    src, g.vsc.as<double>(), lagc, g.status.as<int32_t>(), next_acc, tickets);
             JSW_HIP(hipGetLastError());
             prepared = true;
             if (fixed) continue;
@@ -540,6 +584,12 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
                 ++outer;
                 record(rho);
             }
+        }
+        // the caller's psi in cell order, once
+        if (lo && psi_out && sweeps > 0) {
+            k_cell_order<<<(unsigned)ceil_div(N, kB), kB, 0, s>>>(static_cast<const double *>(last_sweep_pos(g)),
+                                                                 g.posi.as<int32_t>(), g.nc, N, psi_out);
+            JSW_HIP(hipGetLastError());
         }
     } else {
         ensure(g.scratch_c, 4 * N * 2 + 64);            // r32 and dpsi32
@@ -574,8 +624,8 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
             record(rho);
             if (tol > 0.0 && rho <= tol) break;
             if (sweeps >= max_iter) { rc = JSWEEP_E_NOT_CONVERGED; break; }
-            // inner source iteration on the correction in FP32
-            JSW_HIP(hipMemsetAsync(dpsi, 0, 4 * N, s));
+            // inner source iteration on the correction in FP32 (from zero)
+            if (!lo) JSW_HIP(hipMemsetAsync(dpsi, 0, 4 * N, s));
             JSW_HIP(hipMemsetAsync(dphi, 0, 8 * g.nc, s));
             if (from_zero) {
                 k_narrow<<<(int)ceil_div(g.nc, kB), kB, 0, s>>>(q, g.nc, g32);
@@ -592,24 +642,33 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
             // The outer loop then measures the true residual.
             const double target = std::max(0.5 * tol, kFp32Floor * rho);
             double prev_pred = INFINITY;
+            int inner = 0;
             // the first inner sweep is set up here; each later one by the
             // k_dphi of the sweep before it (two accumulator sets alternate)
             if (g.vsc.bytes < (size_t)(8 * g.nc)) g.vsc.alloc(8 * g.nc);
             uint32_t *tickets = reinterpret_cast<uint32_t *>(g.status.as<char>() + 128);
             const bool quads = g.nc % 4 == 0 && ((uintptr_t)dpsi & 15) == 0;
+            const int32_t *posi = lo ? g.posi.as<int32_t>() : nullptr;
             for (int j = 0; j < J && sweeps < max_iter; ++j) {
                 double *a_cur = acc + 2 + 3 * (j & 1), *a_next = acc + 2 + 3 * ((j + 1) & 1);
                 if (j == 0) {
-                    lag_snapshot<float>(g, dpsi, s);
+                    if (lo) {
+                        if (g.n_lag) JSW_HIP(hipMemsetAsync(g.lag_val32.p, 0, 4 * g.n_lag, s));
+                    } else {
+                        lag_snapshot<float>(g, dpsi, s);
+                    }
                     JSW_HIP(hipMemsetAsync(a_cur, 0, 16, s));
                 }
-                launch_sweep32(g, from_zero ? nullptr : r32, g32, dpsi, params, s, j > 0);
+                launch_sweep32(g, from_zero ? nullptr : r32, g32, lo ? nullptr : dpsi, params, s, j > 0);
                 ++sweeps;
-                auto dphi_kernel = quads ? k_dphi<4> : k_dphi<1>;
-                dphi_kernel<<<(int)ceil_div(g.nc, kB * (quads ? 4 : 1)), kB, 0, s>>>(
-                    dpsi, g.weight.as<double>(), sigma_s, g.vol.as<double>(), g.nc, g.nd, from_zero ? q : nullptr,
-                    dphi, g32, g.status.as<int32_t>(), a_cur, a_next, g.vsc.as<float2>(), tickets,
-                    g.lag_mv.as<uint64_t>(), g.lag_u.as<int32_t>(), g.n_lag, g.lag_val32.as<float>());
+                ++inner;
+                const float *dflux = lo ? static_cast<const float *>(last_sweep_pos(g)) : dpsi;
+                const int cpt = lo ? (g.nc % 2 == 0 ? 2 : 1) : (quads ? 4 : 1);
+                auto dphi_kernel = lo ? (cpt == 2 ? k_dphi<2, true> : k_dphi<1, true>) : (quads ? k_dphi<4> : k_dphi<1>);
+                dphi_kernel<<<(int)ceil_div(g.nc, kB * cpt), kB, 0, s>>>(
+                    dflux, posi, g.weight.as<double>(), sigma_s, g.vol.as<double>(), g.nc, g.nd,
+                    from_zero ? q : nullptr, dphi, g32, g.status.as<int32_t>(), a_cur, a_next, g.vsc.as<float2>(),
+                    tickets, g.lag_mv.as<uint64_t>(), g.lag_u.as<int32_t>(), g.n_lag, g.lag_val32.as<float>());
                 JSW_HIP(hipGetLastError());
                 double h[3];   // norm of dphi, correction residual, sweep status
                 JSW_HIP(hipMemcpyAsync(h, a_cur, 24, hipMemcpyDeviceToHost, s));
@@ -622,7 +681,11 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
                 if (j > 0 && pred > 0.9 * prev_pred && pred < 100.0 * kFp32Floor * rho) break;
                 prev_pred = pred;
             }
-            k_update<<<(int)ceil_div(N, kB), kB, 0, s>>>(psi, dpsi, N);
+            if (lo) {
+                if (inner > 0)
+                    k_update<<<(int)ceil_div(N, kB), kB, 0, s>>>(psi, static_cast<const float *>(last_sweep_pos(g)),
+                                                                 g.posi.as<int32_t>(), g.nc, N);
+            } else k_update<<<(int)ceil_div(N, kB), kB, 0, s>>>(psi, dpsi, nullptr, g.nc, N);
             JSW_HIP(hipGetLastError());
         }
     }

@@ -95,7 +95,6 @@ struct SweepArgs {
     uint32_t backoff;                        // the pause doubles every 8 polls, at most this many times
     uint64_t watchdog_ticks;
     uint32_t *stamps;                        // tracing: [3 * n_chunks] or null
-    int32_t n_xcc;                           // XCDs the workgroups are dealt over
     // energy groups swept together (multigroup kernels, NG > 1): group g's
     // arrays follow group 0's at these strides
     int32_t n_groups;
@@ -197,10 +196,10 @@ __global__ void k_sweep(SweepArgs<Real> a) {
     constexpr int NX = NSX > 0 ? NSX : 1;
     static_assert(NG == 1 || (NSX == 0 && sizeof(Real) == 8), "multigroup sweeps read the full FP64 program");
     const int lane = threadIdx.x & 63;
-    // a workgroup off its stream's XCD takes no chunk (it holds nothing
-    // anyone waits for) and raises the placement flag
-    if (!check_stream_placement(a.n_xcc, a.status)) return;
     const int stream = (int)(blockIdx.x % kStreams);
+    // a wavefront off its stream's XCD takes no chunk (it holds nothing
+    // anyone waits for) and raises the placement flag
+    if (!check_stream_placement(a.tickets + 32 * stream + kXccSlot, a.status)) return;
     const int64_t first = a.stream_off[stream];
     const int64_t per_stream = a.stream_off[stream + 1] - first;
     const int ng = NG == 1 ? 1 : a.n_groups;
@@ -378,7 +377,7 @@ __global__ void k_sweep(SweepArgs<Real> a) {
         t_ready = (uint32_t)__builtin_amdgcn_s_memrealtime();
         if (request) pend = (int64_t)__builtin_amdgcn_readfirstlane(nxt);
         at_pos = a.psi_pos + own;
-        at_cell = a.psi + base + K;
+        at_cell = a.psi ? a.psi + base + K : nullptr;
         at_next = a.pos_next + own;
         if (active) {
 #pragma unroll
@@ -408,9 +407,10 @@ __global__ void k_sweep(SweepArgs<Real> a) {
                 // arithmetic) would read as not yet computed
                 if (is_empty(o)) o = std::numeric_limits<Real>::quiet_NaN();
                 // the level-order store publishes the flux; the cell-order
-                // copy is read only after the kernel
+                // copy (when the caller wants one) is read only after the
+                // kernel
                 at_pos[g * a.gs_pos] = o;
-                at_cell[g * a.gs_pos] = o;
+                if (a.psi) at_cell[g * a.gs_pos] = o;
                 __builtin_nontemporal_store(empty_marker<Real>(), at_next + g * a.gs_pos);   // read in the next sweep
                 if (g == 0) out = o;
             }
@@ -568,7 +568,10 @@ __global__ void __launch_bounds__(1024) k_sweep_batch(const BatchInst<Real> *ins
 
 // ticket counters back to zero before a sweep
 __global__ void k_reset_tickets(uint32_t *t) {
-    if (threadIdx.x < kStreams) t[32 * threadIdx.x] = 0u;
+    if (threadIdx.x < kStreams) {
+        t[32 * threadIdx.x] = 0u;
+        t[32 * threadIdx.x + kXccSlot] = kNoXcc;
+    }
 }
 
 static uint64_t watchdog_ticks() {
@@ -778,7 +781,6 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
     a.psi_b = psi_b;
     a.watchdog_ticks = watchdog_ticks();
     a.stamps = g.trace ? g.trace_buf.as<uint32_t>() : nullptr;
-    a.n_xcc = g.n_xcc;
     if (g.trace) g.trace_units = 0;
     {
         const char *e = std::getenv("JSWEEP_POLL_NAP");
@@ -1182,6 +1184,8 @@ void launch_sweep64(Graph &g, const double *src_cell, double *psi, double psi_b,
     else launch_impl<double, 6, 3>(g, src_cell, nullptr, psi, psi_b, p, s, prepared);
 }
 
+void *last_sweep_pos(Graph &g) { return g.dd_pos[1 - g.dd_cur].p; }
+
 void launch_sweep64_staged(Graph &g, const double *src_cell, double *psi, double psi_b, void *vs_buf, hipStream_t s) {
     if (sweep_strategy(g, nullptr) != JSWEEP_STRATEGY_DATA_DRIVEN)
         fail(JSWEEP_E_INVALID_ARG, "the staged sweep runs the data-driven strategy only");
@@ -1206,8 +1210,8 @@ int check_sweep_status(Graph &g, hipStream_t s) {
     JSW_HIP(hipStreamSynchronize(s));
     if (st == 0) return JSWEEP_OK;
     const int rc = (st & kStatusPlacement) ? JSWEEP_E_PLACEMENT : JSWEEP_E_STALLED;
-    if (rc == JSWEEP_E_PLACEMENT)
-        set_last_error("a sweep workgroup ran on another XCD than the workgroups of its stream");
+    set_last_error(rc == JSWEEP_E_PLACEMENT ? "a sweep workgroup ran on another XCD than the workgroups of its stream"
+                                            : "a sweep wavefront's watchdog fired (status word " + std::to_string(st) + ")");
     // a stalled sweep leaves the level-position arrays and the task slots
     // in an unknown state: start over
     g.dd_state[0] = g.dd_state[1] = 0;

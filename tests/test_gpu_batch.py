@@ -104,3 +104,65 @@ def test_residual_history(ensemble):
     _, _, hist = og.source_iteration(p.sigma_t, p.sigma_s, p.q, p.weight, 8)
     assert len(r["history"]) == 8
     assert np.allclose(r["history"], hist, rtol=1e-9, atol=1e-300)
+
+
+ENSEMBLE_GOLDEN = (49, 86, 95, 216)   # smallest / largest tetrahedron and triangle meshes of the ensemble
+
+
+def test_full_ensemble_256():
+    """The whole 256-instance ensemble (500 - 50,000 cells, S4 - S8) in one
+    batch: 20 FP64 source iterations against the oracle's sampled fluxes of
+    its smallest and largest triangle and tetrahedron instances
+    (tests/golden/fullsize_ens<i>.txt, oracle-only), then FP32-refined and
+    FP64 batch solves to rho <= 1e-11, with the autotuned parameters and
+    with the plain direction kernel, against the oracle's converged fluxes
+    of those instances and against each other for every instance."""
+    need_gpu()
+    import os
+    import sys
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+    from make_fullsize_golden import load
+    ps = W.ensemble(seed=4, count=256, min_cells=500, max_cells=50000)
+    print(f"[ensemble] {len(ps)} instances, {sum(p.n_cells for p in ps)} cells", flush=True)
+    gs = [gpu_graph(p) for p in ps]
+    try:
+        tuned = J.autotune(gs, J.JSWEEP_FP32_REFINED)
+        print(f"[ensemble] autotuned {tuned.as_dict()}", flush=True)
+
+        def problems():
+            return [{"sigma_t": dev(p.sigma_t), "sigma_s": dev(p.sigma_s), "q": dev(p.q),
+                     "phi": dev(np.zeros(p.n_cells)), "psi": dev(np.zeros((p.n_dirs, p.n_cells)))} for p in ps]
+
+        pr = problems()
+        J.solve_batch(gs, pr, mode=J.JSWEEP_FP64, tol=0.0, max_iter=20, params=tuned, allow_not_converged=True)
+        gold = {i: load(f"ens{i}") for i in ENSEMBLE_GOLDEN}
+        for i, gd in gold.items():
+            ph = host(pr[i]["phi"])
+            psi = host(pr[i]["psi"])
+            e1 = rel_max(ph[gd["cells"]], gd["phi_fixed"])
+            e2 = rel_max(psi[gd["psi_m"], gd["psi_k"]], gd["psi"])
+            print(f"[ensemble] instance {i} ({ps[i].n_cells} cells, {ps[i].n_dirs} dirs) 20 SI: phi {e1:.2e} "
+                  f"psi {e2:.2e}", flush=True)
+            assert e1 <= 1e-12 and e2 <= 1e-12, i
+        sols = {}
+        for label, mode, prm in (("fp64", J.JSWEEP_FP64, tuned), ("refined", J.JSWEEP_FP32_REFINED, tuned),
+                                 ("refined_plain", J.JSWEEP_FP32_REFINED,
+                                  J.Params(strategy=J.JSWEEP_STRATEGY_DIRECTION))):
+            pr = problems()
+            st = J.solve_batch(gs, pr, mode=mode, tol=1e-11, max_iter=20000, params=prm)
+            sols[label] = [host(x["phi"]) for x in pr]
+            assert max(x["residual"] for x in st) <= 1e-11, label
+            for i, gd in gold.items():
+                ref = gd["phi_converged"]
+                got = sols[label][i][gd["cells"]]
+                err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+                print(f"[ensemble] {label} instance {i}: sweeps {st[i]['sweeps']} rho {st[i]['residual']:.2e} "
+                      f"phi vs oracle {err:.2e}", flush=True)
+                assert err <= 1e-8, (label, i)
+        for label in ("refined", "refined_plain"):
+            worst = max(float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(sols[label], sols["fp64"]))
+            print(f"[ensemble] {label} vs fp64: worst instance phi rel {worst:.2e}", flush=True)
+            assert worst <= 1e-8
+    finally:
+        for g in gs:
+            g.close()

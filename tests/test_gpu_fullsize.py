@@ -8,14 +8,89 @@
 * Kuhn tetrahedra of a 96^3 lattice, S8 (5.3M cells x 80 directions) and
   of a 60^3 lattice, S16 (1.3M cells x 288 directions): the oracle is built
   for four sampled directions only (directions are independent), and the
-  GPU graph arrays and FP64 sweep of those directions are compared."""
+  GPU graph arrays and FP64 sweep of those directions are compared;
+* against the sampled oracle fluxes of tests/golden/fullsize_<name>.txt
+  (written by the oracle-only script there): 20 FP64 source iterations of
+  the hexahedral workload and 2 of each tetrahedral one over every
+  direction (scalar flux at 2,048 cells, angular flux at 1,024 (direction,
+  cell) pairs, within 1e-12), and the FP64 and FP32-refined solves to
+  rho <= 1e-11 against the oracle's solution at rho <= 1e-13 (within 1e-8)
+  and against each other."""
+import os
+import sys
+
 import numpy as np
 import pytest
 
 import workloads as W
-from tests.gpu_common import J, dev, gpu_graph, need_gpu, rel_max, torch
+from tests.gpu_common import J, dev, gpu_graph, host, need_gpu, rel_max, torch
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden(name):
+    sys.path.insert(0, GOLDEN)
+    from make_fullsize_golden import load
+    return load(name)
+
+
+@pytest.mark.parametrize("k,name", [(2, "hex64_s8"), (3, "tetcheck96_s8"), (5, "tetlogn60_s16")])
+def test_full_source_iterations_vs_oracle_samples(k, name):
+    need_gpu()
+    gold = golden(name)
+    n_it = gold["fixed_iterations"]
+    p = W.config(k)
+    print(f"[case] {name} cells={p.n_cells} dirs={p.n_dirs} iterations={n_it}", flush=True)
+    gg = gpu_graph(p)
+    try:
+        phi = dev(np.zeros(p.n_cells))
+        psi = torch.zeros(p.n_dirs * p.n_cells, dtype=torch.float64, device="cuda")
+        st = J.solve(gg, dev(p.sigma_t), dev(p.sigma_s), dev(p.q), phi, psi, mode=J.JSWEEP_FP64, tol=0.0,
+                     max_iter=n_it, allow_not_converged=True)
+        assert st["sweeps"] == n_it
+        ph = host(phi)
+        got_phi = ph[gold["cells"]]
+        got_psi = psi.view(p.n_dirs, p.n_cells)[torch.as_tensor(gold["psi_m"]), torch.as_tensor(gold["psi_k"])]
+        got_psi = host(got_psi)
+        e1, e2 = rel_max(got_phi, gold["phi_fixed"]), rel_max(got_psi, gold["psi"])
+        big, val = gold["fixed_max_cell"]
+        print(f"[{name}] {n_it} SI: phi {e1:.2e} psi {e2:.2e} bitexact {np.array_equal(got_phi, gold['phi_fixed'])} "
+              f"max cell {int(np.argmax(ph))} vs {big}", flush=True)
+        assert e1 <= 1e-12 and e2 <= 1e-12
+        assert abs(ph[big] - val) <= 1e-12 * abs(val)
+    finally:
+        gg.close()
+
+
+@pytest.mark.parametrize("k,name", [(3, "tetcheck96_s8"), (5, "tetlogn60_s16")])
+def test_full_refined_vs_fp64_and_oracle(k, name):
+    need_gpu()
+    gold = golden(name)
+    p = W.config(k)
+    print(f"[case] {name} refined and FP64 to 1e-11", flush=True)
+    gg = gpu_graph(p)
+    try:
+        sol = {}
+        for mode in (J.JSWEEP_FP64, J.JSWEEP_FP32_REFINED):
+            phi = dev(np.zeros(p.n_cells))
+            st = J.solve(gg, dev(p.sigma_t), dev(p.sigma_s), dev(p.q), phi, mode=mode, tol=1e-11, max_iter=5000)
+            ph = host(phi)
+            sol[mode] = ph
+            ref = gold["phi_converged"]
+            got = ph[gold["cells"]]
+            err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+            print(f"[{name}] mode {mode}: sweeps {st['sweeps']} outer {st['outer_iters']} rho {st['residual']:.2e} "
+                  f"phi vs oracle (sampled) {err:.2e}", flush=True)
+            assert st["residual"] <= 1e-11
+            assert err <= 1e-8
+        err = float(np.linalg.norm(sol[J.JSWEEP_FP32_REFINED] - sol[J.JSWEEP_FP64]) /
+                    np.linalg.norm(sol[J.JSWEEP_FP64]))
+        print(f"[{name}] refined vs FP64 phi rel {err:.2e}", flush=True)
+        assert err <= 1e-8
+    finally:
+        gg.close()
 
 
 def test_hex64_s8_full(oracle_mod):
