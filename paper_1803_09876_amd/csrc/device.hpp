@@ -52,6 +52,17 @@ __device__ inline void dir_sum2(const double *w, const double *x, int64_t nc, in
     }
 }
 
+// Logical block of an XCD-aware launch of 8 * per_xcd workgroups.  The
+// dispatcher deals workgroups round robin over the 8 XCDs, so logical block
+// (b mod 8) * per_xcd + b / 8 gives each XCD one contiguous eighth of the
+// blocks, walked in order: gathers of neighbouring cells through the level
+// positions then share L2 lines (in level order the cells of one level
+// that lie in a range of ids are stored together).
+__device__ inline int64_t xcd_block(int64_t per_xcd) {
+    return (int64_t)(blockIdx.x & 7u) * per_xcd + (int64_t)(blockIdx.x >> 3);
+}
+inline int64_t xcd_per(int64_t blocks) { return (blocks + 7) / 8; }
+
 // dir_sum over the level-ordered fluxes of a sweep: the flux of cell K in
 // direction m sits at m nc + posi[m nc + K].  Sixteen directions' positions
 // are loaded together, then their fluxes; the sum runs in ascending m.

@@ -267,8 +267,8 @@ __device__ inline void next_sweep_setup(int64_t t, const int32_t *status, double
 __global__ void k_phi_delta(const double *psi, const int32_t *posi, const double *w, double wsum, const double *q,
                             const double *sigma_s, const double *vol, int64_t nc, int nd, double *phi, double *acc,
                             double *src_next, double *vs_next, LagCells L, const int32_t *status, double *acc_next,
-                            uint32_t *tickets) {
-    const int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                            uint32_t *tickets, int64_t per_xcd) {
+    const int64_t K = xcd_block(per_xcd) * blockDim.x + threadIdx.x;
     next_sweep_setup(K, status, acc, acc_next, tickets);
     double a = 0.0, b = 0.0;
     if (K < nc) {
@@ -292,8 +292,8 @@ __global__ void k_phi_delta(const double *psi, const int32_t *posi, const double
 __global__ void k_phi_delta2(const double *psi, const int32_t *posi, const double *w, double wsum, const double *q,
                              const double *sigma_s, const double *vol, int64_t nc, int nd, double *phi, double *acc,
                              double *src_next, double *vs_next, LagCells L, const int32_t *status, double *acc_next,
-                             uint32_t *tickets) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                             uint32_t *tickets, int64_t per_xcd) {
+    const int64_t t = xcd_block(per_xcd) * blockDim.x + threadIdx.x;
     next_sweep_setup(t, status, acc, acc_next, tickets);
     const int64_t K = 2 * t;
     double a = 0.0, b = 0.0;
@@ -347,8 +347,8 @@ template <int CPT, bool POS = false>
 __global__ void k_dphi(const float *dpsi, const int32_t *posi, const double *w, const double *sigma_s,
                        const double *vol, int64_t nc, int nd, const double *q, double *dphi, float *g32,
                        const int32_t *status, double *acc, double *acc_next, float2 *vs, uint32_t *tickets,
-                       const uint64_t *lag_mv, const int32_t *lag_u, int64_t n_lag, float *lag_val) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                       const uint64_t *lag_mv, const int32_t *lag_u, int64_t n_lag, float *lag_val, int64_t per_xcd) {
+    const int64_t t = xcd_block(per_xcd) * blockDim.x + threadIdx.x;
     if (t == 0) acc[2] = (double)status[0];
     if (t < 2) acc_next[t] = 0.0;
     if (t < kStreams) {
@@ -414,16 +414,17 @@ __global__ void k_dphi(const float *dpsi, const int32_t *posi, const double *w, 
 }
 
 // psi += dpsi (FP64); with posi, dpsi is in level-position order
-__global__ void k_update(double *psi, const float *dpsi, const int32_t *posi, int64_t nc, int64_t n) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_update(double *psi, const float *dpsi, const int32_t *posi, int64_t nc, int64_t n, int64_t per_xcd) {
+    int64_t i = xcd_block(per_xcd) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t j = posi ? (i / nc) * nc + posi[i] : i;
     psi[i] = psi[i] + (double)dpsi[j];
 }
 
 // cell-order copy of level-ordered fluxes: psi[m nc + K] = pos[m nc + posi[m nc + K]]
-__global__ void k_cell_order(const double *pos, const int32_t *posi, int64_t nc, int64_t n, double *psi) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_cell_order(const double *pos, const int32_t *posi, int64_t nc, int64_t n, double *psi,
+                             int64_t per_xcd) {
+    int64_t i = xcd_block(per_xcd) * blockDim.x + threadIdx.x;
     if (i < n) psi[i] = pos[(i / nc) * nc + posi[i]];
 }
 
@@ -553,14 +554,15 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
             // pass over the fluxes for phi; the lagged edges by their
             // downwind cells), and the set-up of the next sweep
             const double *flux = lo ? static_cast<const double *>(last_sweep_pos(g)) : psi;
+            const int64_t pxcd = xcd_per(ceil_div(pairs ? g.nc / 2 : g.nc, kB));
             if (pairs)
-                k_phi_delta2<<<(int)ceil_div(g.nc / 2, kB), kB, 0, s>>>(
+                k_phi_delta2<<<(unsigned)(8 * pxcd), kB, 0, s>>>(
                     flux, posi, g.weight.as<double>(), wsum, q, sigma_s, g.vol.as<double>(), g.nc, g.nd, phi, it_acc,
-                    src, g.vsc.as<double>(), lagc, g.status.as<int32_t>(), next_acc, tickets);
+                    src, g.vsc.as<double>(), lagc, g.status.as<int32_t>(), next_acc, tickets, pxcd);
             else
-                k_phi_delta<<<(int)ceil_div(g.nc, kB), kB, 0, s>>>(
+                k_phi_delta<<<(unsigned)(8 * pxcd), kB, 0, s>>>(
                     flux, posi, g.weight.as<double>(), wsum, q, sigma_s, g.vol.as<double>(), g.nc, g.nd, phi, it_acc,
-                    src, g.vsc.as<double>(), lagc, g.status.as<int32_t>(), next_acc, tickets);
+                    src, g.vsc.as<double>(), lagc, g.status.as<int32_t>(), next_acc, tickets, pxcd);
             JSW_HIP(hipGetLastError());
             prepared = true;
             if (fixed) continue;
@@ -587,8 +589,9 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
         }
         // the caller's psi in cell order, once
         if (lo && psi_out && sweeps > 0) {
-            k_cell_order<<<(unsigned)ceil_div(N, kB), kB, 0, s>>>(static_cast<const double *>(last_sweep_pos(g)),
-                                                                 g.posi.as<int32_t>(), g.nc, N, psi_out);
+            const int64_t pxcd = xcd_per(ceil_div(N, kB));
+            k_cell_order<<<(unsigned)(8 * pxcd), kB, 0, s>>>(static_cast<const double *>(last_sweep_pos(g)),
+                                                            g.posi.as<int32_t>(), g.nc, N, psi_out, pxcd);
             JSW_HIP(hipGetLastError());
         }
     } else {
@@ -665,10 +668,11 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
                 const float *dflux = lo ? static_cast<const float *>(last_sweep_pos(g)) : dpsi;
                 const int cpt = lo ? (g.nc % 2 == 0 ? 2 : 1) : (quads ? 4 : 1);
                 auto dphi_kernel = lo ? (cpt == 2 ? k_dphi<2, true> : k_dphi<1, true>) : (quads ? k_dphi<4> : k_dphi<1>);
-                dphi_kernel<<<(int)ceil_div(g.nc, kB * cpt), kB, 0, s>>>(
+                const int64_t pxcd = xcd_per(ceil_div(g.nc, kB * cpt));
+                dphi_kernel<<<(unsigned)(8 * pxcd), kB, 0, s>>>(
                     dflux, posi, g.weight.as<double>(), sigma_s, g.vol.as<double>(), g.nc, g.nd,
                     from_zero ? q : nullptr, dphi, g32, g.status.as<int32_t>(), a_cur, a_next, g.vsc.as<float2>(),
-                    tickets, g.lag_mv.as<uint64_t>(), g.lag_u.as<int32_t>(), g.n_lag, g.lag_val32.as<float>());
+                    tickets, g.lag_mv.as<uint64_t>(), g.lag_u.as<int32_t>(), g.n_lag, g.lag_val32.as<float>(), pxcd);
                 JSW_HIP(hipGetLastError());
                 double h[3];   // norm of dphi, correction residual, sweep status
                 JSW_HIP(hipMemcpyAsync(h, a_cur, 24, hipMemcpyDeviceToHost, s));
@@ -681,11 +685,12 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
                 if (j > 0 && pred > 0.9 * prev_pred && pred < 100.0 * kFp32Floor * rho) break;
                 prev_pred = pred;
             }
+            const int64_t pxcd = xcd_per(ceil_div(N, kB));
             if (lo) {
                 if (inner > 0)
-                    k_update<<<(int)ceil_div(N, kB), kB, 0, s>>>(psi, static_cast<const float *>(last_sweep_pos(g)),
-                                                                 g.posi.as<int32_t>(), g.nc, N);
-            } else k_update<<<(int)ceil_div(N, kB), kB, 0, s>>>(psi, dpsi, nullptr, g.nc, N);
+                    k_update<<<(unsigned)(8 * pxcd), kB, 0, s>>>(psi, static_cast<const float *>(last_sweep_pos(g)),
+                                                                g.posi.as<int32_t>(), g.nc, N, pxcd);
+            } else k_update<<<(unsigned)(8 * pxcd), kB, 0, s>>>(psi, dpsi, nullptr, g.nc, N, pxcd);
             JSW_HIP(hipGetLastError());
         }
     }

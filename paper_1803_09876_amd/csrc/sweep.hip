@@ -269,16 +269,18 @@ __global__ void k_sweep(SweepArgs<Real> a) {
             }
         }
         // upwind fluxes: interior and lagged ones are loaded together (one
-        // device-scope load per slot and group, the address selected
-        // without branching; other slots read the vertex's own entry and
-        // discard it).  The loads are repeated until no interior slot of any
-        // lane holds the empty marker; polls that keep failing back off.
+        // device-scope load per slot and group, issued only by the lanes
+        // whose slot has such a face).  The loads are repeated until no
+        // interior slot of any lane holds the empty marker; polls that keep
+        // failing back off.
         const Real *from[NS];
         int64_t gstep[NS];
+        bool want[NS];
 #pragma unroll
         for (int j = 0; j < NS; ++j) {
             const int32_t cd = P.code[j];
             const bool lagged = cd <= -2 && cd != kNoFace;
+            want[j] = cd >= 0 || lagged;
             from[j] = cd >= 0 ? a.psi_pos + base + cd : lagged ? a.lag_val + (-(int64_t)cd - 2) : a.psi_pos + own;
             gstep[j] = lagged ? a.gs_lag : a.gs_pos;
         }
@@ -328,7 +330,7 @@ __global__ void k_sweep(SweepArgs<Real> a) {
                 for (int g = 0; g < NG; ++g)
                     if (g < ng) {
 #pragma unroll
-                        for (int j = 0; j < NS; ++j) val[g][j] = ld_coherent(from[j] + g * gstep[j]);
+                        for (int j = 0; j < NS; ++j) val[g][j] = want[j] ? ld_coherent(from[j] + g * gstep[j]) : Real(0);
                     }
                 if constexpr (NSX > 0) {
                     if (nx > 0) {
