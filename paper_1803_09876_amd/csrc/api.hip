@@ -133,6 +133,7 @@ int jsweep_build_graph(const jsweep_mesh *mesh, const jsweep_quadrature *quad, u
             if (!std::isfinite(M.coords[i])) fail(JSWEEP_E_MESH, "non-finite vertex coordinate");
         check_quadrature(*quad);
         auto g = std::make_unique<Graph>();
+        g->uid = next_graph_uid();
         JSW_HIP(hipGetDevice(&g->device));
         hipDeviceProp_t prop;
         JSW_HIP(hipGetDeviceProperties(&prop, g->device));
@@ -486,6 +487,7 @@ int jsweep_trace_read(jsweep_graph h, int64_t *n_chunks, uint32_t *stamps, int32
 void jsweep_graph_destroy(jsweep_graph h) {
     if (!h) return;
     try {
+        union_forget(G(h)->uid);
         delete G(h);
     } catch (...) {
     }

@@ -26,6 +26,11 @@ namespace jsw {
 
 constexpr int kB = 256;
 constexpr int kInnerBlock = 2;   // inner sweeps per graph replay (the granularity of the inner stop)
+// the batched solve's default sweeps the union of all work lists in one
+// data-driven launch while at least this fraction of the cell-angle updates
+// is still iterating (a union sweep walks every chunk), the direction
+// kernels after that
+constexpr double kUnionMinActive = 0.5;
 // outer residual reduction an FP32 correction solve reliably achieves
 constexpr double kFp32Floor = 4e-6;
 
@@ -45,6 +50,9 @@ struct BInst {
     double wsum;                         // sum of the weights
     double *lag64;
     float *lag32;
+    void *vsu;                           // batched data-driven sweep: the instance's V s (FP64) or {V, s}
+                                         // (FP32) in the union's per-cell array, else null
+    void *lagu;                          // and its lagged values in the union's array (FP64 / FP32), else null
     int64_t n_lag, nc;
     int32_t nd, ctype;
     double psi_b;
@@ -127,7 +135,12 @@ __global__ void k_b_zero(const BInst *I, const int64_t *off, int n, int64_t tota
         // whose source is q itself (no per-direction part)
         b.dpsi[x] = 0.0f;
         if (what == 2) b.r32[x] = 0.0f;
-        if (x < b.nc) { b.dphi[x] = 0.0; b.g32[x] = what == 2 ? (float)b.q[x] : 0.0f; }
+        if (x < b.nc) {
+            b.dphi[x] = 0.0;
+            const float src = what == 2 ? (float)b.q[x] : 0.0f;
+            b.g32[x] = src;
+            if (b.vsu) static_cast<float2 *>(b.vsu)[x] = make_float2((float)b.vol[x], src);
+        }
     }
 }
 
@@ -152,7 +165,9 @@ __global__ void k_b_source(const BInst *I, const int64_t *coff, int n, int64_t t
     if (!active[i]) return;
     const BInst &b = I[i];
     const int64_t K = g - coff[i];
-    b.src[K] = b.q[K] + b.sigma_s[K] * b.phi[K];
+    const double src = b.q[K] + b.sigma_s[K] * b.phi[K];
+    b.src[K] = src;
+    if (b.vsu) static_cast<double *>(b.vsu)[K] = b.vol[K] * src;
 }
 
 __global__ void k_b_lag(const BInst *I, const int64_t *loff, int n, int64_t total, const int32_t *active, int fp32) {
@@ -163,8 +178,15 @@ __global__ void k_b_lag(const BInst *I, const int64_t *loff, int n, int64_t tota
     const BInst &b = I[i];
     const int64_t e = g - loff[i];
     const int64_t m = (int64_t)(b.lag_mv[e] >> 32);
-    if (fp32) b.lag32[e] = b.dpsi[m * b.nc + b.lag_u[e]];
-    else b.lag64[e] = b.psi[m * b.nc + b.lag_u[e]];
+    if (fp32) {
+        const float v = b.dpsi[m * b.nc + b.lag_u[e]];
+        b.lag32[e] = v;
+        if (b.lagu) static_cast<float *>(b.lagu)[e] = v;
+    } else {
+        const double v = b.psi[m * b.nc + b.lag_u[e]];
+        b.lag64[e] = v;
+        if (b.lagu) static_cast<double *>(b.lagu)[e] = v;
+    }
 }
 
 // FP64 residual of every active instance; acc[4 i] += ||r||^2, acc[4 i + 1] += ||q||^2
@@ -275,7 +297,9 @@ __global__ void k_b_dphi(const BInst *I, const int64_t *coff, int n, int64_t tot
         const double s = dir_sum(b.w, b.dpsi, b.nc, b.nd, K);
         const double old = b.dphi[K];
         b.dphi[K] = s;
-        b.g32[K] = with_q[i] ? (float)(b.q[K] + b.sigma_s[K] * s) : (float)(b.sigma_s[K] * s);
+        const float src = with_q[i] ? (float)(b.q[K] + b.sigma_s[K] * s) : (float)(b.sigma_s[K] * s);
+        b.g32[K] = src;
+        if (b.vsu) static_cast<float2 *>(b.vsu)[K] = make_float2((float)b.vol[K], src);
         ss = b.vol[K] * (s * s);
         const double d = b.sigma_s[K] * (s - old);
         dd = b.vol[K] * (d * d);
@@ -369,6 +393,8 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
         for (double x : g.weight_h) b.wsum += x;
         b.lag64 = g.lag_val64.as<double>();
         b.lag32 = g.lag_val32.as<float>();
+        b.vsu = nullptr;
+        b.lagu = nullptr;
         b.n_lag = g.n_lag;
         b.nc = g.nc;
         b.nd = g.nd;
@@ -407,9 +433,50 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
             ensure_den(*graphs[i], refined, s);
         }
     }
+    // The sweep of every instance and direction.  DATA_DRIVEN: one launch
+    // of the data-driven kernel over the union of the instances' work lists
+    // (the chunks of converged instances are still walked, only to empty
+    // their entries).  DIRECTION, DIRECTION_LDS: the batched direction
+    // kernels (a converged instance's tasks return at once).  AUTO (the
+    // default): the union launch while at least kUnionMinActive of the
+    // batch's cell-angle updates belong to instances still iterating, the
+    // direction kernels (LDS window where every instance fits it) after.
+    const int strategy = params ? params->strategy : 0;
+    const bool hybrid = strategy == JSWEEP_STRATEGY_AUTO || strategy == JSWEEP_STRATEGY_PATCH;
+    const bool use_union = hybrid || strategy == JSWEEP_STRATEGY_DATA_DRIVEN;
+    const bool use_dir = hybrid || !use_union;
     BatchSweep sweep;
-    sweep.setup(n, graphs, refined, src_cell.data(), src_dir.data(), psi_sweep.data(), psi_b.data(), threads,
-                params ? params->strategy : 0, s);
+    UnionSweep *un = nullptr;
+    if (use_union) {
+        un = &union_for(n, graphs, refined, s);
+        un->refresh_den(graphs, s);
+        un->set_rows(graphs, psi_sweep.data(), src_dir.data(), psi_b.data(), s);
+        for (int i = 0; i < n; ++i) {
+            BInst &b = h[i];
+            b.vsu = static_cast<char *>(un->vs.p) + 8 * (size_t)un->coff[i];
+            b.lagu = static_cast<char *>(un->lag.p) + (refined ? 4 : 8) * (size_t)un->loff[i];
+        }
+        JSW_HIP(hipMemcpyAsync(d_inst.p, h.data(), sizeof(BInst) * n, hipMemcpyHostToDevice, s));
+        JSW_HIP(hipStreamSynchronize(s));
+    }
+    if (use_dir)
+        sweep.setup(n, graphs, refined, src_cell.data(), src_dir.data(), psi_sweep.data(), psi_b.data(),
+                    hybrid ? 0 : threads, hybrid ? JSWEEP_STRATEGY_AUTO : strategy, s);
+    const int wpb = (params && params->waves_per_block > 0) ? params->waves_per_block : 0;
+    std::vector<double> work(n);
+    double all_work = 0.0;
+    for (int i = 0; i < n; ++i) all_work += (work[i] = (double)graphs[i]->nc * graphs[i]->nd);
+    auto union_pays = [&](const std::vector<int32_t> &act) {
+        if (!use_dir) return true;
+        if (!un) return false;
+        double w = 0.0;
+        for (int i = 0; i < n; ++i) w += act[i] ? work[i] : 0.0;
+        return w >= kUnionMinActive * all_work;
+    };
+    auto launch_sweep = [&](const int32_t *act, bool by_union) {
+        if (by_union) un->launch(act, wpb, s);
+        else sweep.launch(act, s);
+    };
     k_b_zero<<<grid_for(A), kB, 0, s>>>(I, d_aoff.as<int64_t>(), n, A, nullptr, 0);
     JSW_HIP(hipGetLastError());
 
@@ -457,7 +524,7 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
             if (total_sweeps >= max_iter) { rc = JSWEEP_E_NOT_CONVERGED; break; }
             k_b_source<<<grid_for(C), kB, 0, s>>>(I, d_coff.as<int64_t>(), n, C, d_active.as<int32_t>());
             if (LG) k_b_lag<<<grid_for(LG), kB, 0, s>>>(I, d_loff.as<int64_t>(), n, LG, d_active.as<int32_t>(), 0);
-            sweep.launch(d_active.as<int32_t>(), s);
+            launch_sweep(d_active.as<int32_t>(), union_pays(active));
             ++total_sweeps;
             for (int i = 0; i < n; ++i) sweeps[i] += active[i];
             // residual from the sweep identity (one pass over psi)
@@ -470,6 +537,10 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
             JSW_HIP(hipGetLastError());
             JSW_HIP(hipMemcpyAsync(acc.data(), d_acc.p, 8 * 4 * n, hipMemcpyDeviceToHost, s));
             JSW_HIP(hipStreamSynchronize(s));
+            if (un) {
+                const int st = un->check_status(s);
+                if (st != JSWEEP_OK) return st;
+            }
             for (int i = 0; i < n; ++i) {
                 if (!active[i]) continue;
                 const double rr = std::max(acc[4 * i], 0.0);
@@ -484,28 +555,39 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
         const int J = (params && params->inner_sweeps > 0) ? params->inner_sweeps : 400;
         DevBuf d_inner(4 * n), d_withq(4 * n);
         std::vector<int32_t> withq(n, 0);
-        // record kInnerBlock inner sweeps once; replay them per block
-        hipGraph_t graph = nullptr;
-        hipGraphExec_t exec = nullptr;
-        JSW_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        for (int k = 0; k < kInnerBlock; ++k) {
-            if (LG) k_b_lag<<<grid_for(LG), kB, 0, s>>>(I, d_loff.as<int64_t>(), n, LG, d_inner.as<int32_t>(), 1);
-            sweep.launch(d_inner.as<int32_t>(), s);
-            // the norms read back after a replay are those of its last pass
-            if (k == kInnerBlock - 1) k_b_clear<<<grid_for(4 * n), kB, 0, s>>>(d_acc.as<double>(), 4 * n);
-            k_b_dphi<<<grid_for(C), kB, 0, s>>>(I, d_coff.as<int64_t>(), n, C, d_inner.as<int32_t>(),
-                                                d_withq.as<int32_t>(), d_acc.as<double>());
-        }
-        hipError_t ce = hipStreamEndCapture(s, &graph);
-        if (ce != hipSuccess) {
-            if (graph) (void)hipGraphDestroy(graph);
-            JSW_HIP(ce);
-        }
-        JSW_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        // record kInnerBlock inner sweeps once; replay them per block.
+        // The union sweep's level-position arrays alternate within the
+        // recorded block (kInnerBlock is even); the first holds the marker
+        // before recording.
+        static_assert(kInnerBlock % 2 == 0, "the recorded block keeps the level-position arrays' alternation");
+        if (un) un->fill_current(s);
+        // one recorded block per sweep kind in use: [0] union, [1] direction kernels
+        hipGraph_t graphs_rec[2] = {nullptr, nullptr};
+        hipGraphExec_t execs[2] = {nullptr, nullptr};
         struct GraphGuard {
-            hipGraph_t g; hipGraphExec_t e;
-            ~GraphGuard() { if (e) (void)hipGraphExecDestroy(e); if (g) (void)hipGraphDestroy(g); }
-        } guard{graph, exec};
+            hipGraph_t *g; hipGraphExec_t *e;
+            ~GraphGuard() {
+                for (int k = 0; k < 2; ++k) {
+                    if (e[k]) (void)hipGraphExecDestroy(e[k]);
+                    if (g[k]) (void)hipGraphDestroy(g[k]);
+                }
+            }
+        } guard{graphs_rec, execs};
+        for (int kind = 0; kind < 2; ++kind) {
+            if ((kind == 0 && !use_union) || (kind == 1 && !use_dir)) continue;
+            JSW_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            for (int k = 0; k < kInnerBlock; ++k) {
+                if (LG) k_b_lag<<<grid_for(LG), kB, 0, s>>>(I, d_loff.as<int64_t>(), n, LG, d_inner.as<int32_t>(), 1);
+                launch_sweep(d_inner.as<int32_t>(), kind == 0);
+                // the norms read back after a replay are those of its last pass
+                if (k == kInnerBlock - 1) k_b_clear<<<grid_for(4 * n), kB, 0, s>>>(d_acc.as<double>(), 4 * n);
+                k_b_dphi<<<grid_for(C), kB, 0, s>>>(I, d_coff.as<int64_t>(), n, C, d_inner.as<int32_t>(),
+                                                    d_withq.as<int32_t>(), d_acc.as<double>());
+            }
+            hipError_t ce = hipStreamEndCapture(s, &graphs_rec[kind]);
+            if (ce != hipSuccess) JSW_HIP(ce);
+            JSW_HIP(hipGraphInstantiate(&execs[kind], graphs_rec[kind], nullptr, nullptr, 0));
+        }
         std::vector<double> prev_pred(n, INFINITY), target(n, 0.0);
         // From the zero iterate with no boundary inflow the residual is q
         // itself (rho = 1): the first solve is source iteration on the
@@ -552,10 +634,14 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
             }
             for (int j = 0; j < J && total_sweeps < max_iter; j += kInnerBlock) {
                 JSW_HIP(hipMemcpyAsync(d_inner.p, inner_active.data(), 4 * n, hipMemcpyHostToDevice, s));
-                JSW_HIP(hipGraphLaunch(exec, s));
+                JSW_HIP(hipGraphLaunch(execs[union_pays(inner_active) ? 0 : 1], s));
                 total_sweeps += kInnerBlock;
                 JSW_HIP(hipMemcpyAsync(acc.data(), d_acc.p, 8 * 4 * n, hipMemcpyDeviceToHost, s));
                 JSW_HIP(hipStreamSynchronize(s));
+                if (un) {
+                    const int st = un->check_status(s);
+                    if (st != JSWEEP_OK) return st;
+                }
                 bool more = false;
                 for (int i = 0; i < n; ++i) {
                     if (!inner_active[i]) continue;
@@ -697,6 +783,9 @@ int autotune(int32_t n, Graph *const *graphs, int32_t mode, jsweep_params *out) 
         // the patch-task kernel (FP64 sweeps only), where its program applies
         if (!fp32 && patch_ready(*graphs[0], s)) cands.push_back(jsweep_params{1, 0, 0, 0, JSWEEP_STRATEGY_PATCH, 0});
     } else {
+        // the union of the instances' work lists in one data-driven launch,
+        // and the batched direction kernels
+        for (int w : {4, 5, 6, 8}) cands.push_back(jsweep_params{w, 0, 0, 0, JSWEEP_STRATEGY_DATA_DRIVEN, 0});
         for (int w : {1, 2, 4, 8, 16}) cands.push_back(jsweep_params{w, 0, 0, 0, JSWEEP_STRATEGY_DIRECTION, 0});
         cands.push_back(ring_probe);
     }
@@ -711,24 +800,40 @@ int autotune(int32_t n, Graph *const *graphs, int32_t mode, jsweep_params *out) 
     for (const jsweep_params &c : cands) {
         float ms = 0.0f;
         BatchSweep bs;
+        UnionSweep *un = nullptr;
         if (n > 1) {
             std::vector<const void *> sc(n);
             std::vector<const float *> sd(n, nullptr);
             std::vector<void *> ps(n);
             std::vector<double> pb(n, 0.0);
             for (int i = 0; i < n; ++i) { sc[i] = src[i].p; ps[i] = psi[i].p; }
-            bs.setup(n, graphs, fp32, sc.data(), sd.data(), ps.data(), pb.data(), 64 * c.waves_per_block, c.strategy, s);
+            if (c.strategy == JSWEEP_STRATEGY_DATA_DRIVEN) {
+                un = &union_for(n, graphs, fp32, s);
+                un->refresh_den(graphs, s);
+                un->set_rows(graphs, ps.data(), sd.data(), pb.data(), s);
+                // unit sources (V s = V, or {V, 1}) are as good as any for timing
+                JSW_HIP(hipMemsetAsync(un->vs.p, 0, un->vs.bytes, s));
+            } else {
+                bs.setup(n, graphs, fp32, sc.data(), sd.data(), ps.data(), pb.data(), 64 * c.waves_per_block,
+                         c.strategy, s);
+            }
         }
         for (int rep = 0; rep < 3; ++rep) {
             JSW_HIP(hipEventRecord(e0, s));
             if (n == 1) {
                 if (fp32) launch_sweep32(*graphs[0], nullptr, src[0].as<float>(), psi[0].as<float>(), &c, s);
                 else launch_sweep64(*graphs[0], src[0].as<double>(), psi[0].as<double>(), 0.0, &c, s);
+            } else if (un) {
+                un->launch(d_active.as<int32_t>(), c.waves_per_block, s);
             } else {
                 bs.launch(d_active.as<int32_t>(), s);
             }
             JSW_HIP(hipEventRecord(e1, s));
             JSW_HIP(hipEventSynchronize(e1));
+            if (un) {
+                const int st = un->check_status(s);
+                if (st != JSWEEP_OK) fail(st, "batched sweep failed while tuning: " + std::string(jsweep_last_error()));
+            }
             if (n == 1) {
                 const int st = check_sweep_status(*graphs[0], s);
                 if (st != JSWEEP_OK)
@@ -745,6 +850,9 @@ int autotune(int32_t n, Graph *const *graphs, int32_t mode, jsweep_params *out) 
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    // for a batch the data-driven union is used through the default hybrid
+    // (union while most of the batch iterates, direction kernels after)
+    if (n > 1 && best_p.strategy == JSWEEP_STRATEGY_DATA_DRIVEN) best_p.strategy = JSWEEP_STRATEGY_AUTO;
     *out = best_p;
     cache_store(key, best_p);
     for (int i = 0; i < n; ++i) { graphs[i]->tuned = best_p; graphs[i]->has_tuned = true; }

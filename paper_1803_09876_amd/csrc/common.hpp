@@ -196,6 +196,8 @@ struct PatchProg {
 // graph handle
 // ---------------------------------------------------------------------------
 struct Graph {
+    uint64_t uid = 0;                    // unique per built graph (process-wide counter)
+    uint32_t prog_version = 0;           // bumped whenever the work list or program is rebuilt
     int device = 0;
     int n_cu = 0;
     int priority = JSWEEP_PRIORITY_BFS;  // order of the work list (JSWEEP_PRIORITY_*)
@@ -298,6 +300,24 @@ void launch_sweep32(Graph &g, const float *src_dir, const float *src_cell, float
 // the cell-order copy.  This returns the array the last data-driven sweep
 // filled (double or float by that sweep's precision).
 void *last_sweep_pos(Graph &g);
+// A direction of a union of graphs swept by one launch of the data-driven
+// kernel (the batched solve): where its arrays start.  pos_base: its first
+// level position in the union's level-position arrays; psi_row: the
+// instance's cell-order fluxes of this direction (or null); cell_off: the
+// instance's first cell in the union's per-cell arrays (cell ids in the
+// union's chunk blocks are global); src_row: the instance's per-direction
+// FP32 source of this direction, by level position (or null); inst: the
+// instance.
+struct DirRow {
+    int64_t pos_base;
+    int64_t cell_off;
+    void *psi_row;
+    const float *src_row;
+    double psi_b;                        // the instance's boundary inflow
+    int32_t inst;
+    int32_t pad;
+};
+
 // Multigroup FP64 sweep: groups (<= kMaxGroups) energy groups of one graph
 // in one launch of the data-driven kernel.  The caller has prepared
 // g.vsc as V s per (group, cell) [groups * nc] and zeroed the stream
@@ -326,6 +346,46 @@ bool patch_ready(Graph &g, hipStream_t s);
 void patch_den(Graph &g, hipStream_t s);
 void launch_patch64(Graph &g, const double *src_cell, double *psi, double psi_b, const jsweep_params *p,
                     hipStream_t s, bool prepared = false);
+
+// Batched data-driven sweep (sweep.hip): the work lists of several graphs
+// merged into one, so that every instance and direction of a batch is
+// swept by one launch of the data-driven kernel.  Stream x of the union
+// holds the chunks of stream x of every instance, ordered by (level,
+// instance, chunk) -- a topological order of every instance at once.  Cell
+// ids in the union's chunk blocks are global (the instance's first cell
+// added), direction fields are global directions (the instance's first
+// direction added), lagged-edge codes index the union's lagged-value array;
+// each global direction's row (DirRow) gives its arrays.  The structure
+// depends only on the graphs' programs and is cached (one batch at a
+// time); denominators, rows and sources are refreshed per solve.
+struct UnionSweep {
+    std::vector<uint64_t> key;           // (uid, program version) of every instance, then the precision
+    bool fp32 = false;
+    int n = 0, ns = 0, n_cu = 0, total_dirs = 0;
+    int64_t n_chunks = 0, C = 0, A = 0, LG = 0;
+    std::vector<int64_t> coff, aoff, loff;        // per instance: first cell, vertex, lagged edge
+    std::vector<int32_t> dir_off;                 // per instance: first global direction
+    std::vector<int64_t> stream_off_h;
+    DevBuf uinst, uchunk, isrc, cblk, pcode, pa, pden, stream_off, rows, status, lag, vs;
+    DevBuf pos[2];
+    int pos_state[2] = {0, 0}, cur = 0;   // element size of the empty markers each array holds (0: none)
+    void build(int n, Graph *const *graphs, bool fp32, hipStream_t s);
+    void refresh_den(Graph *const *graphs, hipStream_t s);
+    // rows: per instance its cell-order flux array (psi_row base), FP32
+    // per-direction source (src_row base, or null) and boundary inflow
+    void set_rows(Graph *const *graphs, void *const *psi, const float *const *src_dir, const double *psi_b,
+                  hipStream_t s);
+    // the current level-position array holds the empty marker (before a
+    // capture: the captured launches keep the alternation consistent)
+    void fill_current(hipStream_t s);
+    void launch(const int32_t *active, int waves_per_block, hipStream_t s);
+    int check_status(hipStream_t s);
+};
+// the cached union of these graphs (rebuilt when any of them changed)
+UnionSweep &union_for(int n, Graph *const *graphs, bool fp32, hipStream_t s);
+// drops the cached union if it holds this graph
+void union_forget(uint64_t uid);
+uint64_t next_graph_uid();
 
 // batched sweep over an ensemble of graphs: one workgroup per
 // (instance, direction), one launch (sweep.hip)

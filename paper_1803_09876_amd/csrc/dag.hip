@@ -975,6 +975,7 @@ static void reorder_impl(Graph &g, int priority, hipStream_t s) {
     g.den64_ok = g.den32_ok = false;
     g.dd_state[0] = g.dd_state[1] = 0;
     g.priority = priority;
+    ++g.prog_version;
     JSW_HIP(hipStreamSynchronize(s));
 }
 

@@ -63,6 +63,7 @@
 #include <cstring>
 
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <cstdlib>
@@ -101,6 +102,10 @@ struct SweepArgs {
     int64_t gs_pos;                          // psi, psi_pos, pos_next: nd * nc
     int64_t gs_den;                          // pden: stride (64 * n_chunks)
     int64_t gs_lag;                          // lag_val: n_lag
+    // union of several graphs (batched sweep): a chunk's direction field is
+    // a global direction whose row locates its arrays; null for one graph
+    const DirRow *rows;
+    const int32_t *active;                   // per instance: chunks of inactive ones only empty their entries
 };
 
 template <class T>
@@ -246,10 +251,33 @@ __global__ void k_sweep(SweepArgs<Real> a) {
         const uint32_t hdr = (uint32_t)__builtin_amdgcn_readfirstlane(P.w2);
         const int64_t pos0 = (int64_t)(uint32_t)__builtin_amdgcn_readlane(P.w2, 2);
         const int m = (int)(hdr & 0xffffu);
-        const bool active = P.item >= 0;
-        const int64_t base = (int64_t)m * a.nc;
+        bool active = P.item >= 0;
         const int64_t K = active ? (int64_t)P.item : 0;
+        // where direction m's arrays start: m nc for one graph, the
+        // direction's row for a union of graphs
+        int64_t base = (int64_t)m * a.nc;
+        Real *cell_row = a.psi ? a.psi + base : nullptr;
+        int64_t cell_k = K;
+        const float *src_row = a.src_dir ? a.src_dir + base : nullptr;
+        Real psi_b = a.psi_b;
+        bool skip = false;
+        if (a.rows) {
+            const DirRow row = a.rows[m];
+            base = row.pos_base;
+            cell_row = static_cast<Real *>(row.psi_row);
+            cell_k = K - row.cell_off;
+            src_row = row.src_row;
+            psi_b = (Real)row.psi_b;
+            skip = a.active && a.active[row.inst] == 0;   // wave-uniform: a chunk has one direction
+        }
         const int64_t own = base + pos0 + lane;
+        if (skip) {
+            // a chunk of an inactive instance computes nothing; it only
+            // empties its entries of the next sweep's array (the instance
+            // may be active again then)
+            if (active) __builtin_nontemporal_store(empty_marker<Real>(), a.pos_next + own);
+            active = false;
+        }
         // V s of the cell (one gather from a per-cell array per group; in
         // FP32 V and s, combined with the per-direction source after the
         // poll, so that nothing waits for these loads before it)
@@ -265,7 +293,7 @@ __global__ void k_sweep(SweepArgs<Real> a) {
                     if (g < ng) num[g] = reinterpret_cast<const double *>(a.vs)[g * a.nc + K];
             } else {
                 vs32 = reinterpret_cast<const float2 *>(a.vs)[K];
-                if (a.src_dir) sd32 = __builtin_nontemporal_load(a.src_dir + own);   // read once per sweep
+                if (src_row) sd32 = __builtin_nontemporal_load(src_row + pos0 + lane);   // read once per sweep
             }
         }
         // upwind fluxes: interior and lagged ones are loaded together (one
@@ -379,20 +407,20 @@ __global__ void k_sweep(SweepArgs<Real> a) {
         t_ready = (uint32_t)__builtin_amdgcn_s_memrealtime();
         if (request) pend = (int64_t)__builtin_amdgcn_readfirstlane(nxt);
         at_pos = a.psi_pos + own;
-        at_cell = a.psi ? a.psi + base + K : nullptr;
+        at_cell = cell_row ? cell_row + cell_k : nullptr;
         at_next = a.pos_next + own;
         if (active) {
 #pragma unroll
             for (int g = 0; g < NG; ++g) {
                 if (g >= ng) continue;
                 Real ng_num = num[g];
-                if constexpr (sizeof(Real) == 4) ng_num = vs32.x * (a.src_dir ? sd32 + vs32.y : vs32.y);
+                if constexpr (sizeof(Real) == 4) ng_num = vs32.x * (src_row ? sd32 + vs32.y : vs32.y);
                 // step-scheme balance, inflow faces in local face order
 #pragma unroll
                 for (int j = 0; j < NS; ++j) {
                     const int32_t cd = P.code[j];
                     const bool lagged = cd <= -2 && cd != kNoFace;
-                    const Real v = (cd >= 0 || lagged) ? val[g][j] : (cd == -1 ? a.psi_b : Real(0));
+                    const Real v = (cd >= 0 || lagged) ? val[g][j] : (cd == -1 ? psi_b : Real(0));
                     if (cd != kNoFace) ng_num = ng_num + P.af[j] * v;
                 }
                 if constexpr (NSX > 0) {
@@ -400,7 +428,7 @@ __global__ void k_sweep(SweepArgs<Real> a) {
                     for (int k = 0; k < NX; ++k) {
                         const int32_t cd = code_x[k];
                         const bool lagged = cd <= -2 && cd != kNoFace;
-                        const Real v = (cd >= 0 || lagged) ? val_x[k] : (cd == -1 ? a.psi_b : Real(0));
+                        const Real v = (cd >= 0 || lagged) ? val_x[k] : (cd == -1 ? psi_b : Real(0));
                         if (cd != kNoFace) ng_num = ng_num + af_x[k] * v;
                     }
                 }
@@ -412,7 +440,7 @@ __global__ void k_sweep(SweepArgs<Real> a) {
                 // copy (when the caller wants one) is read only after the
                 // kernel
                 at_pos[g * a.gs_pos] = o;
-                if (a.psi) at_cell[g * a.gs_pos] = o;
+                if (cell_row) at_cell[g * a.gs_pos] = o;
                 __builtin_nontemporal_store(empty_marker<Real>(), at_next + g * a.gs_pos);   // read in the next sweep
                 if (g == 0) out = o;
             }
@@ -783,6 +811,8 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
     a.psi_b = psi_b;
     a.watchdog_ticks = watchdog_ticks();
     a.stamps = g.trace ? g.trace_buf.as<uint32_t>() : nullptr;
+    a.rows = nullptr;
+    a.active = nullptr;
     if (g.trace) g.trace_units = 0;
     {
         const char *e = std::getenv("JSWEEP_POLL_NAP");
@@ -1367,6 +1397,335 @@ void BatchSweep::launch(const int32_t *active, hipStream_t s) {
                            inst.as<BatchInst<double>>(), task_inst.as<int32_t>(), task_dir.as<int32_t>(), active);
     }
     JSW_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Union of several graphs swept by one launch of the data-driven kernel
+// (the batched solve; structure in common.hpp).
+// ---------------------------------------------------------------------------
+namespace {
+
+struct UnionSrc {
+    const int32_t *cblk;                 // the instance's chunk blocks
+    const int32_t *pcode;                // its program (ns slots, stride S)
+    const void *pa;
+    const void *pden;
+    int64_t S, coff, loff;
+    int32_t ns, dir_off;
+};
+
+std::mutex g_union_mu;
+std::unique_ptr<UnionSweep> g_union[2];   // one per precision
+std::atomic<uint64_t> g_uid{0};
+
+// chunk block of union chunk u from chunk c of instance i: global cell ids
+// and global direction
+__global__ void k_union_block(const int32_t *uinst, const int32_t *uchunk, const UnionSrc *src, int64_t n,
+                              int32_t *blk) {
+    const int64_t u = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (u >= n) return;
+    const UnionSrc r = src[uinst[u]];
+    const int32_t *b = r.cblk + (int64_t)uchunk[u] * kBlock;
+    int32_t *o = blk + u * kBlock;
+    const int32_t K = b[lane];
+    o[lane] = K >= 0 ? (int32_t)(K + r.coff) : -1;
+    if (lane == 0) {
+        const uint32_t w = (uint32_t)b[64];
+        o[64] = (int32_t)(((w & 0xffffu) + (uint32_t)r.dir_off) | (w & 0xffff0000u));
+    }
+    if (lane == 1) o[65] = 0;
+    if (lane == 2) o[66] = b[66];
+}
+
+// program of union chunk u: codes (lagged-edge codes moved to the union's
+// lagged-value array; slots past the instance's ns empty), coefficients
+// and denominators (DEN_ONLY: the denominators alone)
+template <class Real, bool DEN_ONLY>
+__global__ void k_union_prog(const int32_t *uinst, const int32_t *uchunk, const UnionSrc *src, int64_t n, int ns,
+                             int32_t *pcode, Real *pa, Real *pden) {
+    const int64_t u = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (u >= n) return;
+    const UnionSrc r = src[uinst[u]];
+    const int64_t from = (int64_t)uchunk[u] * 64 + lane, to = u * 64 + lane, S = n * 64;
+    pden[to] = static_cast<const Real *>(r.pden)[from];
+    if (DEN_ONLY) return;
+    for (int j = 0; j < ns; ++j) {
+        int32_t cd = kNoFace;
+        Real af = Real(0);
+        if (j < r.ns) {
+            cd = r.pcode[j * r.S + from];
+            af = static_cast<const Real *>(r.pa)[j * r.S + from];
+            if (cd <= -2 && cd != kNoFace) cd = (int32_t)(-((-(int64_t)cd - 2) + r.loff) - 2);
+        }
+        pcode[j * S + to] = cd;
+        pa[j * S + to] = af;
+    }
+}
+
+}  // namespace
+
+uint64_t next_graph_uid() { return ++g_uid; }
+
+void union_forget(uint64_t uid) {
+    std::lock_guard<std::mutex> lock(g_union_mu);
+    for (auto &u : g_union) {
+        if (!u) continue;
+        for (size_t i = 0; i + 1 < u->key.size(); ++i)
+            if ((u->key[i] >> 24) == uid) {
+                u.reset();
+                break;
+            }
+    }
+}
+
+static std::vector<UnionSrc> union_sources(const UnionSweep &u, Graph *const *graphs) {
+    std::vector<UnionSrc> src(u.n);
+    for (int i = 0; i < u.n; ++i) {
+        const Graph &g = *graphs[i];
+        UnionSrc &r = src[i];
+        r.cblk = g.cblk.as<int32_t>();
+        r.pcode = g.pcode.as<int32_t>();
+        r.pa = u.fp32 ? g.pa32.p : g.pa64.p;
+        r.pden = u.fp32 ? g.pden32.p : g.pden64.p;
+        r.S = 64 * g.n_chunks;
+        r.coff = u.coff[i];
+        r.loff = u.loff[i];
+        r.ns = g.ns;
+        r.dir_off = u.dir_off[i];
+    }
+    return src;
+}
+
+void UnionSweep::build(int n_, Graph *const *graphs, bool fp32_, hipStream_t s) {
+    n = n_;
+    fp32 = fp32_;
+    n_cu = graphs[0]->n_cu;
+    ns = 1;
+    coff.assign(n + 1, 0);
+    aoff.assign(n + 1, 0);
+    loff.assign(n + 1, 0);
+    dir_off.assign(n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+        const Graph &g = *graphs[i];
+        if (g.ns > 6) fail(JSWEEP_E_INVALID_ARG, "batched data-driven sweep: too many inflow slots");
+        ns = std::max(ns, g.ns);
+        coff[i + 1] = coff[i] + g.nc;
+        aoff[i + 1] = aoff[i] + g.nc * g.nd;
+        loff[i + 1] = loff[i] + g.n_lag;
+        dir_off[i + 1] = dir_off[i] + g.nd;
+    }
+    C = coff[n];
+    A = aoff[n];
+    LG = loff[n];
+    total_dirs = dir_off[n];
+    if (total_dirs > 0xffff) fail(JSWEEP_E_INVALID_ARG, "batched data-driven sweep: more than 65535 directions in all");
+    if (A >= ((int64_t)1 << 32) || C >= ((int64_t)1 << 31)) fail(JSWEEP_E_INVALID_ARG, "batched data-driven sweep: batch too large");
+    // merged streams: every instance's chunks of stream x, ordered by
+    // (level, instance, chunk)
+    struct Item {
+        int32_t level, inst, chunk;
+    };
+    std::vector<std::vector<Item>> per(kStreams);
+    for (int i = 0; i < n; ++i) {
+        const Graph &g = *graphs[i];
+        std::vector<Chunk> ch(g.n_chunks);
+        if (g.n_chunks) JSW_HIP(hipMemcpy(ch.data(), g.chunks.p, sizeof(Chunk) * g.n_chunks, hipMemcpyDeviceToHost));
+        for (int64_t c = 0; c < g.n_chunks; ++c) {
+            const int m = (int)(ch[c].a & 0xffffu);
+            const int64_t *p = g.lvl_ptr_h.data() + g.lvl_off_h[m];
+            const int L = (int)(std::upper_bound(p, p + g.nlev_h[m] + 1, (int64_t)ch[c].b) - p - 1);
+            per[g.dir_stream_h[m]].push_back(Item{L, i, (int32_t)c});
+        }
+    }
+    std::vector<int32_t> hi, hc;
+    stream_off_h.assign(kStreams + 1, 0);
+    for (int x = 0; x < kStreams; ++x) {
+        auto &v = per[x];
+        std::sort(v.begin(), v.end(), [](const Item &a, const Item &b) {
+            if (a.level != b.level) return a.level < b.level;
+            if (a.inst != b.inst) return a.inst < b.inst;
+            return a.chunk < b.chunk;
+        });
+        stream_off_h[x] = (int64_t)hi.size();
+        for (const Item &it : v) {
+            hi.push_back(it.inst);
+            hc.push_back(it.chunk);
+        }
+    }
+    stream_off_h[kStreams] = (int64_t)hi.size();
+    n_chunks = (int64_t)hi.size();
+    if (n_chunks >= ((int64_t)1 << 31)) fail(JSWEEP_E_INVALID_ARG, "batched data-driven sweep: too many chunks");
+    const int64_t S = 64 * std::max<int64_t>(1, n_chunks);
+    uinst.alloc(4 * std::max<int64_t>(1, n_chunks));
+    uchunk.alloc(4 * std::max<int64_t>(1, n_chunks));
+    isrc.alloc(sizeof(UnionSrc) * n);
+    cblk.alloc(4 * (size_t)kBlock * std::max<int64_t>(1, n_chunks));
+    pcode.alloc(4 * (size_t)ns * S);
+    pa.alloc((fp32 ? 4 : 8) * (size_t)ns * S);
+    pden.alloc((fp32 ? 4 : 8) * (size_t)S);
+    stream_off.alloc(8 * (kStreams + 1));
+    rows.alloc(sizeof(DirRow) * std::max(1, total_dirs));
+    status.alloc(128 + 32 * 4 * kStreams);
+    lag.alloc((fp32 ? 4 : 8) * (size_t)std::max<int64_t>(1, LG));
+    vs.alloc(8 * (size_t)std::max<int64_t>(1, C));
+    for (int k = 0; k < 2; ++k) {
+        pos[k].alloc(8 * (size_t)std::max<int64_t>(1, A));
+        pos_state[k] = 0;
+    }
+    cur = 0;
+    const std::vector<UnionSrc> src = union_sources(*this, graphs);
+    if (n_chunks) {
+        JSW_HIP(hipMemcpyAsync(uinst.p, hi.data(), 4 * n_chunks, hipMemcpyHostToDevice, s));
+        JSW_HIP(hipMemcpyAsync(uchunk.p, hc.data(), 4 * n_chunks, hipMemcpyHostToDevice, s));
+    }
+    JSW_HIP(hipMemcpyAsync(isrc.p, src.data(), sizeof(UnionSrc) * n, hipMemcpyHostToDevice, s));
+    JSW_HIP(hipMemcpyAsync(stream_off.p, stream_off_h.data(), 8 * (kStreams + 1), hipMemcpyHostToDevice, s));
+    JSW_HIP(hipMemsetAsync(status.p, 0, status.bytes, s));
+    if (n_chunks) {
+        k_union_block<<<(unsigned)n_chunks, 64, 0, s>>>(uinst.as<int32_t>(), uchunk.as<int32_t>(), isrc.as<UnionSrc>(),
+                                                        n_chunks, cblk.as<int32_t>());
+        JSW_HIP(hipGetLastError());
+        if (fp32)
+            k_union_prog<float, false><<<(unsigned)n_chunks, 64, 0, s>>>(
+                uinst.as<int32_t>(), uchunk.as<int32_t>(), isrc.as<UnionSrc>(), n_chunks, ns, pcode.as<int32_t>(),
+                pa.as<float>(), pden.as<float>());
+        else
+            k_union_prog<double, false><<<(unsigned)n_chunks, 64, 0, s>>>(
+                uinst.as<int32_t>(), uchunk.as<int32_t>(), isrc.as<UnionSrc>(), n_chunks, ns, pcode.as<int32_t>(),
+                pa.as<double>(), pden.as<double>());
+        JSW_HIP(hipGetLastError());
+    }
+    JSW_HIP(hipStreamSynchronize(s));   // the host tables go out of scope
+}
+
+void UnionSweep::refresh_den(Graph *const *graphs, hipStream_t s) {
+    if (!n_chunks) return;
+    const std::vector<UnionSrc> src = union_sources(*this, graphs);
+    JSW_HIP(hipMemcpyAsync(isrc.p, src.data(), sizeof(UnionSrc) * n, hipMemcpyHostToDevice, s));
+    if (fp32)
+        k_union_prog<float, true><<<(unsigned)n_chunks, 64, 0, s>>>(uinst.as<int32_t>(), uchunk.as<int32_t>(),
+                                                                    isrc.as<UnionSrc>(), n_chunks, ns, nullptr,
+                                                                    nullptr, pden.as<float>());
+    else
+        k_union_prog<double, true><<<(unsigned)n_chunks, 64, 0, s>>>(uinst.as<int32_t>(), uchunk.as<int32_t>(),
+                                                                     isrc.as<UnionSrc>(), n_chunks, ns, nullptr,
+                                                                     nullptr, pden.as<double>());
+    JSW_HIP(hipGetLastError());
+    JSW_HIP(hipStreamSynchronize(s));   // src goes out of scope
+}
+
+void UnionSweep::set_rows(Graph *const *graphs, void *const *psi, const float *const *src_dir, const double *psi_b,
+                          hipStream_t s) {
+    std::vector<DirRow> h(std::max(1, total_dirs));
+    const size_t word = fp32 ? 4 : 8;
+    for (int i = 0; i < n; ++i) {
+        const Graph &g = *graphs[i];
+        for (int m = 0; m < g.nd; ++m) {
+            DirRow &r = h[dir_off[i] + m];
+            r.pos_base = aoff[i] + (int64_t)m * g.nc;
+            r.cell_off = coff[i];
+            r.psi_row = psi[i] ? static_cast<char *>(psi[i]) + word * (size_t)m * g.nc : nullptr;
+            r.src_row = src_dir[i] ? src_dir[i] + (int64_t)m * g.nc : nullptr;
+            r.psi_b = psi_b[i];
+            r.inst = i;
+            r.pad = 0;
+        }
+    }
+    JSW_HIP(hipMemcpyAsync(rows.p, h.data(), sizeof(DirRow) * h.size(), hipMemcpyHostToDevice, s));
+    JSW_HIP(hipStreamSynchronize(s));
+}
+
+void UnionSweep::fill_current(hipStream_t s) {
+    const int want = fp32 ? 4 : 8;
+    if (pos_state[cur] == want || A == 0) return;
+    if (fp32)
+        k_fill_empty<float><<<(int)std::min<int64_t>(ceil_div(A, 256), 8192), 256, 0, s>>>(pos[cur].as<float>(), A);
+    else
+        k_fill_empty<double><<<(int)std::min<int64_t>(ceil_div(A, 256), 8192), 256, 0, s>>>(pos[cur].as<double>(), A);
+    JSW_HIP(hipGetLastError());
+    pos_state[cur] = want;
+}
+
+template <class Real>
+static void union_launch(UnionSweep &u, const int32_t *active, int waves_per_block, hipStream_t s) {
+    SweepArgs<Real> a;
+    a.cblk = u.cblk.as<int32_t>();
+    a.nc = 0;
+    a.stride = 64 * u.n_chunks;
+    a.pcode = u.pcode.as<int32_t>();
+    a.pa = u.pa.as<Real>();
+    a.pden = u.pden.as<Real>();
+    a.vs = u.vs.p;
+    a.src_dir = nullptr;
+    a.psi = nullptr;
+    u.fill_current(s);
+    a.psi_pos = u.pos[u.cur].as<Real>();
+    a.pos_next = u.pos[1 - u.cur].as<Real>();
+    u.pos_state[u.cur] = 0;
+    u.pos_state[1 - u.cur] = (int)sizeof(Real);
+    u.cur = 1 - u.cur;
+    a.status = u.status.as<int32_t>();
+    a.tickets = reinterpret_cast<uint32_t *>(u.status.as<char>() + 128);
+    a.stream_off = u.stream_off.as<int64_t>();
+    a.lag_val = u.lag.as<Real>();
+    a.psi_b = Real(0);
+    a.grab = u.n_chunks < (int64_t)1000000 ? 1 : 2;
+    a.nap = 1;
+    a.backoff = 3;
+    a.watchdog_ticks = watchdog_ticks();
+    a.stamps = nullptr;
+    a.n_groups = 1;
+    a.gs_pos = u.A;
+    a.gs_den = a.stride;
+    a.gs_lag = u.LG;
+    a.rows = u.rows.as<DirRow>();
+    a.active = active;
+    const int wpb = waves_per_block > 0 ? std::min(16, waves_per_block) : 5;
+    int64_t waves = (int64_t)u.n_cu * wpb;
+    const int64_t need = std::max<int64_t>(1, u.n_chunks);
+    if (waves > need) waves = (need + wpb - 1) / wpb * wpb;
+    const int blocks = (int)std::max<int64_t>(waves / wpb, kStreams);
+    k_reset_tickets<<<1, 64, 0, s>>>(a.tickets);
+    JSW_HIP(hipGetLastError());
+    void *args[] = {&a};
+    JSW_HIP(hipLaunchKernel(sweep_kernel_t<Real>(u.ns, false), dim3(blocks), dim3(64 * wpb), args, 0, s));
+}
+
+void UnionSweep::launch(const int32_t *active, int waves_per_block, hipStream_t s) {
+    if (!n_chunks) return;
+    if (fp32) union_launch<float>(*this, active, waves_per_block, s);
+    else union_launch<double>(*this, active, waves_per_block, s);
+}
+
+int UnionSweep::check_status(hipStream_t s) {
+    int32_t st = 0;
+    JSW_HIP(hipMemcpyAsync(&st, status.p, 4, hipMemcpyDeviceToHost, s));
+    JSW_HIP(hipStreamSynchronize(s));
+    if (st == 0) return JSWEEP_OK;
+    pos_state[0] = pos_state[1] = 0;
+    JSW_HIP(hipMemsetAsync(status.p, 0, 64, s));
+    JSW_HIP(hipStreamSynchronize(s));
+    set_last_error(st & kStatusPlacement ? "a batched sweep workgroup ran on another XCD than its stream"
+                                         : "a batched sweep wavefront's watchdog fired");
+    return (st & kStatusPlacement) ? JSWEEP_E_PLACEMENT : JSWEEP_E_STALLED;
+}
+
+UnionSweep &union_for(int n, Graph *const *graphs, bool fp32, hipStream_t s) {
+    std::vector<uint64_t> key(n + 1);
+    for (int i = 0; i < n; ++i) key[i] = (graphs[i]->uid << 24) | (graphs[i]->prog_version & 0xffffffu);
+    key[n] = fp32 ? 1 : 0;
+    std::lock_guard<std::mutex> lock(g_union_mu);
+    std::unique_ptr<UnionSweep> &slot = g_union[fp32 ? 1 : 0];
+    if (!slot || slot->key != key) {
+        slot.reset();   // free the old one first
+        auto u = std::make_unique<UnionSweep>();
+        u->build(n, graphs, fp32, s);
+        u->key = key;
+        slot = std::move(u);
+    }
+    return *slot;
 }
 
 }  // namespace jsw

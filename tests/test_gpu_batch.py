@@ -37,16 +37,38 @@ def test_batch_fp64_matches_oracle_after_20_iterations(ensemble):
         assert e1 <= 1e-12 and e2 <= 1e-12
 
 
-def test_batch_fp64_plain_direction_kernel(ensemble):
+@pytest.mark.parametrize("strategy", [J.JSWEEP_STRATEGY_DIRECTION, J.JSWEEP_STRATEGY_DIRECTION_LDS,
+                                      J.JSWEEP_STRATEGY_DATA_DRIVEN])
+def test_batch_fp64_each_sweep_kernel(ensemble, strategy):
+    """The batched direction kernels (plain and LDS-window) and the union of
+    the instances' work lists in one data-driven launch."""
     probs = _problems(ensemble)
     stats = J.solve_batch([g for _, _, g in ensemble], probs, mode=J.JSWEEP_FP64, tol=0.0, max_iter=5,
-                          params=J.Params(strategy=J.JSWEEP_STRATEGY_DIRECTION), allow_not_converged=True)
+                          params=J.Params(strategy=strategy), allow_not_converged=True)
     for (p, og, _), pr, st in zip(ensemble, probs, stats):
         psi_ref, phi_ref, _ = og.source_iteration(p.sigma_t, p.sigma_s, p.q, p.weight, 5)
         e1, e2 = rel_max(host(pr["phi"]), phi_ref), rel_max(host(pr["psi"]), psi_ref)
-        print(f"[batch64 dir] {p.name} phi {e1:.2e} psi {e2:.2e}", flush=True)
+        print(f"[batch64 s{strategy}] {p.name} phi {e1:.2e} psi {e2:.2e}", flush=True)
         assert st["sweeps"] == 5
         assert e1 <= 1e-12 and e2 <= 1e-12
+
+
+def test_batch_data_driven_partial_convergence_and_boundary(ensemble):
+    """Union sweep with instances converging at different iterations (the
+    chunks of a converged instance only empty their entries) and boundary
+    inflow per instance: each instance's result equals its own solve."""
+    probs = _problems(ensemble)
+    for k, pr in enumerate(probs):
+        pr["psi_boundary"] = 0.1 * k
+    stats = J.solve_batch([g for _, _, g in ensemble], probs, mode=J.JSWEEP_FP64, tol=1e-9, max_iter=2000,
+                          params=J.Params(strategy=J.JSWEEP_STRATEGY_DATA_DRIVEN))
+    sweeps = [st["sweeps"] for st in stats]
+    print(f"[batch64 union tol] sweeps {sweeps}", flush=True)
+    assert len(set(sweeps)) > 1
+    for k, ((p, og, g), pr, st) in enumerate(zip(ensemble, probs, stats)):
+        psi_ref, phi_ref, hist = og.source_iteration(p.sigma_t, p.sigma_s, p.q, p.weight, st["sweeps"], psi_b=0.1 * k)
+        assert rel_max(host(pr["phi"]), phi_ref) <= 1e-12, p.name
+        assert st["residual"] <= 1e-9 and abs(st["residual"] - hist[-1]) <= 1e-6 * hist[-1]
 
 
 def test_batch_refined_converges_to_oracle(ensemble):
@@ -75,7 +97,10 @@ def test_autotune_and_tuned_solve(ensemble):
     _, phi_ref, _ = og.source_iteration(p.sigma_t, p.sigma_s, p.q, p.weight, 5)
     assert rel_max(host(phi), phi_ref) <= 1e-12
     prm_b = J.autotune([g for _, _, g in ensemble], J.JSWEEP_FP32_REFINED)
-    assert prm_b.as_dict()["strategy"] in (J.JSWEEP_STRATEGY_DIRECTION, J.JSWEEP_STRATEGY_DIRECTION_LDS)
+    # batches: the direction kernels, or the default hybrid (AUTO: the union
+    # launch while most of the batch iterates)
+    assert prm_b.as_dict()["strategy"] in (J.JSWEEP_STRATEGY_DIRECTION, J.JSWEEP_STRATEGY_DIRECTION_LDS,
+                                           J.JSWEEP_STRATEGY_AUTO)
 
 
 def test_warm_start_boundary_and_not_converged(ensemble):
@@ -147,7 +172,9 @@ def test_full_ensemble_256():
         sols = {}
         for label, mode, prm in (("fp64", J.JSWEEP_FP64, tuned), ("refined", J.JSWEEP_FP32_REFINED, tuned),
                                  ("refined_plain", J.JSWEEP_FP32_REFINED,
-                                  J.Params(strategy=J.JSWEEP_STRATEGY_DIRECTION))):
+                                  J.Params(strategy=J.JSWEEP_STRATEGY_DIRECTION)),
+                                 ("refined_union", J.JSWEEP_FP32_REFINED,
+                                  J.Params(strategy=J.JSWEEP_STRATEGY_DATA_DRIVEN))):
             pr = problems()
             st = J.solve_batch(gs, pr, mode=mode, tol=1e-11, max_iter=20000, params=prm)
             sols[label] = [host(x["phi"]) for x in pr]
@@ -159,7 +186,7 @@ def test_full_ensemble_256():
                 print(f"[ensemble] {label} instance {i}: sweeps {st[i]['sweeps']} rho {st[i]['residual']:.2e} "
                       f"phi vs oracle {err:.2e}", flush=True)
                 assert err <= 1e-8, (label, i)
-        for label in ("refined", "refined_plain"):
+        for label in ("refined", "refined_plain", "refined_union"):
             worst = max(float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(sols[label], sols["fp64"]))
             print(f"[ensemble] {label} vs fp64: worst instance phi rel {worst:.2e}", flush=True)
             assert worst <= 1e-8
