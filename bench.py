@@ -254,12 +254,20 @@ def ensemble_bench(J, W, torch, steps=5):
     pr = problems()
     J.solve_batch(gs, pr, mode=J.JSWEEP_FP64, tol=0.0, max_iter=2, params=tuned, allow_not_converged=True)
     torch.cuda.synchronize()
+    J.jsweep_profile(gs[0], True)      # the batch's data-driven launches are recorded on its first graph
+    J.jsweep_profile_read(gs[0], reset=True)
     a = time.perf_counter()
     J.solve_batch(gs, pr, mode=J.JSWEEP_FP64, tol=0.0, max_iter=steps, params=tuned, allow_not_converged=True)
     torch.cuda.synchronize()
     step = (time.perf_counter() - a) / steps
+    launches, kms = J.jsweep_profile_read(gs[0], reset=True)
+    J.jsweep_profile(gs[0], False)
     out["fp64_step_ms"] = step * 1e3
     out["fp64_updates_per_s"] = upd / step
+    if launches:
+        edges = sum(interior_edges(J, g, p.n_dirs) for g, p in zip(gs, ps))
+        out["roofline"] = roofline((upd + edges) * 8, kms / launches,
+                                   "k_sweep<double> union of the 256-instance ensemble", launches, edges)
     ttt, ref = {}, None
     for name, mode in (("fp64", J.JSWEEP_FP64), ("fp32_refined", J.JSWEEP_FP32_REFINED)):
         # untimed warm-up of the mode (its first use builds the FP32 records

@@ -363,7 +363,8 @@ int jsweep_patch_info(jsweep_graph g, void *hip_stream, int64_t *out);
 
 /* Kernel timing of the sweep launches on a graph: while enabled, the
  * library records a HIP event pair around every launch of the sweep kernel
- * (on the launch stream).  jsweep_profile_read synchronises on those
+ * (on the launch stream); a batched solve's data-driven launches over the
+ * union of its instances are recorded on its first instance's graph.  jsweep_profile_read synchronises on those
  * events and returns the number of launches and their summed duration in
  * milliseconds since the last reset (reset != 0 clears them afterwards). */
 int jsweep_profile(jsweep_graph g, int32_t enable);

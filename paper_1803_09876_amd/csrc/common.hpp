@@ -369,6 +369,7 @@ struct UnionSweep {
     DevBuf uinst, uchunk, isrc, cblk, pcode, pa, pden, stream_off, rows, status, lag, vs;
     DevBuf pos[2];
     int pos_state[2] = {0, 0}, cur = 0;   // element size of the empty markers each array holds (0: none)
+    Graph *prof = nullptr;               // the batch's first graph: its jsweep_profile records the launches
     void build(int n, Graph *const *graphs, bool fp32, hipStream_t s);
     void refresh_den(Graph *const *graphs, hipStream_t s);
     // rows: per instance its cell-order flux array (psi_row base), FP32

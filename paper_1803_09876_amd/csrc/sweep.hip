@@ -260,24 +260,24 @@ __global__ void k_sweep(SweepArgs<Real> a) {
         int64_t cell_k = K;
         const float *src_row = a.src_dir ? a.src_dir + base : nullptr;
         Real psi_b = a.psi_b;
-        bool skip = false;
+        // union of graphs: the direction's first level position and the
+        // instance come with the chunk block (words 67 - 69), so the polls
+        // below need nothing else; the rest of the direction's row (output
+        // and source rows) is only used after them.  Whether the instance
+        // still iterates is loaded together with the first poll.
+        int act_flag = 1;
         if (a.rows) {
+            base = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(P.w2, 4) << 32) |
+                             (uint64_t)(uint32_t)__builtin_amdgcn_readlane(P.w2, 3));
+            const int inst = __builtin_amdgcn_readlane(P.w2, 5);
+            if (a.active) act_flag = a.active[inst];
             const DirRow row = a.rows[m];
-            base = row.pos_base;
             cell_row = static_cast<Real *>(row.psi_row);
             cell_k = K - row.cell_off;
             src_row = row.src_row;
             psi_b = (Real)row.psi_b;
-            skip = a.active && a.active[row.inst] == 0;   // wave-uniform: a chunk has one direction
         }
         const int64_t own = base + pos0 + lane;
-        if (skip) {
-            // a chunk of an inactive instance computes nothing; it only
-            // empties its entries of the next sweep's array (the instance
-            // may be active again then)
-            if (active) __builtin_nontemporal_store(empty_marker<Real>(), a.pos_next + own);
-            active = false;
-        }
         // V s of the cell (one gather from a per-cell array per group; in
         // FP32 V and s, combined with the per-direction source after the
         // poll, so that nothing waits for these loads before it)
@@ -375,6 +375,7 @@ __global__ void k_sweep(SweepArgs<Real> a) {
 #pragma unroll
                 for (int k = 0; k < NX; ++k) ok = ok && !(code_x[k] >= 0 && is_empty(val_x[k]));
             }
+            if (!__builtin_amdgcn_readfirstlane(act_flag)) break;   // an instance that no longer iterates
             if (__all(ok)) break;
             if (spin == 0) t0 = __builtin_amdgcn_s_memrealtime();
             if ((spin & 7) == 7) {
@@ -406,6 +407,13 @@ __global__ void k_sweep(SweepArgs<Real> a) {
         }
         t_ready = (uint32_t)__builtin_amdgcn_s_memrealtime();
         if (request) pend = (int64_t)__builtin_amdgcn_readfirstlane(nxt);
+        if (!__builtin_amdgcn_readfirstlane(act_flag)) {
+            // a chunk of an instance that no longer iterates computes
+            // nothing; it only empties its entries of the next sweep's array
+            // (the instance may iterate again then)
+            if (active) __builtin_nontemporal_store(empty_marker<Real>(), a.pos_next + own);
+            active = false;
+        }
         at_pos = a.psi_pos + own;
         at_cell = cell_row ? cell_row + cell_k : nullptr;
         at_next = a.pos_next + own;
@@ -1410,7 +1418,7 @@ struct UnionSrc {
     const int32_t *pcode;                // its program (ns slots, stride S)
     const void *pa;
     const void *pden;
-    int64_t S, coff, loff;
+    int64_t S, coff, loff, aoff, nc;
     int32_t ns, dir_off;
 };
 
@@ -1425,7 +1433,8 @@ __global__ void k_union_block(const int32_t *uinst, const int32_t *uchunk, const
     const int64_t u = blockIdx.x;
     const int lane = threadIdx.x;
     if (u >= n) return;
-    const UnionSrc r = src[uinst[u]];
+    const int inst = uinst[u];
+    const UnionSrc r = src[inst];
     const int32_t *b = r.cblk + (int64_t)uchunk[u] * kBlock;
     int32_t *o = blk + u * kBlock;
     const int32_t K = b[lane];
@@ -1436,6 +1445,14 @@ __global__ void k_union_block(const int32_t *uinst, const int32_t *uchunk, const
     }
     if (lane == 1) o[65] = 0;
     if (lane == 2) o[66] = b[66];
+    // the direction's first level position in the union (lo, hi) and the
+    // instance: what the sweep needs before its polls
+    if (lane == 3 || lane == 4) {
+        const int m = (int)((uint32_t)b[64] & 0xffffu);
+        const uint64_t pb = (uint64_t)(r.aoff + (int64_t)m * r.nc);
+        o[67 + lane - 3] = (int32_t)(uint32_t)(lane == 3 ? pb : pb >> 32);
+    }
+    if (lane == 5) o[69] = (int32_t)inst;
 }
 
 // program of union chunk u: codes (lagged-edge codes moved to the union's
@@ -1492,6 +1509,8 @@ static std::vector<UnionSrc> union_sources(const UnionSweep &u, Graph *const *gr
         r.S = 64 * g.n_chunks;
         r.coff = u.coff[i];
         r.loff = u.loff[i];
+        r.aoff = u.aoff[i];
+        r.nc = g.nc;
         r.ns = g.ns;
         r.dir_off = u.dir_off[i];
     }
@@ -1618,6 +1637,7 @@ void UnionSweep::refresh_den(Graph *const *graphs, hipStream_t s) {
 
 void UnionSweep::set_rows(Graph *const *graphs, void *const *psi, const float *const *src_dir, const double *psi_b,
                           hipStream_t s) {
+    prof = graphs[0];
     std::vector<DirRow> h(std::max(1, total_dirs));
     const size_t word = fp32 ? 4 : 8;
     for (int i = 0; i < n; ++i) {
@@ -1689,8 +1709,23 @@ static void union_launch(UnionSweep &u, const int32_t *active, int waves_per_blo
     const int blocks = (int)std::max<int64_t>(waves / wpb, kStreams);
     k_reset_tickets<<<1, 64, 0, s>>>(a.tickets);
     JSW_HIP(hipGetLastError());
+    // kernel timing: recorded on the first instance's graph when its
+    // profiling is on (not while a HIP graph is being recorded)
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    JSW_HIP(hipStreamIsCapturing(s, &cap));
+    const bool prof = u.prof && u.prof->profile && cap == hipStreamCaptureStatusNone;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (prof) {
+        JSW_HIP(hipEventCreate(&ev0));
+        JSW_HIP(hipEventCreate(&ev1));
+        JSW_HIP(hipEventRecord(ev0, s));
+    }
     void *args[] = {&a};
     JSW_HIP(hipLaunchKernel(sweep_kernel_t<Real>(u.ns, false), dim3(blocks), dim3(64 * wpb), args, 0, s));
+    if (prof) {
+        JSW_HIP(hipEventRecord(ev1, s));
+        u.prof->prof_events.push_back({ev0, ev1});
+    }
 }
 
 void UnionSweep::launch(const int32_t *active, int waves_per_block, hipStream_t s) {
