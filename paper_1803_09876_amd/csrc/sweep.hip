@@ -682,9 +682,11 @@ static const void *sweep_kernel(const Graph &g, bool fp32, bool trace = false, i
 constexpr int kMaxSweepBlocksPerCU = 4;
 
 int persistent_waves(Graph &g, bool fp32, const jsweep_params *p, int *waves_per_block, int groups) {
-    // default (measured on 0.3M- to 6.6M-chunk graphs): one workgroup of
-    // five wavefronts per CU, six for FP32 sweeps above a million chunks
-    const int wpb_default = fp32 && g.n_chunks >= (int64_t)1000000 ? 6 : 5;
+    // default (measured on 0.3M- to 6.6M-chunk graphs): one workgroup per
+    // CU, of eight wavefronts for graphs above a million chunks (more
+    // requests in flight; ten or more poll more than they gain), of five
+    // below
+    const int wpb_default = g.n_chunks >= (int64_t)1000000 ? 8 : 5;
     int wpb = (p && p->waves_per_block > 0) ? p->waves_per_block
               : (g.has_tuned && g.tuned.waves_per_block > 0 ? g.tuned.waves_per_block : wpb_default);
     if (wpb > 16) wpb = 16;
@@ -812,10 +814,11 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
     a.tickets = reinterpret_cast<uint32_t *>(g.status.as<char>() + 128);
     a.stream_off = g.stream_off.as<int64_t>();
     // defaults (measured): one chunk per ticket for graphs of a few hundred
-    // thousand chunks, where the critical path dominates; two for larger ones
+    // thousand chunks, where the critical path dominates; three for graphs
+    // above a million chunks
     a.grab = (p && p->chunks_per_ticket > 0) ? p->chunks_per_ticket
              : (g.has_tuned && g.tuned.chunks_per_ticket > 0 ? g.tuned.chunks_per_ticket
-                                                              : (g.n_chunks < (int64_t)1000000 ? 1 : 2));
+                                                              : (g.n_chunks < (int64_t)1000000 ? 1 : 3));
     a.psi_b = psi_b;
     a.watchdog_ticks = watchdog_ticks();
     a.stamps = g.trace ? g.trace_buf.as<uint32_t>() : nullptr;
