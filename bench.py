@@ -339,6 +339,7 @@ def main():
                     help="only the time-to-1e-8 solves (FP64 and FP32-refined) of the workload; one JSON line")
     ap.add_argument("--ensemble-only", action="store_true",
                     help="only the 256-instance batched solve (for profiling the batch kernels)")
+    ap.add_argument("--priority-list", default="", help="with --priorities: comma-separated names to time")
     ap.add_argument("--priorities", action="store_true",
                     help="only the FP64 sweep kernel time of the workload under every work-list priority "
                          "(BFS, LDCP, SLBD, each also angle-major); one JSON line")
@@ -382,24 +383,32 @@ def main():
         return
     if args.priorities:
         res = {}
-        names = {J.JSWEEP_PRIORITY_BFS: "BFS", J.JSWEEP_PRIORITY_LDCP: "LDCP", J.JSWEEP_PRIORITY_SLBD: "SLBD"}
-        for am in (0, J.JSWEEP_PRIORITY_ANGLE_MAJOR):
-            for base in (J.JSWEEP_PRIORITY_BFS, J.JSWEEP_PRIORITY_LDCP, J.JSWEEP_PRIORITY_SLBD):
-                pr = base | am
-                t = time.time()
-                J.set_params(g, J.Params(priority=pr))
-                t_order = time.time() - t
-                J.solve(g, st, ss, q, phi, psi, mode=J.JSWEEP_FP64, tol=0.0, max_iter=max(1, args.warmup),
-                        allow_not_converged=True)
-                J.jsweep_profile(g, True)
-                J.jsweep_profile_read(g, reset=True)
-                J.solve(g, st, ss, q, phi, psi, mode=J.JSWEEP_FP64, tol=0.0, max_iter=args.steps,
-                        allow_not_converged=True)
-                n, ms = J.jsweep_profile_read(g, reset=True)
-                J.jsweep_profile(g, False)
-                key = names[base] + ("+angle-major" if am else "")
-                res[key] = {"fp64_sweep_ms": ms / max(1, n), "reorder_s": t_order}
-                log(f"priority {key}: {res[key]}")
+        names = {J.JSWEEP_PRIORITY_BFS: "BFS", J.JSWEEP_PRIORITY_LDCP: "LDCP", J.JSWEEP_PRIORITY_SLBD: "SLBD",
+                 J.JSWEEP_PRIORITY_PACED: "PACED"}
+        plist = [(names[b] + ("+angle-major" if am else ""), b | am)
+                 for am in (0, J.JSWEEP_PRIORITY_ANGLE_MAJOR) for b in names]
+        plist += [(f"BFS+C=L/{k}", J.JSWEEP_PRIORITY_BFS | J.JSWEEP_PRIORITY_ANGLE_WEIGHT(k)) for k in range(1, 8)]
+        plist += [(f"LDCP+C=L/{k}", J.JSWEEP_PRIORITY_LDCP | J.JSWEEP_PRIORITY_ANGLE_WEIGHT(k)) for k in (2, 3)]
+        plist += [(f"PACED+C=L/{k}", J.JSWEEP_PRIORITY_PACED | J.JSWEEP_PRIORITY_ANGLE_WEIGHT(k)) for k in (5, 7)]
+        if args.priority_list:
+            keep = set(args.priority_list.split(","))
+            plist = [x for x in plist if x[0] in keep]
+        for key, pr in plist:
+            t = time.time()
+            J.set_params(g, J.Params(priority=pr))
+            t_order = time.time() - t
+            J.solve(g, st, ss, q, phi, psi, mode=J.JSWEEP_FP64, tol=0.0, max_iter=max(1, args.warmup),
+                    allow_not_converged=True)
+            J.jsweep_profile(g, True)
+            J.jsweep_profile_read(g, reset=True)
+            J.solve(g, st, ss, q, phi, psi, mode=J.JSWEEP_FP64, tol=0.0, max_iter=args.steps,
+                    allow_not_converged=True)
+            n, ms = J.jsweep_profile_read(g, reset=True)
+            J.jsweep_profile(g, False)
+            ms32, _ = fp32_sweep_ms(J, torch, g, st, ss, q, nc, args.warmup, args.steps)
+            res[key] = {"priority": pr, "fp64_sweep_ms": ms / max(1, n), "fp32_sweep_ms": ms32,
+                        "reorder_s": t_order}
+            log(f"priority {key}: {res[key]}")
         J.set_params(g, None)
         print(json.dumps({"workload": p.name, "priorities": res}))
         return

@@ -90,21 +90,40 @@ extern "C" {
  * would release them (Kahn's algorithm on the chunk graph, ties broken by
  * level order).  Every order is topological, so every priority gives
  * bit-identical fluxes; only the schedule changes.
- *   BFS   breadth first: level, then direction (the default);
+ *   BFS   breadth first: level, then direction;
  *   LDCP  longest distance on the critical path: the longest chunk path to
  *         a sink of the graph first;
  *   SLBD  shortest local boundary distance: the chunk with the shortest
  *         such path (closest to the outflow boundary) first, a depth-first
  *         variant;
+ *   PACED level / (the direction's level count): every direction of a
+ *         stream reaches its last level at the end of the stream, the
+ *         deepest ones in more, smaller steps (with BFS the deepest
+ *         direction of a stream runs alone at the end, with LDCP at the
+ *         start); a pacing of the paper's BFS by each angle's critical path
+ *         (the default);
  *   ANGLE_MAJOR (OR-ed with one of the above): prior(a) * C + prior(p) with
  *         a large C, i.e. the chunk's direction ranks first (ascending), the
  *         strategy only among chunks of one direction.
- * With a priority other than BFS the DIRECTION_LDS strategy is not used
- * (its program lookup needs each level's chunks together). */
+ *   ANGLE_WEIGHT(k) (OR-ed with one of the above, k = 1..7, not with
+ *         ANGLE_MAJOR): the same combined rank with a finite C, the largest
+ *         level count of the stream's directions divided by k (rounded up);
+ *         prior(a) is the direction's rank in its stream (streams hold
+ *         contiguous direction ranges) and prior(p) the strategy's key (for
+ *         BFS the level).  About k directions of a stream are then under
+ *         way at once, each in a different phase of its sweep: fewer sweep
+ *         fronts at a time than BFS across all directions, so the scattered
+ *         per-cell reads stay in cache, with more parallelism than one
+ *         direction at a time.
+ * With a priority other than BFS or PACED the DIRECTION_LDS strategy is not
+ * used (its program lookup needs each level's chunks together). */
 #define JSWEEP_PRIORITY_BFS 1
 #define JSWEEP_PRIORITY_LDCP 2
 #define JSWEEP_PRIORITY_SLBD 3
+#define JSWEEP_PRIORITY_PACED 4
 #define JSWEEP_PRIORITY_ANGLE_MAJOR 0x10
+#define JSWEEP_PRIORITY_ANGLE_WEIGHT(k) (((uint32_t)(k) & 7u) << 5)
+#define JSWEEP_PRIORITY_ANGLE_WEIGHT_OF(p) ((int)(((uint32_t)(p) >> 5) & 7u))
 
 /* ---- solve modes ---------------------------------------------------- */
 #define JSWEEP_FP64 0              /* FP64 source iteration */
@@ -205,7 +224,7 @@ typedef struct {
  * iterate.  With JSWEEP_DEBUG_NO_LAG a cycle is an error instead.
  *
  * mesh, quad: host pointers (copied).  flags: JSWEEP_DEBUG_NO_LAG, and a
- * work-list priority as JSWEEP_PRIORITY_FLAGS(p) (default BFS).
+ * work-list priority as JSWEEP_PRIORITY_FLAGS(p) (default PACED).
  * out: receives the handle (NULL on error).
  * Errors: E_INVALID_ARG, E_MESH, E_QUADRATURE, E_CYCLE, E_DEVICE, E_OOM.
  * Limits: n_cells * faces_per_cell < 2^31; 3D meshes need n_vertices < 2^21

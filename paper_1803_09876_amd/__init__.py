@@ -36,8 +36,14 @@ JSWEEP_WARM_START = 0x100
 JSWEEP_STRATEGY_AUTO, JSWEEP_STRATEGY_DATA_DRIVEN, JSWEEP_STRATEGY_DIRECTION = 0, 1, 2
 JSWEEP_STRATEGY_DIRECTION_LDS = 3
 JSWEEP_STRATEGY_PATCH = 4
-JSWEEP_PRIORITY_BFS, JSWEEP_PRIORITY_LDCP, JSWEEP_PRIORITY_SLBD = 1, 2, 3
+JSWEEP_PRIORITY_BFS, JSWEEP_PRIORITY_LDCP, JSWEEP_PRIORITY_SLBD, JSWEEP_PRIORITY_PACED = 1, 2, 3, 4
 JSWEEP_PRIORITY_ANGLE_MAJOR = 0x10
+
+
+def JSWEEP_PRIORITY_ANGLE_WEIGHT(k: int) -> int:
+    """Priority bits of the finite angle weight C = (largest level count of
+    a stream) / k, k = 1..7 (OR-ed with BFS, LDCP or SLBD)."""
+    return (int(k) & 7) << 5
 
 
 def JSWEEP_PRIORITY_FLAGS(p: int) -> int:

@@ -200,7 +200,7 @@ struct Graph {
     uint32_t prog_version = 0;           // bumped whenever the work list or program is rebuilt
     int device = 0;
     int n_cu = 0;
-    int priority = JSWEEP_PRIORITY_BFS;  // order of the work list (JSWEEP_PRIORITY_*)
+    int priority = JSWEEP_PRIORITY_PACED;  // order of the work list (JSWEEP_PRIORITY_*)
     int dim = 3, ctype = JSWEEP_TET, nfpc = 4;
     int64_t nv = 0, nc = 0, nf = 0;
     int nd = 0;
@@ -273,6 +273,11 @@ struct Graph {
 // build steps (geometry.hip, dag.hip)
 void build_geometry(Graph &g, const jsweep_mesh &mesh, hipStream_t s);
 void build_dag(Graph &g, bool lag_cycles, hipStream_t s);
+// whether the work list keeps the chunks of every (direction, level)
+// together (what the LDS-window kernels read a level's program from)
+inline bool levels_contiguous(const Graph &g) {
+    return g.priority == JSWEEP_PRIORITY_BFS || g.priority == JSWEEP_PRIORITY_PACED;
+}
 // reorder the work list by a priority (JSWEEP_PRIORITY_*), rebuilding what
 // is kept in chunk order
 void set_priority(Graph &g, int priority, hipStream_t s);

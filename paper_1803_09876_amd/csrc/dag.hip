@@ -775,9 +775,13 @@ static void dag_impl(Graph &g, bool lag_cycles, hipStream_t s) {
     JSW_HIP(hipMemcpyAsync(g.lvl_off_d.p, g.lvl_off_h.data(), 8 * g.lvl_off_h.size(), hipMemcpyHostToDevice, s));
     // sweep work list: chunks of <= 64 cells of one (level, direction).
     // Directions are dealt to kStreams streams in contiguous blocks (with
-    // octant-major quadratures a block is an octant); within a stream the
-    // chunks are ordered by level, then direction -- a topological order of
-    // every direction of the stream at once.
+    // octant-major quadratures a block is an octant).  Within a stream the
+    // (direction, level) groups of chunks follow the PACED priority: level
+    // divided by the direction's level count, then level, then direction.
+    // The key grows along every edge of a direction, so the order is
+    // topological for every direction of the stream at once, and the
+    // deepest direction is spread over the whole stream instead of running
+    // alone at its end (as in level-then-direction order).
     g.dir_stream_h.resize(g.nd);
     for (int m = 0; m < g.nd; ++m) g.dir_stream_h[m] = (int32_t)(((int64_t)m * kStreams) / g.nd);
     std::vector<Chunk> ch;
@@ -785,21 +789,34 @@ static void dag_impl(Graph &g, bool lag_cycles, hipStream_t s) {
     g.stream_off_h.assign(kStreams + 1, 0);
     g.lvl_chunk_h.assign(g.lvl_ptr_h.size(), 0);
     g.max_w = g.max_w2 = 0;
+    struct Group {
+        int64_t key;
+        int32_t L, m;
+    };
+    std::vector<Group> grp;
     for (int sidx = 0; sidx < kStreams; ++sidx) {
         g.stream_off_h[sidx] = (int64_t)ch.size();
-        for (int L = 0; L < g.max_levels; ++L)
-            for (int m = 0; m < g.nd; ++m) {
-                if (g.dir_stream_h[m] != sidx || L >= g.nlev_h[m]) continue;
-                const int64_t *p = g.lvl_ptr_h.data() + g.lvl_off_h[m];
-                g.lvl_chunk_h[g.lvl_off_h[m] + L] = (int32_t)ch.size();
-                g.max_w = std::max(g.max_w, p[L + 1] - p[L]);
-                g.max_w2 = std::max(g.max_w2, p[L + 1] - (L > 0 ? p[L - 1] : p[L]));
-                for (int64_t o = p[L]; o < p[L + 1]; o += 64) {
-                    int64_t c = std::min<int64_t>(64, p[L + 1] - o);
-                    ch.push_back(Chunk{(uint32_t)m | ((uint32_t)(c - 1) << 16), (uint32_t)o});
-                }
+        grp.clear();
+        for (int m = 0; m < g.nd; ++m)
+            if (g.dir_stream_h[m] == sidx)
+                for (int L = 0; L < g.nlev_h[m]; ++L) grp.push_back(Group{((int64_t)L << 32) / g.nlev_h[m], L, m});
+        std::sort(grp.begin(), grp.end(), [](const Group &x, const Group &y) {
+            if (x.key != y.key) return x.key < y.key;
+            return x.L != y.L ? x.L < y.L : x.m < y.m;
+        });
+        for (const Group &gr : grp) {
+            const int L = gr.L, m = gr.m;
+            const int64_t *p = g.lvl_ptr_h.data() + g.lvl_off_h[m];
+            g.lvl_chunk_h[g.lvl_off_h[m] + L] = (int32_t)ch.size();
+            g.max_w = std::max(g.max_w, p[L + 1] - p[L]);
+            g.max_w2 = std::max(g.max_w2, p[L + 1] - (L > 0 ? p[L - 1] : p[L]));
+            for (int64_t o = p[L]; o < p[L + 1]; o += 64) {
+                int64_t c = std::min<int64_t>(64, p[L + 1] - o);
+                ch.push_back(Chunk{(uint32_t)m | ((uint32_t)(c - 1) << 16), (uint32_t)o});
             }
+        }
     }
+    g.priority = JSWEEP_PRIORITY_PACED;
     g.stream_off_h[kStreams] = (int64_t)ch.size();
     g.n_chunks = (int64_t)ch.size();
     if (g.n_chunks >= ((int64_t)1 << 31)) fail(JSWEEP_E_INVALID_ARG, "too many sweep chunks");
@@ -840,20 +857,51 @@ static void dag_impl(Graph &g, bool lag_cycles, hipStream_t s) {
 //   LDCP  the longest chunk path from the chunk to a sink, longest first;
 //   SLBD  the same distance, shortest first (the chunk closest to the
 //         outflow boundary of its direction: depth first);
-//   ANGLE_MAJOR (OR-ed) the chunk's direction first, ascending.
+//   PACED the level divided by the direction's level count: every
+//         direction of a stream takes the whole stream to reach its last
+//         level, the deepest ones in proportionally more, shorter steps,
+//         instead of all starting together (BFS: the deepest direction of
+//         the stream ends alone) or the deepest first (LDCP: it starts
+//         alone);
+//   ANGLE_MAJOR (OR-ed) the chunk's direction first, ascending;
+//   ANGLE_WEIGHT(k) (OR-ed, k = 1..7) the paper's combined rank
+//         prior(a) * C + prior(p) with a finite C: prior(a) is the
+//         direction's rank in its stream, prior(p) the strategy's key (the
+//         level for BFS) and C the stream's largest level count divided by
+//         k, rounded up.  Direction r then starts about r / k of a sweep
+//         after the stream's first one, so about k directions of a stream
+//         are under way at any time, each in another phase of its sweep
+//         (C = 0 is BFS across the directions, an unbounded C ANGLE_MAJOR).
+//         Fewer directions at once means fewer sweep fronts, whose cells'
+//         V s gathers then stay in the XCD's L2.
 // Any topological order gives bit-identical fluxes (each flux is a pure
 // function of its upwind fluxes); only the schedule changes.
 // ---------------------------------------------------------------------------
 static std::vector<int64_t> priority_order(const std::vector<Chunk> &ch, const std::vector<int32_t> &dptr,
                                            const std::vector<int32_t> &dep, const std::vector<int64_t> &stream_off,
-                                           int priority) {
+                                           const std::vector<int32_t> &lev_of, const std::vector<int32_t> &dir_stream,
+                                           const std::vector<int32_t> &nlev, int priority) {
     const int64_t n = (int64_t)ch.size();
     const int base = priority & 0xf;
     const bool angle = (priority & JSWEEP_PRIORITY_ANGLE_MAJOR) != 0;
+    const int weight_k = JSWEEP_PRIORITY_ANGLE_WEIGHT_OF(priority);
+    // per direction: rank within its stream; per stream: C
+    const int nd = (int)dir_stream.size();
+    std::vector<int64_t> rank(nd, 0), cw(kStreams, 0);
+    {
+        std::vector<int64_t> seen(kStreams, 0), maxlev(kStreams, 0);
+        for (int m = 0; m < nd; ++m) {
+            const int sidx = dir_stream[m];
+            rank[m] = seen[sidx]++;
+            maxlev[sidx] = std::max<int64_t>(maxlev[sidx], nlev[m]);
+        }
+        if (weight_k > 0)
+            for (int sidx = 0; sidx < kStreams; ++sidx) cw[sidx] = (maxlev[sidx] + weight_k - 1) / weight_k;
+    }
     // longest path (in chunks) to a sink: chunks are in a topological order,
     // so one reverse pass settles every chunk before its upwind chunks
     std::vector<int32_t> bl(n, 0);
-    if (base != JSWEEP_PRIORITY_BFS)
+    if (base == JSWEEP_PRIORITY_LDCP || base == JSWEEP_PRIORITY_SLBD)
         for (int64_t c = n - 1; c >= 0; --c)
             for (int32_t k = dptr[c]; k < dptr[c + 1]; ++k) bl[dep[k]] = std::max(bl[dep[k]], bl[c] + 1);
     // downstream lists and counts of upwind chunks
@@ -873,8 +921,17 @@ static std::vector<int64_t> priority_order(const std::vector<Chunk> &ch, const s
         bool operator>(const Key &o) const { return a != o.a ? a > o.a : b != o.b ? b > o.b : c > o.c; }
     };
     auto key = [&](int64_t c) {
-        const int64_t m = angle ? (int64_t)(ch[c].a & 0xffffu) : 0;
-        const int64_t k = base == JSWEEP_PRIORITY_LDCP ? -(int64_t)bl[c] : base == JSWEEP_PRIORITY_SLBD ? bl[c] : 0;
+        const int dm = (int)(ch[c].a & 0xffffu);
+        const int64_t m = angle ? (int64_t)dm : 0;
+        int64_t k = base == JSWEEP_PRIORITY_LDCP ? -(int64_t)bl[c] : base == JSWEEP_PRIORITY_SLBD ? bl[c] : 0;
+        if (base == JSWEEP_PRIORITY_PACED) k = ((int64_t)lev_of[c] << 32) / std::max(1, nlev[dm]);
+        if (weight_k > 0) {
+            // finite angle weight: BFS ranks by level, the others by their
+            // key (PACED's in level units)
+            if (base == JSWEEP_PRIORITY_BFS) k = lev_of[c];
+            if (base == JSWEEP_PRIORITY_PACED) k = (k * cw[dir_stream[dm]] * weight_k) >> 32;
+            k += rank[dm] * cw[dir_stream[dm]];
+        }
         return Key{m, k, c};
     };
     std::vector<int64_t> order;
@@ -908,11 +965,11 @@ static void reorder_impl(Graph &g, int priority, hipStream_t s) {
     // the level order first (every other order is computed from it, so the
     // result does not depend on the order the graph had before)
     std::vector<int64_t> back(nch);
+    // level of a chunk (all of its vertices share it)
+    std::vector<int32_t> lev_of(nch);
     {
         std::vector<int64_t> lv(nch);
         for (int64_t c = 0; c < nch; ++c) lv[c] = c;
-        // level of a chunk (all of its vertices share it)
-        std::vector<int32_t> lev_of(nch);
         for (int64_t c = 0; c < nch; ++c) {
             const int m = (int)(ch[c].a & 0xffffu);
             const int64_t *p = g.lvl_ptr_h.data() + g.lvl_off_h[m];
@@ -942,11 +999,15 @@ static void reorder_impl(Graph &g, int priority, hipStream_t s) {
             lptr[c + 1] = lptr[c] + (dptr[o + 1] - dptr[o]);
             for (int32_t k = dptr[o], j = lptr[c]; k < dptr[o + 1]; ++k, ++j) ldep[j] = (int32_t)inv[dep[k]];
         }
+        std::vector<int32_t> llev(nch);
+        for (int64_t c = 0; c < nch; ++c) llev[c] = lev_of[back[c]];
         ch.swap(lch);
         dptr.swap(lptr);
         dep.swap(ldep);
+        lev_of.swap(llev);
     }
-    const std::vector<int64_t> order = priority_order(ch, dptr, dep, g.stream_off_h, priority);
+    const std::vector<int64_t> order =
+        priority_order(ch, dptr, dep, g.stream_off_h, lev_of, g.dir_stream_h, g.nlev_h, priority);
     std::vector<Chunk> out(nch);
     for (int64_t c = 0; c < nch; ++c) out[c] = ch[order[c]];
     // first chunk (in the new order) of every (direction, level)
@@ -981,8 +1042,11 @@ static void reorder_impl(Graph &g, int priority, hipStream_t s) {
 
 void set_priority(Graph &g, int priority, hipStream_t s) {
     const int base = priority & 0xf;
-    if ((priority & ~(0xf | JSWEEP_PRIORITY_ANGLE_MAJOR)) || base < JSWEEP_PRIORITY_BFS || base > JSWEEP_PRIORITY_SLBD)
+    if ((priority & ~(0xf | JSWEEP_PRIORITY_ANGLE_MAJOR | JSWEEP_PRIORITY_ANGLE_WEIGHT(7))) ||
+        base < JSWEEP_PRIORITY_BFS || base > JSWEEP_PRIORITY_PACED)
         fail(JSWEEP_E_INVALID_ARG, "unknown work-list priority");
+    if ((priority & JSWEEP_PRIORITY_ANGLE_MAJOR) && JSWEEP_PRIORITY_ANGLE_WEIGHT_OF(priority))
+        fail(JSWEEP_E_INVALID_ARG, "ANGLE_MAJOR and a finite angle weight exclude each other");
     if (priority == g.priority || !g.n_chunks) {
         g.priority = priority;
         return;

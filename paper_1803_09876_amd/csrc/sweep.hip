@@ -1113,8 +1113,8 @@ __global__ void __launch_bounds__(kBRingThreads) k_sweep_batch_ring(const RingAr
 static int ring_items(const Graph &g, bool f32) {
     const int64_t R = f32 ? ring_size<float>() : ring_size<double>();
     // the ring reads a level's program from its consecutive chunks, which
-    // only the level-order (BFS) work list keeps together
-    if (g.priority != JSWEEP_PRIORITY_BFS) return 0;
+    // the BFS and PACED work lists keep together
+    if (!levels_contiguous(g)) return 0;
     if (g.max_w2 > R || g.max_levels > kRingMaxLev || g.ns < 1 || g.ns > 6) return 0;
     return (!f32 && g.ns >= 6) ? 1 : 2;
 }
@@ -1353,7 +1353,7 @@ void BatchSweep::setup(int32_t n, Graph *const *graphs, bool fp32, const void *c
     const int64_t R = fp32 ? bring_size<float>() : bring_size<double>();
     for (int i = 0; i < n && ring; ++i) {
         const Graph &g = *graphs[i];
-        ring = g.n_chunks > 0 && g.priority == JSWEEP_PRIORITY_BFS && g.max_w2 <= R && g.max_levels <= kBRingMaxLev && g.ns >= 1 && g.ns <= kBRingNS;
+        ring = g.n_chunks > 0 && levels_contiguous(g) && g.max_w2 <= R && g.max_levels <= kBRingMaxLev && g.ns >= 1 && g.ns <= kBRingNS;
     }
     const int T = ring ? kBRingThreads * 2 : (threads_ > 0 ? std::min(1024, std::max(64, threads_)) : 256);
     batch_order(n, graphs, T, task_inst, task_dir, n_tasks, s);

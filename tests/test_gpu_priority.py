@@ -1,5 +1,6 @@
 """GPU: work-list priority strategies (paper Sec. V-D: BFS, LDCP, SLBD and
-the angle-major (patch, angle) ranking prior(a) * C + prior(p)).
+the (patch, angle) ranking prior(a) * C + prior(p), with an unbounded C
+(angle-major) or a finite one, a fraction of the level count).
 
 Every priority must give a topological order of each stream's coarsened
 graph (checked on the traced work list) and, since a flux is a pure
@@ -19,6 +20,11 @@ PRIORITIES = [
     J.JSWEEP_PRIORITY_BFS | J.JSWEEP_PRIORITY_ANGLE_MAJOR,
     J.JSWEEP_PRIORITY_LDCP | J.JSWEEP_PRIORITY_ANGLE_MAJOR,
     J.JSWEEP_PRIORITY_SLBD | J.JSWEEP_PRIORITY_ANGLE_MAJOR,
+    J.JSWEEP_PRIORITY_BFS | J.JSWEEP_PRIORITY_ANGLE_WEIGHT(1),
+    J.JSWEEP_PRIORITY_BFS | J.JSWEEP_PRIORITY_ANGLE_WEIGHT(3),
+    J.JSWEEP_PRIORITY_LDCP | J.JSWEEP_PRIORITY_ANGLE_WEIGHT(2),
+    J.JSWEEP_PRIORITY_PACED,
+    J.JSWEEP_PRIORITY_PACED | J.JSWEEP_PRIORITY_ANGLE_WEIGHT(5),
 ]
 
 
@@ -75,6 +81,27 @@ def test_priority_sweeps_bit_identical(cases, priority):
                 for s in np.unique(stream):
                     key = lev[stream == s].astype(np.int64) * 4096 + d[stream == s]
                     assert (np.diff(key) >= 0).all(), name                # level, then direction
+            if priority == J.JSWEEP_PRIORITY_PACED:
+                # level / (level count of the direction), then level order
+                nlev = np.array([len(J.graph_export(g, m, want=("lvl_ptr",))[2]) - 1 for m in range(p.n_dirs)])
+                for s in np.unique(stream):
+                    ds, ls = d[stream == s].astype(np.int64), lev[stream == s].astype(np.int64)
+                    frac = (ls << 32) // nlev[ds]
+                    assert (np.diff(frac) >= 0).all(), name
+            k = (priority >> 5) & 7
+            if k and priority & 0xf == J.JSWEEP_PRIORITY_BFS:
+                # rank * C + level, C = ceil(max levels of the stream / k):
+                # Kahn's queue releases in this key whenever the key itself
+                # is topological, which it is here (an upwind chunk of the
+                # same direction has a lower level)
+                # (ties of the key go by level, as in the level order)
+                nlev = np.array([len(J.graph_export(g, m, want=("lvl_ptr",))[2]) - 1 for m in range(p.n_dirs)])
+                for s in np.unique(stream):
+                    sd = np.arange(p.n_dirs)[(np.arange(p.n_dirs) * 8) // p.n_dirs == s]
+                    C = -(-nlev[sd].max() // k)
+                    ds, ls = d[stream == s].astype(np.int64), lev[stream == s].astype(np.int64)
+                    key = (((ds - sd[0]) * C + ls) * 100000 + ls) * 4096 + ds
+                    assert (np.diff(key) >= 0).all(), name
             exact = np.array_equal(got, ref)
             print(f"[priority {priority:#x}] {name} chunks {len(d)} sweep rel {rel_max(got, ref):.2e} "
                   f"bitexact {exact}", flush=True)
@@ -117,5 +144,8 @@ def test_priority_through_params_and_back(cases):
         assert np.array_equal(host(psi), ref)
         with pytest.raises(J.JsweepError):
             J.set_params(g, J.Params(priority=7))
+        with pytest.raises(J.JsweepError):
+            J.set_params(g, J.Params(priority=J.JSWEEP_PRIORITY_BFS | J.JSWEEP_PRIORITY_ANGLE_MAJOR |
+                                     J.JSWEEP_PRIORITY_ANGLE_WEIGHT(2)))
     finally:
         g.close()
