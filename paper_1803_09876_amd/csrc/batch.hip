@@ -50,7 +50,7 @@ struct BInst {
     double wsum;                         // sum of the weights
     double *lag64;
     float *lag32;
-    void *vsu;                           // batched data-driven sweep: the instance's V s (FP64) or {V, s}
+    void *vsu;                           // batched data-driven sweep: the instance's V s (FP64 or FP32)
                                          // (FP32) in the union's per-cell array, else null
     void *lagu;                          // and its lagged values in the union's array (FP64 / FP32), else null
     int64_t n_lag, nc;
@@ -137,9 +137,9 @@ __global__ void k_b_zero(const BInst *I, const int64_t *off, int n, int64_t tota
         if (what == 2) b.r32[x] = 0.0f;
         if (x < b.nc) {
             b.dphi[x] = 0.0;
-            const float src = what == 2 ? (float)b.q[x] : 0.0f;
-            b.g32[x] = src;
-            if (b.vsu) static_cast<float2 *>(b.vsu)[x] = make_float2((float)b.vol[x], src);
+            const double src = what == 2 ? b.q[x] : 0.0;
+            b.g32[x] = (float)src;
+            if (b.vsu) static_cast<float *>(b.vsu)[x] = (float)(b.vol[x] * src);
         }
     }
 }
@@ -297,9 +297,9 @@ __global__ void k_b_dphi(const BInst *I, const int64_t *coff, int n, int64_t tot
         const double s = dir_sum(b.w, b.dpsi, b.nc, b.nd, K);
         const double old = b.dphi[K];
         b.dphi[K] = s;
-        const float src = with_q[i] ? (float)(b.q[K] + b.sigma_s[K] * s) : (float)(b.sigma_s[K] * s);
-        b.g32[K] = src;
-        if (b.vsu) static_cast<float2 *>(b.vsu)[K] = make_float2((float)b.vol[K], src);
+        const double src = with_q[i] ? b.q[K] + b.sigma_s[K] * s : b.sigma_s[K] * s;
+        b.g32[K] = (float)src;
+        if (b.vsu) static_cast<float *>(b.vsu)[K] = (float)(b.vol[K] * src);
         ss = b.vol[K] * (s * s);
         const double d = b.sigma_s[K] * (s - old);
         dd = b.vol[K] * (d * d);
@@ -453,7 +453,7 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
         un->set_rows(graphs, psi_sweep.data(), src_dir.data(), psi_b.data(), s);
         for (int i = 0; i < n; ++i) {
             BInst &b = h[i];
-            b.vsu = static_cast<char *>(un->vs.p) + 8 * (size_t)un->coff[i];
+            b.vsu = static_cast<char *>(un->vs.p) + (refined ? 4 : 8) * (size_t)un->coff[i];
             b.lagu = static_cast<char *>(un->lag.p) + (refined ? 4 : 8) * (size_t)un->loff[i];
         }
         JSW_HIP(hipMemcpyAsync(d_inst.p, h.data(), sizeof(BInst) * n, hipMemcpyHostToDevice, s));

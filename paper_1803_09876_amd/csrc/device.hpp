@@ -119,9 +119,11 @@ __device__ inline void dir_sum_pos2(const double *w, const T *pos, const int32_t
 // operator, looping over directions:
 //   phi_K = sum_m w_m psi_{K,m}
 //   r_{K,m} = q_K + sigma_s,K phi_K - (den psi_{K,m} - in_{K,m}) / V_K
-// Returns V_K sum_m w_m r^2 (and writes phi_K).  When r32 != null, r is
-// stored in FP32: at the vertex's level position posi[m nc + K] within
-// direction m, or at m nc + K (cell order) when posi is null.
+// Returns V_K sum_m w_m r^2 (and writes phi_K).  When r32 != null, V_K r
+// (the correction sweep's per-direction source times the cell volume, as
+// the balance takes it) is stored in FP32: at the vertex's level position
+// posi[m nc + K] within direction m, or at m nc + K (cell order) when posi
+// is null.
 template <int NF, int DIM>
 __device__ inline double residual_cell(const CellRec<double, NF, DIM> &r, int64_t K, const double *omega,
                                        const double *w, const double *psi, double q, double sigma_s, double psi_b,
@@ -162,7 +164,7 @@ __device__ inline double residual_cell(const CellRec<double, NF, DIM> &r, int64_
                 const double res = src - (den * own[k] - in) / r.V;
                 if (r32) {
                     const int64_t o = (int64_t)(m + k) * nc;
-                    r32[o + (posi ? (int64_t)posi[o + K] : K)] = (float)res;
+                    r32[o + (posi ? (int64_t)posi[o + K] : K)] = (float)(r.V * res);
                 }
                 cell = cell + w[m + k] * (res * res);
             }

@@ -346,7 +346,7 @@ __global__ void k_qnorm(const double *q, const double *vol, int64_t nc, double *
 template <int CPT, bool POS = false>
 __global__ void k_dphi(const float *dpsi, const int32_t *posi, const double *w, const double *sigma_s,
                        const double *vol, int64_t nc, int nd, const double *q, double *dphi, float *g32,
-                       const int32_t *status, double *acc, double *acc_next, float2 *vs, uint32_t *tickets,
+                       const int32_t *status, double *acc, double *acc_next, float *vs, uint32_t *tickets,
                        const uint64_t *lag_mv, const int32_t *lag_u, int64_t n_lag, float *lag_val, int64_t per_xcd) {
     const int64_t t = xcd_block(per_xcd) * blockDim.x + threadIdx.x;
     if (t == 0) acc[2] = (double)status[0];
@@ -401,9 +401,9 @@ __global__ void k_dphi(const float *dpsi, const int32_t *posi, const double *w, 
             const double s = sum[c];
             const double old = dphi[K];
             dphi[K] = s;
-            const float src = q ? (float)(q[K] + sigma_s[K] * s) : (float)(sigma_s[K] * s);
-            g32[K] = src;
-            vs[K] = make_float2((float)vol[K], src);
+            const double src = q ? q[K] + sigma_s[K] * s : sigma_s[K] * s;
+            g32[K] = (float)src;
+            vs[K] = (float)(vol[K] * src);
             a = a + vol[K] * (s * s);
             const double d = sigma_s[K] * (s - old);
             b = b + vol[K] * (d * d);
@@ -671,7 +671,7 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
                 const int64_t pxcd = xcd_per(ceil_div(g.nc, kB * cpt));
                 dphi_kernel<<<(unsigned)(8 * pxcd), kB, 0, s>>>(
                     dflux, posi, g.weight.as<double>(), sigma_s, g.vol.as<double>(), g.nc, g.nd,
-                    from_zero ? q : nullptr, dphi, g32, g.status.as<int32_t>(), a_cur, a_next, g.vsc.as<float2>(),
+                    from_zero ? q : nullptr, dphi, g32, g.status.as<int32_t>(), a_cur, a_next, g.vsc.as<float>(),
                     tickets, g.lag_mv.as<uint64_t>(), g.lag_u.as<int32_t>(), g.n_lag, g.lag_val32.as<float>(), pxcd);
                 JSW_HIP(hipGetLastError());
                 double h[3];   // norm of dphi, correction residual, sweep status

@@ -279,12 +279,12 @@ __global__ void k_sweep(SweepArgs<Real> a) {
         }
         const int64_t own = base + pos0 + lane;
         // V s of the cell (one gather from a per-cell array per group; in
-        // FP32 V and s, combined with the per-direction source after the
-        // poll, so that nothing waits for these loads before it)
+        // FP32 one float, to which the per-direction source, V r, is added
+        // after the poll, so that nothing waits for these loads before it)
         Real num[NG];
 #pragma unroll
         for (int g = 0; g < NG; ++g) num[g] = Real(0);
-        float2 vs32 = make_float2(0.0f, 0.0f);
+        float vs32 = 0.0f;
         float sd32 = 0.0f;
         if (active) {
             if constexpr (sizeof(Real) == 8) {
@@ -292,7 +292,7 @@ __global__ void k_sweep(SweepArgs<Real> a) {
                 for (int g = 0; g < NG; ++g)
                     if (g < ng) num[g] = reinterpret_cast<const double *>(a.vs)[g * a.nc + K];
             } else {
-                vs32 = reinterpret_cast<const float2 *>(a.vs)[K];
+                vs32 = reinterpret_cast<const float *>(a.vs)[K];
                 if (src_row) sd32 = __builtin_nontemporal_load(src_row + pos0 + lane);   // read once per sweep
             }
         }
@@ -422,7 +422,7 @@ __global__ void k_sweep(SweepArgs<Real> a) {
             for (int g = 0; g < NG; ++g) {
                 if (g >= ng) continue;
                 Real ng_num = num[g];
-                if constexpr (sizeof(Real) == 4) ng_num = vs32.x * (src_row ? sd32 + vs32.y : vs32.y);
+                if constexpr (sizeof(Real) == 4) ng_num = src_row ? sd32 + vs32 : vs32;
                 // step-scheme balance, inflow faces in local face order
 #pragma unroll
                 for (int j = 0; j < NS; ++j) {
@@ -515,8 +515,9 @@ __device__ void sweep_direction(const DirArgs<Real, NF, DIM> &a, int m) {
             const CellRec<Real, NF, DIM> r = a.rec[K];
             Real s = Real(0);
             if (a.src_cell) s = a.src_cell[K];
-            if (a.src_dir) s = (Real)a.src_dir[base + i] + s;
+            // the FP32 correction source per direction comes as V r
             Real num = r.V * s;
+            if (a.src_dir) num = num + (Real)a.src_dir[base + i];
             Real den = r.sigV;
 #pragma unroll
             for (int j = 0; j < NF; ++j) {
@@ -731,14 +732,15 @@ __global__ void k_pvol(const int32_t *cblk, int64_t stride, const double *vol, R
 }
 
 // V s per cell for the FP64 sweep (the same product the balance takes),
-// {V, s} for the FP32 sweep
+// and for the FP32 sweep rounded from the FP64 product (one 4-byte gather
+// per vertex instead of V and s)
 __global__ void k_vs64(const double *vol, const double *src, int64_t nc, double *vs) {
     int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (K < nc) vs[K] = src ? vol[K] * src[K] : vol[K] * 0.0;
 }
-__global__ void k_vs32(const double *vol, const float *src, int64_t nc, float2 *vs) {
+__global__ void k_vs32(const double *vol, const float *src, int64_t nc, float *vs) {
     int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (K < nc) vs[K] = make_float2((float)vol[K], src ? src[K] : 0.0f);
+    if (K < nc) vs[K] = src ? (float)(vol[K] * (double)src[K]) : 0.0f;
 }
 
 // vs_buf: where the per-cell V s of this sweep is staged (null: the
@@ -769,7 +771,7 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
         const int gb = (int)ceil_div(g.nc, 256);
         if (f32)
             k_vs32<<<gb, 256, 0, s>>>(g.vol.as<double>(), reinterpret_cast<const float *>(src_cell), g.nc,
-                                     static_cast<float2 *>(vs));
+                                     static_cast<float *>(vs));
         else
             k_vs64<<<gb, 256, 0, s>>>(g.vol.as<double>(), reinterpret_cast<const double *>(src_cell), g.nc,
                                      static_cast<double *>(vs));
@@ -1039,7 +1041,7 @@ __device__ __forceinline__ void ring_direction(const RingArgs<Real> &a, int m, R
                 // V s, evaluated as in the other sweep kernels
                 Real num;
                 if constexpr (sizeof(Real) == 8) num = it.V * sc[k];
-                else num = it.V * (a.src_dir ? it.sd + sc[k] : sc[k]);
+                else num = a.src_dir ? it.V * sc[k] + it.sd : it.V * sc[k];   // sd: V r
 #pragma unroll
                 for (int j = 0; j < NS; ++j) {
                     const int32_t cd = it.code[j];
