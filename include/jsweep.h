@@ -174,7 +174,9 @@ typedef struct jsweep_graph_s *jsweep_graph;   /* opaque, owned by the library *
  *   graphs above 2^26 (cell, direction) pairs or whose tasks exceed the
  *   kernel's LDS limits fall back to DATA_DRIVEN. */
 /* AUTO (and no strategy set) is DATA_DRIVEN for a single graph; the
- * batched solve picks between its own direction kernels. */
+ * batched solve sweeps the union of the instances' work lists with the
+ * DATA_DRIVEN kernel while most of the batch still iterates, and its own
+ * direction kernels after that. */
 #define JSWEEP_STRATEGY_AUTO 0
 #define JSWEEP_STRATEGY_DATA_DRIVEN 1
 #define JSWEEP_STRATEGY_DIRECTION 2
@@ -182,7 +184,14 @@ typedef struct jsweep_graph_s *jsweep_graph;   /* opaque, owned by the library *
 #define JSWEEP_STRATEGY_PATCH 4
 
 /* Launch tuning of the sweep kernels; 0 in a field = default or the value
- * chosen by jsweep_autotune. */
+ * chosen by jsweep_autotune.  The knobs a batched sweep is usually tuned
+ * by map onto these fields: cells per workgroup = 64 * waves_per_block (a
+ * wavefront works on one chunk of up to 64 cells); queue depth =
+ * chunks_per_ticket (the chunks a wavefront holds from one ticket, plus one
+ * whose program it prefetches); directions in flight = the angle weight k
+ * of the priority (JSWEEP_PRIORITY_ANGLE_WEIGHT, about k directions of a
+ * stream at once; 0 = all of them); the batch is always every instance in
+ * one launch. */
 typedef struct {
     int32_t waves_per_block;       /* 64-lane wavefronts per workgroup (1..16) */
     int32_t blocks_per_cu;         /* DATA_DRIVEN: resident workgroups per CU (at most 4, and occupancy) */
@@ -232,7 +241,10 @@ typedef struct {
 int jsweep_build_graph(const jsweep_mesh *mesh, const jsweep_quadrature *quad, uint32_t flags,
                        jsweep_graph *out);
 
-/* Sizes of a built graph (any pointer may be NULL). */
+/* Sizes of a built graph (any pointer may be NULL): cells, directions,
+ * lagged edges (the appendix workflow's step 1, cycle elimination, as the
+ * lag rule above reads it) and the largest level count of any direction
+ * (the depth of the longest dependency chain of the sweep, Sec. II-C). */
 int jsweep_graph_info(jsweep_graph g, int64_t *n_cells, int32_t *n_dirs, int64_t *n_lagged,
                       int32_t *max_levels);
 
@@ -246,9 +258,10 @@ int jsweep_graph_info(jsweep_graph g, int64_t *n_cells, int32_t *n_dirs, int64_t
  * not depend on which program it reads. */
 int jsweep_program_info(jsweep_graph g, int32_t *slots, int32_t *block_slots);
 
-/* Export direction dir's graph: in-degree [n_cells], level [n_cells],
- * level pointers [n_levels + 1] and cells ordered by (level, id)
- * [n_cells].  Buffers are caller-allocated, device memory unless flags has
+/* Export direction dir's graph (Sec. II-C: the sweep of one angle is a
+ * topological traversal of this DAG; Listing 1's count is the in-degree):
+ * in-degree [n_cells], level [n_cells], level pointers [n_levels + 1] and
+ * cells ordered by (level, id) [n_cells].  Buffers are caller-allocated, device memory unless flags has
  * JSWEEP_HOST_PTRS; any may be NULL.  n_levels receives the level count
  * of the direction (size lvl_ptr accordingly; call once with lvl_ptr NULL
  * to learn it). */
@@ -360,7 +373,10 @@ int jsweep_solve_batch(int32_t n, const jsweep_graph *graphs, const jsweep_probl
                        void *hip_stream);
 
 /* Pick launch parameters for these graphs by timing candidate
- * configurations of the sweep kernel on the device (uses scratch problem
+ * configurations of the sweep kernel on the device (the paper tunes its
+ * run-time hyper-parameters, patch size and clustering, by measurement,
+ * Sec. VI; here the workgroup shape, chunks per ticket, kernel strategy and
+ * for FP32-refined solves the inner sweep count) (uses scratch problem
  * data, no caller buffers).  The result is cached in memory and, when the
  * environment variable JSWEEP_TUNE_CACHE names a file, in that JSON file
  * keyed by (cell type, size bucket, direction count, mode, device). */
