@@ -252,11 +252,16 @@ int jsweep_graph_info(jsweep_graph g, int64_t *n_cells, int32_t *n_dirs, int64_t
  * inflow slots per vertex (the largest number of inflow faces of any
  * vertex, at most the faces per cell); *block_slots = how many of those
  * slots the FP64 work-list sweep reads from the chunk blocks instead of the
- * program arrays (0: it reads the full program).  Graphs with more than 3
- * slots get a compact program of 3 slots per vertex when every work-list
- * chunk has at most 7 further (vertex, slot) pairs; the sweep's results do
- * not depend on which program it reads. */
-int jsweep_program_info(jsweep_graph g, int32_t *slots, int32_t *block_slots);
+ * program arrays (0: it reads the full program); *packed = 1 when the
+ * work-list sweeps read the upwind positions packed, three 21-bit
+ * distances back from the vertex's own position in one 8-byte word, with
+ * the few that do not fit (lagged faces, far upwind vertices) in the chunk
+ * blocks.  Graphs with more than 3 slots get a compact program of 3 slots
+ * per vertex when every work-list chunk has at most 7 further (vertex,
+ * slot) pairs; graphs with at most 3 slots get packed positions when every
+ * chunk has at most 12 codes that do not fit.  The sweep's results do not
+ * depend on which program it reads. */
+int jsweep_program_info(jsweep_graph g, int32_t *slots, int32_t *block_slots, int32_t *packed);
 
 /* Export direction dir's graph (Sec. II-C: the sweep of one angle is a
  * topological traversal of this DAG; Listing 1's count is the in-degree):

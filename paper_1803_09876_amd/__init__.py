@@ -109,7 +109,7 @@ def load_library(path: str | None = None):
     P, i32, i64, dbl, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint32
     lib.jsweep_build_graph.argtypes = [ctypes.POINTER(_Mesh), ctypes.POINTER(_Quad), u32, ctypes.POINTER(P)]
     lib.jsweep_graph_info.argtypes = [P, P, P, P, P]
-    lib.jsweep_program_info.argtypes = [P, P, P]
+    lib.jsweep_program_info.argtypes = [P, P, P, P]
     lib.jsweep_graph_export.argtypes = [P, i32, P, P, P, P, P, u32]
     lib.jsweep_graph_lagged.argtypes = [P, P, P, P, P]
     lib.jsweep_sweep.argtypes = [P, P, P, P, P, dbl, P]
@@ -225,12 +225,13 @@ def jsweep_graph_info(g: Graph):
 
 
 def jsweep_program_info(g: Graph):
-    """Sweep program shape: inflow slots per vertex, and how many of them the
-    FP64 work-list sweep reads from the chunk blocks (0: full program)."""
+    """Sweep program shape: inflow slots per vertex, how many of them the
+    FP64 work-list sweep reads from the chunk blocks (0: full program), and
+    whether the work-list sweeps read packed upwind positions."""
     lib = load_library()
-    ns, nx = ctypes.c_int32(), ctypes.c_int32()
-    _check(lib.jsweep_program_info(g.handle, ctypes.byref(ns), ctypes.byref(nx)))
-    return {"slots": ns.value, "block_slots": nx.value}
+    ns, nx, pk = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib.jsweep_program_info(g.handle, ctypes.byref(ns), ctypes.byref(nx), ctypes.byref(pk)))
+    return {"slots": ns.value, "block_slots": nx.value, "packed": bool(pk.value)}
 
 
 def jsweep_graph_export(g: Graph, direction: int, want=("indeg", "level", "lvl_ptr", "lvl_cells")):

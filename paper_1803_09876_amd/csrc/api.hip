@@ -172,12 +172,13 @@ int jsweep_graph_info(jsweep_graph h, int64_t *n_cells, int32_t *n_dirs, int64_t
     });
 }
 
-int jsweep_program_info(jsweep_graph h, int32_t *slots, int32_t *block_slots) {
+int jsweep_program_info(jsweep_graph h, int32_t *slots, int32_t *block_slots, int32_t *packed) {
     return guarded([&]() -> int {
         if (!h) fail(JSWEEP_E_INVALID_ARG, "graph is NULL");
         Graph &g = *G(h);
         if (slots) *slots = g.ns;
         if (block_slots) *block_slots = g.ns_x;
+        if (packed) *packed = g.pk.p ? 1 : 0;
         return JSWEEP_OK;
     });
 }

@@ -85,6 +85,21 @@ constexpr int kBlockDeps = kBlock - 67;
 // inline upwind chunks, which the work-list sweep does not read.
 constexpr int kCompactSlots = 3;
 constexpr int kBlockExtra = 7;
+// Packed codes (graphs with at most 3 inflow slots and no compact entries):
+// the 3 slot codes of a lane in one 64-bit word, 21 bits per slot: the
+// distance back from the vertex's own level position to the upwind one
+// (1 .. kPkMaxDelta), or kPkNoFace / kPkBound (-1, psi_b) / kPkEsc.  An
+// escaped code (a lagged face, or an upwind vertex further back) is an
+// entry of the chunk block: [65] the entry count, [70 + 2 e, 72 + 2 e)
+// entry e = (lane | slot << 8, the int32 code), at most kPkEscMax of them
+// (words 67 - 69 stay free for the batched sweep's direction base).
+constexpr int kPkBits = 21;
+constexpr uint32_t kPkMask = (1u << kPkBits) - 1u;
+constexpr uint32_t kPkNoFace = kPkMask;
+constexpr uint32_t kPkBound = kPkMask - 1u;
+constexpr uint32_t kPkEsc = kPkMask - 2u;
+constexpr uint32_t kPkMaxDelta = kPkMask - 3u;
+constexpr int kPkEscMax = 12;
 
 // Sweep program: per chunk lane (index c * 64 + lane, stride S = 64 *
 // n_chunks) the vertex's inflow faces in local face order, ns slots each:
@@ -229,6 +244,7 @@ struct Graph {
     int ns = 0;                          // sweep program: inflow slots per vertex
     DevBuf pcode, pa64, pa32;            // [ns * S] int32 / double / float (pa32 on first FP32 use)
     DevBuf pcode3, pa3;                  // [kCompactSlots * S] compact FP64 program (see kCompactSlots)
+    DevBuf pk;                           // [S] packed codes (see kPkBits), or empty
     int ns_x = 0;                        // slots past kCompactSlots in the blocks; 0: no compact program
     DevBuf pden64, pden32;               // [S] double / float
     DevBuf sig_last;                     // [nc] sigma_t the denominators were built for
@@ -371,7 +387,7 @@ struct UnionSweep {
     std::vector<int64_t> coff, aoff, loff;        // per instance: first cell, vertex, lagged edge
     std::vector<int32_t> dir_off;                 // per instance: first global direction
     std::vector<int64_t> stream_off_h;
-    DevBuf uinst, uchunk, isrc, cblk, pcode, pa, pden, stream_off, rows, status, lag, vs;
+    DevBuf uinst, uchunk, isrc, cblk, pcode, pa, pden, stream_off, rows, status, lag, vs, pk;
     DevBuf pos[2];
     int pos_state[2] = {0, 0}, cur = 0;   // element size of the empty markers each array holds (0: none)
     Graph *prof = nullptr;               // the batch's first graph: its jsweep_profile records the launches
@@ -387,6 +403,10 @@ struct UnionSweep {
     void launch(const int32_t *active, int waves_per_block, hipStream_t s);
     int check_status(hipStream_t s);
 };
+// packed codes (kPkBits) of a 3-slot program into pk [64 * n_chunks], with
+// the escaped codes as entries of the chunk blocks; false (pk unusable)
+// when a chunk has more than kPkEscMax escaped codes
+bool pack_codes(int32_t *cblk, int64_t n_chunks, int ns, const int32_t *code, uint64_t *pk, hipStream_t s);
 // the cached union of these graphs (rebuilt when any of them changed)
 UnionSweep &union_for(int n, Graph *const *graphs, bool fp32, hipStream_t s);
 // drops the cached union if it holds this graph

@@ -440,6 +440,15 @@ __global__ void k_compact(int32_t *blk, int64_t n_chunks, int ns, const int32_t 
     }
 }
 
+// packed codes of a program of at most 3 slots without compact entries
+static void build_packed(Graph &g, hipStream_t s) {
+    g.pk.release();
+    if (g.ns > 3 || g.ns_x > 0 || !g.n_chunks) return;
+    g.pk.alloc(8 * (size_t)(64 * g.n_chunks));
+    if (!pack_codes(g.cblk.as<int32_t>(), g.n_chunks, g.ns, g.pcode.as<int32_t>(), g.pk.as<uint64_t>(), s))
+        g.pk.release();
+}
+
 static void build_compact(Graph &g, hipStream_t s) {
     g.ns_x = 0;
     g.pcode3.release();
@@ -829,6 +838,7 @@ static void dag_impl(Graph &g, bool lag_cycles, hipStream_t s) {
     build_coarsened<NF, DIM>(g, lag, s);
     build_program<NF, DIM>(g, lag, s);
     build_compact(g, s);
+    build_packed(g, s);
     // the work-list sweep's two level-position flux arrays (FP64 size) and
     // the sigma_t cache are allocated here, so that single-group sweeps
     // allocate nothing
@@ -1028,6 +1038,7 @@ static void reorder_impl(Graph &g, int priority, hipStream_t s) {
     build_coarsened<NF, DIM>(g, lag, s);
     build_program<NF, DIM>(g, lag, s);
     build_compact(g, s);
+    build_packed(g, s);
     // everything kept in chunk order is rebuilt on its next use
     g.pa32.release();
     g.pden32.release();

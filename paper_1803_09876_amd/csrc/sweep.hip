@@ -79,6 +79,7 @@ struct SweepArgs {
     int64_t nc;
     int64_t stride;                          // 64 * n_chunks: program slot stride
     const int32_t *pcode;                    // [ns * stride]
+    const uint64_t *pk;                      // [stride] packed codes (NS <= 3), or null: pcode
     const Real *pa;                          // [ns * stride]
     const Real *pden;                        // [stride]
     const void *vs;                          // [nc] V s (double) or {V, s} (float2) per cell
@@ -160,10 +161,11 @@ struct LaneProg {
     int32_t w2;                              // descriptor word (lanes 0 .. 31)
     Real den[NG];                            // one denominator per energy group
     int32_t code[NS];
+    uint64_t pk;                             // packed codes, decoded into code[] when the chunk starts
     Real af[NS];
 };
 
-template <class Real, int NS, int NG>
+template <bool PK, class Real, int NS, int NG>
 __device__ __forceinline__ void load_prog(const SweepArgs<Real> &a, int64_t c, int lane, LaneProg<Real, NS, NG> &P) {
     // read once per sweep: streamed past the caches (non-temporal), which
     // leaves L2 to the fluxes being handed off and merged
@@ -174,10 +176,36 @@ __device__ __forceinline__ void load_prog(const SweepArgs<Real> &a, int64_t c, i
 #pragma unroll
     for (int g = 0; g < NG; ++g)
         P.den[g] = (g == 0 || g < a.n_groups) ? __builtin_nontemporal_load(a.pden + g * a.gs_den + idx) : Real(1);
+    if constexpr (PK) {
+        P.pk = __builtin_nontemporal_load(a.pk + idx);
+    } else {
+#pragma unroll
+        for (int j = 0; j < NS; ++j) P.code[j] = __builtin_nontemporal_load(a.pcode + j * a.stride + idx);
+    }
+#pragma unroll
+    for (int j = 0; j < NS; ++j) P.af[j] = __builtin_nontemporal_load(a.pa + j * a.stride + idx);
+}
+
+// code[] of a chunk whose program came packed: the upwind level position
+// is the vertex's own one minus the stored distance; escaped codes are
+// entries of the chunk block, which the descriptor lanes already hold
+template <class Real, int NS, int NG>
+__device__ __forceinline__ void unpack_codes(LaneProg<Real, NS, NG> &P, int64_t pos0, int lane) {
+    static_assert(NS <= 3, "packed codes hold 3 slots");
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
-        P.code[j] = __builtin_nontemporal_load(a.pcode + j * a.stride + idx);
-        P.af[j] = __builtin_nontemporal_load(a.pa + j * a.stride + idx);
+        const uint32_t f = (uint32_t)(P.pk >> (kPkBits * j)) & kPkMask;
+        P.code[j] = f == kPkNoFace ? kNoFace : f == kPkBound ? -1 : (int32_t)(pos0 + lane - (int64_t)f);
+    }
+    const int ne = __builtin_amdgcn_readlane(P.w2, 1);
+    for (int e = 0; e < ne; ++e) {
+        const uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane(P.w2, 6 + 2 * e);
+        const int32_t cd = __builtin_amdgcn_readlane(P.w2, 7 + 2 * e);
+        if (lane == (int)(w0 & 63u)) {
+#pragma unroll
+            for (int j = 0; j < NS; ++j)
+                if ((int)(w0 >> 8) == j) P.code[j] = cd;
+        }
     }
 }
 
@@ -195,11 +223,13 @@ __device__ __forceinline__ void keep_live(const T &v) {
 // past NS that the compact program keeps in the chunk blocks (0: none);
 // TRACE: record take / ready / done stamps per chunk; NG: energy groups
 // swept per chunk (multigroup: a.n_groups <= NG groups share the chunk's
-// program, each with its own denominator, source and fluxes).
-template <class Real, int NS, int NSX, bool TRACE, int NG = 1>
+// program, each with its own denominator, source and fluxes); PK: the
+// upwind positions come packed (a.pk, see kPkBits).
+template <class Real, int NS, int NSX, bool TRACE, int NG = 1, bool PK = false>
 __global__ void k_sweep(SweepArgs<Real> a) {
     constexpr int NX = NSX > 0 ? NSX : 1;
     static_assert(NG == 1 || (NSX == 0 && sizeof(Real) == 8), "multigroup sweeps read the full FP64 program");
+    static_assert(!PK || (NS <= 3 && NSX == 0), "packed codes hold 3 slots and no compact entries");
     const int lane = threadIdx.x & 63;
     const int stream = (int)(blockIdx.x % kStreams);
     // a wavefront off its stream's XCD takes no chunk (it holds nothing
@@ -221,7 +251,7 @@ __global__ void k_sweep(SweepArgs<Real> a) {
     if (lane == 0) nxt = atomicAdd(ticket, (uint32_t)a.grab);
     if (t >= per_stream) return;
     LaneProg<Real, NS, NG> P;
-    load_prog(a, first + t, lane, P);
+    load_prog<PK>(a, first + t, lane, P);
     uint32_t t_take = (uint32_t)__builtin_amdgcn_s_memrealtime();
     int64_t pend = (int64_t)__builtin_amdgcn_readfirstlane(nxt);   // start of the requested range
     __builtin_amdgcn_s_waitcnt(0);   // the loop starts with nothing in flight
@@ -245,12 +275,13 @@ __global__ void k_sweep(SweepArgs<Real> a) {
         LaneProg<Real, NS, NG> Pn;
         uint32_t tn_take = 0;
         if (tn < per_stream) {
-            load_prog(a, first + tn, lane, Pn);
+            load_prog<PK>(a, first + tn, lane, Pn);
             tn_take = (uint32_t)__builtin_amdgcn_s_memrealtime();
         }
         const uint32_t hdr = (uint32_t)__builtin_amdgcn_readfirstlane(P.w2);
         const int64_t pos0 = (int64_t)(uint32_t)__builtin_amdgcn_readlane(P.w2, 2);
         const int m = (int)(hdr & 0xffffu);
+        if constexpr (PK) unpack_codes(P, pos0, lane);
         bool active = P.item >= 0;
         const int64_t K = active ? (int64_t)P.item : 0;
         // where direction m's arrays start: m nc for one graph, the
@@ -620,14 +651,23 @@ static uint64_t watchdog_ticks() {
     return (uint64_t)(ms * 1e5);   // s_memrealtime runs at 100 MHz
 }
 
-template <class Real, int NS, int NSX = 0>
+template <class Real, int NS, int NSX = 0, bool PK = false>
 static const void *kernel_ptr(bool trace) {
-    return trace ? reinterpret_cast<const void *>(&k_sweep<Real, NS, NSX, true>)
-                 : reinterpret_cast<const void *>(&k_sweep<Real, NS, NSX, false>);
+    return trace ? reinterpret_cast<const void *>(&k_sweep<Real, NS, NSX, true, 1, PK>)
+                 : reinterpret_cast<const void *>(&k_sweep<Real, NS, NSX, false, 1, PK>);
 }
 
+// pk: the program's upwind positions are packed (at most 3 slots)
 template <class Real>
-static const void *sweep_kernel_t(int ns, bool trace) {
+static const void *sweep_kernel_t(int ns, bool trace, bool pk = false) {
+    if (pk) {
+        switch (ns) {
+        case 1: return kernel_ptr<Real, 1, 0, true>(trace);
+        case 2: return kernel_ptr<Real, 2, 0, true>(trace);
+        case 3: return kernel_ptr<Real, 3, 0, true>(trace);
+        default: fail(JSWEEP_E_DEVICE, "packed codes with more than 3 slots");
+        }
+    }
     switch (ns) {
     case 1: return kernel_ptr<Real, 1>(trace);
     case 2: return kernel_ptr<Real, 2>(trace);
@@ -641,6 +681,12 @@ static const void *sweep_kernel_t(int ns, bool trace) {
 // the FP64 sweep of a graph with a compact program reads kCompactSlots
 // slots from the arrays and ns_x from the chunk blocks
 static bool use_compact(const Graph &g, bool fp32) { return !fp32 && g.ns_x > 0; }
+
+// the single-group work-list sweeps read packed upwind positions where the
+// graph has them (programs of at most 3 slots without compact entries)
+static bool use_packed(const Graph &g, bool fp32, int groups) {
+    return groups <= 1 && g.pk.p && g.ns <= 3 && !use_compact(g, fp32);
+}
 
 // multigroup FP64 kernels: NG groups per chunk, full program
 template <int NG>
@@ -663,7 +709,7 @@ static const void *sweep_kernel(const Graph &g, bool fp32, bool trace = false, i
     if (ns < 1 || ns > 6) fail(JSWEEP_E_DEVICE, "sweep program with an unsupported number of inflow slots");
     if (groups >= 1) {
         if (fp32 || trace) fail(JSWEEP_E_INVALID_ARG, "multigroup sweeps are FP64 and untraced");
-        if (groups == 1) return sweep_kernel_t<double>(ns, false);
+        if (groups == 1) return sweep_kernel_t<double>(ns, false, use_packed(g, false, 1));
         if (groups <= 2) return sweep_kernel_groups<2>(ns);
         if (groups <= 4) return sweep_kernel_groups<4>(ns);
         if (groups <= kMaxGroups) return sweep_kernel_groups<kMaxGroups>(ns);
@@ -677,7 +723,8 @@ static const void *sweep_kernel(const Graph &g, bool fp32, bool trace = false, i
         default: return kernel_ptr<double, 3, 3>(trace);
         }
     }
-    return fp32 ? sweep_kernel_t<float>(ns, trace) : sweep_kernel_t<double>(ns, trace);
+    const bool pk = use_packed(g, fp32, groups);
+    return fp32 ? sweep_kernel_t<float>(ns, trace, pk) : sweep_kernel_t<double>(ns, trace, pk);
 }
 
 constexpr int kMaxSweepBlocksPerCU = 4;
@@ -731,6 +778,62 @@ __global__ void k_pvol(const int32_t *cblk, int64_t stride, const double *vol, R
     pvol[idx] = K < 0 ? Real(0) : (Real)vol[K];
 }
 
+// Packed codes of chunk c (one 64-lane workgroup per chunk): the distance
+// of every slot's upwind position back from the lane's own, or a reserved
+// value; escaped codes go to the chunk block as entries (lane | slot << 8,
+// code), and *too_many is set when a chunk has more than kPkEscMax.  The
+// largest distance kept can be lowered for tests (max_delta).
+__global__ void k_pack_codes(int32_t *blk, int64_t n_chunks, int ns, const int32_t *code, uint64_t *pk,
+                             uint32_t max_delta, int32_t *too_many) {
+    const int64_t c = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (c >= n_chunks) return;
+    const int64_t S = 64 * n_chunks, idx = c * 64 + lane;
+    int32_t *b = blk + c * kBlock;
+    const int64_t pos = (int64_t)b[66] + lane;
+    const int cnt = (int)((uint32_t)b[64] >> 16) + 1;
+    uint64_t v = 0;
+    int n = 0;
+    for (int j = 0; j < 3; ++j) {
+        const int32_t cd = (j < ns && lane < cnt) ? code[j * S + idx] : kNoFace;
+        uint32_t f = kPkEsc;
+        if (cd == kNoFace) f = kPkNoFace;
+        else if (cd == -1) f = kPkBound;
+        else if (cd >= 0 && pos - cd >= 1 && pos - cd <= (int64_t)max_delta) f = (uint32_t)(pos - cd);
+        v |= (uint64_t)f << (kPkBits * j);
+        const bool esc = f == kPkEsc;
+        const uint64_t mask = __ballot(esc);
+        const int e = n + __popcll(mask & ((1ull << lane) - 1ull));
+        if (esc && e < kPkEscMax) {
+            b[70 + 2 * e] = lane | (j << 8);
+            b[71 + 2 * e] = cd;
+        }
+        n += __popcll(mask);
+    }
+    pk[idx] = v;
+    if (lane == 0) {
+        b[65] = n;
+        if (n > kPkEscMax) atomicOr(too_many, 1);
+    }
+}
+
+bool pack_codes(int32_t *cblk, int64_t n_chunks, int ns, const int32_t *code, uint64_t *pk, hipStream_t s) {
+    if (ns > 3 || n_chunks <= 0) return false;
+    uint32_t max_delta = kPkMaxDelta;
+    if (const char *e = std::getenv("JSWEEP_PACK_MAX_DELTA")) {
+        const long v = std::atol(e);
+        if (v >= 1 && v < (long)kPkMaxDelta) max_delta = (uint32_t)v;
+    }
+    DevBuf flag(4);
+    JSW_HIP(hipMemsetAsync(flag.p, 0, 4, s));
+    k_pack_codes<<<(unsigned)n_chunks, 64, 0, s>>>(cblk, n_chunks, ns, code, pk, max_delta, flag.as<int32_t>());
+    JSW_HIP(hipGetLastError());
+    int32_t too_many = 0;
+    JSW_HIP(hipMemcpyAsync(&too_many, flag.p, 4, hipMemcpyDeviceToHost, s));
+    JSW_HIP(hipStreamSynchronize(s));
+    return too_many == 0;
+}
+
 // V s per cell for the FP64 sweep (the same product the balance takes),
 // and for the FP32 sweep rounded from the FP64 product (one 4-byte gather
 // per vertex instead of V and s)
@@ -760,6 +863,7 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
     a.stride = 64 * g.n_chunks;
     const bool compact = use_compact(g, f32) && !mg;   // multigroup kernels read the full program
     a.pcode = compact ? g.pcode3.as<int32_t>() : g.pcode.as<int32_t>();
+    a.pk = use_packed(g, f32, mg ? G : 0) ? g.pk.as<uint64_t>() : nullptr;
     a.pa = reinterpret_cast<const Real *>(compact ? g.pa3.p : f32 ? g.pa32.p : g.pa64.p);
     a.pden = reinterpret_cast<const Real *>(f32 ? g.pden32.p : g.pden64.p);
     void *vs = vs_buf;
@@ -939,6 +1043,7 @@ struct RingItem {
     Real den, V, sd;                         // sd: per-direction source part (FP32 path)
     int32_t K;
     int32_t code[NS];
+    uint64_t pk;                             // packed codes, decoded into code[] when the chunk starts
     Real af[NS];
 };
 
@@ -1620,6 +1725,13 @@ void UnionSweep::build(int n_, Graph *const *graphs, bool fp32_, hipStream_t s) 
                 uinst.as<int32_t>(), uchunk.as<int32_t>(), isrc.as<UnionSrc>(), n_chunks, ns, pcode.as<int32_t>(),
                 pa.as<double>(), pden.as<double>());
         JSW_HIP(hipGetLastError());
+        // packed codes of the merged program (the union's own lagged
+        // indices are escapes like any other)
+        pk.release();
+        if (ns <= 3) {
+            pk.alloc(8 * (size_t)S);
+            if (!pack_codes(cblk.as<int32_t>(), n_chunks, ns, pcode.as<int32_t>(), pk.as<uint64_t>(), s)) pk.release();
+        }
     }
     JSW_HIP(hipStreamSynchronize(s));   // the host tables go out of scope
 }
@@ -1680,6 +1792,7 @@ static void union_launch(UnionSweep &u, const int32_t *active, int waves_per_blo
     a.nc = 0;
     a.stride = 64 * u.n_chunks;
     a.pcode = u.pcode.as<int32_t>();
+    a.pk = (u.pk.p && u.ns <= 3) ? u.pk.as<uint64_t>() : nullptr;
     a.pa = u.pa.as<Real>();
     a.pden = u.pden.as<Real>();
     a.vs = u.vs.p;
@@ -1726,7 +1839,8 @@ static void union_launch(UnionSweep &u, const int32_t *active, int waves_per_blo
         JSW_HIP(hipEventRecord(ev0, s));
     }
     void *args[] = {&a};
-    JSW_HIP(hipLaunchKernel(sweep_kernel_t<Real>(u.ns, false), dim3(blocks), dim3(64 * wpb), args, 0, s));
+    JSW_HIP(hipLaunchKernel(sweep_kernel_t<Real>(u.ns, false, a.pk != nullptr), dim3(blocks), dim3(64 * wpb), args, 0,
+                            s));
     if (prof) {
         JSW_HIP(hipEventRecord(ev1, s));
         u.prof->prof_events.push_back({ev0, ev1});

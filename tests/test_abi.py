@@ -70,7 +70,7 @@ def test_rejects_bad_mesh_arguments():
 def test_null_handles_rejected():
     lib = J.load_library()
     assert lib.jsweep_graph_info(None, None, None, None, None) == J.JSWEEP_E_INVALID_ARG
-    assert lib.jsweep_program_info(None, None, None) == J.JSWEEP_E_INVALID_ARG
+    assert lib.jsweep_program_info(None, None, None, None) == J.JSWEEP_E_INVALID_ARG
     assert lib.jsweep_sweep(None, None, None, None, None, 0.0, None) == J.JSWEEP_E_INVALID_ARG
     assert lib.jsweep_profile(None, 1) == J.JSWEEP_E_INVALID_ARG
     lib.jsweep_graph_destroy(None)
