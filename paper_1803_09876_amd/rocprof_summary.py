@@ -12,6 +12,11 @@
         for the largest device-to-device copy in the run (a plain copy of known size: the
         benchmark's --copy-probe, 512 MiB read and 512 MiB written).
 
+    python -m paper_1803_09876_amd.rocprof_summary counters <csv dir> <kernel substring> <out.md> <title> <command>
+        every counter of a `rocprofv3 --pmc ... --output-format csv` run averaged over the
+        kernel's dispatches (the L2 hit rate, and the ratio SQ_WAVE_CYCLES / SQ_BUSY_CYCLES, are
+        derived when those counters are among them).
+
 Reads only the CSV files rocprofv3 writes; nothing here runs on the GPU.
 """
 from __future__ import annotations
@@ -103,11 +108,40 @@ def traffic(fetch_dir, write_dir, kernel, key, out_json, out_md, command) -> Non
     print(open(out_md).read())
 
 
+def counters(csv_dir, kernel, out, title, command) -> None:
+    path = _one(os.path.join(csv_dir, "**", "*counter_collection.csv"))
+    vals = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if kernel in r["Kernel_Name"]:
+                vals.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    if not vals:
+        raise SystemExit(f"no dispatch of {kernel}")
+    avg = {k: sum(v) / len(v) for k, v in vals.items()}
+    with open(out, "w") as f:
+        f.write(f"# {title}\n\nCommand (on the MI355X, from /tmp with TMPDIR=/tmp):\n\n```\n{command}\n```\n\n")
+        f.write(f"Counters of `{kernel}`, averaged over its dispatches:\n\n| counter | per dispatch | dispatches |\n"
+                "|---|---|---|\n")
+        for k in sorted(avg):
+            f.write(f"| {k} | {avg[k]:.6g} | {len(vals[k])} |\n")
+        if "TCC_HIT_sum" in avg and "TCC_MISS_sum" in avg:
+            h, m = avg["TCC_HIT_sum"], avg["TCC_MISS_sum"]
+            f.write(f"\nL2 hit rate: {h / max(1.0, h + m):.3f} ({h + m:.4g} L2 requests per dispatch).\n")
+        if "SQ_WAVE_CYCLES" in avg and "SQ_BUSY_CYCLES" in avg and avg["SQ_BUSY_CYCLES"] > 0:
+            f.write(f"\nSQ_WAVE_CYCLES / SQ_BUSY_CYCLES (wavefront-cycles per busy cycle of the counting "
+                    f"sequencers, as summed by rocprofv3): {avg['SQ_WAVE_CYCLES'] / avg['SQ_BUSY_CYCLES']:.1f}.\n")
+        if "SQ_WAVES" in avg:
+            f.write(f"\nWavefronts launched per dispatch (SQ_WAVES): {avg['SQ_WAVES']:.0f}.\n")
+    print(open(out).read())
+
+
 def main(argv):
     if len(argv) >= 5 and argv[0] == "kernels":
         kernels(*argv[1:5], *([int(argv[5])] if len(argv) > 5 else []))
     elif len(argv) >= 8 and argv[0] == "traffic":
         traffic(*argv[1:8])
+    elif len(argv) >= 6 and argv[0] == "counters":
+        counters(*argv[1:6])
     else:
         raise SystemExit(__doc__)
 
