@@ -1651,9 +1651,15 @@ void UnionSweep::build(int n_, Graph *const *graphs, bool fp32_, hipStream_t s) 
     total_dirs = dir_off[n];
     if (total_dirs > 0xffff) fail(JSWEEP_E_INVALID_ARG, "batched data-driven sweep: more than 65535 directions in all");
     if (A >= ((int64_t)1 << 32) || C >= ((int64_t)1 << 31)) fail(JSWEEP_E_INVALID_ARG, "batched data-driven sweep: batch too large");
-    // merged streams: every instance's chunks of stream x, ordered by
-    // (level, instance, chunk)
+    // merged streams: every instance's chunks of stream x, ordered as the
+    // PACED priority orders one graph's: by the level over the level count
+    // of the chunk's (instance, direction), then (level, instance, chunk).
+    // The key grows with the level within every (instance, direction), so
+    // the order is topological; instances of every depth reach their last
+    // levels together at the end of the stream, instead of the deepest
+    // ones running alone after the others (as in plain level order)
     struct Item {
+        int64_t key;
         int32_t level, inst, chunk;
     };
     std::vector<std::vector<Item>> per(kStreams);
@@ -1665,7 +1671,7 @@ void UnionSweep::build(int n_, Graph *const *graphs, bool fp32_, hipStream_t s) 
             const int m = (int)(ch[c].a & 0xffffu);
             const int64_t *p = g.lvl_ptr_h.data() + g.lvl_off_h[m];
             const int L = (int)(std::upper_bound(p, p + g.nlev_h[m] + 1, (int64_t)ch[c].b) - p - 1);
-            per[g.dir_stream_h[m]].push_back(Item{L, i, (int32_t)c});
+            per[g.dir_stream_h[m]].push_back(Item{((int64_t)L << 32) / std::max(1, g.nlev_h[m]), L, i, (int32_t)c});
         }
     }
     std::vector<int32_t> hi, hc;
@@ -1673,6 +1679,7 @@ void UnionSweep::build(int n_, Graph *const *graphs, bool fp32_, hipStream_t s) 
     for (int x = 0; x < kStreams; ++x) {
         auto &v = per[x];
         std::sort(v.begin(), v.end(), [](const Item &a, const Item &b) {
+            if (a.key != b.key) return a.key < b.key;
             if (a.level != b.level) return a.level < b.level;
             if (a.inst != b.inst) return a.inst < b.inst;
             return a.chunk < b.chunk;
