@@ -335,8 +335,9 @@ __global__ void k_qnorm(const double *q, const double *vol, int64_t nc, double *
 // V-weighted norm of dphi and that of sigma_s (dphi - dphi_prev): by the
 // sweep identity the latter is the isotropic part of the correction
 // equation's residual, i.e. of the outer residual once the correction is
-// applied.  It also prepares the next inner sweep: the (V, source) pairs
-// the sweep kernel reads, the lagged-edge values of this iterate, zeroed
+// applied.  It also prepares the next inner sweep: the per-cell V s (one
+// float, rounded from the FP64 product) the sweep kernel reads, the
+// lagged-edge values of this iterate, zeroed
 // accumulators (acc_next) and stream tickets.  CPT consecutive cells per
 // thread (1, or 4 when n_cells is a multiple of 4 and dpsi 16-byte
 // aligned: every direction's fluxes are then read in 16-byte pieces); each
