@@ -118,3 +118,52 @@ def test_hex_program_not_packed():
         assert info["slots"] > 3 and not info["packed"]
     finally:
         g.close()
+
+
+def test_batch_union_packed_with_escapes(oracle_mod):
+    """The batched union builds packed codes of its merged program (the
+    instances' lagged indices rebased, escapes like any other): with the
+    largest distance lowered to 800, four small instances keep packed
+    programs while 842 codes escape; 10 FP64 iterations of the union sweep
+    against the oracle, and an FP32-refined batch solve."""
+    need_gpu()
+    import torch
+    ps = W.ensemble(seed=9, count=4, min_cells=600, max_cells=4000)
+    md = 800
+    refs, total = [], 0
+    for p in ps:
+        og = oracle_mod.graph_for(p)
+        worst, n = _escapes(og, p.omega, md)
+        assert worst <= ESC_MAX
+        total += n
+        refs.append(og.source_iteration(p.sigma_t, p.sigma_s, p.q, p.weight, 10))
+    assert total > 0
+    old = os.environ.get(KEY)
+    os.environ[KEY] = str(md)
+    try:
+        gs = [J.build_graph(p.mesh, p.omega, p.weight) for p in ps]
+        try:
+            assert all(J.program_info(g)["packed"] for g in gs)
+            pr = [{"sigma_t": dev(p.sigma_t), "sigma_s": dev(p.sigma_s), "q": dev(p.q),
+                   "phi": dev(np.zeros(p.n_cells)), "psi": dev(np.zeros((p.n_dirs, p.n_cells)))} for p in ps]
+            J.solve_batch(gs, pr, mode=J.JSWEEP_FP64, tol=0.0, max_iter=10,
+                          params=J.Params(strategy=J.JSWEEP_STRATEGY_DATA_DRIVEN), allow_not_converged=True)
+            for i, (p, (psi_ref, phi_ref, _)) in enumerate(zip(ps, refs)):
+                e1, e2 = rel_max(host(pr[i]["phi"]), phi_ref), rel_max(host(pr[i]["psi"]), psi_ref)
+                print(f"[packed union] instance {i} ({p.n_cells} cells, {p.n_dirs} dirs): phi {e1:.2e} psi {e2:.2e}",
+                      flush=True)
+                assert e1 <= 1e-12 and e2 <= 1e-12
+            pr = [{"sigma_t": dev(p.sigma_t), "sigma_s": dev(p.sigma_s), "q": dev(p.q),
+                   "phi": dev(np.zeros(p.n_cells))} for p in ps]
+            st = J.solve_batch(gs, pr, mode=J.JSWEEP_FP32_REFINED, tol=1e-10, max_iter=2000,
+                               params=J.Params(strategy=J.JSWEEP_STRATEGY_DATA_DRIVEN))
+            assert all(x["residual"] <= 1e-10 for x in st)
+            torch.cuda.synchronize()
+        finally:
+            for g in gs:
+                g.close()
+    finally:
+        if old is None:
+            os.environ.pop(KEY, None)
+        else:
+            os.environ[KEY] = old
