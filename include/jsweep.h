@@ -175,8 +175,10 @@ typedef struct jsweep_graph_s *jsweep_graph;   /* opaque, owned by the library *
  *   kernel's LDS limits fall back to DATA_DRIVEN. */
 /* AUTO (and no strategy set) is DATA_DRIVEN for a single graph; the
  * batched solve sweeps the union of the instances' work lists with the
- * DATA_DRIVEN kernel while most of the batch still iterates, and its own
- * direction kernels after that. */
+ * DATA_DRIVEN kernel, compacting the list to the instances still iterating
+ * whenever their work falls below half of the listed work (DATA_DRIVEN for
+ * a batch: the full list every sweep; DIRECTION, DIRECTION_LDS: the
+ * batched direction kernels). */
 #define JSWEEP_STRATEGY_AUTO 0
 #define JSWEEP_STRATEGY_DATA_DRIVEN 1
 #define JSWEEP_STRATEGY_DIRECTION 2

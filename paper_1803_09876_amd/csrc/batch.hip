@@ -438,13 +438,14 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
     // (the chunks of converged instances are still walked, only to empty
     // their entries).  DIRECTION, DIRECTION_LDS: the batched direction
     // kernels (a converged instance's tasks return at once).  AUTO (the
-    // default): the union launch while at least kUnionMinActive of the
-    // batch's cell-angle updates belong to instances still iterating, the
-    // direction kernels (LDS window where every instance fits it) after.
+    // default): the union launch, over a list compacted to the instances
+    // still iterating each time their cell-angle updates fall below
+    // kUnionMinActive of the list's (so at most half of the listed work
+    // is ever walked in vain).
     const int strategy = params ? params->strategy : 0;
     const bool hybrid = strategy == JSWEEP_STRATEGY_AUTO || strategy == JSWEEP_STRATEGY_PATCH;
     const bool use_union = hybrid || strategy == JSWEEP_STRATEGY_DATA_DRIVEN;
-    const bool use_dir = hybrid || !use_union;
+    const bool use_dir = !use_union;
     BatchSweep sweep;
     UnionSweep *un = nullptr;
     if (use_union) {
@@ -466,15 +467,23 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
     std::vector<double> work(n);
     double all_work = 0.0;
     for (int i = 0; i < n; ++i) all_work += (work[i] = (double)graphs[i]->nc * graphs[i]->nd);
-    auto union_pays = [&](const std::vector<int32_t> &act) {
-        if (!use_dir) return true;
-        if (!un) return false;
+    // work of the instances in the union's current list
+    double listed_work = all_work;
+    DevBuf d_cflags(4 * n);   // the instances a compaction keeps (d_active stays the outer set)
+    // compacts the union's list when its active work has halved; true
+    // when it did (a recorded union launch then refers to the old list)
+    auto maybe_compact = [&](const std::vector<int32_t> &act) {
+        if (!un || !hybrid) return false;
         double w = 0.0;
         for (int i = 0; i < n; ++i) w += act[i] ? work[i] : 0.0;
-        return w >= kUnionMinActive * all_work;
+        if (w <= 0.0 || w >= kUnionMinActive * listed_work) return false;
+        JSW_HIP(hipMemcpyAsync(d_cflags.p, act.data(), 4 * n, hipMemcpyHostToDevice, s));
+        un->compact(d_cflags.as<int32_t>(), s);
+        listed_work = w;
+        return true;
     };
-    auto launch_sweep = [&](const int32_t *act, bool by_union) {
-        if (by_union) un->launch(act, wpb, s);
+    auto launch_sweep = [&](const int32_t *act) {
+        if (un) un->launch(act, wpb, s);
         else sweep.launch(act, s);
     };
     k_b_zero<<<grid_for(A), kB, 0, s>>>(I, d_aoff.as<int64_t>(), n, A, nullptr, 0);
@@ -524,7 +533,7 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
             if (total_sweeps >= max_iter) { rc = JSWEEP_E_NOT_CONVERGED; break; }
             k_b_source<<<grid_for(C), kB, 0, s>>>(I, d_coff.as<int64_t>(), n, C, d_active.as<int32_t>());
             if (LG) k_b_lag<<<grid_for(LG), kB, 0, s>>>(I, d_loff.as<int64_t>(), n, LG, d_active.as<int32_t>(), 0);
-            launch_sweep(d_active.as<int32_t>(), union_pays(active));
+            launch_sweep(d_active.as<int32_t>());
             ++total_sweeps;
             for (int i = 0; i < n; ++i) sweeps[i] += active[i];
             // residual from the sweep identity (one pass over psi)
@@ -550,6 +559,7 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
                 if (tol > 0.0 && rho[i] <= tol) active[i] = 0;
             }
             push_active(active);
+            maybe_compact(active);
         }
     } else {
         const int J = (params && params->inner_sweeps > 0) ? params->inner_sweeps : 400;
@@ -560,34 +570,37 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
         // recorded block (kInnerBlock is even); the first holds the marker
         // before recording.
         static_assert(kInnerBlock % 2 == 0, "the recorded block keeps the level-position arrays' alternation");
-        if (un) un->fill_current(s);
-        // one recorded block per sweep kind in use: [0] union, [1] direction kernels
-        hipGraph_t graphs_rec[2] = {nullptr, nullptr};
-        hipGraphExec_t execs[2] = {nullptr, nullptr};
+        // one recorded block of inner sweeps, recorded again whenever the
+        // union's list is compacted
+        hipGraph_t graph_rec = nullptr;
+        hipGraphExec_t exec = nullptr;
         struct GraphGuard {
             hipGraph_t *g; hipGraphExec_t *e;
-            ~GraphGuard() {
-                for (int k = 0; k < 2; ++k) {
-                    if (e[k]) (void)hipGraphExecDestroy(e[k]);
-                    if (g[k]) (void)hipGraphDestroy(g[k]);
-                }
+            void reset() {
+                if (*e) (void)hipGraphExecDestroy(*e);
+                if (*g) (void)hipGraphDestroy(*g);
+                *e = nullptr;
+                *g = nullptr;
             }
-        } guard{graphs_rec, execs};
-        for (int kind = 0; kind < 2; ++kind) {
-            if ((kind == 0 && !use_union) || (kind == 1 && !use_dir)) continue;
+            ~GraphGuard() { reset(); }
+        } guard{&graph_rec, &exec};
+        auto record_block = [&]() {
+            guard.reset();
+            if (un) un->fill_current(s);
             JSW_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             for (int k = 0; k < kInnerBlock; ++k) {
                 if (LG) k_b_lag<<<grid_for(LG), kB, 0, s>>>(I, d_loff.as<int64_t>(), n, LG, d_inner.as<int32_t>(), 1);
-                launch_sweep(d_inner.as<int32_t>(), kind == 0);
+                launch_sweep(d_inner.as<int32_t>());
                 // the norms read back after a replay are those of its last pass
                 if (k == kInnerBlock - 1) k_b_clear<<<grid_for(4 * n), kB, 0, s>>>(d_acc.as<double>(), 4 * n);
                 k_b_dphi<<<grid_for(C), kB, 0, s>>>(I, d_coff.as<int64_t>(), n, C, d_inner.as<int32_t>(),
                                                     d_withq.as<int32_t>(), d_acc.as<double>());
             }
-            hipError_t ce = hipStreamEndCapture(s, &graphs_rec[kind]);
+            hipError_t ce = hipStreamEndCapture(s, &graph_rec);
             if (ce != hipSuccess) JSW_HIP(ce);
-            JSW_HIP(hipGraphInstantiate(&execs[kind], graphs_rec[kind], nullptr, nullptr, 0));
-        }
+            JSW_HIP(hipGraphInstantiate(&exec, graph_rec, nullptr, nullptr, 0));
+        };
+        record_block();
         std::vector<double> prev_pred(n, INFINITY), target(n, 0.0);
         // From the zero iterate with no boundary inflow the residual is q
         // itself (rho = 1): the first solve is source iteration on the
@@ -614,6 +627,17 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
             for (int i = 0; i < n; ++i)
                 if (tol > 0.0 && active[i] && rho[i] <= tol) active[i] = 0;
             push_active(active);
+            // each outer step starts from the list of the instances still
+            // iterating; within it, the list follows the inner iterations'
+            // own stops
+            if (un && hybrid && un->compacted) {
+                un->expand();
+                listed_work = all_work;
+                maybe_compact(active);
+                record_block();
+            } else if (maybe_compact(active)) {
+                record_block();
+            }
             bool any = false;
             for (int i = 0; i < n; ++i) any = any || active[i];
             if (!any) break;
@@ -634,7 +658,7 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
             }
             for (int j = 0; j < J && total_sweeps < max_iter; j += kInnerBlock) {
                 JSW_HIP(hipMemcpyAsync(d_inner.p, inner_active.data(), 4 * n, hipMemcpyHostToDevice, s));
-                JSW_HIP(hipGraphLaunch(execs[union_pays(inner_active) ? 0 : 1], s));
+                JSW_HIP(hipGraphLaunch(exec, s));
                 total_sweeps += kInnerBlock;
                 JSW_HIP(hipMemcpyAsync(acc.data(), d_acc.p, 8 * 4 * n, hipMemcpyDeviceToHost, s));
                 JSW_HIP(hipStreamSynchronize(s));
@@ -655,6 +679,7 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
                     prev_pred[i] = pred;
                 }
                 if (!more) break;
+                if (maybe_compact(inner_active)) record_block();
             }
             k_b_update<<<grid_for(A), kB, 0, s>>>(I, d_aoff.as<int64_t>(), n, A, d_active.as<int32_t>());
             JSW_HIP(hipGetLastError());

@@ -390,6 +390,16 @@ struct UnionSweep {
     DevBuf uinst, uchunk, isrc, cblk, pcode, pa, pden, stream_off, rows, status, lag, vs, pk;
     DevBuf pos[2];
     int pos_state[2] = {0, 0}, cur = 0;   // element size of the empty markers each array holds (0: none)
+    // The compacted list: the chunks of the instances still iterating, in
+    // the same order and layout as the full list (program stride 64 *
+    // n_chunks); launch() walks it while `compacted`.  Its launches keep
+    // the markers of the listed chunks only, so going back to the full list
+    // (expand) refills them on its next launch.
+    DevBuf c_cblk, c_pcode, c_pa, c_pden, c_pk, c_stream_off, c_flag, c_scan, c_tmp;
+    int64_t c_chunks = 0;
+    bool compacted = false;
+    void compact(const int32_t *active, hipStream_t s);
+    void expand();
     Graph *prof = nullptr;               // the batch's first graph: its jsweep_profile records the launches
     void build(int n, Graph *const *graphs, bool fp32, hipStream_t s);
     void refresh_den(Graph *const *graphs, hipStream_t s);

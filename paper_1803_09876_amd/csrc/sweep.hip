@@ -69,6 +69,8 @@
 #include <cstdlib>
 #include <limits>
 
+#include <rocprim/device/device_scan.hpp>
+
 #include "common.hpp"
 
 namespace jsw {
@@ -1781,6 +1783,92 @@ void UnionSweep::set_rows(Graph *const *graphs, void *const *psi, const float *c
     JSW_HIP(hipStreamSynchronize(s));
 }
 
+// compaction of the union's list: flag[u] = the instance of chunk u still
+// iterates; flag[n] = 0 (the scan's last entry is the compacted length)
+__global__ void k_union_flags(const int32_t *uinst, const int32_t *active, int64_t n, int32_t *flag) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < n) flag[u] = active[uinst[u]] ? 1 : 0;
+    else if (u == n) flag[u] = 0;
+}
+
+__global__ void k_union_offsets(const int64_t *stream_off, const int32_t *scan, int64_t *c_stream_off) {
+    const int x = threadIdx.x;
+    if (x <= kStreams) c_stream_off[x] = scan[stream_off[x]];
+}
+
+// chunk u (one 64-lane workgroup) to its place scan[u] in the compacted
+// list: its block and every program array of its lanes
+template <class Real>
+__global__ void k_union_gather(const int32_t *flag, const int32_t *scan, int64_t n, int ns, const int32_t *cblk,
+                               const int32_t *pcode, const Real *pa, const Real *pden, const uint64_t *pk,
+                               int32_t *c_cblk, int32_t *c_pcode, Real *c_pa, Real *c_pden, uint64_t *c_pk) {
+    const int64_t u = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (u >= n || !flag[u]) return;
+    const int64_t v = scan[u], S = 64 * n;
+    const int32_t *b = cblk + u * kBlock;
+    int32_t *o = c_cblk + v * kBlock;
+    o[lane] = b[lane];
+    if (lane < kBlock - 64) o[64 + lane] = b[64 + lane];
+    const int64_t from = u * 64 + lane, to = v * 64 + lane;
+    for (int j = 0; j < ns; ++j) {
+        c_pcode[j * S + to] = pcode[j * S + from];
+        c_pa[j * S + to] = pa[j * S + from];
+    }
+    c_pden[to] = pden[from];
+    if (pk) c_pk[to] = pk[from];
+}
+
+void UnionSweep::compact(const int32_t *active, hipStream_t s) {
+    if (!n_chunks) return;
+    const int64_t S = 64 * n_chunks;
+    const size_t word = fp32 ? 4 : 8;
+    if (!c_cblk.p) {
+        c_cblk.alloc(4 * (size_t)kBlock * n_chunks);
+        c_pcode.alloc(4 * (size_t)ns * S);
+        c_pa.alloc(word * (size_t)ns * S);
+        c_pden.alloc(word * (size_t)S);
+        if (pk.p) c_pk.alloc(8 * (size_t)S);
+        c_stream_off.alloc(8 * (kStreams + 1));
+        c_flag.alloc(4 * (size_t)(n_chunks + 1));
+        c_scan.alloc(4 * (size_t)(n_chunks + 1));
+    }
+    const unsigned gb = (unsigned)ceil_div(n_chunks + 1, 256);
+    k_union_flags<<<gb, 256, 0, s>>>(uinst.as<int32_t>(), active, n_chunks, c_flag.as<int32_t>());
+    JSW_HIP(hipGetLastError());
+    size_t tb = 0;
+    JSW_HIP(rocprim::exclusive_scan(nullptr, tb, c_flag.as<int32_t>(), c_scan.as<int32_t>(), 0, (size_t)(n_chunks + 1),
+                                    rocprim::plus<int32_t>(), s));
+    if (c_tmp.bytes < tb + 16) c_tmp.alloc(tb + 16);
+    JSW_HIP(rocprim::exclusive_scan(c_tmp.p, tb, c_flag.as<int32_t>(), c_scan.as<int32_t>(), 0, (size_t)(n_chunks + 1),
+                                    rocprim::plus<int32_t>(), s));
+    k_union_offsets<<<1, 64, 0, s>>>(stream_off.as<int64_t>(), c_scan.as<int32_t>(), c_stream_off.as<int64_t>());
+    JSW_HIP(hipGetLastError());
+    if (fp32)
+        k_union_gather<float><<<(unsigned)n_chunks, 64, 0, s>>>(
+            c_flag.as<int32_t>(), c_scan.as<int32_t>(), n_chunks, ns, cblk.as<int32_t>(), pcode.as<int32_t>(),
+            pa.as<float>(), pden.as<float>(), pk.p ? pk.as<uint64_t>() : nullptr, c_cblk.as<int32_t>(),
+            c_pcode.as<int32_t>(), c_pa.as<float>(), c_pden.as<float>(), c_pk.p ? c_pk.as<uint64_t>() : nullptr);
+    else
+        k_union_gather<double><<<(unsigned)n_chunks, 64, 0, s>>>(
+            c_flag.as<int32_t>(), c_scan.as<int32_t>(), n_chunks, ns, cblk.as<int32_t>(), pcode.as<int32_t>(),
+            pa.as<double>(), pden.as<double>(), pk.p ? pk.as<uint64_t>() : nullptr, c_cblk.as<int32_t>(),
+            c_pcode.as<int32_t>(), c_pa.as<double>(), c_pden.as<double>(), c_pk.p ? c_pk.as<uint64_t>() : nullptr);
+    JSW_HIP(hipGetLastError());
+    int64_t h = 0;
+    JSW_HIP(hipMemcpyAsync(&h, c_stream_off.as<int64_t>() + kStreams, 8, hipMemcpyDeviceToHost, s));
+    JSW_HIP(hipStreamSynchronize(s));
+    c_chunks = h;
+    compacted = true;
+}
+
+void UnionSweep::expand() {
+    if (!compacted) return;
+    compacted = false;
+    // entries of chunks left out of the compacted launches hold fluxes
+    pos_state[0] = pos_state[1] = 0;
+}
+
 void UnionSweep::fill_current(hipStream_t s) {
     const int want = fp32 ? 4 : 8;
     if (pos_state[cur] == want || A == 0) return;
@@ -1794,14 +1882,17 @@ void UnionSweep::fill_current(hipStream_t s) {
 
 template <class Real>
 static void union_launch(UnionSweep &u, const int32_t *active, int waves_per_block, hipStream_t s) {
+    // the full list, or the compacted one (same program stride)
+    const bool c = u.compacted;
+    const int64_t listed = c ? u.c_chunks : u.n_chunks;
     SweepArgs<Real> a;
-    a.cblk = u.cblk.as<int32_t>();
+    a.cblk = (c ? u.c_cblk : u.cblk).as<int32_t>();
     a.nc = 0;
     a.stride = 64 * u.n_chunks;
-    a.pcode = u.pcode.as<int32_t>();
-    a.pk = (u.pk.p && u.ns <= 3) ? u.pk.as<uint64_t>() : nullptr;
-    a.pa = u.pa.as<Real>();
-    a.pden = u.pden.as<Real>();
+    a.pcode = (c ? u.c_pcode : u.pcode).as<int32_t>();
+    a.pk = (u.pk.p && u.ns <= 3) ? (c ? u.c_pk : u.pk).as<uint64_t>() : nullptr;
+    a.pa = (c ? u.c_pa : u.pa).as<Real>();
+    a.pden = (c ? u.c_pden : u.pden).as<Real>();
     a.vs = u.vs.p;
     a.src_dir = nullptr;
     a.psi = nullptr;
@@ -1813,10 +1904,10 @@ static void union_launch(UnionSweep &u, const int32_t *active, int waves_per_blo
     u.cur = 1 - u.cur;
     a.status = u.status.as<int32_t>();
     a.tickets = reinterpret_cast<uint32_t *>(u.status.as<char>() + 128);
-    a.stream_off = u.stream_off.as<int64_t>();
+    a.stream_off = (c ? u.c_stream_off : u.stream_off).as<int64_t>();
     a.lag_val = u.lag.as<Real>();
     a.psi_b = Real(0);
-    a.grab = u.n_chunks < (int64_t)1000000 ? 1 : 2;
+    a.grab = listed < (int64_t)1000000 ? 1 : 2;
     a.nap = 1;
     a.backoff = 3;
     a.watchdog_ticks = watchdog_ticks();
@@ -1829,7 +1920,7 @@ static void union_launch(UnionSweep &u, const int32_t *active, int waves_per_blo
     a.active = active;
     const int wpb = waves_per_block > 0 ? std::min(16, waves_per_block) : 5;
     int64_t waves = (int64_t)u.n_cu * wpb;
-    const int64_t need = std::max<int64_t>(1, u.n_chunks);
+    const int64_t need = std::max<int64_t>(1, listed);
     if (waves > need) waves = (need + wpb - 1) / wpb * wpb;
     const int blocks = (int)std::max<int64_t>(waves / wpb, kStreams);
     k_reset_tickets<<<1, 64, 0, s>>>(a.tickets);
@@ -1886,6 +1977,7 @@ UnionSweep &union_for(int n, Graph *const *graphs, bool fp32, hipStream_t s) {
         u->key = key;
         slot = std::move(u);
     }
+    slot->expand();   // every user starts from the full list
     return *slot;
 }
 
