@@ -810,7 +810,7 @@ int autotune(int32_t n, Graph *const *graphs, int32_t mode, jsweep_params *out) 
     } else {
         // the union of the instances' work lists in one data-driven launch,
         // and the batched direction kernels
-        for (int w : {4, 5, 6, 8}) cands.push_back(jsweep_params{w, 0, 0, 0, JSWEEP_STRATEGY_DATA_DRIVEN, 0});
+        for (int w : {5, 6, 8, 10, 12}) cands.push_back(jsweep_params{w, 0, 0, 0, JSWEEP_STRATEGY_DATA_DRIVEN, 0});
         for (int w : {1, 2, 4, 8, 16}) cands.push_back(jsweep_params{w, 0, 0, 0, JSWEEP_STRATEGY_DIRECTION, 0});
         cands.push_back(ring_probe);
     }
