@@ -797,10 +797,13 @@ int autotune(int32_t n, Graph *const *graphs, int32_t mode, jsweep_params *out) 
     std::vector<jsweep_params> cands;
     const jsweep_params ring_probe{0, 0, 0, 0, JSWEEP_STRATEGY_DIRECTION_LDS, 0};
     if (n == 1) {
-        // (waves per workgroup, workgroups per CU) x chunks per ticket
-        const int wb[4][2] = {{4, 1}, {5, 1}, {6, 1}, {4, 2}};
+        // (waves per workgroup, workgroups per CU) x chunks per ticket,
+        // around the defaults (5 waves and 1 chunk below a million chunks,
+        // 8 waves and 3 chunks above)
+        const int wb[6][2] = {{4, 1}, {5, 1}, {6, 1}, {8, 1}, {10, 1}, {4, 2}};
         for (const auto &w : wb)
-            for (int grab : {1, 2}) cands.push_back(jsweep_params{w[0], w[1], 0, grab, JSWEEP_STRATEGY_DATA_DRIVEN, 0});
+            for (int grab : {1, 2, 3})
+                cands.push_back(jsweep_params{w[0], w[1], 0, grab, JSWEEP_STRATEGY_DATA_DRIVEN, 0});
         for (int w : {4, 8, 16}) cands.push_back(jsweep_params{w, 0, 0, 0, JSWEEP_STRATEGY_DIRECTION, 0});
         if (sweep_strategy(*graphs[0], nullptr) == JSWEEP_STRATEGY_DIRECTION_LDS ||
             sweep_strategy(*graphs[0], &ring_probe) == JSWEEP_STRATEGY_DIRECTION_LDS)
