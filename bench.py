@@ -152,6 +152,43 @@ def time_to_tol(J, torch, g, p, tol=1e-8):
     return out
 
 
+def multigroup_bench(J, W, torch, g, p, edges, single_sweep_ms, groups=4, iters=4, warmup=1):
+    """FP64 multigroup source iterations (Jacobi over groups, every
+    (direction, group) in one sweep launch) on the workload's graph: time
+    per iteration, the multigroup sweep kernel's time and roofline, and the
+    single-group sweep time for comparison."""
+    mp = W.multigroup(p, groups)
+    st, ss, q = (torch.tensor(a, device="cuda") for a in (mp.sigma_t, mp.sigma_s, mp.q))
+    phi = torch.zeros((groups, p.n_cells), dtype=torch.float64, device="cuda")
+    J.solve_groups(g, st, ss, q, phi, tol=0.0, max_iter=warmup, allow_not_converged=True)
+
+    def timed(k):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        J.solve_groups(g, st, ss, q, phi, tol=0.0, max_iter=k, allow_not_converged=True)
+        torch.cuda.synchronize()
+        return time.perf_counter() - a
+
+    # a solve's set-up (its per-group denominators) apart from its
+    # iterations: the difference of a short and a longer solve
+    t_short = timed(2)
+    J.jsweep_profile(g, True)
+    J.jsweep_profile_read(g, reset=True)
+    t_long = timed(2 + iters)
+    n, ms = J.jsweep_profile_read(g, reset=True)
+    J.jsweep_profile(g, False)
+    sec = (t_long - t_short) / iters
+    setup = t_short - 2 * sec
+    upd = p.n_cells * p.n_dirs * groups
+    kms = ms / max(1, n)
+    del st, ss, q, phi
+    return {"groups": groups, "iteration_ms": sec * 1e3, "updates_per_s": upd / sec, "solve_setup_ms": setup * 1e3,
+            "sweep_kernel_ms": kms, "sweep_updates_per_s_kernel": upd / (kms * 1e-3),
+            "single_group_sweep_ms": single_sweep_ms, "groups_x_single_group_sweep_ms": groups * single_sweep_ms,
+            "roofline": roofline((p.n_cells * p.n_dirs + edges) * 8 * groups, kms,
+                                 f"k_sweep<double> {groups} groups {p.name}", n, edges)}
+
+
 def interior_edges(J, g, n_dirs):
     """Interior upwind edges summed over directions (lagged ones included):
     the in-degrees of every direction plus the lagged edges."""
@@ -332,6 +369,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ttt", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-groups", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--steps-only", action="store_true")
     ap.add_argument("--fp32-steps", action="store_true")
@@ -444,6 +482,10 @@ def main():
         roof32 = roofline((nc * nd + edges) * 4 + nc * nd * 4, ms32, f"k_sweep<float> {p.name}", n32, edges)
         log(f"FP32 correction sweep {ms32:.3f} ms, roofline frac {roof32['frac']:.3f}")
         line_extra["fp32_correction_sweep"] = {"updates_per_s": nc * nd / (ms32 * 1e-3), "roofline": roof32}
+        if not args.no_groups:
+            mg = multigroup_bench(J, W, torch, g, p, edges, avg64)
+            log(f"multigroup: {json.dumps(mg)}")
+            line_extra["multigroup"] = mg
         # one sweep on fixed inputs, compared with the oracle's sampled angular flux is in the GPU tests
         ttt = None
         if not args.no_ttt:

@@ -139,6 +139,62 @@ __global__ void k_group_residual(const CellRec<double, NF, DIM> *rec, const doub
     block_add(qq, acc + 1);
 }
 
+// Graphs without lagged edges keep every group's fluxes in level order for
+// the whole solve (as the single-group solve does).  First every group's
+// new phi (ascending m, through the level positions), two cells of one
+// group per thread (one when n_cells is odd); then, per cell, the residual
+// from the identity the sweep satisfies, which without lagged faces is
+// isotropic:
+//   r_{K,g} = sum over g' (ascending) of sigma_s,g'->g,K (phi'_{K,g'} - phi_{K,g'}),
+// acc[0] += (sum_m w_m) V_K r^2 and acc[1] += V_K q_{K,g}^2 over the
+// groups; phi then takes the new iterate.
+template <bool PAIRS>
+__global__ void k_group_phi_pos(const double *pos, const int32_t *posi, const double *w, int64_t nc, int nd, int G,
+                                int64_t N, double *phin, int64_t per_xcd) {
+    // each XCD takes a contiguous range, so its gathers share its own L2
+    const int64_t t = xcd_block(per_xcd) * blockDim.x + threadIdx.x;
+    const int64_t per = PAIRS ? nc / 2 : nc;
+    if (t >= per * G) return;
+    const int64_t g = t / per, K = (t - g * per) * (PAIRS ? 2 : 1);
+    if constexpr (PAIRS) {
+        double s0, s1;
+        dir_sum_pos2(w, pos + g * N, posi, nc, nd, K, s0, s1);
+        phin[g * nc + K] = s0;
+        phin[g * nc + K + 1] = s1;
+    } else {
+        phin[g * nc + K] = dir_sum_pos(w, pos + g * N, posi, nc, nd, K);
+    }
+}
+
+__global__ void k_group_res(const double *phin, double wsum, const double *q, const double *sigma_s, const double *vol,
+                            int64_t nc, int G, double *phi, double *acc) {
+    const int64_t K = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double rr = 0.0, qq = 0.0;
+    if (K < nc) {
+        const double v = vol[K];
+        for (int g = 0; g < G; ++g) {
+            double r = 0.0;
+            for (int gp = 0; gp < G; ++gp)
+                r = r + sigma_s[((int64_t)gp * G + g) * nc + K] * (phin[(int64_t)gp * nc + K] - phi[(int64_t)gp * nc + K]);
+            rr = rr + wsum * (v * (r * r));
+            const double qk = q[(int64_t)g * nc + K];
+            qq = qq + v * (qk * qk);
+        }
+        for (int g = 0; g < G; ++g) phi[(int64_t)g * nc + K] = phin[(int64_t)g * nc + K];
+    }
+    block_add(rr, acc);
+    block_add(qq, acc + 1);
+}
+
+// cell-order angular flux of every group from the level-ordered one:
+// psi[g N + m nc + K] = pos[g N + m nc + posi[m nc + K]]
+__global__ void k_group_cell_order(const double *pos, const int32_t *posi, int64_t nc, int64_t N, int G, double *psi) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * G) return;
+    const int64_t g = t / N, i = t - g * N;
+    psi[t] = pos[g * N + (i / nc) * nc + posi[i]];
+}
+
 template <int NF, int DIM>
 void launch_den(Graph &g, const double *sigma_t, int G, double *den, hipStream_t s) {
     k_den_groups<NF, DIM><<<(unsigned)ceil_div(g.n_chunks, 4), 256, 0, s>>>(
@@ -165,12 +221,18 @@ int solve_groups(Graph &g, int G, const double *sigma_t, const double *sigma_s, 
     if (G < 1 || G > kMaxGroups) fail(JSWEEP_E_INVALID_ARG, "group count out of range");
     if (params && params->priority && params->priority != g.priority) set_priority(g, params->priority, s);
     const int64_t nc = g.nc, N = nc * g.nd, S = 64 * g.n_chunks;
+    // without lagged edges the fluxes stay in level order (no cell-order
+    // copy per sweep; the residual from the sweep identity)
+    const bool lo = g.n_lag == 0;
     double *psi = psi_out;
-    if (!psi) {
+    if (!psi && !lo) {
         if (g.scratch_a.bytes < (size_t)(8 * N * G)) g.scratch_a.alloc(8 * N * G);
         psi = g.scratch_a.as<double>();
     }
-    JSW_HIP(hipMemsetAsync(psi, 0, 8 * (size_t)N * G, s));
+    if (!lo) JSW_HIP(hipMemsetAsync(psi, 0, 8 * (size_t)N * G, s));
+    double wsum = 0.0;
+    for (double x : g.weight_h) wsum += x;
+    DevBuf phin(lo ? 8 * (size_t)nc * G : 8);   // the new iterate's phi before the residual
     JSW_HIP(hipMemsetAsync(phi, 0, 8 * (size_t)nc * G, s));
     DevBuf den(8 * (size_t)std::max<int64_t>(1, S) * G), acc(64);
     DevBuf lag_val(8 * (size_t)std::max<int64_t>(1, g.n_lag) * G);
@@ -192,14 +254,29 @@ int solve_groups(Graph &g, int G, const double *sigma_t, const double *sigma_s, 
                 g.lag_mv.as<uint64_t>(), g.lag_u.as<int32_t>(), g.n_lag, G, psi, nc, N, lag_val.as<double>());
             JSW_HIP(hipGetLastError());
         }
-        launch_sweep_groups(g, psi, mg, params, s);
+        launch_sweep_groups(g, lo ? nullptr : psi, mg, params, s);
         ++it;
-        k_group_phi<<<(unsigned)ceil_div(nc * G, kB), kB, 0, s>>>(psi, g.weight.as<double>(), nc, g.nd, G, phi);
-        JSW_HIP(hipGetLastError());
         JSW_HIP(hipMemsetAsync(acc.p, 0, 16, s));
-        if (g.ctype == JSWEEP_TRI) launch_residual<3, 2>(g, psi, q, sigma_s, sigma_t, phi, psi_b, G, acc.as<double>(), s);
-        else if (g.ctype == JSWEEP_TET) launch_residual<4, 3>(g, psi, q, sigma_s, sigma_t, phi, psi_b, G, acc.as<double>(), s);
-        else launch_residual<6, 3>(g, psi, q, sigma_s, sigma_t, phi, psi_b, G, acc.as<double>(), s);
+        if (lo) {
+            const double *pos = static_cast<const double *>(last_sweep_pos(g));
+            const bool pairs = nc % 2 == 0;
+            const int64_t pxcd = xcd_per(ceil_div((pairs ? nc / 2 : nc) * G, kB));
+            if (pairs)
+                k_group_phi_pos<true><<<(unsigned)(8 * pxcd), kB, 0, s>>>(
+                    pos, g.posi.as<int32_t>(), g.weight.as<double>(), nc, g.nd, G, N, phin.as<double>(), pxcd);
+            else
+                k_group_phi_pos<false><<<(unsigned)(8 * pxcd), kB, 0, s>>>(
+                    pos, g.posi.as<int32_t>(), g.weight.as<double>(), nc, g.nd, G, N, phin.as<double>(), pxcd);
+            k_group_res<<<(unsigned)ceil_div(nc, kB), kB, 0, s>>>(phin.as<double>(), wsum, q, sigma_s,
+                                                                  g.vol.as<double>(), nc, G, phi, acc.as<double>());
+            JSW_HIP(hipGetLastError());
+        } else {
+            k_group_phi<<<(unsigned)ceil_div(nc * G, kB), kB, 0, s>>>(psi, g.weight.as<double>(), nc, g.nd, G, phi);
+            JSW_HIP(hipGetLastError());
+            if (g.ctype == JSWEEP_TRI) launch_residual<3, 2>(g, psi, q, sigma_s, sigma_t, phi, psi_b, G, acc.as<double>(), s);
+            else if (g.ctype == JSWEEP_TET) launch_residual<4, 3>(g, psi, q, sigma_s, sigma_t, phi, psi_b, G, acc.as<double>(), s);
+            else launch_residual<6, 3>(g, psi, q, sigma_s, sigma_t, phi, psi_b, G, acc.as<double>(), s);
+        }
         const int st = check_sweep_status(g, s);
         if (st != JSWEEP_OK) return st;
         double h[2];
@@ -209,6 +286,13 @@ int solve_groups(Graph &g, int G, const double *sigma_t, const double *sigma_s, 
         if (stats && stats->residual_history && hist < stats->history_capacity) stats->residual_history[hist] = rho;
         ++hist;
         if (tol > 0.0 && rho <= tol) break;
+    }
+    if (lo && psi_out && it > 0) {
+        k_group_cell_order<<<(unsigned)ceil_div(N * G, kB), kB, 0, s>>>(
+            static_cast<const double *>(last_sweep_pos(g)), g.posi.as<int32_t>(), nc, N, G, psi_out);
+        JSW_HIP(hipGetLastError());
+    } else if (lo && psi_out) {
+        JSW_HIP(hipMemsetAsync(psi_out, 0, 8 * (size_t)N * G, s));
     }
     JSW_HIP(hipStreamSynchronize(s));
     if (stats) {

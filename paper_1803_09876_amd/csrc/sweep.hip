@@ -684,15 +684,25 @@ static const void *sweep_kernel_t(int ns, bool trace, bool pk = false) {
 // slots from the arrays and ns_x from the chunk blocks
 static bool use_compact(const Graph &g, bool fp32) { return !fp32 && g.ns_x > 0; }
 
-// the single-group work-list sweeps read packed upwind positions where the
-// graph has them (programs of at most 3 slots without compact entries)
+// the work-list sweeps read packed upwind positions where the graph has
+// them (programs of at most 3 slots without compact entries)
 static bool use_packed(const Graph &g, bool fp32, int groups) {
-    return groups <= 1 && g.pk.p && g.ns <= 3 && !use_compact(g, fp32);
+    (void)groups;
+    return g.pk.p && g.ns <= 3 && !use_compact(g, fp32);
 }
 
-// multigroup FP64 kernels: NG groups per chunk, full program
+// multigroup FP64 kernels: NG groups per chunk, full program (its upwind
+// positions packed where the graph has them)
 template <int NG>
-static const void *sweep_kernel_groups(int ns) {
+static const void *sweep_kernel_groups(int ns, bool pk) {
+    if (pk) {
+        switch (ns) {
+        case 1: return reinterpret_cast<const void *>(&k_sweep<double, 1, 0, false, NG, true>);
+        case 2: return reinterpret_cast<const void *>(&k_sweep<double, 2, 0, false, NG, true>);
+        case 3: return reinterpret_cast<const void *>(&k_sweep<double, 3, 0, false, NG, true>);
+        default: fail(JSWEEP_E_DEVICE, "packed codes with more than 3 slots");
+        }
+    }
     switch (ns) {
     case 1: return reinterpret_cast<const void *>(&k_sweep<double, 1, 0, false, NG>);
     case 2: return reinterpret_cast<const void *>(&k_sweep<double, 2, 0, false, NG>);
@@ -712,9 +722,10 @@ static const void *sweep_kernel(const Graph &g, bool fp32, bool trace = false, i
     if (groups >= 1) {
         if (fp32 || trace) fail(JSWEEP_E_INVALID_ARG, "multigroup sweeps are FP64 and untraced");
         if (groups == 1) return sweep_kernel_t<double>(ns, false, use_packed(g, false, 1));
-        if (groups <= 2) return sweep_kernel_groups<2>(ns);
-        if (groups <= 4) return sweep_kernel_groups<4>(ns);
-        if (groups <= kMaxGroups) return sweep_kernel_groups<kMaxGroups>(ns);
+        const bool pk = use_packed(g, false, groups);
+        if (groups <= 2) return sweep_kernel_groups<2>(ns, pk);
+        if (groups <= 4) return sweep_kernel_groups<4>(ns, pk);
+        if (groups <= kMaxGroups) return sweep_kernel_groups<kMaxGroups>(ns, pk);
         fail(JSWEEP_E_INVALID_ARG, "too many energy groups");
     }
     if (use_compact(g, fp32)) {

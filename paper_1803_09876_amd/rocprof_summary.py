@@ -49,7 +49,7 @@ def kernels(csv_dir: str, out: str, title: str, command: str, top: int = 12) -> 
         f.write("rocprofv3 kernel statistics (durations in microseconds):\n\n"
                 "| kernel | calls | total us | average us | min us | max us | % |\n|---|---|---|---|---|---|---|\n")
         for r in rows[:top]:
-            name = r["Name"]
+            name = r["Name"].replace("(anonymous namespace)::", "")
             name = name.split("(")[0] if "jsw::" in name else (name[:70] + "..." if len(name) > 70 else name)
             f.write(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e3:.1f} | "
                     f"{float(r['AverageNs']) / 1e3:.3f} | {float(r['MinNs']) / 1e3:.3f} | "
