@@ -275,7 +275,7 @@ def cpu_baseline(W):
     }
 
 
-def ensemble_bench(J, W, torch, steps=5):
+def ensemble_bench(J, W, torch, steps=5, ttt_solves=True):
     ps = W.ensemble(seed=4, count=256, min_cells=500, max_cells=50000)
     gs = [J.build_graph(p.mesh, p.omega, p.weight) for p in ps]
     upd = sum(p.n_cells * p.n_dirs for p in ps)
@@ -305,6 +305,10 @@ def ensemble_bench(J, W, torch, steps=5):
         edges = sum(interior_edges(J, g, p.n_dirs) for g, p in zip(gs, ps))
         out["roofline"] = roofline((upd + edges) * 8, kms / launches,
                                    "k_sweep<double> union of the 256-instance ensemble", launches, edges)
+    if not ttt_solves:
+        for g in gs:
+            g.close()
+        return out
     ttt, ref = {}, None
     for name, mode in (("fp64", J.JSWEEP_FP64), ("fp32_refined", J.JSWEEP_FP32_REFINED)):
         # untimed warm-up of the mode (its first use builds the FP32 records
@@ -375,6 +379,8 @@ def main():
     ap.add_argument("--fp32-steps", action="store_true")
     ap.add_argument("--ttt-only", action="store_true",
                     help="only the time-to-1e-8 solves (FP64 and FP32-refined) of the workload; one JSON line")
+    ap.add_argument("--ensemble-steps-only", action="store_true",
+                    help="only the batched ensemble's FP64 steps (every instance iterating)")
     ap.add_argument("--ensemble-only", action="store_true",
                     help="only the 256-instance batched solve (for profiling the batch kernels)")
     ap.add_argument("--priority-list", default="", help="with --priorities: comma-separated names to time")
@@ -401,8 +407,8 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         del x, y
-    if args.ensemble_only:
-        ens = ensemble_bench(J, W, torch, steps=max(1, args.steps))
+    if args.ensemble_only or args.ensemble_steps_only:
+        ens = ensemble_bench(J, W, torch, steps=max(1, args.steps), ttt_solves=not args.ensemble_steps_only)
         print(json.dumps({"ensemble": ens}))
         return
     p = W.config(WORKLOADS[args.workload])
