@@ -443,8 +443,8 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
     // kUnionMinActive of the list's (so at most half of the listed work
     // is ever walked in vain).
     const int strategy = params ? params->strategy : 0;
-    const bool hybrid = strategy == JSWEEP_STRATEGY_AUTO || strategy == JSWEEP_STRATEGY_PATCH;
-    const bool use_union = hybrid || strategy == JSWEEP_STRATEGY_DATA_DRIVEN;
+    const bool compacting = strategy == JSWEEP_STRATEGY_AUTO || strategy == JSWEEP_STRATEGY_PATCH;
+    const bool use_union = compacting || strategy == JSWEEP_STRATEGY_DATA_DRIVEN;
     const bool use_dir = !use_union;
     BatchSweep sweep;
     UnionSweep *un = nullptr;
@@ -462,7 +462,7 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
     }
     if (use_dir)
         sweep.setup(n, graphs, refined, src_cell.data(), src_dir.data(), psi_sweep.data(), psi_b.data(),
-                    hybrid ? 0 : threads, hybrid ? JSWEEP_STRATEGY_AUTO : strategy, s);
+                    threads, strategy, s);
     const int wpb = (params && params->waves_per_block > 0) ? params->waves_per_block : 0;
     std::vector<double> work(n);
     double all_work = 0.0;
@@ -473,7 +473,7 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
     // compacts the union's list when its active work has halved; true
     // when it did (a recorded union launch then refers to the old list)
     auto maybe_compact = [&](const std::vector<int32_t> &act) {
-        if (!un || !hybrid) return false;
+        if (!un || !compacting) return false;
         double w = 0.0;
         for (int i = 0; i < n; ++i) w += act[i] ? work[i] : 0.0;
         if (w <= 0.0 || w >= kUnionMinActive * listed_work) return false;
@@ -630,7 +630,7 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
             // each outer step starts from the list of the instances still
             // iterating; within it, the list follows the inner iterations'
             // own stops
-            if (un && hybrid && un->compacted) {
+            if (un && compacting && un->compacted) {
                 un->expand();
                 listed_work = all_work;
                 maybe_compact(active);
@@ -878,8 +878,8 @@ int autotune(int32_t n, Graph *const *graphs, int32_t mode, jsweep_params *out) 
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    // for a batch the data-driven union is used through the default hybrid
-    // (union while most of the batch iterates, direction kernels after)
+    // for a batch the data-driven union is used through AUTO, which
+    // compacts its list to the instances still iterating
     if (n > 1 && best_p.strategy == JSWEEP_STRATEGY_DATA_DRIVEN) best_p.strategy = JSWEEP_STRATEGY_AUTO;
     *out = best_p;
     cache_store(key, best_p);
