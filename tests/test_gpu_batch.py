@@ -53,17 +53,21 @@ def test_batch_fp64_each_sweep_kernel(ensemble, strategy):
         assert e1 <= 1e-12 and e2 <= 1e-12
 
 
-def test_batch_data_driven_partial_convergence_and_boundary(ensemble):
-    """Union sweep with instances converging at different iterations (the
-    chunks of a converged instance only empty their entries) and boundary
-    inflow per instance: each instance's result equals its own solve."""
+@pytest.mark.parametrize("strategy", [J.JSWEEP_STRATEGY_DATA_DRIVEN, J.JSWEEP_STRATEGY_AUTO])
+def test_batch_data_driven_partial_convergence_and_boundary(ensemble, strategy):
+    """Union sweep with instances converging at different iterations and
+    boundary inflow per instance: each instance's result equals its own
+    solve.  DATA_DRIVEN keeps every instance in the list (the chunks of a
+    converged instance only empty their entries); AUTO compacts the list to
+    the instances still iterating once they hold less than half of its
+    work (here after the tenth sweep, when two of the six still iterate)."""
     probs = _problems(ensemble)
     for k, pr in enumerate(probs):
         pr["psi_boundary"] = 0.1 * k
     stats = J.solve_batch([g for _, _, g in ensemble], probs, mode=J.JSWEEP_FP64, tol=1e-9, max_iter=2000,
-                          params=J.Params(strategy=J.JSWEEP_STRATEGY_DATA_DRIVEN))
+                          params=J.Params(strategy=strategy))
     sweeps = [st["sweeps"] for st in stats]
-    print(f"[batch64 union tol] sweeps {sweeps}", flush=True)
+    print(f"[batch64 union tol s{strategy}] sweeps {sweeps}", flush=True)
     assert len(set(sweeps)) > 1
     for k, ((p, og, g), pr, st) in enumerate(zip(ensemble, probs, stats)):
         psi_ref, phi_ref, hist = og.source_iteration(p.sigma_t, p.sigma_s, p.q, p.weight, st["sweeps"], psi_b=0.1 * k)
