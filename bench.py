@@ -37,7 +37,12 @@ Also reported:
                 half tets, S4-S8) solved together by jsweep_solve_batch:
                 FP64 step throughput and time-to-1e-8, FP64 vs
                 FP32-refined (each the fastest of three after a warm-up),
-                with the autotuned launch parameters.
+                with the autotuned launch parameters;
+  hbm_copy_probe  the best of five 2 GiB device-to-device copies (HIP
+                events): the bandwidth this GPU sustains on a plain stream,
+                the FP64 sweep's algorithmic rate as a fraction of it, and
+                the sweep's counted HBM rate (counter summary over launch
+                time) beside it.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-ttt]
                        [--no-ensemble] [--copy-probe] [--steps-only]
@@ -356,6 +361,27 @@ def fp32_sweep_ms(J, torch, g, st, ss, q, nc, warmup, n=10):
     return ms32 / max(1, n32), n32
 
 
+def copy_probe(torch, mib=2048, reps=5):
+    """Achievable HBM bandwidth on this GPU: the best of `reps` device-to-
+    device copies of `mib` MiB (each moves 2 x mib MiB: read and write),
+    timed with HIP events on the current stream."""
+    n = (mib << 20) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        y.copy_(x)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del x, y
+    return {"bytes_moved": 2 * (mib << 20), "ms": best, "gbs": 2 * (mib << 20) / (best * 1e-3) / 1e9}
+
+
 def roofline(bytes_alg, avg_ms, kernel_key, launches, edges):
     achieved = bytes_alg / (avg_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -518,6 +544,12 @@ def main():
             cpu = cpu_baseline(W)
             log(f"cpu baseline: {json.dumps(cpu)}")
         line_extra["cpu_baseline"] = cpu
+        probe = copy_probe(torch)
+        probe["sweep_frac_of_copy"] = roof["achieved"] / probe["gbs"]
+        if roof["traffic"]:
+            probe["sweep_counted_gbs"] = roof["traffic"] / (avg64 * 1e-3) / 1e9
+        log(f"copy probe: {json.dumps(probe)}")
+        line_extra["hbm_copy_probe"] = probe
 
     line = {
         "metric": "cell-angle updates/s per sweep; time-to-1e-8 residual, FP32-refined vs FP64",
