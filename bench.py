@@ -47,10 +47,12 @@ Also reported:
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-ttt]
                        [--no-ensemble] [--copy-probe] [--steps-only]
                        [--workload tetcheck96_s8|hex64_s8|tetlogn60_s16] [--fp32-steps]
+                       [--groups-only]
   --copy-probe  first copies 512 MiB device to device (the calibration
                 dispatch for HBM byte counters taken on this run)
   --steps-only  only the timed steps and the roofline (for profiler runs)
   --fp32-steps  with --steps-only: time FP32 correction sweeps instead
+  --groups-only only the 4-group source iterations (for profiler runs)
 """
 from __future__ import annotations
 
@@ -189,7 +191,8 @@ def multigroup_bench(J, W, torch, g, p, edges, single_sweep_ms, groups=4, iters=
     del st, ss, q, phi
     return {"groups": groups, "iteration_ms": sec * 1e3, "updates_per_s": upd / sec, "solve_setup_ms": setup * 1e3,
             "sweep_kernel_ms": kms, "sweep_updates_per_s_kernel": upd / (kms * 1e-3),
-            "single_group_sweep_ms": single_sweep_ms, "groups_x_single_group_sweep_ms": groups * single_sweep_ms,
+            "single_group_sweep_ms": single_sweep_ms,
+            "groups_x_single_group_sweep_ms": None if single_sweep_ms is None else groups * single_sweep_ms,
             "roofline": roofline((p.n_cells * p.n_dirs + edges) * 8 * groups, kms,
                                  f"k_sweep<double> {groups} groups {p.name}", n, edges)}
 
@@ -403,6 +406,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--steps-only", action="store_true")
     ap.add_argument("--fp32-steps", action="store_true")
+    ap.add_argument("--groups-only", action="store_true",
+                    help="only the 4-group source iterations of the workload (for profiling the multigroup sweep)")
     ap.add_argument("--ttt-only", action="store_true",
                     help="only the time-to-1e-8 solves (FP64 and FP32-refined) of the workload; one JSON line")
     ap.add_argument("--ensemble-steps-only", action="store_true",
@@ -481,6 +486,11 @@ def main():
             log(f"priority {key}: {res[key]}")
         J.set_params(g, None)
         print(json.dumps({"workload": p.name, "priorities": res}))
+        return
+    if args.groups_only:
+        mg = multigroup_bench(J, W, torch, g, p, interior_edges(J, g, nd), None, iters=max(1, args.steps))
+        log(f"multigroup: {json.dumps(mg)}")
+        print(json.dumps({"workload": p.name, "multigroup": mg}))
         return
     if args.steps_only and args.fp32_steps:
         ms, n = fp32_sweep_ms(J, torch, g, st, ss, q, nc, args.warmup, args.steps)

@@ -12,6 +12,9 @@
 // energy); each group has its own denominators (sigma_t,g), source and
 // fluxes.  Layouts: sigma_t, q, phi [G][nc]; sigma_s [G][G][nc] with the
 // cross section from g' into g at (g' G + g) nc + K; psi [G][nd][nc].
+// Inside the solve the sweep's level-position fluxes, the lagged values and
+// V s keep the groups of one entry adjacent (entry e of group g at e G + g):
+// a face's upwind fluxes of every group are one memory segment.
 #include <cstring>
 
 #include <algorithm>
@@ -61,8 +64,8 @@ __global__ void k_den_groups(const int32_t *blk, int64_t n_chunks, const CellRec
 }
 
 // Group sources s_{K,g} = q_{K,g} + sum over g' (ascending) of
-// sigma_s,g'->g,K phi_{K,g'}, and V s per (group, cell) for the sweep; also
-// zeroes the stream tickets of the sweep that follows.
+// sigma_s,g'->g,K phi_{K,g'}, and V s for the sweep at K G + g; also zeroes
+// the stream tickets of the sweep that follows.
 __global__ void k_group_source(const double *q, const double *sigma_s, const double *phi, const double *vol,
                                int64_t nc, int G, double *vs, uint32_t *tickets) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -71,19 +74,20 @@ __global__ void k_group_source(const double *q, const double *sigma_s, const dou
         tickets[32 * t + kXccSlot] = kNoXcc;
     }
     if (t >= nc * G) return;
-    const int g = (int)(t / nc);
-    const int64_t K = t - (int64_t)g * nc;
-    double v = q[t];
+    const int64_t K = t / G;
+    const int g = (int)(t - K * G);
+    double v = q[(int64_t)g * nc + K];
     for (int gp = 0; gp < G; ++gp) v = v + sigma_s[((int64_t)gp * G + g) * nc + K] * phi[(int64_t)gp * nc + K];
     vs[t] = vol[K] * v;
 }
 
-// previous-iterate values on the lagged edges of every group
+// previous-iterate values on the lagged edges of every group, edge e of
+// group g at e G + g
 __global__ void k_group_lag_snapshot(const uint64_t *lag_mv, const int32_t *lag_u, int64_t n_lag, int G,
                                      const double *psi, int64_t nc, int64_t N, double *val) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_lag * G) return;
-    const int64_t g = t / n_lag, e = t - g * n_lag;
+    const int64_t e = t / G, g = t - e * G;
     val[t] = psi[g * N + (int64_t)(lag_mv[e] >> 32) * nc + lag_u[e]];
 }
 
@@ -139,30 +143,93 @@ __global__ void k_group_residual(const CellRec<double, NF, DIM> *rec, const doub
     block_add(qq, acc + 1);
 }
 
+// the G values of one level-position entry (groups adjacent; 16-byte
+// aligned when G is even)
+template <int G>
+__device__ __forceinline__ void load_groups(const double *e, double (&v)[G]) {
+    if constexpr (G % 2 == 0) {
+#pragma unroll
+        for (int h = 0; h < G / 2; ++h) {
+            const double2 x = reinterpret_cast<const double2 *>(e)[h];
+            v[2 * h] = x.x;
+            v[2 * h + 1] = x.y;
+        }
+    } else {
+#pragma unroll
+        for (int g = 0; g < G; ++g) v[g] = e[g];
+    }
+}
+
 // Graphs without lagged edges keep every group's fluxes in level order for
 // the whole solve (as the single-group solve does).  First every group's
-// new phi (ascending m, through the level positions), two cells of one
-// group per thread (one when n_cells is odd); then, per cell, the residual
-// from the identity the sweep satisfies, which without lagged faces is
-// isotropic:
+// new phi, one cell per thread: phi'_{K,g} = sum_m w_m psi at entry
+// (m nc + posi[m nc + K]) G + g, each group's sum in ascending m; a
+// direction's position is read once for all groups and the groups' fluxes
+// are one segment.  Then, per cell, the residual from the identity the
+// sweep satisfies, which without lagged faces is isotropic:
 //   r_{K,g} = sum over g' (ascending) of sigma_s,g'->g,K (phi'_{K,g'} - phi_{K,g'}),
 // acc[0] += (sum_m w_m) V_K r^2 and acc[1] += V_K q_{K,g}^2 over the
 // groups; phi then takes the new iterate.
-template <bool PAIRS>
-__global__ void k_group_phi_pos(const double *pos, const int32_t *posi, const double *w, int64_t nc, int nd, int G,
-                                int64_t N, double *phin, int64_t per_xcd) {
-    // each XCD takes a contiguous range, so its gathers share its own L2
-    const int64_t t = xcd_block(per_xcd) * blockDim.x + threadIdx.x;
-    const int64_t per = PAIRS ? nc / 2 : nc;
-    if (t >= per * G) return;
-    const int64_t g = t / per, K = (t - g * per) * (PAIRS ? 2 : 1);
-    if constexpr (PAIRS) {
-        double s0, s1;
-        dir_sum_pos2(w, pos + g * N, posi, nc, nd, K, s0, s1);
-        phin[g * nc + K] = s0;
-        phin[g * nc + K + 1] = s1;
-    } else {
-        phin[g * nc + K] = dir_sum_pos(w, pos + g * N, posi, nc, nd, K);
+template <int G>
+__global__ void k_group_phi_pos(const double *pos, const int32_t *posi, const double *w, int64_t nc, int nd,
+                                double *phin, int64_t per_xcd) {
+    // each XCD takes a contiguous range of cells, so its gathers share its own L2
+    const int64_t K = xcd_block(per_xcd) * blockDim.x + threadIdx.x;
+    if (K >= nc) return;
+    constexpr int B = G <= 2 ? 16 : G <= 4 ? 8 : 4;   // directions per batch
+    double s[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) s[g] = 0.0;
+    int32_t p[B];
+    int m = 0;
+    if (B <= nd) {
+#pragma unroll
+        for (int k = 0; k < B; ++k) p[k] = posi[(int64_t)k * nc + K];
+    }
+    for (; m + B <= nd; m += B) {
+        double v[B][G];
+#pragma unroll
+        for (int k = 0; k < B; ++k) load_groups<G>(pos + ((int64_t)(m + k) * nc + p[k]) * G, v[k]);
+        // the next batch's positions travel while these fluxes do
+        if (m + 2 * B <= nd) {
+#pragma unroll
+            for (int k = 0; k < B; ++k) p[k] = posi[(int64_t)(m + B + k) * nc + K];
+        }
+#pragma unroll
+        for (int k = 0; k < B; ++k)
+#pragma unroll
+            for (int g = 0; g < G; ++g) s[g] = s[g] + w[m + k] * v[k][g];
+    }
+    for (; m < nd; ++m) {
+        double v[G];
+        load_groups<G>(pos + ((int64_t)m * nc + posi[(int64_t)m * nc + K]) * G, v);
+#pragma unroll
+        for (int g = 0; g < G; ++g) s[g] = s[g] + w[m] * v[g];
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) phin[(int64_t)g * nc + K] = s[g];
+}
+
+template <int G>
+void launch_group_phi_pos(const double *pos, const int32_t *posi, const double *w, int64_t nc, int nd, double *phin,
+                          hipStream_t s) {
+    const int64_t pxcd = xcd_per(ceil_div(nc, kB));
+    k_group_phi_pos<G><<<(unsigned)(8 * pxcd), kB, 0, s>>>(pos, posi, w, nc, nd, phin, pxcd);
+    JSW_HIP(hipGetLastError());
+}
+
+void group_phi_pos(int G, const double *pos, const int32_t *posi, const double *w, int64_t nc, int nd, double *phin,
+                   hipStream_t s) {
+    static_assert(kMaxGroups == 8, "group_phi_pos is instantiated for 1 - 8 groups");
+    switch (G) {
+    case 1: launch_group_phi_pos<1>(pos, posi, w, nc, nd, phin, s); break;
+    case 2: launch_group_phi_pos<2>(pos, posi, w, nc, nd, phin, s); break;
+    case 3: launch_group_phi_pos<3>(pos, posi, w, nc, nd, phin, s); break;
+    case 4: launch_group_phi_pos<4>(pos, posi, w, nc, nd, phin, s); break;
+    case 5: launch_group_phi_pos<5>(pos, posi, w, nc, nd, phin, s); break;
+    case 6: launch_group_phi_pos<6>(pos, posi, w, nc, nd, phin, s); break;
+    case 7: launch_group_phi_pos<7>(pos, posi, w, nc, nd, phin, s); break;
+    default: launch_group_phi_pos<8>(pos, posi, w, nc, nd, phin, s); break;
     }
 }
 
@@ -187,12 +254,12 @@ __global__ void k_group_res(const double *phin, double wsum, const double *q, co
 }
 
 // cell-order angular flux of every group from the level-ordered one:
-// psi[g N + m nc + K] = pos[g N + m nc + posi[m nc + K]]
+// psi[g N + m nc + K] = pos[(m nc + posi[m nc + K]) G + g]
 __global__ void k_group_cell_order(const double *pos, const int32_t *posi, int64_t nc, int64_t N, int G, double *psi) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= N * G) return;
     const int64_t g = t / N, i = t - g * N;
-    psi[t] = pos[g * N + (i / nc) * nc + posi[i]];
+    psi[t] = pos[((i / nc) * nc + posi[i]) * G + g];
 }
 
 template <int NF, int DIM>
@@ -258,15 +325,8 @@ int solve_groups(Graph &g, int G, const double *sigma_t, const double *sigma_s, 
         ++it;
         JSW_HIP(hipMemsetAsync(acc.p, 0, 16, s));
         if (lo) {
-            const double *pos = static_cast<const double *>(last_sweep_pos(g));
-            const bool pairs = nc % 2 == 0;
-            const int64_t pxcd = xcd_per(ceil_div((pairs ? nc / 2 : nc) * G, kB));
-            if (pairs)
-                k_group_phi_pos<true><<<(unsigned)(8 * pxcd), kB, 0, s>>>(
-                    pos, g.posi.as<int32_t>(), g.weight.as<double>(), nc, g.nd, G, N, phin.as<double>(), pxcd);
-            else
-                k_group_phi_pos<false><<<(unsigned)(8 * pxcd), kB, 0, s>>>(
-                    pos, g.posi.as<int32_t>(), g.weight.as<double>(), nc, g.nd, G, N, phin.as<double>(), pxcd);
+            group_phi_pos(G, static_cast<const double *>(last_sweep_pos(g)), g.posi.as<int32_t>(),
+                          g.weight.as<double>(), nc, g.nd, phin.as<double>(), s);
             k_group_res<<<(unsigned)ceil_div(nc, kB), kB, 0, s>>>(phin.as<double>(), wsum, q, sigma_s,
                                                                   g.vol.as<double>(), nc, G, phi, acc.as<double>());
             JSW_HIP(hipGetLastError());

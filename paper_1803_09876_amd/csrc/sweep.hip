@@ -84,7 +84,7 @@ struct SweepArgs {
     const uint64_t *pk;                      // [stride] packed codes (NS <= 3), or null: pcode
     const Real *pa;                          // [ns * stride]
     const Real *pden;                        // [stride]
-    const void *vs;                          // [nc] V s (double) or {V, s} (float2) per cell
+    const void *vs;                          // [nc] V s per cell (float in the FP32 sweep)
     const float *src_dir;                    // [nd*nc] or null (FP32 path)
     Real *psi;                               // [nd*nc] by cell
     Real *psi_pos;                           // [nd*nc] by level position: this sweep's fluxes (upwind reads)
@@ -99,12 +99,14 @@ struct SweepArgs {
     uint32_t backoff;                        // the pause doubles every 8 polls, at most this many times
     uint64_t watchdog_ticks;
     uint32_t *stamps;                        // tracing: [3 * n_chunks] or null
-    // energy groups swept together (multigroup kernels, NG > 1): group g's
-    // arrays follow group 0's at these strides
+    // energy groups swept together (multigroup kernels, NG > 1): the
+    // level-position arrays, the lagged values and V s keep the groups of
+    // one entry adjacent (entry e of group g at e n_groups + g), so that one
+    // segment holds a face's upwind fluxes of every group; the cell-order
+    // fluxes and the denominators are group-major, at these strides
     int32_t n_groups;
-    int64_t gs_pos;                          // psi, psi_pos, pos_next: nd * nc
+    int64_t gs_pos;                          // psi (cell order): nd * nc
     int64_t gs_den;                          // pden: stride (64 * n_chunks)
-    int64_t gs_lag;                          // lag_val: n_lag
     // union of several graphs (batched sweep): a chunk's direction field is
     // a global direction whose row locates its arrays; null for one graph
     const DirRow *rows;
@@ -211,6 +213,12 @@ __device__ __forceinline__ void unpack_codes(LaneProg<Real, NS, NG> &P, int64_t 
     }
 }
 
+// Multigroup FP64 kernels with an even group count store an entry's
+// groups two at a time
+typedef double Dbl2 __attribute__((ext_vector_type(2)));
+template <class Real, int NG>
+constexpr bool kPairStores = NG > 1 && NG % 2 == 0 && sizeof(Real) == 8;
+
 // Keeps values in registers up to this point.  A store's data and address
 // registers may only be reused once the store has completed; values kept
 // live until the next chunk's poll has waited for everything (and with it
@@ -311,9 +319,12 @@ __global__ void k_sweep(SweepArgs<Real> a) {
             psi_b = (Real)row.psi_b;
         }
         const int64_t own = base + pos0 + lane;
-        // V s of the cell (one gather from a per-cell array per group; in
-        // FP32 one float, to which the per-direction source, V r, is added
-        // after the poll, so that nothing waits for these loads before it)
+        // entry stride of the level-position, lagged-value and V s arrays
+        // (the groups of an entry adjacent)
+        const int64_t gm = NG > 1 ? (int64_t)ng : 1;
+        // V s of the cell (one gather of the cell's groups; in FP32 one
+        // float, to which the per-direction source, V r, is added after the
+        // poll, so that nothing waits for these loads before it)
         Real num[NG];
 #pragma unroll
         for (int g = 0; g < NG; ++g) num[g] = Real(0);
@@ -321,9 +332,25 @@ __global__ void k_sweep(SweepArgs<Real> a) {
         float sd32 = 0.0f;
         if (active) {
             if constexpr (sizeof(Real) == 8) {
+                const double *vk = reinterpret_cast<const double *>(a.vs) + K * gm;
+                if constexpr (kPairStores<Real, NG>) {
+                    if (ng == NG) {
 #pragma unroll
-                for (int g = 0; g < NG; ++g)
-                    if (g < ng) num[g] = reinterpret_cast<const double *>(a.vs)[g * a.nc + K];
+                        for (int h = 0; h < NG / 2; ++h) {
+                            const Dbl2 x = reinterpret_cast<const Dbl2 *>(vk)[h];
+                            num[2 * h] = x.x;
+                            num[2 * h + 1] = x.y;
+                        }
+                    } else {
+#pragma unroll
+                        for (int g = 0; g < NG; ++g)
+                            if (g < ng) num[g] = vk[g];
+                    }
+                } else {
+#pragma unroll
+                    for (int g = 0; g < NG; ++g)
+                        if (g < ng) num[g] = vk[g];
+                }
             } else {
                 vs32 = reinterpret_cast<const float *>(a.vs)[K];
                 if (src_row) sd32 = __builtin_nontemporal_load(src_row + pos0 + lane);   // read once per sweep
@@ -335,15 +362,15 @@ __global__ void k_sweep(SweepArgs<Real> a) {
         // interior slot of any lane holds the empty marker; polls that keep
         // failing back off.
         const Real *from[NS];
-        int64_t gstep[NS];
         bool want[NS];
 #pragma unroll
         for (int j = 0; j < NS; ++j) {
             const int32_t cd = P.code[j];
             const bool lagged = cd <= -2 && cd != kNoFace;
             want[j] = cd >= 0 || lagged;
-            from[j] = cd >= 0 ? a.psi_pos + base + cd : lagged ? a.lag_val + (-(int64_t)cd - 2) : a.psi_pos + own;
-            gstep[j] = lagged ? a.gs_lag : a.gs_pos;
+            from[j] = cd >= 0 ? a.psi_pos + (base + cd) * gm
+                      : lagged ? a.lag_val + (-(int64_t)cd - 2) * gm
+                               : a.psi_pos + own * gm;
         }
         // the compact program's further slots: the chunk's few entries
         // (descriptor lanes 3 ..) go to their lanes
@@ -391,7 +418,7 @@ __global__ void k_sweep(SweepArgs<Real> a) {
                 for (int g = 0; g < NG; ++g)
                     if (g < ng) {
 #pragma unroll
-                        for (int j = 0; j < NS; ++j) val[g][j] = want[j] ? ld_coherent(from[j] + g * gstep[j]) : Real(0);
+                        for (int j = 0; j < NS; ++j) val[g][j] = want[j] ? ld_coherent(from[j] + g) : Real(0);
                     }
                 if constexpr (NSX > 0) {
                     if (nx > 0) {
@@ -447,9 +474,10 @@ __global__ void k_sweep(SweepArgs<Real> a) {
             if (active) __builtin_nontemporal_store(empty_marker<Real>(), a.pos_next + own);
             active = false;
         }
-        at_pos = a.psi_pos + own;
+        at_pos = a.psi_pos + own * gm;
         at_cell = cell_row ? cell_row + cell_k : nullptr;
-        at_next = a.pos_next + own;
+        at_next = a.pos_next + own * gm;
+        Real og[NG];
         if (active) {
 #pragma unroll
             for (int g = 0; g < NG; ++g) {
@@ -480,10 +508,34 @@ __global__ void k_sweep(SweepArgs<Real> a) {
                 // the level-order store publishes the flux; the cell-order
                 // copy (when the caller wants one) is read only after the
                 // kernel
-                at_pos[g * a.gs_pos] = o;
+                if constexpr (kPairStores<Real, NG>) {
+                    og[g] = o;   // stored below, two groups at a time
+                } else {
+                    at_pos[g] = o;
+                    __builtin_nontemporal_store(empty_marker<Real>(), at_next + g);   // read in the next sweep
+                }
                 if (cell_row) at_cell[g * a.gs_pos] = o;
-                __builtin_nontemporal_store(empty_marker<Real>(), at_next + g * a.gs_pos);   // read in the next sweep
                 if (g == 0) out = o;
+            }
+            if constexpr (kPairStores<Real, NG>) {
+                // an entry's groups are adjacent: with every group slot in
+                // use they are 16-byte aligned pairs, each published by one
+                // 16-byte store (its 8-byte halves are written whole)
+                if (ng == NG) {
+#pragma unroll
+                    for (int h = 0; h < NG / 2; ++h) {
+                        reinterpret_cast<Dbl2 *>(at_pos)[h] = Dbl2{og[2 * h], og[2 * h + 1]};
+                        __builtin_nontemporal_store(Dbl2{empty_marker<Real>(), empty_marker<Real>()},
+                                                    reinterpret_cast<Dbl2 *>(at_next) + h);
+                    }
+                } else {
+#pragma unroll
+                    for (int g = 0; g < NG; ++g)
+                        if (g < ng) {
+                            at_pos[g] = og[g];
+                            __builtin_nontemporal_store(empty_marker<Real>(), at_next + g);
+                        }
+                }
             }
         }
         if constexpr (TRACE) {
@@ -902,13 +954,13 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
     a.n_groups = G;
     a.gs_pos = g.nc * g.nd;
     a.gs_den = a.stride;
-    a.gs_lag = g.n_lag;
     if (mg) a.pden = reinterpret_cast<const Real *>(mg->den);
     // the two level-position arrays: this sweep's must hold the empty marker
-    // of its precision in every entry of its G group blocks (the previous
-    // sweep of the same precision left it so; otherwise it is filled here),
-    // and the sweep empties the other one for the next sweep.  State: element
-    // size | (group blocks holding the marker) << 8.
+    // of its precision in its first G nc nd entries (every group of every
+    // position; the previous sweep of the same precision left it so,
+    // otherwise it is filled here), and the sweep empties the other one for
+    // the next sweep.  State: element size | (G of the entries holding the
+    // marker) << 8; a prefix of G' >= G groups' entries covers G's.
     const int want = (int)sizeof(Real) | (G << 8);
     const size_t need_bytes = (size_t)8 * g.nc * g.nd * G;
     for (int i = 0; i < 2; ++i)
@@ -1926,7 +1978,6 @@ static void union_launch(UnionSweep &u, const int32_t *active, int waves_per_blo
     a.n_groups = 1;
     a.gs_pos = u.A;
     a.gs_den = a.stride;
-    a.gs_lag = u.LG;
     a.rows = u.rows.as<DirRow>();
     a.active = active;
     // default (measured on the 256-instance ensemble, time to 1e-8 with a

@@ -40,8 +40,13 @@ def _run(gg, mp, iters, tol=0.0, psi_b=0.0, history=0):
     return host(phi), host(psi), st
 
 
-@pytest.mark.parametrize("groups", [2, 3, 4, 8])
+@pytest.mark.parametrize("groups", [1, 2, 3, 4, 8])
 def test_groups_fixed_iterations(cases, groups):
+    """Six iterations against the oracle (graphs with and without lagged
+    edges; group counts odd and even, one, and the kernel's largest), then a
+    single-group sweep of the same graph: the multigroup sweep keeps a
+    position's groups adjacent in the level-position arrays, and must leave
+    the next sweep's array empty for any group count."""
     for name, p, og, gg in cases:
         mp = W.multigroup(p, groups, seed=groups)
         psi_ref, phi_ref, hist = og.mg_source_iteration(mp.sigma_t, mp.sigma_s, mp.q, mp.weight, 6, psi_b=0.2)
@@ -52,6 +57,9 @@ def test_groups_fixed_iterations(cases, groups):
         assert st["sweeps"] == 6
         assert e1 <= 1e-12 and e2 <= 1e-12, name
         assert np.allclose(st["history"], hist, rtol=1e-9, atol=0), name
+        out = dev(np.zeros((p.n_dirs, p.n_cells)))
+        J.sweep(gg, dev(p.sigma_t), dev(p.q), out)
+        assert np.array_equal(host(out), og.sweep(p.sigma_t, p.q)), name
 
 
 def test_groups_converge_to_oracle(cases):
