@@ -40,7 +40,7 @@ def _run(gg, mp, iters, tol=0.0, psi_b=0.0, history=0):
     return host(phi), host(psi), st
 
 
-@pytest.mark.parametrize("groups", [1, 2, 3, 4, 8])
+@pytest.mark.parametrize("groups", [1, 2, 3, 4, 6, 8])
 def test_groups_fixed_iterations(cases, groups):
     """Six iterations against the oracle (graphs with and without lagged
     edges; group counts odd and even, one, and the kernel's largest), then a
