@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <initializer_list>
 #include <memory>
 #include <string>
 #include <utility>
@@ -93,6 +94,10 @@ constexpr int kBlockExtra = 7;
 // entry of the chunk block: [65] the entry count, [70 + 2 e, 72 + 2 e)
 // entry e = (lane | slot << 8, the int32 code), at most kPkEscMax of them
 // (words 67 - 69 stay free for the batched sweep's direction base).
+// Graph::dd_state bits of a level-position array holding sign-tagged FP64
+// fluxes, and whether their tag (the sign bit) is set
+constexpr int kDdTagged = 1 << 16;
+constexpr int kDdTagSet = 1 << 17;
 constexpr int kPkBits = 21;
 constexpr uint32_t kPkMask = (1u << kPkBits) - 1u;
 constexpr uint32_t kPkNoFace = kPkMask;
@@ -251,7 +256,8 @@ struct Graph {
     bool den64_ok = false, den32_ok = false;
     DevBuf psi_pos;                      // [nd*nc] fluxes of the running sweep in level order (LDS-window sweeps)
     DevBuf dd_pos[2];                    // [nd*nc] alternating level-order flux arrays of the work-list sweep
-    int dd_state[2] = {0, 0};            // element size | group blocks << 8 of the empty markers each array holds, 0 if unknown
+    int dd_state[2] = {0, 0};            // element size | groups << 8 of the markers each array holds (0: unknown),
+                                         // or | kDdTagged (| kDdTagSet) for sign-tagged FP64 fluxes
     int dd_cur = 0;                      // array of the next work-list sweep
     DevBuf pvol64, pvol32;               // [64 n_chunks] cell volume in program order (ring sweep)
     DevBuf vsc;                          // [nc] V s (or {V, s}) of the running sweep, per cell
@@ -307,12 +313,16 @@ struct SweepSrc {
 void refresh_sigma(Graph &g, const double *sigma_t, bool fp32, hipStream_t s);
 // sweep-program denominators from the records' sigma_t V, where not valid
 void ensure_den(Graph &g, bool fp32, hipStream_t s);
-// prepared: g.vsc already holds V s of src_cell for this sweep (FP64) or
-// the (V, s) pairs (FP32) and the data-driven kernel's tickets are zero (the
-// FP64 solve prepares the next sweep in its residual kernels, the FP32
-// correction solve in k_dphi)
+// prepared: g.vsc already holds V s of src_cell for this sweep (FP64, or
+// one float per cell in FP32) and the data-driven kernel's tickets are zero
+// (the FP64 solve prepares the next sweep in its residual kernels, the FP32
+// correction solve in k_dphi).  nonneg: the caller has checked that every
+// input of the sweep (source, cross sections, boundary and lagged values)
+// is non-negative, so every flux is: the data-driven sweep then tags its
+// fluxes by sign instead of writing empty markers, and readers of its
+// level-position array mask the sign bit (last_sweep_keep)
 void launch_sweep64(Graph &g, const double *src_cell, double *psi, double psi_b, const jsweep_params *p, hipStream_t s,
-                    bool prepared = false);
+                    bool prepared = false, bool nonneg = false);
 void launch_sweep32(Graph &g, const float *src_dir, const float *src_cell, float *psi, const jsweep_params *p,
                     hipStream_t s, bool prepared = false);
 // The data-driven sweep always leaves its fluxes in level-position order
@@ -321,6 +331,12 @@ void launch_sweep32(Graph &g, const float *src_dir, const float *src_cell, float
 // the cell-order copy.  This returns the array the last data-driven sweep
 // filled (double or float by that sweep's precision).
 void *last_sweep_pos(Graph &g);
+// The bits to keep of each FP64 flux read from last_sweep_pos: all, or all
+// but the sign bit when that sweep tagged its fluxes by sign
+uint64_t last_sweep_keep(const Graph &g);
+// Whether every element of the given device arrays (pointer, length; null
+// pointers skipped) is >= 0 (NaN is not); one synchronisation
+bool all_nonnegative(std::initializer_list<std::pair<const double *, int64_t>> arrays, hipStream_t s);
 // A direction of a union of graphs swept by one launch of the data-driven
 // kernel (the batched solve): where its arrays start.  pos_base: its first
 // level position in the union's level-position arrays; psi_row: the
@@ -351,6 +367,7 @@ struct GroupSweep {
     const double *den;
     const double *lag_val;
     double psi_b;
+    bool nonneg;                         // every input non-negative (see launch_sweep64)
 };
 void launch_sweep_groups(Graph &g, double *psi, const GroupSweep &mg, const jsweep_params *p, hipStream_t s);
 // FP64 data-driven sweep whose per-cell V s goes to vs_buf (8 n_cells bytes,
@@ -358,7 +375,8 @@ void launch_sweep_groups(Graph &g, double *psi, const GroupSweep &mg, const jswe
 // arrays are allocated when it is built)
 void launch_sweep64_staged(Graph &g, const double *src_cell, double *psi, double psi_b, void *vs_buf, hipStream_t s);
 int check_sweep_status(Graph &g, hipStream_t s);   // JSWEEP_OK, JSWEEP_E_STALLED or JSWEEP_E_PLACEMENT
-int persistent_waves(Graph &g, bool fp32, const jsweep_params *p, int *waves_per_block, int groups = 0);
+int persistent_waves(Graph &g, bool fp32, const jsweep_params *p, int *waves_per_block, int groups = 0,
+                     bool sg = false);
 int sweep_strategy(const Graph &g, const jsweep_params *p);
 
 // patch-task sweep (patch.hip): program built on first use; false when the

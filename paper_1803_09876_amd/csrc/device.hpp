@@ -63,13 +63,22 @@ __device__ inline int64_t xcd_block(int64_t per_xcd) {
 }
 inline int64_t xcd_per(int64_t blocks) { return (blocks + 7) / 8; }
 
+// An FP64 flux read from a sweep's level-position array with only the
+// bits in keep (all but the sign bit when that sweep tagged its fluxes by
+// sign); FP32 fluxes are never tagged
+__device__ __forceinline__ double kept(double v, uint64_t keep) {
+    return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, v) & keep);
+}
+__device__ __forceinline__ float kept(float v, uint64_t) { return v; }
+
 // dir_sum over the level-ordered fluxes of a sweep: the flux of cell K in
 // direction m sits at m nc + posi[m nc + K].  Sixteen directions' positions
 // are loaded together, then their fluxes, and the next sixteen positions
 // are loaded while those fluxes travel (one round trip per batch instead
 // of two); the sum runs in ascending m.
 template <class T>
-__device__ inline double dir_sum_pos(const double *w, const T *pos, const int32_t *posi, int64_t nc, int nd, int64_t K) {
+__device__ inline double dir_sum_pos(const double *w, const T *pos, const int32_t *posi, int64_t nc, int nd, int64_t K,
+                                     uint64_t keep = ~0ull) {
     double s = 0.0;
     int m = 0;
     int32_t p[16];
@@ -80,7 +89,7 @@ __device__ inline double dir_sum_pos(const double *w, const T *pos, const int32_
     for (; m + 16 <= nd; m += 16) {
         T v[16];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) v[k] = pos[(int64_t)(m + k) * nc + p[k]];
+        for (int k = 0; k < 16; ++k) v[k] = kept(pos[(int64_t)(m + k) * nc + p[k]], keep);
         if (m + 32 <= nd) {
 #pragma unroll
             for (int k = 0; k < 16; ++k) p[k] = posi[(int64_t)(m + 16 + k) * nc + K];
@@ -88,7 +97,7 @@ __device__ inline double dir_sum_pos(const double *w, const T *pos, const int32_
 #pragma unroll
         for (int k = 0; k < 16; ++k) s = s + w[m + k] * (double)v[k];
     }
-    for (; m < nd; ++m) s = s + w[m] * (double)pos[(int64_t)m * nc + posi[(int64_t)m * nc + K]];
+    for (; m < nd; ++m) s = s + w[m] * (double)kept(pos[(int64_t)m * nc + posi[(int64_t)m * nc + K]], keep);
     return s;
 }
 
@@ -96,7 +105,7 @@ __device__ inline double dir_sum_pos(const double *w, const T *pos, const int32_
 // positions are one 8-byte load
 template <class T>
 __device__ inline void dir_sum_pos2(const double *w, const T *pos, const int32_t *posi, int64_t nc, int nd, int64_t K,
-                                    double &s0, double &s1) {
+                                    double &s0, double &s1, uint64_t keep = ~0ull) {
     s0 = 0.0;
     s1 = 0.0;
     int m = 0;
@@ -110,8 +119,8 @@ __device__ inline void dir_sum_pos2(const double *w, const T *pos, const int32_t
         T v0[B], v1[B];
 #pragma unroll
         for (int k = 0; k < B; ++k) {
-            v0[k] = pos[(int64_t)(m + k) * nc + p[k].x];
-            v1[k] = pos[(int64_t)(m + k) * nc + p[k].y];
+            v0[k] = kept(pos[(int64_t)(m + k) * nc + p[k].x], keep);
+            v1[k] = kept(pos[(int64_t)(m + k) * nc + p[k].y], keep);
         }
         // the next batch's positions travel while these fluxes do
         if (m + 2 * B <= nd) {
@@ -126,8 +135,8 @@ __device__ inline void dir_sum_pos2(const double *w, const T *pos, const int32_t
     }
     for (; m < nd; ++m) {
         const int2 pm = *reinterpret_cast<const int2 *>(posi + (int64_t)m * nc + K);
-        s0 = s0 + w[m] * (double)pos[(int64_t)m * nc + pm.x];
-        s1 = s1 + w[m] * (double)pos[(int64_t)m * nc + pm.y];
+        s0 = s0 + w[m] * (double)kept(pos[(int64_t)m * nc + pm.x], keep);
+        s1 = s1 + w[m] * (double)kept(pos[(int64_t)m * nc + pm.y], keep);
     }
 }
 

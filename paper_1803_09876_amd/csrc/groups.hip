@@ -144,19 +144,19 @@ __global__ void k_group_residual(const CellRec<double, NF, DIM> *rec, const doub
 }
 
 // the G values of one level-position entry (groups adjacent; 16-byte
-// aligned when G is even)
+// aligned when G is even), with only the bits in keep
 template <int G>
-__device__ __forceinline__ void load_groups(const double *e, double (&v)[G]) {
+__device__ __forceinline__ void load_groups(const double *e, double (&v)[G], uint64_t keep) {
     if constexpr (G % 2 == 0) {
 #pragma unroll
         for (int h = 0; h < G / 2; ++h) {
             const double2 x = reinterpret_cast<const double2 *>(e)[h];
-            v[2 * h] = x.x;
-            v[2 * h + 1] = x.y;
+            v[2 * h] = kept(x.x, keep);
+            v[2 * h + 1] = kept(x.y, keep);
         }
     } else {
 #pragma unroll
-        for (int g = 0; g < G; ++g) v[g] = e[g];
+        for (int g = 0; g < G; ++g) v[g] = kept(e[g], keep);
     }
 }
 
@@ -165,14 +165,15 @@ __device__ __forceinline__ void load_groups(const double *e, double (&v)[G]) {
 // new phi, one cell per thread: phi'_{K,g} = sum_m w_m psi at entry
 // (m nc + posi[m nc + K]) G + g, each group's sum in ascending m; a
 // direction's position is read once for all groups and the groups' fluxes
-// are one segment.  Then, per cell, the residual from the identity the
+// are one segment (each read with the bits in keep, see last_sweep_keep).
+// Then, per cell, the residual from the identity the
 // sweep satisfies, which without lagged faces is isotropic:
 //   r_{K,g} = sum over g' (ascending) of sigma_s,g'->g,K (phi'_{K,g'} - phi_{K,g'}),
 // acc[0] += (sum_m w_m) V_K r^2 and acc[1] += V_K q_{K,g}^2 over the
 // groups; phi then takes the new iterate.
 template <int G>
 __global__ void k_group_phi_pos(const double *pos, const int32_t *posi, const double *w, int64_t nc, int nd,
-                                double *phin, int64_t per_xcd) {
+                                double *phin, int64_t per_xcd, uint64_t keep) {
     // each XCD takes a contiguous range of cells, so its gathers share its own L2
     const int64_t K = xcd_block(per_xcd) * blockDim.x + threadIdx.x;
     if (K >= nc) return;
@@ -189,7 +190,7 @@ __global__ void k_group_phi_pos(const double *pos, const int32_t *posi, const do
     for (; m + B <= nd; m += B) {
         double v[B][G];
 #pragma unroll
-        for (int k = 0; k < B; ++k) load_groups<G>(pos + ((int64_t)(m + k) * nc + p[k]) * G, v[k]);
+        for (int k = 0; k < B; ++k) load_groups<G>(pos + ((int64_t)(m + k) * nc + p[k]) * G, v[k], keep);
         // the next batch's positions travel while these fluxes do
         if (m + 2 * B <= nd) {
 #pragma unroll
@@ -202,7 +203,7 @@ __global__ void k_group_phi_pos(const double *pos, const int32_t *posi, const do
     }
     for (; m < nd; ++m) {
         double v[G];
-        load_groups<G>(pos + ((int64_t)m * nc + posi[(int64_t)m * nc + K]) * G, v);
+        load_groups<G>(pos + ((int64_t)m * nc + posi[(int64_t)m * nc + K]) * G, v, keep);
 #pragma unroll
         for (int g = 0; g < G; ++g) s[g] = s[g] + w[m] * v[g];
     }
@@ -212,24 +213,24 @@ __global__ void k_group_phi_pos(const double *pos, const int32_t *posi, const do
 
 template <int G>
 void launch_group_phi_pos(const double *pos, const int32_t *posi, const double *w, int64_t nc, int nd, double *phin,
-                          hipStream_t s) {
+                          uint64_t keep, hipStream_t s) {
     const int64_t pxcd = xcd_per(ceil_div(nc, kB));
-    k_group_phi_pos<G><<<(unsigned)(8 * pxcd), kB, 0, s>>>(pos, posi, w, nc, nd, phin, pxcd);
+    k_group_phi_pos<G><<<(unsigned)(8 * pxcd), kB, 0, s>>>(pos, posi, w, nc, nd, phin, pxcd, keep);
     JSW_HIP(hipGetLastError());
 }
 
 void group_phi_pos(int G, const double *pos, const int32_t *posi, const double *w, int64_t nc, int nd, double *phin,
-                   hipStream_t s) {
+                   uint64_t keep, hipStream_t s) {
     static_assert(kMaxGroups == 8, "group_phi_pos is instantiated for 1 - 8 groups");
     switch (G) {
-    case 1: launch_group_phi_pos<1>(pos, posi, w, nc, nd, phin, s); break;
-    case 2: launch_group_phi_pos<2>(pos, posi, w, nc, nd, phin, s); break;
-    case 3: launch_group_phi_pos<3>(pos, posi, w, nc, nd, phin, s); break;
-    case 4: launch_group_phi_pos<4>(pos, posi, w, nc, nd, phin, s); break;
-    case 5: launch_group_phi_pos<5>(pos, posi, w, nc, nd, phin, s); break;
-    case 6: launch_group_phi_pos<6>(pos, posi, w, nc, nd, phin, s); break;
-    case 7: launch_group_phi_pos<7>(pos, posi, w, nc, nd, phin, s); break;
-    default: launch_group_phi_pos<8>(pos, posi, w, nc, nd, phin, s); break;
+    case 1: launch_group_phi_pos<1>(pos, posi, w, nc, nd, phin, keep, s); break;
+    case 2: launch_group_phi_pos<2>(pos, posi, w, nc, nd, phin, keep, s); break;
+    case 3: launch_group_phi_pos<3>(pos, posi, w, nc, nd, phin, keep, s); break;
+    case 4: launch_group_phi_pos<4>(pos, posi, w, nc, nd, phin, keep, s); break;
+    case 5: launch_group_phi_pos<5>(pos, posi, w, nc, nd, phin, keep, s); break;
+    case 6: launch_group_phi_pos<6>(pos, posi, w, nc, nd, phin, keep, s); break;
+    case 7: launch_group_phi_pos<7>(pos, posi, w, nc, nd, phin, keep, s); break;
+    default: launch_group_phi_pos<8>(pos, posi, w, nc, nd, phin, keep, s); break;
     }
 }
 
@@ -254,12 +255,13 @@ __global__ void k_group_res(const double *phin, double wsum, const double *q, co
 }
 
 // cell-order angular flux of every group from the level-ordered one:
-// psi[g N + m nc + K] = pos[(m nc + posi[m nc + K]) G + g]
-__global__ void k_group_cell_order(const double *pos, const int32_t *posi, int64_t nc, int64_t N, int G, double *psi) {
+// psi[g N + m nc + K] = pos[(m nc + posi[m nc + K]) G + g] (the bits in keep)
+__global__ void k_group_cell_order(const double *pos, const int32_t *posi, int64_t nc, int64_t N, int G, double *psi,
+                                   uint64_t keep) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= N * G) return;
     const int64_t g = t / N, i = t - g * N;
-    psi[t] = pos[((i / nc) * nc + posi[i]) * G + g];
+    psi[t] = kept(pos[((i / nc) * nc + posi[i]) * G + g], keep);
 }
 
 template <int NF, int DIM>
@@ -308,7 +310,10 @@ int solve_groups(Graph &g, int G, const double *sigma_t, const double *sigma_s, 
     else if (g.ctype == JSWEEP_TET) launch_den<4, 3>(g, sigma_t, G, den.as<double>(), s);
     else launch_den<6, 3>(g, sigma_t, G, den.as<double>(), s);
     uint32_t *tickets = reinterpret_cast<uint32_t *>(g.status.as<char>() + 128);
-    const GroupSweep mg{G, den.as<double>(), lag_val.as<double>(), psi_b};
+    // with every input non-negative every flux is (phi starts from zero,
+    // lagged values from earlier sweeps): the sweeps tag their fluxes by sign
+    const bool nonneg = psi_b >= 0.0 && all_nonnegative({{sigma_t, nc * G}, {sigma_s, nc * G * G}, {q, nc * G}}, s);
+    const GroupSweep mg{G, den.as<double>(), lag_val.as<double>(), psi_b, nonneg};
     int it = 0, hist = 0, rc = JSWEEP_OK;
     double rho = INFINITY;
     while (true) {
@@ -326,7 +331,7 @@ int solve_groups(Graph &g, int G, const double *sigma_t, const double *sigma_s, 
         JSW_HIP(hipMemsetAsync(acc.p, 0, 16, s));
         if (lo) {
             group_phi_pos(G, static_cast<const double *>(last_sweep_pos(g)), g.posi.as<int32_t>(),
-                          g.weight.as<double>(), nc, g.nd, phin.as<double>(), s);
+                          g.weight.as<double>(), nc, g.nd, phin.as<double>(), last_sweep_keep(g), s);
             k_group_res<<<(unsigned)ceil_div(nc, kB), kB, 0, s>>>(phin.as<double>(), wsum, q, sigma_s,
                                                                   g.vol.as<double>(), nc, G, phi, acc.as<double>());
             JSW_HIP(hipGetLastError());
@@ -349,7 +354,8 @@ int solve_groups(Graph &g, int G, const double *sigma_t, const double *sigma_s, 
     }
     if (lo && psi_out && it > 0) {
         k_group_cell_order<<<(unsigned)ceil_div(N * G, kB), kB, 0, s>>>(
-            static_cast<const double *>(last_sweep_pos(g)), g.posi.as<int32_t>(), nc, N, G, psi_out);
+            static_cast<const double *>(last_sweep_pos(g)), g.posi.as<int32_t>(), nc, N, G, psi_out,
+            last_sweep_keep(g));
         JSW_HIP(hipGetLastError());
     } else if (lo && psi_out) {
         JSW_HIP(hipMemsetAsync(psi_out, 0, 8 * (size_t)N * G, s));

@@ -219,9 +219,10 @@ struct LagCells {
 // Lagged in-edges of cell v: the un-lagged residual's extra term
 // w_m V ((d + l)^2 - d^2) per direction m, l = sum a (psi_now - psi_prev) / V;
 // the lagged values are replaced by the new iterate's for the next sweep
-// (psi in cell order, or in level-position order when posi is given)
+// (psi in cell order, or in level-position order when posi is given, its
+// values masked by keep)
 __device__ inline double lag_terms(const LagCells &L, const double *psi, const int32_t *posi, const double *w,
-                                   int64_t nc, int64_t v, double V, double d) {
+                                   int64_t nc, int64_t v, double V, double d, uint64_t keep) {
     double c = 0.0;
     for (int32_t gi = L.cptr[v]; gi < L.cptr[v + 1]; ++gi) {
         const int64_t e = L.cgrp[gi];
@@ -230,7 +231,7 @@ __device__ inline double lag_terms(const LagCells &L, const double *psi, const i
         double l = 0.0;
         for (int64_t f = e; f < L.n && L.mv[f] == key; ++f) {
             const int64_t u = L.u[f];
-            const double now = psi[m * nc + (posi ? (int64_t)posi[m * nc + u] : u)];
+            const double now = kept(psi[m * nc + (posi ? (int64_t)posi[m * nc + u] : u)], keep);
             l = l + L.a[f] * (now - L.val[f]) / V;
             L.val[f] = now;
         }
@@ -259,7 +260,8 @@ __device__ inline void next_sweep_setup(int64_t t, const int32_t *status, double
 // k_phi_delta: phi' (ascending m), the isotropic part d = sigma_s (phi' -
 // phi) and its norm W V d^2 (W = sum of the weights), and V q^2.  psi is
 // the sweep's output in cell order, or (posi given) the level-ordered
-// array the data-driven sweep filled, read through the level positions.
+// array the data-driven sweep filled, read through the level positions with
+// only the bits in keep (see last_sweep_keep).
 // The lagged in-faces of the cell add their terms (lag_terms), so that one
 // kernel gives the whole residual norm.  It also prepares the next sweep:
 // its source q + sigma_s phi', the product V s the sweep kernels read, the
@@ -267,19 +269,19 @@ __device__ inline void next_sweep_setup(int64_t t, const int32_t *status, double
 __global__ void k_phi_delta(const double *psi, const int32_t *posi, const double *w, double wsum, const double *q,
                             const double *sigma_s, const double *vol, int64_t nc, int nd, double *phi, double *acc,
                             double *src_next, double *vs_next, LagCells L, const int32_t *status, double *acc_next,
-                            uint32_t *tickets, int64_t per_xcd) {
+                            uint32_t *tickets, int64_t per_xcd, uint64_t keep) {
     const int64_t K = xcd_block(per_xcd) * blockDim.x + threadIdx.x;
     next_sweep_setup(K, status, acc, acc_next, tickets);
     double a = 0.0, b = 0.0;
     if (K < nc) {
-        const double s = posi ? dir_sum_pos(w, psi, posi, nc, nd, K) : dir_sum(w, psi, nc, nd, K);
+        const double s = posi ? dir_sum_pos(w, psi, posi, nc, nd, K, keep) : dir_sum(w, psi, nc, nd, K);
         const double d = sigma_s[K] * (s - phi[K]);
         phi[K] = s;
         const double sn = q[K] + sigma_s[K] * s;
         src_next[K] = sn;
         vs_next[K] = vol[K] * sn;
         a = wsum * (vol[K] * (d * d));
-        if (L.n > 0) a = a + lag_terms(L, psi, posi, w, nc, K, vol[K], d);
+        if (L.n > 0) a = a + lag_terms(L, psi, posi, w, nc, K, vol[K], d, keep);
         b = vol[K] * (q[K] * q[K]);
     }
     block_add(a, acc);
@@ -292,14 +294,14 @@ __global__ void k_phi_delta(const double *psi, const int32_t *posi, const double
 __global__ void k_phi_delta2(const double *psi, const int32_t *posi, const double *w, double wsum, const double *q,
                              const double *sigma_s, const double *vol, int64_t nc, int nd, double *phi, double *acc,
                              double *src_next, double *vs_next, LagCells L, const int32_t *status, double *acc_next,
-                             uint32_t *tickets, int64_t per_xcd) {
+                             uint32_t *tickets, int64_t per_xcd, uint64_t keep) {
     const int64_t t = xcd_block(per_xcd) * blockDim.x + threadIdx.x;
     next_sweep_setup(t, status, acc, acc_next, tickets);
     const int64_t K = 2 * t;
     double a = 0.0, b = 0.0;
     if (K < nc) {
         double s[2];
-        if (posi) dir_sum_pos2(w, psi, posi, nc, nd, K, s[0], s[1]);
+        if (posi) dir_sum_pos2(w, psi, posi, nc, nd, K, s[0], s[1], keep);
         else dir_sum2(w, psi, nc, nd, K, s[0], s[1]);
         const double2 ph = *reinterpret_cast<const double2 *>(phi + K);
         const double2 ss = *reinterpret_cast<const double2 *>(sigma_s + K);
@@ -311,7 +313,7 @@ __global__ void k_phi_delta2(const double *psi, const int32_t *posi, const doubl
             d[i] = sig[i] * (s[i] - old[i]);
             sn[i] = qk[i] + sig[i] * s[i];
             a = a + wsum * (vk[i] * (d[i] * d[i]));
-            if (L.n > 0) a = a + lag_terms(L, psi, posi, w, nc, K + i, vk[i], d[i]);
+            if (L.n > 0) a = a + lag_terms(L, psi, posi, w, nc, K + i, vk[i], d[i], keep);
             b = b + vk[i] * (qk[i] * qk[i]);
         }
         *reinterpret_cast<double2 *>(phi + K) = make_double2(s[0], s[1]);
@@ -423,10 +425,11 @@ __global__ void k_update(double *psi, const float *dpsi, const int32_t *posi, in
 }
 
 // cell-order copy of level-ordered fluxes: psi[m nc + K] = pos[m nc + posi[m nc + K]]
+// (the bits in keep)
 __global__ void k_cell_order(const double *pos, const int32_t *posi, int64_t nc, int64_t n, double *psi,
-                             int64_t per_xcd) {
+                             int64_t per_xcd, uint64_t keep) {
     int64_t i = xcd_block(per_xcd) * blockDim.x + threadIdx.x;
-    if (i < n) psi[i] = pos[(i / nc) * nc + posi[i]];
+    if (i < n) psi[i] = kept(pos[(i / nc) * nc + posi[i]], keep);
 }
 
 // r in level-position order from its cell-order copy:
@@ -476,6 +479,29 @@ static double residual(Graph &g, const double *psi, const double *q, const doubl
 
 static void ensure(DevBuf &b, size_t bytes) {
     if (b.bytes < bytes) b.alloc(bytes);
+}
+
+// sets *flag when an element is negative or NaN
+__global__ void k_flag_negative(const double *x, int64_t n, int32_t *flag) {
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    bool neg = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) neg = neg || !(x[i] >= 0.0);
+    if (neg) atomicOr(flag, 1);
+}
+
+bool all_nonnegative(std::initializer_list<std::pair<const double *, int64_t>> arrays, hipStream_t s) {
+    DevBuf flag(4);
+    JSW_HIP(hipMemsetAsync(flag.p, 0, 4, s));
+    for (const auto &x : arrays)
+        if (x.first && x.second > 0) {
+            k_flag_negative<<<(int)std::min<int64_t>(ceil_div(x.second, kB), 4096), kB, 0, s>>>(x.first, x.second,
+                                                                                              flag.as<int32_t>());
+            JSW_HIP(hipGetLastError());
+        }
+    int32_t h = 0;
+    JSW_HIP(hipMemcpyAsync(&h, flag.p, 4, hipMemcpyDeviceToHost, s));
+    JSW_HIP(hipStreamSynchronize(s));
+    return h == 0;
 }
 
 int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *q, double psi_b, int32_t mode,
@@ -539,6 +565,12 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
         const bool pairs = g.nc % 2 == 0 && (lo || al16(psi)) && al16(phi) && al16(q) && al16(sigma_s) && al16(src) &&
                            al16(g.vol.p) && al16(g.vsc.p);
         const int32_t *posi = lo ? g.posi.as<int32_t>() : nullptr;
+        // with every input non-negative (cross sections, source, boundary
+        // inflow, the initial iterate) every flux of every sweep is, and the
+        // data-driven sweeps tag their fluxes by sign
+        const bool nonneg = lo && psi_b >= 0.0 &&
+                            all_nonnegative({{sigma_t, g.nc}, {sigma_s, g.nc}, {q, g.nc}, {phi, g.nc},
+                                             {g.n_lag ? psi : nullptr, N}}, s);
         while (true) {
             if (sweeps >= max_iter) { rc = JSWEEP_E_NOT_CONVERGED; break; }
             double *it_acc = norms.as<double>() + 4 * (fixed ? sweeps : (sweeps & 1));
@@ -549,21 +581,22 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
                 if (psi) lag_snapshot<double>(g, psi, s);
                 else if (g.n_lag) JSW_HIP(hipMemsetAsync(g.lag_val64.p, 0, 8 * g.n_lag, s));
             }
-            launch_sweep64(g, src, lo ? nullptr : psi, psi_b, params, s, prepared);
+            launch_sweep64(g, src, lo ? nullptr : psi, psi_b, params, s, prepared, nonneg);
             ++sweeps;
             // residual of the new iterate from the identity above (one
             // pass over the fluxes for phi; the lagged edges by their
             // downwind cells), and the set-up of the next sweep
             const double *flux = lo ? static_cast<const double *>(last_sweep_pos(g)) : psi;
+            const uint64_t keep = lo ? last_sweep_keep(g) : ~0ull;
             const int64_t pxcd = xcd_per(ceil_div(pairs ? g.nc / 2 : g.nc, kB));
             if (pairs)
                 k_phi_delta2<<<(unsigned)(8 * pxcd), kB, 0, s>>>(
                     flux, posi, g.weight.as<double>(), wsum, q, sigma_s, g.vol.as<double>(), g.nc, g.nd, phi, it_acc,
-                    src, g.vsc.as<double>(), lagc, g.status.as<int32_t>(), next_acc, tickets, pxcd);
+                    src, g.vsc.as<double>(), lagc, g.status.as<int32_t>(), next_acc, tickets, pxcd, keep);
             else
                 k_phi_delta<<<(unsigned)(8 * pxcd), kB, 0, s>>>(
                     flux, posi, g.weight.as<double>(), wsum, q, sigma_s, g.vol.as<double>(), g.nc, g.nd, phi, it_acc,
-                    src, g.vsc.as<double>(), lagc, g.status.as<int32_t>(), next_acc, tickets, pxcd);
+                    src, g.vsc.as<double>(), lagc, g.status.as<int32_t>(), next_acc, tickets, pxcd, keep);
             JSW_HIP(hipGetLastError());
             prepared = true;
             if (fixed) continue;
@@ -592,7 +625,8 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
         if (lo && psi_out && sweeps > 0) {
             const int64_t pxcd = xcd_per(ceil_div(N, kB));
             k_cell_order<<<(unsigned)(8 * pxcd), kB, 0, s>>>(static_cast<const double *>(last_sweep_pos(g)),
-                                                            g.posi.as<int32_t>(), g.nc, N, psi_out, pxcd);
+                                                            g.posi.as<int32_t>(), g.nc, N, psi_out, pxcd,
+                                                            last_sweep_keep(g));
             JSW_HIP(hipGetLastError());
         }
     } else {

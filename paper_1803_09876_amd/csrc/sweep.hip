@@ -111,6 +111,7 @@ struct SweepArgs {
     // a global direction whose row locates its arrays; null for one graph
     const DirRow *rows;
     const int32_t *active;                   // per instance: chunks of inactive ones only empty their entries
+    uint64_t tag;                            // sign-tagged sweeps: this sweep's sign bit (kSignBit or 0)
 };
 
 template <class T>
@@ -129,6 +130,26 @@ __device__ __forceinline__ Real empty_marker() {
 }
 __device__ __forceinline__ bool is_empty(double v) { return __builtin_bit_cast(uint64_t, v) == kEmpty64; }
 __device__ __forceinline__ bool is_empty(float v) { return __builtin_bit_cast(uint32_t, v) == kEmpty32; }
+
+// Sign-tagged fluxes (FP64 sweeps of solves whose inputs are all
+// non-negative, so that every flux is): a stored flux carries the sweep's
+// tag in its sign bit, and the tag alternates between the sweeps that fill
+// one array.  A value the array's previous sweep left there, and the empty
+// marker (sign bit clear; an array holding markers is next filled with the
+// sign bit set), read as not yet computed, so no sweep writes markers for
+// the next one.  Readers take the magnitude.
+constexpr uint64_t kSignBit = 0x8000000000000000ull;
+__device__ __forceinline__ double with_tag(double v, uint64_t tag) {
+    return __builtin_bit_cast(double, (__builtin_bit_cast(uint64_t, v) & ~kSignBit) | tag);
+}
+__device__ __forceinline__ double untag(double v) {
+    return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, v) & ~kSignBit);
+}
+template <bool SG, class Real>
+__device__ __forceinline__ bool not_ready(Real v, uint64_t tag) {
+    if constexpr (SG) return (__builtin_bit_cast(uint64_t, v) & kSignBit) != tag;
+    else return is_empty(v);
+}
 
 template <class Real>
 __global__ void k_fill_empty(Real *p, int64_t n) {
@@ -234,12 +255,14 @@ __device__ __forceinline__ void keep_live(const T &v) {
 // TRACE: record take / ready / done stamps per chunk; NG: energy groups
 // swept per chunk (multigroup: a.n_groups <= NG groups share the chunk's
 // program, each with its own denominator, source and fluxes); PK: the
-// upwind positions come packed (a.pk, see kPkBits).
-template <class Real, int NS, int NSX, bool TRACE, int NG = 1, bool PK = false>
+// upwind positions come packed (a.pk, see kPkBits); SG: the fluxes are
+// sign-tagged with a.tag (see kSignBit) and no empty markers are written.
+template <class Real, int NS, int NSX, bool TRACE, int NG = 1, bool PK = false, bool SG = false>
 __global__ void k_sweep(SweepArgs<Real> a) {
     constexpr int NX = NSX > 0 ? NSX : 1;
     static_assert(NG == 1 || (NSX == 0 && sizeof(Real) == 8), "multigroup sweeps read the full FP64 program");
     static_assert(!PK || (NS <= 3 && NSX == 0), "packed codes hold 3 slots and no compact entries");
+    static_assert(!SG || (sizeof(Real) == 8 && NSX == 0 && !TRACE), "sign tags are FP64 work-list sweeps");
     const int lane = threadIdx.x & 63;
     const int stream = (int)(blockIdx.x % kStreams);
     // a wavefront off its stream's XCD takes no chunk (it holds nothing
@@ -430,7 +453,7 @@ __global__ void k_sweep(SweepArgs<Real> a) {
                 for (int g = 0; g < NG; ++g)
                     if (g < ng) {
 #pragma unroll
-                        for (int j = 0; j < NS; ++j) ok = ok && !(P.code[j] >= 0 && is_empty(val[g][j]));
+                        for (int j = 0; j < NS; ++j) ok = ok && !(P.code[j] >= 0 && not_ready<SG>(val[g][j], a.tag));
                     }
 #pragma unroll
                 for (int k = 0; k < NX; ++k) ok = ok && !(code_x[k] >= 0 && is_empty(val_x[k]));
@@ -478,6 +501,12 @@ __global__ void k_sweep(SweepArgs<Real> a) {
         at_cell = cell_row ? cell_row + cell_k : nullptr;
         at_next = a.pos_next + own * gm;
         Real og[NG];
+        if constexpr (SG) {
+#pragma unroll
+            for (int g = 0; g < NG; ++g)
+#pragma unroll
+                for (int j = 0; j < NS; ++j) val[g][j] = untag(val[g][j]);
+        }
         if (active) {
 #pragma unroll
             for (int g = 0; g < NG; ++g) {
@@ -505,16 +534,17 @@ __global__ void k_sweep(SweepArgs<Real> a) {
                 // a NaN carrying the marker's bits (never produced by
                 // arithmetic) would read as not yet computed
                 if (is_empty(o)) o = std::numeric_limits<Real>::quiet_NaN();
-                // the level-order store publishes the flux; the cell-order
-                // copy (when the caller wants one) is read only after the
-                // kernel
+                // the cell-order copy (when the caller wants one) is read
+                // only after the kernel
+                if (cell_row) at_cell[g * a.gs_pos] = o;
+                if constexpr (SG) o = with_tag(o, a.tag);
+                // the level-order store publishes the flux
                 if constexpr (kPairStores<Real, NG>) {
                     og[g] = o;   // stored below, two groups at a time
                 } else {
                     at_pos[g] = o;
-                    __builtin_nontemporal_store(empty_marker<Real>(), at_next + g);   // read in the next sweep
+                    if constexpr (!SG) __builtin_nontemporal_store(empty_marker<Real>(), at_next + g);   // read in the next sweep
                 }
-                if (cell_row) at_cell[g * a.gs_pos] = o;
                 if (g == 0) out = o;
             }
             if constexpr (kPairStores<Real, NG>) {
@@ -525,15 +555,16 @@ __global__ void k_sweep(SweepArgs<Real> a) {
 #pragma unroll
                     for (int h = 0; h < NG / 2; ++h) {
                         reinterpret_cast<Dbl2 *>(at_pos)[h] = Dbl2{og[2 * h], og[2 * h + 1]};
-                        __builtin_nontemporal_store(Dbl2{empty_marker<Real>(), empty_marker<Real>()},
-                                                    reinterpret_cast<Dbl2 *>(at_next) + h);
+                        if constexpr (!SG)
+                            __builtin_nontemporal_store(Dbl2{empty_marker<Real>(), empty_marker<Real>()},
+                                                        reinterpret_cast<Dbl2 *>(at_next) + h);
                     }
                 } else {
 #pragma unroll
                     for (int g = 0; g < NG; ++g)
                         if (g < ng) {
                             at_pos[g] = og[g];
-                            __builtin_nontemporal_store(empty_marker<Real>(), at_next + g);
+                            if constexpr (!SG) __builtin_nontemporal_store(empty_marker<Real>(), at_next + g);
                         }
                 }
             }
@@ -705,30 +736,34 @@ static uint64_t watchdog_ticks() {
     return (uint64_t)(ms * 1e5);   // s_memrealtime runs at 100 MHz
 }
 
+// sg: sign-tagged fluxes (FP64, full program, untraced)
 template <class Real, int NS, int NSX = 0, bool PK = false>
-static const void *kernel_ptr(bool trace) {
+static const void *kernel_ptr(bool trace, bool sg = false) {
+    if constexpr (sizeof(Real) == 8 && NSX == 0) {
+        if (sg) return reinterpret_cast<const void *>(&k_sweep<Real, NS, NSX, false, 1, PK, true>);
+    }
     return trace ? reinterpret_cast<const void *>(&k_sweep<Real, NS, NSX, true, 1, PK>)
                  : reinterpret_cast<const void *>(&k_sweep<Real, NS, NSX, false, 1, PK>);
 }
 
 // pk: the program's upwind positions are packed (at most 3 slots)
 template <class Real>
-static const void *sweep_kernel_t(int ns, bool trace, bool pk = false) {
+static const void *sweep_kernel_t(int ns, bool trace, bool pk = false, bool sg = false) {
     if (pk) {
         switch (ns) {
-        case 1: return kernel_ptr<Real, 1, 0, true>(trace);
-        case 2: return kernel_ptr<Real, 2, 0, true>(trace);
-        case 3: return kernel_ptr<Real, 3, 0, true>(trace);
+        case 1: return kernel_ptr<Real, 1, 0, true>(trace, sg);
+        case 2: return kernel_ptr<Real, 2, 0, true>(trace, sg);
+        case 3: return kernel_ptr<Real, 3, 0, true>(trace, sg);
         default: fail(JSWEEP_E_DEVICE, "packed codes with more than 3 slots");
         }
     }
     switch (ns) {
-    case 1: return kernel_ptr<Real, 1>(trace);
-    case 2: return kernel_ptr<Real, 2>(trace);
-    case 3: return kernel_ptr<Real, 3>(trace);
-    case 4: return kernel_ptr<Real, 4>(trace);
-    case 5: return kernel_ptr<Real, 5>(trace);
-    default: return kernel_ptr<Real, 6>(trace);
+    case 1: return kernel_ptr<Real, 1>(trace, sg);
+    case 2: return kernel_ptr<Real, 2>(trace, sg);
+    case 3: return kernel_ptr<Real, 3>(trace, sg);
+    case 4: return kernel_ptr<Real, 4>(trace, sg);
+    case 5: return kernel_ptr<Real, 5>(trace, sg);
+    default: return kernel_ptr<Real, 6>(trace, sg);
     }
 }
 
@@ -745,39 +780,45 @@ static bool use_packed(const Graph &g, bool fp32, int groups) {
 
 // multigroup FP64 kernels: NG groups per chunk, full program (its upwind
 // positions packed where the graph has them)
+template <int NS, int NG, bool PK>
+static const void *group_kernel_ptr(bool sg) {
+    return sg ? reinterpret_cast<const void *>(&k_sweep<double, NS, 0, false, NG, PK, true>)
+              : reinterpret_cast<const void *>(&k_sweep<double, NS, 0, false, NG, PK>);
+}
 template <int NG>
-static const void *sweep_kernel_groups(int ns, bool pk) {
+static const void *sweep_kernel_groups(int ns, bool pk, bool sg) {
     if (pk) {
         switch (ns) {
-        case 1: return reinterpret_cast<const void *>(&k_sweep<double, 1, 0, false, NG, true>);
-        case 2: return reinterpret_cast<const void *>(&k_sweep<double, 2, 0, false, NG, true>);
-        case 3: return reinterpret_cast<const void *>(&k_sweep<double, 3, 0, false, NG, true>);
+        case 1: return group_kernel_ptr<1, NG, true>(sg);
+        case 2: return group_kernel_ptr<2, NG, true>(sg);
+        case 3: return group_kernel_ptr<3, NG, true>(sg);
         default: fail(JSWEEP_E_DEVICE, "packed codes with more than 3 slots");
         }
     }
     switch (ns) {
-    case 1: return reinterpret_cast<const void *>(&k_sweep<double, 1, 0, false, NG>);
-    case 2: return reinterpret_cast<const void *>(&k_sweep<double, 2, 0, false, NG>);
-    case 3: return reinterpret_cast<const void *>(&k_sweep<double, 3, 0, false, NG>);
-    case 4: return reinterpret_cast<const void *>(&k_sweep<double, 4, 0, false, NG>);
-    case 5: return reinterpret_cast<const void *>(&k_sweep<double, 5, 0, false, NG>);
-    default: return reinterpret_cast<const void *>(&k_sweep<double, 6, 0, false, NG>);
+    case 1: return group_kernel_ptr<1, NG, false>(sg);
+    case 2: return group_kernel_ptr<2, NG, false>(sg);
+    case 3: return group_kernel_ptr<3, NG, false>(sg);
+    case 4: return group_kernel_ptr<4, NG, false>(sg);
+    case 5: return group_kernel_ptr<5, NG, false>(sg);
+    default: return group_kernel_ptr<6, NG, false>(sg);
     }
 }
 
 // groups = 0: the single-group sweep (compact program where the graph has
 // one); groups >= 1: the multigroup sweep over that many groups, which
-// reads the full program
-static const void *sweep_kernel(const Graph &g, bool fp32, bool trace = false, int groups = 0) {
+// reads the full program; sg: sign-tagged fluxes (FP64, full program,
+// untraced: the caller checks)
+static const void *sweep_kernel(const Graph &g, bool fp32, bool trace = false, int groups = 0, bool sg = false) {
     const int ns = g.ns;
     if (ns < 1 || ns > 6) fail(JSWEEP_E_DEVICE, "sweep program with an unsupported number of inflow slots");
     if (groups >= 1) {
         if (fp32 || trace) fail(JSWEEP_E_INVALID_ARG, "multigroup sweeps are FP64 and untraced");
-        if (groups == 1) return sweep_kernel_t<double>(ns, false, use_packed(g, false, 1));
+        if (groups == 1) return sweep_kernel_t<double>(ns, false, use_packed(g, false, 1), sg);
         const bool pk = use_packed(g, false, groups);
-        if (groups <= 2) return sweep_kernel_groups<2>(ns, pk);
-        if (groups <= 4) return sweep_kernel_groups<4>(ns, pk);
-        if (groups <= kMaxGroups) return sweep_kernel_groups<kMaxGroups>(ns, pk);
+        if (groups <= 2) return sweep_kernel_groups<2>(ns, pk, sg);
+        if (groups <= 4) return sweep_kernel_groups<4>(ns, pk, sg);
+        if (groups <= kMaxGroups) return sweep_kernel_groups<kMaxGroups>(ns, pk, sg);
         fail(JSWEEP_E_INVALID_ARG, "too many energy groups");
     }
     if (use_compact(g, fp32)) {
@@ -789,12 +830,12 @@ static const void *sweep_kernel(const Graph &g, bool fp32, bool trace = false, i
         }
     }
     const bool pk = use_packed(g, fp32, groups);
-    return fp32 ? sweep_kernel_t<float>(ns, trace, pk) : sweep_kernel_t<double>(ns, trace, pk);
+    return fp32 ? sweep_kernel_t<float>(ns, trace, pk) : sweep_kernel_t<double>(ns, trace, pk, sg);
 }
 
 constexpr int kMaxSweepBlocksPerCU = 4;
 
-int persistent_waves(Graph &g, bool fp32, const jsweep_params *p, int *waves_per_block, int groups) {
+int persistent_waves(Graph &g, bool fp32, const jsweep_params *p, int *waves_per_block, int groups, bool sg) {
     // default (measured on 0.3M- to 6.6M-chunk graphs): one workgroup per
     // CU, of eight wavefronts for graphs above a million chunks (more
     // requests in flight; ten or more poll more than they gain), of five
@@ -808,7 +849,7 @@ int persistent_waves(Graph &g, bool fp32, const jsweep_params *p, int *waves_per
     // time, waiting for the last
     static std::mutex occ_mu;
     static std::map<std::pair<const void *, int>, int> occ_seen;
-    const void *kern = sweep_kernel(g, fp32, false, groups);
+    const void *kern = sweep_kernel(g, fp32, false, groups, sg);
     int occ = 0;
     {
         std::lock_guard<std::mutex> lock(occ_mu);
@@ -913,11 +954,14 @@ __global__ void k_vs32(const double *vol, const float *src, int64_t nc, float *v
 
 // vs_buf: where the per-cell V s of this sweep is staged (null: the
 // graph's own buffer, allocated on first use); a caller-provided buffer
-// also keeps the launch free of HIP event creation (no profiling)
+// also keeps the launch free of HIP event creation (no profiling); nonneg:
+// every flux of this sweep is non-negative (the caller checked its inputs):
+// an FP64 sweep of the full program then tags its fluxes by sign instead of
+// writing empty markers (see kSignBit)
 template <class Real>
 static void launch_persistent(Graph &g, const Real *src_cell, const float *src_dir, Real *psi, Real psi_b,
                               const jsweep_params *p, hipStream_t s, bool prepared = false,
-                              const GroupSweep *mg = nullptr, void *vs_buf = nullptr) {
+                              const GroupSweep *mg = nullptr, void *vs_buf = nullptr, bool nonneg = false) {
     const bool f32 = sizeof(Real) == 4;
     const int G = mg ? mg->groups : 1;
     if (mg && (f32 || !prepared)) fail(JSWEEP_E_DEVICE, "multigroup sweeps are FP64 with a prepared source");
@@ -955,12 +999,15 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
     a.gs_pos = g.nc * g.nd;
     a.gs_den = a.stride;
     if (mg) a.pden = reinterpret_cast<const Real *>(mg->den);
-    // the two level-position arrays: this sweep's must hold the empty marker
-    // of its precision in its first G nc nd entries (every group of every
-    // position; the previous sweep of the same precision left it so,
-    // otherwise it is filled here), and the sweep empties the other one for
-    // the next sweep.  State: element size | (G of the entries holding the
-    // marker) << 8; a prefix of G' >= G groups' entries covers G's.
+    // the two level-position arrays alternate.  A marker sweep needs the
+    // empty marker of its precision in the first G nc nd entries of its
+    // array (every group of every position; the previous sweep of that
+    // precision left it so, otherwise it is filled here) and empties the
+    // other array for the next sweep.  A sign-tagged sweep needs its array
+    // to hold markers or the fluxes of its own previous G-group tagged
+    // sweep, and takes the other tag; it writes no markers.  State (see
+    // Graph::dd_state): element size | G << 8, plus the tag bits.
+    const bool sg = nonneg && !f32 && !compact && !g.trace && !vs_buf;
     const int want = (int)sizeof(Real) | (G << 8);
     const size_t need_bytes = (size_t)8 * g.nc * g.nd * G;
     for (int i = 0; i < 2; ++i)
@@ -969,16 +1016,28 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
             g.dd_state[i] = 0;
         }
     const int cur = g.dd_cur;
-    const bool covered = (g.dd_state[cur] & 0xff) == (int)sizeof(Real) && (g.dd_state[cur] >> 8) >= G;
-    if (!covered && g.nc * g.nd > 0) {
+    const int st = g.dd_state[cur];
+    bool fill = !(!(st & kDdTagged) && (st & 0xff) == (int)sizeof(Real) && ((st >> 8) & 0xff) >= G);
+    bool tag_set = true;   // markers (sign bit clear) never carry a set tag
+    if (sg && (st & kDdTagged) && ((st >> 8) & 0xff) == G) {
+        tag_set = !(st & kDdTagSet);
+        fill = false;
+    }
+    if (fill && g.nc * g.nd > 0) {
         const int64_t n = g.nc * g.nd * G;
         k_fill_empty<Real><<<(int)std::min<int64_t>(ceil_div(n, 256), 8192), 256, 0, s>>>(g.dd_pos[cur].as<Real>(), n);
         JSW_HIP(hipGetLastError());
     }
     a.psi_pos = g.dd_pos[cur].as<Real>();
     a.pos_next = g.dd_pos[1 - cur].as<Real>();
-    g.dd_state[cur] = 0;
-    g.dd_state[1 - cur] = want;
+    if (sg) {
+        a.tag = tag_set ? kSignBit : 0;
+        g.dd_state[cur] = kDdTagged | (tag_set ? kDdTagSet : 0) | (G << 8) | 8;   // the other array's state stands
+    } else {
+        a.tag = 0;
+        g.dd_state[cur] = 0;
+        g.dd_state[1 - cur] = want;
+    }
     g.dd_cur = 1 - cur;
     a.status = g.status.as<int32_t>();
     a.lag_val = reinterpret_cast<const Real *>(mg ? mg->lag_val : f32 ? g.lag_val32.p : g.lag_val64.p);
@@ -1003,7 +1062,7 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
         a.backoff = b ? (uint32_t)std::min(4, std::max(0, std::atoi(b))) : 3u;
     }
     int wpb = 4;
-    int waves = persistent_waves(g, f32, p, &wpb, mg ? G : 0);
+    int waves = persistent_waves(g, f32, p, &wpb, mg ? G : 0, sg);
     int64_t need = std::max<int64_t>(1, g.n_chunks);
     if (waves > need) waves = (int)((need + wpb - 1) / wpb * wpb);
     int blocks = std::max(waves / wpb, kStreams);
@@ -1017,8 +1076,8 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
     }
     void *args[] = {&a};
     if (mg) a.stamps = nullptr;
-    JSW_HIP(hipLaunchKernel(sweep_kernel(g, f32, a.stamps != nullptr, mg ? G : 0), dim3(blocks), dim3(64 * wpb), args,
-                            0, s));
+    JSW_HIP(hipLaunchKernel(sweep_kernel(g, f32, a.stamps != nullptr, mg ? G : 0, sg), dim3(blocks), dim3(64 * wpb),
+                            args, 0, s));
     if (prof) {
         JSW_HIP(hipEventRecord(ev1, s));
         g.prof_events.push_back({ev0, ev1});
@@ -1378,7 +1437,7 @@ int sweep_strategy(const Graph &g, const jsweep_params *p) {
 
 template <class Real, int NF, int DIM>
 static void launch_impl(Graph &g, const Real *src_cell, const float *src_dir, Real *psi, Real psi_b,
-                        const jsweep_params *p, hipStream_t s, bool prepared = false) {
+                        const jsweep_params *p, hipStream_t s, bool prepared = false, bool nonneg = false) {
     const int st = sweep_strategy(g, p);
     if constexpr (sizeof(Real) == 8) {
         if (st == JSWEEP_STRATEGY_PATCH && patch_ready(g, s)) {
@@ -1389,17 +1448,19 @@ static void launch_impl(Graph &g, const Real *src_cell, const float *src_dir, Re
     if (st == JSWEEP_STRATEGY_DIRECTION_LDS && ring_items(g, sizeof(Real) == 4)) launch_ring<Real>(g, src_cell, src_dir, psi, psi_b, s);
     else if (st == JSWEEP_STRATEGY_DIRECTION || st == JSWEEP_STRATEGY_DIRECTION_LDS)
         launch_dir<Real, NF, DIM>(g, src_cell, src_dir, psi, psi_b, p, s);
-    else launch_persistent<Real>(g, src_cell, src_dir, psi, psi_b, p, s, prepared);
+    else launch_persistent<Real>(g, src_cell, src_dir, psi, psi_b, p, s, prepared, nullptr, nullptr, nonneg);
 }
 
 void launch_sweep64(Graph &g, const double *src_cell, double *psi, double psi_b, const jsweep_params *p, hipStream_t s,
-                    bool prepared) {
-    if (g.ctype == JSWEEP_TRI) launch_impl<double, 3, 2>(g, src_cell, nullptr, psi, psi_b, p, s, prepared);
-    else if (g.ctype == JSWEEP_TET) launch_impl<double, 4, 3>(g, src_cell, nullptr, psi, psi_b, p, s, prepared);
-    else launch_impl<double, 6, 3>(g, src_cell, nullptr, psi, psi_b, p, s, prepared);
+                    bool prepared, bool nonneg) {
+    if (g.ctype == JSWEEP_TRI) launch_impl<double, 3, 2>(g, src_cell, nullptr, psi, psi_b, p, s, prepared, nonneg);
+    else if (g.ctype == JSWEEP_TET) launch_impl<double, 4, 3>(g, src_cell, nullptr, psi, psi_b, p, s, prepared, nonneg);
+    else launch_impl<double, 6, 3>(g, src_cell, nullptr, psi, psi_b, p, s, prepared, nonneg);
 }
 
 void *last_sweep_pos(Graph &g) { return g.dd_pos[1 - g.dd_cur].p; }
+
+uint64_t last_sweep_keep(const Graph &g) { return (g.dd_state[1 - g.dd_cur] & kDdTagged) ? ~kSignBit : ~0ull; }
 
 void launch_sweep64_staged(Graph &g, const double *src_cell, double *psi, double psi_b, void *vs_buf, hipStream_t s) {
     if (sweep_strategy(g, nullptr) != JSWEEP_STRATEGY_DATA_DRIVEN)
@@ -1409,7 +1470,7 @@ void launch_sweep64_staged(Graph &g, const double *src_cell, double *psi, double
 }
 
 void launch_sweep_groups(Graph &g, double *psi, const GroupSweep &mg, const jsweep_params *p, hipStream_t s) {
-    launch_persistent<double>(g, nullptr, nullptr, psi, mg.psi_b, p, s, true, &mg);
+    launch_persistent<double>(g, nullptr, nullptr, psi, mg.psi_b, p, s, true, &mg, nullptr, mg.nonneg);
 }
 
 void launch_sweep32(Graph &g, const float *src_dir, const float *src_cell, float *psi, const jsweep_params *p,
@@ -1980,6 +2041,7 @@ static void union_launch(UnionSweep &u, const int32_t *active, int waves_per_blo
     a.gs_den = a.stride;
     a.rows = u.rows.as<DirRow>();
     a.active = active;
+    a.tag = 0;
     // default (measured on the 256-instance ensemble, time to 1e-8 with a
     // compacted list: 2 / 4 / 8 / 10 / 16 wavefronts 267 / 184 / 138 / 134
     // / 138 ms): the union's deepest instances need many chunks in flight
