@@ -89,13 +89,15 @@ __device__ inline double dir_sum_pos(const double *w, const T *pos, const int32_
     for (; m + 16 <= nd; m += 16) {
         T v[16];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) v[k] = kept(pos[(int64_t)(m + k) * nc + p[k]], keep);
+        for (int k = 0; k < 16; ++k) v[k] = pos[(int64_t)(m + k) * nc + p[k]];
         if (m + 32 <= nd) {
 #pragma unroll
             for (int k = 0; k < 16; ++k) p[k] = posi[(int64_t)(m + 16 + k) * nc + K];
         }
+        // masked only here, after the next positions' loads have been
+        // issued: nothing waits for the fluxes before that
 #pragma unroll
-        for (int k = 0; k < 16; ++k) s = s + w[m + k] * (double)v[k];
+        for (int k = 0; k < 16; ++k) s = s + w[m + k] * (double)kept(v[k], keep);
     }
     for (; m < nd; ++m) s = s + w[m] * (double)kept(pos[(int64_t)m * nc + posi[(int64_t)m * nc + K]], keep);
     return s;
@@ -119,8 +121,8 @@ __device__ inline void dir_sum_pos2(const double *w, const T *pos, const int32_t
         T v0[B], v1[B];
 #pragma unroll
         for (int k = 0; k < B; ++k) {
-            v0[k] = kept(pos[(int64_t)(m + k) * nc + p[k].x], keep);
-            v1[k] = kept(pos[(int64_t)(m + k) * nc + p[k].y], keep);
+            v0[k] = pos[(int64_t)(m + k) * nc + p[k].x];
+            v1[k] = pos[(int64_t)(m + k) * nc + p[k].y];
         }
         // the next batch's positions travel while these fluxes do
         if (m + 2 * B <= nd) {
@@ -129,8 +131,8 @@ __device__ inline void dir_sum_pos2(const double *w, const T *pos, const int32_t
         }
 #pragma unroll
         for (int k = 0; k < B; ++k) {
-            s0 = s0 + w[m + k] * (double)v0[k];
-            s1 = s1 + w[m + k] * (double)v1[k];
+            s0 = s0 + w[m + k] * (double)kept(v0[k], keep);
+            s1 = s1 + w[m + k] * (double)kept(v1[k], keep);
         }
     }
     for (; m < nd; ++m) {

@@ -144,19 +144,19 @@ __global__ void k_group_residual(const CellRec<double, NF, DIM> *rec, const doub
 }
 
 // the G values of one level-position entry (groups adjacent; 16-byte
-// aligned when G is even), with only the bits in keep
+// aligned when G is even)
 template <int G>
-__device__ __forceinline__ void load_groups(const double *e, double (&v)[G], uint64_t keep) {
+__device__ __forceinline__ void load_groups(const double *e, double (&v)[G]) {
     if constexpr (G % 2 == 0) {
 #pragma unroll
         for (int h = 0; h < G / 2; ++h) {
             const double2 x = reinterpret_cast<const double2 *>(e)[h];
-            v[2 * h] = kept(x.x, keep);
-            v[2 * h + 1] = kept(x.y, keep);
+            v[2 * h] = x.x;
+            v[2 * h + 1] = x.y;
         }
     } else {
 #pragma unroll
-        for (int g = 0; g < G; ++g) v[g] = kept(e[g], keep);
+        for (int g = 0; g < G; ++g) v[g] = e[g];
     }
 }
 
@@ -190,22 +190,23 @@ __global__ void k_group_phi_pos(const double *pos, const int32_t *posi, const do
     for (; m + B <= nd; m += B) {
         double v[B][G];
 #pragma unroll
-        for (int k = 0; k < B; ++k) load_groups<G>(pos + ((int64_t)(m + k) * nc + p[k]) * G, v[k], keep);
+        for (int k = 0; k < B; ++k) load_groups<G>(pos + ((int64_t)(m + k) * nc + p[k]) * G, v[k]);
         // the next batch's positions travel while these fluxes do
         if (m + 2 * B <= nd) {
 #pragma unroll
             for (int k = 0; k < B; ++k) p[k] = posi[(int64_t)(m + B + k) * nc + K];
         }
+        // masked only here, after the next positions' loads have been issued
 #pragma unroll
         for (int k = 0; k < B; ++k)
 #pragma unroll
-            for (int g = 0; g < G; ++g) s[g] = s[g] + w[m + k] * v[k][g];
+            for (int g = 0; g < G; ++g) s[g] = s[g] + w[m + k] * kept(v[k][g], keep);
     }
     for (; m < nd; ++m) {
         double v[G];
-        load_groups<G>(pos + ((int64_t)m * nc + posi[(int64_t)m * nc + K]) * G, v, keep);
+        load_groups<G>(pos + ((int64_t)m * nc + posi[(int64_t)m * nc + K]) * G, v);
 #pragma unroll
-        for (int g = 0; g < G; ++g) s[g] = s[g] + w[m] * v[g];
+        for (int g = 0; g < G; ++g) s[g] = s[g] + w[m] * kept(v[g], keep);
     }
 #pragma unroll
     for (int g = 0; g < G; ++g) phin[(int64_t)g * nc + K] = s[g];
