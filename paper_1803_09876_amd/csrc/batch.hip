@@ -170,7 +170,15 @@ __global__ void k_b_source(const BInst *I, const int64_t *coff, int n, int64_t t
     if (b.vsu) static_cast<double *>(b.vsu)[K] = b.vol[K] * src;
 }
 
-__global__ void k_b_lag(const BInst *I, const int64_t *loff, int n, int64_t total, const int32_t *active, int fp32) {
+// an instance's FP64 flux of direction m, cell K: in its cell-order row, or
+// (upos given) at its level position in the union's last level-position
+// array, whose instance i entries start at aoff[i]
+__device__ inline double b_flux(const BInst &b, const double *upos, int64_t base, int64_t m, int64_t K) {
+    return upos ? upos[base + m * b.nc + b.posi[m * b.nc + K]] : b.psi[m * b.nc + K];
+}
+
+__global__ void k_b_lag(const BInst *I, const int64_t *loff, int n, int64_t total, const int32_t *active, int fp32,
+                        const double *upos, const int64_t *aoff) {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= total) return;
     const int i = find_inst(loff, n, g);
@@ -183,7 +191,7 @@ __global__ void k_b_lag(const BInst *I, const int64_t *loff, int n, int64_t tota
         b.lag32[e] = v;
         if (b.lagu) static_cast<float *>(b.lagu)[e] = v;
     } else {
-        const double v = b.psi[m * b.nc + b.lag_u[e]];
+        const double v = b_flux(b, upos, upos ? aoff[i] : 0, m, b.lag_u[e]);
         b.lag64[e] = v;
         if (b.lagu) static_cast<double *>(b.lagu)[e] = v;
     }
@@ -238,8 +246,9 @@ __global__ void k_b_level_order(const BInst *I, const int64_t *aoff, int n, int6
 // Residual of a plain FP64 source iteration from the sweep identity (as in
 // the single-graph solve): phi' (ascending m), d = sigma_s (phi' - phi),
 // acc[4 i] += W V d^2, acc[4 i + 1] += V q^2; then the lagged-edge terms.
+// (upos: the fluxes are read at their level positions, see b_flux)
 __global__ void k_b_phi_delta(const BInst *I, const int64_t *coff, int n, int64_t total, const int32_t *active,
-                              double *acc) {
+                              double *acc, const double *upos, const int64_t *aoff) {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int i = g < total ? find_inst(coff, n, g) : -1;
     if (i >= 0 && !active[i]) i = -1;
@@ -247,7 +256,7 @@ __global__ void k_b_phi_delta(const BInst *I, const int64_t *coff, int n, int64_
     if (i >= 0) {
         const BInst &b = I[i];
         const int64_t K = g - coff[i];
-        const double s = dir_sum(b.w, b.psi, b.nc, b.nd, K);
+        const double s = upos ? dir_sum_pos(b.w, upos + aoff[i], b.posi, b.nc, b.nd, K) : dir_sum(b.w, b.psi, b.nc, b.nd, K);
         const double d = b.sigma_s[K] * (s - b.phi[K]);
         b.phi[K] = s;
         b.dphi[K] = d;
@@ -261,7 +270,7 @@ __global__ void k_b_phi_delta(const BInst *I, const int64_t *coff, int n, int64_
 // one thread per (direction, downwind cell) group of an instance's lagged
 // edges: w_m V ((d + l)^2 - d^2) with l = sum a (psi'_u - psi_u) / V
 __global__ void k_b_lag_residual(const BInst *I, const int64_t *loff, int n, int64_t total, const int32_t *active,
-                                 double *acc) {
+                                 double *acc, const double *upos, const int64_t *aoff) {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int i = g < total ? find_inst(loff, n, g) : -1;
     if (i >= 0 && !active[i]) i = -1;
@@ -274,7 +283,7 @@ __global__ void k_b_lag_residual(const BInst *I, const int64_t *loff, int n, int
             const int64_t m = (int64_t)(key >> 32), v = (int64_t)(key & 0xffffffffu);
             double l = 0.0;
             for (int64_t f = e; f < b.n_lag && b.lag_mv[f] == key; ++f)
-                l = l + b.lag_a[f] * (b.psi[m * b.nc + b.lag_u[f]] - b.lag64[f]) / b.vol[v];
+                l = l + b.lag_a[f] * (b_flux(b, upos, upos ? aoff[i] : 0, m, b.lag_u[f]) - b.lag64[f]) / b.vol[v];
             const double d = b.dphi[v];
             rr = b.w[m] * (b.vol[v] * ((d + l) * (d + l) - d * d));
         }
@@ -316,6 +325,19 @@ __global__ void k_b_update(const BInst *I, const int64_t *aoff, int n, int64_t t
     const BInst &b = I[i];
     const int64_t x = g - aoff[i];
     b.psi[x] = b.psi[x] + (double)b.dpsi[x];
+}
+
+// the cell-order fluxes of the flagged instances from the union's last
+// level-position array: psi[m nc + K] = upos[aoff[i] + m nc + posi[m nc + K]]
+__global__ void k_b_cell_order(const BInst *I, const int64_t *aoff, int n, int64_t total, const int32_t *flag,
+                               const double *upos) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int i = find_inst(aoff, n, g);
+    if (!flag[i]) return;
+    const BInst &b = I[i];
+    const int64_t x = g - aoff[i];
+    b.psi[x] = upos[aoff[i] + (x / b.nc) * b.nc + b.posi[x]];
 }
 
 __global__ void k_b_clear(double *acc, int64_t n) {
@@ -448,10 +470,18 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
     const bool use_dir = !use_union;
     BatchSweep sweep;
     UnionSweep *un = nullptr;
+    // FP64 through the union: the fluxes stay in the union's level-position
+    // arrays (no cell-order copy per sweep); the flux pass and the lagged
+    // values read them at their level positions, and an instance's fluxes
+    // are copied to its cell-order psi when it stops (a later launch writes
+    // markers over them)
+    const bool lo64 = use_union && !refined;
     if (use_union) {
         un = &union_for(n, graphs, refined, s);
         un->refresh_den(graphs, s);
-        un->set_rows(graphs, psi_sweep.data(), src_dir.data(), psi_b.data(), s);
+        std::vector<void *> rows_psi(psi_sweep);
+        if (lo64) std::fill(rows_psi.begin(), rows_psi.end(), nullptr);
+        un->set_rows(graphs, rows_psi.data(), src_dir.data(), psi_b.data(), s);
         for (int i = 0; i < n; ++i) {
             BInst &b = h[i];
             b.vsu = static_cast<char *>(un->vs.p) + (refined ? 4 : 8) * (size_t)un->coff[i];
@@ -526,23 +556,41 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
         // phi of the zero iterate is zero; plain source iteration
         JSW_HIP(hipMemsetAsync(d_acc.p, 0, 8 * 4 * n, s));
         for (int i = 0; i < n; ++i) JSW_HIP(hipMemsetAsync(h[i].phi, 0, 8 * graphs[i]->nc, s));
+        // level-order fluxes (lo64): the last union launch's array (null
+        // before the first: the lagged values then come from the zero psi),
+        // and the instances whose fluxes go to their cell-order psi
+        const double *upos = nullptr;
+        DevBuf d_copy(4 * n);
+        std::vector<int32_t> copy(n, 0);
+        auto copy_out = [&]() {
+            bool anyc = false;
+            for (int i = 0; i < n; ++i) anyc = anyc || copy[i];
+            if (!anyc || !upos) return;
+            JSW_HIP(hipMemcpyAsync(d_copy.p, copy.data(), 4 * n, hipMemcpyHostToDevice, s));
+            k_b_cell_order<<<grid_for(A), kB, 0, s>>>(I, d_aoff.as<int64_t>(), n, A, d_copy.as<int32_t>(), upos);
+            JSW_HIP(hipGetLastError());
+            JSW_HIP(hipStreamSynchronize(s));   // copy is host memory of this scope
+        };
         while (true) {
             bool any = false;
             for (int i = 0; i < n; ++i) any = any || active[i];
             if (!any) break;
             if (total_sweeps >= max_iter) { rc = JSWEEP_E_NOT_CONVERGED; break; }
             k_b_source<<<grid_for(C), kB, 0, s>>>(I, d_coff.as<int64_t>(), n, C, d_active.as<int32_t>());
-            if (LG) k_b_lag<<<grid_for(LG), kB, 0, s>>>(I, d_loff.as<int64_t>(), n, LG, d_active.as<int32_t>(), 0);
+            if (LG)
+                k_b_lag<<<grid_for(LG), kB, 0, s>>>(I, d_loff.as<int64_t>(), n, LG, d_active.as<int32_t>(), 0, upos,
+                                                    d_aoff.as<int64_t>());
             launch_sweep(d_active.as<int32_t>());
+            if (lo64) upos = static_cast<const double *>(un->last_pos());
             ++total_sweeps;
             for (int i = 0; i < n; ++i) sweeps[i] += active[i];
             // residual from the sweep identity (one pass over psi)
             k_b_clear<<<grid_for(4 * n), kB, 0, s>>>(d_acc.as<double>(), 4 * n);
             k_b_phi_delta<<<grid_for(C), kB, 0, s>>>(I, d_coff.as<int64_t>(), n, C, d_active.as<int32_t>(),
-                                                     d_acc.as<double>());
+                                                     d_acc.as<double>(), upos, d_aoff.as<int64_t>());
             if (LG)
                 k_b_lag_residual<<<grid_for(LG), kB, 0, s>>>(I, d_loff.as<int64_t>(), n, LG, d_active.as<int32_t>(),
-                                                             d_acc.as<double>());
+                                                             d_acc.as<double>(), upos, d_aoff.as<int64_t>());
             JSW_HIP(hipGetLastError());
             JSW_HIP(hipMemcpyAsync(acc.data(), d_acc.p, 8 * 4 * n, hipMemcpyDeviceToHost, s));
             JSW_HIP(hipStreamSynchronize(s));
@@ -551,16 +599,24 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
                 if (st != JSWEEP_OK) return st;
             }
             for (int i = 0; i < n; ++i) {
+                copy[i] = 0;
                 if (!active[i]) continue;
                 const double rr = std::max(acc[4 * i], 0.0);
                 rho[i] = acc[4 * i + 1] > 0.0 ? std::sqrt(rr) / std::sqrt(acc[4 * i + 1]) : std::sqrt(rr);
                 ++outer[i];
                 record(i, rho[i]);
-                if (tol > 0.0 && rho[i] <= tol) active[i] = 0;
+                if (tol > 0.0 && rho[i] <= tol) {
+                    active[i] = 0;
+                    copy[i] = lo64 && problems[i].psi != nullptr;
+                }
             }
+            copy_out();
             push_active(active);
             maybe_compact(active);
         }
+        // the instances still iterating at the end
+        for (int i = 0; i < n; ++i) copy[i] = lo64 && active[i] && problems[i].psi != nullptr;
+        copy_out();
     } else {
         const int J = (params && params->inner_sweeps > 0) ? params->inner_sweeps : 400;
         DevBuf d_inner(4 * n), d_withq(4 * n);
@@ -589,7 +645,9 @@ int solve_batch(int32_t n, Graph *const *graphs, const jsweep_problem *problems,
             if (un) un->fill_current(s);
             JSW_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             for (int k = 0; k < kInnerBlock; ++k) {
-                if (LG) k_b_lag<<<grid_for(LG), kB, 0, s>>>(I, d_loff.as<int64_t>(), n, LG, d_inner.as<int32_t>(), 1);
+                if (LG)
+                    k_b_lag<<<grid_for(LG), kB, 0, s>>>(I, d_loff.as<int64_t>(), n, LG, d_inner.as<int32_t>(), 1, nullptr,
+                                                        nullptr);
                 launch_sweep(d_inner.as<int32_t>());
                 // the norms read back after a replay are those of its last pass
                 if (k == kInnerBlock - 1) k_b_clear<<<grid_for(4 * n), kB, 0, s>>>(d_acc.as<double>(), 4 * n);

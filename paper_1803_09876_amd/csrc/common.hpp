@@ -429,6 +429,9 @@ struct UnionSweep {
     // capture: the captured launches keep the alternation consistent)
     void fill_current(hipStream_t s);
     void launch(const int32_t *active, int waves_per_block, hipStream_t s);
+    // the level-position array the last launch filled (instance i's flux
+    // of direction m and cell K at aoff[i] + m nc + posi[m nc + K])
+    const void *last_pos() const { return pos[1 - cur].p; }
     int check_status(hipStream_t s);
 };
 // packed codes (kPkBits) of a 3-slot program into pk [64 * n_chunks], with
