@@ -200,3 +200,38 @@ def test_full_ensemble_256():
     finally:
         for g in gs:
             g.close()
+
+
+@pytest.mark.parametrize("strategy", [J.JSWEEP_STRATEGY_DATA_DRIVEN, J.JSWEEP_STRATEGY_AUTO,
+                                      J.JSWEEP_STRATEGY_DIRECTION])
+def test_batch_with_lagged_edges(oracle_mod, strategy):
+    """Instances whose graphs have cycles (lagged edges: the deformed hex
+    lattices) batched with a lag-free one: the union keeps its FP64 fluxes
+    in level order, so the lagged values and their residual terms are read
+    at the level positions; after a fixed number of iterations, and to a
+    tolerance where the instances stop at different sweeps (psi from the
+    iterate each stopped at), every instance against the oracle."""
+    need_gpu()
+    ps = [W.config(2, "small"),
+          W.Problem("hex3cyc", W.hex_lattice(3, 0.3, 1), *W.quadrature(8, 3), np.full(27, 1.3), np.full(27, 0.9),
+                    np.ones(27)),
+          W.config(3, "small")]
+    ogs = [oracle_mod.graph_for(p) for p in ps]
+    assert ogs[0].n_lagged > 0 and ogs[1].n_lagged > 0 and ogs[2].n_lagged == 0
+    gs = [gpu_graph(p) for p in ps]
+    try:
+        for tol, iters in ((0.0, 7), (1e-9, 2000)):
+            pr = [{"sigma_t": dev(p.sigma_t), "sigma_s": dev(p.sigma_s), "q": dev(p.q), "phi": dev(np.zeros(p.n_cells)),
+                   "psi": dev(np.zeros((p.n_dirs, p.n_cells))), "psi_boundary": 0.1 * k} for k, p in enumerate(ps)]
+            st = J.solve_batch(gs, pr, mode=J.JSWEEP_FP64, tol=tol, max_iter=iters,
+                               params=J.Params(strategy=strategy), allow_not_converged=tol == 0.0)
+            for k, (p, og) in enumerate(zip(ps, ogs)):
+                psi_ref, phi_ref, _ = og.source_iteration(p.sigma_t, p.sigma_s, p.q, p.weight, st[k]["sweeps"],
+                                                          psi_b=0.1 * k)
+                e1, e2 = rel_max(host(pr[k]["phi"]), phi_ref), rel_max(host(pr[k]["psi"]), psi_ref)
+                print(f"[batch lagged s{strategy} tol {tol}] {p.name}: sweeps {st[k]['sweeps']} phi {e1:.2e} "
+                      f"psi {e2:.2e}", flush=True)
+                assert e1 <= 1e-12 and e2 <= 1e-12, (p.name, tol)
+    finally:
+        for g in gs:
+            g.close()
