@@ -46,7 +46,13 @@ def test_tagged_and_marker_solves_alternate(oracle_mod, name, k):
               f"{iters} sweeps): phi {e1:.2e} psi {e2:.2e} bitexact {np.array_equal(host(psi), psi_ref)}", flush=True)
         assert e1 <= 1e-12 and e2 <= 1e-12, i
         if i in (0, 3):
-            # a plain sweep in between (markers)
+            # plain sweeps in between (markers): after the tagged solve of
+            # step 0 first the one that allocates nothing (it fills the
+            # array with markers itself), then the ordinary one
+            if i == 0:
+                out = dev(np.zeros((p.n_dirs, p.n_cells)))
+                J.jsweep_sweep_noalloc(gg, dev(p.sigma_t), dev(q), out)
+                assert np.array_equal(host(out), og.sweep(p.sigma_t, q)), i
             out = dev(np.zeros((p.n_dirs, p.n_cells)))
             J.sweep(gg, dev(p.sigma_t), dev(q), out)
             assert np.array_equal(host(out), og.sweep(p.sigma_t, q)), i
