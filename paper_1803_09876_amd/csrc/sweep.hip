@@ -262,7 +262,7 @@ __global__ void k_sweep(SweepArgs<Real> a) {
     constexpr int NX = NSX > 0 ? NSX : 1;
     static_assert(NG == 1 || (NSX == 0 && sizeof(Real) == 8), "multigroup sweeps read the full FP64 program");
     static_assert(!PK || (NS <= 3 && NSX == 0), "packed codes hold 3 slots and no compact entries");
-    static_assert(!SG || (sizeof(Real) == 8 && NSX == 0 && !TRACE), "sign tags are FP64 work-list sweeps");
+    static_assert(!SG || (sizeof(Real) == 8 && !TRACE), "sign tags are FP64 untraced work-list sweeps");
     const int lane = threadIdx.x & 63;
     const int stream = (int)(blockIdx.x % kStreams);
     // a wavefront off its stream's XCD takes no chunk (it holds nothing
@@ -456,7 +456,7 @@ __global__ void k_sweep(SweepArgs<Real> a) {
                         for (int j = 0; j < NS; ++j) ok = ok && !(P.code[j] >= 0 && not_ready<SG>(val[g][j], a.tag));
                     }
 #pragma unroll
-                for (int k = 0; k < NX; ++k) ok = ok && !(code_x[k] >= 0 && is_empty(val_x[k]));
+                for (int k = 0; k < NX; ++k) ok = ok && !(code_x[k] >= 0 && not_ready<SG>(val_x[k], a.tag));
             }
             if (!__builtin_amdgcn_readfirstlane(act_flag)) break;   // an instance that no longer iterates
             if (__all(ok)) break;
@@ -506,6 +506,8 @@ __global__ void k_sweep(SweepArgs<Real> a) {
             for (int g = 0; g < NG; ++g)
 #pragma unroll
                 for (int j = 0; j < NS; ++j) val[g][j] = untag(val[g][j]);
+#pragma unroll
+            for (int k = 0; k < NX; ++k) val_x[k] = untag(val_x[k]);
         }
         if (active) {
 #pragma unroll
@@ -736,10 +738,10 @@ static uint64_t watchdog_ticks() {
     return (uint64_t)(ms * 1e5);   // s_memrealtime runs at 100 MHz
 }
 
-// sg: sign-tagged fluxes (FP64, full program, untraced)
+// sg: sign-tagged fluxes (FP64, untraced)
 template <class Real, int NS, int NSX = 0, bool PK = false>
 static const void *kernel_ptr(bool trace, bool sg = false) {
-    if constexpr (sizeof(Real) == 8 && NSX == 0) {
+    if constexpr (sizeof(Real) == 8) {
         if (sg) return reinterpret_cast<const void *>(&k_sweep<Real, NS, NSX, false, 1, PK, true>);
     }
     return trace ? reinterpret_cast<const void *>(&k_sweep<Real, NS, NSX, true, 1, PK>)
@@ -807,8 +809,8 @@ static const void *sweep_kernel_groups(int ns, bool pk, bool sg) {
 
 // groups = 0: the single-group sweep (compact program where the graph has
 // one); groups >= 1: the multigroup sweep over that many groups, which
-// reads the full program; sg: sign-tagged fluxes (FP64, full program,
-// untraced: the caller checks)
+// reads the full program; sg: sign-tagged fluxes (FP64, untraced: the
+// caller checks)
 static const void *sweep_kernel(const Graph &g, bool fp32, bool trace = false, int groups = 0, bool sg = false) {
     const int ns = g.ns;
     if (ns < 1 || ns > 6) fail(JSWEEP_E_DEVICE, "sweep program with an unsupported number of inflow slots");
@@ -824,9 +826,9 @@ static const void *sweep_kernel(const Graph &g, bool fp32, bool trace = false, i
     if (use_compact(g, fp32)) {
         static_assert(kCompactSlots == 3, "compact kernels are instantiated for 3 program slots");
         switch (g.ns_x) {
-        case 1: return kernel_ptr<double, 3, 1>(trace);
-        case 2: return kernel_ptr<double, 3, 2>(trace);
-        default: return kernel_ptr<double, 3, 3>(trace);
+        case 1: return kernel_ptr<double, 3, 1>(trace, sg);
+        case 2: return kernel_ptr<double, 3, 2>(trace, sg);
+        default: return kernel_ptr<double, 3, 3>(trace, sg);
         }
     }
     const bool pk = use_packed(g, fp32, groups);
@@ -1007,7 +1009,7 @@ static void launch_persistent(Graph &g, const Real *src_cell, const float *src_d
     // to hold markers or the fluxes of its own previous G-group tagged
     // sweep, and takes the other tag; it writes no markers.  State (see
     // Graph::dd_state): element size | G << 8, plus the tag bits.
-    const bool sg = nonneg && !f32 && !compact && !g.trace && !vs_buf;
+    const bool sg = nonneg && !f32 && !g.trace && !vs_buf;
     const int want = (int)sizeof(Real) | (G << 8);
     const size_t need_bytes = (size_t)8 * g.nc * g.nd * G;
     for (int i = 0; i < 2; ++i)
