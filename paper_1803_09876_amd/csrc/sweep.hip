@@ -2,9 +2,10 @@
 //
 // Work list: chunks of up to 64 vertices (cell, direction) of one level of
 // one direction.  Directions are dealt to kStreams streams; within a stream
-// the chunks are ordered by level, then direction, which is a topological
-// order of all of the stream's directions at once, so every direction is in
-// flight together (patch-angle parallelism, paper Sec. V-B).
+// the chunks follow a priority order that is a topological order of all of
+// the stream's directions at once (by default PACED: level over the
+// direction's level count), so every direction is in flight together
+// (patch-angle parallelism, paper Sec. V-B).
 //
 // Coarsened graph (paper Sec. V-E): a chunk is a cluster of vertices and the
 // work list is ordered by the clusters' graph (the union of their vertices'
@@ -16,10 +17,10 @@
 // cluster.
 //
 // Data: a chunk's lanes read the sweep program (common.hpp) at c * 64 +
-// lane -- inflow-face codes and coefficients, denominator -- as coalesced
-// streams; the scattered accesses are the cell's V s (or V and s in FP32),
-// the upwind fluxes and the cell-order flux store.  Cell records are not
-// read at all.
+// lane -- inflow-face codes (packed where they fit) and coefficients,
+// denominator -- as coalesced streams; the scattered accesses are the
+// cell's V s and the upwind fluxes (and the cell-order flux store when a
+// caller asks for one).  Cell records are not read at all.
 //
 // Execution: a persistent grid of a few workgroups per CU.  A running
 // wavefront takes chunks of its stream (workgroup id mod kStreams, which is
@@ -46,7 +47,8 @@
 // memory round trip per dependency instead of a flag poll, a flux load and
 // a store acknowledgement.  Every entry is one naturally aligned 4- or
 // 8-byte store and load, so a reader sees either the marker or the whole
-// value.
+// value.  FP64 sweeps whose fluxes are all non-negative carry a tag in the
+// sign bit instead and write no markers (kSignBit).
 //
 // Memory ordering across compute units.  Every hand-off stays inside one
 // XCD: a chunk's upwind chunks are in its own stream, and the workgroups of
