@@ -335,7 +335,8 @@ void *last_sweep_pos(Graph &g);
 // but the sign bit when that sweep tagged its fluxes by sign
 uint64_t last_sweep_keep(const Graph &g);
 // Whether every element of the given device arrays (pointer, length; null
-// pointers skipped) is >= 0 (NaN is not); one synchronisation
+// pointers skipped) has its sign bit clear and is not NaN (-0.0 and NaN
+// count as negative); one synchronisation
 bool all_nonnegative(std::initializer_list<std::pair<const double *, int64_t>> arrays, hipStream_t s);
 // A direction of a union of graphs swept by one launch of the data-driven
 // kernel (the batched solve): where its arrays start.  pos_base: its first

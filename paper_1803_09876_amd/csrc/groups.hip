@@ -313,7 +313,7 @@ int solve_groups(Graph &g, int G, const double *sigma_t, const double *sigma_s, 
     uint32_t *tickets = reinterpret_cast<uint32_t *>(g.status.as<char>() + 128);
     // with every input non-negative every flux is (phi starts from zero,
     // lagged values from earlier sweeps): the sweeps tag their fluxes by sign
-    const bool nonneg = psi_b >= 0.0 && all_nonnegative({{sigma_t, nc * G}, {sigma_s, nc * G * G}, {q, nc * G}}, s);
+    const bool nonneg = psi_b >= 0.0 && !std::signbit(psi_b) && all_nonnegative({{sigma_t, nc * G}, {sigma_s, nc * G * G}, {q, nc * G}}, s);
     const GroupSweep mg{G, den.as<double>(), lag_val.as<double>(), psi_b, nonneg};
     int it = 0, hist = 0, rc = JSWEEP_OK;
     double rho = INFINITY;

@@ -481,11 +481,15 @@ static void ensure(DevBuf &b, size_t bytes) {
     if (b.bytes < bytes) b.alloc(bytes);
 }
 
-// sets *flag when an element is negative or NaN
+// sets *flag when an element has its sign bit set (a negative value or
+// -0.0) or is NaN
 __global__ void k_flag_negative(const double *x, int64_t n, int32_t *flag) {
     const int64_t step = (int64_t)gridDim.x * blockDim.x;
     bool neg = false;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) neg = neg || !(x[i] >= 0.0);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
+        const double v = x[i];
+        neg = neg || !(v >= 0.0) || (__builtin_bit_cast(uint64_t, v) >> 63) != 0;
+    }
     if (neg) atomicOr(flag, 1);
 }
 
@@ -567,8 +571,10 @@ int solve(Graph &g, const double *sigma_t, const double *sigma_s, const double *
         const int32_t *posi = lo ? g.posi.as<int32_t>() : nullptr;
         // with every input non-negative (cross sections, source, boundary
         // inflow, the initial iterate) every flux of every sweep is, and the
-        // data-driven sweeps tag their fluxes by sign
-        const bool nonneg = lo && psi_b >= 0.0 &&
+        // data-driven sweeps tag their fluxes by sign.  Non-negative means
+        // sign bit clear: a -0.0 input can make a flux -0.0, whose sign a
+        // tagged store would not keep
+        const bool nonneg = lo && psi_b >= 0.0 && !std::signbit(psi_b) &&
                             all_nonnegative({{sigma_t, g.nc}, {sigma_s, g.nc}, {q, g.nc}, {phi, g.nc},
                                              {g.n_lag ? psi : nullptr, N}}, s);
         while (true) {

@@ -90,3 +90,33 @@ def test_warm_start_with_negative_fluxes(oracle_mod):
         if label == "non-negative":
             assert rel_max(host(psi), psi_ref) <= 1e-12
     gg.close()
+
+
+def test_negative_zero_inputs_keep_their_sign(oracle_mod):
+    """A source, scattering cross section and boundary inflow of -0.0 make
+    every flux -0.0 in the oracle's arithmetic.  A sign-tagged store would
+    not keep that sign, so the solve takes markers and returns the oracle's
+    bits, the sign of every zero included."""
+    need_gpu()
+    p = W.config(3, "small")
+    og = oracle_mod.graph_for(p)
+    gg = gpu_graph(p)
+    q = np.full(p.n_cells, -0.0)
+    sigma_s = np.full(p.n_cells, -0.0)
+    psi_ref, phi_ref, _ = og.source_iteration(p.sigma_t, sigma_s, q, p.weight, 3, psi_b=-0.0)
+    assert np.signbit(psi_ref).all() and (psi_ref == 0.0).all()
+    phi = dev(np.ones(p.n_cells))
+    psi = dev(np.ones((p.n_dirs, p.n_cells)))
+    J.solve(gg, dev(p.sigma_t), dev(sigma_s), dev(q), phi, psi, psi_boundary=-0.0, mode=J.JSWEEP_FP64, tol=0.0,
+            max_iter=3, allow_not_converged=True)
+    got, got_phi = host(psi), host(phi)
+    print(f"[tags -0] psi sign bits set: {np.signbit(got).mean():.3f} (oracle {np.signbit(psi_ref).mean():.3f})",
+          flush=True)
+    assert np.array_equal(np.signbit(got), np.signbit(psi_ref)) and np.array_equal(got, psi_ref)
+    assert np.array_equal(np.signbit(got_phi), np.signbit(phi_ref)) and np.array_equal(got_phi, phi_ref)
+    # the next solve with non-negative inputs on the same graph is tagged again
+    psi_ref2, phi_ref2, _ = og.source_iteration(p.sigma_t, p.sigma_s, p.q, p.weight, 3)
+    J.solve(gg, dev(p.sigma_t), dev(p.sigma_s), dev(p.q), phi, psi, mode=J.JSWEEP_FP64, tol=0.0, max_iter=3,
+            allow_not_converged=True)
+    assert rel_max(host(psi), psi_ref2) <= 1e-12 and rel_max(host(phi), phi_ref2) <= 1e-12
+    gg.close()
