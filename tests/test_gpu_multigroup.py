@@ -3,7 +3,8 @@ launch, Jacobi over groups) through the C ABI against the oracle's
 multigroup iteration: fluxes after a fixed number of iterations within
 1e-12 (bit-exact in practice), the residual history, convergence to the
 oracle's fixed point, one group equal to the single-group solve, and group
-counts that leave part of the kernel's group slots empty."""
+counts that leave part of the kernel's group slots empty; sign-tagged and marker
+solves alternating on one graph."""
 import numpy as np
 import pytest
 
@@ -96,3 +97,36 @@ def test_groups_bad_arguments(cases):
     with pytest.raises(J.JsweepError) as e:
         _run(gg, mp, 2)
     assert e.value.code == J.JSWEEP_E_INVALID_ARG
+
+
+def test_groups_tagged_and_marker_solves_alternate(cases):
+    """With every input non-negative the multigroup sweeps tag their fluxes
+    by sign; a negative source or inflow makes them write markers.  On one
+    graph (with and without lagged edges): solves that switch between the
+    two, change the group count and use odd and even iteration counts, then
+    a single-group sweep; every result against the oracle."""
+    rng = np.random.default_rng(5)
+    for name, p, og, gg in cases[:2]:
+        m4 = W.multigroup(p, 4, seed=21)
+        m3 = W.multigroup(p, 3, seed=22)
+        q4neg = m4.q.copy()
+        q4neg[1] -= 1.5 * rng.random(p.n_cells)      # a negative source in one group
+        assert (q4neg < 0).any()
+        # (groups' problem, source, inflow, iterations)
+        steps = [(m4, m4.q, 0.2, 5), (m4, q4neg, 0.2, 4), (m3, m3.q, 0.0, 3), (m3, m3.q, 0.1, 2),
+                 (m4, m4.q, -0.1, 3), (m4, m4.q, 0.0, 4)]
+        for i, (mp, q, psi_b, iters) in enumerate(steps):
+            psi_ref, phi_ref, _ = og.mg_source_iteration(mp.sigma_t, mp.sigma_s, q, mp.weight, iters, psi_b=psi_b)
+            G = mp.n_groups
+            phi = dev(np.zeros((G, p.n_cells)))
+            psi = dev(np.zeros((G, p.n_dirs, p.n_cells)))
+            J.solve_groups(gg, dev(mp.sigma_t), dev(mp.sigma_s), dev(q), phi, psi, psi_boundary=psi_b, tol=0.0,
+                           max_iter=iters, allow_not_converged=True)
+            e1, e2 = rel_max(host(phi), phi_ref), rel_max(host(psi), psi_ref)
+            kind = "negative" if (q < 0).any() or psi_b < 0 else "non-negative"
+            print(f"[groups tags] {name} step {i} ({G} groups, {kind} inputs, {iters} iterations): phi {e1:.2e} "
+                  f"psi {e2:.2e} bitexact {np.array_equal(host(psi), psi_ref)}", flush=True)
+            assert e1 <= 1e-12 and e2 <= 1e-12, (name, i)
+        out = dev(np.zeros((p.n_dirs, p.n_cells)))
+        J.sweep(gg, dev(p.sigma_t), dev(p.q), out)
+        assert np.array_equal(host(out), og.sweep(p.sigma_t, p.q)), name
