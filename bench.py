@@ -38,6 +38,9 @@ Also reported:
                 FP64 step throughput and time-to-1e-8, FP64 vs
                 FP32-refined (each the fastest of three after a warm-up),
                 with the autotuned launch parameters;
+  flux_pass     the rest of a step (step time minus the sweep kernel's):
+                the flux pass's algorithmic bytes (12 B per cell-angle pair
+                and 56 B per cell) and the rate they imply;
   hbm_copy_probe  the best of five 2 GiB device-to-device copies (HIP
                 events): the bandwidth this GPU sustains on a plain stream,
                 the FP64 sweep's algorithmic rate as a fraction of it, and
@@ -517,6 +520,15 @@ def main():
     roof = roofline((nc * nd + edges) * 8, avg64, f"k_sweep<double> {p.name}", launches, edges)
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, sweep kernel {avg64:.3f} ms, "
         f"roofline frac {roof['frac']:.3f}")
+    # the rest of a step is the flux pass (one kernel: scalar flux gathered
+    # through the level positions, identity residual, next source and V s):
+    # 8 B of flux and 4 B of position per (direction, cell), 7 per-cell
+    # doubles (phi, sigma_s, q, V read; phi, source, V s written)
+    rest_ms = ms_per_step - avg64
+    flux_bytes = nc * nd * 12 + nc * 8 * 7
+    flux_pass = {"ms_step_minus_sweep": rest_ms, "algorithmic_bytes": flux_bytes,
+                 "gbs": flux_bytes / (rest_ms * 1e-3) / 1e9 if rest_ms > 0 else None,
+                 "note": "lagged-edge terms not counted" if info["n_lagged"] else None}
 
     line_extra = {}
     if not args.steps_only:
@@ -581,6 +593,7 @@ def main():
         "cpu_baseline": line_extra.pop("cpu_baseline", None),
         "sweep_kernel_ms": {"fp64": avg64},
         "sweep_updates_per_s_kernel": {"fp64": nc * nd / (avg64 * 1e-3)},
+        "flux_pass": flux_pass,
     }
     line.update(line_extra)
     print(json.dumps(line))
