@@ -151,8 +151,9 @@ typedef struct jsweep_graph_s *jsweep_graph;   /* opaque, owned by the library *
  * DATA_DRIVEN: a persistent kernel over all directions at once; vertices of
  *   a level-ordered work list run as soon as their upwind vertices are done
  *   (the level-ordered flux array holds an empty marker, or in FP64 solves
- *   whose inputs are all non-negative the previous sweep's sign tag, until
- *   a flux is written; waiting vertices poll it).
+ *   whose inputs all have the sign bit clear, i.e. hold no negative value,
+ *   -0.0 or NaN, the previous sweep's sign tag, until a flux is written;
+ *   waiting vertices poll it).
  * DIRECTION: one workgroup per direction walks that direction's levels with
  *   a workgroup barrier between levels; directions run side by side.
  * DIRECTION_LDS: as DIRECTION, with the recent fluxes of the direction in an
