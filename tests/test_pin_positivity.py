@@ -57,3 +57,21 @@ def test_negative_zero_inputs_give_negative_zero_fluxes(oracle_mod, name, mesh, 
     # a +0.0 inflow alone clears the sign of every flux fed by a boundary
     psi_p, _, _ = g.source_iteration(st, np.full(n, -0.0), np.full(n, -0.0), w, 3, psi_b=0.0)
     assert (psi_p == 0.0).all() and not np.signbit(psi_p).all(), name
+
+
+@pytest.mark.parametrize("name,mesh,sn", [_cases()[1], _cases()[3]])
+def test_multigroup_nonnegative_inputs_give_sign_clear_fluxes(oracle_mod, name, mesh, sn):
+    """The multigroup iteration: a group's source sums the non-negative
+    scattering from every group, so its fluxes stay sign-clear too."""
+    om, w = W.quadrature(sn, mesh.dim)
+    g = oracle_mod.Graph(mesh, om)
+    n, G = g.n_cells, 3
+    rng = np.random.default_rng(63)
+    st = rng.uniform(0.3, 2.5, (G, n))
+    ss = rng.uniform(0.0, 0.3, (G, G, n)) * st[None, :, :]
+    ss[rng.random((G, G, n)) < 0.3] = 0.0
+    q = rng.uniform(0.0, 1.0, (G, n))
+    q[1] = 0.0                      # a group fed by scattering only
+    psi, phi, _ = g.mg_source_iteration(st, ss, q, w, 4, psi_b=0.2)
+    assert (psi >= 0.0).all() and not np.signbit(psi).any(), name
+    assert not np.signbit(phi).any() and (phi[1] > 0.0).any(), name
